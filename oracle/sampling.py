@@ -1,0 +1,77 @@
+"""Per-element uniform samples (oracle side).
+
+Follows sec. 4.1: uniform density p_t = 1/|Omega_t| on each target element,
+N independent samples per element (uniform-density estimator), drawn per
+algorithm step 3 as two independent U(0,1) scalars mapped to area-uniform
+barycentric weights by the map of Osada et al. (2002) and then mapped to the
+physical element by the affine element map.
+
+Reading for tetrahedra (the paper gives no 3D rule): three independent U(0,1)
+scalars are sorted, s1 <= s2 <= s3, and the spacings
+(s1, s2-s1, s3-s2, 1-s3) are the barycentric weights; uniform spacings are
+Dirichlet(1,1,1,1), i.e. uniform on the tetrahedron.
+
+Counter layout (one Philox4x32-10 block per 2D sample, two per 3D sample):
+counter = (j, t, stream, blk), key = (seed_lo, seed_hi), where t is the target
+element index, j the sample index within the element.
+  2D: blk 0 words (0,1) -> xi, words (2,3) -> eta;
+      lambda = (1 - sqrt(xi), sqrt(xi) (1 - eta), sqrt(xi) eta).
+  3D: blk 0 words (0,1) -> u1, words (2,3) -> u2; blk 1 words (0,1) -> u3.
+lambda_k multiplies vertex k of the element in connectivity order.
+
+Parity: pinned by closed-form simplex moments and an equal-volume chi-square
+test (uniformity), plus exactness of the affine identity sum(lambda) = 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import philox
+
+
+def uniforms(dim: int, t: np.ndarray, j: np.ndarray, seed: int, stream: int):
+    """The d open-interval doubles of sample (t, j); returns (n, d)."""
+    k0, k1 = philox.key_from_seed(seed)
+    t = np.asarray(t, dtype=np.uint32)
+    j = np.asarray(j, dtype=np.uint32)
+    s = np.uint32(stream)
+    w = philox.philox4x32_10(j, t, s, np.uint32(0), k0, k1)
+    u = [philox.uniform53(w[0], w[1]), philox.uniform53(w[2], w[3])]
+    if dim == 3:
+        w1 = philox.philox4x32_10(j, t, s, np.uint32(1), k0, k1)
+        u.append(philox.uniform53(w1[0], w1[1]))
+    return np.stack(u, axis=1)
+
+
+def barycentric_from_uniforms(dim: int, u: np.ndarray) -> np.ndarray:
+    """Map d uniforms to d+1 barycentric weights, uniform on the simplex."""
+    if dim == 2:
+        # Osada et al. (2002): area-uniform point from (xi, eta)
+        xi, eta = u[:, 0], u[:, 1]
+        r = np.sqrt(xi)
+        return np.stack([1.0 - r, r * (1.0 - eta), r * eta], axis=1)
+    if dim == 3:
+        s = np.sort(u, axis=1)
+        return np.stack([s[:, 0], s[:, 1] - s[:, 0], s[:, 2] - s[:, 1], 1.0 - s[:, 2]], axis=1)
+    raise ValueError("dim must be 2 or 3")
+
+
+def element_samples(dim: int, n_elems: int, n_samples: int, seed: int, stream: int,
+                    elems: np.ndarray | None = None) -> np.ndarray:
+    """Barycentric weights of every sample of the given elements, shape (len(elems), N, d+1)."""
+    if elems is None:
+        elems = np.arange(n_elems)
+    elems = np.asarray(elems)
+    t = np.repeat(elems, n_samples)
+    j = np.tile(np.arange(n_samples), elems.size)
+    lam = barycentric_from_uniforms(dim, uniforms(dim, t, j, seed, stream))
+    return lam.reshape(elems.size, n_samples, dim + 1)
+
+
+def physical_points(coords: np.ndarray, conn: np.ndarray, lam: np.ndarray,
+                    elems: np.ndarray | None = None) -> np.ndarray:
+    """Affine element map X = sum_k lambda_k x_{v_k}; lam is (E', N, d+1) -> (E', N, d)."""
+    if elems is None:
+        elems = np.arange(conn.shape[0])
+    verts = coords[conn[elems]]                      # (E', d+1, d)
+    return np.einsum("tjk,tkc->tjc", lam, verts)

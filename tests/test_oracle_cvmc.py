@@ -1,0 +1,213 @@
+"""Pins of the oracle's control-variate Monte Carlo transfer and supermesh projection.
+
+Each test checks the oracle against a fact fixed by the paper or by the
+mathematics (special cases, identities, unbiasedness, convergence rates), so
+that a dropped term, a wrong sign, a wrong vertex index or a transposed
+operand anywhere in the pipeline fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cvmc, geometry, supermesh
+from oracle.source import P1Source
+from workloads import fields, meshes
+
+
+def _pair(kind="2d", seeds=(1, 2)):
+    if kind == "2d":
+        return meshes.delaunay_tri_mesh(9, 0.3, seeds[0]), meshes.delaunay_tri_mesh(13, 0.3, seeds[1])
+    return meshes.kuhn_tet_mesh(4, 0.08, seeds[0]), meshes.kuhn_tet_mesh(6, 0.08, seeds[1])
+
+
+def _source(smesh, name):
+    sc, sconn = smesh
+    return P1Source(sc, sconn, fields.evaluate(name, np, sc))
+
+
+# ---- building blocks ---------------------------------------------------------------------
+def test_neumaier_sum_matches_fsum():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((300, 7)) * 10.0 ** rng.integers(-8, 8, (300, 7))
+    s = cvmc.neumaier_sum(x, axis=0)
+    ref = np.array([math.fsum(x[:, c]) for c in range(7)])
+    assert np.array_equal(s, ref) or np.abs(s - ref).max() <= 1e-16 * np.abs(x).sum(axis=0).max()
+
+
+@pytest.mark.parametrize("kind", ["2d", "3d"])
+def test_control_load_is_alpha_M_g(kind):
+    (tc, tconn), _ = _pair(kind)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((2, tc.shape[0]))
+    M = geometry.mass_matrix(tc, tconn)
+    for alpha in (1.0, 0.3):
+        bg = cvmc.control_load(tc, tconn, g, alpha)
+        ref = alpha * (M @ g.T).T
+        assert np.abs(bg - ref).max() <= 1e-15 * np.abs(ref).max() * 10
+
+
+def test_assembly_scatters_to_connectivity():
+    conn = np.array([[0, 1, 2], [2, 1, 3]])
+    beta = np.arange(6, dtype=float).reshape(1, 2, 3) + 1.0
+    b = cvmc.assemble(conn, beta, 4)
+    assert b.tolist() == [[1.0, 2.0 + 5.0, 3.0 + 4.0, 6.0]]
+
+
+def test_jacobi_cg_matches_direct():
+    (tc, tconn), _ = _pair("3d")
+    M = geometry.mass_matrix(tc, tconn)
+    b = np.random.default_rng(1).standard_normal(tc.shape[0])
+    x1 = cvmc.jacobi_cg(M, b, 1e-15)
+    x2 = cvmc.solve_mass(M, b[None], 3)[0]
+    assert cvmc.rel_l2(x1, x2) < 1e-13
+
+
+# ---- special cases of the whole pipeline ----------------------------------------------
+@pytest.mark.parametrize("kind", ["2d", "3d"])
+@pytest.mark.parametrize("N", [1, 7, 64])
+def test_affine_source_reproduced_with_alpha_one(kind, N):
+    """f^s affine lies in V_t, g = f^s, the residual vanishes: x = f at the nodes."""
+    tmesh, smesh = _pair(kind)
+    src = _source(smesh, "affine")
+    r = cvmc.transfer(*tmesh, src, N, alpha=1.0, seed=17, stream=2)
+    assert cvmc.rel_l2(r["x"], fields.evaluate("affine", np, tmesh[0])) < 1e-13
+    assert np.abs(r["b_res"]).max() < 1e-15
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.4, 1.0])
+def test_constant_source_conserved_for_any_alpha(alpha):
+    """sum_k lambda_k = 1 makes sum(b) = c |domain| exactly, for any samples and alpha."""
+    tmesh, smesh = _pair("2d")
+    src = _source(smesh, "constant")
+    r = cvmc.transfer(*tmesh, src, 5, alpha=alpha, seed=4, stream=0)
+    assert abs(r["report"][0]["sum_b"] - 2.5) < 1e-13
+    assert abs(r["report"][0]["int_x"] - 2.5) < 1e-13
+    if alpha == 1.0:
+        # the residual is identically zero, so the nodal values are exact too
+        assert cvmc.rel_l2(r["x"], np.full(tmesh[0].shape[0], 2.5)) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["2d", "3d"])
+def test_identical_meshes_reproduce_nodal_field(kind):
+    """Source mesh == target mesh, alpha = 1: f^s = g on every element, so x = F."""
+    tmesh, _ = _pair(kind)
+    name = "smooth_2d" if kind == "2d" else "gaussian_bumps_3d"
+    src = _source(tmesh, name)
+    r = cvmc.transfer(*tmesh, src, 9, alpha=1.0, seed=8, stream=1)
+    assert cvmc.rel_l2(r["x"], src.values) < 1e-12
+
+
+@pytest.mark.parametrize("alpha", [0.0, 1.0])
+def test_discrete_conservation_identity(alpha):
+    """Testing the Galerkin system with the constant function: m^T x = sum(b)."""
+    tmesh, smesh = _pair("2d")
+    r = cvmc.transfer(*tmesh, _source(smesh, "front_2d"), 11, alpha=alpha, seed=2, stream=0)
+    assert r["report"][0]["cons_defect"] < 1e-13
+
+
+# ---- supermesh (exact b) -----------------------------------------------------------------
+@pytest.fixture(scope="module")
+def sm_case():
+    tmesh, smesh = _pair("2d")
+    pieces = supermesh.intersections(*tmesh, *smesh)
+    return tmesh, smesh, pieces
+
+
+def test_supermesh_partition_identity(sm_case):
+    tmesh, smesh, pieces = sm_case
+    sv = fields.evaluate("smooth_2d", np, smesh[0])
+    sm = supermesh.supermesh_projection(*tmesh, *smesh, sv, pieces=pieces)
+    vol = geometry.element_measures(*tmesh)
+    assert np.abs(sm["area_sum"] - vol).max() < 1e-16 * 20
+    src = P1Source(*smesh, sv)
+    assert abs(sm["b"].sum() - src.integral()[0]) < 1e-14
+    assert abs(sm["int_fs"][0] - src.integral()[0]) < 1e-14
+
+
+def test_supermesh_affine_source_gives_M_f(sm_case):
+    """An affine f^s lies in V_t, so the exact load vector is M f(nodes) on any mesh pair."""
+    tmesh, smesh, pieces = sm_case
+    sv = fields.evaluate("affine", np, smesh[0])
+    sm = supermesh.supermesh_projection(*tmesh, *smesh, sv, x_target=fields.evaluate("affine", np, tmesh[0]),
+                                        pieces=pieces)
+    M = geometry.mass_matrix(*tmesh)
+    ref = M @ fields.evaluate("affine", np, tmesh[0])[0]
+    assert np.abs(sm["b"][0] - ref).max() < 1e-15
+    assert sm["E_L2"][0] < 1e-7        # sqrt of a rounding-level integral
+
+
+def test_supermesh_identical_meshes_gives_MF():
+    tmesh, _ = _pair("2d")
+    sv = fields.evaluate("front_2d", np, tmesh[0])
+    sm = supermesh.supermesh_projection(*tmesh, *tmesh, sv)
+    ref = geometry.mass_matrix(*tmesh) @ sv[0]
+    assert np.abs(sm["b"][0] - ref).max() < 1e-15
+
+
+# ---- statistics: unbiasedness and N^-1/2 -------------------------------------------------
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 1.0])
+def test_estimator_unbiased_against_supermesh(sm_case, alpha):
+    """E[b_hat] = b: replicate means sit within sampling error of the exact b."""
+    tmesh, smesh, pieces = sm_case
+    sv = fields.evaluate("front_2d", np, smesh[0])
+    exact = supermesh.supermesh_projection(*tmesh, *smesh, sv, pieces=pieces)["b"][0]
+    src = P1Source(*smesh, sv)
+    R = 300
+    bs = np.array([cvmc.transfer(*tmesh, src, 6, alpha=alpha, seed=1000 + s, stream=3)["b"][0]
+                   for s in range(R)])
+    z = (bs.mean(axis=0) - exact) / (bs.std(axis=0, ddof=1) / math.sqrt(R))
+    assert np.abs(z).max() < 4.5
+    assert 0.6 < np.mean(z ** 2) < 1.5
+
+
+def test_error_decays_as_inverse_sqrt_N(sm_case):
+    tmesh, smesh, pieces = sm_case
+    sv = fields.evaluate("front_2d", np, smesh[0])
+    exact = supermesh.supermesh_projection(*tmesh, *smesh, sv, pieces=pieces)["b"][0]
+    src = P1Source(*smesh, sv)
+    Ns = [4, 16, 64, 256]
+    rms = []
+    for N in Ns:
+        errs = [cvmc.transfer(*tmesh, src, N, alpha=0.5, seed=50 + s, stream=N)["b"][0] - exact
+                for s in range(24)]
+        rms.append(np.sqrt(np.mean(np.square(errs))))
+    slope = np.polyfit(np.log(Ns), np.log(rms), 1)[0]
+    assert abs(slope + 0.5) < 0.08
+
+
+def test_error_decreases_as_alpha_goes_to_one(sm_case):
+    tmesh, smesh, pieces = sm_case
+    sv = fields.evaluate("paper_f3", np, smesh[0])
+    exact = supermesh.supermesh_projection(*tmesh, *smesh, sv, pieces=pieces)["b"][0]
+    src = P1Source(*smesh, sv)
+    rms = []
+    for alpha in (0.0, 0.5, 0.75, 1.0):
+        errs = [cvmc.transfer(*tmesh, src, 20, alpha=alpha, seed=7 + s, stream=0)["b"][0] - exact
+                for s in range(16)]
+        rms.append(np.sqrt(np.mean(np.square(errs))))
+    assert all(a > b for a, b in zip(rms, rms[1:]))
+    assert rms[-1] < 0.1 * rms[0]
+
+
+def test_h_convergence_rates():
+    """alpha = 1, N = 20: E_L2 ~ h^2 and the RMS conservation error ~ h^3 (2D, P1)."""
+    res = []
+    for kt, ks in [(9, 13), (17, 25), (33, 49)]:
+        tc, tconn = meshes.structured_tri_mesh(kt, 0.2, 21)
+        sc, sconn = meshes.delaunay_tri_mesh(ks, 0.3, 22)
+        sv = fields.evaluate("paper_f2", np, sc)
+        src = P1Source(sc, sconn, sv)
+        pieces = supermesh.intersections(tc, tconn, sc, sconn)
+        el2, em = [], []
+        for s in range(6):
+            r = cvmc.transfer(tc, tconn, src, 20, 1.0, seed=s, stream=0)
+            sm = supermesh.supermesh_projection(tc, tconn, sc, sconn, sv, r["x"], pieces=pieces)
+            el2.append(sm["E_L2"][0])
+            em.append(sm["E_mass"][0])
+        res.append((1.0 / (kt - 1), np.mean(el2), np.sqrt(np.mean(np.square(em)))))
+    res = np.array(res)
+    s_l2 = np.polyfit(np.log(res[:, 0]), np.log(res[:, 1]), 1)[0]
+    s_m = np.polyfit(np.log(res[:, 0]), np.log(res[:, 2]), 1)[0]
+    assert 1.8 < s_l2 < 2.2
+    assert 2.6 < s_m < 3.4

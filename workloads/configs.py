@@ -1,0 +1,104 @@
+"""Named synthetic transfer workloads.
+
+Each workload is a seeded (target mesh, source mesh, source field, sampling)
+tuple.  The paper's gmsh/LTX/WEST meshes are unavailable; these stand in with
+the same element types and the size range the paper times (1e3 to 2.3e6
+elements).  Sizes:
+
+======================  ===  ==================  =========  ===================  ==========  ====  ==
+name                    dim  target             E          source               E_s         N     F
+======================  ===  ==================  =========  ===================  ==========  ====  ==
+tri2d_4k                2    Delaunay 45^2       3,872      Delaunay 70^2        9,522       64    1
+tri2d_1m                2    structured 708^2    999,698    structured 1415^2    3,998,792   256   1
+tet3d_2m                3    Kuhn 71^3 nodes     2,058,000  Kuhn 111^3 nodes     7,986,000   128   1
+tet3d_1m_64f            3    Kuhn 56^3 nodes     998,250    Kuhn 88^3 nodes      3,951,018   128   64
+======================  ===  ==================  =========  ===================  ==========  ====  ==
+
+Seeds: target jitter 11, source jitter 12, field parameters 13, Philox key
+``0x0F7A5EED00000000 + index``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from functools import lru_cache
+
+import numpy as np
+
+from . import fields as _fields
+from . import meshes as _meshes
+
+PHILOX_SEED_BASE = 0x0F7A5EED00000000
+
+
+@dataclass(frozen=True)
+class MeshSpec:
+    kind: str          # structured_tri | delaunay_tri | kuhn_tet
+    k: int             # nodes per axis
+    jitter: float      # fraction of the grid spacing
+    seed: int
+
+    def build(self):
+        return _meshes.make_mesh(self.kind, self.k, self.jitter, self.seed)
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    dim: int
+    target: MeshSpec
+    source: MeshSpec
+    field: str
+    samples_per_elem: int
+    n_fields: int = 1
+    alpha: float = 1.0
+    index: int = 0
+    bins: tuple = (0, 0, 0)      # 0 = library default
+    rtol: float = 1e-14
+
+    @property
+    def philox_seed(self) -> int:
+        return PHILOX_SEED_BASE + self.index
+
+
+WORKLOADS = {
+    "tri2d_4k": Workload(
+        "tri2d_4k", 2,
+        MeshSpec("delaunay_tri", 45, 0.3, 11), MeshSpec("delaunay_tri", 70, 0.3, 12),
+        "smooth_2d", 64, index=1),
+    "tri2d_1m": Workload(
+        "tri2d_1m", 2,
+        MeshSpec("structured_tri", 708, 0.2, 11), MeshSpec("structured_tri", 1415, 0.2, 12),
+        "front_2d", 256, index=2, bins=(512, 512, 0)),
+    "tet3d_2m": Workload(
+        "tet3d_2m", 3,
+        MeshSpec("kuhn_tet", 71, 0.08, 11), MeshSpec("kuhn_tet", 111, 0.08, 12),
+        "gaussian_bumps_3d", 128, index=3),
+    "tet3d_1m_64f": Workload(
+        "tet3d_1m_64f", 3,
+        MeshSpec("kuhn_tet", 56, 0.08, 11), MeshSpec("kuhn_tet", 88, 0.08, 12),
+        "fourier_fields_3d", 128, n_fields=64, index=4),
+}
+
+
+@lru_cache(maxsize=8)
+def build_mesh(spec: MeshSpec):
+    coords, conn = spec.build()
+    coords.setflags(write=False)
+    conn.setflags(write=False)
+    return coords, conn
+
+
+def source_nodal_values(w: Workload, src_coords: np.ndarray) -> np.ndarray:
+    """(F, n_s) nodal values of the workload's field on its source mesh."""
+    return np.ascontiguousarray(_fields.evaluate(w.field, np, src_coords), dtype=np.float64)
+
+
+def scaled(w: Workload, target_k: int, source_k: int, samples_per_elem: int | None = None,
+           name: str | None = None) -> Workload:
+    """Same recipe at a different size (for tests that need a smaller instance)."""
+    return Workload(
+        name or f"{w.name}@{target_k}/{source_k}", w.dim,
+        MeshSpec(w.target.kind, target_k, w.target.jitter, w.target.seed),
+        MeshSpec(w.source.kind, source_k, w.source.jitter, w.source.seed),
+        w.field, samples_per_elem or w.samples_per_elem, w.n_fields, w.alpha, w.index,
+        (0, 0, 0), w.rtol)

@@ -1,0 +1,127 @@
+"""Seeded synthetic P1 meshes of the unit square / unit cube.
+
+Input generators only: these build node coordinates and element connectivity
+and hold none of the transfer method's arithmetic.  Both the CPU oracle and the
+GPU path consume the same arrays.
+
+Conventions
+-----------
+* ``coords`` is ``(n_nodes, dim)`` float64, ``conn`` is ``(n_elems, dim+1)``
+  int32, every element positively oriented (counter-clockwise triangles,
+  right-handed tetrahedra).
+* "k-grid" means k nodes per axis, i.e. (k-1) cells per axis.
+* Jitter moves every node by a uniform offset in ``[-a*h, a*h]`` per axis, but
+  a coordinate that sits exactly on the domain boundary (0 or 1) is not moved,
+  so boundary nodes slide tangentially, corners stay fixed, and the mesh covers
+  exactly ``[0,1]^dim``.
+
+The paper's meshes (gmsh square meshes from 1k to 2.3M triangles, the LTX and
+WEST reactor meshes) are not available; these generators stand in for them
+with the same element type, dimension and size range.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def _grid_points(k: int, dim: int) -> np.ndarray:
+    g = np.linspace(0.0, 1.0, k)
+    axes = np.meshgrid(*([g] * dim), indexing="ij")
+    # node id = i + j*k (+ l*k*k): the x index varies fastest
+    return np.stack([a.transpose(tuple(reversed(range(dim)))).ravel() for a in axes], axis=1)
+
+
+def jittered_grid_points(k: int, dim: int, jitter: float, seed: int) -> np.ndarray:
+    """k^dim grid nodes on [0,1]^dim with tangential-only boundary jitter."""
+    p = _grid_points(k, dim)
+    h = 1.0 / (k - 1)
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-jitter * h, jitter * h, size=p.shape)
+    d[(p == 0.0) | (p == 1.0)] = 0.0
+    return np.ascontiguousarray(p + d)
+
+
+def _orient(coords: np.ndarray, conn: np.ndarray) -> np.ndarray:
+    """Swap the last two vertices of negatively oriented simplices."""
+    x0 = coords[conn[:, 0]]
+    e = [coords[conn[:, i]] - x0 for i in range(1, conn.shape[1])]
+    if conn.shape[1] == 3:
+        det = e[0][:, 0] * e[1][:, 1] - e[0][:, 1] * e[1][:, 0]
+    else:
+        det = (e[0][:, 0] * (e[1][:, 1] * e[2][:, 2] - e[1][:, 2] * e[2][:, 1])
+               - e[0][:, 1] * (e[1][:, 0] * e[2][:, 2] - e[1][:, 2] * e[2][:, 0])
+               + e[0][:, 2] * (e[1][:, 0] * e[2][:, 1] - e[1][:, 1] * e[2][:, 0]))
+    flip = det < 0
+    conn = conn.copy()
+    conn[flip, -2], conn[flip, -1] = conn[flip, -1].copy(), conn[flip, -2].copy()
+    return conn
+
+
+def structured_tri_mesh(k: int, jitter: float, seed: int):
+    """Jittered k x k node grid, every cell split along its (i,j)-(i+1,j+1) diagonal.
+
+    2*(k-1)^2 triangles.  Any jitter below h/4 keeps every area positive.
+    """
+    coords = jittered_grid_points(k, 2, jitter, seed)
+    i, j = np.meshgrid(np.arange(k - 1), np.arange(k - 1), indexing="xy")
+    i = i.ravel(); j = j.ravel()
+    a = i + j * k
+    b = a + 1
+    c = a + k + 1
+    d = a + k
+    conn = np.empty((2 * a.size, 3), dtype=np.int64)
+    conn[0::2] = np.stack([a, b, c], 1)
+    conn[1::2] = np.stack([a, c, d], 1)
+    conn = _orient(coords, conn)
+    return coords, conn.astype(np.int32)
+
+
+def delaunay_tri_mesh(k: int, jitter: float, seed: int):
+    """Delaunay triangulation of a jittered k x k point grid (2n - 2 - #hull triangles)."""
+    from scipy.spatial import Delaunay
+
+    coords = jittered_grid_points(k, 2, jitter, seed)
+    tri = Delaunay(coords)
+    if len(tri.coplanar):
+        raise RuntimeError("Delaunay dropped points")
+    conn = _orient(coords, tri.simplices.astype(np.int64))
+    return coords, conn.astype(np.int32)
+
+
+# the six monotone lattice paths from corner (0,0,0) to (1,1,1) of a cube
+_KUHN_PATHS = list(itertools.permutations(range(3)))
+
+
+def kuhn_tet_mesh(k: int, jitter: float, seed: int):
+    """Perturbed Kuhn (Freudenthal) split of a (k-1)^3 hex grid: 6*(k-1)^3 tets.
+
+    Jitter up to about 0.09h keeps every volume positive; the default 0.08h
+    is used for the 3D workloads.
+    """
+    coords = jittered_grid_points(k, 3, jitter, seed)
+    c = k - 1
+    ii, jj, ll = np.meshgrid(np.arange(c), np.arange(c), np.arange(c), indexing="ij")
+    base = (ii + jj * k + ll * k * k).transpose(2, 1, 0).ravel()
+    stride = np.array([1, k, k * k])
+    tets = []
+    for perm in _KUHN_PATHS:
+        v0 = base
+        v1 = v0 + stride[perm[0]]
+        v2 = v1 + stride[perm[1]]
+        v3 = v0 + stride.sum()
+        tets.append(np.stack([v0, v1, v2, v3], 1))
+    conn = np.stack(tets, 1).reshape(-1, 4)
+    conn = _orient(coords, conn)
+    return coords, conn.astype(np.int32)
+
+
+def make_mesh(kind: str, k: int, jitter: float, seed: int):
+    if kind == "structured_tri":
+        return structured_tri_mesh(k, jitter, seed)
+    if kind == "delaunay_tri":
+        return delaunay_tri_mesh(k, jitter, seed)
+    if kind == "kuhn_tet":
+        return kuhn_tet_mesh(k, jitter, seed)
+    raise ValueError(f"unknown mesh kind {kind!r}")
