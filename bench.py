@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Throughput of the CV-MC field transfer hot path on one MI355X.
+
+One step is one whole transfer with the inputs resident in HBM:
+  ft_sample_points   (node queries + N Philox samples per target element)
+  ft_source_eval     (the built-in P1 source answers every point query)
+  ft_consume_queries (residual, per-element Monte Carlo sums, node assembly)
+  ft_project         (b = alpha M g + b_res, Jacobi-PCG to rtol, conservation report)
+Setup (mass matrix, incidence, source bins) is timed separately: it is paid
+once per mesh pair.
+
+Prints one JSON line.  Per-phase times come from HIP events recorded on the
+stream the library launches on; the dominant kernel's achieved bandwidth is
+its algorithmic bytes divided by its average event-measured duration.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "target elements/s and point queries/s per transfer; % HBM roofline vs FP64"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(phase, dim, E, n, N, F, p, src=None):
+    """Compulsory HBM bytes of one launch of a phase (measurement)."""
+    Q = n + E * N
+    if phase == "emit":
+        # write d coordinates per query; read connectivity and vertex coordinates per element
+        return Q * dim * p + E * ((dim + 1) * 4 + (dim + 1) * dim * 8) + n * dim * 8
+    if phase == "eval":
+        # read d coordinates and write F values per query; read the source mesh once
+        rs = 8 if dim == 2 else 16
+        mesh = src["E"] * (rs * 8 + 2 * dim * 4 + (dim + 1) * 4) + src["n_reg"] * 4 + src["nbins"] * 8 \
+            + src["n"] * F * 8
+        return Q * (dim + F) * p + mesh
+    if phase == "consume":
+        # read F values per query; per element connectivity, measure and beta; node assembly
+        return Q * F * p + E * ((dim + 1) * 4 + 8 + (dim + 1) * F * 8) + E * (dim + 1) * (4 + F * 8) + n * F * 16
+    raise ValueError(phase)
+
+
+def cpu_baseline(w, tmesh, smesh, svals, sample_elems):
+    """The oracle, untuned, on the first `sample_elems` target elements (steps 3-5)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cvmc
+    from oracle.source import P1Source
+
+    tc, tconn = tmesh
+    sc, sconn = smesh
+    src = P1Source(sc, sconn, svals)
+    with threadpool_limits(limits=1):
+        g = np.atleast_2d(src(tc))
+        els = np.arange(sample_elems)
+        t0 = time.perf_counter()
+        lam, X = cvmc.query_points(tc, np.asarray(tconn, dtype=np.int64), w.samples_per_elem, w.philox_seed, 0, els)
+        y = np.atleast_2d(src(X.reshape(-1, tc.shape[1]))).reshape(g.shape[0], els.size, w.samples_per_elem)
+        cvmc.element_loads(tc, np.asarray(tconn, dtype=np.int64), g, y, lam, w.alpha, els)
+        dt = time.perf_counter() - t0
+    return {
+        "value": sample_elems / dt, "unit": "target elements/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle steps 3-5 (Philox sampling, P1-source localization and evaluation, residual "
+                   f"element sums) on the first {sample_elems} of {tconn.shape[0]} target elements "
+                   f"x {w.samples_per_elem} samples, numpy single-threaded, {dt:.1f} s; node queries, "
+                   f"assembly and the mass solve excluded"),
+        "seconds": dt,
+    }
+
+
+def calibrate_copy(nbytes):
+    """A plain device copy of known size, for scaling rocprof FETCH_SIZE / WRITE_SIZE."""
+    import torch
+
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": nbytes}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tri2d_1m")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-elems", type=int, default=1500)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the transfer shards by target elements but the multi-GPU path is not built", file=sys.stderr)
+        sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2603_00538_amd import ft
+    from workloads import configs
+
+    w = configs.WORKLOADS[args.workload]
+    log(f"workload {w.name}: building meshes")
+    tmesh = configs.build_mesh(w.target)
+    smesh = configs.build_mesh(w.source)
+    svals = configs.source_nodal_values(w, smesh[0])
+    tc, tconn = tmesh
+    sc, sconn = smesh
+    dim, E, n = w.dim, tconn.shape[0], tc.shape[0]
+    N, F = w.samples_per_elem, w.n_fields
+    prec = ft.FT_F32 if args.precision == "f32" else ft.FT_F64
+    p = 4 if prec == ft.FT_F32 else 8
+    dt_ = torch.float32 if prec == ft.FT_F32 else torch.float64
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    # ---- setup (once per mesh pair)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = ft.Target(tc, tconn)
+    S = ft.Source(sc, sconn, svals, bins=w.bins if any(w.bins) else None)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup {setup_s * 1e3:.1f} ms; nnz {T.info.nnz}")
+    Q = T.query_count(N)
+    cfg = ft.SampleCfg(N, F, w.alpha, w.philox_seed, 0, prec)
+    pts = torch.empty((dim, Q), dtype=dt_, device=dev)
+    vals = torch.empty((F, Q), dtype=dt_, device=dev)
+    x = torch.empty((F, n), dtype=torch.float64, device=dev)
+    b = torch.empty((F, n), dtype=torch.float64, device=dev)
+
+    phases = ["emit", "eval", "consume", "project"]
+    times = {k: [] for k in phases}
+    reports = None
+    status = None
+
+    def step(record):
+        nonlocal reports, status
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        if record:
+            ev[0].record()
+        T.sample_points(cfg, out=pts)
+        if record:
+            ev[1].record()
+        S.eval(pts, out=vals)
+        if record:
+            ev[2].record()
+        T.consume(cfg, vals)
+        if record:
+            ev[3].record()
+        res = T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
+        if record:
+            ev[4].record()
+        reports, status = res.reports, res.status
+        return ev
+
+    for i in range(args.warmup):
+        step(False)
+        log(f"warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs.append(step(True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for ev in evs:
+        for k, name in enumerate(phases):
+            times[name].append(ev[k].elapsed_time(ev[k + 1]))
+    log(f"timed {args.steps} steps in {wall:.3f} s")
+    ms_step = wall * 1e3 / args.steps
+    phase_ms = {k: float(np.mean(v)) for k, v in times.items()}
+
+    si = S.info
+    src_info = {"E": sconn.shape[0], "n": sc.shape[0], "n_reg": int(si.n_registrations),
+                "nbins": int(np.prod([si.bins[c] for c in range(dim)]))}
+    dom = max(["emit", "eval", "consume"], key=lambda k: phase_ms[k])
+    abytes = algorithmic_bytes(dom, dim, E, n, N, F, p, src_info)
+    achieved = abytes / (phase_ms[dom] * 1e-3) / 1e9
+    kernel_names = {"emit": "k_emit", "eval": "k_src_eval", "consume": "k_consume"}
+    out = {
+        "metric": METRIC,
+        "value": E / (ms_step * 1e-3),
+        "unit": "target elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == ft.FT_F64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dim": dim, "target_elements": E, "target_nodes": n,
+                   "source_elements": int(sconn.shape[0]), "samples_per_elem": N, "n_fields": F,
+                   "queries": Q, "alpha": w.alpha, "rtol": w.rtol,
+                   "bins": list(w.bins[:dim]) if any(w.bins) else "default", "precision": args.precision},
+        "queries_per_s": Q / (ms_step * 1e-3),
+        "phases_ms": phase_ms,
+        "setup_ms": setup_s * 1e3,
+        "cg_iters": reports[0]["iters"],
+        "cons_defect": reports[0]["cons_defect"],
+        "rel_resid": reports[0]["rel_resid"],
+        "status": ft.STATUS_NAMES[status],
+        "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": abytes, "avg_ms": phase_ms[dom]},
+    }
+    out["config"]["bins"] = [int(si.bins[c]) for c in range(dim)]
+    out["config"]["bin_registrations"] = int(si.n_registrations)
+    T.close()
+    S.close()
+    del pts, vals
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, bounded sample)")
+        cb = cpu_baseline(w, tmesh, smesh, svals, args.cpu_sample_elems)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

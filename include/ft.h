@@ -1,0 +1,229 @@
+/*
+ * ft.h - stochastic conservative field transfer on MI355X (gfx950).
+ *
+ * C ABI of the hot path of the control-variate Monte Carlo (CV-MC) Galerkin
+ * projection of Paudel, Smith and Merson (arXiv 2603.00538): a field f^s that
+ * can only be queried at points is projected onto a P1 target space,
+ *
+ *     b_i = integral f^s psi_i   (sec. 2, Eq. load_vector),
+ *     M x = b                    (sec. 2, Eq. galerkin_system),
+ *
+ * with b estimated per target element as the exact control part plus a Monte
+ * Carlo estimate of the residual (sec. 4.1, Eq. cv_element_load_residual_operator
+ * and the seven-step algorithm that closes sec. 4.1).
+ *
+ * A transfer is four calls, matching the algorithm's steps:
+ *
+ *   ft_target_create    setup, once per target mesh (mass matrix, incidence)
+ *   ft_sample_points    step 1 + 3: the point-query list (nodes, then samples)
+ *   -- the caller evaluates f^s at every query point (the black box) --
+ *   ft_consume_queries  steps 4-6: residual, per-element MC sums, assembly
+ *   ft_project          steps 2 + 7: control load, M x = b, conservation report
+ *
+ * plus a mesh-backed P1 source with uniform-grid point localization
+ * (ft_source_*), standing in for the black box in benchmarks (sec. 5.3).
+ *
+ * Conventions (all calls):
+ *  - Pointers marked "device" are HIP device memory owned by the caller; the
+ *    library never retains them after the call returns.  "host" pointers are
+ *    ordinary host memory.
+ *  - Arrays are structure-of-arrays: coords[c * ld + i] is coordinate c of
+ *    point i; values[f * ld + q] is field f at query q.
+ *  - Every call enqueues its work on `stream` and returns without waiting,
+ *    except ft_target_create, ft_source_create_p1, ft_source_stats and
+ *    ft_project, which synchronize `stream` before returning.
+ *  - Argument, ordering and mesh errors are returned immediately with no work
+ *    enqueued; a failed HIP call returns FT_E_DEVICE.  ft_last_error() gives a
+ *    message for the last failure on the calling thread.
+ *  - A handle may be used by one host thread at a time.
+ */
+#ifndef FT_H
+#define FT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FT_OK = 0,
+    FT_E_ARG = -1,         /* invalid argument: null pointer, size or enum out of range      */
+    FT_E_MESH = -2,        /* degenerate element or connectivity out of range                 */
+    FT_E_ORDER = -3,       /* call out of order (e.g. project before consume)                 */
+    FT_E_DEVICE = -4,      /* a HIP runtime call failed                                       */
+    FT_E_NOCONV = -5,      /* CG stopped at max_iter above rtol (x is still written)          */
+    FT_E_NONFINITE = -6,   /* NaN/Inf query values were consumed (x is still written)         */
+    FT_E_OOM = -7,         /* device allocation failed                                        */
+    FT_E_UNSUPPORTED = -8  /* valid but not implemented combination                           */
+} ft_status;
+
+typedef enum {
+    FT_F64 = 0,            /* points and values in binary64                                   */
+    FT_F32 = 1             /* points and values in binary32 (coordinates converted inside)    */
+} ft_precision;
+
+typedef struct ft_target ft_target;
+typedef struct ft_source ft_source;
+
+/* Sampling configuration of one transfer (sec. 4.1 steps 3-5). */
+typedef struct {
+    int32_t  samples_per_elem;  /* N >= 1: samples per target element (the paper uses N = 20)     */
+    int32_t  n_fields;          /* F >= 1: fields transferred together, sharing the samples       */
+    double   alpha;             /* control-variate coefficient (Eq. cv_centered_integrand); 1.0    */
+    uint64_t seed;              /* Philox4x32-10 key                                               */
+    uint32_t stream_id;         /* realization id: Philox counter word 2                           */
+    int32_t  precision;         /* ft_precision of the query points and values                     */
+} ft_sample_cfg;
+
+/* Mass solve configuration (sec. 4.1 step 7). */
+typedef struct {
+    double  rtol;               /* stop when ||b - M x||_2 <= rtol ||b||_2 (recurrence residual)   */
+    int32_t max_iter;           /* Jacobi-PCG iteration cap per field                              */
+} ft_solve_cfg;
+
+/* Per-field result of ft_project (conservation: sec. 2 Eq. conservation, App. B). */
+typedef struct {
+    double  sum_b;              /* sum_i b_i                                                       */
+    double  int_x;              /* m^T x = integral of the transferred field, m = M 1             */
+    double  cons_defect;        /* |int_x - sum_b| / |sum_b|                                       */
+    double  rel_resid;          /* true residual ||b - M x||_2 / ||b||_2 after the solve           */
+    int32_t iters;              /* CG iterations taken                                             */
+    int32_t status;             /* FT_OK, FT_E_NOCONV or FT_E_NONFINITE for this field             */
+    int64_t n_nonfinite;        /* non-finite query values seen by the last consume                */
+} ft_report;
+
+/* Sizes of a target after setup. */
+typedef struct {
+    int32_t dim;
+    int64_t n_nodes;
+    int64_t n_elems;
+    int64_t nnz;                /* stored entries of M (CSR)                                        */
+    int64_t n_inverted;         /* elements with negative orientation (accepted; |det J| is used) */
+} ft_target_info;
+
+/*
+ * ft_target_create - setup of a P1 target mesh (sec. 2: M_ki = int psi_k psi_i,
+ * computed exactly; the element measure |Omega_t| = |det J_t| / d! used by
+ * sec. 4.1).
+ *   dim      2 (triangles) or 3 (tetrahedra)
+ *   coords   device, binary64, [dim][n_nodes] (SoA)
+ *   conn     device, int32, [n_elems][dim+1] vertex ids in [0, n_nodes)
+ *   out      host; receives a new handle (library-owned device memory:
+ *            copies of the mesh, CSR mass matrix, Jacobi diagonal, lumped
+ *            mass, node->element incidence, work vectors)
+ * Errors: FT_E_ARG (dim, sizes, null), FT_E_MESH (id out of range, or an
+ * element with |det J| <= 1e-12 h^d, h its longest edge), FT_E_OOM.
+ * Synchronizes `stream`.
+ */
+ft_status ft_target_create(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems,
+                           const int32_t* conn, hipStream_t stream, ft_target** out);
+
+/* Release a target and all its device memory (null is accepted).  The
+ * caller must make sure no work using it is still pending on any stream. */
+ft_status ft_target_destroy(ft_target* t);
+
+ft_status ft_target_get_info(const ft_target* t, ft_target_info* info /* host */);
+
+/* Number of query points of a transfer: Q = n_nodes + n_elems * N (-1 on bad args). */
+int64_t ft_query_count(const ft_target* t, int32_t samples_per_elem);
+
+/*
+ * ft_sample_points - the point-query list (sec. 4.1 step 1 and step 3).
+ * Entries [0, n_nodes) are the target nodes (the control g = I_h f^s is
+ * f^s at the nodes); entry n_nodes + t*N + j is sample j of element t:
+ * Philox4x32-10 at counter (j, t, stream_id, blk) with key seed gives
+ * uniforms, mapped to area/volume-uniform barycentric weights (Osada map for
+ * triangles, sorted spacings for tetrahedra) and then to the physical point
+ * sum_k lambda_k x_{v_k}.
+ *   points   device, [dim][Q] in cfg->precision (Q = ft_query_count)
+ * Errors: FT_E_ARG.  Asynchronous on `stream`.
+ */
+ft_status ft_sample_points(ft_target* t, const ft_sample_cfg* cfg, void* points, hipStream_t stream);
+
+/*
+ * ft_consume_queries - steps 4-6 of sec. 4.1 for the caller's point values.
+ *   values   device, [F][Q] in cfg->precision: f^s at every query point, in
+ *            the layout of ft_sample_points (nodes first, then samples)
+ * For every element t and local vertex k:
+ *   beta_tk = |Omega_t| / N * sum_j (y_tj - alpha sum_l lambda_l g_{v_l}) lambda_k,
+ * with lambda regenerated from the same Philox stream (cfg must match the
+ * one given to ft_sample_points), then b_res,v = sum of beta_tk over the
+ * (t, k) at node v in a fixed order (no floating-point atomics, so results
+ * are bitwise reproducible).  The control values g (the first n_nodes
+ * entries of each field) are copied into the target.  Non-finite values are
+ * counted and reported by ft_project.
+ * Errors: FT_E_ARG, FT_E_OOM.  Asynchronous on `stream`.
+ */
+ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void* values, hipStream_t stream);
+
+/*
+ * ft_project - step 2 and step 7 of sec. 4.1 and the conservation report.
+ * b = alpha M g + b_res (the control load integrated exactly), then Jacobi-PCG
+ * on M y = b_res from y = 0 and x = alpha g + y (the same iterates as CG on
+ * M x = b started at x = alpha g), stopping at ||b - M x|| <= rtol ||b||.
+ *   x        device, binary64, [F][n_nodes]: the transferred coefficients
+ *   b_out    device, binary64, [F][n_nodes] or null: the load vector b
+ *   rep      host, [F] reports
+ * Errors: FT_E_ORDER (no consume since the last sample), FT_E_ARG; per-field
+ * FT_E_NOCONV / FT_E_NONFINITE are returned (the worst of them) after x is
+ * written.  Synchronizes `stream`.
+ */
+ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep,
+                     hipStream_t stream);
+
+/*
+ * ft_source_create_p1 - a P1 field on a source mesh, evaluated at points by
+ * uniform-grid localization (sec. 5.3: grid cells per axis int(L sqrt(#elements))).
+ *   coords         device, binary64, [dim][n_nodes]
+ *   conn           device, int32, [n_elems][dim+1]
+ *   nodal_values   device, binary64, [n_fields][n_nodes]
+ *   bins           host, [dim] cells per axis, or null / zeros for the default
+ *                  int(sqrt(n_elems)) per axis in 2D, round(cbrt(n_elems/6)) in 3D
+ * Localization rule: the element maximizing min_k mu_k(x) (mu: barycentric
+ * coordinates); exact ties go to the lowest element id; a best min mu below
+ * -1e-10 counts as out of domain and is evaluated by extrapolation from that
+ * element.  Errors: FT_E_ARG, FT_E_MESH, FT_E_OOM.  Synchronizes `stream`.
+ */
+ft_status ft_source_create_p1(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems,
+                              const int32_t* conn, int32_t n_fields, const double* nodal_values,
+                              const int32_t* bins, hipStream_t stream, ft_source** out);
+
+/*
+ * ft_source_eval - evaluate the P1 source at points.
+ *   points     device, [dim][ld] in `precision`, points 0..n_points-1 used
+ *   values     device, [n_fields][ld_out] in `precision`
+ *   elem_ids   device, int32, [n_points], or null: the containing source element
+ * ld / ld_out are the leading dimensions (>= n_points).
+ * Errors: FT_E_ARG.  Asynchronous on `stream`.
+ */
+ft_status ft_source_eval(ft_source* s, int64_t n_points, const void* points, int64_t ld, int32_t precision,
+                         void* values, int64_t ld_out, int32_t* elem_ids, hipStream_t stream);
+
+/* Sizes of a source after setup. */
+typedef struct {
+    int32_t dim;
+    int32_t n_fields;
+    int64_t n_nodes;
+    int64_t n_elems;
+    int32_t bins[3];            /* cells per axis of the localization grid (1 for unused axes)    */
+    int64_t n_registrations;    /* element ids stored over all bins                                */
+} ft_source_info;
+
+ft_status ft_source_get_info(const ft_source* s, ft_source_info* info /* host */);
+
+/* Out-of-domain points seen by ft_source_eval since the last call (then reset).
+ * Synchronizes `stream`. */
+ft_status ft_source_stats(ft_source* s, int64_t* n_out_of_domain /* host */, hipStream_t stream);
+
+ft_status ft_source_destroy(ft_source* s);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* ft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FT_H */

@@ -1,0 +1,266 @@
+// The extern "C" boundary: argument validation, call-order state, dispatch.
+// No exception crosses it; every failure is a status plus ft_last_error().
+#include <cmath>
+#include <new>
+
+#include "common.h"
+
+namespace ft {
+const char* last_error();
+ft_status target_setup(ft_target* T, const double* coords, const int32_t* conn, hipStream_t s);
+ft_status solver_alloc(ft_target* T, hipStream_t s);
+ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipStream_t s);
+ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s);
+ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep, hipStream_t s);
+ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, const double* values,
+                       const int32_t* bins, hipStream_t s);
+ft_status source_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
+                      int32_t* ids, hipStream_t s);
+ft_status source_release(ft_source* S);
+
+static void target_release(ft_target* T) {
+    void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
+                  T->beta, T->g, T->bres, T->r, T->z, T->p, T->q, T->y, T->b, T->scal, T->partials, T->ticket,
+                  T->counters};
+    for (void* p : ps) dev_free(p);
+    if (T->h_scal) (void)hipHostFree(T->h_scal);
+}
+
+static ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
+    FT_ARG_CHECK(cfg, "cfg is null");
+    FT_ARG_CHECK(cfg->samples_per_elem >= 1, "samples_per_elem must be >= 1 (got %d)", cfg->samples_per_elem);
+    FT_ARG_CHECK(cfg->n_fields >= 1, "n_fields must be >= 1 (got %d)", cfg->n_fields);
+    FT_ARG_CHECK(cfg->precision == FT_F64 || cfg->precision == FT_F32, "precision must be FT_F64 or FT_F32");
+    FT_ARG_CHECK(std::isfinite(cfg->alpha), "alpha must be finite");
+    if (uint64_t(T->E) * uint64_t(cfg->samples_per_elem) >= (uint64_t(1) << 32) ||
+        uint64_t(T->E) * 64u >= (uint64_t(1) << 32)) {
+        set_error("n_elems * max(samples_per_elem, 64) must stay below 2^32 per transfer");
+        return FT_E_UNSUPPORTED;
+    }
+    return FT_OK;
+}
+
+static bool same_samples(const ft_sample_cfg& a, const ft_sample_cfg& b) {
+    return a.samples_per_elem == b.samples_per_elem && a.seed == b.seed && a.stream_id == b.stream_id &&
+           a.precision == b.precision;
+}
+
+}  // namespace ft
+
+using namespace ft;
+
+#define FT_GUARD_BEGIN try {
+#define FT_GUARD_END                                  \
+    }                                                 \
+    catch (const std::bad_alloc&) {                   \
+        set_error("host allocation failed");          \
+        return FT_E_OOM;                              \
+    }                                                 \
+    catch (...) {                                     \
+        set_error("unexpected internal exception");   \
+        return FT_E_DEVICE;                           \
+    }
+
+struct ft_target_ext : ft_target {
+    bool sampled = false;
+    ft_sample_cfg sampled_cfg{};
+};
+
+extern "C" {
+
+ft_status ft_target_create(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems, const int32_t* conn,
+                           hipStream_t stream, ft_target** out) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(out, "out is null");
+    *out = nullptr;
+    FT_ARG_CHECK(dim == 2 || dim == 3, "dim must be 2 or 3 (got %d)", dim);
+    FT_ARG_CHECK(coords && conn, "coords and conn must be device pointers");
+    FT_ARG_CHECK(n_nodes >= dim + 1 && n_nodes < INT32_MAX, "n_nodes out of range (%lld)", (long long)n_nodes);
+    FT_ARG_CHECK(n_elems >= 1 && n_elems * (dim + 1) < INT32_MAX, "n_elems out of range (%lld)", (long long)n_elems);
+    auto* T = new ft_target_ext();
+    T->dim = dim;
+    T->n = n_nodes;
+    T->E = n_elems;
+    ft_status st = target_setup(T, coords, conn, stream);
+    if (st == FT_OK) st = solver_alloc(T, stream);
+    if (st == FT_OK && hipStreamSynchronize(stream) != hipSuccess) {
+        set_error("stream synchronization failed after setup");
+        st = FT_E_DEVICE;
+    }
+    if (st != FT_OK) {
+        (void)hipStreamSynchronize(stream);
+        target_release(T);
+        delete T;
+        return st;
+    }
+    *out = T;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_target_destroy(ft_target* t) {
+    if (!t) return FT_OK;
+    target_release(t);
+    delete static_cast<ft_target_ext*>(t);
+    return FT_OK;
+}
+
+ft_status ft_target_get_info(const ft_target* t, ft_target_info* info) {
+    clear_error();
+    FT_ARG_CHECK(t && info, "null argument");
+    info->dim = t->dim;
+    info->n_nodes = t->n;
+    info->n_elems = t->E;
+    info->nnz = t->nnz;
+    info->n_inverted = t->n_inverted;
+    return FT_OK;
+}
+
+int64_t ft_query_count(const ft_target* t, int32_t samples_per_elem) {
+    if (!t || samples_per_elem < 1) return -1;
+    return t->n + t->E * int64_t(samples_per_elem);
+}
+
+ft_status ft_sample_points(ft_target* t, const ft_sample_cfg* cfg, void* points, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t, "target is null");
+    FT_TRY(check_sample_cfg(t, cfg));
+    FT_ARG_CHECK(points, "points is null");
+    FT_TRY(emit_points(t, cfg, points, stream));
+    auto* T = static_cast<ft_target_ext*>(t);
+    T->sampled = true;
+    T->sampled_cfg = *cfg;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void* values, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t, "target is null");
+    FT_TRY(check_sample_cfg(t, cfg));
+    FT_ARG_CHECK(values, "values is null");
+    auto* T = static_cast<ft_target_ext*>(t);
+    if (!T->sampled || !same_samples(T->sampled_cfg, *cfg)) {
+        set_error("consume needs a prior ft_sample_points with the same samples_per_elem, seed, stream_id and "
+                  "precision");
+        return FT_E_ORDER;
+    }
+    if (cfg->n_fields > T->F_cap) {
+        // buffers may still be read by queued work of an earlier transfer
+        FT_TRY_HIP(hipStreamSynchronize(stream));
+        dev_free(T->beta);
+        dev_free(T->g);
+        dev_free(T->bres);
+        T->beta = T->g = T->bres = nullptr;
+        T->F_cap = 0;
+        const size_t F = size_t(cfg->n_fields);
+        FT_TRY(dev_alloc_n(&T->beta, F * size_t(T->E) * (T->dim + 1)));
+        FT_TRY(dev_alloc_n(&T->g, F * size_t(T->n)));
+        FT_TRY(dev_alloc_n(&T->bres, F * size_t(T->n)));
+        T->F_cap = cfg->n_fields;
+    }
+    T->consumed = false;
+    FT_TRY(consume_values(T, cfg, values, stream));
+    T->consumed = true;
+    T->consumed_cfg = *cfg;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep,
+                     hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t && cfg && x && rep, "null argument");
+    FT_ARG_CHECK(cfg->rtol >= 0.0 && std::isfinite(cfg->rtol), "rtol must be finite and >= 0");
+    FT_ARG_CHECK(cfg->max_iter >= 0, "max_iter must be >= 0");
+    if (!t->consumed) {
+        set_error("ft_project needs a prior ft_consume_queries");
+        return FT_E_ORDER;
+    }
+    return project(t, cfg, x, b_out, rep, stream);
+    FT_GUARD_END
+}
+
+ft_status ft_source_create_p1(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems,
+                              const int32_t* conn, int32_t n_fields, const double* nodal_values, const int32_t* bins,
+                              hipStream_t stream, ft_source** out) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(out, "out is null");
+    *out = nullptr;
+    FT_ARG_CHECK(dim == 2 || dim == 3, "dim must be 2 or 3 (got %d)", dim);
+    FT_ARG_CHECK(coords && conn && nodal_values, "coords, conn and nodal_values must be device pointers");
+    FT_ARG_CHECK(n_nodes >= dim + 1 && n_nodes < INT32_MAX, "n_nodes out of range (%lld)", (long long)n_nodes);
+    FT_ARG_CHECK(n_elems >= 1 && n_elems < INT32_MAX, "n_elems out of range (%lld)", (long long)n_elems);
+    FT_ARG_CHECK(n_fields >= 1, "n_fields must be >= 1");
+    if (bins)
+        for (int c = 0; c < dim; ++c) FT_ARG_CHECK(bins[c] >= 0, "bins must be >= 0 (0 = default)");
+    auto* S = new ft_source();
+    S->dim = dim;
+    S->n = n_nodes;
+    S->E = n_elems;
+    S->F = n_fields;
+    const ft_status st = source_setup(S, coords, conn, nodal_values, bins, stream);
+    if (st != FT_OK) {
+        (void)hipStreamSynchronize(stream);
+        source_release(S);
+        delete S;
+        return st;
+    }
+    *out = S;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_source_eval(ft_source* s, int64_t n_points, const void* points, int64_t ld, int32_t precision,
+                         void* values, int64_t ld_out, int32_t* elem_ids, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(s, "source is null");
+    FT_ARG_CHECK(n_points >= 0, "n_points must be >= 0");
+    FT_ARG_CHECK(n_points == 0 || (points && values), "points and values must be device pointers");
+    FT_ARG_CHECK(ld >= n_points && ld_out >= n_points, "leading dimensions must be >= n_points");
+    FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
+    FT_ARG_CHECK(n_points < (int64_t(1) << 39), "n_points too large");
+    return source_eval(s, n_points, points, ld, precision, values, ld_out, elem_ids, stream);
+    FT_GUARD_END
+}
+
+ft_status ft_source_get_info(const ft_source* s, ft_source_info* info) {
+    clear_error();
+    FT_ARG_CHECK(s && info, "null argument");
+    info->dim = s->dim;
+    info->n_fields = s->F;
+    info->n_nodes = s->n;
+    info->n_elems = s->E;
+    for (int c = 0; c < 3; ++c) info->bins[c] = s->nb[c];
+    info->n_registrations = s->n_reg;
+    return FT_OK;
+}
+
+ft_status ft_source_stats(ft_source* s, int64_t* n_out_of_domain, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(s && n_out_of_domain, "null argument");
+    FT_TRY_HIP(hipMemcpyAsync(s->h_counters, s->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+    FT_TRY_HIP(hipMemsetAsync(s->counters, 0, sizeof(unsigned long long), stream));
+    FT_TRY_HIP(hipStreamSynchronize(stream));
+    *n_out_of_domain = int64_t(s->h_counters[0]);
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_source_destroy(ft_source* s) {
+    if (!s) return FT_OK;
+    source_release(s);
+    delete s;
+    return FT_OK;
+}
+
+const char* ft_last_error(void) { return ft::last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+// Internal helpers shared by the HIP translation units of libft.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/ft.h"
+
+namespace ft {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define FT_TRY_HIP(expr)                                                          \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::ft::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                  \
+            return FT_E_DEVICE;                                                   \
+        }                                                                         \
+    } while (0)
+
+#define FT_TRY(expr)                     \
+    do {                                 \
+        ft_status s_ = (expr);           \
+        if (s_ != FT_OK) return s_;      \
+    } while (0)
+
+#define FT_ARG_CHECK(cond, ...)                 \
+    do {                                        \
+        if (!(cond)) {                          \
+            ::ft::set_error(__VA_ARGS__);       \
+            return FT_E_ARG;                    \
+        }                                       \
+    } while (0)
+
+// Device allocation that reports FT_E_OOM (and honours an optional byte cap
+// from the FT_MAX_BYTES environment variable, for failure-path tests).
+ft_status dev_alloc(void** p, size_t bytes);
+template <class T>
+ft_status dev_alloc_n(T** p, size_t n) { return dev_alloc(reinterpret_cast<void**>(p), n * sizeof(T) + 8); }
+void dev_free(void* p);
+
+// Frees registered scratch allocations when a setup routine returns.
+struct ScratchGuard {
+    void** ps[16];
+    int count = 0;
+    void add(void** p) { ps[count++] = p; }
+    ~ScratchGuard() {
+        for (int i = 0; i < count; ++i) {
+            dev_free(*ps[i]);
+            *ps[i] = nullptr;
+        }
+    }
+};
+
+inline unsigned int grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned int)(g < 1 ? 1 : g);
+}
+
+// Exclusive scan of n int32 counts into n+1 int64 offsets (device arrays,
+// work enqueued on stream; `tmp` must hold scan_tmp_elems(n) int64).
+int64_t scan_tmp_elems(int64_t n);
+ft_status exclusive_scan(const int32_t* counts, int64_t* offsets, int64_t n, int64_t* tmp, hipStream_t s);
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): ten rounds of two 32x32->64-bit
+// multiplications per 4-word counter block, key bumped by the Weyl constants
+// between rounds.
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// (2m+1) 2^-53 with m = ((a<<32)|b) >> 12, built exactly from the bit pattern
+// 1.m (a double in [1,2)): (1 + m 2^-52) - 1 + 2^-53, all three steps exact.
+__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
+    const uint64_t m = ((uint64_t(a) << 32) | b) >> 12;
+    const double one_m = __longlong_as_double((long long)(0x3FF0000000000000ull | m));
+    return (one_m - 1.0) + 0x1p-53;
+}
+
+// (2k+1) 2^-24 with k the top 23 bits of the same m, i.e. a >> 9.
+__device__ __forceinline__ float uniform24(uint32_t a) {
+    const float one_k = __uint_as_float(0x3F800000u | (a >> 9));
+    return (one_k - 1.0f) + 0x1p-24f;
+}
+
+// ---------------------------------------------------------------- division by an invariant
+// Unsigned 32-bit division by a runtime-invariant d >= 1 with one multiply-high
+// (Granlund & Montgomery, "Division by invariant integers using multiplication",
+// PLDI 1994): l = ceil(log2 d), m' = floor(2^32 (2^l - d) / d) + 1,
+// q = (t + ((n - t) >> min(l,1))) >> max(l-1, 0) with t = mulhi(m', n).
+struct FastDiv {
+    uint32_t d, mul, sh1, sh2;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+    return FastDiv{d, uint32_t(m), l < 1 ? l : 1u, l > 1 ? l - 1 : 0u};
+}
+
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv& f) {
+    const uint32_t t = __umulhi(f.mul, n);
+    return (t + ((n - t) >> f.sh1)) >> f.sh2;
+}
+
+// ---------------------------------------------------------------- wave helpers (wave64)
+__device__ __forceinline__ double wave_sum_xor(double v, int width) {
+    for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int read_lane(int v, int lane) {
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+__device__ __forceinline__ int uniform_int(int v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+}  // namespace ft
+
+// ---------------------------------------------------------------- handles
+struct ft_target {
+    int dim = 0;
+    int64_t n = 0, E = 0, nnz = 0, n_inverted = 0;
+    // mesh copies
+    double* coords = nullptr;   // [dim][n]
+    int32_t* conn = nullptr;    // [E][dim+1]
+    double* vol = nullptr;      // [E]
+    // mass matrix (CSR) and derived vectors
+    int64_t* rowptr = nullptr;  // [n+1]
+    int32_t* col = nullptr;     // [nnz]
+    double* val = nullptr;      // [nnz]
+    double* diag = nullptr;     // [n]
+    double* lumped = nullptr;   // [n] m = M 1
+    // node -> (element, local vertex) incidence, entries t*(dim+1)+k ascending
+    int64_t* inc_ptr = nullptr; // [n+1]
+    int32_t* inc = nullptr;     // [E*(dim+1)]
+    // per-transfer state
+    int F_cap = 0;
+    double* beta = nullptr;     // [F][E][dim+1]
+    double* g = nullptr;        // [F][n]
+    double* bres = nullptr;     // [F][n]
+    // solver work vectors and reduction scratch
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *y = nullptr, *b = nullptr;
+    double* scal = nullptr;               // device scalars
+    double* partials = nullptr;           // per-block partial sums
+    unsigned int* ticket = nullptr;       // last-block counters
+    unsigned long long* counters = nullptr;  // [0] non-finite values seen by consume
+    double* h_scal = nullptr;             // pinned host mirror
+    int reduce_blocks = 0;
+    // call-order state
+    bool consumed = false;
+    ft_sample_cfg consumed_cfg{};
+};
+
+struct ft_source {
+    int dim = 0;
+    int64_t n = 0, E = 0;
+    int F = 0;
+    double* coords = nullptr;   // [dim][n]
+    int32_t* conn = nullptr;    // [E][dim+1]
+    double* values = nullptr;   // [F][n]
+    double* rec = nullptr;      // [E][RS]: origin + inverse Jacobian (barycentric map)
+    float* box = nullptr;       // [E][2*dim] outward-rounded bounding boxes
+    int32_t nb[3] = {1, 1, 1};  // bins per axis
+    double lo[3] = {0, 0, 0};   // grid origin
+    double inv_h[3] = {1, 1, 1};// bins per unit length
+    int64_t* bin_ptr = nullptr; // [nbins+1]
+    int32_t* bin_elems = nullptr;
+    int64_t n_reg = 0;
+    unsigned long long* counters = nullptr;  // [0] out-of-domain points
+    unsigned long long* h_counters = nullptr;
+};

@@ -1,0 +1,247 @@
+// Sample emission and consumption: the Monte Carlo part of the CV-MC load vector.
+//
+// Emission (sec. 4.1 step 1 and step 3) writes the point-query list: the n
+// target nodes, then sample j of element t at position n + t*N + j.
+//
+// Consumption (sec. 4.1 steps 4-6) forms, for every element t and local
+// vertex k, the residual element load of Eq. cv_element_load_residual_operator
+// with the uniform density of Eq. mc_element_integral_operator_uniform:
+//   beta_tk = |Omega_t| / N * sum_j (y_tj - alpha g(X_tj)) psi_k(X_tj),
+// where psi_k(X_tj) = lambda_k of the sample (P1 basis = barycentric
+// coordinates) and g(X_tj) = sum_l lambda_l g_{v_l} (the control, P1 on the
+// target).  lambda is regenerated from the same Philox counters instead of
+// being stored.  Then b_res,v = sum of beta_tk over the incidence list of v.
+//
+// Thread mapping of the consume kernel: a group of G lanes (G = smallest
+// power of two >= N, at most 64) per element; lanes stride over the samples
+// (coalesced reads of y), keep per-lane partial sums, and the group reduces
+// them with a fixed butterfly.  No floating-point atomics anywhere, so results
+// are bitwise reproducible run to run.
+#include "sampling.h"
+
+namespace ft {
+
+template <int D, bool F32>
+__global__ __launch_bounds__(256) void k_emit(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
+                                              uint32_t total, uint32_t N, FastDiv divN, SampleKey key,
+                                              void* __restrict__ out_, int64_t ld) {
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    if (idx >= total) return;
+    const uint32_t t = fast_div(idx, divN);
+    const uint32_t j = idx - t * N;
+    int v[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
+    const int64_t q = n + int64_t(idx);
+    if constexpr (!F32) {
+        double lam[D + 1];
+        sample_lambda<D>(t, j, key, lam);
+        double* out = static_cast<double*>(out_);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double x = lam[0] * X[c * n + v[0]];
+#pragma unroll
+            for (int k = 1; k <= D; ++k) x = fma(lam[k], X[c * n + v[k]], x);
+            out[c * ld + q] = x;
+        }
+    } else {
+        float lam[D + 1];
+        sample_lambda_f32<D>(t, j, key, lam);
+        float* out = static_cast<float*>(out_);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            float x = lam[0] * float(X[c * n + v[0]]);
+#pragma unroll
+            for (int k = 1; k <= D; ++k) x = fmaf(lam[k], float(X[c * n + v[k]]), x);
+            out[c * ld + q] = x;
+        }
+    }
+}
+
+template <bool F32>
+__global__ void k_emit_nodes(const double* __restrict__ X, int64_t n, int dim, void* __restrict__ out_, int64_t ld) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < dim; ++c) {
+        if (F32)
+            static_cast<float*>(out_)[c * ld + i] = float(X[c * n + i]);
+        else
+            static_cast<double*>(out_)[c * ld + i] = X[c * n + i];
+    }
+}
+
+template <int D, int G, int FC, bool F32>
+__global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, int64_t ld, int F,
+                                                 const int32_t* __restrict__ conn, const double* __restrict__ vol,
+                                                 int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
+                                                 double* __restrict__ beta, unsigned long long* __restrict__ nonfinite) {
+    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t t = gid / G;
+    const int lane = int(gid & (G - 1));
+    if (t >= E) return;   // the whole group leaves together
+    int v[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
+    const double scale = vol[t] / double(N);
+    const int64_t qbase = n + int64_t(t) * N;
+    unsigned int nf = 0;
+    for (int f0 = 0; f0 < F; f0 += FC) {
+        double gk[FC][D + 1];
+        double acc[FC][D + 1];
+#pragma unroll
+        for (int f = 0; f < FC; ++f)
+#pragma unroll
+            for (int k = 0; k <= D; ++k) {
+                acc[f][k] = 0.0;
+                const int64_t off = int64_t(f0 + f < F ? f0 + f : 0) * ld + v[k];
+                gk[f][k] = F32 ? double(static_cast<const float*>(values_)[off])
+                               : static_cast<const double*>(values_)[off];
+            }
+        for (uint32_t j = lane; j < N; j += G) {
+            double lam[D + 1];
+            if constexpr (F32) {
+                float lf[D + 1];
+                sample_lambda_f32<D>(t, j, key, lf);
+#pragma unroll
+                for (int k = 0; k <= D; ++k) lam[k] = lf[k];
+            } else {
+                sample_lambda<D>(t, j, key, lam);
+            }
+#pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                if (f0 + f >= F) break;
+                const int64_t off = int64_t(f0 + f) * ld + qbase + j;
+                const double y = F32 ? double(static_cast<const float*>(values_)[off])
+                                     : static_cast<const double*>(values_)[off];
+                nf += !isfinite(y);
+                double gx = lam[0] * gk[f][0];
+#pragma unroll
+                for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
+                const double r = y - alpha * gx;
+#pragma unroll
+                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < FC; ++f)
+#pragma unroll
+            for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
+        if (lane == 0) {
+#pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                if (f0 + f >= F) break;
+#pragma unroll
+                for (int k = 0; k <= D; ++k) beta[(int64_t(f0 + f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+            }
+        }
+    }
+    if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
+}
+
+// b_res,v = sum over the incidence list of v (ascending (t, k)) of beta; also
+// keeps g_v = values[f][v] (the control at the nodes) for the solve.
+template <int D, bool F32>
+__global__ void k_assemble(const double* __restrict__ beta, int64_t E, const int64_t* __restrict__ inc_ptr,
+                           const int32_t* __restrict__ inc, int64_t n, int F, const void* __restrict__ values_,
+                           int64_t ld, double* __restrict__ bres, double* __restrict__ g) {
+    const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
+    for (int f = 0; f < F; ++f) {
+        const double* bf = beta + int64_t(f) * E * (D + 1);
+        double s = 0.0;
+        for (int64_t i = b; i < e; ++i) s += bf[inc[i]];
+        bres[int64_t(f) * n + v] = s;
+        const int64_t off = int64_t(f) * ld + v;
+        g[int64_t(f) * n + v] = F32 ? double(static_cast<const float*>(values_)[off])
+                                    : static_cast<const double*>(values_)[off];
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int n) {
+    if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------- host side
+static SampleKey make_key(const ft_sample_cfg* cfg) {
+    return SampleKey{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
+}
+
+template <int D>
+static ft_status emit_impl(ft_target* T, const ft_sample_cfg* cfg, void* points, hipStream_t s) {
+    const uint32_t N = uint32_t(cfg->samples_per_elem);
+    const uint64_t total = uint64_t(T->E) * N;
+    const int64_t ld = T->n + int64_t(total);
+    const bool f32 = cfg->precision == FT_F32;
+    if (f32)
+        k_emit_nodes<true><<<grid_for(T->n, 256), 256, 0, s>>>(T->coords, T->n, D, points, ld);
+    else
+        k_emit_nodes<false><<<grid_for(T->n, 256), 256, 0, s>>>(T->coords, T->n, D, points, ld);
+    if (total) {
+        const FastDiv dv = make_fastdiv(N);
+        const SampleKey key = make_key(cfg);
+        const unsigned grid = grid_for(int64_t(total), 256);
+        if (f32)
+            k_emit<D, true><<<grid, 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(total), N, dv, key, points, ld);
+        else
+            k_emit<D, false><<<grid, 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(total), N, dv, key, points, ld);
+    }
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
+ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipStream_t s) {
+    return T->dim == 2 ? emit_impl<2>(T, cfg, points, s) : emit_impl<3>(T, cfg, points, s);
+}
+
+template <int D, int G, int FC, bool F32>
+static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, hipStream_t s) {
+    const SampleKey key = make_key(cfg);
+    const unsigned grid = grid_for(T->E * G, 256);
+    k_consume<D, G, FC, F32><<<grid, 256, 0, s>>>(values, ld, cfg->n_fields, T->conn, T->vol, T->n, uint32_t(T->E),
+                                                  uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->beta,
+                                                  T->counters);
+}
+
+template <int D, int G, bool F32>
+static void consume_fc(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, hipStream_t s) {
+    if (cfg->n_fields == 1)
+        launch_consume<D, G, 1, F32>(T, cfg, values, ld, s);
+    else
+        launch_consume<D, G, 4, F32>(T, cfg, values, ld, s);
+}
+
+template <int D, bool F32>
+static void consume_g(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, hipStream_t s) {
+    const int N = cfg->samples_per_elem;
+    if (N >= 64) consume_fc<D, 64, F32>(T, cfg, values, ld, s);
+    else if (N > 16) consume_fc<D, 32, F32>(T, cfg, values, ld, s);
+    else if (N > 8) consume_fc<D, 16, F32>(T, cfg, values, ld, s);
+    else if (N > 4) consume_fc<D, 8, F32>(T, cfg, values, ld, s);
+    else if (N > 2) consume_fc<D, 4, F32>(T, cfg, values, ld, s);
+    else if (N > 1) consume_fc<D, 2, F32>(T, cfg, values, ld, s);
+    else consume_fc<D, 1, F32>(T, cfg, values, ld, s);
+}
+
+template <int D>
+static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
+    const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
+    const bool f32 = cfg->precision == FT_F32;
+    k_zero_u64<<<1, 64, 0, s>>>(T->counters, 1);   // a kernel, not a memset: safe inside captured graphs
+    if (f32) consume_g<D, true>(T, cfg, values, ld, s);
+    else consume_g<D, false>(T, cfg, values, ld, s);
+    if (f32)
+        k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n,
+                                                               cfg->n_fields, values, ld, T->bres, T->g);
+    else
+        k_assemble<D, false><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n,
+                                                                cfg->n_fields, values, ld, T->bres, T->g);
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
+ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
+    return T->dim == 2 ? consume_impl<2>(T, cfg, values, s) : consume_impl<3>(T, cfg, values, s);
+}
+
+}  // namespace ft

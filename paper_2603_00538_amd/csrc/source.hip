@@ -1,0 +1,529 @@
+// Built-in P1 source: uniform-grid point localization and P1 evaluation.
+//
+// Benchmarks need a source that can only be queried at points (sec. 2, the
+// black-box setting); here it is a P1 field on a source mesh, localized with
+// a uniform grid of bins as in sec. 5.3 (int(L sqrt(#elements)) cells per
+// axis by default).
+//
+// Localization rule: the element maximizing min_k mu_k(x) (mu: barycentric
+// coordinates); exact ties -> lowest element id; a best min mu below -1e-10
+// is out of the domain (counted, extrapolated from that element).  A point
+// whose best element has min mu > 1e-12 is strictly inside it, and no other
+// element can tie or win, so the search stops there.
+//
+// Layout: every source element e has a record rec[e*RS ...] = (x0, A) with A
+// the inverse of J = [x1-x0 | ... | xd-x0], so mu_{k+1} = sum_c A[k][c] (x-x0)_c
+// and mu_0 = 1 - sum mu; plus an outward-rounded binary32 bounding box.  Bins
+// hold the ids of every element whose box overlaps them (CSR, ascending ids).
+//
+// The evaluation kernel works one wavefront at a time: the 64 points of a
+// wave are usually samples of one target element, so they share a handful of
+// bins.  The wave computes its own bounding box, culls each bin's candidates
+// 64 at a time against it (one candidate per lane, a ballot), and then every
+// lane tests its point against each surviving candidate, whose record is
+// wave-uniform (scalar loads).  Waves whose points span many bins (scattered
+// input) fall back to one bin per lane.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace ft {
+
+constexpr double kInsideTau = 1e-12;
+constexpr double kOutTol = -1e-10;
+
+template <int D>
+struct RecSize { static constexpr int value = D == 2 ? 8 : 16; };
+
+__device__ __forceinline__ float f32_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+__device__ __forceinline__ float f32_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+struct GridView {
+    int32_t nb[3];
+    double lo[3];
+    double inv_h[3];
+};
+
+// Bin index along axis c; monotone in x, so a point inside a box always maps
+// into the box's bin range.  NaN maps to bin 0.
+__device__ __forceinline__ int bin_of(double x, int c, const GridView& g) {
+    double u = (x - g.lo[c]) * g.inv_h[c];
+    u = fmin(fmax(u, 0.0), double(g.nb[c] - 1));
+    return int(u);
+}
+
+template <int D>
+__global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
+                           double* __restrict__ rec, float* __restrict__ box, unsigned long long* __restrict__ flags) {
+    constexpr int RS = RecSize<D>::value;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int v[D + 1];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        v[k] = conn[e * (D + 1) + k];
+        bad |= (v[k] < 0) | (int64_t(v[k]) >= n);
+    }
+    if (bad) {
+        atomicAdd(&flags[0], 1ull);
+        return;
+    }
+    double x[D + 1][D];
+#pragma unroll
+    for (int k = 0; k <= D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[k][c] = X[c * n + v[k]];
+    double J[D][D];   // J[c][k] = x_{k+1,c} - x_{0,c}
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int k = 0; k < D; ++k) J[c][k] = x[k + 1][c] - x[0][c];
+    double A[D][D], det;
+    if constexpr (D == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        A[0][0] = J[1][1] / det;
+        A[0][1] = -J[0][1] / det;
+        A[1][0] = -J[1][0] / det;
+        A[1][1] = J[0][0] / det;
+    } else {
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        // inverse = adjugate / det (rows of A index the barycentric coordinate)
+        A[0][0] = c00 / det;
+        A[1][0] = c01 / det;
+        A[2][0] = c02 / det;
+        A[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        A[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        A[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        A[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        A[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        A[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    double h2 = 0.0;
+#pragma unroll
+    for (int a = 0; a <= D; ++a)
+#pragma unroll
+        for (int b = a + 1; b <= D; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) s += (x[b][c] - x[a][c]) * (x[b][c] - x[a][c]);
+            h2 = fmax(h2, s);
+        }
+    const double hd = D == 2 ? h2 : h2 * sqrt(h2);
+    if (!(fabs(det) > 1e-12 * hd)) atomicAdd(&flags[1], 1ull);
+    double* r = rec + e * RS;
+#pragma unroll
+    for (int c = 0; c < D; ++c) r[c] = x[0][c];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) r[D + k * D + c] = A[k][c];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        double lo = x[0][c], hi = x[0][c];
+#pragma unroll
+        for (int k = 1; k <= D; ++k) {
+            lo = fmin(lo, x[k][c]);
+            hi = fmax(hi, x[k][c]);
+        }
+        box[e * 2 * D + c] = f32_down(lo);
+        box[e * 2 * D + D + c] = f32_up(hi);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void elem_bin_range(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
+                                               int64_t e, const GridView& g, int (&b0)[3], int (&b1)[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { b0[c] = 0; b1[c] = 0; }
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        double lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) {
+            const double xv = X[c * n + conn[e * (D + 1) + k]];
+            lo = fmin(lo, xv);
+            hi = fmax(hi, xv);
+        }
+        b0[c] = bin_of(lo, c, g);
+        b1[c] = bin_of(hi, c, g);
+    }
+}
+
+template <int D, bool FILL>
+__global__ void k_src_register(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
+                               GridView g, int32_t* __restrict__ cnt, const int64_t* __restrict__ ptr,
+                               int32_t* __restrict__ elems) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int b0[3], b1[3];
+    elem_bin_range<D>(X, n, conn, e, g, b0, b1);
+    for (int bz = b0[2]; bz <= b1[2]; ++bz)
+        for (int by = b0[1]; by <= b1[1]; ++by)
+            for (int bx = b0[0]; bx <= b1[0]; ++bx) {
+                const int64_t b = (int64_t(bz) * g.nb[1] + by) * g.nb[0] + bx;
+                if (!FILL) {
+                    atomicAdd(&cnt[b], 1);
+                } else {
+                    const int pos = atomicAdd(&cnt[b], 1);
+                    elems[ptr[b] + pos] = int32_t(e);
+                }
+            }
+}
+
+__global__ void k_minmax(const double* __restrict__ X, int64_t n, int dim, double* __restrict__ out) {
+    // out[(blockIdx.x * dim + c) * 2 + {0,1}] = block min / max of coordinate c
+    __shared__ double smin[256], smax[256];
+    for (int c = 0; c < dim; ++c) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+            lo = fmin(lo, X[c * n + i]);
+            hi = fmax(hi, X[c * n + i]);
+        }
+        smin[threadIdx.x] = lo;
+        smax[threadIdx.x] = hi;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+                smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            out[(blockIdx.x * dim + c) * 2 + 0] = smin[0];
+            out[(blockIdx.x * dim + c) * 2 + 1] = smax[0];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_sort_bins(const int64_t* __restrict__ ptr, int64_t nseg, int32_t* __restrict__ data) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    int32_t* a = data + ptr[s];
+    const int64_t len = ptr[s + 1] - ptr[s];
+    for (int64_t i = 1; i < len; ++i) {
+        const int32_t x = a[i];
+        int64_t j = i - 1;
+        while (j >= 0 && a[j] > x) {
+            a[j + 1] = a[j];
+            --j;
+        }
+        a[j + 1] = x;
+    }
+}
+
+// ---------------------------------------------------------------- evaluation
+struct SrcView {
+    const double* rec;
+    const float* box;
+    const int32_t* conn;
+    const double* values;
+    const int64_t* bin_ptr;
+    const int32_t* bin_elems;
+    int64_t n;
+    int F;
+    GridView g;
+};
+
+template <int D>
+__device__ __forceinline__ void test_candidate(const double* __restrict__ r, int e, const double (&p)[D], double& best,
+                                               int& bid, double (&bmu)[D + 1]) {
+    double d[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) d[c] = p[c] - r[c];
+    double mu[D + 1];
+    mu[0] = 1.0;
+    double mn = INFINITY;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) s = fma(r[D + k * D + c], d[c], s);
+        mu[k + 1] = s;
+        mu[0] -= s;
+        mn = fmin(mn, s);
+    }
+    mn = fmin(mn, mu[0]);
+    const bool better = (mn > best) || (mn == best && e < bid);
+    if (better) {
+        best = mn;
+        bid = e;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) bmu[k] = mu[k];
+    }
+}
+
+template <int D, bool IN_F32, bool OUT_F32>
+__global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t npts, const void* __restrict__ pts_, int64_t ld,
+                                                  void* __restrict__ out_, int64_t ld_out, int32_t* __restrict__ ids,
+                                                  unsigned long long* __restrict__ n_ood) {
+    constexpr int RS = RecSize<D>::value;
+    constexpr int MAX_SPAN = D == 2 ? 4 : 8;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = i < npts;
+    double p[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        if (IN_F32)
+            p[c] = active ? double(static_cast<const float*>(pts_)[c * ld + i]) : 0.0;
+        else
+            p[c] = active ? static_cast<const double*>(pts_)[c * ld + i] : 0.0;
+    }
+    if (!__any(active)) return;
+    double wlo[D], whi[D];
+    int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
+    int span = 1;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        wlo[c] = wave_min(active ? p[c] : INFINITY);
+        whi[c] = wave_max(active ? p[c] : -INFINITY);
+        b0[c] = uniform_int(bin_of(wlo[c], c, S.g));
+        b1[c] = uniform_int(bin_of(whi[c], c, S.g));
+        span *= b1[c] - b0[c] + 1;
+    }
+    double best = -DBL_MAX;
+    int bid = INT_MAX;
+    double bmu[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) bmu[k] = 0.0;
+
+    if (span <= MAX_SPAN) {
+        float flo[D], fhi[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            flo[c] = f32_down(wlo[c]);
+            fhi[c] = f32_up(whi[c]);
+        }
+        bool finished = false;
+        for (int bz = b0[2]; bz <= b1[2] && !finished; ++bz)
+            for (int by = b0[1]; by <= b1[1] && !finished; ++by)
+                for (int bx = b0[0]; bx <= b1[0] && !finished; ++bx) {
+                    const int64_t b = (int64_t(bz) * S.g.nb[1] + by) * S.g.nb[0] + bx;
+                    const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
+                    for (int64_t c0 = start; c0 < end && !finished; c0 += 64) {
+                        int cid = -1;
+                        bool ov = false;
+                        if (c0 + lane < end) {
+                            cid = S.bin_elems[c0 + lane];
+                            const float* bx_ = S.box + int64_t(cid) * 2 * D;
+                            ov = true;
+#pragma unroll
+                            for (int c = 0; c < D; ++c) ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
+                        }
+                        uint64_t mask = __ballot(ov);
+                        while (mask) {
+                            const int l = __ffsll((unsigned long long)mask) - 1;
+                            mask &= mask - 1;
+                            const int e = read_lane(cid, l);
+                            test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid, bmu);
+                            if (__all(!active || best > kInsideTau)) {
+                                finished = true;
+                                break;
+                            }
+                        }
+                    }
+                }
+    } else {
+        int64_t b = 0;
+        {
+            int bc[3] = {0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < D; ++c) bc[c] = bin_of(p[c], c, S.g);
+            b = (int64_t(bc[2]) * S.g.nb[1] + bc[1]) * S.g.nb[0] + bc[0];
+        }
+        if (active) {
+            const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
+            for (int64_t c = start; c < end; ++c) {
+                const int e = S.bin_elems[c];
+                test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid, bmu);
+                if (best > kInsideTau) break;
+            }
+        }
+    }
+
+    const bool found = bid != INT_MAX;
+    const bool ood = active && (!found || best < kOutTol);
+    const uint64_t om = __ballot(ood);
+    if (lane == 0 && om) atomicAdd(n_ood, (unsigned long long)__popcll(om));
+    if (!active) return;
+    if (ids) ids[i] = found ? bid : -1;
+    int vtx[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) vtx[k] = found ? S.conn[int64_t(bid) * (D + 1) + k] : 0;
+    for (int f = 0; f < S.F; ++f) {
+        double y = 0.0;
+        if (found) {
+            const double* Fv = S.values + int64_t(f) * S.n;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) y = fma(bmu[k], Fv[vtx[k]], y);
+        }
+        if (OUT_F32)
+            static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
+        else
+            static_cast<double*>(out_)[int64_t(f) * ld_out + i] = y;
+    }
+}
+
+// ---------------------------------------------------------------- host side
+template <int D>
+static ft_status build(ft_source* S, const double* coords, const int32_t* conn, const double* values,
+                       const int32_t* bins, hipStream_t s) {
+    constexpr int RS = RecSize<D>::value;
+    const int64_t n = S->n, E = S->E;
+    constexpr int B = 256;
+    FT_TRY(dev_alloc_n(&S->coords, size_t(D) * n));
+    FT_TRY(dev_alloc_n(&S->conn, size_t(E) * (D + 1)));
+    FT_TRY(dev_alloc_n(&S->values, size_t(S->F) * n));
+    FT_TRY(dev_alloc_n(&S->rec, size_t(E) * RS));
+    FT_TRY(dev_alloc_n(&S->box, size_t(E) * 2 * D));
+    FT_TRY(dev_alloc_n(&S->counters, 4));
+    FT_TRY_HIP(hipHostMalloc((void**)&S->h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+    FT_TRY_HIP(hipMemcpyAsync(S->coords, coords, sizeof(double) * D * n, hipMemcpyDeviceToDevice, s));
+    FT_TRY_HIP(hipMemcpyAsync(S->conn, conn, sizeof(int32_t) * (D + 1) * E, hipMemcpyDeviceToDevice, s));
+    FT_TRY_HIP(hipMemcpyAsync(S->values, values, sizeof(double) * S->F * n, hipMemcpyDeviceToDevice, s));
+    FT_TRY_HIP(hipMemsetAsync(S->counters, 0, 4 * sizeof(unsigned long long), s));
+
+    unsigned long long* flags = nullptr;
+    double* mm = nullptr;
+    int32_t* cnt = nullptr;
+    int64_t* tmp = nullptr;
+    ScratchGuard guard;
+    guard.add((void**)&flags);
+    guard.add((void**)&mm);
+    guard.add((void**)&cnt);
+    guard.add((void**)&tmp);
+    FT_TRY(dev_alloc_n(&flags, 4));
+    FT_TRY_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned long long), s));
+    k_src_geom<D><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, S->rec, S->box, flags);
+    const int mmb = 256;
+    FT_TRY(dev_alloc_n(&mm, size_t(mmb) * D * 2));
+    k_minmax<<<mmb, 256, 0, s>>>(S->coords, n, D, mm);
+    FT_TRY_HIP(hipGetLastError());
+    unsigned long long hf[4];
+    std::vector<double> hmm(size_t(mmb) * D * 2);
+    FT_TRY_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipMemcpyAsync(hmm.data(), mm, sizeof(double) * hmm.size(), hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    if (hf[0]) {
+        set_error("%llu source element(s) reference a node id outside [0, %lld)", hf[0], (long long)n);
+        return FT_E_MESH;
+    }
+    if (hf[1]) {
+        set_error("%llu degenerate source element(s): |det J| <= 1e-12 h^d", hf[1]);
+        return FT_E_MESH;
+    }
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, ext_max = 0.0;
+    for (int c = 0; c < D; ++c) {
+        lo[c] = INFINITY;
+        hi[c] = -INFINITY;
+        for (int b = 0; b < mmb; ++b) {
+            lo[c] = std::fmin(lo[c], hmm[(b * D + c) * 2]);
+            hi[c] = std::fmax(hi[c], hmm[(b * D + c) * 2 + 1]);
+        }
+        ext_max = std::fmax(ext_max, hi[c] - lo[c]);
+    }
+    // default bins: int(sqrt(E)) (2D) or round(cbrt(E/6)) (3D) along the longest axis
+    const double per_axis = D == 2 ? std::floor(std::sqrt(double(E))) : std::round(std::cbrt(double(E) / 6.0));
+    int64_t nbins = 1;
+    for (int c = 0; c < D; ++c) {
+        int32_t nb = bins && bins[c] > 0 ? bins[c] : 0;
+        if (nb == 0) {
+            const double ext = hi[c] - lo[c];
+            nb = int32_t(std::max(1.0, std::ceil(per_axis * (ext_max > 0 ? ext / ext_max : 1.0) - 1e-9)));
+        }
+        S->nb[c] = nb;
+        const double ext = hi[c] - lo[c];
+        S->lo[c] = lo[c];
+        S->inv_h[c] = ext > 0 ? double(nb) / ext : 0.0;
+        nbins *= nb;
+    }
+    if (nbins > (int64_t(1) << 30)) {
+        set_error("bin grid of %lld cells is too large", (long long)nbins);
+        return FT_E_ARG;
+    }
+    GridView g{};
+    for (int c = 0; c < 3; ++c) {
+        g.nb[c] = S->nb[c];
+        g.lo[c] = S->lo[c];
+        g.inv_h[c] = S->inv_h[c];
+    }
+    FT_TRY(dev_alloc_n(&cnt, size_t(nbins)));
+    FT_TRY(dev_alloc_n(&tmp, size_t(scan_tmp_elems(nbins))));
+    FT_TRY(dev_alloc_n(&S->bin_ptr, size_t(nbins + 1)));
+    FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
+    k_src_register<D, false><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, nullptr, nullptr);
+    FT_TRY(exclusive_scan(cnt, S->bin_ptr, nbins, tmp, s));
+    int64_t nreg = 0;
+    FT_TRY_HIP(hipMemcpyAsync(&nreg, S->bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    S->n_reg = nreg;
+    FT_TRY(dev_alloc_n(&S->bin_elems, size_t(nreg)));
+    FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
+    k_src_register<D, true><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, S->bin_ptr, S->bin_elems);
+    k_sort_bins<<<grid_for(nbins, B), B, 0, s>>>(S->bin_ptr, nbins, S->bin_elems);
+    FT_TRY_HIP(hipGetLastError());
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    return FT_OK;
+}
+
+ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, const double* values,
+                       const int32_t* bins, hipStream_t s) {
+    return S->dim == 2 ? build<2>(S, coords, conn, values, bins, s) : build<3>(S, coords, conn, values, bins, s);
+}
+
+template <int D>
+static ft_status launch_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
+                             int64_t ld_out, int32_t* ids, hipStream_t s) {
+    SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
+    for (int c = 0; c < 3; ++c) {
+        v.g.nb[c] = S->nb[c];
+        v.g.lo[c] = S->lo[c];
+        v.g.inv_h[c] = S->inv_h[c];
+    }
+    const unsigned grid = grid_for(npts, 256);
+    if (prec == FT_F64)
+        k_src_eval<D, false, false><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);
+    else
+        k_src_eval<D, true, true><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
+ft_status source_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
+                      int32_t* ids, hipStream_t s) {
+    if (npts == 0) return FT_OK;
+    return S->dim == 2 ? launch_eval<2>(S, npts, pts, ld, prec, out, ld_out, ids, s)
+                       : launch_eval<3>(S, npts, pts, ld, prec, out, ld_out, ids, s);
+}
+
+ft_status source_release(ft_source* S) {
+    dev_free(S->coords);
+    dev_free(S->conn);
+    dev_free(S->values);
+    dev_free(S->rec);
+    dev_free(S->box);
+    dev_free(S->bin_ptr);
+    dev_free(S->bin_elems);
+    dev_free(S->counters);
+    if (S->h_counters) (void)hipHostFree(S->h_counters);
+    return FT_OK;
+}
+
+}  // namespace ft

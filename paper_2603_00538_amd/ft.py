@@ -1,0 +1,299 @@
+"""ctypes binding of libft (include/ft.h).
+
+The functions ``ft_*`` mirror the C entry points one to one and only marshal
+arguments: every step of the transfer runs in the HIP library.  PyTorch
+supplies device memory and the current stream.  ``Target`` and ``Source`` are
+small conveniences that keep the mesh tensors in the layouts the library
+expects (structure-of-arrays coordinates, int32 connectivity).
+
+The library must be built (``python -m paper_2603_00538_amd.build``); there is
+no fallback: loading fails loudly if ``libft.so`` is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libft.so")
+
+FT_OK, FT_E_ARG, FT_E_MESH, FT_E_ORDER, FT_E_DEVICE, FT_E_NOCONV, FT_E_NONFINITE, FT_E_OOM, FT_E_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+FT_F64, FT_F32 = 0, 1
+STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -4: "FT_E_DEVICE",
+                -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
+
+EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
+            "ft_consume_queries", "ft_project", "ft_source_create_p1", "ft_source_eval", "ft_source_stats",
+            "ft_source_destroy", "ft_source_get_info", "ft_last_error"]
+
+
+class SampleCfg(ctypes.Structure):
+    _fields_ = [("samples_per_elem", ctypes.c_int32), ("n_fields", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("precision", ctypes.c_int32)]
+
+
+class SolveCfg(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("sum_b", ctypes.c_double), ("int_x", ctypes.c_double), ("cons_defect", ctypes.c_double),
+                ("rel_resid", ctypes.c_double), ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("n_nonfinite", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TargetInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("n_inverted", ctypes.c_int64)]
+
+
+class SourceInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_fields", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
+                ("n_elems", ctypes.c_int64), ("bins", ctypes.c_int32 * 3), ("n_registrations", ctypes.c_int64)]
+
+
+class FtError(RuntimeError):
+    def __init__(self, status: int, fn: str, msg: str):
+        super().__init__(f"{fn} -> {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libft.so (once); raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2603_00538_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ft_target_create": (I32, [I32, I64, P, I64, P, P, ctypes.POINTER(P)]),
+        "ft_target_destroy": (I32, [P]),
+        "ft_target_get_info": (I32, [P, ctypes.POINTER(TargetInfo)]),
+        "ft_query_count": (I64, [P, I32]),
+        "ft_sample_points": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
+        "ft_consume_queries": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
+        "ft_project": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P]),
+        "ft_source_create_p1": (I32, [I32, I64, P, I64, P, I32, P, P, P, ctypes.POINTER(P)]),
+        "ft_source_eval": (I32, [P, I64, P, I64, I32, P, I64, P, P]),
+        "ft_source_stats": (I32, [P, ctypes.POINTER(I64), P]),
+        "ft_source_destroy": (I32, [P]),
+        "ft_source_get_info": (I32, [P, ctypes.POINTER(SourceInfo)]),
+        "ft_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, fn: str, allow=()):
+    if status != FT_OK and status not in allow:
+        raise FtError(status, fn, load().ft_last_error().decode())
+    return status
+
+
+# ------------------------------------------------------------------ C entry points
+def ft_target_create(dim, n_nodes, coords_ptr, n_elems, conn_ptr, stream):
+    h = ctypes.c_void_p()
+    _check(load().ft_target_create(dim, n_nodes, coords_ptr, n_elems, conn_ptr, stream, ctypes.byref(h)),
+           "ft_target_create")
+    return h
+
+
+def ft_target_destroy(h):
+    return load().ft_target_destroy(h)
+
+
+def ft_target_get_info(h) -> TargetInfo:
+    info = TargetInfo()
+    _check(load().ft_target_get_info(h, ctypes.byref(info)), "ft_target_get_info")
+    return info
+
+
+def ft_query_count(h, samples_per_elem):
+    return load().ft_query_count(h, samples_per_elem)
+
+
+def ft_sample_points(h, cfg: SampleCfg, points_ptr, stream):
+    return _check(load().ft_sample_points(h, ctypes.byref(cfg), points_ptr, stream), "ft_sample_points")
+
+
+def ft_consume_queries(h, cfg: SampleCfg, values_ptr, stream):
+    return _check(load().ft_consume_queries(h, ctypes.byref(cfg), values_ptr, stream), "ft_consume_queries")
+
+
+def ft_project(h, cfg: SolveCfg, x_ptr, b_ptr, n_fields, stream, allow=(FT_E_NOCONV, FT_E_NONFINITE)):
+    reps = (Report * n_fields)()
+    st = _check(load().ft_project(h, ctypes.byref(cfg), x_ptr, b_ptr, reps, stream), "ft_project", allow)
+    return st, [r.as_dict() for r in reps]
+
+
+def ft_source_create_p1(dim, n_nodes, coords_ptr, n_elems, conn_ptr, n_fields, values_ptr, bins, stream):
+    h = ctypes.c_void_p()
+    b = None
+    if bins is not None:
+        b = (ctypes.c_int32 * 3)(*[int(v) for v in list(bins) + [0] * (3 - len(bins))])
+    _check(load().ft_source_create_p1(dim, n_nodes, coords_ptr, n_elems, conn_ptr, n_fields, values_ptr, b, stream,
+                                      ctypes.byref(h)), "ft_source_create_p1")
+    return h
+
+
+def ft_source_eval(h, n_points, points_ptr, ld, precision, values_ptr, ld_out, ids_ptr, stream):
+    return _check(load().ft_source_eval(h, n_points, points_ptr, ld, precision, values_ptr, ld_out, ids_ptr, stream),
+                  "ft_source_eval")
+
+
+def ft_source_stats(h, stream):
+    n = ctypes.c_int64()
+    _check(load().ft_source_stats(h, ctypes.byref(n), stream), "ft_source_stats")
+    return n.value
+
+
+def ft_source_destroy(h):
+    return load().ft_source_destroy(h)
+
+
+def ft_source_get_info(h) -> SourceInfo:
+    info = SourceInfo()
+    _check(load().ft_source_get_info(h, ctypes.byref(info)), "ft_source_get_info")
+    return info
+
+
+# ------------------------------------------------------------------ torch conveniences
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _soa(coords, device):
+    """(n, d) array/tensor -> contiguous (d, n) float64 device tensor."""
+    torch = _torch()
+    t = torch.as_tensor(coords, dtype=torch.float64)
+    return t.t().contiguous().to(device)
+
+
+@dataclass
+class Transfer:
+    """Result of one transfer (device tensors and host reports)."""
+    x: object
+    b: object
+    reports: list
+    status: int
+
+
+class Target:
+    """A P1 target mesh on the device (ft_target_create ... ft_target_destroy)."""
+
+    def __init__(self, coords, conn, device="cuda"):
+        torch = _torch()
+        self.dim = int(coords.shape[1])
+        self.coords = _soa(coords, device)                                  # (d, n)
+        self.conn = torch.as_tensor(conn, dtype=torch.int32).contiguous().to(device)
+        self.n_nodes = int(coords.shape[0])
+        self.n_elems = int(conn.shape[0])
+        self.handle = ft_target_create(self.dim, self.n_nodes, self.coords.data_ptr(), self.n_elems,
+                                       self.conn.data_ptr(), current_stream())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ft_target_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self):
+        return ft_target_get_info(self.handle)
+
+    def query_count(self, N):
+        return ft_query_count(self.handle, N)
+
+    def sample_points(self, cfg: SampleCfg, out=None):
+        torch = _torch()
+        Q = self.query_count(cfg.samples_per_elem)
+        dt = torch.float32 if cfg.precision == FT_F32 else torch.float64
+        if out is None:
+            out = torch.empty((self.dim, Q), dtype=dt, device=self.coords.device)
+        ft_sample_points(self.handle, cfg, out.data_ptr(), current_stream())
+        return out
+
+    def consume(self, cfg: SampleCfg, values):
+        ft_consume_queries(self.handle, cfg, values.data_ptr(), current_stream())
+
+    def project(self, n_fields=1, rtol=1e-14, max_iter=500, want_b=True, x=None, b=None):
+        torch = _torch()
+        if x is None:
+            x = torch.empty((n_fields, self.n_nodes), dtype=torch.float64, device=self.coords.device)
+        if want_b and b is None:
+            b = torch.empty((n_fields, self.n_nodes), dtype=torch.float64, device=self.coords.device)
+        st, reps = ft_project(self.handle, SolveCfg(rtol, max_iter), x.data_ptr(),
+                              b.data_ptr() if want_b else None, n_fields, current_stream())
+        return Transfer(x, b, reps, st)
+
+
+class Source:
+    """Mesh-backed P1 source with uniform-grid localization (ft_source_*)."""
+
+    def __init__(self, coords, conn, nodal_values, bins=None, device="cuda"):
+        torch = _torch()
+        self.dim = int(coords.shape[1])
+        self.coords = _soa(coords, device)
+        self.conn = torch.as_tensor(conn, dtype=torch.int32).contiguous().to(device)
+        v = torch.as_tensor(nodal_values, dtype=torch.float64)
+        if v.ndim == 1:
+            v = v[None, :]
+        self.values = v.contiguous().to(device)
+        self.n_fields = int(self.values.shape[0])
+        self.handle = ft_source_create_p1(self.dim, int(coords.shape[0]), self.coords.data_ptr(), int(conn.shape[0]),
+                                          self.conn.data_ptr(), self.n_fields, self.values.data_ptr(), bins,
+                                          current_stream())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ft_source_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval(self, points, out=None, ids=None, n_points=None):
+        """points: (d, ld) device tensor (float64 or float32); returns (F, ld) values."""
+        torch = _torch()
+        ld = int(points.shape[1])
+        n = ld if n_points is None else int(n_points)
+        prec = FT_F32 if points.dtype == torch.float32 else FT_F64
+        if out is None:
+            out = torch.empty((self.n_fields, ld), dtype=points.dtype, device=points.device)
+        ft_source_eval(self.handle, n, points.data_ptr(), ld, prec, out.data_ptr(), int(out.shape[1]),
+                       ids.data_ptr() if ids is not None else None, current_stream())
+        return out
+
+    @property
+    def info(self):
+        return ft_source_get_info(self.handle)
+
+    def take_out_of_domain(self):
+        return ft_source_stats(self.handle, current_stream())

@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI: symbols, struct layouts, argument validation.
+
+No call here reaches the GPU: every call is rejected by host validation first.
+"""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2603_00538_amd import ft
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ft.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ft.LIB_PATH):
+        pytest.skip("libft.so not built")
+    return ft.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ft_status|int64_t|const char\*)\s+(ft_\w+)\(", text, re.M)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared_functions() == sorted(ft.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    nm = shutil.which("nm")
+    if nm:
+        out = subprocess.run([nm, "-D", "--defined-only", ft.LIB_PATH], capture_output=True, text=True).stdout
+        exported = set(re.findall(r" T (ft_\w+)$", out, re.M))
+        assert set(_declared_functions()) <= exported
+
+
+def test_struct_layouts_match_header(tmp_path):
+    gcc = shutil.which("gcc")
+    if not gcc or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("gcc or HIP headers unavailable")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ft.h"\n'
+                   "#define P(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f))\n"
+                   "int main(void){\n"
+                   'printf("ft_sample_cfg %zu\\n", sizeof(ft_sample_cfg));\n'
+                   'printf("ft_solve_cfg %zu\\n", sizeof(ft_solve_cfg));\n'
+                   'printf("ft_report %zu\\n", sizeof(ft_report));\n'
+                   'printf("ft_target_info %zu\\n", sizeof(ft_target_info));\n'
+                   "P(ft_sample_cfg, alpha); P(ft_sample_cfg, seed); P(ft_sample_cfg, stream_id); "
+                   "P(ft_sample_cfg, precision);\n"
+                   "P(ft_report, iters); P(ft_report, status); P(ft_report, n_nonfinite);\n"
+                   "P(ft_target_info, n_nodes); P(ft_target_info, n_inverted);\n"
+                   "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True, capture_output=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split("\n")
+               if line)
+    assert int(got["ft_sample_cfg"]) == ctypes.sizeof(ft.SampleCfg)
+    assert int(got["ft_solve_cfg"]) == ctypes.sizeof(ft.SolveCfg)
+    assert int(got["ft_report"]) == ctypes.sizeof(ft.Report)
+    assert int(got["ft_target_info"]) == ctypes.sizeof(ft.TargetInfo)
+    for cls, cname in [(ft.SampleCfg, "ft_sample_cfg"), (ft.Report, "ft_report"), (ft.TargetInfo, "ft_target_info")]:
+        for fname, _ in cls._fields_:
+            key = f"{cname}.{fname}"
+            if key in got:
+                assert int(got[key]) == getattr(cls, fname).offset, key
+
+
+def test_host_validation_rejects_bad_arguments(lib):
+    P = ctypes.c_void_p
+    h = P()
+    fake = P(0x1000)    # never dereferenced: validation fails first
+    assert lib.ft_target_create(5, 10, fake, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert "dim" in lib.ft_last_error().decode()
+    assert lib.ft_target_create(2, 10, None, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert lib.ft_target_create(2, 2, fake, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert lib.ft_target_create(2, 10, fake, 0, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert lib.ft_target_create(2, 10, fake, 4, fake, None, None) == ft.FT_E_ARG
+    assert lib.ft_query_count(None, 4) == -1
+    cfg = ft.SampleCfg(0, 1, 1.0, 0, 0, ft.FT_F64)
+    assert lib.ft_sample_points(None, ctypes.byref(cfg), fake, None) == ft.FT_E_ARG
+    assert lib.ft_consume_queries(None, ctypes.byref(cfg), fake, None) == ft.FT_E_ARG
+    rep = ft.Report()
+    scfg = ft.SolveCfg(1e-14, 100)
+    assert lib.ft_project(None, ctypes.byref(scfg), fake, None, ctypes.byref(rep), None) == ft.FT_E_ARG
+    assert lib.ft_source_create_p1(4, 10, fake, 4, fake, 1, fake, None, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert lib.ft_source_create_p1(2, 10, fake, 4, fake, 0, fake, None, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert lib.ft_source_eval(None, 10, fake, 10, 0, fake, 10, None, None) == ft.FT_E_ARG
+    assert lib.ft_source_get_info(None, None) == ft.FT_E_ARG
+    assert lib.ft_target_destroy(None) == ft.FT_OK
+    assert lib.ft_source_destroy(None) == ft.FT_OK
+
+
+def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(ft, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        ft.load(str(tmp_path / "nope.so"))
