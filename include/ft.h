@@ -174,6 +174,19 @@ ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b
                      hipStream_t stream);
 
 /*
+ * ft_transfer_p1 - steps 1 and 3-6 of sec. 4.1 with the built-in P1 source `s`
+ * in place of a caller-side black box, without materializing the query list:
+ * the same samples (Philox counters of cfg), the same localization rule and
+ * the same element sums as ft_sample_points + ft_source_eval +
+ * ft_consume_queries, fused into one pass over the samples.  Follow with
+ * ft_project.  Requires cfg->precision == FT_F64, cfg->n_fields equal to the
+ * source's field count (at most 4), and a source of the target's dimension.
+ * Out-of-domain samples are counted in the source (ft_source_stats).
+ * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Asynchronous on `stream`.
+ */
+ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, hipStream_t stream);
+
+/*
  * ft_source_create_p1 - a P1 field on a source mesh, evaluated at points by
  * uniform-grid localization (sec. 5.3: grid cells per axis int(L sqrt(#elements))).
  *   coords         device, binary64, [dim][n_nodes]

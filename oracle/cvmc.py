@@ -16,7 +16,8 @@ Follows sec. 4.1 step by step, in the paper's notation:
 
 The sum over j in step 5 is compensated (Neumaier) so that the oracle's own
 rounding stays far below the parity tolerance.  The solve is a sparse direct
-factorisation (SuperLU) where it fits, else a plain Jacobi-CG to 1e-15.
+factorisation (SuperLU) up to 2e5 nodes in 2D / 6e4 in 3D, else a plain
+Jacobi-CG to 1e-15 (both pinned against each other).
 
 The point-query layout shared with the library is: entries [0, n) are the n
 target nodes (step 1), entries [n, n + E N) the samples, element-major
@@ -101,8 +102,8 @@ def assemble(conn: np.ndarray, beta: np.ndarray, n_nodes: int) -> np.ndarray:
 def solve_mass(M: sp.csr_matrix, b: np.ndarray, dim: int) -> np.ndarray:
     """Step 7: x = M^-1 b for each field row of b."""
     n = M.shape[0]
-    if n <= (700_000 if dim == 2 else 120_000):
-        lu = spla.splu(M.tocsc())
+    if n <= (200_000 if dim == 2 else 60_000):
+        lu = spla.splu(M.tocsc(), permc_spec="MMD_AT_PLUS_A")
         return np.stack([lu.solve(bf) for bf in b])
     return np.stack([jacobi_cg(M, bf, 1e-15) for bf in b])
 

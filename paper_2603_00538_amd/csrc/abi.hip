@@ -17,6 +17,7 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
 ft_status source_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
                       int32_t* ids, hipStream_t s);
 ft_status source_release(ft_source* S);
+ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s);
 
 static void target_release(ft_target* T) {
     void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
@@ -37,6 +38,22 @@ static ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) 
         set_error("n_elems * max(samples_per_elem, 64) must stay below 2^32 per transfer");
         return FT_E_UNSUPPORTED;
     }
+    return FT_OK;
+}
+
+static ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream) {
+    if (F <= T->F_cap) return FT_OK;
+    // buffers may still be read by queued work of an earlier transfer
+    FT_TRY_HIP(hipStreamSynchronize(stream));
+    dev_free(T->beta);
+    dev_free(T->g);
+    dev_free(T->bres);
+    T->beta = T->g = T->bres = nullptr;
+    T->F_cap = 0;
+    FT_TRY(dev_alloc_n(&T->beta, size_t(F) * size_t(T->E) * (T->dim + 1)));
+    FT_TRY(dev_alloc_n(&T->g, size_t(F) * size_t(T->n)));
+    FT_TRY(dev_alloc_n(&T->bres, size_t(F) * size_t(T->n)));
+    T->F_cap = F;
     return FT_OK;
 }
 
@@ -148,24 +165,32 @@ ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void*
                   "precision");
         return FT_E_ORDER;
     }
-    if (cfg->n_fields > T->F_cap) {
-        // buffers may still be read by queued work of an earlier transfer
-        FT_TRY_HIP(hipStreamSynchronize(stream));
-        dev_free(T->beta);
-        dev_free(T->g);
-        dev_free(T->bres);
-        T->beta = T->g = T->bres = nullptr;
-        T->F_cap = 0;
-        const size_t F = size_t(cfg->n_fields);
-        FT_TRY(dev_alloc_n(&T->beta, F * size_t(T->E) * (T->dim + 1)));
-        FT_TRY(dev_alloc_n(&T->g, F * size_t(T->n)));
-        FT_TRY(dev_alloc_n(&T->bres, F * size_t(T->n)));
-        T->F_cap = cfg->n_fields;
-    }
+    FT_TRY(ensure_field_buffers(T, cfg->n_fields, stream));
     T->consumed = false;
     FT_TRY(consume_values(T, cfg, values, stream));
     T->consumed = true;
     T->consumed_cfg = *cfg;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t && s, "target and source must be non-null");
+    FT_TRY(check_sample_cfg(t, cfg));
+    FT_ARG_CHECK(s->dim == t->dim, "source dimension %d differs from target dimension %d", s->dim, t->dim);
+    FT_ARG_CHECK(cfg->n_fields == s->F, "n_fields (%d) must equal the source's field count (%d)", cfg->n_fields,
+                 s->F);
+    if (cfg->precision != FT_F64 || cfg->n_fields > 4) {
+        set_error("the fused built-in route supports FT_F64 and at most 4 fields");
+        return FT_E_UNSUPPORTED;
+    }
+    FT_TRY(ensure_field_buffers(t, cfg->n_fields, stream));
+    t->consumed = false;
+    FT_TRY(transfer_p1(t, s, cfg, stream));
+    t->consumed = true;
+    t->consumed_cfg = *cfg;
     return FT_OK;
     FT_GUARD_END
 }

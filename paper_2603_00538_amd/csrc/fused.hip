@@ -1,0 +1,145 @@
+// Fused transfer from the built-in P1 source: sec. 4.1 steps 1 and 3-6 in one
+// pass over the samples, with no point-query list in memory.
+//
+// For each target element t and sample j the kernel draws lambda from the
+// Philox stream (same counters as the emission kernel), forms the physical
+// point, localizes it in the source with the wave-cooperative bin search,
+// interpolates f^s there, and accumulates the residual element load
+//   beta_tk = |Omega_t| / N * sum_j (f^s(X_tj) - alpha g(X_tj)) lambda_k
+// exactly as the consume kernel does.  Sample j of element t is handled by the
+// same lane, in the same round and with the same wave neighbours as in the
+// emit -> evaluate -> consume sequence (for N >= 64), so the two routes give the
+// same numbers.  Only the control g (f^s at the target nodes) and beta are
+// written.
+#include "locate.h"
+#include "sampling.h"
+
+namespace ft {
+
+template <int D, int G, int FC>
+__global__ __launch_bounds__(256) void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n,
+                                                  const int32_t* __restrict__ conn, const double* __restrict__ vol,
+                                                  uint32_t E, uint32_t N, double alpha, SampleKey key,
+                                                  const double* __restrict__ g, double* __restrict__ beta,
+                                                  unsigned long long* __restrict__ nonfinite,
+                                                  unsigned long long* __restrict__ n_ood) {
+    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t t = gid / G;
+    const int lane = int(gid & (G - 1));
+    const bool valid = t < E;
+    const uint32_t tt = valid ? t : 0u;
+    int v[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(tt) * (D + 1) + k];
+    double xv[D + 1][D];
+#pragma unroll
+    for (int k = 0; k <= D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) xv[k][c] = X[c * n + v[k]];
+    double gk[FC][D + 1], acc[FC][D + 1];
+#pragma unroll
+    for (int f = 0; f < FC; ++f)
+#pragma unroll
+        for (int k = 0; k <= D; ++k) {
+            acc[f][k] = 0.0;
+            gk[f][k] = f < S.F ? g[int64_t(f) * n + v[k]] : 0.0;
+        }
+    unsigned int nf = 0, nood = 0;
+    // every lane runs the same number of rounds: the localization is wave-cooperative
+    for (uint32_t j0 = 0; j0 < N; j0 += G) {
+        const uint32_t j = j0 + lane;
+        const bool active = valid && j < N;
+        double lam[D + 1];
+        if (active) {
+            sample_lambda<D>(tt, j, key, lam);
+        } else {
+#pragma unroll
+            for (int k = 0; k <= D; ++k) lam[k] = 0.0;
+        }
+        double p[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double x = lam[0] * xv[0][c];
+#pragma unroll
+            for (int k = 1; k <= D; ++k) x = fma(lam[k], xv[k][c], x);
+            p[c] = x;
+        }
+        double best, bmu[D + 1];
+        int bid;
+        locate_wave<D>(S, p, active, best, bid, bmu);
+        if (!active) continue;
+        nood += (bid == INT_MAX || best < kOutTol);
+#pragma unroll
+        for (int f = 0; f < FC; ++f) {
+            if (f >= S.F) break;
+            const double y = p1_value<D>(S, bid, bmu, f);
+            nf += !isfinite(y);
+            double gx = lam[0] * gk[f][0];
+#pragma unroll
+            for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
+            const double r = y - alpha * gx;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FC; ++f)
+#pragma unroll
+        for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
+    if (valid && lane == 0) {
+        const double scale = vol[t] / double(N);
+#pragma unroll
+        for (int f = 0; f < FC; ++f) {
+            if (f >= S.F) break;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) beta[(int64_t(f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+        }
+    }
+    if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
+    if (nood) atomicAdd(n_ood, (unsigned long long)nood);
+}
+
+SrcView source_view(const ft_source* S);
+ft_status source_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
+                      int32_t* ids, hipStream_t s);
+ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s);
+void zero_counter(unsigned long long* p, hipStream_t s);
+
+template <int D, int G, int FC>
+static void launch_fused(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
+    const SampleKey key{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
+    const unsigned grid = grid_for(T->E * G, 256);
+    k_fused_p1<D, G, FC><<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
+                                             uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta,
+                                             T->counters, S->counters);
+}
+
+template <int D, int G>
+static void fused_fc(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
+    if (cfg->n_fields == 1) launch_fused<D, G, 1>(T, S, cfg, s);
+    else launch_fused<D, G, 4>(T, S, cfg, s);
+}
+
+template <int D>
+static void fused_g(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
+    const int N = cfg->samples_per_elem;
+    if (N >= 64) fused_fc<D, 64>(T, S, cfg, s);
+    else if (N > 16) fused_fc<D, 32>(T, S, cfg, s);
+    else if (N > 8) fused_fc<D, 16>(T, S, cfg, s);
+    else if (N > 4) fused_fc<D, 8>(T, S, cfg, s);
+    else if (N > 2) fused_fc<D, 4>(T, S, cfg, s);
+    else if (N > 1) fused_fc<D, 2>(T, S, cfg, s);
+    else fused_fc<D, 1>(T, S, cfg, s);
+}
+
+ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
+    // step 1: the control, f^s at the target nodes, straight into T->g
+    FT_TRY(source_eval(S, T->n, T->coords, T->n, FT_F64, T->g, T->n, nullptr, s));
+    zero_counter(T->counters, s);
+    if (T->dim == 2) fused_g<2>(T, S, cfg, s);
+    else fused_g<3>(T, S, cfg, s);
+    FT_TRY_HIP(hipGetLastError());
+    return assemble_residual(T, cfg->n_fields, nullptr, 0, false, s);
+}
+
+}  // namespace ft

@@ -139,7 +139,8 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
 }
 
 // b_res,v = sum over the incidence list of v (ascending (t, k)) of beta; also
-// keeps g_v = values[f][v] (the control at the nodes) for the solve.
+// keeps g_v = values[f][v] (the control at the nodes) for the solve, unless
+// values is null (the fused route writes g itself).
 template <int D, bool F32>
 __global__ void k_assemble(const double* __restrict__ beta, int64_t E, const int64_t* __restrict__ inc_ptr,
                            const int32_t* __restrict__ inc, int64_t n, int F, const void* __restrict__ values_,
@@ -152,9 +153,11 @@ __global__ void k_assemble(const double* __restrict__ beta, int64_t E, const int
         double s = 0.0;
         for (int64_t i = b; i < e; ++i) s += bf[inc[i]];
         bres[int64_t(f) * n + v] = s;
-        const int64_t off = int64_t(f) * ld + v;
-        g[int64_t(f) * n + v] = F32 ? double(static_cast<const float*>(values_)[off])
-                                    : static_cast<const double*>(values_)[off];
+        if (values_) {
+            const int64_t off = int64_t(f) * ld + v;
+            g[int64_t(f) * n + v] = F32 ? double(static_cast<const float*>(values_)[off])
+                                        : static_cast<const double*>(values_)[off];
+        }
     }
 }
 
@@ -223,21 +226,36 @@ static void consume_g(ft_target* T, const ft_sample_cfg* cfg, const void* values
     else consume_fc<D, 1, F32>(T, cfg, values, ld, s);
 }
 
+void zero_counter(unsigned long long* p, hipStream_t s) {
+    k_zero_u64<<<1, 64, 0, s>>>(p, 1);   // a kernel, not a memset: safe inside captured graphs
+}
+
+template <int D>
+static void launch_assemble(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s) {
+    if (f32)
+        k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
+                                                               ld, T->bres, T->g);
+    else
+        k_assemble<D, false><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
+                                                                ld, T->bres, T->g);
+}
+
+ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s) {
+    if (T->dim == 2) launch_assemble<2>(T, F, values, ld, f32, s);
+    else launch_assemble<3>(T, F, values, ld, f32, s);
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
 template <int D>
 static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
     const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
     const bool f32 = cfg->precision == FT_F32;
-    k_zero_u64<<<1, 64, 0, s>>>(T->counters, 1);   // a kernel, not a memset: safe inside captured graphs
+    zero_counter(T->counters, s);
     if (f32) consume_g<D, true>(T, cfg, values, ld, s);
     else consume_g<D, false>(T, cfg, values, ld, s);
-    if (f32)
-        k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n,
-                                                               cfg->n_fields, values, ld, T->bres, T->g);
-    else
-        k_assemble<D, false><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n,
-                                                                cfg->n_fields, values, ld, T->bres, T->g);
     FT_TRY_HIP(hipGetLastError());
-    return FT_OK;
+    return assemble_residual(T, cfg->n_fields, values, ld, f32, s);
 }
 
 ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {

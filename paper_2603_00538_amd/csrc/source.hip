@@ -5,63 +5,21 @@
 // a uniform grid of bins as in sec. 5.3 (int(L sqrt(#elements)) cells per
 // axis by default).
 //
-// Localization rule: the element maximizing min_k mu_k(x) (mu: barycentric
-// coordinates); exact ties -> lowest element id; a best min mu below -1e-10
-// is out of the domain (counted, extrapolated from that element).  A point
-// whose best element has min mu > 1e-12 is strictly inside it, and no other
-// element can tie or win, so the search stops there.
+// Localization rule and search: see locate.h.
 //
 // Layout: every source element e has a record rec[e*RS ...] = (x0, A) with A
 // the inverse of J = [x1-x0 | ... | xd-x0], so mu_{k+1} = sum_c A[k][c] (x-x0)_c
 // and mu_0 = 1 - sum mu; plus an outward-rounded binary32 bounding box.  Bins
 // hold the ids of every element whose box overlaps them (CSR, ascending ids).
-//
-// The evaluation kernel works one wavefront at a time: the 64 points of a
-// wave are usually samples of one target element, so they share a handful of
-// bins.  The wave computes its own bounding box, culls each bin's candidates
-// 64 at a time against it (one candidate per lane, a ballot), and then every
-// lane tests its point against each surviving candidate, whose record is
-// wave-uniform (scalar loads).  Waves whose points span many bins (scattered
-// input) fall back to one bin per lane.
+
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <vector>
 
-#include "common.h"
+#include "locate.h"
 
 namespace ft {
-
-constexpr double kInsideTau = 1e-12;
-constexpr double kOutTol = -1e-10;
-
-template <int D>
-struct RecSize { static constexpr int value = D == 2 ? 8 : 16; };
-
-__device__ __forceinline__ float f32_down(double x) {
-    float f = (float)x;
-    if ((double)f > x) f = nextafterf(f, -INFINITY);
-    return f;
-}
-__device__ __forceinline__ float f32_up(double x) {
-    float f = (float)x;
-    if ((double)f < x) f = nextafterf(f, INFINITY);
-    return f;
-}
-
-struct GridView {
-    int32_t nb[3];
-    double lo[3];
-    double inv_h[3];
-};
-
-// Bin index along axis c; monotone in x, so a point inside a box always maps
-// into the box's bin range.  NaN maps to bin 0.
-__device__ __forceinline__ int bin_of(double x, int c, const GridView& g) {
-    double u = (x - g.lo[c]) * g.inv_h[c];
-    u = fmin(fmax(u, 0.0), double(g.nb[c] - 1));
-    return int(u);
-}
 
 template <int D>
 __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
@@ -228,53 +186,10 @@ __global__ void k_sort_bins(const int64_t* __restrict__ ptr, int64_t nseg, int32
     }
 }
 
-// ---------------------------------------------------------------- evaluation
-struct SrcView {
-    const double* rec;
-    const float* box;
-    const int32_t* conn;
-    const double* values;
-    const int64_t* bin_ptr;
-    const int32_t* bin_elems;
-    int64_t n;
-    int F;
-    GridView g;
-};
-
-template <int D>
-__device__ __forceinline__ void test_candidate(const double* __restrict__ r, int e, const double (&p)[D], double& best,
-                                               int& bid, double (&bmu)[D + 1]) {
-    double d[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) d[c] = p[c] - r[c];
-    double mu[D + 1];
-    mu[0] = 1.0;
-    double mn = INFINITY;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < D; ++c) s = fma(r[D + k * D + c], d[c], s);
-        mu[k + 1] = s;
-        mu[0] -= s;
-        mn = fmin(mn, s);
-    }
-    mn = fmin(mn, mu[0]);
-    const bool better = (mn > best) || (mn == best && e < bid);
-    if (better) {
-        best = mn;
-        bid = e;
-#pragma unroll
-        for (int k = 0; k <= D; ++k) bmu[k] = mu[k];
-    }
-}
-
 template <int D, bool IN_F32, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t npts, const void* __restrict__ pts_, int64_t ld,
                                                   void* __restrict__ out_, int64_t ld_out, int32_t* __restrict__ ids,
                                                   unsigned long long* __restrict__ n_ood) {
-    constexpr int RS = RecSize<D>::value;
-    constexpr int MAX_SPAN = D == 2 ? 4 : 8;
     const int lane = threadIdx.x & 63;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool active = i < npts;
@@ -287,93 +202,17 @@ __global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t npts, const
             p[c] = active ? static_cast<const double*>(pts_)[c * ld + i] : 0.0;
     }
     if (!__any(active)) return;
-    double wlo[D], whi[D];
-    int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
-    int span = 1;
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-        wlo[c] = wave_min(active ? p[c] : INFINITY);
-        whi[c] = wave_max(active ? p[c] : -INFINITY);
-        b0[c] = uniform_int(bin_of(wlo[c], c, S.g));
-        b1[c] = uniform_int(bin_of(whi[c], c, S.g));
-        span *= b1[c] - b0[c] + 1;
-    }
-    double best = -DBL_MAX;
-    int bid = INT_MAX;
-    double bmu[D + 1];
-#pragma unroll
-    for (int k = 0; k <= D; ++k) bmu[k] = 0.0;
-
-    if (span <= MAX_SPAN) {
-        float flo[D], fhi[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            flo[c] = f32_down(wlo[c]);
-            fhi[c] = f32_up(whi[c]);
-        }
-        bool finished = false;
-        for (int bz = b0[2]; bz <= b1[2] && !finished; ++bz)
-            for (int by = b0[1]; by <= b1[1] && !finished; ++by)
-                for (int bx = b0[0]; bx <= b1[0] && !finished; ++bx) {
-                    const int64_t b = (int64_t(bz) * S.g.nb[1] + by) * S.g.nb[0] + bx;
-                    const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
-                    for (int64_t c0 = start; c0 < end && !finished; c0 += 64) {
-                        int cid = -1;
-                        bool ov = false;
-                        if (c0 + lane < end) {
-                            cid = S.bin_elems[c0 + lane];
-                            const float* bx_ = S.box + int64_t(cid) * 2 * D;
-                            ov = true;
-#pragma unroll
-                            for (int c = 0; c < D; ++c) ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
-                        }
-                        uint64_t mask = __ballot(ov);
-                        while (mask) {
-                            const int l = __ffsll((unsigned long long)mask) - 1;
-                            mask &= mask - 1;
-                            const int e = read_lane(cid, l);
-                            test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid, bmu);
-                            if (__all(!active || best > kInsideTau)) {
-                                finished = true;
-                                break;
-                            }
-                        }
-                    }
-                }
-    } else {
-        int64_t b = 0;
-        {
-            int bc[3] = {0, 0, 0};
-#pragma unroll
-            for (int c = 0; c < D; ++c) bc[c] = bin_of(p[c], c, S.g);
-            b = (int64_t(bc[2]) * S.g.nb[1] + bc[1]) * S.g.nb[0] + bc[0];
-        }
-        if (active) {
-            const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
-            for (int64_t c = start; c < end; ++c) {
-                const int e = S.bin_elems[c];
-                test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid, bmu);
-                if (best > kInsideTau) break;
-            }
-        }
-    }
-
+    double best, bmu[D + 1];
+    int bid;
+    locate_wave<D>(S, p, active, best, bid, bmu);
     const bool found = bid != INT_MAX;
     const bool ood = active && (!found || best < kOutTol);
     const uint64_t om = __ballot(ood);
     if (lane == 0 && om) atomicAdd(n_ood, (unsigned long long)__popcll(om));
     if (!active) return;
     if (ids) ids[i] = found ? bid : -1;
-    int vtx[D + 1];
-#pragma unroll
-    for (int k = 0; k <= D; ++k) vtx[k] = found ? S.conn[int64_t(bid) * (D + 1) + k] : 0;
     for (int f = 0; f < S.F; ++f) {
-        double y = 0.0;
-        if (found) {
-            const double* Fv = S.values + int64_t(f) * S.n;
-#pragma unroll
-            for (int k = 0; k <= D; ++k) y = fma(bmu[k], Fv[vtx[k]], y);
-        }
+        const double y = p1_value<D>(S, bid, bmu, f);
         if (OUT_F32)
             static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
         else
@@ -488,15 +327,20 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
     return S->dim == 2 ? build<2>(S, coords, conn, values, bins, s) : build<3>(S, coords, conn, values, bins, s);
 }
 
-template <int D>
-static ft_status launch_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
-                             int64_t ld_out, int32_t* ids, hipStream_t s) {
+SrcView source_view(const ft_source* S) {
     SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
         v.g.lo[c] = S->lo[c];
         v.g.inv_h[c] = S->inv_h[c];
     }
+    return v;
+}
+
+template <int D>
+static ft_status launch_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
+                             int64_t ld_out, int32_t* ids, hipStream_t s) {
+    const SrcView v = source_view(S);
     const unsigned grid = grid_for(npts, 256);
     if (prec == FT_F64)
         k_src_eval<D, false, false><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);

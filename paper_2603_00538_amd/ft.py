@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
-            "ft_consume_queries", "ft_project", "ft_source_create_p1", "ft_source_eval", "ft_source_stats",
+            "ft_consume_queries", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval", "ft_source_stats",
             "ft_source_destroy", "ft_source_get_info", "ft_last_error"]
 
 
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH):
         "ft_query_count": (I64, [P, I32]),
         "ft_sample_points": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
         "ft_consume_queries": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
+        "ft_transfer_p1": (I32, [P, P, ctypes.POINTER(SampleCfg), P]),
         "ft_project": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P]),
         "ft_source_create_p1": (I32, [I32, I64, P, I64, P, I32, P, P, P, ctypes.POINTER(P)]),
         "ft_source_eval": (I32, [P, I64, P, I64, I32, P, I64, P, P]),
@@ -132,6 +133,10 @@ def ft_sample_points(h, cfg: SampleCfg, points_ptr, stream):
 
 def ft_consume_queries(h, cfg: SampleCfg, values_ptr, stream):
     return _check(load().ft_consume_queries(h, ctypes.byref(cfg), values_ptr, stream), "ft_consume_queries")
+
+
+def ft_transfer_p1(h, src, cfg: SampleCfg, stream):
+    return _check(load().ft_transfer_p1(h, src, ctypes.byref(cfg), stream), "ft_transfer_p1")
 
 
 def ft_project(h, cfg: SolveCfg, x_ptr, b_ptr, n_fields, stream, allow=(FT_E_NOCONV, FT_E_NONFINITE)):
@@ -239,6 +244,10 @@ class Target:
 
     def consume(self, cfg: SampleCfg, values):
         ft_consume_queries(self.handle, cfg, values.data_ptr(), current_stream())
+
+    def transfer_from(self, source, cfg: SampleCfg):
+        """Fused steps 1 and 3-6 from a built-in Source (no query list in memory)."""
+        ft_transfer_p1(self.handle, source.handle, cfg, current_stream())
 
     def project(self, n_fields=1, rtol=1e-14, max_iter=500, want_b=True, x=None, b=None):
         torch = _torch()

@@ -305,3 +305,28 @@ def test_allocation_cap_reports_oom(monkeypatch):
     monkeypatch.delenv("FT_MAX_BYTES")
     T = ft.Target(*tm)
     T.close()
+
+
+# ---------------------------------------------------------------- fused built-in route
+@pytest.mark.parametrize("dim,N", [(2, 64), (2, 20), (3, 16), (2, 256)])
+def test_fused_route_matches_unfused_and_oracle(dim, N):
+    tm, sm = _small_2d() if dim == 2 else _small_3d()
+    name = "front_2d" if dim == 2 else "gaussian_bumps_3d"
+    sv = fields.evaluate(name, np, sm[0])
+    log(f"fused route dim={dim} N={N}")
+    ref = gpu_transfer(tm, sm, sv, N, 1.0, 77, 1)
+    T = ft.Target(*tm)
+    S = ft.Source(*sm, sv)
+    cfg = ft.SampleCfg(N, 1, 1.0, 77, 1, ft.FT_F64)
+    T.transfer_from(S, cfg)
+    res = T.project(1)
+    x, b = res.x.cpu().numpy(), res.b.cpu().numpy()
+    assert rel_l2(x, ref["x"]) < 1e-14 and rel_l2(b, ref["b"]) < 1e-14
+    o = oracle_transfer(tm, sm, sv, N, 1.0, 77, 1)
+    assert rel_l2(b, o["b"]) < 1e-12 and rel_l2(x, o["x"]) < 1e-12
+    assert S.take_out_of_domain() == 0
+    with pytest.raises(ft.FtError) as e:
+        T.transfer_from(S, ft.SampleCfg(N, 1, 1.0, 77, 1, ft.FT_F32))
+    assert e.value.status == ft.FT_E_UNSUPPORTED
+    T.close()
+    S.close()
