@@ -44,6 +44,12 @@ def algorithmic_bytes(phase, dim, E, n, N, F, p, src=None):
         mesh = src["E"] * (rs * 8 + 2 * dim * 4 + (dim + 1) * 4) + src["n_reg"] * 4 + src["nbins"] * 8 \
             + src["n"] * F * 8
         return Q * (dim + F) * p + mesh
+    if phase == "fused":
+        # per element: connectivity, vertex coordinates, control values, measure, beta; the source mesh once
+        rs = 8 if dim == 2 else 16
+        mesh = src["E"] * (rs * 8 + 2 * dim * 4 + (dim + 1) * 4) + src["n_reg"] * 4 + src["nbins"] * 8 \
+            + src["n"] * F * 8
+        return E * ((dim + 1) * 4 + (dim + 1) * dim * 8 + (dim + 1) * F * 8 + 8 + (dim + 1) * F * 8) + mesh
     if phase == "consume":
         # read F values per query; per element connectivity, measure and beta; node assembly
         return Q * F * p + E * ((dim + 1) * 4 + 8 + (dim + 1) * F * 8) + E * (dim + 1) * (4 + F * 8) + n * F * 16
@@ -101,6 +107,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-elems", type=int, default=1500)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--route", default="blackbox", choices=["blackbox", "fused"],
+                    help="blackbox: sample -> source eval -> consume through the point-query list; "
+                         "fused: ft_transfer_p1 (built-in source, no query list)")
+    ap.add_argument("--no-fused", action="store_true", help="skip the extra fused-route measurement")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -149,55 +159,70 @@ def main():
     x = torch.empty((F, n), dtype=torch.float64, device=dev)
     b = torch.empty((F, n), dtype=torch.float64, device=dev)
 
-    phases = ["emit", "eval", "consume", "project"]
+    phases = ["emit", "eval", "consume", "project"] if args.route == "blackbox" else ["fused", "project"]
     times = {k: [] for k in phases}
     reports = None
     status = None
 
-    def step(record):
+    def step(record, route):
         nonlocal reports, status
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        nev = 5 if route == "blackbox" else 3
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(nev)] if record else None
         if record:
             ev[0].record()
-        T.sample_points(cfg, out=pts)
+        if route == "blackbox":
+            T.sample_points(cfg, out=pts)
+            if record:
+                ev[1].record()
+            S.eval(pts, out=vals)
+            if record:
+                ev[2].record()
+            T.consume(cfg, vals)
+        else:
+            T.transfer_from(S, cfg)
         if record:
-            ev[1].record()
-        S.eval(pts, out=vals)
-        if record:
-            ev[2].record()
-        T.consume(cfg, vals)
-        if record:
-            ev[3].record()
+            ev[nev - 2].record()
         res = T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
         if record:
-            ev[4].record()
+            ev[nev - 1].record()
         reports, status = res.reports, res.status
         return ev
 
-    for i in range(args.warmup):
-        step(False)
-        log(f"warmup {i + 1}/{args.warmup}")
-    torch.cuda.synchronize()
-    evs = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        evs.append(step(True))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for ev in evs:
-        for k, name in enumerate(phases):
-            times[name].append(ev[k].elapsed_time(ev[k + 1]))
-    log(f"timed {args.steps} steps in {wall:.3f} s")
+    def timed(route, steps, warmup):
+        names = ["emit", "eval", "consume", "project"] if route == "blackbox" else ["fused", "project"]
+        tms = {k: [] for k in names}
+        for i in range(warmup):
+            step(False, route)
+            log(f"{route} warmup {i + 1}/{warmup}")
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            evs.append(step(True, route))
+        torch.cuda.synchronize()
+        wall_ = time.perf_counter() - t0
+        for ev in evs:
+            for k, name in enumerate(names):
+                tms[name].append(ev[k].elapsed_time(ev[k + 1]))
+        log(f"{route}: timed {steps} steps in {wall_:.3f} s")
+        return wall_, {k: float(np.mean(v)) for k, v in tms.items()}
+
+    wall, phase_ms = timed(args.route, args.steps, args.warmup)
     ms_step = wall * 1e3 / args.steps
-    phase_ms = {k: float(np.mean(v)) for k, v in times.items()}
+    extra_route = None
+    if args.route == "blackbox" and not args.no_fused and F <= 4 and prec == ft.FT_F64:
+        fw, fph = timed("fused", args.steps, 1)
+        extra_route = {"route": "fused (ft_transfer_p1, no query list)", "ms_per_step": fw * 1e3 / args.steps,
+                       "value": E / (fw / args.steps), "phases_ms": fph}
 
     si = S.info
     src_info = {"E": sconn.shape[0], "n": sc.shape[0], "n_reg": int(si.n_registrations),
                 "nbins": int(np.prod([si.bins[c] for c in range(dim)]))}
-    dom = max(["emit", "eval", "consume"], key=lambda k: phase_ms[k])
+    cand = [k for k in ("emit", "eval", "consume", "fused") if k in phase_ms]
+    dom = max(cand, key=lambda k: phase_ms[k])
     abytes = algorithmic_bytes(dom, dim, E, n, N, F, p, src_info)
     achieved = abytes / (phase_ms[dom] * 1e-3) / 1e9
-    kernel_names = {"emit": "k_emit", "eval": "k_src_eval", "consume": "k_consume"}
+    kernel_names = {"emit": "k_emit", "eval": "k_src_eval", "consume": "k_consume", "fused": "k_fused_p1"}
     out = {
         "metric": METRIC,
         "value": E / (ms_step * 1e-3),
@@ -211,7 +236,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == ft.FT_F64 else "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "dim": dim, "target_elements": E, "target_nodes": n,
+        "config": {"workload": w.name, "route": args.route, "dim": dim, "target_elements": E, "target_nodes": n,
                    "source_elements": int(sconn.shape[0]), "samples_per_elem": N, "n_fields": F,
                    "queries": Q, "alpha": w.alpha, "rtol": w.rtol,
                    "bins": list(w.bins[:dim]) if any(w.bins) else "default", "precision": args.precision},
@@ -226,6 +251,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes": abytes, "avg_ms": phase_ms[dom]},
     }
+    if extra_route is not None:
+        out["fused_route"] = extra_route
     out["config"]["bins"] = [int(si.bins[c]) for c in range(dim)]
     out["config"]["bin_registrations"] = int(si.n_registrations)
     T.close()

@@ -160,6 +160,9 @@ ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void*
 
 /*
  * ft_project - step 2 and step 7 of sec. 4.1 and the conservation report.
+ * Several fields (F > 1, at most 64) are solved together by a batched PCG that
+ * reads M once per iteration for all of them, each field with its own
+ * scalars and stopping test.
  * b = alpha M g + b_res (the control load integrated exactly), then Jacobi-PCG
  * on M y = b_res from y = 0 and x = alpha g + y (the same iterates as CG on
  * M x = b started at x = alpha g), stopping at ||b - M x|| <= rtol ||b||.

@@ -6,17 +6,17 @@
 // point, localizes it in the source with the wave-cooperative bin search,
 // interpolates f^s there, and accumulates the residual element load
 //   beta_tk = |Omega_t| / N * sum_j (f^s(X_tj) - alpha g(X_tj)) lambda_k
-// exactly as the consume kernel does.  Sample j of element t is handled by the
-// same lane, in the same round and with the same wave neighbours as in the
-// emit -> evaluate -> consume sequence (for N >= 64), so the two routes give the
-// same numbers.  Only the control g (f^s at the target nodes) and beta are
-// written.
+// exactly as the consume kernel does.  The localization rule's winner does
+// not depend on which points share a wave, so the two routes give the same
+// element, the same barycentrics and the same values; the element sums run
+// in the consume kernel's lane order for N >= 64 with G*P samples per round.
+// Only the control g (f^s at the target nodes) and beta are written.
 #include "locate.h"
 #include "sampling.h"
 
 namespace ft {
 
-template <int D, int G, int FC>
+template <int D, int G, int P, int FC>
 __global__ __launch_bounds__(256) void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n,
                                                   const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                   uint32_t E, uint32_t N, double alpha, SampleKey key,
@@ -45,41 +45,50 @@ __global__ __launch_bounds__(256) void k_fused_p1(SrcView S, const double* __res
             gk[f][k] = f < S.F ? g[int64_t(f) * n + v[k]] : 0.0;
         }
     unsigned int nf = 0, nood = 0;
-    // every lane runs the same number of rounds: the localization is wave-cooperative
-    for (uint32_t j0 = 0; j0 < N; j0 += G) {
-        const uint32_t j = j0 + lane;
-        const bool active = valid && j < N;
-        double lam[D + 1];
-        if (active) {
-            sample_lambda<D>(tt, j, key, lam);
-        } else {
+    // every lane runs the same number of rounds: the localization is wave-cooperative.
+    // Round r, slot q of a lane holds sample j = r*G*P + q*G + lane.
+    for (uint32_t j0 = 0; j0 < N; j0 += G * P) {
+        double lam[P][D + 1], pt[P][D];
+        bool act[P];
 #pragma unroll
-            for (int k = 0; k <= D; ++k) lam[k] = 0.0;
+        for (int q = 0; q < P; ++q) {
+            const uint32_t j = j0 + q * G + lane;
+            act[q] = valid && j < N;
+            if (act[q]) {
+                sample_lambda<D>(tt, j, key, lam[q]);
+            } else {
+#pragma unroll
+                for (int k = 0; k <= D; ++k) lam[q][k] = 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                double x = lam[q][0] * xv[0][c];
+#pragma unroll
+                for (int k = 1; k <= D; ++k) x = fma(lam[q][k], xv[k][c], x);
+                pt[q][c] = x;
+            }
         }
-        double p[D];
+        double best[P];
+        int bid[P];
+        locate_wave<D, P>(S, pt, act, best, bid);
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            double x = lam[0] * xv[0][c];
+        for (int q = 0; q < P; ++q) {
+            if (!act[q]) continue;
+            nood += (bid[q] == INT_MAX || best[q] < kOutTol);
+            double mu[D + 1];
+            winner_mu<D>(S, bid[q], pt[q], mu);
 #pragma unroll
-            for (int k = 1; k <= D; ++k) x = fma(lam[k], xv[k][c], x);
-            p[c] = x;
-        }
-        double best, bmu[D + 1];
-        int bid;
-        locate_wave<D>(S, p, active, best, bid, bmu);
-        if (!active) continue;
-        nood += (bid == INT_MAX || best < kOutTol);
+            for (int f = 0; f < FC; ++f) {
+                if (f >= S.F) break;
+                const double y = p1_value<D>(S, bid[q], mu, f);
+                nf += !isfinite(y);
+                double gx = lam[q][0] * gk[f][0];
 #pragma unroll
-        for (int f = 0; f < FC; ++f) {
-            if (f >= S.F) break;
-            const double y = p1_value<D>(S, bid, bmu, f);
-            nf += !isfinite(y);
-            double gx = lam[0] * gk[f][0];
+                for (int k = 1; k <= D; ++k) gx = fma(lam[q][k], gk[f][k], gx);
+                const double r = y - alpha * gx;
 #pragma unroll
-            for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
-            const double r = y - alpha * gx;
-#pragma unroll
-            for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[q][k], acc[f][k]);
+            }
         }
     }
 #pragma unroll
@@ -105,31 +114,34 @@ ft_status source_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, i
 ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s);
 void zero_counter(unsigned long long* p, hipStream_t s);
 
-template <int D, int G, int FC>
+template <int D, int G, int P, int FC>
 static void launch_fused(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
     const SampleKey key{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
     const unsigned grid = grid_for(T->E * G, 256);
-    k_fused_p1<D, G, FC><<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
+    k_fused_p1<D, G, P, FC><<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
                                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta,
                                              T->counters, S->counters);
 }
 
-template <int D, int G>
+template <int D, int G, int P>
 static void fused_fc(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
-    if (cfg->n_fields == 1) launch_fused<D, G, 1>(T, S, cfg, s);
-    else launch_fused<D, G, 4>(T, S, cfg, s);
+    if (cfg->n_fields == 1) launch_fused<D, G, P, 1>(T, S, cfg, s);
+    else launch_fused<D, G, P, 4>(T, S, cfg, s);
 }
 
+// lanes per element G and samples per lane per round P
 template <int D>
 static void fused_g(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
     const int N = cfg->samples_per_elem;
-    if (N >= 64) fused_fc<D, 64>(T, S, cfg, s);
-    else if (N > 16) fused_fc<D, 32>(T, S, cfg, s);
-    else if (N > 8) fused_fc<D, 16>(T, S, cfg, s);
-    else if (N > 4) fused_fc<D, 8>(T, S, cfg, s);
-    else if (N > 2) fused_fc<D, 4>(T, S, cfg, s);
-    else if (N > 1) fused_fc<D, 2>(T, S, cfg, s);
-    else fused_fc<D, 1>(T, S, cfg, s);
+    if (N >= 256) fused_fc<D, 64, 4>(T, S, cfg, s);
+    else if (N >= 128) fused_fc<D, 64, 2>(T, S, cfg, s);
+    else if (N >= 64) fused_fc<D, 64, 1>(T, S, cfg, s);
+    else if (N > 16) fused_fc<D, 32, 1>(T, S, cfg, s);
+    else if (N > 8) fused_fc<D, 16, 1>(T, S, cfg, s);
+    else if (N > 4) fused_fc<D, 8, 1>(T, S, cfg, s);
+    else if (N > 2) fused_fc<D, 4, 1>(T, S, cfg, s);
+    else if (N > 1) fused_fc<D, 2, 1>(T, S, cfg, s);
+    else fused_fc<D, 1, 1>(T, S, cfg, s);
 }
 
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {

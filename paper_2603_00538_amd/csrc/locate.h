@@ -66,13 +66,14 @@ struct SrcView {
     GridView g;
 };
 
+// Barycentric coordinates of p in element e (record r): mu_{k+1} = A[k] . (p - x0),
+// mu_0 = 1 - sum.  Returns min_k mu_k.
 template <int D>
-__device__ __forceinline__ void test_candidate(const double* __restrict__ r, int e, const double (&p)[D], double& best,
-                                               int& bid, double (&bmu)[D + 1]) {
+__device__ __forceinline__ double barycentric(const double* __restrict__ r, const double (&p)[D],
+                                              double (&mu)[D + 1]) {
     double d[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) d[c] = p[c] - r[c];
-    double mu[D + 1];
     mu[0] = 1.0;
     double mn = INFINITY;
 #pragma unroll
@@ -84,41 +85,54 @@ __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int
         mu[0] -= s;
         mn = fmin(mn, s);
     }
-    mn = fmin(mn, mu[0]);
-    const bool better = (mn > best) || (mn == best && e < bid);
-    if (better) {
+    return fmin(mn, mu[0]);
+}
+
+template <int D>
+__device__ __forceinline__ void test_candidate(const double* __restrict__ r, int e, const double (&p)[D], double& best,
+                                               int& bid) {
+    double mu[D + 1];
+    const double mn = barycentric<D>(r, p, mu);
+    if ((mn > best) || (mn == best && e < bid)) {
         best = mn;
         bid = e;
-#pragma unroll
-        for (int k = 0; k <= D; ++k) bmu[k] = mu[k];
     }
 }
 
-// Rule winner for this lane's point p among the candidates of the bins the
-// wave's points touch (see the file comment).  Every lane of the wave must
-// call it (lanes without a point pass active = false).  Returns best = max
-// min-barycentric, bid = its element id (INT_MAX if no candidate), bmu = mu.
-template <int D>
-__device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[D], bool active, double& best,
-                                            int& bid, double (&bmu)[D + 1]) {
+// Rule winner for each of this lane's P points among the candidates of the
+// bins the wave's points touch (see the file comment).  Every lane of the
+// wave must call it (points a lane does not own pass active = false).
+// Returns best = max min-barycentric and bid = its element id (INT_MAX if no
+// candidate was found) per point; barycentric() recomputes mu for the winner.
+template <int D, int P>
+__device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[P][D], const bool (&active)[P],
+                                            double (&best)[P], int (&bid)[P]) {
     constexpr int RS = RecSize<D>::value;
-    constexpr int MAX_SPAN = D == 2 ? 4 : 8;
+    constexpr int MAX_SPAN = D == 2 ? 9 : 12;
     const int lane = threadIdx.x & 63;
     double wlo[D], whi[D];
     int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
     int span = 1;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-        wlo[c] = wave_min(active ? p[c] : INFINITY);
-        whi[c] = wave_max(active ? p[c] : -INFINITY);
+        double lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+            if (active[q]) {
+                lo = fmin(lo, p[q][c]);
+                hi = fmax(hi, p[q][c]);
+            }
+        wlo[c] = wave_min(lo);
+        whi[c] = wave_max(hi);
         b0[c] = uniform_int(bin_of(wlo[c], c, S.g));
         b1[c] = uniform_int(bin_of(whi[c], c, S.g));
         span *= b1[c] - b0[c] + 1;
     }
-    best = -DBL_MAX;
-    bid = INT_MAX;
 #pragma unroll
-    for (int k = 0; k <= D; ++k) bmu[k] = 0.0;
+    for (int q = 0; q < P; ++q) {
+        best[q] = -DBL_MAX;
+        bid[q] = INT_MAX;
+    }
 
     if (span <= MAX_SPAN) {
         float flo[D], fhi[D];
@@ -148,8 +162,14 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                             const int l = __ffsll((unsigned long long)mask) - 1;
                             mask &= mask - 1;
                             const int e = read_lane(cid, l);
-                            test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid, bmu);
-                            if (__all(!active || best > kInsideTau)) {
+                            const double* r = S.rec + int64_t(e) * RS;
+                            bool done = true;
+#pragma unroll
+                            for (int q = 0; q < P; ++q) {
+                                test_candidate<D>(r, e, p[q], best[q], bid[q]);
+                                done &= !active[q] || best[q] > kInsideTau;
+                            }
+                            if (__all(done)) {
                                 finished = true;
                                 break;
                             }
@@ -157,23 +177,32 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                     }
                 }
     } else {
-        int64_t b = 0;
-        {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            if (!active[q]) continue;
             int bc[3] = {0, 0, 0};
 #pragma unroll
-            for (int c = 0; c < D; ++c) bc[c] = bin_of(p[c], c, S.g);
-            b = (int64_t(bc[2]) * S.g.nb[1] + bc[1]) * S.g.nb[0] + bc[0];
-        }
-        if (active) {
+            for (int c = 0; c < D; ++c) bc[c] = bin_of(p[q][c], c, S.g);
+            const int64_t b = (int64_t(bc[2]) * S.g.nb[1] + bc[1]) * S.g.nb[0] + bc[0];
             const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
             for (int64_t c = start; c < end; ++c) {
                 const int e = S.bin_elems[c];
-                test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid, bmu);
-                if (best > kInsideTau) break;
+                test_candidate<D>(S.rec + int64_t(e) * RS, e, p[q], best[q], bid[q]);
+                if (best[q] > kInsideTau) break;
             }
         }
     }
+}
 
+// Barycentric coordinates of p in the located element (zeros if none).
+template <int D>
+__device__ __forceinline__ void winner_mu(const SrcView& S, int bid, const double (&p)[D], double (&mu)[D + 1]) {
+    if (bid == INT_MAX) {
+#pragma unroll
+        for (int k = 0; k <= D; ++k) mu[k] = 0.0;
+        return;
+    }
+    (void)barycentric<D>(S.rec + int64_t(bid) * RecSize<D>::value, p, mu);
 }
 
 // P1 value of field f at a located point (0 if no element was found).

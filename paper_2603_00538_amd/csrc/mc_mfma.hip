@@ -1,0 +1,186 @@
+// Many-field element sums on the matrix cores (sec. 4.1 step 5 for F fields).
+//
+// For one target element t with N samples and F fields the residual element
+// loads form a small matrix product,
+//   beta_t (F x (d+1)) = R_t^T (F x N) * Lambda_t (N x (d+1)) * |Omega_t| / N,
+//   R_t[j][f] = y_f(X_tj) - alpha sum_l lambda_jl g_f(v_l),
+// i.e. the residual of Eq. cv_element_load_residual_operator for every field
+// at once.  It runs on v_mfma_f32_16x16x32_{f16,bf16}: M = 16 fields per tile,
+// K = 32 samples per step, N = 16 columns of which the first d+1 are the
+// barycentric weights.  Matrix-core products are split into hi + lo parts,
+//   r lambda ~ r_hi lambda_hi + r_hi lambda_lo + r_lo lambda_hi
+// (three MFMAs, FP32 accumulation), which keeps about 22 bits (f16) or 16 bits
+// (bf16) of each product.  For f16 every field row is first scaled by a power
+// of two so that its largest residual sits in [2^13, 2^14) (exact, undone on
+// output); bf16 shares the binary32 exponent range and needs no scaling.
+//
+// One wavefront per element; the block's four waves stage their lambda
+// (recomputed from the same Philox counters as the emission, binary32 form)
+// and the control values in LDS.  Every element sum is a fixed sequence of
+// MFMAs, so results are reproducible run to run.
+#include "sampling.h"
+
+namespace ft {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+
+constexpr int MF_NMAX = 256;   // samples per element handled by this kernel
+
+template <bool BF16>
+struct Split;
+
+template <>
+struct Split<false> {
+    using vec = v8h;
+    static __device__ __forceinline__ void set(vec& hi, vec& lo, int i, float v) {
+        const _Float16 h = (_Float16)v;
+        hi[i] = h;
+        lo[i] = (_Float16)(v - (float)h);
+    }
+    static __device__ __forceinline__ v4f mma(const vec& a, const vec& b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Split<true> {
+    using vec = v8b;
+    static __device__ __forceinline__ void set(vec& hi, vec& lo, int i, float v) {
+        const __bf16 h = (__bf16)v;
+        hi[i] = h;
+        lo[i] = (__bf16)(v - (float)h);
+    }
+    static __device__ __forceinline__ v4f mma(const vec& a, const vec& b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int D, bool BF16>
+__global__ __launch_bounds__(256) void k_consume_mfma(const float* __restrict__ values, int64_t ld, int F,
+                                                      const int32_t* __restrict__ conn, const double* __restrict__ vol,
+                                                      int64_t n, uint32_t E, uint32_t N, float alpha, SampleKey key,
+                                                      double* __restrict__ beta,
+                                                      unsigned long long* __restrict__ nonfinite) {
+    using S = Split<BF16>;
+    __shared__ float lam_s[4][MF_NMAX][4];
+    __shared__ float g_s[4][4][64];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * 4u + uint32_t(w);
+    const bool valid = t < E;
+    const uint32_t tt = valid ? t : 0u;
+    int v[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(tt) * (D + 1) + k];
+    // stage lambda (binary32 sampling form) and the control values
+    for (uint32_t j = lane; j < MF_NMAX; j += 64) {
+        float lf[D + 1];
+        if (valid && j < N) {
+            sample_lambda_f32<D>(tt, j, key, lf);
+        } else {
+#pragma unroll
+            for (int k = 0; k <= D; ++k) lf[k] = 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lam_s[w][j][k] = k <= D ? lf[k < D + 1 ? k : 0] : 0.0f;
+    }
+    for (int idx = lane; idx < 4 * 64; idx += 64) {
+        const int k = idx >> 6, f = idx & 63;
+        g_s[w][k][f] = (valid && k <= D && f < F) ? values[int64_t(f) * ld + v[k]] : 0.0f;
+    }
+    __syncthreads();
+
+    const int sg = lane >> 4;            // sample group within a K step (8 samples)
+    const int col = lane & 15;           // B / C column: barycentric index when < d+1
+    const int64_t qbase = n + int64_t(tt) * N;
+    const int ksteps = int((N + 31) / 32);
+    unsigned int nf = 0;
+    const double scale_out = valid ? vol[tt] / double(N) : 0.0;
+    for (int f0 = 0; f0 < F; f0 += 16) {
+        const int f = f0 + (lane & 15);  // A row: field
+        const bool frow = valid && f < F;
+        // pass 1: largest residual magnitude of this field row (f16 scaling)
+        float mx = 0.0f;
+        if (!BF16) {
+            for (int ks = 0; ks < ksteps; ++ks)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t j = uint32_t(ks * 32 + sg * 8 + i);
+                    if (frow && j < N) {
+                        const float y = values[int64_t(f) * ld + qbase + j];
+                        float gx = 0.0f;
+#pragma unroll
+                        for (int k = 0; k <= D; ++k) gx = fmaf(lam_s[w][j][k], g_s[w][k][f & 63], gx);
+                        const float r = y - alpha * gx;
+                        mx = fmaxf(mx, fabsf(r));
+                    }
+                }
+            mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+            mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+        }
+        int e = 0;
+        if (!BF16 && mx > 0.0f && isfinite(mx)) e = 13 - ilogbf(mx);
+        const float sc = ldexpf(1.0f, e);
+        // pass 2: split products on the matrix cores
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int ks = 0; ks < ksteps; ++ks) {
+            typename S::vec ahi, alo, bhi, blo;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t j = uint32_t(ks * 32 + sg * 8 + i);
+                float r = 0.0f;
+                if (frow && j < N) {
+                    const float y = values[int64_t(f) * ld + qbase + j];
+                    nf += !isfinite(y);
+                    float gx = 0.0f;
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) gx = fmaf(lam_s[w][j][k], g_s[w][k][f & 63], gx);
+                    r = (y - alpha * gx) * sc;
+                }
+                S::set(ahi, alo, i, r);
+                const float lv = (col <= D && j < MF_NMAX) ? lam_s[w][j < MF_NMAX ? j : 0][col & 3] : 0.0f;
+                S::set(bhi, blo, i, lv);
+            }
+            acc = S::mma(ahi, bhi, acc);
+            acc = S::mma(ahi, blo, acc);
+            acc = S::mma(alo, bhi, acc);
+        }
+        // C[row][col]: row = 4*sg + i (field f0 + row), col = barycentric index
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 4 * sg + i;
+            const int er = __shfl(e, row, 64);
+            const int fo = f0 + row;
+            if (valid && col <= D && fo < F)
+                beta[(int64_t(fo) * E + tt) * (D + 1) + col] = ldexp(double(acc[i]), -er) * scale_out;
+        }
+    }
+    if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
+}
+
+ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
+    const SampleKey key{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
+    const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
+    const unsigned grid = grid_for(T->E, 4);
+    const bool bf = cfg->precision == FT_SPLIT_BF16;
+    const float* vals = static_cast<const float*>(values);
+    const uint32_t N = uint32_t(cfg->samples_per_elem);
+    const float a = float(cfg->alpha);
+    if (T->dim == 2) {
+        if (bf) k_consume_mfma<2, true><<<grid, 256, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+                                                             uint32_t(T->E), N, a, key, T->beta, T->counters);
+        else k_consume_mfma<2, false><<<grid, 256, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+                                                           uint32_t(T->E), N, a, key, T->beta, T->counters);
+    } else {
+        if (bf) k_consume_mfma<3, true><<<grid, 256, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+                                                             uint32_t(T->E), N, a, key, T->beta, T->counters);
+        else k_consume_mfma<3, false><<<grid, 256, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+                                                           uint32_t(T->E), N, a, key, T->beta, T->counters);
+    }
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
+}  // namespace ft

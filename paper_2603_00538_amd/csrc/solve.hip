@@ -133,7 +133,8 @@ __global__ __launch_bounds__(RB) void k_cg_init(Mat A, const double* __restrict_
         scal[S_RR] = t[1];
         scal[S_TOL2] = tol2;
         scal[S_ITERS] = 0.0;
-        scal[S_DONE] = (t[1] <= tol2) ? 1.0 : 0.0;
+        // a non-finite right-hand side cannot converge: stop at once (reported as non-finite)
+        scal[S_DONE] = (t[1] <= tol2 || !isfinite(t[1]) || !isfinite(tol2)) ? 1.0 : 0.0;
     });
 }
 
@@ -228,8 +229,12 @@ ft_status solver_alloc(ft_target* T, hipStream_t s) {
     return FT_OK;
 }
 
+ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep,
+                        hipStream_t s);
+
 ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep, hipStream_t s) {
     const int F = T->consumed_cfg.n_fields;
+    if (F > 1) return project_multi(T, cfg, x, b_out, rep, s);
     const double alpha = T->consumed_cfg.alpha;
     const int64_t n = T->n;
     const unsigned nb = unsigned(T->reduce_blocks);

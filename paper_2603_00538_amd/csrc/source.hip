@@ -186,38 +186,50 @@ __global__ void k_sort_bins(const int64_t* __restrict__ ptr, int64_t nseg, int32
     }
 }
 
-template <int D, bool IN_F32, bool OUT_F32>
+// Each wave owns 64*P consecutive points; lane l holds points base + q*64 + l.
+template <int D, int P, bool IN_F32, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t npts, const void* __restrict__ pts_, int64_t ld,
                                                   void* __restrict__ out_, int64_t ld_out, int32_t* __restrict__ ids,
                                                   unsigned long long* __restrict__ n_ood) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const bool active = i < npts;
-    double p[D];
+    const int64_t base = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * (64 * P);
+    if (base >= npts) return;   // wave-uniform
+    double p[P][D];
+    bool active[P];
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-        if (IN_F32)
-            p[c] = active ? double(static_cast<const float*>(pts_)[c * ld + i]) : 0.0;
-        else
-            p[c] = active ? static_cast<const double*>(pts_)[c * ld + i] : 0.0;
+    for (int q = 0; q < P; ++q) {
+        const int64_t i = base + q * 64 + lane;
+        active[q] = i < npts;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            if (IN_F32)
+                p[q][c] = active[q] ? double(static_cast<const float*>(pts_)[c * ld + i]) : 0.0;
+            else
+                p[q][c] = active[q] ? static_cast<const double*>(pts_)[c * ld + i] : 0.0;
+        }
     }
-    if (!__any(active)) return;
-    double best, bmu[D + 1];
-    int bid;
-    locate_wave<D>(S, p, active, best, bid, bmu);
-    const bool found = bid != INT_MAX;
-    const bool ood = active && (!found || best < kOutTol);
-    const uint64_t om = __ballot(ood);
-    if (lane == 0 && om) atomicAdd(n_ood, (unsigned long long)__popcll(om));
-    if (!active) return;
-    if (ids) ids[i] = found ? bid : -1;
-    for (int f = 0; f < S.F; ++f) {
-        const double y = p1_value<D>(S, bid, bmu, f);
-        if (OUT_F32)
-            static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
-        else
-            static_cast<double*>(out_)[int64_t(f) * ld_out + i] = y;
+    double best[P];
+    int bid[P];
+    locate_wave<D, P>(S, p, active, best, bid);
+    unsigned int nood = 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        if (!active[q]) continue;
+        const int64_t i = base + q * 64 + lane;
+        const bool found = bid[q] != INT_MAX;
+        nood += !found || best[q] < kOutTol;
+        if (ids) ids[i] = found ? bid[q] : -1;
+        double mu[D + 1];
+        winner_mu<D>(S, bid[q], p[q], mu);
+        for (int f = 0; f < S.F; ++f) {
+            const double y = p1_value<D>(S, bid[q], mu, f);
+            if (OUT_F32)
+                static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
+            else
+                static_cast<double*>(out_)[int64_t(f) * ld_out + i] = y;
+        }
     }
+    if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
 
 // ---------------------------------------------------------------- host side
@@ -340,12 +352,13 @@ SrcView source_view(const ft_source* S) {
 template <int D>
 static ft_status launch_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
                              int64_t ld_out, int32_t* ids, hipStream_t s) {
+    constexpr int P = 4;   // points per lane: one wave covers 256 consecutive points
     const SrcView v = source_view(S);
-    const unsigned grid = grid_for(npts, 256);
+    const unsigned grid = grid_for(npts, 256 * P);
     if (prec == FT_F64)
-        k_src_eval<D, false, false><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);
+        k_src_eval<D, P, false, false><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);
     else
-        k_src_eval<D, true, true><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);
+        k_src_eval<D, P, true, true><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
 }

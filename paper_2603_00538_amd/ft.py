@@ -186,6 +186,20 @@ def current_stream():
     return _torch().cuda.current_stream().cuda_stream
 
 
+def _device_ptr(t, name, dtype=None, shape0=None):
+    """Data pointer of a contiguous CUDA tensor (raises instead of passing a wrong layout)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (got strides {tuple(t.stride())})")
+    if dtype is not None and t.dtype not in dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected one of {dtype}")
+    if shape0 is not None and t.shape[0] != shape0:
+        raise ValueError(f"{name} has leading size {t.shape[0]}, expected {shape0}")
+    return t.data_ptr()
+
+
 def _soa(coords, device):
     """(n, d) array/tensor -> contiguous (d, n) float64 device tensor."""
     torch = _torch()
@@ -239,11 +253,18 @@ class Target:
         dt = torch.float32 if cfg.precision == FT_F32 else torch.float64
         if out is None:
             out = torch.empty((self.dim, Q), dtype=dt, device=self.coords.device)
-        ft_sample_points(self.handle, cfg, out.data_ptr(), current_stream())
+        if out.numel() < self.dim * Q:
+            raise ValueError(f"points buffer holds {out.numel()} values, needs {self.dim * Q}")
+        ft_sample_points(self.handle, cfg, _device_ptr(out, "points", (dt,)), current_stream())
         return out
 
     def consume(self, cfg: SampleCfg, values):
-        ft_consume_queries(self.handle, cfg, values.data_ptr(), current_stream())
+        torch = _torch()
+        dt = torch.float64 if cfg.precision == FT_F64 else torch.float32
+        Q = self.query_count(cfg.samples_per_elem)
+        if values.numel() < cfg.n_fields * Q:
+            raise ValueError(f"values hold {values.numel()} entries, need {cfg.n_fields * Q}")
+        ft_consume_queries(self.handle, cfg, _device_ptr(values, "values", (dt,)), current_stream())
 
     def transfer_from(self, source, cfg: SampleCfg):
         """Fused steps 1 and 3-6 from a built-in Source (no query list in memory)."""
@@ -255,8 +276,9 @@ class Target:
             x = torch.empty((n_fields, self.n_nodes), dtype=torch.float64, device=self.coords.device)
         if want_b and b is None:
             b = torch.empty((n_fields, self.n_nodes), dtype=torch.float64, device=self.coords.device)
-        st, reps = ft_project(self.handle, SolveCfg(rtol, max_iter), x.data_ptr(),
-                              b.data_ptr() if want_b else None, n_fields, current_stream())
+        f64 = (torch.float64,)
+        st, reps = ft_project(self.handle, SolveCfg(rtol, max_iter), _device_ptr(x, "x", f64, n_fields),
+                              _device_ptr(b, "b", f64, n_fields) if want_b else None, n_fields, current_stream())
         return Transfer(x, b, reps, st)
 
 
@@ -291,13 +313,20 @@ class Source:
     def eval(self, points, out=None, ids=None, n_points=None):
         """points: (d, ld) device tensor (float64 or float32); returns (F, ld) values."""
         torch = _torch()
+        if points.ndim != 2 or points.shape[0] != self.dim:
+            raise ValueError(f"points must have shape ({self.dim}, n)")
         ld = int(points.shape[1])
         n = ld if n_points is None else int(n_points)
         prec = FT_F32 if points.dtype == torch.float32 else FT_F64
         if out is None:
             out = torch.empty((self.n_fields, ld), dtype=points.dtype, device=points.device)
-        ft_source_eval(self.handle, n, points.data_ptr(), ld, prec, out.data_ptr(), int(out.shape[1]),
-                       ids.data_ptr() if ids is not None else None, current_stream())
+        if out.ndim != 2 or out.shape[0] != self.n_fields or out.shape[1] < n or out.dtype != points.dtype:
+            raise ValueError("out must have shape (n_fields, >= n) and the dtype of points")
+        if ids is not None and (ids.dtype != torch.int32 or ids.numel() < n):
+            raise ValueError("ids must be int32 with at least n entries")
+        ft_source_eval(self.handle, n, _device_ptr(points, "points", (torch.float32, torch.float64)), ld, prec,
+                       _device_ptr(out, "out"), int(out.shape[1]),
+                       _device_ptr(ids, "ids") if ids is not None else None, current_stream())
         return out
 
     @property

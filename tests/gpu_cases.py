@@ -72,7 +72,7 @@ def oracle_query_points(tmesh, N, seed, stream):
     dim = tc.shape[1]
     lam = sampling.element_samples(dim, tconn.shape[0], N, seed, stream)
     X = sampling.physical_points(tc, np.asarray(tconn, dtype=np.int64), lam)
-    return np.concatenate([tc, X.reshape(-1, dim)], axis=0).T
+    return np.ascontiguousarray(np.concatenate([tc, X.reshape(-1, dim)], axis=0).T)
 
 
 def rel_l2(a, b):
