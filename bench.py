@@ -174,7 +174,7 @@ def main():
             T.sample_points(cfg, out=pts)
             if record:
                 ev[1].record()
-            S.eval(pts, out=vals)
+            S.eval_query_list(pts, n, out=vals)
             if record:
                 ev[2].record()
             T.consume(cfg, vals)

@@ -21,7 +21,7 @@ ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipS
 
 static void target_release(ft_target* T) {
     void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
-                  T->beta, T->g, T->bres, T->r, T->z, T->p, T->q, T->y, T->b, T->scal, T->partials, T->ticket,
+                  T->beta, T->g, T->bres, T->r, T->z, T->p, T->q, T->y, T->b, T->scal, T->partials,
                   T->counters};
     for (void* p : ps) dev_free(p);
     if (T->h_scal) (void)hipHostFree(T->h_scal);

@@ -179,7 +179,6 @@ struct ft_target {
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *y = nullptr, *b = nullptr;
     double* scal = nullptr;               // device scalars
     double* partials = nullptr;           // per-block partial sums
-    unsigned int* ticket = nullptr;       // last-block counters
     unsigned long long* counters = nullptr;  // [0] non-finite values seen by consume
     double* h_scal = nullptr;             // pinned host mirror
     int reduce_blocks = 0;
@@ -196,12 +195,13 @@ struct ft_source {
     int32_t* conn = nullptr;    // [E][dim+1]
     double* values = nullptr;   // [F][n]
     double* rec = nullptr;      // [E][RS]: origin + inverse Jacobian (barycentric map)
-    float* box = nullptr;       // [E][2*dim] outward-rounded bounding boxes
+    float* box = nullptr;       // [E][8 | 6] outward-rounded boxes (2D also x+y, x-y ranges)
     int32_t nb[3] = {1, 1, 1};  // bins per axis
     double lo[3] = {0, 0, 0};   // grid origin
     double inv_h[3] = {1, 1, 1};// bins per unit length
     int64_t* bin_ptr = nullptr; // [nbins+1]
     int32_t* bin_elems = nullptr;
+    int32_t* bin_first = nullptr;   // [E][dim] first bin index per axis of each element's box
     int64_t n_reg = 0;
     unsigned long long* counters = nullptr;  // [0] out-of-domain points
     unsigned long long* h_counters = nullptr;

@@ -5,15 +5,25 @@
 // Localization rule: the element maximizing min_k mu_k(x) (mu: barycentric
 // coordinates); exact ties -> lowest element id; a best min mu below -1e-10
 // is out of the domain (counted, extrapolated from that element).  A point
-// whose best element has min mu > 1e-12 is strictly inside it, and no other
-// element can tie or win, so the search stops there.
+// whose best element has min mu > 1e-12 is strictly inside it: no other
+// element can tie or win, and rounding (far below 1e-12) cannot change that.
 //
-// The 64 points of a wave are usually samples of one target element, so they
-// share a handful of bins.  The wave computes its own bounding box, culls each
-// bin's candidates 64 at a time against it (one candidate per lane, a
-// ballot), and then every lane tests its point against each surviving
-// candidate, whose record is wave-uniform (scalar loads).  Waves whose points
-// span many bins (scattered input) fall back to one bin per lane.
+// Search.  The points of a wave (64 lanes x P points) are usually samples of
+// one or two target elements, so they share a handful of bins.  The wave
+// forms its points' bounding box (and, in 2D, their ranges of x+y and x-y: an
+// octagon), then culls each bin's candidates 64 at a time, one per lane:
+//   - the element's box must meet the wave's box (and octagon, in 2D);
+//   - it must not already have been offered by an earlier bin of the wave;
+//   - no barycentric coordinate may be below -1e-9 on the whole wave box.
+// Every lane then tests its points against each surviving candidate, whose
+// record is wave-uniform (scalar loads).  The selection test evaluates the
+// barycentrics as absolute affine functions (no per-candidate set-up) and
+// accepts an element once its min mu exceeds 1e-9, far above that form's
+// rounding, so an accepted element truly contains the point and is the
+// unique winner.  Points never accepted (within 1e-9 of a face, or outside)
+// are re-searched in their own bin with the full rule.  The barycentrics used
+// to interpolate are always recomputed from the element origin.  Waves whose points span
+// many bins (scattered input) search one bin per point.
 #pragma once
 
 #include <cfloat>
@@ -22,11 +32,26 @@
 
 namespace ft {
 
-constexpr double kInsideTau = 1e-12;
+constexpr double kInsideTau = 1e-12;   // strictly inside (rule winner is unique)
+constexpr double kFastTau = 1e-9;      // accepted by the fast selection test (absolute affine form)
 constexpr double kOutTol = -1e-10;
 
+// Record of element e, rec[e*RS ...] (doubles):
+//   [0, D)                 origin x0 (vertex 0)
+//   [D, D + D*D)           A, the inverse of J = [x1-x0 | ... | xd-x0] (row k gives mu_{k+1})
+//   [AF, AF + D + 1)       constants c_k of mu_k(x) = c_k + g_k . x in absolute coordinates
+//   [AF + D + 1, ...)      gradients g_k (D each), k = 0..D
+// The absolute affine form selects the element; the origin form gives the
+// barycentrics used to interpolate.
 template <int D>
-struct RecSize { static constexpr int value = D == 2 ? 8 : 16; };
+struct RecSize { static constexpr int value = D == 2 ? 16 : 32; };
+template <int D>
+struct RecAffine { static constexpr int value = D + D * D; };
+
+// floats per element in the box array: min/max per axis, plus (2D) the
+// ranges of x+y and x-y
+template <int D>
+struct BoxSize { static constexpr int value = D == 2 ? 8 : 6; };
 
 __device__ __forceinline__ float f32_down(double x) {
     float f = (float)x;
@@ -53,7 +78,6 @@ __device__ __forceinline__ int bin_of(double x, int c, const GridView& g) {
     return int(u);
 }
 
-// ---------------------------------------------------------------- evaluation
 struct SrcView {
     const double* rec;
     const float* box;
@@ -61,13 +85,14 @@ struct SrcView {
     const double* values;
     const int64_t* bin_ptr;
     const int32_t* bin_elems;
+    const int32_t* bin_first;
     int64_t n;
     int F;
     GridView g;
 };
 
-// Barycentric coordinates of p in element e (record r): mu_{k+1} = A[k] . (p - x0),
-// mu_0 = 1 - sum.  Returns min_k mu_k.
+// Barycentric coordinates of p in the element of record r (origin x0 and the
+// inverse Jacobian A): mu_{k+1} = A[k] . (p - x0), mu_0 = 1 - sum.  Returns min mu.
 template <int D>
 __device__ __forceinline__ double barycentric(const double* __restrict__ r, const double (&p)[D],
                                               double (&mu)[D + 1]) {
@@ -88,6 +113,7 @@ __device__ __forceinline__ double barycentric(const double* __restrict__ r, cons
     return fmin(mn, mu[0]);
 }
 
+// Full rule (max of min mu, ties to the lowest id), absolute coordinates.
 template <int D>
 __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int e, const double (&p)[D], double& best,
                                                int& bid) {
@@ -99,16 +125,70 @@ __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int
     }
 }
 
-// Rule winner for each of this lane's P points among the candidates of the
-// bins the wave's points touch (see the file comment).  Every lane of the
-// wave must call it (points a lane does not own pass active = false).
-// Returns best = max min-barycentric and bid = its element id (INT_MAX if no
-// candidate was found) per point; barycentric() recomputes mu for the winner.
+// min_k mu_k(p) from the absolute affine form (selection only).
+template <int D>
+__device__ __forceinline__ double affine_min_mu(const double* __restrict__ r, const double (&p)[D]) {
+    constexpr int AF = RecAffine<D>::value;
+    double mn = INFINITY;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        double s = r[AF + k];
+#pragma unroll
+        for (int c = 0; c < D; ++c) s = fma(r[AF + D + 1 + k * D + c], p[c], s);
+        mn = fmin(mn, s);
+    }
+    return mn;
+}
+
+// Conservative test whether element r can contain a point of the box
+// [lo, hi]: false only if some barycentric coordinate is below -1e-9 on the
+// whole box (a linear function's maximum over a box sits at a corner).
+template <int D>
+__device__ __forceinline__ bool box_may_meet(const double* __restrict__ r, const double (&lo)[D],
+                                             const double (&hi)[D]) {
+    constexpr int AF = RecAffine<D>::value;
+    bool meet = true;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        double mx = r[AF + k];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const double gk = r[AF + D + 1 + k * D + c];
+            mx += fmax(gk * lo[c], gk * hi[c]);
+        }
+        meet &= mx >= -1e-9;
+    }
+    return meet;
+}
+
+// Own-bin search of one point with the full rule (absolute coordinates).
+template <int D>
+__device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)[D], double& best, int& bid) {
+    constexpr int RS = RecSize<D>::value;
+    int bc[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < D; ++c) bc[c] = bin_of(p[c], c, S.g);
+    const int64_t b = (int64_t(bc[2]) * S.g.nb[1] + bc[1]) * S.g.nb[0] + bc[0];
+    const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
+    best = -DBL_MAX;
+    bid = INT_MAX;
+    for (int64_t c = start; c < end; ++c) {
+        const int e = S.bin_elems[c];
+        test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid);
+        if (best > kInsideTau) break;
+    }
+}
+
+// Rule winner for each of this lane's P points (see the file comment).  Every
+// lane of the wave must call it (points a lane does not own pass
+// active = false).  Returns best = max min-barycentric and bid = its element
+// id (INT_MAX if no candidate was found) per point.
 template <int D, int P>
 __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[P][D], const bool (&active)[P],
                                             double (&best)[P], int (&bid)[P]) {
     constexpr int RS = RecSize<D>::value;
-    constexpr int MAX_SPAN = D == 2 ? 9 : 12;
+    constexpr int BS = BoxSize<D>::value;
+    constexpr int MAX_SPAN = D == 2 ? 16 : 27;
     const int lane = threadIdx.x & 63;
     double wlo[D], whi[D];
     int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
@@ -141,21 +221,46 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             flo[c] = f32_down(wlo[c]);
             fhi[c] = f32_up(whi[c]);
         }
+        float fu[4] = {-INFINITY, INFINITY, -INFINITY, INFINITY};   // wave ranges of x+y and x-y (2D)
+        if constexpr (D == 2) {
+            double ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
+#pragma unroll
+            for (int q = 0; q < P; ++q)
+                if (active[q]) {
+                    const double u = p[q][0] + p[q][1], v = p[q][0] - p[q][1];
+                    ulo = fmin(ulo, u);
+                    uhi = fmax(uhi, u);
+                    vlo = fmin(vlo, v);
+                    vhi = fmax(vhi, v);
+                }
+            fu[0] = f32_down(wave_min(ulo));
+            fu[1] = f32_up(wave_max(uhi));
+            fu[2] = f32_down(wave_min(vlo));
+            fu[3] = f32_up(wave_max(vhi));
+        }
         bool finished = false;
         for (int bz = b0[2]; bz <= b1[2] && !finished; ++bz)
             for (int by = b0[1]; by <= b1[1] && !finished; ++by)
                 for (int bx = b0[0]; bx <= b1[0] && !finished; ++bx) {
                     const int64_t b = (int64_t(bz) * S.g.nb[1] + by) * S.g.nb[0] + bx;
                     const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
+                    const int cur[3] = {bx, by, bz};
                     for (int64_t c0 = start; c0 < end && !finished; c0 += 64) {
                         int cid = -1;
                         bool ov = false;
                         if (c0 + lane < end) {
                             cid = S.bin_elems[c0 + lane];
-                            const float* bx_ = S.box + int64_t(cid) * 2 * D;
+                            const float* bx_ = S.box + int64_t(cid) * BS;
                             ov = true;
 #pragma unroll
-                            for (int c = 0; c < D; ++c) ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
+                            for (int c = 0; c < D; ++c) {
+                                ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
+                                // offer each element once per wave: in the first of the wave's bins it is in
+                                ov &= max(S.bin_first[int64_t(cid) * D + c], b0[c]) == cur[c];
+                            }
+                            if constexpr (D == 2)
+                                ov &= (bx_[4] <= fu[1]) & (bx_[6] >= fu[0]) & (bx_[5] <= fu[3]) & (bx_[7] >= fu[2]);
+                            if (ov) ov = box_may_meet<D>(S.rec + int64_t(cid) * RS, wlo, whi);
                         }
                         uint64_t mask = __ballot(ov);
                         while (mask) {
@@ -166,8 +271,12 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                             bool done = true;
 #pragma unroll
                             for (int q = 0; q < P; ++q) {
-                                test_candidate<D>(r, e, p[q], best[q], bid[q]);
-                                done &= !active[q] || best[q] > kInsideTau;
+                                const double mn = affine_min_mu<D>(r, p[q]);
+                                if (mn > best[q]) {
+                                    best[q] = mn;
+                                    bid[q] = e;
+                                }
+                                done &= !active[q] || best[q] > kFastTau;
                             }
                             if (__all(done)) {
                                 finished = true;
@@ -176,21 +285,22 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                         }
                     }
                 }
-    } else {
+        // points not accepted by the fast test (near a face, or outside): the full rule
+        // in the point's own bin; accepted points get their exact min mu
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             if (!active[q]) continue;
-            int bc[3] = {0, 0, 0};
-#pragma unroll
-            for (int c = 0; c < D; ++c) bc[c] = bin_of(p[q][c], c, S.g);
-            const int64_t b = (int64_t(bc[2]) * S.g.nb[1] + bc[1]) * S.g.nb[0] + bc[0];
-            const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
-            for (int64_t c = start; c < end; ++c) {
-                const int e = S.bin_elems[c];
-                test_candidate<D>(S.rec + int64_t(e) * RS, e, p[q], best[q], bid[q]);
-                if (best[q] > kInsideTau) break;
+            if (best[q] > kFastTau) {
+                double mu[D + 1];
+                best[q] = barycentric<D>(S.rec + int64_t(bid[q]) * RS, p[q], mu);
+            } else {
+                locate_point<D>(S, p[q], best[q], bid[q]);
             }
         }
+    } else {
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+            if (active[q]) locate_point<D>(S, p[q], best[q], bid[q]);
     }
 }
 

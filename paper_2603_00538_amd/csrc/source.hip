@@ -90,6 +90,27 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
     for (int k = 0; k < D; ++k)
 #pragma unroll
         for (int c = 0; c < D; ++c) r[D + k * D + c] = A[k][c];
+    // absolute affine form: mu_{k+1}(x) = A[k] . x - A[k] . x0, mu_0 = 1 - sum
+    constexpr int AF = RecAffine<D>::value;
+    double csum = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) r[AF + D + 1 + c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double ck = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            ck = fma(-A[k][c], x[0][c], ck);
+            r[AF + D + 1 + (k + 1) * D + c] = A[k][c];
+            r[AF + D + 1 + c] -= A[k][c];
+        }
+        r[AF + k + 1] = ck;
+        csum += ck;
+    }
+    r[AF] = 1.0 - csum;
+#pragma unroll
+    for (int i = AF + (D + 1) * (D + 1); i < RS; ++i) r[i] = 0.0;
+    constexpr int BS = BoxSize<D>::value;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         double lo = x[0][c], hi = x[0][c];
@@ -98,8 +119,24 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
             lo = fmin(lo, x[k][c]);
             hi = fmax(hi, x[k][c]);
         }
-        box[e * 2 * D + c] = f32_down(lo);
-        box[e * 2 * D + D + c] = f32_up(hi);
+        box[e * BS + c] = f32_down(lo);
+        box[e * BS + D + c] = f32_up(hi);
+    }
+    if constexpr (D == 2) {
+        // ranges of u = x + y and v = x - y over the vertices: [umin, vmin, umax, vmax]
+        double ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) {
+            const double u = x[k][0] + x[k][1], v = x[k][0] - x[k][1];
+            ulo = fmin(ulo, u);
+            uhi = fmax(uhi, u);
+            vlo = fmin(vlo, v);
+            vhi = fmax(vhi, v);
+        }
+        box[e * BS + 4] = f32_down(ulo);
+        box[e * BS + 5] = f32_down(vlo);
+        box[e * BS + 6] = f32_up(uhi);
+        box[e * BS + 7] = f32_up(vhi);
     }
 }
 
@@ -125,11 +162,14 @@ __device__ __forceinline__ void elem_bin_range(const double* __restrict__ X, int
 template <int D, bool FILL>
 __global__ void k_src_register(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
                                GridView g, int32_t* __restrict__ cnt, const int64_t* __restrict__ ptr,
-                               int32_t* __restrict__ elems) {
+                               int32_t* __restrict__ elems, int32_t* __restrict__ first) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= E) return;
     int b0[3], b1[3];
     elem_bin_range<D>(X, n, conn, e, g, b0, b1);
+    if (!FILL)
+#pragma unroll
+        for (int c = 0; c < D; ++c) first[e * D + c] = b0[c];
     for (int bz = b0[2]; bz <= b1[2]; ++bz)
         for (int by = b0[1]; by <= b1[1]; ++by)
             for (int bx = b0[0]; bx <= b1[0]; ++bx) {
@@ -243,7 +283,7 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     FT_TRY(dev_alloc_n(&S->conn, size_t(E) * (D + 1)));
     FT_TRY(dev_alloc_n(&S->values, size_t(S->F) * n));
     FT_TRY(dev_alloc_n(&S->rec, size_t(E) * RS));
-    FT_TRY(dev_alloc_n(&S->box, size_t(E) * 2 * D));
+    FT_TRY(dev_alloc_n(&S->box, size_t(E) * BoxSize<D>::value));
     FT_TRY(dev_alloc_n(&S->counters, 4));
     FT_TRY_HIP(hipHostMalloc((void**)&S->h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault));
     FT_TRY_HIP(hipMemcpyAsync(S->coords, coords, sizeof(double) * D * n, hipMemcpyDeviceToDevice, s));
@@ -319,7 +359,9 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     FT_TRY(dev_alloc_n(&tmp, size_t(scan_tmp_elems(nbins))));
     FT_TRY(dev_alloc_n(&S->bin_ptr, size_t(nbins + 1)));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
-    k_src_register<D, false><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, nullptr, nullptr);
+    FT_TRY(dev_alloc_n(&S->bin_first, size_t(E) * D));
+    k_src_register<D, false><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, nullptr, nullptr,
+                                                           S->bin_first);
     FT_TRY(exclusive_scan(cnt, S->bin_ptr, nbins, tmp, s));
     int64_t nreg = 0;
     FT_TRY_HIP(hipMemcpyAsync(&nreg, S->bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -327,7 +369,8 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     S->n_reg = nreg;
     FT_TRY(dev_alloc_n(&S->bin_elems, size_t(nreg)));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
-    k_src_register<D, true><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, S->bin_ptr, S->bin_elems);
+    k_src_register<D, true><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, S->bin_ptr, S->bin_elems,
+                                                          nullptr);
     k_sort_bins<<<grid_for(nbins, B), B, 0, s>>>(S->bin_ptr, nbins, S->bin_elems);
     FT_TRY_HIP(hipGetLastError());
     FT_TRY_HIP(hipStreamSynchronize(s));
@@ -340,7 +383,7 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
 }
 
 SrcView source_view(const ft_source* S) {
-    SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
+    SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->bin_first, S->n, S->F, {}};
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
         v.g.lo[c] = S->lo[c];
@@ -378,6 +421,7 @@ ft_status source_release(ft_source* S) {
     dev_free(S->box);
     dev_free(S->bin_ptr);
     dev_free(S->bin_elems);
+    dev_free(S->bin_first);
     dev_free(S->counters);
     if (S->h_counters) (void)hipHostFree(S->h_counters);
     return FT_OK;

@@ -310,24 +310,37 @@ class Source:
         except Exception:
             pass
 
-    def eval(self, points, out=None, ids=None, n_points=None):
-        """points: (d, ld) device tensor (float64 or float32); returns (F, ld) values."""
+    def eval(self, points, out=None, ids=None, start=0, count=None):
+        """Evaluate points[:, start:start+count] of a (d, ld) device tensor into out[:, start:start+count].
+
+        Returns out, (F, ld) in the dtype of points.  The range form lets a
+        caller evaluate blocks of a query list separately (e.g. the node block
+        and the sample block), with the list's leading dimension.
+        """
         torch = _torch()
         if points.ndim != 2 or points.shape[0] != self.dim:
             raise ValueError(f"points must have shape ({self.dim}, n)")
         ld = int(points.shape[1])
-        n = ld if n_points is None else int(n_points)
+        count = ld - start if count is None else int(count)
+        if start < 0 or count < 0 or start + count > ld:
+            raise ValueError("start/count out of range")
         prec = FT_F32 if points.dtype == torch.float32 else FT_F64
         if out is None:
             out = torch.empty((self.n_fields, ld), dtype=points.dtype, device=points.device)
-        if out.ndim != 2 or out.shape[0] != self.n_fields or out.shape[1] < n or out.dtype != points.dtype:
-            raise ValueError("out must have shape (n_fields, >= n) and the dtype of points")
-        if ids is not None and (ids.dtype != torch.int32 or ids.numel() < n):
-            raise ValueError("ids must be int32 with at least n entries")
-        ft_source_eval(self.handle, n, _device_ptr(points, "points", (torch.float32, torch.float64)), ld, prec,
-                       _device_ptr(out, "out"), int(out.shape[1]),
-                       _device_ptr(ids, "ids") if ids is not None else None, current_stream())
+        if out.ndim != 2 or out.shape[0] != self.n_fields or out.shape[1] < start + count or out.dtype != points.dtype:
+            raise ValueError("out must have shape (n_fields, >= start + count) and the dtype of points")
+        if ids is not None and (ids.dtype != torch.int32 or ids.numel() < start + count):
+            raise ValueError("ids must be int32 with at least start + count entries")
+        isz = points.element_size()
+        ft_source_eval(self.handle, count, _device_ptr(points, "points", (torch.float32, torch.float64)) + start * isz,
+                       ld, prec, _device_ptr(out, "out") + start * isz, int(out.shape[1]),
+                       (_device_ptr(ids, "ids") + start * 4) if ids is not None else None, current_stream())
         return out
+
+    def eval_query_list(self, points, n_nodes, out=None, ids=None):
+        """Evaluate a transfer's query list as its two blocks (target nodes, then samples)."""
+        out = self.eval(points, out=out, ids=ids, start=0, count=n_nodes)
+        return self.eval(points, out=out, ids=ids, start=n_nodes)
 
     @property
     def info(self):

@@ -36,7 +36,7 @@ def gpu_transfer(tmesh, smesh, svals, N, alpha=1.0, seed=7, stream=0, precision=
     pts = T.sample_points(cfg)
     ids = torch.full((pts.shape[1],), -7, dtype=torch.int32, device=pts.device)
     if black_box is None:
-        vals = S.eval(pts, ids=ids)
+        vals = S.eval_query_list(pts, tc.shape[0], ids=ids)
     else:
         vals = black_box(pts)
         F = vals.shape[0]

@@ -43,7 +43,7 @@ def _run(tm, sm, sv, precision):
     cfg = ft.SampleCfg(W.samples_per_elem, 1, W.alpha, W.philox_seed, 0, precision)
     pts = T.sample_points(cfg)
     ids = torch.empty(pts.shape[1], dtype=torch.int32, device="cuda")
-    vals = S.eval(pts, ids=ids)
+    vals = S.eval_query_list(pts, tc.shape[0], ids=ids)
     T.consume(cfg, vals)
     res = T.project(1, rtol=W.rtol)
     torch.cuda.synchronize()
@@ -145,7 +145,7 @@ def test_fullsize_solution_and_conservation(case, fp64):
 def test_fullsize_rerun_is_bitwise_identical(case, fp64):
     T, S, cfg, pts, vals, ids, res = fp64
     x0 = res.x.clone()
-    S.eval(pts, out=vals)
+    S.eval_query_list(pts, T.info.n_nodes, out=vals)
     T.consume(cfg, vals)
     again = T.project(1, rtol=W.rtol)
     assert torch.equal(again.x, x0)
