@@ -61,7 +61,10 @@ typedef enum {
 
 typedef enum {
     FT_F64 = 0,            /* points and values in binary64                                   */
-    FT_F32 = 1             /* points and values in binary32 (coordinates converted inside)    */
+    FT_F32 = 1,            /* points and values in binary32 (coordinates converted inside)    */
+    FT_SPLIT_F16 = 2,      /* binary32 points and values; element sums of many fields on the
+                              matrix cores as hi+lo binary16 products, binary32 accumulation   */
+    FT_SPLIT_BF16 = 3      /* as FT_SPLIT_F16 with hi+lo bfloat16 products                    */
 } ft_precision;
 
 typedef struct ft_target ft_target;

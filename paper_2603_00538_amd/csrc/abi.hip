@@ -31,7 +31,8 @@ static ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) 
     FT_ARG_CHECK(cfg, "cfg is null");
     FT_ARG_CHECK(cfg->samples_per_elem >= 1, "samples_per_elem must be >= 1 (got %d)", cfg->samples_per_elem);
     FT_ARG_CHECK(cfg->n_fields >= 1, "n_fields must be >= 1 (got %d)", cfg->n_fields);
-    FT_ARG_CHECK(cfg->precision == FT_F64 || cfg->precision == FT_F32, "precision must be FT_F64 or FT_F32");
+    FT_ARG_CHECK(cfg->precision >= FT_F64 && cfg->precision <= FT_SPLIT_BF16, "precision out of range (%d)",
+                 cfg->precision);
     FT_ARG_CHECK(std::isfinite(cfg->alpha), "alpha must be finite");
     if (uint64_t(T->E) * uint64_t(cfg->samples_per_elem) >= (uint64_t(1) << 32) ||
         uint64_t(T->E) * 64u >= (uint64_t(1) << 32)) {
@@ -57,9 +58,12 @@ static ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream) {
     return FT_OK;
 }
 
+// binary32 point forms (FT_F32 and the split forms) sample the same points
+static bool point_f32(int prec) { return prec != FT_F64; }
+
 static bool same_samples(const ft_sample_cfg& a, const ft_sample_cfg& b) {
     return a.samples_per_elem == b.samples_per_elem && a.seed == b.seed && a.stream_id == b.stream_id &&
-           a.precision == b.precision;
+           point_f32(a.precision) == point_f32(b.precision);
 }
 
 }  // namespace ft
@@ -162,7 +166,7 @@ ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void*
     auto* T = static_cast<ft_target_ext*>(t);
     if (!T->sampled || !same_samples(T->sampled_cfg, *cfg)) {
         set_error("consume needs a prior ft_sample_points with the same samples_per_elem, seed, stream_id and "
-                  "precision");
+                  "point precision");
         return FT_E_ORDER;
     }
     FT_TRY(ensure_field_buffers(T, cfg->n_fields, stream));

@@ -180,7 +180,7 @@ static ft_status emit_impl(ft_target* T, const ft_sample_cfg* cfg, void* points,
     const uint32_t N = uint32_t(cfg->samples_per_elem);
     const uint64_t total = uint64_t(T->E) * N;
     const int64_t ld = T->n + int64_t(total);
-    const bool f32 = cfg->precision == FT_F32;
+    const bool f32 = cfg->precision != FT_F64;
     if (f32)
         k_emit_nodes<true><<<grid_for(T->n, 256), 256, 0, s>>>(T->coords, T->n, D, points, ld);
     else
@@ -252,12 +252,19 @@ ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld,
     return FT_OK;
 }
 
+ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s);
+constexpr int kMfmaMaxSamples = 256;   // the matrix-core form stages <= 256 samples
+constexpr int kMfmaMaxFields = 64;     // and <= 64 control values per vertex in LDS
+
 template <int D>
 static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
     const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
-    const bool f32 = cfg->precision == FT_F32;
+    const bool f32 = cfg->precision != FT_F64;
+    const bool split = cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16;
     zero_counter(T->counters, s);
-    if (f32) consume_g<D, true>(T, cfg, values, ld, s);
+    if (split && cfg->samples_per_elem <= kMfmaMaxSamples && cfg->n_fields <= kMfmaMaxFields)
+        FT_TRY(consume_mfma(T, cfg, values, s));
+    else if (f32) consume_g<D, true>(T, cfg, values, ld, s);
     else consume_g<D, false>(T, cfg, values, ld, s);
     FT_TRY_HIP(hipGetLastError());
     return assemble_residual(T, cfg->n_fields, values, ld, f32, s);

@@ -7,9 +7,14 @@
 // are shared by its Fp lanes and the products read Fp consecutive doubles per
 // column (coalesced), so the matrix is read once for all fields.  Every field
 // keeps its own CG scalars and convergence flag; a converged field stops
-// updating while the others continue.  Reductions are deterministic: each lane
-// sums its own field over a fixed set of rows, blocks add their waves in a
-// fixed order, and the last block adds block partials in block order.
+// updating while the others continue.
+//
+// Reductions without atomics: each block writes one partial per field (its
+// lanes of that field, in a fixed order); a one-block kernel adds the partials
+// of every field in block order and updates that field's CG scalars.  One
+// iteration is four launches: (direction p = z + beta p_old formed on the fly,
+// q = M p, partial p.q), (alpha), (update y, r, z, partial r.z, r.r),
+// (stopping test, beta for the next direction).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -19,9 +24,10 @@
 namespace ft {
 
 constexpr int MB = 256;               // threads per block
-constexpr int MAX_MBLOCKS = 1024;
+constexpr int MAX_MBLOCKS = 512;
 
-enum { SC_RHO = 0, SC_ALPHA, SC_BETA, SC_RR, SC_BB, SC_DONE, SC_ITERS, SC_TOL2, SC_SUMB, SC_INTX, SC_TRR, SC_ALL,
+enum { PM_BB = 0, PM_SB, PM_RZ, PM_RR, PM_PQ, PM_TRR, PM_MX, PM_COUNT };
+enum { SC_RHO = 0, SC_ALPHA, SC_BETA, SC_TOL2, SC_DONE, SC_ITERS, SC_BB, SC_SUMB, SC_INTX, SC_TRR, SC_ALL,
        SC_COUNT };
 
 struct MView {
@@ -34,65 +40,47 @@ struct MView {
     int F, Fp, shift;   // Fp = 1 << shift
 };
 
-__device__ __forceinline__ double row_dot(const MView& A, int64_t i, const double* __restrict__ v, int f) {
-    double s = 0.0;
-    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) s = fma(A.val[k], v[int64_t(A.col[k]) * A.Fp + f], s);
-    return s;
-}
-
-// Sum each lane's NV values per field over the block (fixed order), then over
-// blocks in the last block; fin(f, totals) runs once per field there.
-template <int NV, class Fin>
-__device__ __forceinline__ void field_reduce(const MView& A, double (&v)[NV], double* __restrict__ partials,
-                                             unsigned int* ticket, Fin fin) {
-    __shared__ double sm[NV][MB];
-    __shared__ bool last;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) sm[k][threadIdx.x] = v[k];
-    __syncthreads();
-    // lanes with the same field: threadIdx % Fp; rows in a fixed order
-    if (threadIdx.x < unsigned(A.Fp)) {
-        const int f = threadIdx.x;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int r = f; r < MB; r += A.Fp) s += sm[k][r];
-            partials[(int64_t(k) * A.Fp + f) * gridDim.x + blockIdx.x] = s;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (threadIdx.x < unsigned(A.Fp)) {
-        const int f = threadIdx.x;
-        double t[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (unsigned int b = 0; b < gridDim.x; ++b) s += partials[(int64_t(k) * A.Fp + f) * gridDim.x + b];
-            t[k] = s;
-        }
-        if (f < A.F) fin(f, t);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *ticket = 0u;
-}
-
 #define FOR_ROWS(A, i, f)                                                                        \
     const int f = int(threadIdx.x) & (A.Fp - 1);                                                 \
     const int64_t row0 = (int64_t(blockIdx.x) * MB + threadIdx.x) >> A.shift;                    \
     const int64_t rstride = (int64_t(gridDim.x) * MB) >> A.shift;                                \
     for (int64_t i = row0; i < A.n; i += rstride)
 
+__device__ __forceinline__ double row_dot(const MView& A, int64_t i, const double* __restrict__ v, int f) {
+    double s = 0.0;
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) s = fma(A.val[k], v[int64_t(A.col[k]) * A.Fp + f], s);
+    return s;
+}
+
+// part[(slot * Fp + f) * nb + block] = sum over this block's lanes of field f (fixed order)
+template <int NV>
+__device__ __forceinline__ void field_partials(const MView& A, const double (&v)[NV], const int (&slot)[NV],
+                                               double* __restrict__ part) {
+    __shared__ double sm[NV][MB];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sm[k][threadIdx.x] = v[k];
+    __syncthreads();
+    if (threadIdx.x < unsigned(A.Fp)) {
+        const int f = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int r = f; r < MB; r += A.Fp) s += sm[k][r];
+            part[(int64_t(slot[k]) * A.Fp + f) * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+__device__ __forceinline__ double field_total(const MView& A, const double* __restrict__ part, int slot, int f,
+                                              int nb) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t(slot) * A.Fp + f) * nb + b];
+    return s;
+}
+
 __global__ __launch_bounds__(MB) void k_m_transpose_in(const double* __restrict__ src, int64_t n, int F, int Fp,
                                                        double* __restrict__ dst) {
-    // dst[i*Fp + f] = src[f*n + i] (0 for padded fields)
-    const int64_t idx = int64_t(blockIdx.x) * MB + threadIdx.x;
+    const int64_t idx = int64_t(blockIdx.x) * MB + threadIdx.x;   // dst[i*Fp + f] = src[f*n + i]
     if (idx >= n * Fp) return;
     const int64_t i = idx / Fp;
     const int f = int(idx - i * Fp);
@@ -101,19 +89,17 @@ __global__ __launch_bounds__(MB) void k_m_transpose_in(const double* __restrict_
 
 __global__ __launch_bounds__(MB) void k_m_transpose_out(const double* __restrict__ src, int64_t n, int F, int Fp,
                                                         double* __restrict__ dst) {
-    // dst[f*n + i] = src[i*Fp + f]
-    const int64_t idx = int64_t(blockIdx.x) * MB + threadIdx.x;
+    const int64_t idx = int64_t(blockIdx.x) * MB + threadIdx.x;   // dst[f*n + i] = src[i*Fp + f]
     if (idx >= n * F) return;
     const int f = int(idx / n);
     const int64_t i = idx - int64_t(f) * n;
     dst[idx] = src[i * Fp + f];
 }
 
-// B = alpha M G + R (R holds b_res on entry); sums ||b||^2 and sum b per field.
+// B = alpha M G + R (R holds b_res); partials of ||b||^2 and sum b.
 __global__ __launch_bounds__(MB) void k_m_rhs(MView A, const double* __restrict__ G, double alpha,
                                               const double* __restrict__ Bres, double* __restrict__ B,
-                                              double* __restrict__ sc, double* __restrict__ partials,
-                                              unsigned int* ticket) {
+                                              double* __restrict__ part) {
     double v[2] = {0.0, 0.0};
     FOR_ROWS(A, i, f) {
         const double bi = alpha * row_dot(A, i, G, f) + Bres[i * A.Fp + f];
@@ -121,67 +107,109 @@ __global__ __launch_bounds__(MB) void k_m_rhs(MView A, const double* __restrict_
         v[0] = fma(bi, bi, v[0]);
         v[1] += bi;
     }
-    field_reduce<2>(A, v, partials, ticket, [&](int ff, double (&t)[2]) {
-        sc[SC_BB * A.Fp + ff] = t[0];
-        sc[SC_SUMB * A.Fp + ff] = t[1];
-    });
+    const int slot[2] = {PM_BB, PM_SB};
+    field_partials<2>(A, v, slot, part);
 }
 
-__global__ __launch_bounds__(MB) void k_m_init(MView A, double rtol2, double* __restrict__ Y, double* __restrict__ R,
-                                               double* __restrict__ Z, double* __restrict__ P, double* __restrict__ sc,
-                                               double* __restrict__ partials, unsigned int* ticket) {
+// Y = 0, Z = D^-1 R, P_old = 0; partials of r.z and r.r.
+__global__ __launch_bounds__(MB) void k_m_init(MView A, double* __restrict__ Y, const double* __restrict__ R,
+                                               double* __restrict__ Z, double* __restrict__ P,
+                                               double* __restrict__ part) {
     double v[2] = {0.0, 0.0};
     FOR_ROWS(A, i, f) {
         const int64_t o = i * A.Fp + f;
-        const double ri = R[o];   // b_res
+        const double ri = R[o];
         const double zi = ri / A.diag[i];
         Y[o] = 0.0;
         Z[o] = zi;
-        P[o] = zi;
+        P[o] = 0.0;
         v[0] = fma(ri, zi, v[0]);
         v[1] = fma(ri, ri, v[1]);
     }
-    field_reduce<2>(A, v, partials, ticket, [&](int ff, double (&t)[2]) {
-        const double tol2 = rtol2 * sc[SC_BB * A.Fp + ff];
-        sc[SC_RHO * A.Fp + ff] = t[0];
-        sc[SC_RR * A.Fp + ff] = t[1];
-        sc[SC_TOL2 * A.Fp + ff] = tol2;
-        sc[SC_ITERS * A.Fp + ff] = 0.0;
-        sc[SC_DONE * A.Fp + ff] = (t[1] <= tol2 || !isfinite(t[1]) || !isfinite(tol2)) ? 1.0 : 0.0;
-        sc[SC_ALPHA * A.Fp + ff] = 0.0;
-        sc[SC_BETA * A.Fp + ff] = 0.0;
-    });
+    const int slot[2] = {PM_RZ, PM_RR};
+    field_partials<2>(A, v, slot, part);
 }
 
-// all-fields-done flag: computed by one small kernel after every update
-__global__ void k_m_all_done(int F, int Fp, double* __restrict__ sc) {
-    if (threadIdx.x == 0) {
-        double all = 1.0;
-        for (int f = 0; f < F; ++f) all = sc[SC_DONE * Fp + f] != 0.0 ? all : 0.0;
-        sc[SC_ALL * Fp] = all;
+// Per-field scalar updates from the partials (one block; thread f = field).
+//   mode 0: after k_m_rhs   -> ||b||^2, sum b, threshold, reset
+//   mode 1: after r.z, r.r  -> stopping test, beta = rz / rho (0 at k = 0), rho = rz
+//   mode 2: after p.q       -> alpha = rho / pq
+//   mode 3: after k_m_report -> true residual, m^T x
+__global__ __launch_bounds__(MB) void k_m_scalars(MView A, int mode, int k, int nb, double rtol2,
+                                                  const double* __restrict__ part, double* __restrict__ sc) {
+    const int f = threadIdx.x;
+    __shared__ int not_done;
+    if (threadIdx.x == 0) not_done = 0;
+    __syncthreads();
+    if (f < A.F) {
+        const int Fp = A.Fp;
+        if (mode == 0) {
+            const double bb = field_total(A, part, PM_BB, f, nb);
+            sc[SC_BB * Fp + f] = bb;
+            sc[SC_SUMB * Fp + f] = field_total(A, part, PM_SB, f, nb);
+            sc[SC_TOL2 * Fp + f] = rtol2 * bb;
+            sc[SC_DONE * Fp + f] = 0.0;
+            sc[SC_ITERS * Fp + f] = 0.0;
+            sc[SC_BETA * Fp + f] = 0.0;
+            sc[SC_ALPHA * Fp + f] = 0.0;
+            not_done = 1;
+        } else if (mode == 1) {
+            if (sc[SC_DONE * Fp + f] == 0.0) {
+                const double rz = field_total(A, part, PM_RZ, f, nb);
+                const double rr = field_total(A, part, PM_RR, f, nb);
+                if (rr <= sc[SC_TOL2 * Fp + f] || !isfinite(rr)) {
+                    sc[SC_DONE * Fp + f] = 1.0;
+                    sc[SC_ITERS * Fp + f] = double(k);
+                } else {
+                    sc[SC_BETA * Fp + f] = k == 0 ? 0.0 : rz / sc[SC_RHO * Fp + f];
+                    sc[SC_RHO * Fp + f] = rz;
+                    sc[SC_ITERS * Fp + f] = double(k);
+                    atomicOr(&not_done, 1);
+                }
+            }
+        } else if (mode == 2) {
+            if (sc[SC_DONE * Fp + f] == 0.0) {
+                sc[SC_ALPHA * Fp + f] = sc[SC_RHO * Fp + f] / field_total(A, part, PM_PQ, f, nb);
+                atomicOr(&not_done, 1);
+            }
+        } else {
+            sc[SC_TRR * Fp + f] = field_total(A, part, PM_TRR, f, nb);
+            sc[SC_INTX * Fp + f] = field_total(A, part, PM_MX, f, nb);
+        }
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && mode != 3) sc[SC_ALL * A.Fp] = not_done ? 0.0 : 1.0;
 }
 
-__global__ __launch_bounds__(MB) void k_m_spmv(MView A, const double* __restrict__ P, double* __restrict__ Qv,
-                                               double* __restrict__ sc, double* __restrict__ partials,
-                                               unsigned int* ticket) {
+// direction and product: P_new = Z + beta P_old (own rows), Q = M P; partial p.q
+__global__ __launch_bounds__(MB) void k_m_spmv(MView A, const double* __restrict__ Z, const double* __restrict__ Pold,
+                                               double* __restrict__ Pnew, double* __restrict__ Qv,
+                                               const double* __restrict__ sc, double* __restrict__ part) {
     if (sc[SC_ALL * A.Fp] != 0.0) return;
     double v[1] = {0.0};
-    FOR_ROWS(A, i, f) {
-        const double qi = row_dot(A, i, P, f);
-        Qv[i * A.Fp + f] = qi;
-        v[0] = fma(P[i * A.Fp + f], qi, v[0]);
+    {
+        FOR_ROWS(A, i, f) {
+            const bool live = f < A.F && sc[SC_DONE * A.Fp + f] == 0.0;
+            const double bt = live ? sc[SC_BETA * A.Fp + f] : 0.0;
+            double qi = 0.0;
+            for (int64_t kk = A.rowptr[i]; kk < A.rowptr[i + 1]; ++kk) {
+                const int64_t o = int64_t(A.col[kk]) * A.Fp + f;
+                qi = fma(A.val[kk], fma(bt, Pold[o], Z[o]), qi);
+            }
+            const int64_t o = i * A.Fp + f;
+            const double pi = fma(bt, Pold[o], Z[o]);
+            Pnew[o] = pi;
+            Qv[o] = qi;
+            if (live) v[0] = fma(pi, qi, v[0]);
+        }
     }
-    field_reduce<1>(A, v, partials, ticket, [&](int ff, double (&t)[1]) {
-        const bool done = sc[SC_DONE * A.Fp + ff] != 0.0;
-        sc[SC_ALPHA * A.Fp + ff] = done ? 0.0 : sc[SC_RHO * A.Fp + ff] / t[0];
-    });
+    const int slot[1] = {PM_PQ};
+    field_partials<1>(A, v, slot, part);
 }
 
 __global__ __launch_bounds__(MB) void k_m_update(MView A, const double* __restrict__ P, const double* __restrict__ Qv,
                                                  double* __restrict__ Y, double* __restrict__ R, double* __restrict__ Z,
-                                                 double* __restrict__ sc, double* __restrict__ partials,
-                                                 unsigned int* ticket) {
+                                                 const double* __restrict__ sc, double* __restrict__ part) {
     if (sc[SC_ALL * A.Fp] != 0.0) return;
     double v[2] = {0.0, 0.0};
     {
@@ -198,27 +226,11 @@ __global__ __launch_bounds__(MB) void k_m_update(MView A, const double* __restri
             v[1] = fma(ri, ri, v[1]);
         }
     }
-    field_reduce<2>(A, v, partials, ticket, [&](int ff, double (&t)[2]) {
-        if (sc[SC_DONE * A.Fp + ff] != 0.0) return;
-        sc[SC_BETA * A.Fp + ff] = t[0] / sc[SC_RHO * A.Fp + ff];
-        sc[SC_RHO * A.Fp + ff] = t[0];
-        sc[SC_RR * A.Fp + ff] = t[1];
-        sc[SC_ITERS * A.Fp + ff] += 1.0;
-        if (t[1] <= sc[SC_TOL2 * A.Fp + ff]) sc[SC_DONE * A.Fp + ff] = 1.0;
-    });
+    const int slot[2] = {PM_RZ, PM_RR};
+    field_partials<2>(A, v, slot, part);
 }
 
-__global__ __launch_bounds__(MB) void k_m_direction(MView A, const double* __restrict__ Z, double* __restrict__ P,
-                                                    const double* __restrict__ sc) {
-    if (sc[SC_ALL * A.Fp] != 0.0) return;
-    FOR_ROWS(A, i, f) {
-        if (f >= A.F || sc[SC_DONE * A.Fp + f] != 0.0) continue;
-        const int64_t o = i * A.Fp + f;
-        P[o] = fma(sc[SC_BETA * A.Fp + f], P[o], Z[o]);
-    }
-}
-
-// X = alpha G + Y (in place into Y), then true residual and m^T x per field
+// X = alpha G + Y (in place into Y)
 __global__ __launch_bounds__(MB) void k_m_solution(MView A, const double* __restrict__ G, double alpha,
                                                    double* __restrict__ Y) {
     FOR_ROWS(A, i, f) {
@@ -228,8 +240,7 @@ __global__ __launch_bounds__(MB) void k_m_solution(MView A, const double* __rest
 }
 
 __global__ __launch_bounds__(MB) void k_m_report(MView A, const double* __restrict__ B, const double* __restrict__ X,
-                                                 double* __restrict__ sc, double* __restrict__ partials,
-                                                 unsigned int* ticket) {
+                                                 double* __restrict__ part) {
     double v[2] = {0.0, 0.0};
     FOR_ROWS(A, i, f) {
         const int64_t o = i * A.Fp + f;
@@ -237,10 +248,8 @@ __global__ __launch_bounds__(MB) void k_m_report(MView A, const double* __restri
         v[0] = fma(ri, ri, v[0]);
         v[1] = fma(A.lumped[i], X[o], v[1]);
     }
-    field_reduce<2>(A, v, partials, ticket, [&](int ff, double (&t)[2]) {
-        sc[SC_TRR * A.Fp + ff] = t[0];
-        sc[SC_INTX * A.Fp + ff] = t[1];
-    });
+    const int slot[2] = {PM_TRR, PM_MX};
+    field_partials<2>(A, v, slot, part);
 }
 
 ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep,
@@ -255,60 +264,57 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
     }
     const int64_t n = T->n;
     const double alpha = T->consumed_cfg.alpha;
-    const int nb = int(std::min<int64_t>(MAX_MBLOCKS, (n * Fp + MB - 1) / MB));
+    const int nb = int(std::max<int64_t>(1, std::min<int64_t>(MAX_MBLOCKS, (n * Fp + MB - 1) / MB)));
     MView A{T->rowptr, T->col, T->val, T->diag, T->lumped, n, F, Fp, shift};
 
     // work arrays (freed on return; the solve is synchronous)
     double *G = nullptr, *B = nullptr, *Y = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Qv = nullptr;
-    double *sc = nullptr, *partials = nullptr;
-    unsigned int* ticket = nullptr;
+    double *sc = nullptr, *part = nullptr;
     ScratchGuard guard;
-    for (double** p : {&G, &B, &Y, &R, &Z, &P, &Qv}) {
+    for (double** p : {&G, &B, &Y, &R, &Z, &Qv}) {
         guard.add((void**)p);
         FT_TRY(dev_alloc_n(p, size_t(n) * Fp));
     }
+    guard.add((void**)&P);
+    FT_TRY(dev_alloc_n(&P, size_t(2) * n * Fp));   // two direction buffers, alternating
     guard.add((void**)&sc);
-    guard.add((void**)&partials);
-    guard.add((void**)&ticket);
+    guard.add((void**)&part);
     FT_TRY(dev_alloc_n(&sc, size_t(SC_COUNT) * Fp));
-    FT_TRY(dev_alloc_n(&partials, size_t(2) * Fp * nb));
-    FT_TRY(dev_alloc_n(&ticket, 4));
+    FT_TRY(dev_alloc_n(&part, size_t(PM_COUNT) * Fp * nb));
     std::vector<double> h(size_t(SC_COUNT) * Fp);
-    FT_TRY_HIP(hipMemsetAsync(ticket, 0, 4 * sizeof(unsigned int), s));
-    FT_TRY_HIP(hipMemsetAsync(sc, 0, sizeof(double) * SC_COUNT * Fp, s));
 
     unsigned long long nonfinite = 0;
     FT_TRY_HIP(hipMemcpyAsync(&nonfinite, T->counters, sizeof(nonfinite), hipMemcpyDeviceToHost, s));
     const unsigned gt = grid_for(n * Fp, MB);
     k_m_transpose_in<<<gt, MB, 0, s>>>(T->g, n, F, Fp, G);
     k_m_transpose_in<<<gt, MB, 0, s>>>(T->bres, n, F, Fp, R);
-    k_m_rhs<<<nb, MB, 0, s>>>(A, G, alpha, R, B, sc, partials, ticket);
-    k_m_init<<<nb, MB, 0, s>>>(A, cfg->rtol * cfg->rtol, Y, R, Z, P, sc, partials, ticket);
-    k_m_all_done<<<1, 64, 0, s>>>(F, Fp, sc);
+    k_m_rhs<<<nb, MB, 0, s>>>(A, G, alpha, R, B, part);
+    k_m_scalars<<<1, 64, 0, s>>>(A, 0, 0, nb, cfg->rtol * cfg->rtol, part, sc);
+    k_m_init<<<nb, MB, 0, s>>>(A, Y, R, Z, P, part);
+    k_m_scalars<<<1, 64, 0, s>>>(A, 1, 0, nb, 0.0, part, sc);
     FT_TRY_HIP(hipGetLastError());
     int launched = 0, chunk = 8;
-    bool all_done = false;
     while (launched < cfg->max_iter) {
         const int k = std::min(chunk, cfg->max_iter - launched);
         for (int it = 0; it < k; ++it) {
-            k_m_spmv<<<nb, MB, 0, s>>>(A, P, Qv, sc, partials, ticket);
-            k_m_update<<<nb, MB, 0, s>>>(A, P, Qv, Y, R, Z, sc, partials, ticket);
-            k_m_all_done<<<1, 64, 0, s>>>(F, Fp, sc);
-            k_m_direction<<<nb, MB, 0, s>>>(A, Z, P, sc);
+            const int kk = launched + it;
+            double* Pold = P + ((kk & 1) ? n * Fp : 0);
+            double* Pnew = P + ((kk & 1) ? 0 : n * Fp);
+            k_m_spmv<<<nb, MB, 0, s>>>(A, Z, Pold, Pnew, Qv, sc, part);
+            k_m_scalars<<<1, 64, 0, s>>>(A, 2, kk, nb, 0.0, part, sc);
+            k_m_update<<<nb, MB, 0, s>>>(A, Pnew, Qv, Y, R, Z, sc, part);
+            k_m_scalars<<<1, 64, 0, s>>>(A, 1, kk + 1, nb, 0.0, part, sc);
         }
         launched += k;
         FT_TRY_HIP(hipGetLastError());
         FT_TRY_HIP(hipMemcpyAsync(h.data(), sc, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
         FT_TRY_HIP(hipStreamSynchronize(s));
-        if (h[SC_ALL * Fp] != 0.0) {
-            all_done = true;
-            break;
-        }
+        if (h[SC_ALL * Fp] != 0.0) break;
         chunk = 4;
     }
-    (void)all_done;
     k_m_solution<<<nb, MB, 0, s>>>(A, G, alpha, Y);
-    k_m_report<<<nb, MB, 0, s>>>(A, B, Y, sc, partials, ticket);
+    k_m_report<<<nb, MB, 0, s>>>(A, B, Y, part);
+    k_m_scalars<<<1, 64, 0, s>>>(A, 3, 0, nb, 0.0, part, sc);
     const unsigned go = grid_for(n * F, MB);
     k_m_transpose_out<<<go, MB, 0, s>>>(Y, n, F, Fp, x);
     if (b_out) k_m_transpose_out<<<go, MB, 0, s>>>(B, n, F, Fp, b_out);

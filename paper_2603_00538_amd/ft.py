@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libft.so")
 
 FT_OK, FT_E_ARG, FT_E_MESH, FT_E_ORDER, FT_E_DEVICE, FT_E_NOCONV, FT_E_NONFINITE, FT_E_OOM, FT_E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
-FT_F64, FT_F32 = 0, 1
+FT_F64, FT_F32, FT_SPLIT_F16, FT_SPLIT_BF16 = 0, 1, 2, 3
 STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -4: "FT_E_DEVICE",
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
@@ -250,7 +250,7 @@ class Target:
     def sample_points(self, cfg: SampleCfg, out=None):
         torch = _torch()
         Q = self.query_count(cfg.samples_per_elem)
-        dt = torch.float32 if cfg.precision == FT_F32 else torch.float64
+        dt = torch.float64 if cfg.precision == FT_F64 else torch.float32
         if out is None:
             out = torch.empty((self.dim, Q), dtype=dt, device=self.coords.device)
         if out.numel() < self.dim * Q:

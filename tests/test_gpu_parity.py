@@ -330,3 +330,29 @@ def test_fused_route_matches_unfused_and_oracle(dim, N):
     assert e.value.status == ft.FT_E_UNSUPPORTED
     T.close()
     S.close()
+
+
+# ---------------------------------------------------------------- split matrix-core form
+@pytest.mark.parametrize("prec", [ft.FT_SPLIT_F16, ft.FT_SPLIT_BF16])
+@pytest.mark.parametrize("dim,F,N", [(3, 20, 16), (3, 64, 128), (2, 9, 40), (2, 33, 256)])
+def test_split_matrix_core_form_within_1e5(prec, dim, F, N):
+    """Many fields at once through the split-product MFMA element sums."""
+    tm, sm = _small_2d() if dim == 2 else _small_3d()
+    modes = fields.fourier_modes(seed=13 + F, n_fields=F, n_modes=4, kmax=2)
+    if dim == 3:
+        sv = fields.fourier_fields_3d(np, sm[0][:, 0], sm[0][:, 1], sm[0][:, 2], modes)
+    else:
+        sv = fields.fourier_fields_3d(np, sm[0][:, 0], sm[0][:, 1], 0.25 + 0 * sm[0][:, 0], modes)
+    log(f"split form prec={prec} dim={dim} F={F} N={N}")
+    g = gpu_transfer(tm, sm, sv, N, 1.0, 40 + F, 1, precision=prec)
+    o = oracle_transfer(tm, sm, sv, N, 1.0, 40 + F, 1)
+    assert g["status"] == ft.FT_OK
+    assert g["x"].shape == (F, tm[0].shape[0])
+    ex = max(rel_l2(g["x"][f], o["x"][f]) for f in range(F))
+    eb = max(rel_l2(g["b"][f], o["b"][f]) for f in range(F))
+    log(f"worst field: rel l2 x {ex:.2e}, b {eb:.2e}")
+    assert ex < 1e-5 and eb < 1e-5
+    for f in range(F):
+        rep, orep = g["reports"][f], o["report"][f]
+        assert abs(rep["sum_b"] - orep["sum_b"]) <= 1e-6 * max(abs(orep["sum_b"]), 1e-300)
+        assert rep["cons_defect"] < 1e-6
