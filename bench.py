@@ -16,6 +16,7 @@ its algorithmic bytes divided by its average event-measured duration.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "target elements/s and point queries/s per transfer; % HBM roofline vs FP64"
+PRECISIONS = {"f64": "FT_F64", "f32": "FT_F32", "split-f16": "FT_SPLIT_F16", "split-bf16": "FT_SPLIT_BF16"}
+DTYPES = {"f64": "f64", "f32": "f32", "split-f16": "f32+f16x2", "split-bf16": "f32+bf16x2"}
+
+# device sources each timed kernel is compiled from: a counter record taken on
+# other sources no longer describes the kernel and is not reported
+KERNEL_SOURCES = {
+    "k_emit": ["mc.hip", "sampling.h", "common.h"],
+    "k_src_eval": ["source.hip", "locate.h", "common.h"],
+    "k_consume": ["mc.hip", "sampling.h", "common.h"],
+    "k_consume_mfma": ["mc_mfma.hip", "sampling.h", "common.h"],
+    "k_fused_p1": ["fused.hip", "locate.h", "sampling.h", "common.h"],
+}
+TRAFFIC_RECORDS = os.path.join(ROOT, "profiles", "hbm_traffic.md")
 
 
 def log(msg):
@@ -85,6 +99,72 @@ def cpu_baseline(w, tmesh, smesh, svals, sample_elems):
     }
 
 
+def sources_digest(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2603_00538_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    record of this kernel and workload, or None when there is none or it was
+    taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_RECORDS):
+        return None
+    digest = sources_digest(kernel)
+    with open(TRAFFIC_RECORDS) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line.startswith("record "):
+                continue
+            r = json.loads(line[len("record "):])
+            if (r["kernel"], r["workload"], r["precision"], r["sources"]) == (kernel, workload, precision, digest):
+                return r["fetch_bytes"] + r["write_bytes"]
+    return None
+
+
+def sequential_f64(T, w, tmesh, smesh, svals):
+    """The comparator of the many-field form: F one-field FP64 transfers, one
+    after another (each field's source set up untimed; emit, eval, consume and
+    project timed with events)."""
+    import numpy as np
+    import torch
+
+    from paper_2603_00538_amd import ft
+
+    tc, tconn = tmesh
+    sc, sconn = smesh
+    n, E = tc.shape[0], tconn.shape[0]
+    N, F, dim = w.samples_per_elem, svals.shape[0], tc.shape[1]
+    Q = T.query_count(N)
+    pts = torch.empty((dim, Q), dtype=torch.float64, device="cuda")
+    vals = torch.empty((1, Q), dtype=torch.float64, device="cuda")
+    x = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    total = 0.0
+    iters = []
+    for f in range(F):
+        S1 = ft.Source(sc, sconn, np.ascontiguousarray(svals[f:f + 1]), bins=w.bins if any(w.bins) else None)
+        cfg = ft.SampleCfg(N, 1, w.alpha, w.philox_seed, 0, ft.FT_F64)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        T.sample_points(cfg, out=pts)
+        S1.eval_query_list(pts, n, out=vals)
+        T.consume(cfg, vals)
+        res = T.project(1, rtol=w.rtol, max_iter=1000, x=x)
+        e1.record()
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1)
+        iters.append(res.reports[0]["iters"])
+        S1.close()
+        if f % 16 == 15:
+            log(f"sequential FP64 transfers: {f + 1}/{F}")
+    return {"transfers": F, "ms_total": total, "value": E / (total * 1e-3), "unit": "target elements/s (all fields)",
+            "cg_iters_max": int(max(iters))}
+
+
 def calibrate_copy(nbytes):
     """A plain device copy of known size, for scaling rocprof FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -103,14 +183,16 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tri2d_1m")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--precision", default="f64", choices=list(PRECISIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-elems", type=int, default=1500)
+    ap.add_argument("--cpu-sample-elems", type=int, default=20000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     ap.add_argument("--route", default="blackbox", choices=["blackbox", "fused"],
                     help="blackbox: sample -> source eval -> consume through the point-query list; "
                          "fused: ft_transfer_p1 (built-in source, no query list)")
     ap.add_argument("--no-fused", action="store_true", help="skip the extra fused-route measurement")
+    ap.add_argument("--sequential", action="store_true",
+                    help="multi-field workloads: also time F sequential one-field FP64 transfers")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -138,9 +220,9 @@ def main():
     sc, sconn = smesh
     dim, E, n = w.dim, tconn.shape[0], tc.shape[0]
     N, F = w.samples_per_elem, w.n_fields
-    prec = ft.FT_F32 if args.precision == "f32" else ft.FT_F64
-    p = 4 if prec == ft.FT_F32 else 8
-    dt_ = torch.float32 if prec == ft.FT_F32 else torch.float64
+    prec = getattr(ft, PRECISIONS[args.precision])
+    p = 8 if prec == ft.FT_F64 else 4
+    dt_ = torch.float64 if prec == ft.FT_F64 else torch.float32
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
@@ -222,7 +304,9 @@ def main():
     dom = max(cand, key=lambda k: phase_ms[k])
     abytes = algorithmic_bytes(dom, dim, E, n, N, F, p, src_info)
     achieved = abytes / (phase_ms[dom] * 1e-3) / 1e9
-    kernel_names = {"emit": "k_emit", "eval": "k_src_eval", "consume": "k_consume", "fused": "k_fused_p1"}
+    split = prec in (ft.FT_SPLIT_F16, ft.FT_SPLIT_BF16) and N <= 256 and F <= 64
+    kernel_names = {"emit": "k_emit", "eval": "k_src_eval", "consume": "k_consume_mfma" if split else "k_consume",
+                    "fused": "k_fused_p1"}
     out = {
         "metric": METRIC,
         "value": E / (ms_step * 1e-3),
@@ -234,7 +318,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == ft.FT_F64 else "f32",
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "route": args.route, "dim": dim, "target_elements": E, "target_nodes": n,
                    "source_elements": int(sconn.shape[0]), "samples_per_elem": N, "n_fields": F,
@@ -248,17 +332,21 @@ def main():
         "rel_resid": reports[0]["rel_resid"],
         "status": ft.STATUS_NAMES[status],
         "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(kernel_names[dom], w.name, args.precision),
                      "algorithmic_bytes": abytes, "avg_ms": phase_ms[dom]},
     }
     if extra_route is not None:
         out["fused_route"] = extra_route
     out["config"]["bins"] = [int(si.bins[c]) for c in range(dim)]
     out["config"]["bin_registrations"] = int(si.n_registrations)
-    T.close()
     S.close()
     del pts, vals
     torch.cuda.empty_cache()
+    if args.sequential and F > 1:
+        out["sequential_f64"] = sequential_f64(T, w, tmesh, smesh, svals)
+        out["sequential_f64"]["speedup_of_batched"] = out["sequential_f64"]["ms_total"] / ms_step
+    T.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample)")
         cb = cpu_baseline(w, tmesh, smesh, svals, args.cpu_sample_elems)

@@ -220,6 +220,20 @@ ft_status ft_source_create_p1(int32_t dim, int64_t n_nodes, const double* coords
 ft_status ft_source_eval(ft_source* s, int64_t n_points, const void* points, int64_t ld, int32_t precision,
                          void* values, int64_t ld_out, int32_t* elem_ids, hipStream_t stream);
 
+/*
+ * ft_source_eval_queries - ft_source_eval over a query list from
+ * ft_sample_points (sec. 4.1 steps 1 and 4): the first n_nodes points (the
+ * target nodes) and the remaining n_points - n_nodes (the element-major
+ * samples) are split into wavefronts separately, so that with N a multiple
+ * of 256 every wavefront's points lie in one target element and share their
+ * candidate source elements.  One launch.  Results are identical to
+ * ft_source_eval on the same points for any n_nodes in [0, n_points].
+ * Arguments as for ft_source_eval.  Errors: FT_E_ARG.  Asynchronous on `stream`.
+ */
+ft_status ft_source_eval_queries(ft_source* s, int64_t n_nodes, int64_t n_points, const void* points, int64_t ld,
+                                 int32_t precision, void* values, int64_t ld_out, int32_t* elem_ids,
+                                 hipStream_t stream);
+
 /* Sizes of a source after setup. */
 typedef struct {
     int32_t dim;

@@ -14,7 +14,7 @@ ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* val
 ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep, hipStream_t s);
 ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, const double* values,
                        const int32_t* bins, hipStream_t s);
-ft_status source_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
+ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
                       int32_t* ids, hipStream_t s);
 ft_status source_release(ft_source* S);
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s);
@@ -255,7 +255,23 @@ ft_status ft_source_eval(ft_source* s, int64_t n_points, const void* points, int
     FT_ARG_CHECK(ld >= n_points && ld_out >= n_points, "leading dimensions must be >= n_points");
     FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
     FT_ARG_CHECK(n_points < (int64_t(1) << 39), "n_points too large");
-    return source_eval(s, n_points, points, ld, precision, values, ld_out, elem_ids, stream);
+    return source_eval(s, 0, n_points, points, ld, precision, values, ld_out, elem_ids, stream);
+    FT_GUARD_END
+}
+
+ft_status ft_source_eval_queries(ft_source* s, int64_t n_nodes, int64_t n_points, const void* points, int64_t ld,
+                                 int32_t precision, void* values, int64_t ld_out, int32_t* elem_ids,
+                                 hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(s, "source is null");
+    FT_ARG_CHECK(n_points >= 0, "n_points must be >= 0");
+    FT_ARG_CHECK(n_nodes >= 0 && n_nodes <= n_points, "n_nodes must lie in [0, n_points]");
+    FT_ARG_CHECK(n_points == 0 || (points && values), "points and values must be device pointers");
+    FT_ARG_CHECK(ld >= n_points && ld_out >= n_points, "leading dimensions must be >= n_points");
+    FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
+    FT_ARG_CHECK(n_points < (int64_t(1) << 39), "n_points too large");
+    return source_eval(s, n_nodes, n_points, points, ld, precision, values, ld_out, elem_ids, stream);
     FT_GUARD_END
 }
 

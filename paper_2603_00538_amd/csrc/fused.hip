@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_fused_p1(SrcView S, const double* __res
                                                   const double* __restrict__ g, double* __restrict__ beta,
                                                   unsigned long long* __restrict__ nonfinite,
                                                   unsigned long long* __restrict__ n_ood) {
-    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t gid = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
     const uint32_t t = gid / G;
     const int lane = int(gid & (G - 1));
     const bool valid = t < E;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_fused_p1(SrcView S, const double* __res
 }
 
 SrcView source_view(const ft_source* S);
-ft_status source_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
+ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
                       int32_t* ids, hipStream_t s);
 ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s);
 void zero_counter(unsigned long long* p, hipStream_t s);
@@ -146,7 +146,7 @@ static void fused_g(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStr
 
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
     // step 1: the control, f^s at the target nodes, straight into T->g
-    FT_TRY(source_eval(S, T->n, T->coords, T->n, FT_F64, T->g, T->n, nullptr, s));
+    FT_TRY(source_eval(S, 0, T->n, T->coords, T->n, FT_F64, T->g, T->n, nullptr, s));
     zero_counter(T->counters, s);
     if (T->dim == 2) fused_g<2>(T, S, cfg, s);
     else fused_g<3>(T, S, cfg, s);

@@ -129,15 +129,45 @@ __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int
 template <int D>
 __device__ __forceinline__ double affine_min_mu(const double* __restrict__ r, const double (&p)[D]) {
     constexpr int AF = RecAffine<D>::value;
-    double mn = INFINITY;
+    double mn = 0.0;
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
         double s = r[AF + k];
 #pragma unroll
         for (int c = 0; c < D; ++c) s = fma(r[AF + D + 1 + k * D + c], p[c], s);
-        mn = fmin(mn, s);
+        mn = k == 0 ? s : fmin(mn, s);
     }
     return mn;
+}
+
+// Wave-uniform value copied into a vector register once, so that the
+// per-point products below take it as an operand instead of copying it for
+// every point (a VOP3 instruction reads at most one scalar register here).
+__device__ __forceinline__ double to_vgpr(double u) {
+    double v;
+    asm("v_mov_b64 %0, %1" : "=v"(v) : "s"(u));
+    return v;
+}
+
+// One candidate record against the P points of this lane: the affine form's
+// offsets are held in vector registers, the gradients stay scalar.
+template <int D, int P>
+__device__ __forceinline__ void affine_min_mu_multi(const double* __restrict__ r, const double (&p)[P][D],
+                                                    double (&mn)[P]) {
+    constexpr int AF = RecAffine<D>::value;
+    double a[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) a[k] = to_vgpr(r[AF + k]);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+#pragma unroll
+        for (int k = 0; k <= D; ++k) {
+            double s = a[k];
+#pragma unroll
+            for (int c = 0; c < D; ++c) s = fma(r[AF + D + 1 + k * D + c], p[q][c], s);
+            mn[q] = k == 0 ? s : fmin(mn[q], s);
+        }
+    }
 }
 
 // Conservative test whether element r can contain a point of the box
@@ -208,9 +238,11 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         b1[c] = uniform_int(bin_of(whi[c], c, S.g));
         span *= b1[c] - b0[c] + 1;
     }
+    // inactive points start above the acceptance threshold so that the
+    // wave's exit test needs no activity mask
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        best[q] = -DBL_MAX;
+        best[q] = active[q] ? -DBL_MAX : DBL_MAX;
         bid[q] = INT_MAX;
     }
 
@@ -268,15 +300,15 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                             mask &= mask - 1;
                             const int e = read_lane(cid, l);
                             const double* r = S.rec + int64_t(e) * RS;
+                            double mn[P];
+                            affine_min_mu_multi<D, P>(r, p, mn);
                             bool done = true;
 #pragma unroll
                             for (int q = 0; q < P; ++q) {
-                                const double mn = affine_min_mu<D>(r, p[q]);
-                                if (mn > best[q]) {
-                                    best[q] = mn;
-                                    bid[q] = e;
-                                }
-                                done &= !active[q] || best[q] > kFastTau;
+                                // first strictly larger value wins (branch-free)
+                                bid[q] = mn[q] > best[q] ? e : bid[q];
+                                best[q] = fmax(best[q], mn[q]);
+                                done &= best[q] > kFastTau;
                             }
                             if (__all(done)) {
                                 finished = true;

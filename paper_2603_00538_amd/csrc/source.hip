@@ -228,18 +228,23 @@ __global__ void k_sort_bins(const int64_t* __restrict__ ptr, int64_t nseg, int32
 
 // Each wave owns 64*P consecutive points; lane l holds points base + q*64 + l.
 template <int D, int P, bool IN_F32, bool OUT_F32>
-__global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t npts, const void* __restrict__ pts_, int64_t ld,
-                                                  void* __restrict__ out_, int64_t ld_out, int32_t* __restrict__ ids,
-                                                  unsigned long long* __restrict__ n_ood) {
+__global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t head, int64_t npts, const void* __restrict__ pts_,
+                                                  int64_t ld, void* __restrict__ out_, int64_t ld_out,
+                                                  int32_t* __restrict__ ids, unsigned long long* __restrict__ n_ood) {
+    // two segments, [0, head) and [head, npts), each starting on a wavefront boundary
+    constexpr int64_t WP = 64 * P;
     const int lane = threadIdx.x & 63;
-    const int64_t base = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * (64 * P);
-    if (base >= npts) return;   // wave-uniform
+    const int64_t wave = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 4 + (threadIdx.x >> 6);
+    const int64_t wh = (head + WP - 1) / WP;
+    const int64_t base = wave < wh ? wave * WP : head + (wave - wh) * WP;
+    const int64_t lim = wave < wh ? head : npts;
+    if (base >= lim) return;   // wave-uniform
     double p[P][D];
     bool active[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int64_t i = base + q * 64 + lane;
-        active[q] = i < npts;
+        active[q] = i < lim;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             if (IN_F32)
@@ -393,24 +398,26 @@ SrcView source_view(const ft_source* S) {
 }
 
 template <int D>
-static ft_status launch_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
-                             int64_t ld_out, int32_t* ids, hipStream_t s) {
+static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec,
+                             void* out, int64_t ld_out, int32_t* ids, hipStream_t s) {
     constexpr int P = 4;   // points per lane: one wave covers 256 consecutive points
+    constexpr int64_t WP = 64 * P;
     const SrcView v = source_view(S);
-    const unsigned grid = grid_for(npts, 256 * P);
+    const int64_t waves = (head + WP - 1) / WP + (npts - head + WP - 1) / WP;
+    const unsigned grid = unsigned((waves + 3) / 4);
     if (prec == FT_F64)
-        k_src_eval<D, P, false, false><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);
+        k_src_eval<D, P, false, false><<<grid, 256, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
     else
-        k_src_eval<D, P, true, true><<<grid, 256, 0, s>>>(v, npts, pts, ld, out, ld_out, ids, S->counters);
+        k_src_eval<D, P, true, true><<<grid, 256, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
 }
 
-ft_status source_eval(ft_source* S, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
-                      int32_t* ids, hipStream_t s) {
+ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
+                      int64_t ld_out, int32_t* ids, hipStream_t s) {
     if (npts == 0) return FT_OK;
-    return S->dim == 2 ? launch_eval<2>(S, npts, pts, ld, prec, out, ld_out, ids, s)
-                       : launch_eval<3>(S, npts, pts, ld, prec, out, ld_out, ids, s);
+    return S->dim == 2 ? launch_eval<2>(S, head, npts, pts, ld, prec, out, ld_out, ids, s)
+                       : launch_eval<3>(S, head, npts, pts, ld, prec, out, ld_out, ids, s);
 }
 
 ft_status source_release(ft_source* S) {

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
-            "ft_consume_queries", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval", "ft_source_stats",
+            "ft_consume_queries", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval",
+            "ft_source_eval_queries", "ft_source_stats",
             "ft_source_destroy", "ft_source_get_info", "ft_last_error"]
 
 
@@ -86,6 +87,7 @@ def load(path: str = LIB_PATH):
         "ft_project": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P]),
         "ft_source_create_p1": (I32, [I32, I64, P, I64, P, I32, P, P, P, ctypes.POINTER(P)]),
         "ft_source_eval": (I32, [P, I64, P, I64, I32, P, I64, P, P]),
+        "ft_source_eval_queries": (I32, [P, I64, I64, P, I64, I32, P, I64, P, P]),
         "ft_source_stats": (I32, [P, ctypes.POINTER(I64), P]),
         "ft_source_destroy": (I32, [P]),
         "ft_source_get_info": (I32, [P, ctypes.POINTER(SourceInfo)]),
@@ -158,6 +160,11 @@ def ft_source_create_p1(dim, n_nodes, coords_ptr, n_elems, conn_ptr, n_fields, v
 def ft_source_eval(h, n_points, points_ptr, ld, precision, values_ptr, ld_out, ids_ptr, stream):
     return _check(load().ft_source_eval(h, n_points, points_ptr, ld, precision, values_ptr, ld_out, ids_ptr, stream),
                   "ft_source_eval")
+
+
+def ft_source_eval_queries(h, n_nodes, n_points, points_ptr, ld, precision, values_ptr, ld_out, ids_ptr, stream):
+    return _check(load().ft_source_eval_queries(h, n_nodes, n_points, points_ptr, ld, precision, values_ptr, ld_out,
+                                                ids_ptr, stream), "ft_source_eval_queries")
 
 
 def ft_source_stats(h, stream):
@@ -338,9 +345,25 @@ class Source:
         return out
 
     def eval_query_list(self, points, n_nodes, out=None, ids=None):
-        """Evaluate a transfer's query list as its two blocks (target nodes, then samples)."""
-        out = self.eval(points, out=out, ids=ids, start=0, count=n_nodes)
-        return self.eval(points, out=out, ids=ids, start=n_nodes)
+        """Evaluate a transfer's whole (d, Q) query list in one launch, its node block
+        and its sample block in separate wavefronts (ft_source_eval_queries)."""
+        torch = _torch()
+        if points.ndim != 2 or points.shape[0] != self.dim:
+            raise ValueError(f"points must have shape ({self.dim}, n)")
+        ld = int(points.shape[1])
+        if not 0 <= n_nodes <= ld:
+            raise ValueError("n_nodes out of range")
+        prec = FT_F32 if points.dtype == torch.float32 else FT_F64
+        if out is None:
+            out = torch.empty((self.n_fields, ld), dtype=points.dtype, device=points.device)
+        if out.ndim != 2 or out.shape[0] != self.n_fields or out.shape[1] < ld or out.dtype != points.dtype:
+            raise ValueError("out must have shape (n_fields, >= Q) and the dtype of points")
+        if ids is not None and (ids.dtype != torch.int32 or ids.numel() < ld):
+            raise ValueError("ids must be int32 with at least Q entries")
+        ft_source_eval_queries(self.handle, int(n_nodes), ld, _device_ptr(points, "points", (torch.float32, torch.float64)),
+                               ld, prec, _device_ptr(out, "out"), int(out.shape[1]),
+                               _device_ptr(ids, "ids") if ids is not None else None, current_stream())
+        return out
 
     @property
     def info(self):
