@@ -252,6 +252,54 @@ ft_status ft_source_stats(ft_source* s, int64_t* n_out_of_domain /* host */, hip
 
 ft_status ft_source_destroy(ft_source* s);
 
+/*
+ * Batches: many independent transfers from built-in P1 sources (one field
+ * each, FT_F64), of mixed dimension, size and samples per element, run as
+ * one sequence of launches.  Target elements of all transfers are the work
+ * units of one persistent kernel (sec. 4.1: the element sums of step 5 are
+ * independent), the node sums and the mass solves of all transfers share
+ * their launches.  Each transfer gives exactly the samples and element sums
+ * of ft_transfer_p1 on the same target, source and cfg (samples_per_elem > 8),
+ * and a solution of the same M x = b to the same tolerance.
+ */
+typedef struct ft_batch ft_batch;
+
+enum { FT_BATCH_GRAPH = 1 };   /* capture a run as a HIP graph; later runs replay it */
+
+/*
+ * ft_batch_create - set up a batch of `count` transfers.
+ *   targets, sources   host arrays [count] of handles; not owned: they must
+ *                      outlive the batch, and no other call may use them while
+ *                      ft_batch_run runs.  Targets must be distinct.
+ *   cfgs               host [count]: per-transfer sample configuration
+ *                      (n_fields 1 = the source's field count, FT_F64)
+ *   flags              0 or FT_BATCH_GRAPH
+ * Builds the work lists (node, element and row tiles, elements ordered by
+ * decreasing cost) and the batch's solver vectors on the device.
+ * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Synchronizes `stream`.
+ */
+ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* const* sources,
+                          const ft_sample_cfg* cfgs, int32_t flags, hipStream_t stream, ft_batch** out);
+
+/*
+ * ft_batch_run - sec. 4.1 steps 1-7 for every transfer of the batch.
+ *   x        host array [count] of device pointers: x[k] binary64 [n_nodes of target k]
+ *   b        host array [count] of device pointers (load vectors) or null entries, or null
+ *   reports  host [count], one report per transfer
+ *   status   host [count] or null: per-transfer status
+ * The solve launches exactly cfg->max_iter Jacobi-PCG iterations (a converged
+ * system's tiles return at once), so a run has no host synchronization until
+ * its end; with FT_BATCH_GRAPH the first run with a given (rtol, max_iter) is
+ * captured and replayed afterwards.  Afterwards every target is in the state
+ * ft_transfer_p1 leaves (ft_project may re-solve it).
+ * Returns FT_OK, or the worst per-transfer status (FT_E_NONFINITE before
+ * FT_E_NOCONV).  Synchronizes `stream`.
+ */
+ft_status ft_batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec,
+                       ft_report* reports, int32_t* status, hipStream_t stream);
+
+ft_status ft_batch_destroy(ft_batch* b);
+
 /* Message describing the last failure on this thread ("" if none). */
 const char* ft_last_error(void);
 

@@ -18,6 +18,14 @@ ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts,
                       int32_t* ids, hipStream_t s);
 ft_status source_release(ft_source* S);
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s);
+ft_status batch_setup(ft_batch* b, hipStream_t s);
+ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec, ft_report* rep,
+                    int32_t* status, hipStream_t s);
+void batch_release(ft_batch* b);
+ft_batch* batch_new(int count, ft_target* const* targets, ft_source* const* sources, const ft_sample_cfg* cfgs,
+                    bool graph);
+void batch_delete(ft_batch* b);
+void batch_mark_consumed(ft_batch* b);
 
 static void target_release(ft_target* T) {
     void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
@@ -27,7 +35,7 @@ static void target_release(ft_target* T) {
     if (T->h_scal) (void)hipHostFree(T->h_scal);
 }
 
-static ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
+ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
     FT_ARG_CHECK(cfg, "cfg is null");
     FT_ARG_CHECK(cfg->samples_per_elem >= 1, "samples_per_elem must be >= 1 (got %d)", cfg->samples_per_elem);
     FT_ARG_CHECK(cfg->n_fields >= 1, "n_fields must be >= 1 (got %d)", cfg->n_fields);
@@ -42,7 +50,7 @@ static ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) 
     return FT_OK;
 }
 
-static ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream) {
+ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream) {
     if (F <= T->F_cap) return FT_OK;
     // buffers may still be read by queued work of an earlier transfer
     FT_TRY_HIP(hipStreamSynchronize(stream));
@@ -212,6 +220,62 @@ ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b
     }
     return project(t, cfg, x, b_out, rep, stream);
     FT_GUARD_END
+}
+
+ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* const* sources,
+                          const ft_sample_cfg* cfgs, int32_t flags, hipStream_t stream, ft_batch** out) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(out, "out is null");
+    *out = nullptr;
+    FT_ARG_CHECK(count >= 1 && count <= (1 << 20), "count out of range (%d)", count);
+    FT_ARG_CHECK(targets && sources && cfgs, "targets, sources and cfgs must be host arrays");
+    FT_ARG_CHECK((flags & ~FT_BATCH_GRAPH) == 0, "unknown flags 0x%x", flags);
+    for (int k = 0; k < count; ++k) {
+        const ft_target* t = targets[k];
+        const ft_source* s = sources[k];
+        FT_ARG_CHECK(t && s, "transfer %d: null target or source", k);
+        FT_TRY(check_sample_cfg(t, &cfgs[k]));
+        FT_ARG_CHECK(s->dim == t->dim, "transfer %d: source dimension %d differs from target dimension %d", k,
+                     s->dim, t->dim);
+        if (cfgs[k].precision != FT_F64 || cfgs[k].n_fields != 1 || s->F != 1) {
+            set_error("transfer %d: batches run FT_F64 transfers of one field from one-field sources", k);
+            return FT_E_UNSUPPORTED;
+        }
+        for (int j = 0; j < k; ++j)
+            FT_ARG_CHECK(targets[j] != t, "transfers %d and %d share a target (its work buffers)", j, k);
+    }
+    ft_batch* b = batch_new(count, targets, sources, cfgs, (flags & FT_BATCH_GRAPH) != 0);
+    const ft_status st = batch_setup(b, stream);
+    if (st != FT_OK) {
+        (void)hipStreamSynchronize(stream);
+        batch_release(b);
+        batch_delete(b);
+        return st;
+    }
+    *out = b;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec,
+                       ft_report* reports, int32_t* status, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(b && cfg && x && reports, "null argument");
+    FT_ARG_CHECK(cfg->rtol >= 0.0 && std::isfinite(cfg->rtol), "rtol must be finite and >= 0");
+    FT_ARG_CHECK(cfg->max_iter >= 0 && cfg->max_iter <= 100000, "max_iter must lie in [0, 100000]");
+    const ft_status st = batch_run(b, cfg, x, bvec, reports, status, stream);
+    if (st == FT_OK || st == FT_E_NOCONV || st == FT_E_NONFINITE) batch_mark_consumed(b);
+    return st;
+    FT_GUARD_END
+}
+
+ft_status ft_batch_destroy(ft_batch* b) {
+    if (!b) return FT_OK;
+    batch_release(b);
+    batch_delete(b);
+    return FT_OK;
 }
 
 ft_status ft_source_create_p1(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems,

@@ -1,0 +1,608 @@
+// Many transfers at once: target/source pairs of mixed dimension and size,
+// each with its own samples per element, run as one sequence of launches
+// (sec. 4.1 steps 1-7 for every pair; the pairs are independent work units,
+// sec. 4.1 last paragraph).  Built-in P1 sources, one field per transfer.
+//
+// Work lists built once at creation:
+//   node tiles     (transfer, 256 target nodes)      step 1, the control g
+//   element tiles  (transfer, 64/G target elements)  steps 3-5, fused
+//   row tiles      (transfer, 256 rows)              steps 2, 6, 7 and the report
+// The node and element stages are persistent kernels: a grid sized to the
+// device walks its list with a fixed stride; element tiles are ordered by
+// decreasing cost (largest N and 3D first), so the long tiles start first and
+// the short ones fill the tail.  Each element tile is one wavefront; its
+// (dimension, lanes per element G, samples per lane P) variant is chosen per
+// transfer exactly as the single-transfer route chooses it.
+//
+// The solve is a batched Jacobi-PCG: all systems share the launches, every
+// system keeps its own scalars, and a converged system's tiles return at once.
+// Reductions have no atomics: each row tile writes its partial sums, and one
+// wavefront per system adds its tiles' partials in tile order.  The number of
+// iterations launched is fixed (max_iter), so the whole run contains no host
+// synchronization and no memset and can be captured as one graph, replayed
+// on every later call.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "fused.h"
+
+struct ft_batch;
+
+namespace ft {
+
+ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg);
+ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream);
+SrcView source_view(const ft_source* S);
+
+constexpr int BT = 256;   // threads per block; rows per row tile
+
+struct BatchXfer {
+    SrcView src;
+    const double* coords;
+    const int32_t* conn;
+    const double* vol;
+    const int64_t* inc_ptr;
+    const int32_t* inc;
+    const int64_t* rowptr;
+    const int32_t* col;
+    const double* val;
+    const double* diag;
+    const double* lumped;
+    double* g;
+    double* beta;
+    double* bres;
+    unsigned long long* src_ood;   // the source's out-of-domain counter
+    int64_t n, E;
+    int64_t row0;                  // first row in the concatenated solver vectors
+    int32_t tile0, ntiles;         // this system's row tiles
+    int32_t dim;
+    uint32_t N;
+    double alpha;
+    SampleKey key;
+};
+
+struct Tile {
+    int32_t k;         // transfer
+    int32_t variant;   // element tiles: (dimension, G, P); node tiles: dimension
+    int64_t start;     // first element / node / row
+};
+
+// partial slots per row tile, scalar slots per system
+enum { BP_BB = 0, BP_SB, BP_RZ, BP_RR, BP_PQ, BP_TRR, BP_MX, BP_COUNT };
+enum { BS_RHO = 0, BS_ALPHA, BS_BETA, BS_TOL2, BS_DONE, BS_ITERS, BS_BB, BS_SUMB, BS_INTX, BS_TRR, BS_COUNT };
+
+// ---------------------------------------------------------------- variants
+// G lanes per element and P samples per lane per round, as the single-transfer
+// fused route picks them (N <= 8 uses G = 16 here).
+constexpr int kVariants = 5;
+static int variant_of(int N) {
+    if (N >= 256) return 0;   // G 64, P 4
+    if (N >= 128) return 1;   // G 64, P 2
+    if (N >= 64) return 2;    // G 64, P 1
+    if (N > 16) return 3;     // G 32
+    return 4;                 // G 16
+}
+static int lanes_of(int v) { return v <= 2 ? 64 : (v == 3 ? 32 : 16); }
+
+template <int D, int G, int P>
+__device__ __forceinline__ void batch_elements(const BatchXfer& x, int64_t start, int lane, unsigned& nf,
+                                               unsigned& nood) {
+    const uint32_t t = uint32_t(start) + uint32_t(lane / G);
+    fused_elements<D, G, P, 1>(x.src, x.coords, x.n, x.conn, x.vol, uint32_t(x.E), x.N, x.alpha, x.key, x.g,
+                               x.beta, t, lane % G, nf, nood);
+}
+
+__global__ __launch_bounds__(256) void k_batch_fused(const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles,
+                                                     int64_t n_tiles, unsigned long long* __restrict__ nonfinite) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = int64_t(gridDim.x) * 4;
+    for (int64_t w = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 4 + (threadIdx.x >> 6); w < n_tiles; w += stride) {
+        const Tile tl = tiles[w];
+        const BatchXfer& x = X[tl.k];
+        unsigned nf = 0, nood = 0;
+        switch (tl.variant) {
+            case 0: batch_elements<2, 64, 4>(x, tl.start, lane, nf, nood); break;
+            case 1: batch_elements<2, 64, 2>(x, tl.start, lane, nf, nood); break;
+            case 2: batch_elements<2, 64, 1>(x, tl.start, lane, nf, nood); break;
+            case 3: batch_elements<2, 32, 1>(x, tl.start, lane, nf, nood); break;
+            case 4: batch_elements<2, 16, 1>(x, tl.start, lane, nf, nood); break;
+            case kVariants + 0: batch_elements<3, 64, 4>(x, tl.start, lane, nf, nood); break;
+            case kVariants + 1: batch_elements<3, 64, 2>(x, tl.start, lane, nf, nood); break;
+            case kVariants + 2: batch_elements<3, 64, 1>(x, tl.start, lane, nf, nood); break;
+            case kVariants + 3: batch_elements<3, 32, 1>(x, tl.start, lane, nf, nood); break;
+            default: batch_elements<3, 16, 1>(x, tl.start, lane, nf, nood); break;
+        }
+        if (nf) atomicAdd(nonfinite + tl.k, (unsigned long long)nf);
+        if (nood) atomicAdd(x.src_ood, (unsigned long long)nood);
+    }
+}
+
+// step 1: g = f^s at the target nodes, 256 nodes per wavefront
+__global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles,
+                                                     int64_t n_tiles) {
+    const int64_t stride = int64_t(gridDim.x) * 4;
+    for (int64_t w = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 4 + (threadIdx.x >> 6); w < n_tiles; w += stride) {
+        const Tile tl = tiles[w];
+        const BatchXfer& x = X[tl.k];
+        unsigned nood;
+        if (tl.variant == 2)
+            nood = eval_wave<2, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr);
+        else
+            nood = eval_wave<3, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr);
+        if (nood) atomicAdd(x.src_ood, (unsigned long long)nood);
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------- row-tile kernels
+__device__ __forceinline__ double tile_total(double v) {
+    __shared__ double sm[BT / 64];
+    v = wave_sum_xor(v, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = sm[0];
+    for (int k = 1; k < BT / 64; ++k) s += sm[k];
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ void tile_partial(double* __restrict__ part, int slot, double v) {
+    const double t = tile_total(v);
+    if (threadIdx.x == 0) part[int64_t(blockIdx.x) * BP_COUNT + slot] = t;
+}
+
+__device__ __forceinline__ double row_dot(const BatchXfer& x, int64_t i, const double* __restrict__ v) {
+    double s = 0.0;
+    for (int64_t k = x.rowptr[i]; k < x.rowptr[i + 1]; ++k) s = fma(x.val[k], v[x.col[k]], s);
+    return s;
+}
+
+// step 6: b_res = sum over the incidence list of beta (ascending (t, k))
+__global__ __launch_bounds__(BT) void k_batch_assemble(const BatchXfer* __restrict__ X, const Tile* __restrict__ rt) {
+    const Tile tl = rt[blockIdx.x];
+    const BatchXfer& x = X[tl.k];
+    const int64_t v = tl.start + threadIdx.x;
+    if (v >= x.n) return;
+    double s = 0.0;
+    for (int64_t i = x.inc_ptr[v]; i < x.inc_ptr[v + 1]; ++i) s += x.beta[x.inc[i]];
+    x.bres[v] = s;
+}
+
+// step 2 and the right-hand side: b = alpha M g + b_res; partials of ||b||^2, sum b
+__global__ __launch_bounds__(BT) void k_batch_rhs(const BatchXfer* __restrict__ X, const Tile* __restrict__ rt,
+                                                  double* __restrict__ B, double* __restrict__ part) {
+    const Tile tl = rt[blockIdx.x];
+    const BatchXfer& x = X[tl.k];
+    const int64_t i = tl.start + threadIdx.x;
+    double bb = 0.0, sb = 0.0;
+    if (i < x.n) {
+        const double bi = x.alpha * row_dot(x, i, x.g) + x.bres[i];
+        B[x.row0 + i] = bi;
+        bb = bi * bi;
+        sb = bi;
+    }
+    tile_partial(part, BP_BB, bb);
+    tile_partial(part, BP_SB, sb);
+}
+
+// y = 0, r = b_res, z = D^-1 r, p_old = 0; partials of r.z and r.r
+__global__ __launch_bounds__(BT) void k_batch_cg_init(const BatchXfer* __restrict__ X, const Tile* __restrict__ rt,
+                                                      double* __restrict__ Y, double* __restrict__ R,
+                                                      double* __restrict__ Z, double* __restrict__ Pold,
+                                                      double* __restrict__ part) {
+    const Tile tl = rt[blockIdx.x];
+    const BatchXfer& x = X[tl.k];
+    const int64_t i = tl.start + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < x.n) {
+        const int64_t o = x.row0 + i;
+        const double ri = x.bres[i];
+        const double zi = ri / x.diag[i];
+        Y[o] = 0.0;
+        R[o] = ri;
+        Z[o] = zi;
+        Pold[o] = 0.0;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    tile_partial(part, BP_RZ, rz);
+    tile_partial(part, BP_RR, rr);
+}
+
+// p_new = z + beta p_old (own rows), q = M p; partial p.q
+__global__ __launch_bounds__(BT) void k_batch_cg_spmv(const BatchXfer* __restrict__ X, const Tile* __restrict__ rt,
+                                                      const double* __restrict__ Z, const double* __restrict__ Pold,
+                                                      double* __restrict__ Pnew, double* __restrict__ Qv,
+                                                      const double* __restrict__ sc, double* __restrict__ part) {
+    const Tile tl = rt[blockIdx.x];
+    if (sc[int64_t(tl.k) * BS_COUNT + BS_DONE] != 0.0) return;   // block-uniform
+    const BatchXfer& x = X[tl.k];
+    const double bt = sc[int64_t(tl.k) * BS_COUNT + BS_BETA];
+    const int64_t i = tl.start + threadIdx.x;
+    const double* z = Z + x.row0;
+    const double* po = Pold + x.row0;
+    double pq = 0.0;
+    if (i < x.n) {
+        double qi = 0.0;
+        for (int64_t k = x.rowptr[i]; k < x.rowptr[i + 1]; ++k) {
+            const int32_t j = x.col[k];
+            qi = fma(x.val[k], fma(bt, po[j], z[j]), qi);
+        }
+        const double pi = fma(bt, po[i], z[i]);
+        Pnew[x.row0 + i] = pi;
+        Qv[x.row0 + i] = qi;
+        pq = pi * qi;
+    }
+    tile_partial(part, BP_PQ, pq);
+}
+
+// y += alpha p, r -= alpha q, z = D^-1 r; partials of r.z and r.r
+__global__ __launch_bounds__(BT) void k_batch_cg_update(const BatchXfer* __restrict__ X, const Tile* __restrict__ rt,
+                                                        const double* __restrict__ Pv, const double* __restrict__ Qv,
+                                                        double* __restrict__ Y, double* __restrict__ R,
+                                                        double* __restrict__ Z, const double* __restrict__ sc,
+                                                        double* __restrict__ part) {
+    const Tile tl = rt[blockIdx.x];
+    if (sc[int64_t(tl.k) * BS_COUNT + BS_DONE] != 0.0) return;
+    const BatchXfer& x = X[tl.k];
+    const double a = sc[int64_t(tl.k) * BS_COUNT + BS_ALPHA];
+    const int64_t i = tl.start + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < x.n) {
+        const int64_t o = x.row0 + i;
+        Y[o] = fma(a, Pv[o], Y[o]);
+        const double ri = fma(-a, Qv[o], R[o]);
+        const double zi = ri / x.diag[i];
+        R[o] = ri;
+        Z[o] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    tile_partial(part, BP_RZ, rz);
+    tile_partial(part, BP_RR, rr);
+}
+
+// x = alpha g + y into the caller's arrays (pointer table); b copied if asked
+__global__ __launch_bounds__(BT) void k_batch_solution(const BatchXfer* __restrict__ X, const Tile* __restrict__ rt,
+                                                       const double* __restrict__ Y, const double* __restrict__ B,
+                                                       double* const* __restrict__ xs, double* const* __restrict__ bs) {
+    const Tile tl = rt[blockIdx.x];
+    const BatchXfer& x = X[tl.k];
+    const int64_t i = tl.start + threadIdx.x;
+    if (i >= x.n) return;
+    xs[tl.k][i] = fma(x.alpha, x.g[i], Y[x.row0 + i]);
+    if (bs[tl.k]) bs[tl.k][i] = B[x.row0 + i];
+}
+
+// partials of ||b - M x||^2 and m^T x
+__global__ __launch_bounds__(BT) void k_batch_report(const BatchXfer* __restrict__ X, const Tile* __restrict__ rt,
+                                                     const double* __restrict__ B, double* const* __restrict__ xs,
+                                                     double* __restrict__ part) {
+    const Tile tl = rt[blockIdx.x];
+    const BatchXfer& x = X[tl.k];
+    const int64_t i = tl.start + threadIdx.x;
+    double trr = 0.0, mx = 0.0;
+    if (i < x.n) {
+        const double* xv = xs[tl.k];
+        const double ri = B[x.row0 + i] - row_dot(x, i, xv);
+        trr = ri * ri;
+        mx = x.lumped[i] * xv[i];
+    }
+    tile_partial(part, BP_TRR, trr);
+    tile_partial(part, BP_MX, mx);
+}
+
+// Per-system scalars from the tile partials: one wavefront per system adds its
+// tiles' partials (lane-strided, fixed butterfly) and lane 0 updates.
+//   mode 0: after the rhs           ||b||^2, sum b, threshold, reset
+//   mode 1: after r.z and r.r       stopping test; beta = rz / rho (0 at it = 0); rho = rz
+//   mode 2: after p.q               alpha = rho / p.q
+//   mode 3: after the report        ||b - M x||^2, m^T x
+__device__ __forceinline__ double system_total(const BatchXfer& x, const double* __restrict__ part, int slot) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < x.ntiles; t += 64) s += part[int64_t(x.tile0 + t) * BP_COUNT + slot];
+    return wave_sum_xor(s, 64);
+}
+
+__global__ __launch_bounds__(64) void k_batch_scalars(const BatchXfer* __restrict__ X, int mode, int it, double rtol2,
+                                                      const double* __restrict__ part, double* __restrict__ sc) {
+    const BatchXfer& x = X[blockIdx.x];
+    double* s = sc + int64_t(blockIdx.x) * BS_COUNT;
+    if (mode == 0) {
+        const double bb = system_total(x, part, BP_BB);
+        const double sb = system_total(x, part, BP_SB);
+        if (threadIdx.x == 0) {
+            s[BS_BB] = bb;
+            s[BS_SUMB] = sb;
+            s[BS_TOL2] = rtol2 * bb;
+            s[BS_DONE] = 0.0;
+            s[BS_ITERS] = 0.0;
+            s[BS_BETA] = 0.0;
+            s[BS_ALPHA] = 0.0;
+            s[BS_RHO] = 0.0;
+        }
+    } else if (mode == 1) {
+        if (s[BS_DONE] != 0.0) return;
+        const double rz = system_total(x, part, BP_RZ);
+        const double rr = system_total(x, part, BP_RR);
+        if (threadIdx.x == 0) {
+            s[BS_ITERS] = double(it);
+            if (rr <= s[BS_TOL2] || !isfinite(rr)) {
+                s[BS_DONE] = 1.0;
+            } else {
+                s[BS_BETA] = it == 0 ? 0.0 : rz / s[BS_RHO];
+                s[BS_RHO] = rz;
+            }
+        }
+    } else if (mode == 2) {
+        if (s[BS_DONE] != 0.0) return;
+        const double pq = system_total(x, part, BP_PQ);
+        if (threadIdx.x == 0) s[BS_ALPHA] = s[BS_RHO] / pq;
+    } else {
+        const double trr = system_total(x, part, BP_TRR);
+        const double mx = system_total(x, part, BP_MX);
+        if (threadIdx.x == 0) {
+            s[BS_TRR] = trr;
+            s[BS_INTX] = mx;
+        }
+    }
+}
+
+}  // namespace ft
+
+// ---------------------------------------------------------------- host side
+struct ft_batch {
+    int count = 0;
+    std::vector<ft_target*> T;
+    std::vector<ft_source*> S;
+    std::vector<ft_sample_cfg> cfg;
+    int64_t rows = 0;
+    int64_t n_elem_tiles = 0, n_node_tiles = 0, n_row_tiles = 0;
+    ft::BatchXfer* d_x = nullptr;
+    ft::Tile* d_elem = nullptr;
+    ft::Tile* d_node = nullptr;
+    ft::Tile* d_row = nullptr;
+    double *B = nullptr, *Y = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
+    double* part = nullptr;
+    double* sc = nullptr;
+    unsigned long long* nonfinite = nullptr;
+    double** d_xs = nullptr;      // [2][count] pointer tables: x, then b
+    double** h_xs = nullptr;      // pinned mirror
+    double* h_sc = nullptr;       // pinned [count][BS_COUNT]
+    unsigned long long* h_nf = nullptr;
+    unsigned grid_elem = 1, grid_node = 1;
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double cap_rtol = -1.0;
+    int cap_iters = -1;
+};
+
+namespace ft {
+
+ft_batch* batch_new(int count, ft_target* const* targets, ft_source* const* sources, const ft_sample_cfg* cfgs,
+                    bool graph) {
+    auto* b = new ft_batch();
+    b->count = count;
+    b->T.assign(targets, targets + count);
+    b->S.assign(sources, sources + count);
+    b->cfg.assign(cfgs, cfgs + count);
+    b->use_graph = graph;
+    return b;
+}
+
+void batch_delete(ft_batch* b) { delete b; }
+
+// after a run every target holds g, beta and b_res of its transfer, as after
+// ft_transfer_p1: ft_project may re-solve it on its own
+void batch_mark_consumed(ft_batch* b) {
+    for (int k = 0; k < b->count; ++k) {
+        b->T[k]->consumed = true;
+        b->T[k]->consumed_cfg = b->cfg[k];
+    }
+}
+
+void batch_release(ft_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    void* ps[] = {b->d_x, b->d_elem, b->d_node, b->d_row, b->B, b->Y, b->R, b->Z, b->P, b->Q, b->part, b->sc,
+                  b->nonfinite, b->d_xs};
+    for (void* p : ps) dev_free(p);
+    if (b->h_xs) (void)hipHostFree(b->h_xs);
+    if (b->h_sc) (void)hipHostFree(b->h_sc);
+    if (b->h_nf) (void)hipHostFree(b->h_nf);
+}
+
+template <typename K>
+static unsigned persistent_grid(K kernel, int64_t waves) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t want = (waves + 3) / 4;
+    return unsigned(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(cus) * per_cu)));
+}
+
+ft_status batch_setup(ft_batch* b, hipStream_t s) {
+    const int K = b->count;
+    std::vector<BatchXfer> xs(K);
+    std::vector<Tile> elem, node, row;
+    struct Group {
+        double cost;
+        int k;
+    };
+    std::vector<Group> order;
+    int64_t row0 = 0;
+    for (int k = 0; k < K; ++k) {
+        ft_target* T = b->T[k];
+        ft_source* S = b->S[k];
+        const ft_sample_cfg& c = b->cfg[k];
+        FT_TRY(ensure_field_buffers(T, 1, s));
+        BatchXfer& x = xs[k];
+        x.src = source_view(S);
+        x.coords = T->coords;
+        x.conn = T->conn;
+        x.vol = T->vol;
+        x.inc_ptr = T->inc_ptr;
+        x.inc = T->inc;
+        x.rowptr = T->rowptr;
+        x.col = T->col;
+        x.val = T->val;
+        x.diag = T->diag;
+        x.lumped = T->lumped;
+        x.g = T->g;
+        x.beta = T->beta;
+        x.bres = T->bres;
+        x.src_ood = S->counters;
+        x.n = T->n;
+        x.E = T->E;
+        x.row0 = row0;
+        x.tile0 = int32_t(row.size());
+        x.dim = T->dim;
+        x.N = uint32_t(c.samples_per_elem);
+        x.alpha = c.alpha;
+        x.key = SampleKey{uint32_t(c.seed & 0xFFFFFFFFu), uint32_t(c.seed >> 32), c.stream_id};
+        for (int64_t v = 0; v < T->n; v += BT) row.push_back(Tile{k, T->dim, v});
+        for (int64_t v = 0; v < T->n; v += 256) node.push_back(Tile{k, T->dim, v});
+        x.ntiles = int32_t(row.size()) - x.tile0;
+        row0 += T->n;
+        const int var = variant_of(c.samples_per_elem);
+        const int epw = 64 / lanes_of(var);   // elements per wavefront
+        // cost of one tile ~ samples it draws, 3D localization about 1.5x dearer
+        order.push_back(Group{double(epw) * c.samples_per_elem * (T->dim == 3 ? 1.5 : 1.0), k});
+    }
+    std::stable_sort(order.begin(), order.end(), [](const Group& a, const Group& c) { return a.cost > c.cost; });
+    for (const Group& gp : order) {
+        const int k = gp.k;
+        const int var = variant_of(b->cfg[k].samples_per_elem);
+        const int epw = 64 / lanes_of(var);
+        const int code = var + (b->T[k]->dim == 3 ? kVariants : 0);
+        for (int64_t t = 0; t < b->T[k]->E; t += epw) elem.push_back(Tile{k, code, t});
+    }
+    if (row.size() >= (size_t(1) << 31)) {
+        set_error("batch too large (%zu row tiles)", row.size());
+        return FT_E_UNSUPPORTED;
+    }
+    b->rows = row0;
+    b->n_elem_tiles = int64_t(elem.size());
+    b->n_node_tiles = int64_t(node.size());
+    b->n_row_tiles = int64_t(row.size());
+    FT_TRY(dev_alloc_n(&b->d_x, size_t(K)));
+    FT_TRY(dev_alloc_n(&b->d_elem, elem.size()));
+    FT_TRY(dev_alloc_n(&b->d_node, node.size()));
+    FT_TRY(dev_alloc_n(&b->d_row, row.size()));
+    for (double** p : {&b->B, &b->Y, &b->R, &b->Z, &b->Q}) FT_TRY(dev_alloc_n(p, size_t(row0)));
+    FT_TRY(dev_alloc_n(&b->P, size_t(2 * row0)));
+    FT_TRY(dev_alloc_n(&b->part, size_t(row.size()) * BP_COUNT));
+    FT_TRY(dev_alloc_n(&b->sc, size_t(K) * BS_COUNT));
+    FT_TRY(dev_alloc_n(&b->nonfinite, size_t(K)));
+    FT_TRY(dev_alloc_n(&b->d_xs, size_t(2 * K)));
+    FT_TRY_HIP(hipHostMalloc((void**)&b->h_xs, sizeof(double*) * 2 * K, hipHostMallocDefault));
+    FT_TRY_HIP(hipHostMalloc((void**)&b->h_sc, sizeof(double) * BS_COUNT * K, hipHostMallocDefault));
+    FT_TRY_HIP(hipHostMalloc((void**)&b->h_nf, sizeof(unsigned long long) * K, hipHostMallocDefault));
+    FT_TRY_HIP(hipMemcpyAsync(b->d_x, xs.data(), sizeof(BatchXfer) * K, hipMemcpyHostToDevice, s));
+    FT_TRY_HIP(hipMemcpyAsync(b->d_elem, elem.data(), sizeof(Tile) * elem.size(), hipMemcpyHostToDevice, s));
+    FT_TRY_HIP(hipMemcpyAsync(b->d_node, node.data(), sizeof(Tile) * node.size(), hipMemcpyHostToDevice, s));
+    FT_TRY_HIP(hipMemcpyAsync(b->d_row, row.data(), sizeof(Tile) * row.size(), hipMemcpyHostToDevice, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
+    b->grid_elem = persistent_grid(k_batch_fused, b->n_elem_tiles);
+    b->grid_node = persistent_grid(k_batch_nodes, b->n_node_tiles);
+    if (b->use_graph) FT_TRY_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    return FT_OK;
+}
+
+// Every launch of one run, in order; no host synchronization, no memset.
+static ft_status enqueue_run(ft_batch* b, const ft_solve_cfg* cfg, hipStream_t s) {
+    const int K = b->count;
+    const unsigned nrt = unsigned(b->n_row_tiles);
+    const int64_t rows = b->rows;
+    k_fill_u64<<<grid_for(K, 256), 256, 0, s>>>(b->nonfinite, K);
+    if (b->n_node_tiles) k_batch_nodes<<<b->grid_node, 256, 0, s>>>(b->d_x, b->d_node, b->n_node_tiles);
+    if (b->n_elem_tiles)
+        k_batch_fused<<<b->grid_elem, 256, 0, s>>>(b->d_x, b->d_elem, b->n_elem_tiles, b->nonfinite);
+    k_batch_assemble<<<nrt, BT, 0, s>>>(b->d_x, b->d_row);
+    k_batch_rhs<<<nrt, BT, 0, s>>>(b->d_x, b->d_row, b->B, b->part);
+    k_batch_scalars<<<K, 64, 0, s>>>(b->d_x, 0, 0, cfg->rtol * cfg->rtol, b->part, b->sc);
+    k_batch_cg_init<<<nrt, BT, 0, s>>>(b->d_x, b->d_row, b->Y, b->R, b->Z, b->P, b->part);
+    k_batch_scalars<<<K, 64, 0, s>>>(b->d_x, 1, 0, 0.0, b->part, b->sc);
+    for (int it = 0; it < cfg->max_iter; ++it) {
+        double* Pold = b->P + ((it & 1) ? rows : 0);
+        double* Pnew = b->P + ((it & 1) ? 0 : rows);
+        k_batch_cg_spmv<<<nrt, BT, 0, s>>>(b->d_x, b->d_row, b->Z, Pold, Pnew, b->Q, b->sc, b->part);
+        k_batch_scalars<<<K, 64, 0, s>>>(b->d_x, 2, it, 0.0, b->part, b->sc);
+        k_batch_cg_update<<<nrt, BT, 0, s>>>(b->d_x, b->d_row, Pnew, b->Q, b->Y, b->R, b->Z, b->sc, b->part);
+        k_batch_scalars<<<K, 64, 0, s>>>(b->d_x, 1, it + 1, 0.0, b->part, b->sc);
+    }
+    k_batch_solution<<<nrt, BT, 0, s>>>(b->d_x, b->d_row, b->Y, b->B, b->d_xs, b->d_xs + K);
+    k_batch_report<<<nrt, BT, 0, s>>>(b->d_x, b->d_row, b->B, b->d_xs, b->part);
+    k_batch_scalars<<<K, 64, 0, s>>>(b->d_x, 3, 0, 0.0, b->part, b->sc);
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
+ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec, ft_report* rep,
+                    int32_t* status, hipStream_t s) {
+    const int K = b->count;
+    for (int k = 0; k < K; ++k) {
+        b->h_xs[k] = x[k];
+        b->h_xs[K + k] = bvec ? bvec[k] : nullptr;
+    }
+    FT_TRY_HIP(hipMemcpyAsync(b->d_xs, b->h_xs, sizeof(double*) * 2 * K, hipMemcpyHostToDevice, s));
+    if (b->use_graph) {
+        if (!b->exec || b->cap_rtol != cfg->rtol || b->cap_iters != cfg->max_iter) {
+            if (b->exec) {
+                FT_TRY_HIP(hipGraphExecDestroy(b->exec));
+                b->exec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            FT_TRY_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+            const ft_status st = enqueue_run(b, cfg, b->cap_stream);
+            const hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+            if (st != FT_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            FT_TRY_HIP(e);
+            const hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            FT_TRY_HIP(ie);
+            b->cap_rtol = cfg->rtol;
+            b->cap_iters = cfg->max_iter;
+        }
+        FT_TRY_HIP(hipGraphLaunch(b->exec, s));
+    } else {
+        FT_TRY(enqueue_run(b, cfg, s));
+    }
+    FT_TRY_HIP(hipMemcpyAsync(b->h_sc, b->sc, sizeof(double) * BS_COUNT * K, hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipMemcpyAsync(b->h_nf, b->nonfinite, sizeof(unsigned long long) * K, hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    ft_status worst = FT_OK;
+    for (int k = 0; k < K; ++k) {
+        const double* h = b->h_sc + int64_t(k) * BS_COUNT;
+        ft_report& R = rep[k];
+        R.sum_b = h[BS_SUMB];
+        R.int_x = h[BS_INTX];
+        R.cons_defect = h[BS_SUMB] != 0.0 ? std::fabs(h[BS_INTX] - h[BS_SUMB]) / std::fabs(h[BS_SUMB])
+                                          : std::fabs(h[BS_INTX]);
+        R.rel_resid = h[BS_BB] > 0.0 ? std::sqrt(h[BS_TRR] / h[BS_BB]) : std::sqrt(h[BS_TRR]);
+        R.iters = int32_t(h[BS_ITERS]);
+        R.n_nonfinite = int64_t(b->h_nf[k]);
+        R.status = b->h_nf[k] ? FT_E_NONFINITE : (h[BS_DONE] != 0.0 ? FT_OK : FT_E_NOCONV);
+        if (status) status[k] = R.status;
+        if (R.status != FT_OK && (worst == FT_OK || R.status == FT_E_NONFINITE)) worst = ft_status(R.status);
+    }
+    if (worst == FT_E_NONFINITE) set_error("non-finite source values in at least one transfer of the batch");
+    else if (worst == FT_E_NOCONV) set_error("CG did not reach rtol=%g within %d iterations for at least one transfer",
+                                             cfg->rtol, cfg->max_iter);
+    return worst;
+}
+
+}  // namespace ft

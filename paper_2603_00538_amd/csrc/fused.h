@@ -1,0 +1,100 @@
+// Fused per-element work of the built-in-source route (sec. 4.1 steps 3-5):
+// sample, localize, interpolate and accumulate the residual element loads of
+// target element t, with G lanes per element and P samples per lane per
+// round.  Shared by the single-transfer kernel and the batched kernel.
+#pragma once
+
+#include "locate.h"
+#include "sampling.h"
+
+namespace ft {
+
+// lane: index within the element's lane group [0, G); t >= E marks an idle
+// group (it still takes part in the wave-cooperative localization).  Adds the
+// lane's non-finite and out-of-domain counts to nf / nood.
+template <int D, int G, int P, int FC>
+__device__ __forceinline__ void fused_elements(const SrcView& S, const double* __restrict__ X, int64_t n,
+                                               const int32_t* __restrict__ conn, const double* __restrict__ vol,
+                                               uint32_t E, uint32_t N, double alpha, SampleKey key,
+                                               const double* __restrict__ g, double* __restrict__ beta, uint32_t t,
+                                               int lane, unsigned& nf, unsigned& nood) {
+    const bool valid = t < E;
+    const uint32_t tt = valid ? t : 0u;
+    int v[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(tt) * (D + 1) + k];
+    double xv[D + 1][D];
+#pragma unroll
+    for (int k = 0; k <= D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) xv[k][c] = X[c * n + v[k]];
+    double gk[FC][D + 1], acc[FC][D + 1];
+#pragma unroll
+    for (int f = 0; f < FC; ++f)
+#pragma unroll
+        for (int k = 0; k <= D; ++k) {
+            acc[f][k] = 0.0;
+            gk[f][k] = f < S.F ? g[int64_t(f) * n + v[k]] : 0.0;
+        }
+    // every lane runs the same number of rounds: the localization is wave-cooperative.
+    // Round r, slot q of a lane holds sample j = r*G*P + q*G + lane.
+    for (uint32_t j0 = 0; j0 < N; j0 += G * P) {
+        double lam[P][D + 1], pt[P][D];
+        bool act[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const uint32_t j = j0 + q * G + lane;
+            act[q] = valid && j < N;
+            if (act[q]) {
+                sample_lambda<D>(tt, j, key, lam[q]);
+            } else {
+#pragma unroll
+                for (int k = 0; k <= D; ++k) lam[q][k] = 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                double x = lam[q][0] * xv[0][c];
+#pragma unroll
+                for (int k = 1; k <= D; ++k) x = fma(lam[q][k], xv[k][c], x);
+                pt[q][c] = x;
+            }
+        }
+        double best[P];
+        int bid[P];
+        locate_wave<D, P>(S, pt, act, best, bid);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            if (!act[q]) continue;
+            nood += (bid[q] == INT_MAX || best[q] < kOutTol);
+            double mu[D + 1];
+            winner_mu<D>(S, bid[q], pt[q], mu);
+#pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                if (f >= S.F) break;
+                const double y = p1_value<D>(S, bid[q], mu, f);
+                nf += !isfinite(y);
+                double gx = lam[q][0] * gk[f][0];
+#pragma unroll
+                for (int k = 1; k <= D; ++k) gx = fma(lam[q][k], gk[f][k], gx);
+                const double r = y - alpha * gx;
+#pragma unroll
+                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[q][k], acc[f][k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FC; ++f)
+#pragma unroll
+        for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
+    if (valid && lane == 0) {
+        const double scale = vol[t] / double(N);
+#pragma unroll
+        for (int f = 0; f < FC; ++f) {
+            if (f >= S.F) break;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) beta[(int64_t(f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+        }
+    }
+}
+
+}  // namespace ft

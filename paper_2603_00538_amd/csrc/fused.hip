@@ -11,8 +11,7 @@
 // element, the same barycentrics and the same values; the element sums run
 // in the consume kernel's lane order for N >= 64 with G*P samples per round.
 // Only the control g (f^s at the target nodes) and beta are written.
-#include "locate.h"
-#include "sampling.h"
+#include "fused.h"
 
 namespace ft {
 
@@ -24,86 +23,8 @@ __global__ __launch_bounds__(256) void k_fused_p1(SrcView S, const double* __res
                                                   unsigned long long* __restrict__ nonfinite,
                                                   unsigned long long* __restrict__ n_ood) {
     const uint32_t gid = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
-    const uint32_t t = gid / G;
-    const int lane = int(gid & (G - 1));
-    const bool valid = t < E;
-    const uint32_t tt = valid ? t : 0u;
-    int v[D + 1];
-#pragma unroll
-    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(tt) * (D + 1) + k];
-    double xv[D + 1][D];
-#pragma unroll
-    for (int k = 0; k <= D; ++k)
-#pragma unroll
-        for (int c = 0; c < D; ++c) xv[k][c] = X[c * n + v[k]];
-    double gk[FC][D + 1], acc[FC][D + 1];
-#pragma unroll
-    for (int f = 0; f < FC; ++f)
-#pragma unroll
-        for (int k = 0; k <= D; ++k) {
-            acc[f][k] = 0.0;
-            gk[f][k] = f < S.F ? g[int64_t(f) * n + v[k]] : 0.0;
-        }
-    unsigned int nf = 0, nood = 0;
-    // every lane runs the same number of rounds: the localization is wave-cooperative.
-    // Round r, slot q of a lane holds sample j = r*G*P + q*G + lane.
-    for (uint32_t j0 = 0; j0 < N; j0 += G * P) {
-        double lam[P][D + 1], pt[P][D];
-        bool act[P];
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            const uint32_t j = j0 + q * G + lane;
-            act[q] = valid && j < N;
-            if (act[q]) {
-                sample_lambda<D>(tt, j, key, lam[q]);
-            } else {
-#pragma unroll
-                for (int k = 0; k <= D; ++k) lam[q][k] = 0.0;
-            }
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                double x = lam[q][0] * xv[0][c];
-#pragma unroll
-                for (int k = 1; k <= D; ++k) x = fma(lam[q][k], xv[k][c], x);
-                pt[q][c] = x;
-            }
-        }
-        double best[P];
-        int bid[P];
-        locate_wave<D, P>(S, pt, act, best, bid);
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            if (!act[q]) continue;
-            nood += (bid[q] == INT_MAX || best[q] < kOutTol);
-            double mu[D + 1];
-            winner_mu<D>(S, bid[q], pt[q], mu);
-#pragma unroll
-            for (int f = 0; f < FC; ++f) {
-                if (f >= S.F) break;
-                const double y = p1_value<D>(S, bid[q], mu, f);
-                nf += !isfinite(y);
-                double gx = lam[q][0] * gk[f][0];
-#pragma unroll
-                for (int k = 1; k <= D; ++k) gx = fma(lam[q][k], gk[f][k], gx);
-                const double r = y - alpha * gx;
-#pragma unroll
-                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[q][k], acc[f][k]);
-            }
-        }
-    }
-#pragma unroll
-    for (int f = 0; f < FC; ++f)
-#pragma unroll
-        for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
-    if (valid && lane == 0) {
-        const double scale = vol[t] / double(N);
-#pragma unroll
-        for (int f = 0; f < FC; ++f) {
-            if (f >= S.F) break;
-#pragma unroll
-            for (int k = 0; k <= D; ++k) beta[(int64_t(f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
-        }
-    }
+    unsigned nf = 0, nood = 0;
+    fused_elements<D, G, P, FC>(S, X, n, conn, vol, E, N, alpha, key, g, beta, gid / G, int(gid & (G - 1)), nf, nood);
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
     if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }

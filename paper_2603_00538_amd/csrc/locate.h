@@ -11,19 +11,21 @@
 // Search.  The points of a wave (64 lanes x P points) are usually samples of
 // one or two target elements, so they share a handful of bins.  The wave
 // forms its points' bounding box (and, in 2D, their ranges of x+y and x-y: an
-// octagon), then culls each bin's candidates 64 at a time, one per lane:
+// octagon) and the box of bins it covers; the registrations of all those bins
+// form one flat candidate sequence, culled 64 at a time, one per lane:
 //   - the element's box must meet the wave's box (and octagon, in 2D);
-//   - it must not already have been offered by an earlier bin of the wave;
+//   - it is offered only in the first of the wave's bins it is registered in;
 //   - no barycentric coordinate may be below -1e-9 on the whole wave box.
-// Every lane then tests its points against each surviving candidate, whose
-// record is wave-uniform (scalar loads).  The selection test evaluates the
-// barycentrics as absolute affine functions (no per-candidate set-up) and
-// accepts an element once its min mu exceeds 1e-9, far above that form's
-// rounding, so an accepted element truly contains the point and is the
-// unique winner.  Points never accepted (within 1e-9 of a face, or outside)
-// are re-searched in their own bin with the full rule.  The barycentrics used
-// to interpolate are always recomputed from the element origin.  Waves whose points span
-// many bins (scattered input) search one bin per point.
+// Survivors write their absolute affine barycentric form to the wave's LDS
+// slots; every lane then tests its points against each survivor (broadcast
+// LDS reads, two candidates per step).  The selection test accepts an element
+// once its min mu exceeds 1e-9, far above that form's rounding, so an
+// accepted element truly contains the point and is the unique winner.  Points
+// never accepted (within 1e-9 of a face, or outside) are re-searched in their
+// own bin with the full rule.  The barycentrics used to interpolate are always
+// recomputed from the element origin.  Waves whose points span many bins
+// (scattered input) search one bin per point.  Callers launch 256-thread
+// blocks (four waves share the block's LDS slots).
 #pragma once
 
 #include <cfloat>
@@ -125,51 +127,6 @@ __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int
     }
 }
 
-// min_k mu_k(p) from the absolute affine form (selection only).
-template <int D>
-__device__ __forceinline__ double affine_min_mu(const double* __restrict__ r, const double (&p)[D]) {
-    constexpr int AF = RecAffine<D>::value;
-    double mn = 0.0;
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        double s = r[AF + k];
-#pragma unroll
-        for (int c = 0; c < D; ++c) s = fma(r[AF + D + 1 + k * D + c], p[c], s);
-        mn = k == 0 ? s : fmin(mn, s);
-    }
-    return mn;
-}
-
-// Wave-uniform value copied into a vector register once, so that the
-// per-point products below take it as an operand instead of copying it for
-// every point (a VOP3 instruction reads at most one scalar register here).
-__device__ __forceinline__ double to_vgpr(double u) {
-    double v;
-    asm("v_mov_b64 %0, %1" : "=v"(v) : "s"(u));
-    return v;
-}
-
-// One candidate record against the P points of this lane: the affine form's
-// offsets are held in vector registers, the gradients stay scalar.
-template <int D, int P>
-__device__ __forceinline__ void affine_min_mu_multi(const double* __restrict__ r, const double (&p)[P][D],
-                                                    double (&mn)[P]) {
-    constexpr int AF = RecAffine<D>::value;
-    double a[D + 1];
-#pragma unroll
-    for (int k = 0; k <= D; ++k) a[k] = to_vgpr(r[AF + k]);
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-#pragma unroll
-        for (int k = 0; k <= D; ++k) {
-            double s = a[k];
-#pragma unroll
-            for (int c = 0; c < D; ++c) s = fma(r[AF + D + 1 + k * D + c], p[q][c], s);
-            mn[q] = k == 0 ? s : fmin(mn[q], s);
-        }
-    }
-}
-
 // Conservative test whether element r can contain a point of the box
 // [lo, hi]: false only if some barycentric coordinate is below -1e-9 on the
 // whole box (a linear function's maximum over a box sits at a corner).
@@ -189,6 +146,38 @@ __device__ __forceinline__ bool box_may_meet(const double* __restrict__ r, const
         meet &= mx >= -1e-9;
     }
     return meet;
+}
+
+// The same test on the affine form held in registers: af = [c_0..c_D, g_0, ..., g_D].
+template <int D>
+__device__ __forceinline__ bool box_may_meet_af(const double (&af)[(D + 1) * (D + 1)], const double (&lo)[D],
+                                                const double (&hi)[D]) {
+    bool meet = true;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        double mx = af[k];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const double gk = af[D + 1 + k * D + c];
+            mx += fmax(gk * lo[c], gk * hi[c]);
+        }
+        meet &= mx >= -1e-9;
+    }
+    return meet;
+}
+
+// min_k mu_k(p) from an affine form in LDS (wave-uniform address: a broadcast read).
+template <int D>
+__device__ __forceinline__ double affine_min_mu_lds(const double* af, const double (&p)[D]) {
+    double mn = 0.0;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        double s = af[k];
+#pragma unroll
+        for (int c = 0; c < D; ++c) s = fma(af[D + 1 + k * D + c], p[c], s);
+        mn = k == 0 ? s : fmin(mn, s);
+    }
+    return mn;
 }
 
 // Own-bin search of one point with the full rule (absolute coordinates).
@@ -213,6 +202,18 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
 // lane of the wave must call it (points a lane does not own pass
 // active = false).  Returns best = max min-barycentric and bid = its element
 // id (INT_MAX if no candidate was found) per point.
+// Inclusive prefix sum over the first 32 lanes of the wave (enough for the
+// at most 27 bins a wave searches).
+__device__ __forceinline__ int wave_scan_incl(int x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int t = __shfl_up(x, d, 64);
+        if (lane >= d) x += t;
+    }
+    return x;
+}
+
 template <int D, int P>
 __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[P][D], const bool (&active)[P],
                                             double (&best)[P], int (&bid)[P]) {
@@ -270,53 +271,95 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             fu[2] = f32_down(wave_min(vlo));
             fu[3] = f32_up(wave_max(vhi));
         }
+        // Lane i < span describes bin i of the wave's bin box (x fastest): its
+        // coordinates, first registration and count.  The candidate slots of all
+        // these bins are then culled 64 at a time in one flat sequence.
+        constexpr int AL = (D + 1) * (D + 1);   // affine form: D+1 constants, (D+1) x D gradients
+        __shared__ double c_af[4][64 * AL];     // per wave of a 256-thread block
+        __shared__ int c_id[4][64];
+        const int w = (threadIdx.x >> 6) & 3;
+        const int wx = b1[0] - b0[0] + 1, wy = b1[1] - b0[1] + 1;
+        int cb[3] = {0, 0, 0};
+        int64_t bstart = 0;
+        int bcnt = 0;
+        if (lane < span) {
+            cb[0] = b0[0] + lane % wx;
+            cb[1] = b0[1] + (lane / wx) % wy;
+            cb[2] = b0[2] + lane / (wx * wy);
+            const int64_t b = (int64_t(cb[2]) * S.g.nb[1] + cb[1]) * S.g.nb[0] + cb[0];
+            bstart = S.bin_ptr[b];
+            bcnt = int(S.bin_ptr[b + 1] - bstart);
+        }
+        const int incl = wave_scan_incl(bcnt);
+        const int total = __builtin_amdgcn_readlane(incl, span - 1);
         bool finished = false;
-        for (int bz = b0[2]; bz <= b1[2] && !finished; ++bz)
-            for (int by = b0[1]; by <= b1[1] && !finished; ++by)
-                for (int bx = b0[0]; bx <= b1[0] && !finished; ++bx) {
-                    const int64_t b = (int64_t(bz) * S.g.nb[1] + by) * S.g.nb[0] + bx;
-                    const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
-                    const int cur[3] = {bx, by, bz};
-                    for (int64_t c0 = start; c0 < end && !finished; c0 += 64) {
-                        int cid = -1;
-                        bool ov = false;
-                        if (c0 + lane < end) {
-                            cid = S.bin_elems[c0 + lane];
-                            const float* bx_ = S.box + int64_t(cid) * BS;
-                            ov = true;
+        for (int c0 = 0; c0 < total && !finished; c0 += 64) {
+            const int sl = c0 + lane;
+            int i = 0;   // bin of slot sl: the number of bins whose inclusive count is <= sl
+            for (int u = 0; u < span - 1; ++u) i += sl >= __builtin_amdgcn_readlane(incl, u);
+            const int excl_i = __shfl(incl - bcnt, i, 64);
+            const int64_t st_i = __shfl((long long)bstart, i, 64);
+            int cur[3];
 #pragma unroll
-                            for (int c = 0; c < D; ++c) {
-                                ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
-                                // offer each element once per wave: in the first of the wave's bins it is in
-                                ov &= max(S.bin_first[int64_t(cid) * D + c], b0[c]) == cur[c];
-                            }
-                            if constexpr (D == 2)
-                                ov &= (bx_[4] <= fu[1]) & (bx_[6] >= fu[0]) & (bx_[5] <= fu[3]) & (bx_[7] >= fu[2]);
-                            if (ov) ov = box_may_meet<D>(S.rec + int64_t(cid) * RS, wlo, whi);
-                        }
-                        uint64_t mask = __ballot(ov);
-                        while (mask) {
-                            const int l = __ffsll((unsigned long long)mask) - 1;
-                            mask &= mask - 1;
-                            const int e = read_lane(cid, l);
-                            const double* r = S.rec + int64_t(e) * RS;
-                            double mn[P];
-                            affine_min_mu_multi<D, P>(r, p, mn);
-                            bool done = true;
+            for (int c = 0; c < 3; ++c) cur[c] = __shfl(cb[c], i, 64);
+            int cid = -1;
+            bool ov = false;
+            double af[AL];
+            if (sl < total) {
+                cid = S.bin_elems[st_i + (sl - excl_i)];
+                const float* bx_ = S.box + int64_t(cid) * BS;
+                ov = true;
 #pragma unroll
-                            for (int q = 0; q < P; ++q) {
-                                // first strictly larger value wins (branch-free)
-                                bid[q] = mn[q] > best[q] ? e : bid[q];
-                                best[q] = fmax(best[q], mn[q]);
-                                done &= best[q] > kFastTau;
-                            }
-                            if (__all(done)) {
-                                finished = true;
-                                break;
-                            }
-                        }
-                    }
+                for (int c = 0; c < D; ++c) {
+                    ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
+                    // offer each element once per wave: in the first of the wave's bins it is in
+                    ov &= max(S.bin_first[int64_t(cid) * D + c], b0[c]) == cur[c];
                 }
+                if constexpr (D == 2)
+                    ov &= (bx_[4] <= fu[1]) & (bx_[6] >= fu[0]) & (bx_[5] <= fu[3]) & (bx_[7] >= fu[2]);
+                if (ov) {
+                    const double* r = S.rec + int64_t(cid) * RS + RecAffine<D>::value;
+#pragma unroll
+                    for (int m = 0; m < AL; ++m) af[m] = r[m];
+                    ov = box_may_meet_af<D>(af, wlo, whi);
+                }
+            }
+            // survivors' affine forms go to this wave's LDS slots, in lane order
+            const uint64_t mask = __ballot(ov);
+            if (ov) {
+                const int slot = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u)));
+#pragma unroll
+                for (int m = 0; m < AL; ++m) c_af[w][slot * AL + m] = af[m];
+                c_id[w][slot] = cid;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int nc = __popcll((unsigned long long)mask);
+            // two candidates per step; a repeat of the last one changes nothing
+            // (the first strictly larger value wins)
+            for (int c = 0; c < nc; c += 2) {
+                const int c2 = c + 1 < nc ? c + 1 : c;
+                const double* a1 = &c_af[w][c * AL];
+                const double* a2 = &c_af[w][c2 * AL];
+                const int e1 = c_id[w][c], e2 = c_id[w][c2];
+                bool done = true;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const double m1 = affine_min_mu_lds<D>(a1, p[q]);
+                    const double m2 = affine_min_mu_lds<D>(a2, p[q]);
+                    bid[q] = m1 > best[q] ? e1 : bid[q];
+                    best[q] = fmax(best[q], m1);
+                    bid[q] = m2 > best[q] ? e2 : bid[q];
+                    best[q] = fmax(best[q], m2);
+                    done &= best[q] > kFastTau;
+                }
+                if (__all(done)) {
+                    finished = true;
+                    break;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
         // points not accepted by the fast test (near a face, or outside): the full rule
         // in the point's own bin; accepted points get their exact min mu
 #pragma unroll
@@ -356,6 +399,52 @@ __device__ __forceinline__ double p1_value(const SrcView& S, int bid, const doub
 #pragma unroll
     for (int k = 0; k <= D; ++k) y = fma(bmu[k], Fv[S.conn[int64_t(bid) * (D + 1) + k]], y);
     return y;
+}
+
+// Localize and evaluate the points [base, min(base + 64P, lim)) of a (d, ld)
+// point array: lane l takes points base + q*64 + l.  Writes values (and ids
+// if non-null) and returns this lane's count of out-of-domain points.
+template <int D, int P, bool IN_F32, bool OUT_F32>
+__device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, int64_t lim,
+                                              const void* __restrict__ pts_, int64_t ld, void* __restrict__ out_,
+                                              int64_t ld_out, int32_t* __restrict__ ids) {
+    const int lane = threadIdx.x & 63;
+    double p[P][D];
+    bool active[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t i = base + q * 64 + lane;
+        active[q] = i < lim;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            if (IN_F32)
+                p[q][c] = active[q] ? double(static_cast<const float*>(pts_)[c * ld + i]) : 0.0;
+            else
+                p[q][c] = active[q] ? static_cast<const double*>(pts_)[c * ld + i] : 0.0;
+        }
+    }
+    double best[P];
+    int bid[P];
+    locate_wave<D, P>(S, p, active, best, bid);
+    unsigned int nood = 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        if (!active[q]) continue;
+        const int64_t i = base + q * 64 + lane;
+        const bool found = bid[q] != INT_MAX;
+        nood += !found || best[q] < kOutTol;
+        if (ids) ids[i] = found ? bid[q] : -1;
+        double mu[D + 1];
+        winner_mu<D>(S, bid[q], p[q], mu);
+        for (int f = 0; f < S.F; ++f) {
+            const double y = p1_value<D>(S, bid[q], mu, f);
+            if (OUT_F32)
+                static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
+            else
+                static_cast<double*>(out_)[int64_t(f) * ld_out + i] = y;
+        }
+    }
+    return nood;
 }
 
 }  // namespace ft

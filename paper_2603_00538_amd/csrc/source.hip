@@ -233,47 +233,12 @@ __global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t head, int64
                                                   int32_t* __restrict__ ids, unsigned long long* __restrict__ n_ood) {
     // two segments, [0, head) and [head, npts), each starting on a wavefront boundary
     constexpr int64_t WP = 64 * P;
-    const int lane = threadIdx.x & 63;
     const int64_t wave = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 4 + (threadIdx.x >> 6);
     const int64_t wh = (head + WP - 1) / WP;
     const int64_t base = wave < wh ? wave * WP : head + (wave - wh) * WP;
     const int64_t lim = wave < wh ? head : npts;
     if (base >= lim) return;   // wave-uniform
-    double p[P][D];
-    bool active[P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int64_t i = base + q * 64 + lane;
-        active[q] = i < lim;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            if (IN_F32)
-                p[q][c] = active[q] ? double(static_cast<const float*>(pts_)[c * ld + i]) : 0.0;
-            else
-                p[q][c] = active[q] ? static_cast<const double*>(pts_)[c * ld + i] : 0.0;
-        }
-    }
-    double best[P];
-    int bid[P];
-    locate_wave<D, P>(S, p, active, best, bid);
-    unsigned int nood = 0;
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        if (!active[q]) continue;
-        const int64_t i = base + q * 64 + lane;
-        const bool found = bid[q] != INT_MAX;
-        nood += !found || best[q] < kOutTol;
-        if (ids) ids[i] = found ? bid[q] : -1;
-        double mu[D + 1];
-        winner_mu<D>(S, bid[q], p[q], mu);
-        for (int f = 0; f < S.F; ++f) {
-            const double y = p1_value<D>(S, bid[q], mu, f);
-            if (OUT_F32)
-                static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
-            else
-                static_cast<double*>(out_)[int64_t(f) * ld_out + i] = y;
-        }
-    }
+    const unsigned nood = eval_wave<D, P, IN_F32, OUT_F32>(S, base, lim, pts_, ld, out_, ld_out, ids);
     if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
 

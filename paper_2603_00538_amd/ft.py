@@ -21,12 +21,13 @@ LIB_PATH = os.path.join(HERE, "libft.so")
 FT_OK, FT_E_ARG, FT_E_MESH, FT_E_ORDER, FT_E_DEVICE, FT_E_NOCONV, FT_E_NONFINITE, FT_E_OOM, FT_E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FT_F64, FT_F32, FT_SPLIT_F16, FT_SPLIT_BF16 = 0, 1, 2, 3
+FT_BATCH_GRAPH = 1
 STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -4: "FT_E_DEVICE",
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
             "ft_consume_queries", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval",
-            "ft_source_eval_queries", "ft_source_stats",
+            "ft_source_eval_queries", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_last_error"]
 
 
@@ -91,6 +92,9 @@ def load(path: str = LIB_PATH):
         "ft_source_stats": (I32, [P, ctypes.POINTER(I64), P]),
         "ft_source_destroy": (I32, [P]),
         "ft_source_get_info": (I32, [P, ctypes.POINTER(SourceInfo)]),
+        "ft_batch_create": (I32, [I32, P, P, ctypes.POINTER(SampleCfg), I32, P, ctypes.POINTER(P)]),
+        "ft_batch_run": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P, P]),
+        "ft_batch_destroy": (I32, [P]),
         "ft_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -145,6 +149,30 @@ def ft_project(h, cfg: SolveCfg, x_ptr, b_ptr, n_fields, stream, allow=(FT_E_NOC
     reps = (Report * n_fields)()
     st = _check(load().ft_project(h, ctypes.byref(cfg), x_ptr, b_ptr, reps, stream), "ft_project", allow)
     return st, [r.as_dict() for r in reps]
+
+
+def ft_batch_create(targets, sources, cfgs, flags, stream):
+    K = len(targets)
+    th = (ctypes.c_void_p * K)(*targets)
+    sh = (ctypes.c_void_p * K)(*sources)
+    cf = (SampleCfg * K)(*cfgs)
+    out = ctypes.c_void_p()
+    _check(load().ft_batch_create(K, th, sh, cf, flags, stream, ctypes.byref(out)), "ft_batch_create")
+    return out
+
+
+def ft_batch_run(h, cfg: SolveCfg, x_ptrs, b_ptrs, stream, allow=(FT_E_NOCONV, FT_E_NONFINITE)):
+    K = len(x_ptrs)
+    xs = (ctypes.c_void_p * K)(*x_ptrs)
+    bs = (ctypes.c_void_p * K)(*b_ptrs) if b_ptrs is not None else None
+    reps = (Report * K)()
+    sts = (ctypes.c_int32 * K)()
+    st = _check(load().ft_batch_run(h, ctypes.byref(cfg), xs, bs, reps, sts, stream), "ft_batch_run", allow)
+    return st, [r.as_dict() for r in reps], list(sts)
+
+
+def ft_batch_destroy(h):
+    return _check(load().ft_batch_destroy(h), "ft_batch_destroy")
 
 
 def ft_source_create_p1(dim, n_nodes, coords_ptr, n_elems, conn_ptr, n_fields, values_ptr, bins, stream):
@@ -371,3 +399,43 @@ class Source:
 
     def take_out_of_domain(self):
         return ft_source_stats(self.handle, current_stream())
+
+
+class Batch:
+    """Many built-in-source transfers run together (ft_batch_create / ft_batch_run).
+
+    targets, sources: Target and Source objects (kept alive by the batch);
+    cfgs: one SampleCfg per transfer.  run() returns, per transfer, the
+    solution x (device tensor) and the load vector b, the reports and the
+    per-transfer statuses.
+    """
+
+    def __init__(self, targets, sources, cfgs, graph=False):
+        self.targets, self.sources = list(targets), list(sources)
+        self.cfgs = list(cfgs)
+        self.handle = ft_batch_create([t.handle for t in self.targets], [s.handle for s in self.sources],
+                                      self.cfgs, FT_BATCH_GRAPH if graph else 0, current_stream())
+
+    def run(self, rtol=1e-14, max_iter=60, xs=None, bs=None, want_b=True):
+        torch = _torch()
+        dev = self.targets[0].coords.device
+        if xs is None:
+            xs = [torch.empty(t.n_nodes, dtype=torch.float64, device=dev) for t in self.targets]
+        if want_b and bs is None:
+            bs = [torch.empty(t.n_nodes, dtype=torch.float64, device=dev) for t in self.targets]
+        f64 = (torch.float64,)
+        xp = [_device_ptr(x, "x", f64) for x in xs]
+        bp = [_device_ptr(b, "b", f64) for b in bs] if want_b else None
+        st, reps, sts = ft_batch_run(self.handle, SolveCfg(rtol, max_iter), xp, bp, current_stream())
+        return xs, bs, reps, sts, st
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ft_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

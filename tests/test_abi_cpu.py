@@ -96,6 +96,10 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.ft_source_create_p1(2, 10, fake, 4, fake, 0, fake, None, None, ctypes.byref(h)) == ft.FT_E_ARG
     assert lib.ft_source_eval(None, 10, fake, 10, 0, fake, 10, None, None) == ft.FT_E_ARG
     assert lib.ft_source_eval_queries(None, 4, 10, fake, 10, 0, fake, 10, None, None) == ft.FT_E_ARG
+    assert lib.ft_batch_create(0, None, None, None, 0, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert lib.ft_batch_create(1, None, None, None, 0, None, None) == ft.FT_E_ARG
+    assert lib.ft_batch_run(None, None, None, None, None, None, None) == ft.FT_E_ARG
+    assert lib.ft_batch_destroy(None) == ft.FT_OK
     assert lib.ft_source_get_info(None, None) == ft.FT_E_ARG
     assert lib.ft_target_destroy(None) == ft.FT_OK
     assert lib.ft_source_destroy(None) == ft.FT_OK

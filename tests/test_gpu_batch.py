@@ -1,0 +1,124 @@
+"""GPU parity of batched transfers (ft_batch_create / ft_batch_run).
+
+A small uneven batch (2D and 3D targets of different sizes, N from 16 to 256)
+is checked transfer by transfer against the FP64 oracle (load vector and
+solution within 1e-12 relative L2), against the single-transfer fused route
+(same samples and element sums: load vectors agree to rounding of the
+control product), and, captured as a graph, replay by replay against the
+eager run (bitwise).
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import log, oracle_transfer, rel_l2
+from paper_2603_00538_amd import ft
+from workloads import fields, meshes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SEED = 0x0F7A5EED000000B0
+
+
+def _items():
+    """(target mesh, source mesh, source values, N) of an uneven batch."""
+    out = []
+    specs = [
+        (meshes.delaunay_tri_mesh(12, 0.3, 41), meshes.delaunay_tri_mesh(17, 0.3, 42), "front_2d", 32),
+        (meshes.structured_tri_mesh(15, 0.2, 43), meshes.structured_tri_mesh(25, 0.2, 44), "smooth_2d", 64),
+        (meshes.kuhn_tet_mesh(5, 0.08, 45), meshes.kuhn_tet_mesh(7, 0.08, 46), "gaussian_bumps_3d", 16),
+        (meshes.structured_tri_mesh(10, 0.2, 47), meshes.structured_tri_mesh(18, 0.2, 48), "front_2d", 128),
+        (meshes.kuhn_tet_mesh(6, 0.08, 49), meshes.kuhn_tet_mesh(9, 0.08, 50), "gaussian_bumps_3d", 256),
+        (meshes.delaunay_tri_mesh(9, 0.3, 51), meshes.delaunay_tri_mesh(13, 0.3, 52), "smooth_2d", 20),
+    ]
+    for tm, sm, fname, N in specs:
+        out.append((tm, sm, fields.evaluate(fname, np, sm[0]), N))
+    return out
+
+
+@pytest.fixture(scope="module")
+def batch_case():
+    items = _items()
+    targets = [ft.Target(*tm) for tm, _, _, _ in items]
+    sources = [ft.Source(*sm, sv) for _, sm, sv, _ in items]
+    cfgs = [ft.SampleCfg(N, 1, 1.0, SEED, k, ft.FT_F64) for k, (_, _, _, N) in enumerate(items)]
+    log("batch: eager run")
+    B = ft.Batch(targets, sources, cfgs)
+    xs, bs, reps, sts, st = B.run(rtol=1e-14, max_iter=80)
+    torch.cuda.synchronize()
+    eager = ([x.clone() for x in xs], [b.clone() for b in bs], reps, sts, st)
+    yield items, targets, sources, cfgs, eager
+    B.close()
+    for t in targets:
+        t.close()
+    for s in sources:
+        s.close()
+
+
+def test_batch_matches_oracle(batch_case):
+    items, targets, sources, cfgs, (xs, bs, reps, sts, st) = batch_case
+    assert st == ft.FT_OK and all(s == ft.FT_OK for s in sts)
+    for k, (tm, sm, sv, N) in enumerate(items):
+        o = oracle_transfer(tm, sm, sv, N, 1.0, SEED, k)
+        eb = rel_l2(bs[k].cpu().numpy(), o["b"][0])
+        ex = rel_l2(xs[k].cpu().numpy(), o["x"][0])
+        log(f"transfer {k}: dim {tm[0].shape[1]} E {tm[1].shape[0]} N {N}: b {eb:.2e} x {ex:.2e} "
+            f"iters {reps[k]['iters']}")
+        assert eb < 1e-12 and ex < 1e-12
+        assert reps[k]["cons_defect"] < 1e-13
+        assert abs(reps[k]["sum_b"] - o["report"][0]["sum_b"]) <= 1e-13 * abs(o["report"][0]["sum_b"])
+
+
+def test_batch_matches_single_route(batch_case):
+    items, targets, sources, cfgs, (xs, bs, reps, sts, st) = batch_case
+    for k, (T, S, cfg) in enumerate(zip(targets, sources, cfgs)):
+        T.transfer_from(S, cfg)
+        r = T.project(1, rtol=1e-14)
+        b1 = r.b[0].cpu().numpy()
+        x1 = r.x[0].cpu().numpy()
+        assert rel_l2(bs[k].cpu().numpy(), b1) < 1e-15
+        assert rel_l2(xs[k].cpu().numpy(), x1) < 1e-13
+
+
+def test_batch_graph_replays_match_eager(batch_case):
+    items, targets, sources, cfgs, (xs, bs, reps, sts, st) = batch_case
+    G = ft.Batch(targets, sources, cfgs, graph=True)
+    for rep in range(3):
+        gx, gb, greps, gsts, gst = G.run(rtol=1e-14, max_iter=80)
+        torch.cuda.synchronize()
+        for k in range(len(items)):
+            assert torch.equal(gx[k], xs[k]), (rep, k)
+            assert torch.equal(gb[k], bs[k]), (rep, k)
+            assert greps[k]["iters"] == reps[k]["iters"]
+        # eager work of the program between replays
+        targets[0].transfer_from(sources[0], cfgs[0])
+        targets[0].project(1)
+        z = torch.ones(1000, device="cuda").cumsum(0)
+        torch.cuda.synchronize()
+        assert float(z[-1]) == 1000.0
+    G.close()
+
+
+def test_batch_iteration_cap_reports_noconv(batch_case):
+    items, targets, sources, cfgs, _ = batch_case
+    B = ft.Batch(targets, sources, cfgs)
+    xs, bs, reps, sts, st = B.run(rtol=1e-14, max_iter=2)
+    assert st == ft.FT_E_NOCONV
+    assert all(s == ft.FT_E_NOCONV for s in sts)
+    xs, bs, reps, sts, st = B.run(rtol=1e-14, max_iter=80)
+    assert st == ft.FT_OK
+    B.close()
+
+
+def test_batch_rejects_bad_configurations(batch_case):
+    items, targets, sources, cfgs, _ = batch_case
+    with pytest.raises(ft.FtError) as e:
+        ft.Batch([targets[0], targets[0]], [sources[0], sources[0]], [cfgs[0], cfgs[0]])
+    assert e.value.status == ft.FT_E_ARG
+    bad = ft.SampleCfg(cfgs[0].samples_per_elem, 1, 1.0, SEED, 0, ft.FT_F32)
+    with pytest.raises(ft.FtError) as e:
+        ft.Batch([targets[0]], [sources[0]], [bad])
+    assert e.value.status == ft.FT_E_UNSUPPORTED
+    with pytest.raises(ft.FtError) as e:
+        ft.Batch([targets[0]], [sources[2]], [cfgs[0]])   # 2D target, 3D source
+    assert e.value.status == ft.FT_E_ARG

@@ -16,6 +16,14 @@ tet3d_1m_64f            3    Kuhn 56^3 nodes     998,250    Kuhn 88^3 nodes     
 
 Seeds: target jitter 11, source jitter 12, field parameters 13, Philox key
 ``0x0F7A5EED00000000 + index``.
+
+Batch workload (``batch_items``): 256 transfers whose target sizes are
+log-uniform in [1e3, 5e5] elements, 2D (structured triangles) or 3D (Kuhn
+tetrahedra) by a fair coin, each with its own source mesh 2-4 times finer
+(element count), its own smooth field 1 + 0.5 sum_q a_q cos(2 pi k_q.x + phi_q)
+(4 modes, k_q in {0,1,2}^d without 0, a_q ~ N(0,1), phi_q ~ U[0, 2 pi)) and N
+drawn from {32, 64, 128, 256}.  Seed 14; Philox key base + 5, stream id =
+transfer index.
 """
 from __future__ import annotations
 
@@ -102,3 +110,56 @@ def scaled(w: Workload, target_k: int, source_k: int, samples_per_elem: int | No
         MeshSpec(w.source.kind, source_k, w.source.jitter, w.source.seed),
         w.field, samples_per_elem or w.samples_per_elem, w.n_fields, w.alpha, w.index,
         (0, 0, 0), w.rtol)
+
+
+@dataclass(frozen=True)
+class BatchItem:
+    dim: int
+    target: MeshSpec
+    source: MeshSpec
+    kvec: tuple          # (4, dim) integer wave vectors
+    amp: tuple           # (4,)
+    phase: tuple         # (4,)
+    samples_per_elem: int
+    stream_id: int
+
+    def field(self, xp, coords):
+        """Nodal values (1, n) of this transfer's field at coords (n, dim)."""
+        out = 1.0 + 0.0 * coords[:, 0]
+        for q in range(len(self.amp)):
+            arg = 2.0 * np.pi * sum(self.kvec[q][c] * coords[:, c] for c in range(self.dim)) + self.phase[q]
+            out = out + 0.5 * self.amp[q] * xp.cos(arg)
+        return out[None, :]
+
+
+BATCH_PHILOX_SEED = PHILOX_SEED_BASE + 5
+
+
+def batch_items(count: int = 256, seed: int = 14, e_min: float = 1e3, e_max: float = 5e5):
+    """The uneven batch: see the module docstring."""
+    rng = np.random.default_rng(seed)
+    items = []
+    for k in range(count):
+        E = float(np.exp(rng.uniform(np.log(e_min), np.log(e_max))))
+        dim = 2 if rng.random() < 0.5 else 3
+        ratio = int(rng.integers(2, 5))
+        N = int(rng.choice([32, 64, 128, 256]))
+        kv = []
+        while len(kv) < 4:
+            v = tuple(int(c) for c in rng.integers(0, 3, size=dim))
+            if any(v):
+                kv.append(v)
+        amp = tuple(float(a) for a in rng.standard_normal(4))
+        phase = tuple(float(f) for f in rng.uniform(0.0, 2.0 * np.pi, 4))
+        if dim == 2:
+            kt = max(3, int(round(np.sqrt(E / 2.0))) + 1)
+            ks = max(3, int(round(np.sqrt(ratio * E / 2.0))) + 1)
+            tgt = MeshSpec("structured_tri", kt, 0.2, 1000 + k)
+            src = MeshSpec("structured_tri", ks, 0.2, 2000 + k)
+        else:
+            kt = max(3, int(round((E / 6.0) ** (1.0 / 3.0))) + 1)
+            ks = max(3, int(round((ratio * E / 6.0) ** (1.0 / 3.0))) + 1)
+            tgt = MeshSpec("kuhn_tet", kt, 0.08, 1000 + k)
+            src = MeshSpec("kuhn_tet", ks, 0.08, 2000 + k)
+        items.append(BatchItem(dim, tgt, src, tuple(kv), amp, phase, N, k))
+    return items
