@@ -46,6 +46,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def source_mesh_bytes(dim, F, src):
+    """The built-in source read once: element records (128 / 256 B), binary32
+    boxes, bin lists; connectivity and nodal values only for F > 1 (one field's
+    vertex values sit in the records)."""
+    rec, box = (128, 32) if dim == 2 else (256, 24)
+    b = src["E"] * (rec + box) + src["n_reg"] * 4 + src["nbins"] * 8
+    if F > 1:
+        b += src["E"] * (dim + 1) * 4 + src["n"] * F * 8
+    return b
+
+
 def algorithmic_bytes(phase, dim, E, n, N, F, p, src=None):
     """Compulsory HBM bytes of one launch of a phase (measurement)."""
     Q = n + E * N
@@ -54,16 +65,11 @@ def algorithmic_bytes(phase, dim, E, n, N, F, p, src=None):
         return Q * dim * p + E * ((dim + 1) * 4 + (dim + 1) * dim * 8) + n * dim * 8
     if phase == "eval":
         # read d coordinates and write F values per query; read the source mesh once
-        rs = 8 if dim == 2 else 16
-        mesh = src["E"] * (rs * 8 + 2 * dim * 4 + (dim + 1) * 4) + src["n_reg"] * 4 + src["nbins"] * 8 \
-            + src["n"] * F * 8
-        return Q * (dim + F) * p + mesh
+        return Q * (dim + F) * p + source_mesh_bytes(dim, F, src)
     if phase == "fused":
         # per element: connectivity, vertex coordinates, control values, measure, beta; the source mesh once
-        rs = 8 if dim == 2 else 16
-        mesh = src["E"] * (rs * 8 + 2 * dim * 4 + (dim + 1) * 4) + src["n_reg"] * 4 + src["nbins"] * 8 \
-            + src["n"] * F * 8
-        return E * ((dim + 1) * 4 + (dim + 1) * dim * 8 + (dim + 1) * F * 8 + 8 + (dim + 1) * F * 8) + mesh
+        return E * ((dim + 1) * 4 + (dim + 1) * dim * 8 + (dim + 1) * F * 8 + 8 + (dim + 1) * F * 8) \
+            + source_mesh_bytes(dim, F, src)
     if phase == "consume":
         # read F values per query; per element connectivity, measure and beta; node assembly
         return Q * F * p + E * ((dim + 1) * 4 + 8 + (dim + 1) * F * 8) + E * (dim + 1) * (4 + F * 8) + n * F * 16
@@ -165,6 +171,93 @@ def sequential_f64(T, w, tmesh, smesh, svals):
             "cg_iters_max": int(max(iters))}
 
 
+def bench_batch(args):
+    """The uneven batch: 256 built-in-source transfers (mixed 2D/3D, 1e3-5e5
+    elements, N in {32..256}) per ft_batch_run, captured as one graph."""
+    import numpy as np
+    import torch
+
+    from paper_2603_00538_amd import ft
+    from workloads import configs
+
+    items = configs.batch_items()
+    log(f"batch256: building {len(items)} mesh pairs")
+    t0 = time.perf_counter()
+    host = []
+    for it in items:
+        tc, tconn = it.target.build()
+        sc, sconn = it.source.build()
+        host.append((tc, tconn, sc, sconn, np.ascontiguousarray(it.field(np, sc))))
+    log(f"meshes built in {time.perf_counter() - t0:.1f} s")
+    torch.cuda.set_device(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    targets = [ft.Target(tc, tconn) for tc, tconn, _, _, _ in host]
+    sources = [ft.Source(sc, sconn, sv) for _, _, sc, sconn, sv in host]
+    cfgs = [ft.SampleCfg(it.samples_per_elem, 1, 1.0, configs.BATCH_PHILOX_SEED, it.stream_id, ft.FT_F64)
+            for it in items]
+    B = ft.Batch(targets, sources, cfgs, graph=True)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    E_tot = int(sum(t.n_elems for t in targets))
+    S_tot = int(sum(t.n_elems * it.samples_per_elem for t, it in zip(targets, items)))
+    xs = [torch.empty(t.n_nodes, dtype=torch.float64, device="cuda") for t in targets]
+    bs = [torch.empty(t.n_nodes, dtype=torch.float64, device="cuda") for t in targets]
+    max_iter = 60
+    for i in range(max(1, args.warmup)):
+        B.run(rtol=1e-14, max_iter=max_iter, xs=xs, bs=bs)
+        log(f"batch warmup {i + 1}")
+    torch.cuda.synchronize()
+    times = []
+    reps = sts = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, _, reps, sts, st = B.run(rtol=1e-14, max_iter=max_iter, xs=xs, bs=bs)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    wall = time.perf_counter() - t0
+    ms = wall * 1e3 / args.steps
+    src_bytes = 0
+    for S in sources:
+        si = S.info
+        src_bytes += source_mesh_bytes(si.dim, 1, {"E": si.n_elems, "n": si.n_nodes, "n_reg": si.n_registrations,
+                                                   "nbins": int(np.prod([si.bins[c] for c in range(si.dim)]))})
+    # per element: connectivity, vertex coordinates, control values, measure, beta
+    elem_bytes = sum(t.n_elems * ((t.dim + 1) * 4 + (t.dim + 1) * t.dim * 8 + (t.dim + 1) * 8 + 8 + (t.dim + 1) * 8)
+                     for t in targets)
+    abytes = src_bytes + elem_bytes
+    achieved = abytes / (float(np.mean(times)) * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": E_tot / (ms * 1e-3),
+        "unit": "target elements/s (aggregate over the batch)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch256", "transfers": len(items), "target_elements": E_tot, "samples": S_tot,
+                   "dims": {"2": sum(1 for it in items if it.dim == 2), "3": sum(1 for it in items if it.dim == 3)},
+                   "samples_per_elem": "per transfer from {32, 64, 128, 256}", "alpha": 1.0, "rtol": 1e-14,
+                   "cg_launches": max_iter, "graph": True},
+        "queries_per_s": S_tot / (ms * 1e-3),
+        "event_ms": float(np.mean(times)),
+        "setup_ms": setup_s * 1e3,
+        "cg_iters_max": int(max(r["iters"] for r in reps)),
+        "cons_defect_max": float(max(r["cons_defect"] for r in reps)),
+        "status": ft.STATUS_NAMES[st],
+        "roofline": {"bound": "hbm", "kernel": "ft_batch_run (whole graph)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": abytes, "avg_ms": float(np.mean(times))},
+    }
+    B.close()
+    for t in targets:
+        t.close()
+    for s_ in sources:
+        s_.close()
+    print(json.dumps(out), flush=True)
+
+
 def calibrate_copy(nbytes):
     """A plain device copy of known size, for scaling rocprof FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -211,6 +304,9 @@ def main():
     from paper_2603_00538_amd import ft
     from workloads import configs
 
+    if args.workload == "batch256":
+        bench_batch(args)
+        return
     w = configs.WORKLOADS[args.workload]
     log(f"workload {w.name}: building meshes")
     tmesh = configs.build_mesh(w.target)

@@ -4,7 +4,7 @@
 // sec. 4.1 last paragraph).  Built-in P1 sources, one field per transfer.
 //
 // Work lists built once at creation:
-//   node tiles     (transfer, 256 target nodes)      step 1, the control g
+//   node tiles     (transfer, 256 / 128 target nodes) step 1, the control g
 //   element tiles  (transfer, 64/G target elements)  steps 3-5, fused
 //   row tiles      (transfer, 256 rows)              steps 2, 6, 7 and the report
 // The node and element stages are persistent kernels: a grid sized to the
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchXfer* __restrict
     }
 }
 
-// step 1: g = f^s at the target nodes, 256 nodes per wavefront
+// step 1: g = f^s at the target nodes, 256 (2D) or 128 (3D) nodes per wavefront
 __global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles,
                                                      int64_t n_tiles) {
     const int64_t stride = int64_t(gridDim.x) * 4;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict
         if (tl.variant == 2)
             nood = eval_wave<2, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr);
         else
-            nood = eval_wave<3, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr);
+            nood = eval_wave<3, 2, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr);
         if (nood) atomicAdd(x.src_ood, (unsigned long long)nood);
     }
 }
@@ -471,7 +471,8 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
         x.alpha = c.alpha;
         x.key = SampleKey{uint32_t(c.seed & 0xFFFFFFFFu), uint32_t(c.seed >> 32), c.stream_id};
         for (int64_t v = 0; v < T->n; v += BT) row.push_back(Tile{k, T->dim, v});
-        for (int64_t v = 0; v < T->n; v += 256) node.push_back(Tile{k, T->dim, v});
+        const int node_tile = T->dim == 2 ? 256 : 128;   // points per wavefront of the node stage
+        for (int64_t v = 0; v < T->n; v += node_tile) node.push_back(Tile{k, T->dim, v});
         x.ntiles = int32_t(row.size()) - x.tile0;
         row0 += T->n;
         const int var = variant_of(c.samples_per_elem);

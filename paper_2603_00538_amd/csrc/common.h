@@ -163,6 +163,14 @@ __device__ __forceinline__ int uniform_int(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// A value known to be equal in every lane, moved to scalar registers.
+__device__ __forceinline__ double uniform_double(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(u));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(u >> 32));
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 }  // namespace ft
 
 // ---------------------------------------------------------------- handles
@@ -213,7 +221,6 @@ struct ft_source {
     double inv_h[3] = {1, 1, 1};// bins per unit length
     int64_t* bin_ptr = nullptr; // [nbins+1]
     int32_t* bin_elems = nullptr;
-    int32_t* bin_first = nullptr;   // [E][dim] first bin index per axis of each element's box
     int64_t n_reg = 0;
     unsigned long long* counters = nullptr;  // [0] out-of-domain points
     unsigned long long* h_counters = nullptr;

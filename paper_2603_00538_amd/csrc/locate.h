@@ -16,9 +16,9 @@
 //   - the element's box must meet the wave's box (and octagon, in 2D);
 //   - it is offered only in the first of the wave's bins it is registered in;
 //   - no barycentric coordinate may be below -1e-9 on the whole wave box.
-// Survivors write their absolute affine barycentric form to the wave's LDS
-// slots; every lane then tests its points against each survivor (broadcast
-// LDS reads, two candidates per step).  The selection test accepts an element
+// Each lane parks its candidate's absolute affine barycentric form in the
+// wave's LDS; every lane then tests its points against each survivor in lane
+// order (broadcast LDS reads).  The selection test accepts an element
 // once its min mu exceeds 1e-9, far above that form's rounding, so an
 // accepted element truly contains the point and is the unique winner.  Points
 // never accepted (within 1e-9 of a face, or outside) are re-searched in their
@@ -38,17 +38,27 @@ constexpr double kInsideTau = 1e-12;   // strictly inside (rule winner is unique
 constexpr double kFastTau = 1e-9;      // accepted by the fast selection test (absolute affine form)
 constexpr double kOutTol = -1e-10;
 
-// Record of element e, rec[e*RS ...] (doubles):
-//   [0, D)                 origin x0 (vertex 0)
-//   [D, D + D*D)           A, the inverse of J = [x1-x0 | ... | xd-x0] (row k gives mu_{k+1})
-//   [AF, AF + D + 1)       constants c_k of mu_k(x) = c_k + g_k . x in absolute coordinates
-//   [AF + D + 1, ...)      gradients g_k (D each), k = 0..D
-// The absolute affine form selects the element; the origin form gives the
-// barycentrics used to interpolate.
+// Record of element e, rec[e*RS ...] (doubles; 128 B in 2D, 256 B in 3D):
+//   [0, D)                    origin x0 (vertex 0)
+//   [AF, AF + D + 1)          constants c_k of mu_k(x) = c_k + g_k . x, AF = D
+//   [AF + D + 1, BF)          gradients g_k (D each), k = 0..D; g_1..g_D are the
+//                             rows of the inverse of J = [x1-x0 | ... | xd-x0]
+//   [BF, VAL)                 the element's first bin per axis (int32 each)
+//   [VAL, VAL + D + 1)        vertex values of a one-field source (else zero)
+// The absolute affine form [c | g] selects the element (one contiguous
+// block the cull loads with the first-bin slot); the origin form
+// mu_{k+1} = g_{k+1} . (x - x0) gives the barycentrics used to interpolate,
+// and for one field the vertex values sit in the same record.
 template <int D>
 struct RecSize { static constexpr int value = D == 2 ? 16 : 32; };
 template <int D>
-struct RecAffine { static constexpr int value = D + D * D; };
+struct RecAffine { static constexpr int value = D; };
+template <int D>
+struct RecBinFirst { static constexpr int value = D + (D + 1) * (D + 1); };
+template <int D>
+struct RecValues { static constexpr int value = RecBinFirst<D>::value + (D == 2 ? 1 : 2); };
+static_assert(RecValues<2>::value + 3 <= RecSize<2>::value, "2D record overflow");
+static_assert(RecValues<3>::value + 4 <= RecSize<3>::value, "3D record overflow");
 
 // floats per element in the box array: min/max per axis, plus (2D) the
 // ranges of x+y and x-y
@@ -87,7 +97,6 @@ struct SrcView {
     const double* values;
     const int64_t* bin_ptr;
     const int32_t* bin_elems;
-    const int32_t* bin_first;
     int64_t n;
     int F;
     GridView g;
@@ -107,7 +116,7 @@ __device__ __forceinline__ double barycentric(const double* __restrict__ r, cons
     for (int k = 0; k < D; ++k) {
         double s = 0.0;
 #pragma unroll
-        for (int c = 0; c < D; ++c) s = fma(r[D + k * D + c], d[c], s);
+        for (int c = 0; c < D; ++c) s = fma(r[RecAffine<D>::value + D + 1 + (k + 1) * D + c], d[c], s);
         mu[k + 1] = s;
         mu[0] -= s;
         mn = fmin(mn, s);
@@ -127,28 +136,10 @@ __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int
     }
 }
 
-// Conservative test whether element r can contain a point of the box
+// Conservative test whether an element can contain a point of the box
 // [lo, hi]: false only if some barycentric coordinate is below -1e-9 on the
-// whole box (a linear function's maximum over a box sits at a corner).
-template <int D>
-__device__ __forceinline__ bool box_may_meet(const double* __restrict__ r, const double (&lo)[D],
-                                             const double (&hi)[D]) {
-    constexpr int AF = RecAffine<D>::value;
-    bool meet = true;
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        double mx = r[AF + k];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            const double gk = r[AF + D + 1 + k * D + c];
-            mx += fmax(gk * lo[c], gk * hi[c]);
-        }
-        meet &= mx >= -1e-9;
-    }
-    return meet;
-}
-
-// The same test on the affine form held in registers: af = [c_0..c_D, g_0, ..., g_D].
+// whole box (a linear function's maximum over a box sits at a corner).  The
+// affine form is held in registers: af = [c_0..c_D, g_0, ..., g_D].
 template <int D>
 __device__ __forceinline__ bool box_may_meet_af(const double (&af)[(D + 1) * (D + 1)], const double (&lo)[D],
                                                 const double (&hi)[D]) {
@@ -233,8 +224,8 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 lo = fmin(lo, p[q][c]);
                 hi = fmax(hi, p[q][c]);
             }
-        wlo[c] = wave_min(lo);
-        whi[c] = wave_max(hi);
+        wlo[c] = uniform_double(wave_min(lo));
+        whi[c] = uniform_double(wave_max(hi));
         b0[c] = uniform_int(bin_of(wlo[c], c, S.g));
         b1[c] = uniform_int(bin_of(whi[c], c, S.g));
         span *= b1[c] - b0[c] + 1;
@@ -276,7 +267,6 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         // these bins are then culled 64 at a time in one flat sequence.
         constexpr int AL = (D + 1) * (D + 1);   // affine form: D+1 constants, (D+1) x D gradients
         __shared__ double c_af[4][64 * AL];     // per wave of a 256-thread block
-        __shared__ int c_id[4][64];
         const int w = (threadIdx.x >> 6) & 3;
         const int wx = b1[0] - b0[0] + 1, wy = b1[1] - b0[1] + 1;
         int cb[3] = {0, 0, 0};
@@ -306,51 +296,43 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             bool ov = false;
             double af[AL];
             if (sl < total) {
+                // box and record load together (one round trip)
                 cid = S.bin_elems[st_i + (sl - excl_i)];
                 const float* bx_ = S.box + int64_t(cid) * BS;
+                const double* r = S.rec + int64_t(cid) * RS;
+#pragma unroll
+                for (int m = 0; m < AL; ++m) af[m] = r[RecAffine<D>::value + m];
+                const int32_t* first = reinterpret_cast<const int32_t*>(r + RecBinFirst<D>::value);
                 ov = true;
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
                     ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
                     // offer each element once per wave: in the first of the wave's bins it is in
-                    ov &= max(S.bin_first[int64_t(cid) * D + c], b0[c]) == cur[c];
+                    ov &= max(first[c], b0[c]) == cur[c];
                 }
                 if constexpr (D == 2)
                     ov &= (bx_[4] <= fu[1]) & (bx_[6] >= fu[0]) & (bx_[5] <= fu[3]) & (bx_[7] >= fu[2]);
-                if (ov) {
-                    const double* r = S.rec + int64_t(cid) * RS + RecAffine<D>::value;
-#pragma unroll
-                    for (int m = 0; m < AL; ++m) af[m] = r[m];
-                    ov = box_may_meet_af<D>(af, wlo, whi);
-                }
+                ov = ov && box_may_meet_af<D>(af, wlo, whi);
             }
-            // survivors' affine forms go to this wave's LDS slots, in lane order
-            const uint64_t mask = __ballot(ov);
-            if (ov) {
-                const int slot = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u)));
+            // every lane parks its candidate's affine form in its own LDS slot; the
+            // survivors are then read back in lane order
+            if (sl < total) {
 #pragma unroll
-                for (int m = 0; m < AL; ++m) c_af[w][slot * AL + m] = af[m];
-                c_id[w][slot] = cid;
+                for (int m = 0; m < AL; ++m) c_af[w][lane * AL + m] = af[m];
             }
+            uint64_t mask = __ballot(ov);
             __builtin_amdgcn_wave_barrier();
-            const int nc = __popcll((unsigned long long)mask);
-            // two candidates per step; a repeat of the last one changes nothing
-            // (the first strictly larger value wins)
-            for (int c = 0; c < nc; c += 2) {
-                const int c2 = c + 1 < nc ? c + 1 : c;
-                const double* a1 = &c_af[w][c * AL];
-                const double* a2 = &c_af[w][c2 * AL];
-                const int e1 = c_id[w][c], e2 = c_id[w][c2];
+            while (mask) {
+                const int l1 = __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                const int e1 = read_lane(cid, l1);
+                const double* a1 = &c_af[w][l1 * AL];
                 bool done = true;
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const double m1 = affine_min_mu_lds<D>(a1, p[q]);
-                    const double m2 = affine_min_mu_lds<D>(a2, p[q]);
                     bid[q] = m1 > best[q] ? e1 : bid[q];
                     best[q] = fmax(best[q], m1);
-                    bid[q] = m2 > best[q] ? e2 : bid[q];
-                    best[q] = fmax(best[q], m2);
                     done &= best[q] > kFastTau;
                 }
                 if (__all(done)) {
@@ -394,8 +376,14 @@ __device__ __forceinline__ void winner_mu(const SrcView& S, int bid, const doubl
 template <int D>
 __device__ __forceinline__ double p1_value(const SrcView& S, int bid, const double (&bmu)[D + 1], int f) {
     if (bid == INT_MAX) return 0.0;
-    const double* Fv = S.values + int64_t(f) * S.n;
     double y = 0.0;
+    if (S.F == 1) {   // vertex values in the element's record
+        const double* rv = S.rec + int64_t(bid) * RecSize<D>::value + RecValues<D>::value;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) y = fma(bmu[k], rv[k], y);
+        return y;
+    }
+    const double* Fv = S.values + int64_t(f) * S.n;
 #pragma unroll
     for (int k = 0; k <= D; ++k) y = fma(bmu[k], Fv[S.conn[int64_t(bid) * (D + 1) + k]], y);
     return y;

@@ -7,10 +7,12 @@
 //
 // Localization rule and search: see locate.h.
 //
-// Layout: every source element e has a record rec[e*RS ...] = (x0, A) with A
-// the inverse of J = [x1-x0 | ... | xd-x0], so mu_{k+1} = sum_c A[k][c] (x-x0)_c
-// and mu_0 = 1 - sum mu; plus an outward-rounded binary32 bounding box.  Bins
-// hold the ids of every element whose box overlaps them (CSR, ascending ids).
+// Layout: every source element e has a record rec[e*RS ...] holding its
+// origin, its barycentric map (absolute affine form, whose gradients g_1..g_D
+// are the rows of the inverse of J = [x1-x0 | ... | xd-x0]), its first bin per
+// axis and, for one field, its vertex values (see locate.h); plus an
+// outward-rounded binary32 bounding box.  Bins hold the ids of every element
+// whose box overlaps them (CSR, ascending ids).
 
 #include <algorithm>
 #include <cfloat>
@@ -23,7 +25,8 @@ namespace ft {
 
 template <int D>
 __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
-                           double* __restrict__ rec, float* __restrict__ box, unsigned long long* __restrict__ flags) {
+                           const double* __restrict__ values, int F, double* __restrict__ rec,
+                           float* __restrict__ box, unsigned long long* __restrict__ flags) {
     constexpr int RS = RecSize<D>::value;
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= E) return;
@@ -85,16 +88,12 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
     if (!(fabs(det) > 1e-12 * hd)) atomicAdd(&flags[1], 1ull);
     double* r = rec + e * RS;
 #pragma unroll
+    for (int i = 0; i < RS; ++i) r[i] = 0.0;
+#pragma unroll
     for (int c = 0; c < D; ++c) r[c] = x[0][c];
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-#pragma unroll
-        for (int c = 0; c < D; ++c) r[D + k * D + c] = A[k][c];
-    // absolute affine form: mu_{k+1}(x) = A[k] . x - A[k] . x0, mu_0 = 1 - sum
+    // absolute affine form: g_{k+1} = A[k], c_{k+1} = -A[k] . x0; g_0 = -sum g, c_0 = 1 - sum c
     constexpr int AF = RecAffine<D>::value;
     double csum = 0.0;
-#pragma unroll
-    for (int c = 0; c < D; ++c) r[AF + D + 1 + c] = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         double ck = 0.0;
@@ -108,8 +107,9 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
         csum += ck;
     }
     r[AF] = 1.0 - csum;
+    if (F == 1)
 #pragma unroll
-    for (int i = AF + (D + 1) * (D + 1); i < RS; ++i) r[i] = 0.0;
+        for (int k = 0; k <= D; ++k) r[RecValues<D>::value + k] = values[v[k]];
     constexpr int BS = BoxSize<D>::value;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
@@ -162,14 +162,17 @@ __device__ __forceinline__ void elem_bin_range(const double* __restrict__ X, int
 template <int D, bool FILL>
 __global__ void k_src_register(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
                                GridView g, int32_t* __restrict__ cnt, const int64_t* __restrict__ ptr,
-                               int32_t* __restrict__ elems, int32_t* __restrict__ first) {
+                               int32_t* __restrict__ elems, double* __restrict__ rec) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= E) return;
     int b0[3], b1[3];
     elem_bin_range<D>(X, n, conn, e, g, b0, b1);
-    if (!FILL)
+    if (!FILL) {
+        // first bin per axis, in the element's record
+        int32_t* first = reinterpret_cast<int32_t*>(rec + e * RecSize<D>::value + RecBinFirst<D>::value);
 #pragma unroll
-        for (int c = 0; c < D; ++c) first[e * D + c] = b0[c];
+        for (int c = 0; c < D; ++c) first[c] = b0[c];
+    }
     for (int bz = b0[2]; bz <= b1[2]; ++bz)
         for (int by = b0[1]; by <= b1[1]; ++by)
             for (int bx = b0[0]; bx <= b1[0]; ++bx) {
@@ -272,7 +275,7 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     guard.add((void**)&tmp);
     FT_TRY(dev_alloc_n(&flags, 4));
     FT_TRY_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned long long), s));
-    k_src_geom<D><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, S->rec, S->box, flags);
+    k_src_geom<D><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, S->values, S->F, S->rec, S->box, flags);
     const int mmb = 256;
     FT_TRY(dev_alloc_n(&mm, size_t(mmb) * D * 2));
     k_minmax<<<mmb, 256, 0, s>>>(S->coords, n, D, mm);
@@ -329,9 +332,8 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     FT_TRY(dev_alloc_n(&tmp, size_t(scan_tmp_elems(nbins))));
     FT_TRY(dev_alloc_n(&S->bin_ptr, size_t(nbins + 1)));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
-    FT_TRY(dev_alloc_n(&S->bin_first, size_t(E) * D));
     k_src_register<D, false><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, nullptr, nullptr,
-                                                           S->bin_first);
+                                                           S->rec);
     FT_TRY(exclusive_scan(cnt, S->bin_ptr, nbins, tmp, s));
     int64_t nreg = 0;
     FT_TRY_HIP(hipMemcpyAsync(&nreg, S->bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -353,7 +355,7 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
 }
 
 SrcView source_view(const ft_source* S) {
-    SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->bin_first, S->n, S->F, {}};
+    SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
         v.g.lo[c] = S->lo[c];
@@ -365,7 +367,9 @@ SrcView source_view(const ft_source* S) {
 template <int D>
 static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec,
                              void* out, int64_t ld_out, int32_t* ids, hipStream_t s) {
-    constexpr int P = 4;   // points per lane: one wave covers 256 consecutive points
+    // points per lane: a wave covers 256 consecutive points in 2D, 128 in 3D
+    // (one target element's samples at N = 256 / 128; fewer registers in 3D)
+    constexpr int P = D == 2 ? 4 : 2;
     constexpr int64_t WP = 64 * P;
     const SrcView v = source_view(S);
     const int64_t waves = (head + WP - 1) / WP + (npts - head + WP - 1) / WP;
@@ -393,7 +397,6 @@ ft_status source_release(ft_source* S) {
     dev_free(S->box);
     dev_free(S->bin_ptr);
     dev_free(S->bin_elems);
-    dev_free(S->bin_first);
     dev_free(S->counters);
     if (S->h_counters) (void)hipHostFree(S->h_counters);
     return FT_OK;
