@@ -83,7 +83,10 @@ typedef struct {
 /* Mass solve configuration (sec. 4.1 step 7). */
 typedef struct {
     double  rtol;               /* stop when ||b - M x||_2 <= rtol ||b||_2 (recurrence residual)   */
-    int32_t max_iter;           /* Jacobi-PCG iteration cap per field                              */
+    int32_t max_iter;           /* Jacobi-PCG iteration cap per field (per refinement step)        */
+    int32_t refine_steps;       /* 0: binary64 PCG.  k > 0 (one field): up to k steps of binary64  */
+                                /* residual + iterative refinement around a binary32 inner PCG     */
+                                /* (binary64 dot products), stopping on the true residual          */
 } ft_solve_cfg;
 
 /* Per-field result of ft_project (conservation: sec. 2 Eq. conservation, App. B). */
@@ -282,7 +285,8 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
                           const ft_sample_cfg* cfgs, int32_t flags, hipStream_t stream, ft_batch** out);
 
 /*
- * ft_batch_run - sec. 4.1 steps 1-7 for every transfer of the batch.
+ * ft_batch_run - sec. 4.1 steps 1-7 for every transfer of the batch
+ * (binary64 solve: cfg->refine_steps must be 0).
  *   x        host array [count] of device pointers: x[k] binary64 [n_nodes of target k]
  *   b        host array [count] of device pointers (load vectors) or null entries, or null
  *   reports  host [count], one report per transfer

@@ -30,7 +30,7 @@ void batch_mark_consumed(ft_batch* b);
 static void target_release(ft_target* T) {
     void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
                   T->beta, T->g, T->bres, T->r, T->z, T->p, T->q, T->y, T->b, T->scal, T->partials,
-                  T->counters};
+                  T->counters, T->val32, T->diag32, T->w32, T->scal32};
     for (void* p : ps) dev_free(p);
     if (T->h_scal) (void)hipHostFree(T->h_scal);
 }
@@ -214,6 +214,7 @@ ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b
     FT_ARG_CHECK(t && cfg && x && rep, "null argument");
     FT_ARG_CHECK(cfg->rtol >= 0.0 && std::isfinite(cfg->rtol), "rtol must be finite and >= 0");
     FT_ARG_CHECK(cfg->max_iter >= 0, "max_iter must be >= 0");
+    FT_ARG_CHECK(cfg->refine_steps >= 0 && cfg->refine_steps <= 100, "refine_steps must lie in [0, 100]");
     if (!t->consumed) {
         set_error("ft_project needs a prior ft_consume_queries");
         return FT_E_ORDER;
@@ -265,6 +266,7 @@ ft_status ft_batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, d
     FT_ARG_CHECK(b && cfg && x && reports, "null argument");
     FT_ARG_CHECK(cfg->rtol >= 0.0 && std::isfinite(cfg->rtol), "rtol must be finite and >= 0");
     FT_ARG_CHECK(cfg->max_iter >= 0 && cfg->max_iter <= 100000, "max_iter must lie in [0, 100000]");
+    FT_ARG_CHECK(cfg->refine_steps == 0, "batches solve in binary64 (refine_steps must be 0)");
     const ft_status st = batch_run(b, cfg, x, bvec, reports, status, stream);
     if (st == FT_OK || st == FT_E_NOCONV || st == FT_E_NONFINITE) batch_mark_consumed(b);
     return st;

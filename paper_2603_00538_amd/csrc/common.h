@@ -201,6 +201,11 @@ struct ft_target {
     double* partials = nullptr;           // per-block partial sums
     unsigned long long* counters = nullptr;  // [0] non-finite values seen by consume
     double* h_scal = nullptr;             // pinned host mirror
+    // mixed-precision solve (binary32 inner PCG), allocated on first use
+    float* val32 = nullptr;               // [nnz] binary32 copy of M
+    float* diag32 = nullptr;              // [n]
+    float* w32 = nullptr;                 // [6n] r, z, p (2n), q, d in binary32
+    double* scal32 = nullptr;             // inner-solve scalars
     int reduce_blocks = 0;
     // call-order state
     bool consumed = false;

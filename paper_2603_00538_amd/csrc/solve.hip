@@ -23,63 +23,9 @@
 #include <algorithm>
 #include <cmath>
 
-#include "common.h"
+#include "solve_common.h"
 
 namespace ft {
-
-constexpr int RB = 256;            // threads per block in the solver kernels
-constexpr int MAX_RBLOCKS = 512;   // grid size cap (grid-stride loops beyond it)
-
-// partial-sum slots (each nb doubles) and device scalar slots
-enum { P_BB = 0, P_SB, P_RZ, P_RR, P_PQ, P_TRR, P_MX, P_COUNT };
-enum { S_RHO0 = 0, S_RHO1, S_TOL2, S_DONE, S_ITERS, S_BB, S_SUMB, S_TRR, S_INTX, S_COUNT };
-
-__device__ __forceinline__ double block_total(double v) {
-    __shared__ double sm[RB / 64];
-    __shared__ double tot;
-    v = wave_sum_xor(v, 64);
-    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = sm[0];
-        for (int k = 1; k < RB / 64; ++k) s += sm[k];
-        tot = s;
-    }
-    __syncthreads();
-    const double t = tot;
-    __syncthreads();
-    return t;
-}
-
-// Sum of the nb partials of one slot, in block order (same value in every block).
-__device__ __forceinline__ double partial_total(const double* __restrict__ part, int slot, int nb) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += RB) s += part[slot * nb + b];
-    return block_total(s);
-}
-
-__device__ __forceinline__ void write_partial(double* __restrict__ part, int slot, double v) {
-    const double t = block_total(v);
-    if (threadIdx.x == 0) part[slot * gridDim.x + blockIdx.x] = t;
-}
-
-__device__ __forceinline__ double csr_row(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                          const double* __restrict__ val, const double* __restrict__ x, int64_t i) {
-    double s = 0.0;
-    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) s = fma(val[k], x[col[k]], s);
-    return s;
-}
-
-struct Mat {
-    const int64_t* rowptr;
-    const int32_t* col;
-    const double* val;
-    const double* diag;
-    const double* lumped;
-    int64_t n;
-};
-
-#define FOR_ROW(i) for (int64_t i = int64_t(blockIdx.x) * RB + threadIdx.x; i < A.n; i += int64_t(gridDim.x) * RB)
 
 // b = alpha M g + b_res; partials of ||b||^2 and sum b.
 __global__ __launch_bounds__(RB) void k_rhs(Mat A, const double* __restrict__ g, const double* __restrict__ bres,
@@ -245,8 +191,264 @@ ft_status solver_alloc(ft_target* T, hipStream_t s) {
 ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep,
                         hipStream_t s);
 
+// ---------------------------------------------------------------- mixed precision
+// Binary64 residual and iterative refinement around a binary32 inner solve
+// (sec. 4.1 step 7 in the binary32 form).  Outer: r = b_res - M y in binary64;
+// stop when ||r|| <= rtol ||b|| (the true residual of M x = b, x = alpha g + y).
+// Inner: Jacobi-PCG on M d = r with binary32 matrix values and vectors and
+// binary64 accumulation of every dot product, to ||r - M d|| <= 1e-6 ||r||
+// (binary32 carries about seven digits and D^-1 M is well conditioned, so each
+// step gains about six); then y += d.
+constexpr double kInnerRtol = 1e-6;
+enum { M_RHO0 = 0, M_RHO1, M_TOL2, M_DONE, M_ITERS, M_COUNT };
+
+struct Mat32 {
+    const int64_t* rowptr;
+    const int32_t* col;
+    const float* val;
+    const float* diag;
+    int64_t n;
+};
+
+__global__ void k_to_f32(const double* __restrict__ src, int64_t n, float* __restrict__ dst) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = float(src[i]);
+}
+
+// y = 0, r = b_res; partial of ||r||^2
+__global__ __launch_bounds__(RB) void k_mx_start(Mat A, const double* __restrict__ bres, double* __restrict__ y,
+                                                 double* __restrict__ r, double* __restrict__ part) {
+    double rr = 0.0;
+    FOR_ROW(i) {
+        const double ri = bres[i];
+        y[i] = 0.0;
+        r[i] = ri;
+        rr = fma(ri, ri, rr);
+    }
+    write_partial(part, P_RR, rr);
+}
+
+// outer residual r = b_res - M y (binary64); partial of ||r||^2
+__global__ __launch_bounds__(RB) void k_mx_resid(Mat A, const double* __restrict__ bres, const double* __restrict__ y,
+                                                 double* __restrict__ r, double* __restrict__ part) {
+    double rr = 0.0;
+    FOR_ROW(i) {
+        const double ri = bres[i] - csr_row(A.rowptr, A.col, A.val, y, i);
+        r[i] = ri;
+        rr = fma(ri, ri, rr);
+    }
+    write_partial(part, P_RR, rr);
+}
+
+// one block: the outer totals (mode 0: also ||b||^2, sum b and the threshold)
+__global__ __launch_bounds__(RB) void k_mx_totals(int mode, int nb, double rtol2, const double* __restrict__ part,
+                                                  double* __restrict__ scal) {
+    const double rr = partial_total(part, P_RR, nb);
+    if (mode == 0) {
+        const double bb = partial_total(part, P_BB, nb);
+        const double sb = partial_total(part, P_SB, nb);
+        if (threadIdx.x == 0) {
+            scal[S_BB] = bb;
+            scal[S_SUMB] = sb;
+            scal[S_TOL2] = rtol2 * bb;
+        }
+    }
+    if (threadIdx.x == 0) scal[S_TRR] = rr;
+}
+
+// inner start: r32 = r, z32 = D^-1 r32, d = 0, p_old = 0; partials of r.z, r.r
+__global__ __launch_bounds__(RB) void k_m32_init(Mat32 A, const double* __restrict__ r64, float* __restrict__ r,
+                                                 float* __restrict__ z, float* __restrict__ d,
+                                                 float* __restrict__ p_old, double* __restrict__ part,
+                                                 double* __restrict__ sc) {
+    double rz = 0.0, rr = 0.0;
+    FOR_ROW(i) {
+        const float ri = float(r64[i]);
+        const float zi = ri / A.diag[i];
+        r[i] = ri;
+        z[i] = zi;
+        d[i] = 0.0f;
+        p_old[i] = 0.0f;
+        rz = fma(double(ri), double(zi), rz);
+        rr = fma(double(ri), double(ri), rr);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[M_DONE] = 0.0;
+        sc[M_ITERS] = 0.0;
+    }
+    write_partial(part, P_RZ, rz);
+    write_partial(part, P_RR, rr);
+}
+
+__global__ __launch_bounds__(RB) void k_m32_spmv(Mat32 A, int k, const float* __restrict__ z,
+                                                 const float* __restrict__ p_old, float* __restrict__ p_new,
+                                                 float* __restrict__ q, double* __restrict__ part,
+                                                 double* __restrict__ sc) {
+    if (sc[M_DONE] != 0.0) return;
+    const double rz = partial_total(part, P_RZ, gridDim.x);
+    const double rr = partial_total(part, P_RR, gridDim.x);
+    const double tol2 = k == 0 ? kInnerRtol * kInnerRtol * rr : sc[M_TOL2];
+    if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) sc[M_TOL2] = tol2;
+    if (rr <= tol2 || !isfinite(rr)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc[M_DONE] = 1.0;
+            sc[M_ITERS] = double(k);
+        }
+        return;
+    }
+    const float bt = k == 0 ? 0.0f : float(rz / sc[M_RHO0 + ((k - 1) & 1)]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[M_RHO0 + (k & 1)] = rz;
+    double pq = 0.0;
+    FOR_ROW(i) {
+        float qi = 0.0f;
+        for (int64_t kk = A.rowptr[i]; kk < A.rowptr[i + 1]; ++kk) {
+            const int32_t j = A.col[kk];
+            qi = fmaf(A.val[kk], fmaf(bt, p_old[j], z[j]), qi);
+        }
+        const float pi = fmaf(bt, p_old[i], z[i]);
+        p_new[i] = pi;
+        q[i] = qi;
+        pq = fma(double(pi), double(qi), pq);
+    }
+    write_partial(part, P_PQ, pq);
+}
+
+__global__ __launch_bounds__(RB) void k_m32_update(Mat32 A, int k, const float* __restrict__ p,
+                                                   const float* __restrict__ q, float* __restrict__ d,
+                                                   float* __restrict__ r, float* __restrict__ z,
+                                                   double* __restrict__ part, const double* __restrict__ sc) {
+    if (sc[M_DONE] != 0.0) return;
+    const float a = float(sc[M_RHO0 + (k & 1)] / partial_total(part, P_PQ, gridDim.x));
+    double rz = 0.0, rr = 0.0;
+    FOR_ROW(i) {
+        d[i] = fmaf(a, p[i], d[i]);
+        const float ri = fmaf(-a, q[i], r[i]);
+        const float zi = ri / A.diag[i];
+        r[i] = ri;
+        z[i] = zi;
+        rz = fma(double(ri), double(zi), rz);
+        rr = fma(double(ri), double(ri), rr);
+    }
+    write_partial(part, P_RZ, rz);
+    write_partial(part, P_RR, rr);
+}
+
+__global__ __launch_bounds__(RB) void k_m32_check(int k, int nb, const double* __restrict__ part,
+                                                  double* __restrict__ sc) {
+    if (sc[M_DONE] != 0.0) return;
+    const double rr = partial_total(part, P_RR, nb);
+    if (threadIdx.x == 0) {
+        sc[M_ITERS] = double(k);
+        if (rr <= sc[M_TOL2] || !isfinite(rr)) sc[M_DONE] = 1.0;
+    }
+}
+
+// y += d (binary32 correction into the binary64 iterate)
+__global__ void k_mx_apply(int64_t n, const float* __restrict__ d, double* __restrict__ y) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        y[i] += double(d[i]);
+}
+
+static ft_status mixed_alloc(ft_target* T, hipStream_t s) {
+    if (T->val32) return FT_OK;
+    FT_TRY(dev_alloc_n(&T->val32, size_t(T->nnz)));
+    FT_TRY(dev_alloc_n(&T->diag32, size_t(T->n)));
+    FT_TRY(dev_alloc_n(&T->w32, size_t(6) * T->n));
+    FT_TRY(dev_alloc_n(&T->scal32, size_t(M_COUNT)));
+    k_to_f32<<<grid_for(T->nnz, 256), 256, 0, s>>>(T->val, T->nnz, T->val32);
+    k_to_f32<<<grid_for(T->n, 256), 256, 0, s>>>(T->diag, T->n, T->diag32);
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
+static ft_status read_scalars(ft_target* T, const double* src, int count, hipStream_t s) {
+    FT_TRY_HIP(hipMemcpyAsync(T->h_scal, src, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    return FT_OK;
+}
+
+static ft_status project_mixed(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep,
+                               hipStream_t s) {
+    FT_TRY(mixed_alloc(T, s));
+    const double alpha = T->consumed_cfg.alpha;
+    const int64_t n = T->n;
+    const int nb = T->reduce_blocks;
+    Mat A{T->rowptr, T->col, T->val, T->diag, T->lumped, n};
+    Mat32 A32{T->rowptr, T->col, T->val32, T->diag32, n};
+    float* r32 = T->w32;
+    float* z32 = r32 + n;
+    float* p32 = z32 + n;   // two buffers
+    float* q32 = p32 + 2 * n;
+    float* d32 = q32 + n;
+    unsigned long long nonfinite = 0;
+    FT_TRY_HIP(hipMemcpyAsync(&nonfinite, T->counters, sizeof(nonfinite), hipMemcpyDeviceToHost, s));
+    double* bf = b_out ? b_out : T->b;
+    k_rhs<<<nb, RB, 0, s>>>(A, T->g, T->bres, alpha, bf, T->partials);
+    k_mx_start<<<nb, RB, 0, s>>>(A, T->bres, T->y, T->r, T->partials);
+    k_mx_totals<<<1, RB, 0, s>>>(0, nb, cfg->rtol * cfg->rtol, T->partials, T->scal);
+    FT_TRY_HIP(hipGetLastError());
+    FT_TRY(read_scalars(T, T->scal, S_COUNT, s));
+    const double tol2 = T->h_scal[S_TOL2];
+    double rr = T->h_scal[S_TRR];
+    int iters = 0;
+    bool done = rr <= tol2 || !std::isfinite(rr);
+    for (int step = 0; step < cfg->refine_steps && !done; ++step) {
+        k_m32_init<<<nb, RB, 0, s>>>(A32, T->r, r32, z32, d32, p32, T->partials, T->scal32);
+        int launched = 0, chunk = 8;
+        while (launched < cfg->max_iter) {
+            const int k = std::min(chunk, cfg->max_iter - launched);
+            for (int it = 0; it < k; ++it) {
+                const int kk = launched + it;
+                float* p_old = p32 + ((kk & 1) ? n : 0);
+                float* p_new = p32 + ((kk & 1) ? 0 : n);
+                k_m32_spmv<<<nb, RB, 0, s>>>(A32, kk, z32, p_old, p_new, q32, T->partials, T->scal32);
+                k_m32_update<<<nb, RB, 0, s>>>(A32, kk, p_new, q32, d32, r32, z32, T->partials, T->scal32);
+            }
+            launched += k;
+            k_m32_check<<<1, RB, 0, s>>>(launched, nb, T->partials, T->scal32);
+            FT_TRY_HIP(hipGetLastError());
+            FT_TRY(read_scalars(T, T->scal32, M_COUNT, s));
+            if (T->h_scal[M_DONE] != 0.0) break;
+            chunk = 4;
+        }
+        iters += int(T->h_scal[M_ITERS]);
+        k_mx_apply<<<grid_for(n, 256), 256, 0, s>>>(n, d32, T->y);
+        k_mx_resid<<<nb, RB, 0, s>>>(A, T->bres, T->y, T->r, T->partials);
+        k_mx_totals<<<1, RB, 0, s>>>(1, nb, 0.0, T->partials, T->scal);
+        FT_TRY_HIP(hipGetLastError());
+        FT_TRY(read_scalars(T, T->scal, S_COUNT, s));
+        rr = T->h_scal[S_TRR];
+        done = rr <= tol2 || !std::isfinite(rr);
+    }
+    k_solution<<<nb, RB, 0, s>>>(n, T->g, T->y, alpha, x);
+    k_report<<<nb, RB, 0, s>>>(A, bf, x, T->partials);
+    k_report_totals<<<1, RB, 0, s>>>(nb, T->partials, T->scal);
+    FT_TRY_HIP(hipGetLastError());
+    FT_TRY(read_scalars(T, T->scal, S_COUNT, s));
+    const double* h = T->h_scal;
+    ft_report& R = rep[0];
+    R.sum_b = h[S_SUMB];
+    R.int_x = h[S_INTX];
+    R.cons_defect = h[S_SUMB] != 0.0 ? std::fabs(h[S_INTX] - h[S_SUMB]) / std::fabs(h[S_SUMB]) : std::fabs(h[S_INTX]);
+    R.rel_resid = h[S_BB] > 0.0 ? std::sqrt(h[S_TRR] / h[S_BB]) : std::sqrt(h[S_TRR]);
+    R.iters = iters;
+    R.n_nonfinite = int64_t(nonfinite);
+    R.status = nonfinite ? FT_E_NONFINITE : (done ? FT_OK : FT_E_NOCONV);
+    if (R.status == FT_E_NONFINITE) set_error("%llu non-finite query value(s) were consumed", nonfinite);
+    else if (R.status == FT_E_NOCONV)
+        set_error("refinement did not reach rtol=%g within %d steps", cfg->rtol, cfg->refine_steps);
+    return ft_status(R.status);
+}
+
 ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep, hipStream_t s) {
     const int F = T->consumed_cfg.n_fields;
+    if (cfg->refine_steps > 0) {
+        if (F > 1) {
+            set_error("the mixed-precision solve (refine_steps > 0) handles one field per call");
+            return FT_E_UNSUPPORTED;
+        }
+        return project_mixed(T, cfg, x, b_out, rep, s);
+    }
     if (F > 1) return project_multi(T, cfg, x, b_out, rep, s);
     const double alpha = T->consumed_cfg.alpha;
     const int64_t n = T->n;

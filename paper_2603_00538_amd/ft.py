@@ -37,7 +37,7 @@ class SampleCfg(ctypes.Structure):
 
 
 class SolveCfg(ctypes.Structure):
-    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("refine_steps", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -305,14 +305,14 @@ class Target:
         """Fused steps 1 and 3-6 from a built-in Source (no query list in memory)."""
         ft_transfer_p1(self.handle, source.handle, cfg, current_stream())
 
-    def project(self, n_fields=1, rtol=1e-14, max_iter=500, want_b=True, x=None, b=None):
+    def project(self, n_fields=1, rtol=1e-14, max_iter=500, want_b=True, x=None, b=None, refine_steps=0):
         torch = _torch()
         if x is None:
             x = torch.empty((n_fields, self.n_nodes), dtype=torch.float64, device=self.coords.device)
         if want_b and b is None:
             b = torch.empty((n_fields, self.n_nodes), dtype=torch.float64, device=self.coords.device)
         f64 = (torch.float64,)
-        st, reps = ft_project(self.handle, SolveCfg(rtol, max_iter), _device_ptr(x, "x", f64, n_fields),
+        st, reps = ft_project(self.handle, SolveCfg(rtol, max_iter, refine_steps), _device_ptr(x, "x", f64, n_fields),
                               _device_ptr(b, "b", f64, n_fields) if want_b else None, n_fields, current_stream())
         return Transfer(x, b, reps, st)
 

@@ -384,3 +384,32 @@ def test_query_list_launch_matches_plain_eval(dim, N):
     assert int((ids_a < 0).sum()) == 0
     T.close()
     S.close()
+
+
+# ---------------------------------------------------------------- mixed-precision solve
+def test_refinement_solve_matches_binary64_solve(c1):
+    """binary32 inner PCG + binary64 residual refinement reaches the binary64
+    solution of the same M x = b (FP32-form load vector)."""
+    w, tm, sm, sv = c1
+    tc, tconn = tm
+    T = ft.Target(tc, tconn)
+    S = ft.Source(*sm, sv)
+    cfg = ft.SampleCfg(w.samples_per_elem, 1, w.alpha, w.philox_seed, 0, ft.FT_F32)
+    pts = T.sample_points(cfg)
+    vals = S.eval_query_list(pts, tc.shape[0])
+    T.consume(cfg, vals)
+    ref = T.project(1, rtol=1e-14)
+    mixed = T.project(1, rtol=1e-14, refine_steps=4)
+    torch.cuda.synchronize()
+    rep = mixed.reports[0]
+    log(f"refinement: {rep['iters']} inner iterations, rel resid {rep['rel_resid']:.2e}")
+    assert mixed.status == ft.FT_OK
+    assert rep["rel_resid"] < 1e-13
+    assert torch.equal(mixed.b, ref.b)
+    assert rel_l2(mixed.x.cpu().numpy(), ref.x.cpu().numpy()) < 1e-13
+    assert rep["cons_defect"] < 1e-13
+    one = T.project(1, rtol=1e-14, refine_steps=1)
+    assert one.status == ft.FT_E_NOCONV            # one binary32 step gains about six digits only
+    assert one.reports[0]["rel_resid"] < 1e-4
+    T.close()
+    S.close()
