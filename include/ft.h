@@ -256,6 +256,35 @@ ft_status ft_source_stats(ft_source* s, int64_t* n_out_of_domain /* host */, hip
 ft_status ft_source_destroy(ft_source* s);
 
 /*
+ * Plans: the setup/online split of a transfer from the built-in source
+ * (sec. 5.3: localization is paid once at initialization, later transfers
+ * between the same meshes only evaluate, accumulate and solve).
+ */
+typedef struct ft_plan ft_plan;
+
+/*
+ * ft_plan_create - draw the samples of `cfg` on target `t` and localize every
+ * target node and sample in source `s` once (the containing source element
+ * of each query is kept on the device, 4 bytes per query).  cfg: FT_F64,
+ * n_fields equal to the source's field count.  t and s are not owned and must
+ * outlive the plan.  Out-of-domain queries are counted in the source.
+ * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Synchronizes `stream`.
+ */
+ft_status ft_plan_create(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, hipStream_t stream, ft_plan** out);
+
+/*
+ * ft_plan_transfer - sec. 4.1 steps 1 and 3-6 with the cached localization:
+ * the source field given by `nodal_values` (device, binary64, [n_fields][n_nodes
+ * of the source mesh]; null = the source's own values) is interpolated at the
+ * plan's samples and nodes, and the residual element sums and node assembly
+ * follow as in ft_transfer_p1 (bitwise equal to it for the source's own
+ * values).  Follow with ft_project.  Asynchronous on `stream`.
+ */
+ft_status ft_plan_transfer(ft_plan* p, const double* nodal_values, hipStream_t stream);
+
+ft_status ft_plan_destroy(ft_plan* p);
+
+/*
  * Batches: many independent transfers from built-in P1 sources (one field
  * each, FT_F64), of mixed dimension, size and samples per element, run as
  * one sequence of launches.  Target elements of all transfers are the work

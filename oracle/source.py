@@ -2,10 +2,10 @@
 
 The method itself only needs point values f^s(x) (sec. 2: the source may be
 known only through pointwise evaluations; algorithm step 1 and step 4 query
-it).  For benchmarks the source is a P1 field on a source mesh ("functions ...
-interpolated onto the source mesh", sec. 5.1), evaluated at a point by finding
-the containing source element and interpolating with its barycentric
-coordinates mu.
+it).  For benchmarks the source is a P1 field on a source mesh (the test
+functions of sec. 5.1 are nodal interpolants on the source mesh), evaluated at
+a point by finding the containing source element and interpolating with its
+barycentric coordinates mu.
 
 Localization rule (reading; the paper is silent on ties): the source element
 maximising min_k mu_k(x); among exact ties, the lowest element id.  A point

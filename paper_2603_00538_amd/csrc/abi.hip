@@ -26,6 +26,12 @@ ft_batch* batch_new(int count, ft_target* const* targets, ft_source* const* sour
                     bool graph);
 void batch_delete(ft_batch* b);
 void batch_mark_consumed(ft_batch* b);
+ft_status plan_setup(ft_plan* pl, hipStream_t s);
+ft_status plan_transfer(ft_plan* pl, const double* vals, hipStream_t s);
+ft_plan* plan_new(ft_target* T, ft_source* S, const ft_sample_cfg* cfg);
+void plan_delete(ft_plan* p);
+ft_target* plan_target(ft_plan* p);
+const ft_sample_cfg* plan_cfg(const ft_plan* p);
 
 static void target_release(ft_target* T) {
     void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
@@ -221,6 +227,52 @@ ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b
     }
     return project(t, cfg, x, b_out, rep, stream);
     FT_GUARD_END
+}
+
+ft_status ft_plan_create(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, hipStream_t stream, ft_plan** out) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(out, "out is null");
+    *out = nullptr;
+    FT_ARG_CHECK(t && s, "target and source must be non-null");
+    FT_TRY(check_sample_cfg(t, cfg));
+    FT_ARG_CHECK(s->dim == t->dim, "source dimension %d differs from target dimension %d", s->dim, t->dim);
+    FT_ARG_CHECK(cfg->n_fields == s->F, "n_fields (%d) must equal the source's field count (%d)", cfg->n_fields,
+                 s->F);
+    if (cfg->precision != FT_F64) {
+        set_error("plans run the FT_F64 form");
+        return FT_E_UNSUPPORTED;
+    }
+    FT_TRY(ensure_field_buffers(t, cfg->n_fields, stream));
+    ft_plan* p = plan_new(t, s, cfg);
+    const ft_status st = plan_setup(p, stream);
+    if (st != FT_OK) {
+        (void)hipStreamSynchronize(stream);
+        plan_delete(p);
+        return st;
+    }
+    *out = p;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_plan_transfer(ft_plan* p, const double* nodal_values, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(p, "plan is null");
+    ft_target* t = plan_target(p);
+    FT_TRY(ensure_field_buffers(t, plan_cfg(p)->n_fields, stream));
+    t->consumed = false;
+    FT_TRY(plan_transfer(p, nodal_values, stream));
+    t->consumed = true;
+    t->consumed_cfg = *plan_cfg(p);
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_plan_destroy(ft_plan* p) {
+    plan_delete(p);
+    return FT_OK;
 }
 
 ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* const* sources,

@@ -422,6 +422,7 @@ __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, in
         const bool found = bid[q] != INT_MAX;
         nood += !found || best[q] < kOutTol;
         if (ids) ids[i] = found ? bid[q] : -1;
+        if (!out_) continue;   // localization only
         double mu[D + 1];
         winner_mu<D>(S, bid[q], p[q], mu);
         for (int f = 0; f < S.F; ++f) {

@@ -28,6 +28,7 @@ STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
             "ft_consume_queries", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval",
             "ft_source_eval_queries", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
+            "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_last_error"]
 
 
@@ -95,6 +96,9 @@ def load(path: str = LIB_PATH):
         "ft_batch_create": (I32, [I32, P, P, ctypes.POINTER(SampleCfg), I32, P, ctypes.POINTER(P)]),
         "ft_batch_run": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P, P]),
         "ft_batch_destroy": (I32, [P]),
+        "ft_plan_create": (I32, [P, P, ctypes.POINTER(SampleCfg), P, ctypes.POINTER(P)]),
+        "ft_plan_transfer": (I32, [P, P, P]),
+        "ft_plan_destroy": (I32, [P]),
         "ft_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -169,6 +173,20 @@ def ft_batch_run(h, cfg: SolveCfg, x_ptrs, b_ptrs, stream, allow=(FT_E_NOCONV, F
     sts = (ctypes.c_int32 * K)()
     st = _check(load().ft_batch_run(h, ctypes.byref(cfg), xs, bs, reps, sts, stream), "ft_batch_run", allow)
     return st, [r.as_dict() for r in reps], list(sts)
+
+
+def ft_plan_create(t, s, cfg: SampleCfg, stream):
+    out = ctypes.c_void_p()
+    _check(load().ft_plan_create(t, s, ctypes.byref(cfg), stream, ctypes.byref(out)), "ft_plan_create")
+    return out
+
+
+def ft_plan_transfer(h, values_ptr, stream):
+    return _check(load().ft_plan_transfer(h, values_ptr, stream), "ft_plan_transfer")
+
+
+def ft_plan_destroy(h):
+    return _check(load().ft_plan_destroy(h), "ft_plan_destroy")
 
 
 def ft_batch_destroy(h):
@@ -330,6 +348,7 @@ class Source:
             v = v[None, :]
         self.values = v.contiguous().to(device)
         self.n_fields = int(self.values.shape[0])
+        self.n_nodes = int(coords.shape[0])
         self.handle = ft_source_create_p1(self.dim, int(coords.shape[0]), self.coords.data_ptr(), int(conn.shape[0]),
                                           self.conn.data_ptr(), self.n_fields, self.values.data_ptr(), bins,
                                           current_stream())
@@ -432,6 +451,37 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             ft_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Setup/online split (ft_plan_create / ft_plan_transfer): localize once,
+    then transfer new nodal values of the source field as often as needed."""
+
+    def __init__(self, target, source, cfg: SampleCfg):
+        self.target, self.source, self.cfg = target, source, cfg
+        self.handle = ft_plan_create(target.handle, source.handle, cfg, current_stream())
+
+    def transfer(self, nodal_values=None):
+        """nodal_values: (F, n_source_nodes) float64 device tensor, or None for the source's own.
+        Follow with target.project()."""
+        torch = _torch()
+        ptr = None
+        if nodal_values is not None:
+            if tuple(nodal_values.shape) != (self.cfg.n_fields, self.source.n_nodes):
+                raise ValueError(f"nodal_values must have shape ({self.cfg.n_fields}, {self.source.n_nodes})")
+            ptr = _device_ptr(nodal_values, "nodal_values", (torch.float64,))
+        ft_plan_transfer(self.handle, ptr, current_stream())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ft_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
