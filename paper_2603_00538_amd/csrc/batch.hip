@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchXfer* __restrict
                                                      int64_t n_tiles, unsigned long long* __restrict__ nonfinite) {
     const int lane = threadIdx.x & 63;
     const int64_t stride = int64_t(gridDim.x) * 4;
-    for (int64_t w = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 4 + (threadIdx.x >> 6); w < n_tiles; w += stride) {
+    for (int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); w < n_tiles; w += stride) {
         const Tile tl = tiles[w];
         const BatchXfer& x = X[tl.k];
         unsigned nf = 0, nood = 0;
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchXfer* __restrict
 __global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles,
                                                      int64_t n_tiles) {
     const int64_t stride = int64_t(gridDim.x) * 4;
-    for (int64_t w = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 4 + (threadIdx.x >> 6); w < n_tiles; w += stride) {
+    for (int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); w < n_tiles; w += stride) {
         const Tile tl = tiles[w];
         const BatchXfer& x = X[tl.k];
         unsigned nood;

@@ -128,18 +128,6 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv& f) {
 }
 
 // ---------------------------------------------------------------- wave helpers (wave64)
-// The command processor hands workgroups to the chip's eight XCDs in turn
-// (block b to XCD b mod 8), and each XCD has its own L2.  Renumbering so that
-// every XCD walks one contiguous eighth of the grid keeps spatially
-// neighbouring work (and the source elements it reads) in one L2.  A
-// bijection on [0, nb): the first 8*floor(nb/8) blocks are permuted, the tail
-// keeps its numbers.
-constexpr uint32_t kXcds = 8;
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
-    const uint32_t q = nb / kXcds;
-    return b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
-}
-
 __device__ __forceinline__ double wave_sum_xor(double v, int width) {
     for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
     return v;

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void k_fused_p1(SrcView S, const double* __res
                                                   const double* __restrict__ g, double* __restrict__ beta,
                                                   unsigned long long* __restrict__ nonfinite,
                                                   unsigned long long* __restrict__ n_ood) {
-    const uint32_t gid = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
     unsigned nf = 0, nood = 0;
     fused_elements<D, G, P, FC>(S, X, n, conn, vol, E, N, alpha, key, g, beta, gid / G, int(gid & (G - 1)), nf, nood);
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_plan_locate(SrcView S, const double* __
                                                      const int32_t* __restrict__ conn, uint32_t E, uint32_t N,
                                                      SampleKey key, int32_t* __restrict__ ids,
                                                      unsigned long long* __restrict__ n_ood) {
-    const uint32_t gid = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
     const uint32_t t = gid / G;
     const int lane = int(gid & (G - 1));
     const bool valid = t < E;

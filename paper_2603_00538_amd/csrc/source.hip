@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t head, int64
                                                   int32_t* __restrict__ ids, unsigned long long* __restrict__ n_ood) {
     // two segments, [0, head) and [head, npts), each starting on a wavefront boundary
     constexpr int64_t WP = 64 * P;
-    const int64_t wave = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 4 + (threadIdx.x >> 6);
+    const int64_t wave = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     const int64_t wh = (head + WP - 1) / WP;
     const int64_t base = wave < wh ? wave * WP : head + (wave - wh) * WP;
     const int64_t lim = wave < wh ? head : npts;
