@@ -244,7 +244,7 @@ typedef struct {
     int64_t n_nodes;
     int64_t n_elems;
     int32_t bins[3];            /* cells per axis of the localization grid (1 for unused axes)    */
-    int64_t n_registrations;    /* element ids stored over all bins                                */
+    int64_t n_registrations;    /* element ids stored over all bins (one per element)              */
 } ft_source_info;
 
 ft_status ft_source_get_info(const ft_source* s, ft_source_info* info /* host */);

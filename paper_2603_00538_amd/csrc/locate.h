@@ -8,24 +8,28 @@
 // whose best element has min mu > 1e-12 is strictly inside it: no other
 // element can tie or win, and rounding (far below 1e-12) cannot change that.
 //
-// Search.  The points of a wave (64 lanes x P points) are usually samples of
-// one or two target elements, so they share a handful of bins.  The wave
-// forms its points' bounding box (and, in 2D, their ranges of x+y and x-y: an
-// octagon) and the box of bins it covers; the registrations of all those bins
-// form one flat candidate sequence, culled 64 at a time, one per lane:
+// Search.  Every element is registered once, in the bin holding the lower
+// corner of its box; with ext the largest element extent in bins (minus one)
+// per axis, the elements that can meet a region of bins [lo, hi] are those
+// registered in [lo - ext, hi].  The points of a wave (64 lanes x P points)
+// are usually samples of one target element, so they share a handful of bins.
+// The wave forms its points' bounding box (and, in 2D, their ranges of x+y
+// and x-y: an octagon) and the bins that can hold candidates; lanes load
+// those bins' ranges and a wave scan turns them into one flat candidate
+// sequence (no element appears twice), culled 64 at a time, one per lane:
 //   - the element's box must meet the wave's box (and octagon, in 2D);
-//   - it is offered only in the first of the wave's bins it is registered in;
 //   - no barycentric coordinate may be below -1e-9 on the whole wave box.
 // Each lane parks its candidate's absolute affine barycentric form in the
 // wave's LDS; every lane then tests its points against each survivor in lane
-// order (broadcast LDS reads).  The selection test accepts an element
-// once its min mu exceeds 1e-9, far above that form's rounding, so an
-// accepted element truly contains the point and is the unique winner.  Points
-// never accepted (within 1e-9 of a face, or outside) are re-searched in their
-// own bin with the full rule.  The barycentrics used to interpolate are always
-// recomputed from the element origin.  Waves whose points span many bins
-// (scattered input) search one bin per point.  Callers launch 256-thread
-// blocks (four waves share the block's LDS slots).
+// order (broadcast LDS reads).  The selection test accepts an element once
+// its min mu exceeds 1e-9, far above that form's rounding, so an accepted
+// element truly contains the point and is the unique winner.  Points never
+// accepted (within 1e-9 of a face, or outside) are re-searched alone with the
+// full rule over the bins that can hold their elements.  The barycentrics
+// used to interpolate are always recomputed from the element origin.  Waves
+// whose points need more than 64 bins (scattered input) search point by
+// point.  Callers launch 256-thread blocks (four waves share the block's LDS
+// slots).
 #pragma once
 
 #include <cfloat>
@@ -41,22 +45,19 @@ constexpr double kOutTol = -1e-10;
 // Record of element e, rec[e*RS ...] (doubles; 128 B in 2D, 256 B in 3D):
 //   [0, D)                    origin x0 (vertex 0)
 //   [AF, AF + D + 1)          constants c_k of mu_k(x) = c_k + g_k . x, AF = D
-//   [AF + D + 1, BF)          gradients g_k (D each), k = 0..D; g_1..g_D are the
+//   [AF + D + 1, VAL)         gradients g_k (D each), k = 0..D; g_1..g_D are the
 //                             rows of the inverse of J = [x1-x0 | ... | xd-x0]
-//   [BF, VAL)                 the element's first bin per axis (int32 each)
 //   [VAL, VAL + D + 1)        vertex values of a one-field source (else zero)
-// The absolute affine form [c | g] selects the element (one contiguous
-// block the cull loads with the first-bin slot); the origin form
-// mu_{k+1} = g_{k+1} . (x - x0) gives the barycentrics used to interpolate,
-// and for one field the vertex values sit in the same record.
+// The absolute affine form [c | g] selects the element (one contiguous block
+// the cull loads); the origin form mu_{k+1} = g_{k+1} . (x - x0) gives the
+// barycentrics used to interpolate, and for one field the vertex values sit
+// in the same record.
 template <int D>
 struct RecSize { static constexpr int value = D == 2 ? 16 : 32; };
 template <int D>
 struct RecAffine { static constexpr int value = D; };
 template <int D>
-struct RecBinFirst { static constexpr int value = D + (D + 1) * (D + 1); };
-template <int D>
-struct RecValues { static constexpr int value = RecBinFirst<D>::value + (D == 2 ? 1 : 2); };
+struct RecValues { static constexpr int value = D + (D + 1) * (D + 1); };
 static_assert(RecValues<2>::value + 3 <= RecSize<2>::value, "2D record overflow");
 static_assert(RecValues<3>::value + 4 <= RecSize<3>::value, "3D record overflow");
 
@@ -78,6 +79,7 @@ __device__ __forceinline__ float f32_up(double x) {
 
 struct GridView {
     int32_t nb[3];
+    int32_t ext[3];   // largest element extent in bins minus one, per axis
     double lo[3];
     double inv_h[3];
 };
@@ -175,30 +177,37 @@ __device__ __forceinline__ double affine_min_mu_lds(const double* af, const doub
 template <int D>
 __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)[D], double& best, int& bid) {
     constexpr int RS = RecSize<D>::value;
-    int bc[3] = {0, 0, 0};
+    int hi[3] = {0, 0, 0}, lo[3] = {0, 0, 0};
 #pragma unroll
-    for (int c = 0; c < D; ++c) bc[c] = bin_of(p[c], c, S.g);
-    const int64_t b = (int64_t(bc[2]) * S.g.nb[1] + bc[1]) * S.g.nb[0] + bc[0];
-    const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
+    for (int c = 0; c < D; ++c) {
+        hi[c] = bin_of(p[c], c, S.g);
+        lo[c] = max(hi[c] - S.g.ext[c], 0);
+    }
     best = -DBL_MAX;
     bid = INT_MAX;
-    for (int64_t c = start; c < end; ++c) {
-        const int e = S.bin_elems[c];
-        test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid);
-        if (best > kInsideTau) break;
-    }
+    // every element overlapping p's bin has its first bin in [hi - ext, hi]
+    for (int bz = lo[2]; bz <= hi[2]; ++bz)
+        for (int by = lo[1]; by <= hi[1]; ++by)
+            for (int bx = lo[0]; bx <= hi[0]; ++bx) {
+                const int64_t b = (int64_t(bz) * S.g.nb[1] + by) * S.g.nb[0] + bx;
+                const int64_t start = S.bin_ptr[b], end = S.bin_ptr[b + 1];
+                for (int64_t c = start; c < end; ++c) {
+                    const int e = S.bin_elems[c];
+                    test_candidate<D>(S.rec + int64_t(e) * RS, e, p, best, bid);
+                    if (best > kInsideTau) return;   // strictly inside: the unique winner
+                }
+            }
 }
 
 // Rule winner for each of this lane's P points (see the file comment).  Every
 // lane of the wave must call it (points a lane does not own pass
 // active = false).  Returns best = max min-barycentric and bid = its element
 // id (INT_MAX if no candidate was found) per point.
-// Inclusive prefix sum over the first 32 lanes of the wave (enough for the
-// at most 27 bins a wave searches).
+// Inclusive prefix sum over the 64 lanes of the wave.
 __device__ __forceinline__ int wave_scan_incl(int x) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
+    for (int d = 1; d < 64; d <<= 1) {
         const int t = __shfl_up(x, d, 64);
         if (lane >= d) x += t;
     }
@@ -210,7 +219,7 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                                             double (&best)[P], int (&bid)[P]) {
     constexpr int RS = RecSize<D>::value;
     constexpr int BS = BoxSize<D>::value;
-    constexpr int MAX_SPAN = D == 2 ? 16 : 27;
+    constexpr int MAX_SPAN = 64;   // bins a wave searches as one flat sequence (one per lane)
     const int lane = threadIdx.x & 63;
     double wlo[D], whi[D];
     int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
@@ -226,7 +235,8 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             }
         wlo[c] = uniform_double(wave_min(lo));
         whi[c] = uniform_double(wave_max(hi));
-        b0[c] = uniform_int(bin_of(wlo[c], c, S.g));
+        // elements meeting the wave's box have their first bin in [bin(lo) - ext, bin(hi)]
+        b0[c] = uniform_int(max(bin_of(wlo[c], c, S.g) - S.g.ext[c], 0));
         b1[c] = uniform_int(bin_of(whi[c], c, S.g));
         span *= b1[c] - b0[c] + 1;
     }
@@ -269,14 +279,11 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         __shared__ double c_af[4][64 * AL];     // per wave of a 256-thread block
         const int w = (threadIdx.x >> 6) & 3;
         const int wx = b1[0] - b0[0] + 1, wy = b1[1] - b0[1] + 1;
-        int cb[3] = {0, 0, 0};
         int64_t bstart = 0;
         int bcnt = 0;
         if (lane < span) {
-            cb[0] = b0[0] + lane % wx;
-            cb[1] = b0[1] + (lane / wx) % wy;
-            cb[2] = b0[2] + lane / (wx * wy);
-            const int64_t b = (int64_t(cb[2]) * S.g.nb[1] + cb[1]) * S.g.nb[0] + cb[0];
+            const int cx = b0[0] + lane % wx, cy = b0[1] + (lane / wx) % wy, cz = b0[2] + lane / (wx * wy);
+            const int64_t b = (int64_t(cz) * S.g.nb[1] + cy) * S.g.nb[0] + cx;
             bstart = S.bin_ptr[b];
             bcnt = int(S.bin_ptr[b + 1] - bstart);
         }
@@ -285,13 +292,16 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         bool finished = false;
         for (int c0 = 0; c0 < total && !finished; c0 += 64) {
             const int sl = c0 + lane;
-            int i = 0;   // bin of slot sl: the number of bins whose inclusive count is <= sl
-            for (int u = 0; u < span - 1; ++u) i += sl >= __builtin_amdgcn_readlane(incl, u);
+            // bin of slot sl: the first lane whose inclusive count exceeds sl (binary search)
+            int i = 0, ihi = span - 1;
+#pragma unroll
+            for (int step = 0; step < 6; ++step) {
+                const int mid = (i + ihi) >> 1;
+                if (__shfl(incl, mid, 64) > sl) ihi = mid;
+                else i = mid + 1 <= ihi ? mid + 1 : ihi;
+            }
             const int excl_i = __shfl(incl - bcnt, i, 64);
             const int64_t st_i = __shfl((long long)bstart, i, 64);
-            int cur[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) cur[c] = __shfl(cb[c], i, 64);
             int cid = -1;
             bool ov = false;
             double af[AL];
@@ -302,14 +312,9 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 const double* r = S.rec + int64_t(cid) * RS;
 #pragma unroll
                 for (int m = 0; m < AL; ++m) af[m] = r[RecAffine<D>::value + m];
-                const int32_t* first = reinterpret_cast<const int32_t*>(r + RecBinFirst<D>::value);
                 ov = true;
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
-                    // offer each element once per wave: in the first of the wave's bins it is in
-                    ov &= max(first[c], b0[c]) == cur[c];
-                }
+                for (int c = 0; c < D; ++c) ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
                 if constexpr (D == 2)
                     ov &= (bx_[4] <= fu[1]) & (bx_[6] >= fu[0]) & (bx_[5] <= fu[3]) & (bx_[7] >= fu[2]);
                 ov = ov && box_may_meet_af<D>(af, wlo, whi);

@@ -9,10 +9,11 @@
 //
 // Layout: every source element e has a record rec[e*RS ...] holding its
 // origin, its barycentric map (absolute affine form, whose gradients g_1..g_D
-// are the rows of the inverse of J = [x1-x0 | ... | xd-x0]), its first bin per
-// axis and, for one field, its vertex values (see locate.h); plus an
-// outward-rounded binary32 bounding box.  Bins hold the ids of every element
-// whose box overlaps them (CSR, ascending ids).
+// are the rows of the inverse of J = [x1-x0 | ... | xd-x0]) and, for one
+// field, its vertex values (see locate.h); plus an outward-rounded binary32
+// bounding box.  Each element is registered once, in the bin holding the lower
+// corner of its box (CSR, ascending ids per bin); the largest box extent in
+// bins tells a search how far below a region's bins to look.
 
 #include <algorithm>
 #include <cfloat>
@@ -159,31 +160,25 @@ __device__ __forceinline__ void elem_bin_range(const double* __restrict__ X, int
     }
 }
 
+// Each element is registered once, in the bin of its box's lower corner; the
+// count pass also records the largest box extent in bins per axis.
 template <int D, bool FILL>
 __global__ void k_src_register(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
                                GridView g, int32_t* __restrict__ cnt, const int64_t* __restrict__ ptr,
-                               int32_t* __restrict__ elems, double* __restrict__ rec) {
+                               int32_t* __restrict__ elems, int32_t* __restrict__ ext) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= E) return;
     int b0[3], b1[3];
     elem_bin_range<D>(X, n, conn, e, g, b0, b1);
+    const int64_t b = (int64_t(b0[2]) * g.nb[1] + b0[1]) * g.nb[0] + b0[0];
     if (!FILL) {
-        // first bin per axis, in the element's record
-        int32_t* first = reinterpret_cast<int32_t*>(rec + e * RecSize<D>::value + RecBinFirst<D>::value);
+        atomicAdd(&cnt[b], 1);
 #pragma unroll
-        for (int c = 0; c < D; ++c) first[c] = b0[c];
+        for (int c = 0; c < D; ++c) atomicMax(&ext[c], b1[c] - b0[c]);
+    } else {
+        const int pos = atomicAdd(&cnt[b], 1);
+        elems[ptr[b] + pos] = int32_t(e);
     }
-    for (int bz = b0[2]; bz <= b1[2]; ++bz)
-        for (int by = b0[1]; by <= b1[1]; ++by)
-            for (int bx = b0[0]; bx <= b1[0]; ++bx) {
-                const int64_t b = (int64_t(bz) * g.nb[1] + by) * g.nb[0] + bx;
-                if (!FILL) {
-                    atomicAdd(&cnt[b], 1);
-                } else {
-                    const int pos = atomicAdd(&cnt[b], 1);
-                    elems[ptr[b] + pos] = int32_t(e);
-                }
-            }
 }
 
 __global__ void k_minmax(const double* __restrict__ X, int64_t n, int dim, double* __restrict__ out) {
@@ -267,11 +262,13 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     unsigned long long* flags = nullptr;
     double* mm = nullptr;
     int32_t* cnt = nullptr;
+    int32_t* ext = nullptr;
     int64_t* tmp = nullptr;
     ScratchGuard guard;
     guard.add((void**)&flags);
     guard.add((void**)&mm);
     guard.add((void**)&cnt);
+    guard.add((void**)&ext);
     guard.add((void**)&tmp);
     FT_TRY(dev_alloc_n(&flags, 4));
     FT_TRY_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned long long), s));
@@ -332,13 +329,17 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     FT_TRY(dev_alloc_n(&tmp, size_t(scan_tmp_elems(nbins))));
     FT_TRY(dev_alloc_n(&S->bin_ptr, size_t(nbins + 1)));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
-    k_src_register<D, false><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, nullptr, nullptr,
-                                                           S->rec);
+    FT_TRY(dev_alloc_n(&ext, 3));
+    FT_TRY_HIP(hipMemsetAsync(ext, 0, sizeof(int32_t) * 3, s));
+    k_src_register<D, false><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, nullptr, nullptr, ext);
     FT_TRY(exclusive_scan(cnt, S->bin_ptr, nbins, tmp, s));
     int64_t nreg = 0;
+    int32_t hext[3] = {0, 0, 0};
     FT_TRY_HIP(hipMemcpyAsync(&nreg, S->bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipMemcpyAsync(hext, ext, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, s));
     FT_TRY_HIP(hipStreamSynchronize(s));
     S->n_reg = nreg;
+    for (int c = 0; c < 3; ++c) S->ext[c] = c < D ? hext[c] : 0;
     FT_TRY(dev_alloc_n(&S->bin_elems, size_t(nreg)));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
     k_src_register<D, true><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, S->bin_ptr, S->bin_elems,
@@ -358,6 +359,7 @@ SrcView source_view(const ft_source* S) {
     SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
+        v.g.ext[c] = S->ext[c];
         v.g.lo[c] = S->lo[c];
         v.g.inv_h[c] = S->inv_h[c];
     }
