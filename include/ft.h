@@ -237,6 +237,21 @@ ft_status ft_source_eval_queries(ft_source* s, int64_t n_nodes, int64_t n_points
                                  int32_t precision, void* values, int64_t ld_out, int32_t* elem_ids,
                                  hipStream_t stream);
 
+/*
+ * ft_source_autotune - choose the bin grid for a query distribution.  For
+ * each candidate resolution (cells along the longest axis of the source's
+ * box, the other axes proportionally fewer) the bins are rebuilt and
+ * ft_source_eval_queries is timed on `points` (a sample of the real queries,
+ * laid out as for ft_source_eval_queries); the fastest grid is kept.
+ *   candidates  host [n_candidates], 1..64 entries
+ *   bins_out    host [3] or null: the chosen cells per axis
+ * The tuning launches' out-of-domain counts are discarded (the count is
+ * reset).  Errors: FT_E_ARG, FT_E_OOM, FT_E_DEVICE.  Synchronizes `stream`.
+ */
+ft_status ft_source_autotune(ft_source* s, int64_t n_nodes, int64_t n_points, const void* points, int64_t ld,
+                             int32_t precision, int32_t n_candidates, const int32_t* candidates, int32_t* bins_out,
+                             hipStream_t stream);
+
 /* Sizes of a source after setup. */
 typedef struct {
     int32_t dim;

@@ -17,6 +17,8 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
 ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
                       int32_t* ids, hipStream_t s);
 ft_status source_release(ft_source* S);
+ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, int ncand,
+                          const int32_t* cand, hipStream_t s);
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s);
 ft_status batch_setup(ft_batch* b, hipStream_t s);
 ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec, ft_report* rep,
@@ -390,6 +392,27 @@ ft_status ft_source_eval_queries(ft_source* s, int64_t n_nodes, int64_t n_points
     FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
     FT_ARG_CHECK(n_points < (int64_t(1) << 39), "n_points too large");
     return source_eval(s, n_nodes, n_points, points, ld, precision, values, ld_out, elem_ids, stream);
+    FT_GUARD_END
+}
+
+ft_status ft_source_autotune(ft_source* s, int64_t n_nodes, int64_t n_points, const void* points, int64_t ld,
+                             int32_t precision, int32_t n_candidates, const int32_t* candidates, int32_t* bins_out,
+                             hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(s, "source is null");
+    FT_ARG_CHECK(n_points >= 1 && points, "a sample of at least one point is needed");
+    FT_ARG_CHECK(n_nodes >= 0 && n_nodes <= n_points, "n_nodes must lie in [0, n_points]");
+    FT_ARG_CHECK(ld >= n_points, "ld must be >= n_points");
+    FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
+    FT_ARG_CHECK(n_candidates >= 1 && n_candidates <= 64 && candidates, "1..64 candidates are needed");
+    for (int c = 0; c < n_candidates; ++c)
+        FT_ARG_CHECK(candidates[c] >= 1 && candidates[c] <= (1 << 20), "candidate %d out of range (%d)", c,
+                     candidates[c]);
+    FT_TRY(source_autotune(s, n_nodes, n_points, points, ld, precision, n_candidates, candidates, stream));
+    if (bins_out)
+        for (int c = 0; c < 3; ++c) bins_out[c] = s->nb[c];
+    return FT_OK;
     FT_GUARD_END
 }
 

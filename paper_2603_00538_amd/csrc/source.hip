@@ -241,77 +241,30 @@ __global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t head, int64
 }
 
 // ---------------------------------------------------------------- host side
+// (Re)build the bin grid: nb[c] > 0 fixes the cells on axis c; otherwise the
+// longest axis gets `per_axis` cells and the others proportionally fewer.
 template <int D>
-static ft_status build(ft_source* S, const double* coords, const int32_t* conn, const double* values,
-                       const int32_t* bins, hipStream_t s) {
-    constexpr int RS = RecSize<D>::value;
-    const int64_t n = S->n, E = S->E;
+static ft_status build_bins(ft_source* S, const int32_t (&nb_in)[3], double per_axis, hipStream_t s) {
     constexpr int B = 256;
-    FT_TRY(dev_alloc_n(&S->coords, size_t(D) * n));
-    FT_TRY(dev_alloc_n(&S->conn, size_t(E) * (D + 1)));
-    FT_TRY(dev_alloc_n(&S->values, size_t(S->F) * n));
-    FT_TRY(dev_alloc_n(&S->rec, size_t(E) * RS));
-    FT_TRY(dev_alloc_n(&S->box, size_t(E) * BoxSize<D>::value));
-    FT_TRY(dev_alloc_n(&S->counters, 4));
-    FT_TRY_HIP(hipHostMalloc((void**)&S->h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault));
-    FT_TRY_HIP(hipMemcpyAsync(S->coords, coords, sizeof(double) * D * n, hipMemcpyDeviceToDevice, s));
-    FT_TRY_HIP(hipMemcpyAsync(S->conn, conn, sizeof(int32_t) * (D + 1) * E, hipMemcpyDeviceToDevice, s));
-    FT_TRY_HIP(hipMemcpyAsync(S->values, values, sizeof(double) * S->F * n, hipMemcpyDeviceToDevice, s));
-    FT_TRY_HIP(hipMemsetAsync(S->counters, 0, 4 * sizeof(unsigned long long), s));
-
-    unsigned long long* flags = nullptr;
-    double* mm = nullptr;
-    int32_t* cnt = nullptr;
-    int32_t* ext = nullptr;
-    int64_t* tmp = nullptr;
-    ScratchGuard guard;
-    guard.add((void**)&flags);
-    guard.add((void**)&mm);
-    guard.add((void**)&cnt);
-    guard.add((void**)&ext);
-    guard.add((void**)&tmp);
-    FT_TRY(dev_alloc_n(&flags, 4));
-    FT_TRY_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned long long), s));
-    k_src_geom<D><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, S->values, S->F, S->rec, S->box, flags);
-    const int mmb = 256;
-    FT_TRY(dev_alloc_n(&mm, size_t(mmb) * D * 2));
-    k_minmax<<<mmb, 256, 0, s>>>(S->coords, n, D, mm);
-    FT_TRY_HIP(hipGetLastError());
-    unsigned long long hf[4];
-    std::vector<double> hmm(size_t(mmb) * D * 2);
-    FT_TRY_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
-    FT_TRY_HIP(hipMemcpyAsync(hmm.data(), mm, sizeof(double) * hmm.size(), hipMemcpyDeviceToHost, s));
-    FT_TRY_HIP(hipStreamSynchronize(s));
-    if (hf[0]) {
-        set_error("%llu source element(s) reference a node id outside [0, %lld)", hf[0], (long long)n);
-        return FT_E_MESH;
-    }
-    if (hf[1]) {
-        set_error("%llu degenerate source element(s): |det J| <= 1e-12 h^d", hf[1]);
-        return FT_E_MESH;
-    }
-    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, ext_max = 0.0;
-    for (int c = 0; c < D; ++c) {
-        lo[c] = INFINITY;
-        hi[c] = -INFINITY;
-        for (int b = 0; b < mmb; ++b) {
-            lo[c] = std::fmin(lo[c], hmm[(b * D + c) * 2]);
-            hi[c] = std::fmax(hi[c], hmm[(b * D + c) * 2 + 1]);
-        }
-        ext_max = std::fmax(ext_max, hi[c] - lo[c]);
-    }
-    // default bins: int(sqrt(E)) (2D) or round(cbrt(E/6)) (3D) along the longest axis
-    const double per_axis = D == 2 ? std::floor(std::sqrt(double(E))) : std::round(std::cbrt(double(E) / 6.0));
+    const int64_t n = S->n, E = S->E;
+    dev_free(S->bin_ptr);
+    dev_free(S->bin_elems);
+    S->bin_ptr = nullptr;
+    S->bin_elems = nullptr;
+    double ext_max = 0.0;
+    for (int c = 0; c < D; ++c) ext_max = std::fmax(ext_max, S->dom_hi[c] - S->dom_lo[c]);
     int64_t nbins = 1;
+    for (int c = 0; c < 3; ++c) {
+        S->nb[c] = 1;
+        S->lo[c] = 0.0;
+        S->inv_h[c] = 0.0;
+    }
     for (int c = 0; c < D; ++c) {
-        int32_t nb = bins && bins[c] > 0 ? bins[c] : 0;
-        if (nb == 0) {
-            const double ext = hi[c] - lo[c];
-            nb = int32_t(std::max(1.0, std::ceil(per_axis * (ext_max > 0 ? ext / ext_max : 1.0) - 1e-9)));
-        }
+        const double ext = S->dom_hi[c] - S->dom_lo[c];
+        int32_t nb = nb_in[c];
+        if (nb <= 0) nb = int32_t(std::max(1.0, std::ceil(per_axis * (ext_max > 0 ? ext / ext_max : 1.0) - 1e-9)));
         S->nb[c] = nb;
-        const double ext = hi[c] - lo[c];
-        S->lo[c] = lo[c];
+        S->lo[c] = S->dom_lo[c];
         S->inv_h[c] = ext > 0 ? double(nb) / ext : 0.0;
         nbins *= nb;
     }
@@ -325,6 +278,13 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
         g.lo[c] = S->lo[c];
         g.inv_h[c] = S->inv_h[c];
     }
+    int32_t* cnt = nullptr;
+    int32_t* ext = nullptr;
+    int64_t* tmp = nullptr;
+    ScratchGuard guard;
+    guard.add((void**)&cnt);
+    guard.add((void**)&ext);
+    guard.add((void**)&tmp);
     FT_TRY(dev_alloc_n(&cnt, size_t(nbins)));
     FT_TRY(dev_alloc_n(&tmp, size_t(scan_tmp_elems(nbins))));
     FT_TRY(dev_alloc_n(&S->bin_ptr, size_t(nbins + 1)));
@@ -348,6 +308,64 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     FT_TRY_HIP(hipGetLastError());
     FT_TRY_HIP(hipStreamSynchronize(s));
     return FT_OK;
+}
+
+
+template <int D>
+static ft_status build(ft_source* S, const double* coords, const int32_t* conn, const double* values,
+                       const int32_t* bins, hipStream_t s) {
+    constexpr int RS = RecSize<D>::value;
+    const int64_t n = S->n, E = S->E;
+    constexpr int B = 256;
+    FT_TRY(dev_alloc_n(&S->coords, size_t(D) * n));
+    FT_TRY(dev_alloc_n(&S->conn, size_t(E) * (D + 1)));
+    FT_TRY(dev_alloc_n(&S->values, size_t(S->F) * n));
+    FT_TRY(dev_alloc_n(&S->rec, size_t(E) * RS));
+    FT_TRY(dev_alloc_n(&S->box, size_t(E) * BoxSize<D>::value));
+    FT_TRY(dev_alloc_n(&S->counters, 4));
+    FT_TRY_HIP(hipHostMalloc((void**)&S->h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+    FT_TRY_HIP(hipMemcpyAsync(S->coords, coords, sizeof(double) * D * n, hipMemcpyDeviceToDevice, s));
+    FT_TRY_HIP(hipMemcpyAsync(S->conn, conn, sizeof(int32_t) * (D + 1) * E, hipMemcpyDeviceToDevice, s));
+    FT_TRY_HIP(hipMemcpyAsync(S->values, values, sizeof(double) * S->F * n, hipMemcpyDeviceToDevice, s));
+    FT_TRY_HIP(hipMemsetAsync(S->counters, 0, 4 * sizeof(unsigned long long), s));
+
+    unsigned long long* flags = nullptr;
+    double* mm = nullptr;
+    ScratchGuard guard;
+    guard.add((void**)&flags);
+    guard.add((void**)&mm);
+    FT_TRY(dev_alloc_n(&flags, 4));
+    FT_TRY_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned long long), s));
+    k_src_geom<D><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, S->values, S->F, S->rec, S->box, flags);
+    const int mmb = 256;
+    FT_TRY(dev_alloc_n(&mm, size_t(mmb) * D * 2));
+    k_minmax<<<mmb, 256, 0, s>>>(S->coords, n, D, mm);
+    FT_TRY_HIP(hipGetLastError());
+    unsigned long long hf[4];
+    std::vector<double> hmm(size_t(mmb) * D * 2);
+    FT_TRY_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipMemcpyAsync(hmm.data(), mm, sizeof(double) * hmm.size(), hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    if (hf[0]) {
+        set_error("%llu source element(s) reference a node id outside [0, %lld)", hf[0], (long long)n);
+        return FT_E_MESH;
+    }
+    if (hf[1]) {
+        set_error("%llu degenerate source element(s): |det J| <= 1e-12 h^d", hf[1]);
+        return FT_E_MESH;
+    }
+    for (int c = 0; c < D; ++c) {
+        S->dom_lo[c] = INFINITY;
+        S->dom_hi[c] = -INFINITY;
+        for (int b = 0; b < mmb; ++b) {
+            S->dom_lo[c] = std::fmin(S->dom_lo[c], hmm[(b * D + c) * 2]);
+            S->dom_hi[c] = std::fmax(S->dom_hi[c], hmm[(b * D + c) * 2 + 1]);
+        }
+    }
+    int32_t nb[3] = {0, 0, 0};
+    for (int c = 0; c < D; ++c) nb[c] = bins && bins[c] > 0 ? bins[c] : 0;
+    const double per_axis = D == 2 ? std::floor(std::sqrt(double(E))) : std::round(std::cbrt(double(E) / 6.0));
+    return build_bins<D>(S, nb, per_axis, s);
 }
 
 ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, const double* values,
@@ -382,6 +400,57 @@ static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const voi
         k_src_eval<D, P, true, true><<<grid, 256, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
+}
+
+// Bin-grid autotuner: for each candidate resolution, rebuild the bins and time
+// the evaluation of a sample of the real queries (two timed launches after a
+// warm-up); keep the fastest.  The tuning launches' out-of-domain counts are
+// discarded.
+template <int D>
+static ft_status autotune_impl(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec,
+                              int ncand, const int32_t* cand, hipStream_t s) {
+    const size_t esz = prec == FT_F64 ? 8 : 4;
+    unsigned char* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ScratchGuard guard;
+    guard.add((void**)&out);
+    FT_TRY(dev_alloc_n(&out, size_t(S->F) * size_t(npts) * esz));
+    FT_TRY_HIP(hipEventCreate(&e0));
+    FT_TRY_HIP(hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    int best = cand[0];
+    ft_status st = FT_OK;
+    const int32_t none[3] = {0, 0, 0};
+    for (int c = 0; c < ncand && st == FT_OK; ++c) {
+        st = build_bins<D>(S, none, double(cand[c]), s);
+        if (st != FT_OK) break;
+        st = launch_eval<D>(S, head, npts, pts, ld, prec, out, npts, nullptr, s);
+        if (hipEventRecord(e0, s) != hipSuccess) st = FT_E_DEVICE;
+        for (int r = 0; r < 2 && st == FT_OK; ++r) st = launch_eval<D>(S, head, npts, pts, ld, prec, out, npts, nullptr, s);
+        float ms = 0.0f;
+        if (st == FT_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
+            set_error("event timing failed while tuning the bin grid");
+            st = FT_E_DEVICE;
+        }
+        if (st == FT_OK && ms < best_ms) {
+            best_ms = ms;
+            best = cand[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FT_OK) return st;
+    FT_TRY(build_bins<D>(S, none, double(best), s));
+    FT_TRY_HIP(hipMemsetAsync(S->counters, 0, sizeof(unsigned long long), s));
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    return FT_OK;
+}
+
+ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, int ncand,
+                          const int32_t* cand, hipStream_t s) {
+    return S->dim == 2 ? autotune_impl<2>(S, head, npts, pts, ld, prec, ncand, cand, s)
+                       : autotune_impl<3>(S, head, npts, pts, ld, prec, ncand, cand, s);
 }
 
 ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out,

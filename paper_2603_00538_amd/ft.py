@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -
 
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
             "ft_consume_queries", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval",
-            "ft_source_eval_queries", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
+            "ft_source_eval_queries", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_last_error"]
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
         "ft_source_create_p1": (I32, [I32, I64, P, I64, P, I32, P, P, P, ctypes.POINTER(P)]),
         "ft_source_eval": (I32, [P, I64, P, I64, I32, P, I64, P, P]),
         "ft_source_eval_queries": (I32, [P, I64, I64, P, I64, I32, P, I64, P, P]),
+        "ft_source_autotune": (I32, [P, I64, I64, P, I64, I32, I32, P, P, P]),
         "ft_source_stats": (I32, [P, ctypes.POINTER(I64), P]),
         "ft_source_destroy": (I32, [P]),
         "ft_source_get_info": (I32, [P, ctypes.POINTER(SourceInfo)]),
@@ -173,6 +174,14 @@ def ft_batch_run(h, cfg: SolveCfg, x_ptrs, b_ptrs, stream, allow=(FT_E_NOCONV, F
     sts = (ctypes.c_int32 * K)()
     st = _check(load().ft_batch_run(h, ctypes.byref(cfg), xs, bs, reps, sts, stream), "ft_batch_run", allow)
     return st, [r.as_dict() for r in reps], list(sts)
+
+
+def ft_source_autotune(h, n_nodes, n_points, points_ptr, ld, precision, candidates, stream):
+    cand = (ctypes.c_int32 * len(candidates))(*candidates)
+    out = (ctypes.c_int32 * 3)()
+    _check(load().ft_source_autotune(h, n_nodes, n_points, points_ptr, ld, precision, len(candidates), cand, out,
+                                     stream), "ft_source_autotune")
+    return list(out)
 
 
 def ft_plan_create(t, s, cfg: SampleCfg, stream):
@@ -411,6 +420,14 @@ class Source:
                                ld, prec, _device_ptr(out, "out"), int(out.shape[1]),
                                _device_ptr(ids, "ids") if ids is not None else None, current_stream())
         return out
+
+    def autotune(self, points, n_nodes, candidates):
+        """Pick the bin grid that evaluates this (d, Q) query sample fastest; returns the cells per axis."""
+        torch = _torch()
+        prec = FT_F32 if points.dtype == torch.float32 else FT_F64
+        ptr = _device_ptr(points, "points", (torch.float32, torch.float64))
+        return ft_source_autotune(self.handle, int(n_nodes), int(points.shape[1]), ptr, int(points.shape[1]), prec,
+                                  list(candidates), current_stream())
 
     @property
     def info(self):

@@ -413,3 +413,22 @@ def test_refinement_solve_matches_binary64_solve(c1):
     assert one.reports[0]["rel_resid"] < 1e-4
     T.close()
     S.close()
+
+
+def test_bin_autotune_keeps_results(c1):
+    """The autotuner only changes the bin grid: values and ids stay those of the rule."""
+    w, tm, sm, sv = c1
+    S = ft.Source(*sm, sv)
+    pts = torch.as_tensor(oracle_query_points(tm, 16, w.philox_seed, 0), device="cuda")
+    n = tm[0].shape[0]
+    ids0 = torch.empty(pts.shape[1], dtype=torch.int32, device="cuda")
+    v0 = S.eval_query_list(pts, n, ids=ids0).clone()
+    chosen = S.autotune(pts[:, : n + 4000].contiguous(), n, [8, 24, 48, 97, 160])
+    log(f"autotune chose bins {chosen}")
+    assert chosen[0] in (8, 24, 48, 97, 160) or chosen[1] in (8, 24, 48, 97, 160)
+    assert list(S.info.bins)[:2] == chosen[:2]
+    assert S.take_out_of_domain() == 0
+    ids1 = torch.empty_like(ids0)
+    v1 = S.eval_query_list(pts, n, ids=ids1)
+    assert torch.equal(v0, v1) and torch.equal(ids0, ids1)
+    S.close()
