@@ -285,6 +285,8 @@ def main():
                          "fused: ft_transfer_p1 (built-in source, no query list)")
     ap.add_argument("--no-fused", action="store_true", help="skip the extra fused-route measurement")
     ap.add_argument("--bins", type=int, default=0, help="source bin cells per axis (0: the workload's choice)")
+    ap.add_argument("--autotune", default="auto", choices=["auto", "on", "off"],
+                    help="tune the source bin grid on a sample of the queries (auto: when the workload fixes none)")
     ap.add_argument("--sequential", action="store_true",
                     help="multi-field workloads: also time F sequential one-field FP64 transfers")
     args = ap.parse_args()
@@ -333,6 +335,23 @@ def main():
     setup_s = time.perf_counter() - t0
     log(f"setup {setup_s * 1e3:.1f} ms; nnz {T.info.nnz}")
     Q = T.query_count(N)
+    tuned = None
+    if args.autotune == "on" or (args.autotune == "auto" and bins is None):
+        # sample: the node block and the first elements' samples of this transfer's query list
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m = min(Q, n + max(N, (4_000_000 // N) * N))
+        sample = torch.empty((dim, Q), dtype=dt_, device=dev)
+        T.sample_points(ft.SampleCfg(N, F, w.alpha, w.philox_seed, 0, prec), out=sample)
+        sample = sample[:, :m].contiguous()
+        base = int(S.info.bins[0])
+        cands = sorted({max(4, int(round(base * f))) for f in (0.6, 0.75, 0.9, 1.0, 1.15, 1.3)})
+        tuned = {"candidates": cands, "chosen": S.autotune(sample, n, cands)[:dim],
+                 "sample_queries": m, "ms": 0.0}
+        del sample
+        torch.cuda.synchronize()
+        tuned["ms"] = (time.perf_counter() - t0) * 1e3
+        log(f"autotuned bins {tuned['chosen']} from {cands} in {tuned['ms']:.0f} ms")
     cfg = ft.SampleCfg(N, F, w.alpha, w.philox_seed, 0, prec)
     pts = torch.empty((dim, Q), dtype=dt_, device=dev)
     vals = torch.empty((F, Q), dtype=dt_, device=dev)
@@ -466,6 +485,8 @@ def main():
         out["fused_route"] = extra_route
     if plan_route is not None:
         out["plan_route"] = plan_route
+    if tuned is not None:
+        out["bin_autotune"] = tuned
     out["config"]["bins"] = [int(si.bins[c]) for c in range(dim)]
     out["config"]["bin_registrations"] = int(si.n_registrations)
     S.close()

@@ -202,7 +202,8 @@ ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
  *   conn           device, int32, [n_elems][dim+1]
  *   nodal_values   device, binary64, [n_fields][n_nodes]
  *   bins           host, [dim] cells per axis, or null / zeros for the default
- *                  int(sqrt(n_elems)) per axis in 2D, round(cbrt(n_elems/6)) in 3D
+ *                  int(sqrt(n_elems)) along the longest axis in 2D,
+ *                  round(0.75 cbrt(n_elems/6)) in 3D (ft_source_autotune refines it)
  * Localization rule: the element maximizing min_k mu_k(x) (mu: barycentric
  * coordinates); exact ties go to the lowest element id; a best min mu below
  * -1e-10 counts as out of domain and is evaluated by extrapolation from that

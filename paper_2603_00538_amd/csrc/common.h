@@ -210,7 +210,7 @@ struct ft_source {
     double* rec = nullptr;      // [E][RS]: origin + inverse Jacobian (barycentric map)
     float* box = nullptr;       // [E][8 | 6] outward-rounded boxes (2D also x+y, x-y ranges)
     int32_t nb[3] = {1, 1, 1};  // bins per axis
-    int32_t ext[3] = {0, 0, 0}; // largest element extent in bins minus one, per axis
+    double hx[3] = {0, 0, 0};   // largest half-extent of an element box per axis (enlarged)
     double dom_lo[3] = {0, 0, 0}, dom_hi[3] = {0, 0, 0};   // bounding box of the source nodes
     double lo[3] = {0, 0, 0};   // grid origin
     double inv_h[3] = {1, 1, 1};// bins per unit length

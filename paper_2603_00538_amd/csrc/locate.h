@@ -8,10 +8,10 @@
 // whose best element has min mu > 1e-12 is strictly inside it: no other
 // element can tie or win, and rounding (far below 1e-12) cannot change that.
 //
-// Search.  Every element is registered once, in the bin holding the lower
-// corner of its box; with ext the largest element extent in bins (minus one)
-// per axis, the elements that can meet a region of bins [lo, hi] are those
-// registered in [lo - ext, hi].  The points of a wave (64 lanes x P points)
+// Search.  Every element is registered once, in the bin holding the centre
+// of its box; with hx the largest half-extent of an element box per axis, the
+// elements that can meet a region [lo, hi] are registered in the bins of
+// [lo - hx, hi + hx].  The points of a wave (64 lanes x P points)
 // are usually samples of one target element, so they share a handful of bins.
 // The wave forms its points' bounding box (and, in 2D, their ranges of x+y
 // and x-y: an octagon) and the bins that can hold candidates; lanes load
@@ -79,9 +79,9 @@ __device__ __forceinline__ float f32_up(double x) {
 
 struct GridView {
     int32_t nb[3];
-    int32_t ext[3];   // largest element extent in bins minus one, per axis
     double lo[3];
     double inv_h[3];
+    double hx[3];   // largest half-extent of an element's box, per axis (slightly enlarged)
 };
 
 // Bin index along axis c; monotone in x, so a point inside a box always maps
@@ -180,12 +180,12 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
     int hi[3] = {0, 0, 0}, lo[3] = {0, 0, 0};
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-        hi[c] = bin_of(p[c], c, S.g);
-        lo[c] = max(hi[c] - S.g.ext[c], 0);
+        lo[c] = bin_of(p[c] - S.g.hx[c], c, S.g);
+        hi[c] = bin_of(p[c] + S.g.hx[c], c, S.g);
     }
     best = -DBL_MAX;
     bid = INT_MAX;
-    // every element overlapping p's bin has its first bin in [hi - ext, hi]
+    // an element whose box holds p has its box centre within hx of p
     for (int bz = lo[2]; bz <= hi[2]; ++bz)
         for (int by = lo[1]; by <= hi[1]; ++by)
             for (int bx = lo[0]; bx <= hi[0]; ++bx) {
@@ -235,9 +235,9 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             }
         wlo[c] = uniform_double(wave_min(lo));
         whi[c] = uniform_double(wave_max(hi));
-        // elements meeting the wave's box have their first bin in [bin(lo) - ext, bin(hi)]
-        b0[c] = uniform_int(max(bin_of(wlo[c], c, S.g) - S.g.ext[c], 0));
-        b1[c] = uniform_int(bin_of(whi[c], c, S.g));
+        // elements meeting the wave's box have their box centre within hx of it
+        b0[c] = uniform_int(bin_of(wlo[c] - S.g.hx[c], c, S.g));
+        b1[c] = uniform_int(bin_of(whi[c] + S.g.hx[c], c, S.g));
         span *= b1[c] - b0[c] + 1;
     }
     // inactive points start above the acceptance threshold so that the

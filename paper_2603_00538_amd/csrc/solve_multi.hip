@@ -10,8 +10,8 @@
 // updating while the others continue.
 //
 // Reductions without atomics: each block writes one partial per field (its
-// lanes of that field, in a fixed order); a one-block kernel adds the partials
-// of every field in block order and updates that field's CG scalars.  One
+// lanes of that field, in a fixed order); a kernel with one block per field
+// adds that field's partials in block order and updates its CG scalars.  One
 // iteration is four launches: (direction p = z + beta p_old formed on the fly,
 // q = M p, partial p.q), (alpha), (update y, r, z, partial r.z, r.r),
 // (stopping test, beta for the next direction).
@@ -24,11 +24,10 @@
 namespace ft {
 
 constexpr int MB = 256;               // threads per block
-constexpr int MAX_MBLOCKS = 512;
+constexpr int MAX_MBLOCKS = 4096;   // enough waves to cover the gather latency at 64 fields
 
 enum { PM_BB = 0, PM_SB, PM_RZ, PM_RR, PM_PQ, PM_TRR, PM_MX, PM_COUNT };
-enum { SC_RHO = 0, SC_ALPHA, SC_BETA, SC_TOL2, SC_DONE, SC_ITERS, SC_BB, SC_SUMB, SC_INTX, SC_TRR, SC_ALL,
-       SC_COUNT };
+enum { SC_RHO = 0, SC_ALPHA, SC_BETA, SC_TOL2, SC_DONE, SC_ITERS, SC_BB, SC_SUMB, SC_INTX, SC_TRR, SC_COUNT };
 
 struct MView {
     const int64_t* rowptr;
@@ -69,13 +68,6 @@ __device__ __forceinline__ void field_partials(const MView& A, const double (&v)
             part[(int64_t(slot[k]) * A.Fp + f) * gridDim.x + blockIdx.x] = s;
         }
     }
-}
-
-__device__ __forceinline__ double field_total(const MView& A, const double* __restrict__ part, int slot, int f,
-                                              int nb) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t(slot) * A.Fp + f) * nb + b];
-    return s;
 }
 
 __global__ __launch_bounds__(MB) void k_m_transpose_in(const double* __restrict__ src, int64_t n, int F, int Fp,
@@ -130,62 +122,82 @@ __global__ __launch_bounds__(MB) void k_m_init(MView A, double* __restrict__ Y, 
     field_partials<2>(A, v, slot, part);
 }
 
-// Per-field scalar updates from the partials (one block; thread f = field).
+// Sum of one field's nb block partials of a slot, in block order (every
+// thread of the block returns it).
+__device__ __forceinline__ double field_block_total(const MView& A, const double* __restrict__ part, int slot, int f,
+                                                    int nb) {
+    __shared__ double sm[MB / 64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += MB) s += part[(int64_t(slot) * A.Fp + f) * nb + b];
+    s = wave_sum_xor(s, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = sm[0];
+    for (int w = 1; w < MB / 64; ++w) t += sm[w];
+    __syncthreads();
+    return t;
+}
+
+// Per-field scalar updates from the partials (one block per field).
 //   mode 0: after k_m_rhs   -> ||b||^2, sum b, threshold, reset
 //   mode 1: after r.z, r.r  -> stopping test, beta = rz / rho (0 at k = 0), rho = rz
 //   mode 2: after p.q       -> alpha = rho / pq
 //   mode 3: after k_m_report -> true residual, m^T x
 __global__ __launch_bounds__(MB) void k_m_scalars(MView A, int mode, int k, int nb, double rtol2,
                                                   const double* __restrict__ part, double* __restrict__ sc) {
-    const int f = threadIdx.x;
-    __shared__ int not_done;
-    if (threadIdx.x == 0) not_done = 0;
-    __syncthreads();
-    if (f < A.F) {
-        const int Fp = A.Fp;
-        if (mode == 0) {
-            const double bb = field_total(A, part, PM_BB, f, nb);
+    const int f = blockIdx.x;
+    const int Fp = A.Fp;
+    if (mode == 0) {
+        const double bb = field_block_total(A, part, PM_BB, f, nb);
+        const double sb = field_block_total(A, part, PM_SB, f, nb);
+        if (threadIdx.x == 0) {
             sc[SC_BB * Fp + f] = bb;
-            sc[SC_SUMB * Fp + f] = field_total(A, part, PM_SB, f, nb);
+            sc[SC_SUMB * Fp + f] = sb;
             sc[SC_TOL2 * Fp + f] = rtol2 * bb;
             sc[SC_DONE * Fp + f] = 0.0;
             sc[SC_ITERS * Fp + f] = 0.0;
             sc[SC_BETA * Fp + f] = 0.0;
             sc[SC_ALPHA * Fp + f] = 0.0;
-            not_done = 1;
-        } else if (mode == 1) {
-            if (sc[SC_DONE * Fp + f] == 0.0) {
-                const double rz = field_total(A, part, PM_RZ, f, nb);
-                const double rr = field_total(A, part, PM_RR, f, nb);
-                if (rr <= sc[SC_TOL2 * Fp + f] || !isfinite(rr)) {
-                    sc[SC_DONE * Fp + f] = 1.0;
-                    sc[SC_ITERS * Fp + f] = double(k);
-                } else {
-                    sc[SC_BETA * Fp + f] = k == 0 ? 0.0 : rz / sc[SC_RHO * Fp + f];
-                    sc[SC_RHO * Fp + f] = rz;
-                    sc[SC_ITERS * Fp + f] = double(k);
-                    atomicOr(&not_done, 1);
-                }
+        }
+    } else if (mode == 1) {
+        if (sc[SC_DONE * Fp + f] != 0.0) return;   // block-uniform
+        const double rz = field_block_total(A, part, PM_RZ, f, nb);
+        const double rr = field_block_total(A, part, PM_RR, f, nb);
+        if (threadIdx.x == 0) {
+            sc[SC_ITERS * Fp + f] = double(k);
+            if (rr <= sc[SC_TOL2 * Fp + f] || !isfinite(rr)) {
+                sc[SC_DONE * Fp + f] = 1.0;
+            } else {
+                sc[SC_BETA * Fp + f] = k == 0 ? 0.0 : rz / sc[SC_RHO * Fp + f];
+                sc[SC_RHO * Fp + f] = rz;
             }
-        } else if (mode == 2) {
-            if (sc[SC_DONE * Fp + f] == 0.0) {
-                sc[SC_ALPHA * Fp + f] = sc[SC_RHO * Fp + f] / field_total(A, part, PM_PQ, f, nb);
-                atomicOr(&not_done, 1);
-            }
-        } else {
-            sc[SC_TRR * Fp + f] = field_total(A, part, PM_TRR, f, nb);
-            sc[SC_INTX * Fp + f] = field_total(A, part, PM_MX, f, nb);
+        }
+    } else if (mode == 2) {
+        if (sc[SC_DONE * Fp + f] != 0.0) return;
+        const double pq = field_block_total(A, part, PM_PQ, f, nb);
+        if (threadIdx.x == 0) sc[SC_ALPHA * Fp + f] = sc[SC_RHO * Fp + f] / pq;
+    } else {
+        const double trr = field_block_total(A, part, PM_TRR, f, nb);
+        const double mx = field_block_total(A, part, PM_MX, f, nb);
+        if (threadIdx.x == 0) {
+            sc[SC_TRR * Fp + f] = trr;
+            sc[SC_INTX * Fp + f] = mx;
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && mode != 3) sc[SC_ALL * A.Fp] = not_done ? 0.0 : 1.0;
+}
+
+// true when every field has converged (wave-uniform scalar loads)
+__device__ __forceinline__ bool all_done(const MView& A, const double* __restrict__ sc) {
+    for (int f = 0; f < A.F; ++f)
+        if (sc[SC_DONE * A.Fp + f] == 0.0) return false;
+    return true;
 }
 
 // direction and product: P_new = Z + beta P_old (own rows), Q = M P; partial p.q
 __global__ __launch_bounds__(MB) void k_m_spmv(MView A, const double* __restrict__ Z, const double* __restrict__ Pold,
                                                double* __restrict__ Pnew, double* __restrict__ Qv,
                                                const double* __restrict__ sc, double* __restrict__ part) {
-    if (sc[SC_ALL * A.Fp] != 0.0) return;
+    if (all_done(A, sc)) return;
     double v[1] = {0.0};
     {
         FOR_ROWS(A, i, f) {
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(MB) void k_m_spmv(MView A, const double* __restrict
 __global__ __launch_bounds__(MB) void k_m_update(MView A, const double* __restrict__ P, const double* __restrict__ Qv,
                                                  double* __restrict__ Y, double* __restrict__ R, double* __restrict__ Z,
                                                  const double* __restrict__ sc, double* __restrict__ part) {
-    if (sc[SC_ALL * A.Fp] != 0.0) return;
+    if (all_done(A, sc)) return;
     double v[2] = {0.0, 0.0};
     {
         FOR_ROWS(A, i, f) {
@@ -289,9 +301,9 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
     k_m_transpose_in<<<gt, MB, 0, s>>>(T->g, n, F, Fp, G);
     k_m_transpose_in<<<gt, MB, 0, s>>>(T->bres, n, F, Fp, R);
     k_m_rhs<<<nb, MB, 0, s>>>(A, G, alpha, R, B, part);
-    k_m_scalars<<<1, 64, 0, s>>>(A, 0, 0, nb, cfg->rtol * cfg->rtol, part, sc);
+    k_m_scalars<<<F, MB, 0, s>>>(A, 0, 0, nb, cfg->rtol * cfg->rtol, part, sc);
     k_m_init<<<nb, MB, 0, s>>>(A, Y, R, Z, P, part);
-    k_m_scalars<<<1, 64, 0, s>>>(A, 1, 0, nb, 0.0, part, sc);
+    k_m_scalars<<<F, MB, 0, s>>>(A, 1, 0, nb, 0.0, part, sc);
     FT_TRY_HIP(hipGetLastError());
     int launched = 0, chunk = 8;
     while (launched < cfg->max_iter) {
@@ -301,20 +313,22 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
             double* Pold = P + ((kk & 1) ? n * Fp : 0);
             double* Pnew = P + ((kk & 1) ? 0 : n * Fp);
             k_m_spmv<<<nb, MB, 0, s>>>(A, Z, Pold, Pnew, Qv, sc, part);
-            k_m_scalars<<<1, 64, 0, s>>>(A, 2, kk, nb, 0.0, part, sc);
+            k_m_scalars<<<F, MB, 0, s>>>(A, 2, kk, nb, 0.0, part, sc);
             k_m_update<<<nb, MB, 0, s>>>(A, Pnew, Qv, Y, R, Z, sc, part);
-            k_m_scalars<<<1, 64, 0, s>>>(A, 1, kk + 1, nb, 0.0, part, sc);
+            k_m_scalars<<<F, MB, 0, s>>>(A, 1, kk + 1, nb, 0.0, part, sc);
         }
         launched += k;
         FT_TRY_HIP(hipGetLastError());
         FT_TRY_HIP(hipMemcpyAsync(h.data(), sc, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
         FT_TRY_HIP(hipStreamSynchronize(s));
-        if (h[SC_ALL * Fp] != 0.0) break;
+        bool done_all = true;
+        for (int f = 0; f < F; ++f) done_all &= h[SC_DONE * Fp + f] != 0.0;
+        if (done_all) break;
         chunk = 4;
     }
     k_m_solution<<<nb, MB, 0, s>>>(A, G, alpha, Y);
     k_m_report<<<nb, MB, 0, s>>>(A, B, Y, part);
-    k_m_scalars<<<1, 64, 0, s>>>(A, 3, 0, nb, 0.0, part, sc);
+    k_m_scalars<<<F, MB, 0, s>>>(A, 3, 0, nb, 0.0, part, sc);
     const unsigned go = grid_for(n * F, MB);
     k_m_transpose_out<<<go, MB, 0, s>>>(Y, n, F, Fp, x);
     if (b_out) k_m_transpose_out<<<go, MB, 0, s>>>(B, n, F, Fp, b_out);

@@ -11,13 +11,14 @@
 // origin, its barycentric map (absolute affine form, whose gradients g_1..g_D
 // are the rows of the inverse of J = [x1-x0 | ... | xd-x0]) and, for one
 // field, its vertex values (see locate.h); plus an outward-rounded binary32
-// bounding box.  Each element is registered once, in the bin holding the lower
-// corner of its box (CSR, ascending ids per bin); the largest box extent in
-// bins tells a search how far below a region's bins to look.
+// bounding box.  Each element is registered once, in the bin holding the
+// centre of its box (CSR, ascending ids per bin); the largest half-extent of a
+// box tells a search how far around a region to look.
 
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "locate.h"
@@ -141,11 +142,16 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
     }
 }
 
-template <int D>
-__device__ __forceinline__ void elem_bin_range(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
-                                               int64_t e, const GridView& g, int (&b0)[3], int (&b1)[3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) { b0[c] = 0; b1[c] = 0; }
+// Each element is registered once, in the bin of its box centre; the count
+// pass also records the largest half-extent of a box per axis (as the bits of
+// a non-negative double, whose integer order is the numeric order).
+template <int D, bool FILL>
+__global__ void k_src_register(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
+                               GridView g, int32_t* __restrict__ cnt, const int64_t* __restrict__ ptr,
+                               int32_t* __restrict__ elems, unsigned long long* __restrict__ hx) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int bc[3] = {0, 0, 0};
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         double lo = INFINITY, hi = -INFINITY;
@@ -155,26 +161,12 @@ __device__ __forceinline__ void elem_bin_range(const double* __restrict__ X, int
             lo = fmin(lo, xv);
             hi = fmax(hi, xv);
         }
-        b0[c] = bin_of(lo, c, g);
-        b1[c] = bin_of(hi, c, g);
+        bc[c] = bin_of(0.5 * (lo + hi), c, g);
+        if (!FILL) atomicMax(&hx[c], __double_as_longlong(0.5 * (hi - lo)));
     }
-}
-
-// Each element is registered once, in the bin of its box's lower corner; the
-// count pass also records the largest box extent in bins per axis.
-template <int D, bool FILL>
-__global__ void k_src_register(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
-                               GridView g, int32_t* __restrict__ cnt, const int64_t* __restrict__ ptr,
-                               int32_t* __restrict__ elems, int32_t* __restrict__ ext) {
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    int b0[3], b1[3];
-    elem_bin_range<D>(X, n, conn, e, g, b0, b1);
-    const int64_t b = (int64_t(b0[2]) * g.nb[1] + b0[1]) * g.nb[0] + b0[0];
+    const int64_t b = (int64_t(bc[2]) * g.nb[1] + bc[1]) * g.nb[0] + bc[0];
     if (!FILL) {
         atomicAdd(&cnt[b], 1);
-#pragma unroll
-        for (int c = 0; c < D; ++c) atomicMax(&ext[c], b1[c] - b0[c]);
     } else {
         const int pos = atomicAdd(&cnt[b], 1);
         elems[ptr[b] + pos] = int32_t(e);
@@ -279,27 +271,32 @@ static ft_status build_bins(ft_source* S, const int32_t (&nb_in)[3], double per_
         g.inv_h[c] = S->inv_h[c];
     }
     int32_t* cnt = nullptr;
-    int32_t* ext = nullptr;
+    unsigned long long* hxb = nullptr;
     int64_t* tmp = nullptr;
     ScratchGuard guard;
     guard.add((void**)&cnt);
-    guard.add((void**)&ext);
+    guard.add((void**)&hxb);
     guard.add((void**)&tmp);
     FT_TRY(dev_alloc_n(&cnt, size_t(nbins)));
     FT_TRY(dev_alloc_n(&tmp, size_t(scan_tmp_elems(nbins))));
     FT_TRY(dev_alloc_n(&S->bin_ptr, size_t(nbins + 1)));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
-    FT_TRY(dev_alloc_n(&ext, 3));
-    FT_TRY_HIP(hipMemsetAsync(ext, 0, sizeof(int32_t) * 3, s));
-    k_src_register<D, false><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, nullptr, nullptr, ext);
+    FT_TRY(dev_alloc_n(&hxb, 3));
+    FT_TRY_HIP(hipMemsetAsync(hxb, 0, sizeof(unsigned long long) * 3, s));
+    k_src_register<D, false><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, nullptr, nullptr, hxb);
     FT_TRY(exclusive_scan(cnt, S->bin_ptr, nbins, tmp, s));
     int64_t nreg = 0;
-    int32_t hext[3] = {0, 0, 0};
+    unsigned long long hbits[3] = {0, 0, 0};
     FT_TRY_HIP(hipMemcpyAsync(&nreg, S->bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    FT_TRY_HIP(hipMemcpyAsync(hext, ext, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipMemcpyAsync(hbits, hxb, sizeof(hbits), hipMemcpyDeviceToHost, s));
     FT_TRY_HIP(hipStreamSynchronize(s));
     S->n_reg = nreg;
-    for (int c = 0; c < 3; ++c) S->ext[c] = c < D ? hext[c] : 0;
+    for (int c = 0; c < 3; ++c) {
+        double h = 0.0;
+        std::memcpy(&h, &hbits[c], sizeof(h));
+        // enlarged so that rounding of box centres and of the search bounds cannot drop an element
+        S->hx[c] = c < D ? h * (1.0 + 1e-9) + 1e-300 : 0.0;
+    }
     FT_TRY(dev_alloc_n(&S->bin_elems, size_t(nreg)));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nbins, s));
     k_src_register<D, true><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, g, cnt, S->bin_ptr, S->bin_elems,
@@ -364,7 +361,11 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     }
     int32_t nb[3] = {0, 0, 0};
     for (int c = 0; c < D; ++c) nb[c] = bins && bins[c] > 0 ? bins[c] : 0;
-    const double per_axis = D == 2 ? std::floor(std::sqrt(double(E))) : std::round(std::cbrt(double(E) / 6.0));
+    // default cells along the longest axis: int(sqrt(E)) in 2D (sec. 5.3); in 3D
+    // about 0.75 of the cube-root of E/6 (a Kuhn-split hex per 0.4 bins): with
+    // centre registration the region a wavefront searches must stay within 64 bins
+    const double per_axis = D == 2 ? std::floor(std::sqrt(double(E)))
+                                   : std::max(1.0, std::round(0.75 * std::cbrt(double(E) / 6.0)));
     return build_bins<D>(S, nb, per_axis, s);
 }
 
@@ -377,7 +378,7 @@ SrcView source_view(const ft_source* S) {
     SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
-        v.g.ext[c] = S->ext[c];
+        v.g.hx[c] = S->hx[c];
         v.g.lo[c] = S->lo[c];
         v.g.inv_h[c] = S->inv_h[c];
     }
