@@ -10,14 +10,16 @@
 // barycentric weights.  Matrix-core products are split into hi + lo parts,
 //   r lambda ~ r_hi lambda_hi + r_hi lambda_lo + r_lo lambda_hi
 // (three MFMAs, FP32 accumulation), which keeps about 22 bits (f16) or 16 bits
-// (bf16) of each product.  For f16 every field row is first scaled by a power
-// of two so that its largest residual sits in [2^13, 2^14) (exact, undone on
-// output); bf16 shares the binary32 exponent range and needs no scaling.
+// (bf16) of each product.  For f16 every field row of a K step is first
+// scaled by a power of two so that its largest residual sits in [2^13, 2^14)
+// (exact, undone when the step's products are added to binary64 running
+// sums); bf16 shares the binary32 exponent range and needs no scaling.
 //
 // One wavefront per element; the block's four waves stage their lambda
-// (recomputed from the same Philox counters as the emission, binary32 form)
-// and the control values in LDS.  Every element sum is a fixed sequence of
-// MFMAs, so results are reproducible run to run.
+// (recomputed from the same Philox counters as the emission, binary32 form),
+// the control values and a chunk of query values in LDS.  Every element sum
+// is a fixed sequence of MFMAs and binary64 adds, so results are reproducible
+// run to run.
 #include "sampling.h"
 
 namespace ft {
@@ -57,6 +59,13 @@ struct Split<true> {
     }
 };
 
+// One wavefront per element.  Values are read a field row at a time (64
+// consecutive samples, one per lane: fully coalesced) into the wave's LDS
+// chunk, then read back in the MFMA operand layout; every K step of 32
+// samples gets its own power-of-two row scaling (f16), and its products are
+// unscaled into binary64 running sums, so memory is read once.
+constexpr int MF_CHUNK = 64;   // samples staged per chunk (two K steps)
+
 template <int D, bool BF16>
 __global__ __launch_bounds__(256) void k_consume_mfma(const float* __restrict__ values, int64_t ld, int F,
                                                       const int32_t* __restrict__ conn, const double* __restrict__ vol,
@@ -66,6 +75,7 @@ __global__ __launch_bounds__(256) void k_consume_mfma(const float* __restrict__ 
     using S = Split<BF16>;
     __shared__ float lam_s[4][MF_NMAX][4];
     __shared__ float g_s[4][4][64];
+    __shared__ float r_s[4][16][MF_CHUNK + 1];   // +1: row stride off the bank period
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * 4u + uint32_t(w);
@@ -93,68 +103,72 @@ __global__ __launch_bounds__(256) void k_consume_mfma(const float* __restrict__ 
     __syncthreads();
 
     const int sg = lane >> 4;            // sample group within a K step (8 samples)
-    const int col = lane & 15;           // B / C column: barycentric index when < d+1
+    const int col = lane & 15;           // A row (field in the tile) / B, C column
     const int64_t qbase = n + int64_t(tt) * N;
-    const int ksteps = int((N + 31) / 32);
     unsigned int nf = 0;
     const double scale_out = valid ? vol[tt] / double(N) : 0.0;
     for (int f0 = 0; f0 < F; f0 += 16) {
-        const int f = f0 + (lane & 15);  // A row: field
-        const bool frow = valid && f < F;
-        // pass 1: largest residual magnitude of this field row (f16 scaling)
-        float mx = 0.0f;
-        if (!BF16) {
-            for (int ks = 0; ks < ksteps; ++ks)
+        double run[4] = {0.0, 0.0, 0.0, 0.0};   // C[4 sg + i][col], unscaled
+        for (uint32_t c0 = 0; c0 < N; c0 += MF_CHUNK) {
+            // coalesced: row r's samples c0 .. c0+63, one per lane
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t j = c0 + uint32_t(lane);
+                float y = 0.0f;
+                if (valid && f0 + r < F && j < N) {
+                    y = values[int64_t(f0 + r) * ld + qbase + j];
+                    nf += !isfinite(y);
+                }
+                r_s[w][r][lane] = y;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int ks = 0; ks < MF_CHUNK / 32; ++ks) {
+                if (c0 + uint32_t(ks * 32) >= N) break;   // wave-uniform: no samples left in this chunk
+                const uint32_t jb = c0 + uint32_t(ks * 32 + sg * 8);
+                const int f = f0 + col;
+                float rv[8];
+                float mx = 0.0f;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const uint32_t j = uint32_t(ks * 32 + sg * 8 + i);
-                    if (frow && j < N) {
-                        const float y = values[int64_t(f) * ld + qbase + j];
+                    const uint32_t j = jb + uint32_t(i);
+                    float r = 0.0f;
+                    if (valid && f < F && j < N) {
                         float gx = 0.0f;
 #pragma unroll
                         for (int k = 0; k <= D; ++k) gx = fmaf(lam_s[w][j][k], g_s[w][k][f & 63], gx);
-                        const float r = y - alpha * gx;
-                        mx = fmaxf(mx, fabsf(r));
+                        r = r_s[w][col][ks * 32 + sg * 8 + i] - alpha * gx;
                     }
+                    rv[i] = r;
+                    mx = fmaxf(mx, fabsf(r));
                 }
-            mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-            mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-        }
-        int e = 0;
-        if (!BF16 && mx > 0.0f && isfinite(mx)) e = 13 - ilogbf(mx);
-        const float sc = ldexpf(1.0f, e);
-        // pass 2: split products on the matrix cores
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int ks = 0; ks < ksteps; ++ks) {
-            typename S::vec ahi, alo, bhi, blo;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const uint32_t j = uint32_t(ks * 32 + sg * 8 + i);
-                float r = 0.0f;
-                if (frow && j < N) {
-                    const float y = values[int64_t(f) * ld + qbase + j];
-                    nf += !isfinite(y);
-                    float gx = 0.0f;
-#pragma unroll
-                    for (int k = 0; k <= D; ++k) gx = fmaf(lam_s[w][j][k], g_s[w][k][f & 63], gx);
-                    r = (y - alpha * gx) * sc;
+                int e = 0;
+                if (!BF16) {   // row maximum over this K step's 32 samples -> [2^13, 2^14)
+                    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+                    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+                    if (mx > 0.0f && isfinite(mx)) e = 13 - ilogbf(mx);
                 }
-                S::set(ahi, alo, i, r);
-                const float lv = (col <= D && j < MF_NMAX) ? lam_s[w][j < MF_NMAX ? j : 0][col & 3] : 0.0f;
-                S::set(bhi, blo, i, lv);
+                const float sc = ldexpf(1.0f, e);
+                typename S::vec ahi, alo, bhi, blo;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t j = jb + uint32_t(i);
+                    S::set(ahi, alo, i, rv[i] * sc);
+                    const float lv = (col <= D && j < MF_NMAX) ? lam_s[w][j < MF_NMAX ? j : 0][col & 3] : 0.0f;
+                    S::set(bhi, blo, i, lv);
+                }
+                v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = S::mma(ahi, bhi, acc);
+                acc = S::mma(ahi, blo, acc);
+                acc = S::mma(alo, bhi, acc);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) run[i] += ldexp(double(acc[i]), -__shfl(e, 4 * sg + i, 64));
             }
-            acc = S::mma(ahi, bhi, acc);
-            acc = S::mma(ahi, blo, acc);
-            acc = S::mma(alo, bhi, acc);
+            __builtin_amdgcn_wave_barrier();
         }
         // C[row][col]: row = 4*sg + i (field f0 + row), col = barycentric index
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int row = 4 * sg + i;
-            const int er = __shfl(e, row, 64);
-            const int fo = f0 + row;
-            if (valid && col <= D && fo < F)
-                beta[(int64_t(fo) * E + tt) * (D + 1) + col] = ldexp(double(acc[i]), -er) * scale_out;
+            const int fo = f0 + 4 * sg + i;
+            if (valid && col <= D && fo < F) beta[(int64_t(fo) * E + tt) * (D + 1) + col] = run[i] * scale_out;
         }
     }
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);

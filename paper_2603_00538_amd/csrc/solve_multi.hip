@@ -193,28 +193,51 @@ __device__ __forceinline__ bool all_done(const MView& A, const double* __restric
     return true;
 }
 
-// direction and product: P_new = Z + beta P_old (own rows), Q = M P; partial p.q
-__global__ __launch_bounds__(MB) void k_m_spmv(MView A, const double* __restrict__ Z, const double* __restrict__ Pold,
+// direction and product over this thread's rows: P_new = Z + beta P_old (own
+// rows), Q = M P; returns the partial of p.q.  WAVE_ROW (64 fields): a
+// wavefront owns one row, so the row index and its matrix entries are
+// wave-uniform and load through the scalar cache.
+template <bool WAVE_ROW>
+__device__ __forceinline__ double spmv_rows(const MView& A, const int64_t* __restrict__ rowptr,
+                                            const int32_t* __restrict__ colidx, const double* __restrict__ val,
+                                            const double* __restrict__ Z, const double* __restrict__ Pold,
+                                            double* __restrict__ Pnew, double* __restrict__ Qv,
+                                            const double* __restrict__ sc) {
+    const int f = int(threadIdx.x) & (A.Fp - 1);
+    int64_t row0 = (int64_t(blockIdx.x) * MB + threadIdx.x) >> A.shift;
+    if (WAVE_ROW) row0 = uniform_int(int(row0));
+    const int64_t rstride = (int64_t(gridDim.x) * MB) >> A.shift;
+    const bool live = f < A.F && sc[SC_DONE * A.Fp + f] == 0.0;
+    const double bt = live ? sc[SC_BETA * A.Fp + f] : 0.0;
+    double pq = 0.0;
+    for (int64_t i = row0; i < A.n; i += rstride) {
+        double qi = 0.0;
+        const int64_t k0 = rowptr[i], k1 = rowptr[i + 1];
+#pragma unroll 4
+        for (int64_t kk = k0; kk < k1; ++kk) {
+            const int64_t o = int64_t(colidx[kk]) * A.Fp + f;
+            qi = fma(val[kk], fma(bt, Pold[o], Z[o]), qi);
+        }
+        const int64_t o = i * A.Fp + f;
+        const double pi = fma(bt, Pold[o], Z[o]);
+        Pnew[o] = pi;
+        Qv[o] = qi;
+        if (live) pq = fma(pi, qi, pq);
+    }
+    return pq;
+}
+
+// (the matrix arrays are separate no-alias parameters so that uniform loads
+// of them may use the scalar cache)
+__global__ __launch_bounds__(MB) void k_m_spmv(MView A, const int64_t* __restrict__ rowptr,
+                                               const int32_t* __restrict__ colidx, const double* __restrict__ val,
+                                               const double* __restrict__ Z, const double* __restrict__ Pold,
                                                double* __restrict__ Pnew, double* __restrict__ Qv,
                                                const double* __restrict__ sc, double* __restrict__ part) {
     if (all_done(A, sc)) return;
-    double v[1] = {0.0};
-    {
-        FOR_ROWS(A, i, f) {
-            const bool live = f < A.F && sc[SC_DONE * A.Fp + f] == 0.0;
-            const double bt = live ? sc[SC_BETA * A.Fp + f] : 0.0;
-            double qi = 0.0;
-            for (int64_t kk = A.rowptr[i]; kk < A.rowptr[i + 1]; ++kk) {
-                const int64_t o = int64_t(A.col[kk]) * A.Fp + f;
-                qi = fma(A.val[kk], fma(bt, Pold[o], Z[o]), qi);
-            }
-            const int64_t o = i * A.Fp + f;
-            const double pi = fma(bt, Pold[o], Z[o]);
-            Pnew[o] = pi;
-            Qv[o] = qi;
-            if (live) v[0] = fma(pi, qi, v[0]);
-        }
-    }
+    double v[1];
+    v[0] = A.Fp == 64 ? spmv_rows<true>(A, rowptr, colidx, val, Z, Pold, Pnew, Qv, sc)
+                      : spmv_rows<false>(A, rowptr, colidx, val, Z, Pold, Pnew, Qv, sc);
     const int slot[1] = {PM_PQ};
     field_partials<1>(A, v, slot, part);
 }
@@ -312,7 +335,7 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
             const int kk = launched + it;
             double* Pold = P + ((kk & 1) ? n * Fp : 0);
             double* Pnew = P + ((kk & 1) ? 0 : n * Fp);
-            k_m_spmv<<<nb, MB, 0, s>>>(A, Z, Pold, Pnew, Qv, sc, part);
+            k_m_spmv<<<nb, MB, 0, s>>>(A, A.rowptr, A.col, A.val, Z, Pold, Pnew, Qv, sc, part);
             k_m_scalars<<<F, MB, 0, s>>>(A, 2, kk, nb, 0.0, part, sc);
             k_m_update<<<nb, MB, 0, s>>>(A, Pnew, Qv, Y, R, Z, sc, part);
             k_m_scalars<<<F, MB, 0, s>>>(A, 1, kk + 1, nb, 0.0, part, sc);
