@@ -97,7 +97,6 @@ struct SrcView {
     const float* box;
     const int32_t* conn;
     const double* values;
-    const double* values_nm;   // [n][F] node-major copy of the values (F > 1)
     const int64_t* bin_ptr;
     const int32_t* bin_elems;
     int64_t n;
@@ -431,38 +430,12 @@ __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, in
         if (!out_) continue;   // localization only
         double mu[D + 1];
         winner_mu<D>(S, bid[q], p[q], mu);
-        if (S.F == 1) {
-            const double y = p1_value<D>(S, bid[q], mu, 0);
+        for (int f = 0; f < S.F; ++f) {
+            const double y = p1_value<D>(S, bid[q], mu, f);
             if (OUT_F32)
-                static_cast<float*>(out_)[i] = float(y);
+                static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
             else
-                static_cast<double*>(out_)[i] = y;
-            continue;
-        }
-        // many fields: each vertex's values are contiguous (node-major copy),
-        // read 4 fields per 32-byte load; same arithmetic as p1_value
-        int vtx[D + 1];
-#pragma unroll
-        for (int k = 0; k <= D; ++k) vtx[k] = bid[q] == INT_MAX ? -1 : S.conn[int64_t(bid[q]) * (D + 1) + k];
-        for (int f0 = 0; f0 < S.F; f0 += 4) {
-            double y[4] = {0.0, 0.0, 0.0, 0.0};
-            if (vtx[0] >= 0) {
-#pragma unroll
-                for (int k = 0; k <= D; ++k) {
-                    const double* vk = S.values_nm + int64_t(vtx[k]) * S.F + f0;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (f0 + u < S.F) y[u] = fma(mu[k], vk[u], y[u]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (f0 + u >= S.F) break;
-                if (OUT_F32)
-                    static_cast<float*>(out_)[int64_t(f0 + u) * ld_out + i] = float(y[u]);
-                else
-                    static_cast<double*>(out_)[int64_t(f0 + u) * ld_out + i] = y[u];
-            }
+                static_cast<double*>(out_)[int64_t(f) * ld_out + i] = y;
         }
     }
     return nood;

@@ -140,29 +140,30 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
 
 // b_res,v = sum over the incidence list of v (ascending (t, k)) of beta; also
 // keeps g_v = values[f][v] (the control at the nodes) for the solve, unless
-// values is null (the fused route writes g itself).  One thread per (field,
-// node), nodes fastest: the writes of a field are coalesced and many fields
-// give many threads.
+// values is null (the fused route writes g itself).
 template <int D, bool F32>
 __global__ void k_assemble(const double* __restrict__ beta, int64_t E, const int64_t* __restrict__ inc_ptr,
                            const int32_t* __restrict__ inc, int64_t n, int F, const void* __restrict__ values_,
                            int64_t ld, double* __restrict__ bres, double* __restrict__ g,
                            unsigned long long* __restrict__ nonfinite) {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * F) return;
-    const int f = int(idx / n);
-    const int64_t v = idx - int64_t(f) * n;
+    const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= n) return;
     const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
-    const double* bf = beta + int64_t(f) * E * (D + 1);
-    double s = 0.0;
-    for (int64_t i = b; i < e; ++i) s += bf[inc[i]];
-    bres[int64_t(f) * n + v] = s;
-    if (values_) {
-        const int64_t off = int64_t(f) * ld + v;
-        const double gv = F32 ? double(static_cast<const float*>(values_)[off]) : static_cast<const double*>(values_)[off];
-        g[int64_t(f) * n + v] = gv;
-        if (!isfinite(gv)) atomicAdd(nonfinite, 1ull);
+    unsigned int nf = 0;
+    for (int f = 0; f < F; ++f) {
+        const double* bf = beta + int64_t(f) * E * (D + 1);
+        double s = 0.0;
+        for (int64_t i = b; i < e; ++i) s += bf[inc[i]];
+        bres[int64_t(f) * n + v] = s;
+        if (values_) {
+            const int64_t off = int64_t(f) * ld + v;
+            const double gv = F32 ? double(static_cast<const float*>(values_)[off])
+                                  : static_cast<const double*>(values_)[off];
+            nf += !isfinite(gv);
+            g[int64_t(f) * n + v] = gv;
+        }
     }
+    if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
 
 __global__ void k_zero_u64(unsigned long long* __restrict__ p, int n) {
@@ -237,10 +238,10 @@ void zero_counter(unsigned long long* p, hipStream_t s) {
 template <int D>
 static void launch_assemble(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s) {
     if (f32)
-        k_assemble<D, true><<<grid_for(T->n * F, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
+        k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
                                                                ld, T->bres, T->g, T->counters);
     else
-        k_assemble<D, false><<<grid_for(T->n * F, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
+        k_assemble<D, false><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
                                                                 ld, T->bres, T->g, T->counters);
 }
 

@@ -173,15 +173,6 @@ __global__ void k_src_register(const double* __restrict__ X, int64_t n, const in
     }
 }
 
-// [F][n] -> [n][F] copy of the nodal values (a vertex's fields contiguous)
-__global__ void k_node_major(const double* __restrict__ src, int64_t n, int F, double* __restrict__ dst) {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * F) return;
-    const int64_t v = idx / F;
-    const int f = int(idx - v * F);
-    dst[idx] = src[int64_t(f) * n + v];
-}
-
 __global__ void k_minmax(const double* __restrict__ X, int64_t n, int dim, double* __restrict__ out) {
     // out[(blockIdx.x * dim + c) * 2 + {0,1}] = block min / max of coordinate c
     __shared__ double smin[256], smax[256];
@@ -343,10 +334,6 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     FT_TRY(dev_alloc_n(&flags, 4));
     FT_TRY_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned long long), s));
     k_src_geom<D><<<grid_for(E, B), B, 0, s>>>(S->coords, n, S->conn, E, S->values, S->F, S->rec, S->box, flags);
-    if (S->F > 1) {
-        FT_TRY(dev_alloc_n(&S->values_nm, size_t(S->F) * n));
-        k_node_major<<<grid_for(int64_t(S->F) * n, B), B, 0, s>>>(S->values, n, S->F, S->values_nm);
-    }
     const int mmb = 256;
     FT_TRY(dev_alloc_n(&mm, size_t(mmb) * D * 2));
     k_minmax<<<mmb, 256, 0, s>>>(S->coords, n, D, mm);
@@ -388,7 +375,7 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
 }
 
 SrcView source_view(const ft_source* S) {
-    SrcView v{S->rec, S->box, S->conn, S->values, S->values_nm, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
+    SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
         v.g.hx[c] = S->hx[c];
@@ -478,7 +465,6 @@ ft_status source_release(ft_source* S) {
     dev_free(S->coords);
     dev_free(S->conn);
     dev_free(S->values);
-    dev_free(S->values_nm);
     dev_free(S->rec);
     dev_free(S->box);
     dev_free(S->bin_ptr);
