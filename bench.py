@@ -50,7 +50,7 @@ def source_mesh_bytes(dim, F, src):
     """The built-in source read once: element records (128 / 256 B), binary32
     boxes, bin lists; connectivity and nodal values only for F > 1 (one field's
     vertex values sit in the records)."""
-    rec, box = (128, 32) if dim == 2 else (256, 24)
+    rec, box = (128, 32) if dim == 2 else (256, 48)
     b = src["E"] * (rec + box) + src["n_reg"] * 4 + src["nbins"] * 8
     if F > 1:
         b += src["E"] * (dim + 1) * 4 + src["n"] * F * 8
@@ -285,6 +285,8 @@ def main():
                          "fused: ft_transfer_p1 (built-in source, no query list)")
     ap.add_argument("--no-fused", action="store_true", help="skip the extra fused-route measurement")
     ap.add_argument("--bins", type=int, default=0, help="source bin cells per axis (0: the workload's choice)")
+    ap.add_argument("--refine-steps", type=int, default=0,
+                    help="mass solve: 0 = binary64 PCG; k > 0 = binary32 inner PCG with k binary64 refinement steps")
     ap.add_argument("--autotune", default="auto", choices=["auto", "on", "off"],
                     help="tune the source bin grid on a sample of the queries (auto: when the workload fixes none)")
     ap.add_argument("--sequential", action="store_true",
@@ -381,7 +383,7 @@ def main():
             T.transfer_from(S, cfg)
         if record:
             ev[nev - 2].record()
-        res = T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
+        res = T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b, refine_steps=args.refine_steps)
         if record:
             ev[nev - 1].record()
         reports, status = res.reports, res.status
@@ -468,7 +470,9 @@ def main():
         "config": {"workload": w.name, "route": args.route, "dim": dim, "target_elements": E, "target_nodes": n,
                    "source_elements": int(sconn.shape[0]), "samples_per_elem": N, "n_fields": F,
                    "queries": Q, "alpha": w.alpha, "rtol": w.rtol,
-                   "bins": list(w.bins[:dim]) if any(w.bins) else "default", "precision": args.precision},
+                   "bins": list(w.bins[:dim]) if any(w.bins) else "default", "precision": args.precision,
+                   "solve": "binary64 PCG" if args.refine_steps == 0 else
+                            f"binary32 PCG + {args.refine_steps} binary64 refinement steps"},
         "queries_per_s": Q / (ms_step * 1e-3),
         "phases_ms": phase_ms,
         "setup_ms": setup_s * 1e3,

@@ -39,23 +39,24 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
     // every lane runs the same number of rounds: the localization is wave-cooperative.
     // Round r, slot q of a lane holds sample j = r*G*P + q*G + lane.
     for (uint32_t j0 = 0; j0 < N; j0 += G * P) {
-        double lam[P][D + 1], pt[P][D];
+        double pt[P][D];
         bool act[P];
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const uint32_t j = j0 + q * G + lane;
             act[q] = valid && j < N;
+            double lam[D + 1];
             if (act[q]) {
-                sample_lambda<D>(tt, j, key, lam[q]);
+                sample_lambda<D>(tt, j, key, lam);
             } else {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) lam[q][k] = 0.0;
+                for (int k = 0; k <= D; ++k) lam[k] = 0.0;
             }
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                double x = lam[q][0] * xv[0][c];
+                double x = lam[0] * xv[0][c];
 #pragma unroll
-                for (int k = 1; k <= D; ++k) x = fma(lam[q][k], xv[k][c], x);
+                for (int k = 1; k <= D; ++k) x = fma(lam[k], xv[k][c], x);
                 pt[q][c] = x;
             }
         }
@@ -68,17 +69,21 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
             nood += (bid[q] == INT_MAX || best[q] < kOutTol);
             double mu[D + 1];
             winner_mu<D>(S, bid[q], pt[q], mu);
+            // lambda again from its counter: keeping P of them live through the
+            // localization costs more registers (occupancy) than the Philox rounds
+            double lam[D + 1];
+            sample_lambda<D>(tt, j0 + q * G + lane, key, lam);
 #pragma unroll
             for (int f = 0; f < FC; ++f) {
                 if (f >= S.F) break;
                 const double y = p1_value<D>(S, bid[q], mu, f);
                 nf += !isfinite(y);
-                double gx = lam[q][0] * gk[f][0];
+                double gx = lam[0] * gk[f][0];
 #pragma unroll
-                for (int k = 1; k <= D; ++k) gx = fma(lam[q][k], gk[f][k], gx);
+                for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
                 const double r = y - alpha * gx;
 #pragma unroll
-                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[q][k], acc[f][k]);
+                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
             }
         }
     }

@@ -13,11 +13,11 @@
 // elements that can meet a region [lo, hi] are registered in the bins of
 // [lo - hx, hi + hx].  The points of a wave (64 lanes x P points)
 // are usually samples of one target element, so they share a handful of bins.
-// The wave forms its points' bounding box (and, in 2D, their ranges of x+y
-// and x-y: an octagon) and the bins that can hold candidates; lanes load
+// The wave forms its points' bounding box and their ranges along a few more
+// directions (x±y in 2D, x-y, y-z, x-z in 3D) and the bins that can hold candidates; lanes load
 // those bins' ranges and a wave scan turns them into one flat candidate
 // sequence (no element appears twice), culled 64 at a time, one per lane:
-//   - the element's box must meet the wave's box (and octagon, in 2D);
+//   - the element's box and direction ranges must meet the wave's;
 //   - no barycentric coordinate may be below -1e-9 on the whole wave box.
 // Each lane parks its candidate's absolute affine barycentric form in the
 // wave's LDS; every lane then tests its points against each survivor in lane
@@ -61,10 +61,22 @@ struct RecValues { static constexpr int value = D + (D + 1) * (D + 1); };
 static_assert(RecValues<2>::value + 3 <= RecSize<2>::value, "2D record overflow");
 static_assert(RecValues<3>::value + 4 <= RecSize<3>::value, "3D record overflow");
 
-// floats per element in the box array: min/max per axis, plus (2D) the
-// ranges of x+y and x-y
+// Extra directions of the element and wave boxes: x+y and x-y in 2D (with the
+// axes an octagon); x-y, y-z and x-z in 3D (the planes that split a hex into
+// its six Kuhn tetrahedra).
 template <int D>
-struct BoxSize { static constexpr int value = D == 2 ? 8 : 6; };
+struct Dirs {
+    static constexpr int n = D == 2 ? 2 : 3;
+    static __host__ __device__ __forceinline__ double proj(int k, const double* x) {
+        if (D == 2) return k == 0 ? x[0] + x[1] : x[0] - x[1];
+        return k == 0 ? x[0] - x[1] : (k == 1 ? x[1] - x[2] : x[0] - x[2]);
+    }
+};
+
+// floats per element in the box array, outward-rounded:
+// [min per axis | max per axis | min per direction | max per direction]
+template <int D>
+struct BoxSize { static constexpr int value = 2 * D + 2 * Dirs<D>::n; };
 
 __device__ __forceinline__ float f32_down(double x) {
     float f = (float)x;
@@ -203,6 +215,12 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
 // lane of the wave must call it (points a lane does not own pass
 // active = false).  Returns best = max min-barycentric and bid = its element
 // id (INT_MAX if no candidate was found) per point.
+// LDS slots for the candidates' affine forms: 64 per wave of a 256-thread
+// block, sized for 3D.  One array at namespace scope, so that a kernel that
+// inlines several localization variants (the batch) allocates it once.
+constexpr int kMaxAL = 16;
+__shared__ double g_cand_af[4 * 64 * kMaxAL];
+
 // Inclusive prefix sum over the 64 lanes of the wave.
 __device__ __forceinline__ int wave_scan_incl(int x) {
     const int lane = threadIdx.x & 63;
@@ -255,29 +273,26 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             flo[c] = f32_down(wlo[c]);
             fhi[c] = f32_up(whi[c]);
         }
-        float fu[4] = {-INFINITY, INFINITY, -INFINITY, INFINITY};   // wave ranges of x+y and x-y (2D)
-        if constexpr (D == 2) {
-            double ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
+        constexpr int ND = Dirs<D>::n;
+        float fdlo[ND], fdhi[ND];   // wave ranges along the extra directions
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            double lo = INFINITY, hi = -INFINITY;
 #pragma unroll
             for (int q = 0; q < P; ++q)
                 if (active[q]) {
-                    const double u = p[q][0] + p[q][1], v = p[q][0] - p[q][1];
-                    ulo = fmin(ulo, u);
-                    uhi = fmax(uhi, u);
-                    vlo = fmin(vlo, v);
-                    vhi = fmax(vhi, v);
+                    const double u = Dirs<D>::proj(k, p[q]);
+                    lo = fmin(lo, u);
+                    hi = fmax(hi, u);
                 }
-            fu[0] = f32_down(wave_min(ulo));
-            fu[1] = f32_up(wave_max(uhi));
-            fu[2] = f32_down(wave_min(vlo));
-            fu[3] = f32_up(wave_max(vhi));
+            fdlo[k] = f32_down(wave_min(lo));
+            fdhi[k] = f32_up(wave_max(hi));
         }
         // Lane i < span describes bin i of the wave's bin box (x fastest): its
         // coordinates, first registration and count.  The candidate slots of all
         // these bins are then culled 64 at a time in one flat sequence.
         constexpr int AL = (D + 1) * (D + 1);   // affine form: D+1 constants, (D+1) x D gradients
-        __shared__ double c_af[4][64 * AL];     // per wave of a 256-thread block
-        const int w = (threadIdx.x >> 6) & 3;
+        double* c_af = g_cand_af + ((threadIdx.x >> 6) & 3) * (64 * kMaxAL);   // this wave's slots
         const int wx = b1[0] - b0[0] + 1, wy = b1[1] - b0[1] + 1;
         int64_t bstart = 0;
         int bcnt = 0;
@@ -315,15 +330,15 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 ov = true;
 #pragma unroll
                 for (int c = 0; c < D; ++c) ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
-                if constexpr (D == 2)
-                    ov &= (bx_[4] <= fu[1]) & (bx_[6] >= fu[0]) & (bx_[5] <= fu[3]) & (bx_[7] >= fu[2]);
+#pragma unroll
+                for (int k = 0; k < ND; ++k) ov &= (bx_[2 * D + k] <= fdhi[k]) & (bx_[2 * D + ND + k] >= fdlo[k]);
                 ov = ov && box_may_meet_af<D>(af, wlo, whi);
             }
             // every lane parks its candidate's affine form in its own LDS slot; the
             // survivors are then read back in lane order
             if (sl < total) {
 #pragma unroll
-                for (int m = 0; m < AL; ++m) c_af[w][lane * AL + m] = af[m];
+                for (int m = 0; m < AL; ++m) c_af[lane * AL + m] = af[m];
             }
             uint64_t mask = __ballot(ov);
             __builtin_amdgcn_wave_barrier();
@@ -331,7 +346,7 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 const int l1 = __ffsll((unsigned long long)mask) - 1;
                 mask &= mask - 1;
                 const int e1 = read_lane(cid, l1);
-                const double* a1 = &c_af[w][l1 * AL];
+                const double* a1 = &c_af[l1 * AL];
                 bool done = true;
 #pragma unroll
                 for (int q = 0; q < P; ++q) {

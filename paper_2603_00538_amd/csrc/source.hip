@@ -124,21 +124,18 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
         box[e * BS + c] = f32_down(lo);
         box[e * BS + D + c] = f32_up(hi);
     }
-    if constexpr (D == 2) {
-        // ranges of u = x + y and v = x - y over the vertices: [umin, vmin, umax, vmax]
-        double ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
+    constexpr int ND = Dirs<D>::n;
 #pragma unroll
-        for (int k = 0; k <= D; ++k) {
-            const double u = x[k][0] + x[k][1], v = x[k][0] - x[k][1];
-            ulo = fmin(ulo, u);
-            uhi = fmax(uhi, u);
-            vlo = fmin(vlo, v);
-            vhi = fmax(vhi, v);
+    for (int k = 0; k < ND; ++k) {
+        double lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int j = 0; j <= D; ++j) {
+            const double u = Dirs<D>::proj(k, x[j]);
+            lo = fmin(lo, u);
+            hi = fmax(hi, u);
         }
-        box[e * BS + 4] = f32_down(ulo);
-        box[e * BS + 5] = f32_down(vlo);
-        box[e * BS + 6] = f32_up(uhi);
-        box[e * BS + 7] = f32_up(vhi);
+        box[e * BS + 2 * D + k] = f32_down(lo);
+        box[e * BS + 2 * D + ND + k] = f32_up(hi);
     }
 }
 
