@@ -8,11 +8,11 @@
 //   element tiles  (transfer, 64/G target elements)  steps 3-5, fused
 //   row tiles      (transfer, 256 rows)              steps 2, 6, 7 and the report
 // The node and element stages are persistent kernels: a grid sized to the
-// device walks its list with a fixed stride; element tiles are ordered by
-// decreasing cost (largest N and 3D first), so the long tiles start first and
-// the short ones fill the tail.  Each element tile is one wavefront; its
-// (dimension, lanes per element G, samples per lane P) variant is chosen per
-// transfer exactly as the single-transfer route chooses it.
+// device walks its list with a fixed stride.  Each element tile is one
+// wavefront; its (dimension, lanes per element G, samples per lane P) variant
+// is chosen per transfer exactly as the single-transfer route chooses it, and
+// every variant runs as a launch of its own (each with its own register
+// budget, hence occupancy), the dearest variants (largest N, 3D) first.
 //
 // The solve is a batched Jacobi-PCG: all systems share the launches, every
 // system keeps its own scalars, and a converged system's tiles return at once.
@@ -94,28 +94,72 @@ __device__ __forceinline__ void batch_elements(const BatchXfer& x, int64_t start
                                x.beta, t, lane % G, nf, nood);
 }
 
-__global__ __launch_bounds__(256) void k_batch_fused(const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles,
-                                                     int64_t n_tiles, unsigned long long* __restrict__ nonfinite) {
+// One launch per (dimension, G, P) variant over that variant's tiles
+// [first, last), so that each variant gets its own register budget.
+template <int D, int G, int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 2 ? 3 : 2))) void k_batch_fused(
+    const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles, int64_t first, int64_t last,
+    unsigned long long* __restrict__ nonfinite) {
     const int lane = threadIdx.x & 63;
     const int64_t stride = int64_t(gridDim.x) * 4;
-    for (int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); w < n_tiles; w += stride) {
+    // the wave index, uniform by construction: the tile and its descriptor load into scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    for (int64_t w = first + int64_t(blockIdx.x) * 4 + wv; w < last; w += stride) {
         const Tile tl = tiles[w];
         const BatchXfer& x = X[tl.k];
         unsigned nf = 0, nood = 0;
-        switch (tl.variant) {
-            case 0: batch_elements<2, 64, 4>(x, tl.start, lane, nf, nood); break;
-            case 1: batch_elements<2, 64, 2>(x, tl.start, lane, nf, nood); break;
-            case 2: batch_elements<2, 64, 1>(x, tl.start, lane, nf, nood); break;
-            case 3: batch_elements<2, 32, 1>(x, tl.start, lane, nf, nood); break;
-            case 4: batch_elements<2, 16, 1>(x, tl.start, lane, nf, nood); break;
-            case kVariants + 0: batch_elements<3, 64, 4>(x, tl.start, lane, nf, nood); break;
-            case kVariants + 1: batch_elements<3, 64, 2>(x, tl.start, lane, nf, nood); break;
-            case kVariants + 2: batch_elements<3, 64, 1>(x, tl.start, lane, nf, nood); break;
-            case kVariants + 3: batch_elements<3, 32, 1>(x, tl.start, lane, nf, nood); break;
-            default: batch_elements<3, 16, 1>(x, tl.start, lane, nf, nood); break;
-        }
+        batch_elements<D, G, P>(x, tl.start, lane, nf, nood);
         if (nf) atomicAdd(nonfinite + tl.k, (unsigned long long)nf);
         if (nood) atomicAdd(x.src_ood, (unsigned long long)nood);
+    }
+}
+
+constexpr int kCodes = 2 * kVariants;   // variant + kVariants for 3D
+
+template <int D, int G, int P>
+static void launch_fused_v(unsigned grid, hipStream_t s, const BatchXfer* X, const Tile* tiles, int64_t first,
+                           int64_t last, unsigned long long* nf) {
+    k_batch_fused<D, G, P><<<grid, 256, 0, s>>>(X, tiles, first, last, nf);
+}
+
+template <int D, int G, int P>
+static int fused_blocks_per_cu() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<D, G, P>, 256, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+
+// (launch, resident blocks per CU) of element-stage code c
+static void launch_fused(int c, unsigned grid, hipStream_t s, const BatchXfer* X, const Tile* tiles, int64_t first,
+                         int64_t last, unsigned long long* nf) {
+    switch (c) {
+        case 0: launch_fused_v<2, 64, 4>(grid, s, X, tiles, first, last, nf); break;
+        case 1: launch_fused_v<2, 64, 2>(grid, s, X, tiles, first, last, nf); break;
+        case 2: launch_fused_v<2, 64, 1>(grid, s, X, tiles, first, last, nf); break;
+        case 3: launch_fused_v<2, 32, 1>(grid, s, X, tiles, first, last, nf); break;
+        case 4: launch_fused_v<2, 16, 1>(grid, s, X, tiles, first, last, nf); break;
+        case kVariants + 0: launch_fused_v<3, 64, 4>(grid, s, X, tiles, first, last, nf); break;
+        case kVariants + 1: launch_fused_v<3, 64, 2>(grid, s, X, tiles, first, last, nf); break;
+        case kVariants + 2: launch_fused_v<3, 64, 1>(grid, s, X, tiles, first, last, nf); break;
+        case kVariants + 3: launch_fused_v<3, 32, 1>(grid, s, X, tiles, first, last, nf); break;
+        default: launch_fused_v<3, 16, 1>(grid, s, X, tiles, first, last, nf); break;
+    }
+}
+
+static int fused_per_cu(int c) {
+    switch (c) {
+        case 0: return fused_blocks_per_cu<2, 64, 4>();
+        case 1: return fused_blocks_per_cu<2, 64, 2>();
+        case 2: return fused_blocks_per_cu<2, 64, 1>();
+        case 3: return fused_blocks_per_cu<2, 32, 1>();
+        case 4: return fused_blocks_per_cu<2, 16, 1>();
+        case kVariants + 0: return fused_blocks_per_cu<3, 64, 4>();
+        case kVariants + 1: return fused_blocks_per_cu<3, 64, 2>();
+        case kVariants + 2: return fused_blocks_per_cu<3, 64, 1>();
+        case kVariants + 3: return fused_blocks_per_cu<3, 32, 1>();
+        default: return fused_blocks_per_cu<3, 16, 1>();
     }
 }
 
@@ -123,7 +167,8 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchXfer* __restrict
 __global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles,
                                                      int64_t n_tiles) {
     const int64_t stride = int64_t(gridDim.x) * 4;
-    for (int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); w < n_tiles; w += stride) {
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    for (int64_t w = int64_t(blockIdx.x) * 4 + wv; w < n_tiles; w += stride) {
         const Tile tl = tiles[w];
         const BatchXfer& x = X[tl.k];
         unsigned nood;
@@ -376,7 +421,12 @@ struct ft_batch {
     double** h_xs = nullptr;      // pinned mirror
     double* h_sc = nullptr;       // pinned [count][BS_COUNT]
     unsigned long long* h_nf = nullptr;
-    unsigned grid_elem = 1, grid_node = 1;
+    // element launch i runs code code_order[i] over tiles [code_first[i], code_first[i + 1]),
+    // dearest tiles first
+    int code_order[ft::kCodes] = {};
+    int64_t code_first[ft::kCodes + 1] = {};
+    unsigned code_grid[ft::kCodes] = {};
+    unsigned grid_node = 1;
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -420,15 +470,13 @@ void batch_release(ft_batch* b) {
     if (b->h_nf) (void)hipHostFree(b->h_nf);
 }
 
-template <typename K>
-static unsigned persistent_grid(K kernel, int64_t waves) {
-    int dev = 0, cus = 0, per_cu = 0;
+static unsigned persistent_grid(int per_cu, int64_t waves) {
+    int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                                                  hipSuccess)
         cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
     const int64_t want = (waves + 3) / 4;
-    return unsigned(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(cus) * per_cu)));
+    return unsigned(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(cus) * std::max(1, per_cu))));
 }
 
 ft_status batch_setup(ft_batch* b, hipStream_t s) {
@@ -481,13 +529,27 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
         order.push_back(Group{double(epw) * c.samples_per_elem * (T->dim == 3 ? 1.5 : 1.0), k});
     }
     std::stable_sort(order.begin(), order.end(), [](const Group& a, const Group& c) { return a.cost > c.cost; });
+    // element tiles grouped by code; codes in the order of their dearest transfer
+    std::vector<std::vector<Tile>> by_code(kCodes);
+    bool seen[kCodes] = {};
+    int n_order = 0;
     for (const Group& gp : order) {
         const int k = gp.k;
         const int var = variant_of(b->cfg[k].samples_per_elem);
         const int epw = 64 / lanes_of(var);
         const int code = var + (b->T[k]->dim == 3 ? kVariants : 0);
-        for (int64_t t = 0; t < b->T[k]->E; t += epw) elem.push_back(Tile{k, code, t});
+        if (!seen[code]) b->code_order[n_order++] = code;
+        seen[code] = true;
+        for (int64_t t = 0; t < b->T[k]->E; t += epw) by_code[code].push_back(Tile{k, code, t});
     }
+    for (int c = 0; c < kCodes; ++c)
+        if (!seen[c]) b->code_order[n_order++] = c;
+    for (int i = 0; i < kCodes; ++i) {
+        const int c = b->code_order[i];
+        b->code_first[i] = int64_t(elem.size());
+        elem.insert(elem.end(), by_code[c].begin(), by_code[c].end());
+    }
+    b->code_first[kCodes] = int64_t(elem.size());
     if (row.size() >= (size_t(1) << 31)) {
         set_error("batch too large (%zu row tiles)", row.size());
         return FT_E_UNSUPPORTED;
@@ -514,8 +576,12 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
     FT_TRY_HIP(hipMemcpyAsync(b->d_node, node.data(), sizeof(Tile) * node.size(), hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipMemcpyAsync(b->d_row, row.data(), sizeof(Tile) * row.size(), hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
-    b->grid_elem = persistent_grid(k_batch_fused, b->n_elem_tiles);
-    b->grid_node = persistent_grid(k_batch_nodes, b->n_node_tiles);
+    for (int i = 0; i < kCodes; ++i)
+        b->code_grid[i] = persistent_grid(fused_per_cu(b->code_order[i]), b->code_first[i + 1] - b->code_first[i]);
+    int node_per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&node_per_cu, k_batch_nodes, 256, 0) != hipSuccess)
+        node_per_cu = 1;
+    b->grid_node = persistent_grid(node_per_cu, b->n_node_tiles);
     if (b->use_graph) FT_TRY_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     return FT_OK;
 }
@@ -527,8 +593,10 @@ static ft_status enqueue_run(ft_batch* b, const ft_solve_cfg* cfg, hipStream_t s
     const int64_t rows = b->rows;
     k_fill_u64<<<grid_for(K, 256), 256, 0, s>>>(b->nonfinite, K);
     if (b->n_node_tiles) k_batch_nodes<<<b->grid_node, 256, 0, s>>>(b->d_x, b->d_node, b->n_node_tiles);
-    if (b->n_elem_tiles)
-        k_batch_fused<<<b->grid_elem, 256, 0, s>>>(b->d_x, b->d_elem, b->n_elem_tiles, b->nonfinite);
+    for (int i = 0; i < kCodes; ++i)
+        if (b->code_first[i + 1] > b->code_first[i])
+            launch_fused(b->code_order[i], b->code_grid[i], s, b->d_x, b->d_elem, b->code_first[i],
+                         b->code_first[i + 1], b->nonfinite);
     k_batch_assemble<<<nrt, BT, 0, s>>>(b->d_x, b->d_row);
     k_batch_rhs<<<nrt, BT, 0, s>>>(b->d_x, b->d_row, b->B, b->part);
     k_batch_scalars<<<K, 64, 0, s>>>(b->d_x, 0, 0, cfg->rtol * cfg->rtol, b->part, b->sc);
