@@ -306,7 +306,7 @@ def main():
     ap.add_argument("--route", default="blackbox", choices=["blackbox", "fused"],
                     help="blackbox: sample -> source eval -> consume through the point-query list; "
                          "fused: ft_transfer_p1 (built-in source, no query list)")
-    ap.add_argument("--no-fused", action="store_true", help="skip the extra fused-route measurement")
+    ap.add_argument("--no-fused", action="store_true", help="skip the extra fused-route and plan-route measurements")
     ap.add_argument("--bins", type=int, default=0, help="source bin cells per axis (0: the workload's choice)")
     ap.add_argument("--refine-steps", type=int, default=0,
                     help="mass solve: 0 = binary64 PCG; k > 0 = binary32 inner PCG with k binary64 refinement steps")
@@ -363,16 +363,24 @@ def main():
     Q = T.query_count(N)
     tuned = None
     if args.autotune == "on" or (args.autotune == "auto" and bins is None):
-        # sample: the node block and the first elements' samples of this transfer's query list
+        # sample: the samples of elements spread evenly over the target (about
+        # 4M queries) of this transfer's query list.  The node block is left
+        # out: it is a small part of a step, but in a structured node order
+        # its waves take the point-by-point search, whose cost falls with
+        # finer bins and would steer the choice away from the sample waves'.
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        m = min(Q, n + max(N, (4_000_000 // N) * N))
-        sample = torch.empty((dim, Q), dtype=dt_, device=dev)
-        T.sample_points(ft.SampleCfg(N, F, w.alpha, w.philox_seed, 0, prec), out=sample)
-        sample = sample[:, :m].contiguous()
+        full = torch.empty((dim, Q), dtype=dt_, device=dev)
+        T.sample_points(ft.SampleCfg(N, F, w.alpha, w.philox_seed, 0, prec), out=full)
+        E_ = T.n_elems
+        picked = torch.linspace(0, E_ - 1, max(1, min(E_, 4_000_000 // N)), device=dev).round().long().unique()
+        qidx = (n + picked[:, None] * N + torch.arange(N, device=dev)[None, :]).reshape(-1)
+        sample = full[:, qidx].contiguous()
+        m = int(sample.shape[1])
+        del full
         base = int(S.info.bins[0])
         cands = sorted({max(4, int(round(base * f))) for f in (0.75, 0.9, 1.0, 1.15, 1.3, 1.5, 1.7)})
-        tuned = {"candidates": cands, "chosen": S.autotune(sample, n, cands)[:dim],
+        tuned = {"candidates": cands, "chosen": S.autotune(sample, 0, cands)[:dim],
                  "sample_queries": m, "ms": 0.0}
         del sample
         torch.cuda.synchronize()

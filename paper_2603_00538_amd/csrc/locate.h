@@ -18,10 +18,12 @@
 // those bins' ranges and a wave scan turns them into one flat candidate
 // sequence (no element appears twice), culled 64 at a time, one per lane:
 //   - the element's box and direction ranges must meet the wave's;
-//   - no barycentric coordinate may be below -1e-9 on the whole wave box.
-// Each lane parks its candidate's absolute affine barycentric form in the
-// wave's LDS; every lane then tests its points against each survivor in lane
-// order (broadcast LDS reads).  The selection test accepts an element once
+//   - then (only for those, which fetch the element's absolute affine
+//     barycentric form) no barycentric coordinate may be below -1e-9 on the
+//     whole wave box.
+// Each survivor's lane parks that affine form in the wave's LDS; every lane
+// then tests its points against each survivor in lane order (broadcast LDS
+// reads).  The selection test accepts an element once
 // its min mu exceeds 1e-9, far above that form's rounding, so an accepted
 // element truly contains the point and is the unique winner.  Points never
 // accepted (within 1e-9 of a face, or outside) are re-searched alone with the
@@ -211,10 +213,6 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
             }
 }
 
-// Rule winner for each of this lane's P points (see the file comment).  Every
-// lane of the wave must call it (points a lane does not own pass
-// active = false).  Returns best = max min-barycentric and bid = its element
-// id (INT_MAX if no candidate was found) per point.
 // LDS slots for the candidates' affine forms: 64 per wave of a 256-thread
 // block, sized for 3D.  One array at namespace scope, so that a kernel that
 // inlines several localization variants (the batch) allocates it once.
@@ -232,6 +230,12 @@ __device__ __forceinline__ int wave_scan_incl(int x) {
     return x;
 }
 
+// Rule winner for each of this lane's P points (see the file comment).  Every
+// lane of the wave must call it (points a lane does not own pass
+// active = false).  Returns bid = the winner's element id (INT_MAX if no
+// candidate was found) and best = its min-barycentric: from the candidates'
+// absolute affine forms for points the fast test accepted (then above
+// kFastTau, so inside), from the full rule for the others.
 template <int D, int P>
 __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[P][D], const bool (&active)[P],
                                             double (&best)[P], int (&bid)[P]) {
@@ -319,24 +323,24 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             const int64_t st_i = __shfl((long long)bstart, i, 64);
             int cid = -1;
             bool ov = false;
-            double af[AL];
             if (sl < total) {
-                // box and record load together (one round trip)
                 cid = S.bin_elems[st_i + (sl - excl_i)];
                 const float* bx_ = S.box + int64_t(cid) * BS;
-                const double* r = S.rec + int64_t(cid) * RS;
-#pragma unroll
-                for (int m = 0; m < AL; ++m) af[m] = r[RecAffine<D>::value + m];
                 ov = true;
 #pragma unroll
                 for (int c = 0; c < D; ++c) ov &= (bx_[c] <= fhi[c]) & (bx_[D + c] >= flo[c]);
 #pragma unroll
                 for (int k = 0; k < ND; ++k) ov &= (bx_[2 * D + k] <= fdhi[k]) & (bx_[2 * D + ND + k] >= fdlo[k]);
-                ov = ov && box_may_meet_af<D>(af, wlo, whi);
             }
-            // every lane parks its candidate's affine form in its own LDS slot; the
-            // survivors are then read back in lane order
-            if (sl < total) {
+            // only the box survivors (a small fraction of the slots) fetch their affine
+            // form, test it against the wave's box and park it in their own LDS slot;
+            // the survivors are then read back in lane order
+            if (ov) {
+                double af[AL];
+                const double* r = S.rec + int64_t(cid) * RS;
+#pragma unroll
+                for (int m = 0; m < AL; ++m) af[m] = r[RecAffine<D>::value + m];
+                ov = box_may_meet_af<D>(af, wlo, whi);
 #pragma unroll
                 for (int m = 0; m < AL; ++m) c_af[lane * AL + m] = af[m];
             }
@@ -363,17 +367,10 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             __builtin_amdgcn_wave_barrier();
         }
         // points not accepted by the fast test (near a face, or outside): the full rule
-        // in the point's own bin; accepted points get their exact min mu
+        // in the point's own bin
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-            if (!active[q]) continue;
-            if (best[q] > kFastTau) {
-                double mu[D + 1];
-                best[q] = barycentric<D>(S.rec + int64_t(bid[q]) * RS, p[q], mu);
-            } else {
-                locate_point<D>(S, p[q], best[q], bid[q]);
-            }
-        }
+        for (int q = 0; q < P; ++q)
+            if (active[q] && !(best[q] > kFastTau)) locate_point<D>(S, p[q], best[q], bid[q]);
     } else {
 #pragma unroll
         for (int q = 0; q < P; ++q)
