@@ -363,17 +363,20 @@ def main():
     Q = T.query_count(N)
     tuned = None
     if args.autotune == "on" or (args.autotune == "auto" and bins is None):
-        # sample: the samples of elements spread evenly over the target (about
-        # 4M queries) of this transfer's query list.  The node block is left
-        # out: it is a small part of a step, but in a structured node order
-        # its waves take the point-by-point search, whose cost falls with
-        # finer bins and would steer the choice away from the sample waves'.
+        # sample: about 4M queries of this transfer's query list, the samples of
+        # 16 runs of consecutive elements spread evenly over the target (runs,
+        # so that neighbouring waves share cached candidates as in a full
+        # step).  The node block is left out: it is a small part of a step,
+        # but in a structured node order its waves take the point-by-point
+        # search, whose cost falls with finer bins.
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         full = torch.empty((dim, Q), dtype=dt_, device=dev)
         T.sample_points(ft.SampleCfg(N, F, w.alpha, w.philox_seed, 0, prec), out=full)
         E_ = T.n_elems
-        picked = torch.linspace(0, E_ - 1, max(1, min(E_, 4_000_000 // N)), device=dev).round().long().unique()
+        run_len = max(1, min(E_, 4_000_000 // N) // 16)
+        starts = torch.linspace(0, E_ - run_len, 16, device=dev).round().long()
+        picked = (starts[:, None] + torch.arange(run_len, device=dev)[None, :]).reshape(-1).unique()
         qidx = (n + picked[:, None] * N + torch.arange(N, device=dev)[None, :]).reshape(-1)
         sample = full[:, qidx].contiguous()
         m = int(sample.shape[1])

@@ -133,14 +133,34 @@ __device__ __forceinline__ double wave_sum_xor(double v, int width) {
     return v;
 }
 
-__device__ __forceinline__ double wave_min(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+// Binary32 minimum / maximum over the 64 lanes, returned wave-uniform (in
+// scalar registers): butterflies inside each row of 16 lanes on the DPP
+// crossbar (quad permutations for lanes i^1 and i^2, row rotations by 4 and 8),
+// then the four row results.  No LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, CTRL, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+__device__ __forceinline__ float lane_f32(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+__device__ __forceinline__ float wave_min_f32(float v) {
+    v = fminf(v, dpp_f32<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = fminf(v, dpp_f32<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = fminf(v, dpp_f32<0x124>(v));   // row_ror:4
+    v = fminf(v, dpp_f32<0x128>(v));   // row_ror:8
+    return fminf(fminf(lane_f32(v, 0), lane_f32(v, 16)), fminf(lane_f32(v, 32), lane_f32(v, 48)));
+}
+
+__device__ __forceinline__ float wave_max_f32(float v) {
+    v = fmaxf(v, dpp_f32<0xB1>(v));
+    v = fmaxf(v, dpp_f32<0x4E>(v));
+    v = fmaxf(v, dpp_f32<0x124>(v));
+    v = fmaxf(v, dpp_f32<0x128>(v));
+    return fmaxf(fmaxf(lane_f32(v, 0), lane_f32(v, 16)), fmaxf(lane_f32(v, 32), lane_f32(v, 48)));
 }
 
 __device__ __forceinline__ int read_lane(int v, int lane) {

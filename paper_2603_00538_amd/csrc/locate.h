@@ -219,15 +219,23 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
 constexpr int kMaxAL = 16;
 __shared__ double g_cand_af[4 * 64 * kMaxAL];
 
-// Inclusive prefix sum over the 64 lanes of the wave.
+// Inclusive prefix sum over the 64 lanes of the wave: a scan inside each row
+// of 16 lanes on the DPP crossbar (shifts by 1, 2, 4, 8; lanes shifted in
+// from outside the row read zero), then the totals of the rows below.
+template <int CTRL>
+__device__ __forceinline__ int dpp_shr_zero(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, true);
+}
+
 __device__ __forceinline__ int wave_scan_incl(int x) {
     const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int t = __shfl_up(x, d, 64);
-        if (lane >= d) x += t;
-    }
-    return x;
+    x += dpp_shr_zero<0x111>(x);   // row_shr:1
+    x += dpp_shr_zero<0x112>(x);   // row_shr:2
+    x += dpp_shr_zero<0x114>(x);   // row_shr:4
+    x += dpp_shr_zero<0x118>(x);   // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(x, 15), r1 = __builtin_amdgcn_readlane(x, 31),
+              r2 = __builtin_amdgcn_readlane(x, 47);
+    return x + (lane >= 16 ? r0 : 0) + (lane >= 32 ? r1 : 0) + (lane >= 48 ? r2 : 0);
 }
 
 // Rule winner for each of this lane's P points (see the file comment).  Every
@@ -243,7 +251,9 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
     constexpr int BS = BoxSize<D>::value;
     constexpr int MAX_SPAN = 64;   // bins a wave searches as one flat sequence (one per lane)
     const int lane = threadIdx.x & 63;
+    // the wave's box, rounded outward to binary32 (DPP reductions, no LDS)
     double wlo[D], whi[D];
+    float flo[D], fhi[D];
     int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
     int span = 1;
 #pragma unroll
@@ -255,8 +265,10 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 lo = fmin(lo, p[q][c]);
                 hi = fmax(hi, p[q][c]);
             }
-        wlo[c] = uniform_double(wave_min(lo));
-        whi[c] = uniform_double(wave_max(hi));
+        flo[c] = wave_min_f32(f32_down(lo));
+        fhi[c] = wave_max_f32(f32_up(hi));
+        wlo[c] = flo[c];
+        whi[c] = fhi[c];
         // elements meeting the wave's box have their box centre within hx of it
         b0[c] = uniform_int(bin_of(wlo[c] - S.g.hx[c], c, S.g));
         b1[c] = uniform_int(bin_of(whi[c] + S.g.hx[c], c, S.g));
@@ -271,12 +283,6 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
     }
 
     if (span <= MAX_SPAN) {
-        float flo[D], fhi[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            flo[c] = f32_down(wlo[c]);
-            fhi[c] = f32_up(whi[c]);
-        }
         constexpr int ND = Dirs<D>::n;
         float fdlo[ND], fdhi[ND];   // wave ranges along the extra directions
 #pragma unroll
@@ -289,8 +295,8 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                     lo = fmin(lo, u);
                     hi = fmax(hi, u);
                 }
-            fdlo[k] = f32_down(wave_min(lo));
-            fdhi[k] = f32_up(wave_max(hi));
+            fdlo[k] = wave_min_f32(f32_down(lo));
+            fdhi[k] = wave_max_f32(f32_up(hi));
         }
         // Lane i < span describes bin i of the wave's bin box (x fastest): its
         // coordinates, first registration and count.  The candidate slots of all
