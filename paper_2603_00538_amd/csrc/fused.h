@@ -18,6 +18,9 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
                                                uint32_t E, uint32_t N, double alpha, SampleKey key,
                                                const double* __restrict__ g, double* __restrict__ beta, uint32_t t,
                                                int lane, unsigned& nf, unsigned& nood) {
+    // with one element per wave, its connectivity, vertices and control values
+    // are wave-uniform: scalar loads into scalar registers
+    if (G == 64) t = __builtin_amdgcn_readfirstlane(t);
     const bool valid = t < E;
     const uint32_t tt = valid ? t : 0u;
     int v[D + 1];

@@ -15,10 +15,13 @@
 
 namespace ft {
 
-// One field in 2D: held to 168 registers (three waves per SIMD), 21% faster
-// than the unconstrained allocation, which leaves two.
+// One field: register targets for four waves per SIMD in 2D and three in 3D
+// with one element per wave and at most two samples per lane (the other 3D
+// variants would spill at three and keep two).  The unconstrained allocation
+// leaves two waves per SIMD (2D: 21% slower).
 template <int D, int G, int P, int FC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 2 && FC == 1 ? 3 : 1)))
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(FC != 1 ? 1 : (D == 2 ? 4 : (G == 64 && P <= 2 ? 3 : 2)))))
 void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
                 const double* __restrict__ vol, uint32_t E, uint32_t N, double alpha, SampleKey key,
                 const double* __restrict__ g, double* __restrict__ beta, unsigned long long* __restrict__ nonfinite,
