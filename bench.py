@@ -37,7 +37,7 @@ KERNEL_SOURCES = {
     "k_src_eval": ["source.hip", "locate.h", "common.h"],
     "k_consume": ["mc.hip", "sampling.h", "common.h"],
     "k_consume_mfma": ["mc_mfma.hip", "sampling.h", "common.h"],
-    "k_fused_p1": ["fused.hip", "locate.h", "sampling.h", "common.h"],
+    "k_fused_p1": ["fused.hip", "fused.h", "locate.h", "sampling.h", "common.h"],
 }
 TRAFFIC_RECORDS = os.path.join(ROOT, "profiles", "hbm_traffic.md")
 
