@@ -16,14 +16,11 @@
 // The wave forms its points' bounding box and their ranges along a few more
 // directions (x±y in 2D, x-y, y-z, x-z in 3D) and the bins that can hold candidates; lanes load
 // those bins' ranges and a wave scan turns them into one flat candidate
-// sequence (no element appears twice), culled 64 at a time, one per lane:
-//   - the element's box and direction ranges must meet the wave's;
-//   - then (only for those, which fetch the element's absolute affine
-//     barycentric form) no barycentric coordinate may be below -1e-9 on the
-//     whole wave box.
-// Each survivor's lane parks that affine form in the wave's LDS; every lane
-// then tests its points against each survivor in lane order (broadcast LDS
-// reads).  The selection test accepts an element once
+// sequence (no element appears twice), culled 64 at a time, one per lane: the
+// element's box and direction ranges must meet the wave's.  Only the
+// survivors fetch the element's absolute affine barycentric form, and park it
+// in the wave's LDS; every lane then tests its points against each survivor
+// in lane order (broadcast LDS reads).  The selection test accepts an element once
 // its min mu exceeds 1e-9, far above that form's rounding, so an accepted
 // element truly contains the point and is the unique winner.  Points never
 // accepted (within 1e-9 of a face, or outside) are re-searched alone with the
@@ -150,27 +147,6 @@ __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int
         best = mn;
         bid = e;
     }
-}
-
-// Conservative test whether an element can contain a point of the box
-// [lo, hi]: false only if some barycentric coordinate is below -1e-9 on the
-// whole box (a linear function's maximum over a box sits at a corner).  The
-// affine form is held in registers: af = [c_0..c_D, g_0, ..., g_D].
-template <int D>
-__device__ __forceinline__ bool box_may_meet_af(const double (&af)[(D + 1) * (D + 1)], const double (&lo)[D],
-                                                const double (&hi)[D]) {
-    bool meet = true;
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        double mx = af[k];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            const double gk = af[D + 1 + k * D + c];
-            mx += fmax(gk * lo[c], gk * hi[c]);
-        }
-        meet &= mx >= -1e-9;
-    }
-    return meet;
 }
 
 // min_k mu_k(p) from an affine form in LDS (wave-uniform address: a broadcast read).
@@ -338,17 +314,13 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
 #pragma unroll
                 for (int k = 0; k < ND; ++k) ov &= (bx_[2 * D + k] <= fdhi[k]) & (bx_[2 * D + ND + k] >= fdlo[k]);
             }
-            // only the box survivors (a small fraction of the slots) fetch their affine
-            // form, test it against the wave's box and park it in their own LDS slot;
-            // the survivors are then read back in lane order
+            // only the survivors (a small fraction of the slots) fetch their affine
+            // form and park it in their own LDS slot; they are then read back in
+            // lane order
             if (ov) {
-                double af[AL];
                 const double* r = S.rec + int64_t(cid) * RS;
 #pragma unroll
-                for (int m = 0; m < AL; ++m) af[m] = r[RecAffine<D>::value + m];
-                ov = box_may_meet_af<D>(af, wlo, whi);
-#pragma unroll
-                for (int m = 0; m < AL; ++m) c_af[lane * AL + m] = af[m];
+                for (int m = 0; m < AL; ++m) c_af[lane * AL + m] = r[RecAffine<D>::value + m];
             }
             uint64_t mask = __ballot(ov);
             __builtin_amdgcn_wave_barrier();

@@ -1,6 +1,7 @@
 """GPU parity of batched transfers (ft_batch_create / ft_batch_run).
 
-A small uneven batch (2D and 3D targets of different sizes, N from 16 to 256)
+A small uneven batch (2D and 3D targets of different sizes, N from 8 to 256,
+every element-stage variant of both dimensions)
 is checked transfer by transfer against the FP64 oracle (load vector and
 solution within 1e-12 relative L2), against the single-transfer fused route
 (same samples and element sums: load vectors agree to rounding of the
@@ -30,6 +31,12 @@ def _items():
         (meshes.structured_tri_mesh(10, 0.2, 47), meshes.structured_tri_mesh(18, 0.2, 48), "front_2d", 128),
         (meshes.kuhn_tet_mesh(6, 0.08, 49), meshes.kuhn_tet_mesh(9, 0.08, 50), "gaussian_bumps_3d", 256),
         (meshes.delaunay_tri_mesh(9, 0.3, 51), meshes.delaunay_tri_mesh(13, 0.3, 52), "smooth_2d", 20),
+        # the remaining (dimension, lanes per element, samples per lane) variants
+        (meshes.structured_tri_mesh(8, 0.2, 53), meshes.structured_tri_mesh(14, 0.2, 54), "smooth_2d", 256),
+        (meshes.delaunay_tri_mesh(10, 0.3, 55), meshes.delaunay_tri_mesh(15, 0.3, 56), "front_2d", 8),
+        (meshes.kuhn_tet_mesh(5, 0.08, 57), meshes.kuhn_tet_mesh(8, 0.08, 58), "gaussian_bumps_3d", 128),
+        (meshes.kuhn_tet_mesh(4, 0.08, 59), meshes.kuhn_tet_mesh(6, 0.08, 60), "gaussian_bumps_3d", 64),
+        (meshes.kuhn_tet_mesh(5, 0.08, 61), meshes.kuhn_tet_mesh(7, 0.08, 62), "gaussian_bumps_3d", 40),
     ]
     for tm, sm, fname, N in specs:
         out.append((tm, sm, fields.evaluate(fname, np, sm[0]), N))
