@@ -88,10 +88,10 @@ static int lanes_of(int v) { return v <= 2 ? 64 : (v == 3 ? 32 : 16); }
 
 template <int D, int G, int P>
 __device__ __forceinline__ void batch_elements(const BatchXfer& x, int64_t start, int lane, unsigned& nf,
-                                               unsigned& nood) {
+                                               unsigned& nood, double* c_af) {
     const uint32_t t = uint32_t(start) + uint32_t(lane / G);
     fused_elements<D, G, P, 1>(x.src, x.coords, x.n, x.conn, x.vol, uint32_t(x.E), x.N, x.alpha, x.key, x.g,
-                               x.beta, t, lane % G, nf, nood);
+                               x.beta, t, lane % G, nf, nood, c_af);
 }
 
 // One launch per (dimension, G, P) variant over that variant's tiles
@@ -100,15 +100,17 @@ template <int D, int G, int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 2 ? 3 : 2))) void k_batch_fused(
     const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles, int64_t first, int64_t last,
     unsigned long long* __restrict__ nonfinite) {
+    __shared__ double lds[4 * kWaveSlots<D>];
     const int lane = threadIdx.x & 63;
     const int64_t stride = int64_t(gridDim.x) * 4;
     // the wave index, uniform by construction: the tile and its descriptor load into scalar registers
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    double* c_af = lds + wv * kWaveSlots<D>;
     for (int64_t w = first + int64_t(blockIdx.x) * 4 + wv; w < last; w += stride) {
         const Tile tl = tiles[w];
         const BatchXfer& x = X[tl.k];
         unsigned nf = 0, nood = 0;
-        batch_elements<D, G, P>(x, tl.start, lane, nf, nood);
+        batch_elements<D, G, P>(x, tl.start, lane, nf, nood, c_af);
         if (nf) atomicAdd(nonfinite + tl.k, (unsigned long long)nf);
         if (nood) atomicAdd(x.src_ood, (unsigned long long)nood);
     }
@@ -166,16 +168,18 @@ static int fused_per_cu(int c) {
 // step 1: g = f^s at the target nodes, 256 (2D) or 128 (3D) nodes per wavefront
 __global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles,
                                                      int64_t n_tiles) {
+    __shared__ double lds[4 * kWaveSlots<3>];   // sized for the larger (3D) slots
     const int64_t stride = int64_t(gridDim.x) * 4;
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    double* c_af = lds + wv * kWaveSlots<3>;
     for (int64_t w = int64_t(blockIdx.x) * 4 + wv; w < n_tiles; w += stride) {
         const Tile tl = tiles[w];
         const BatchXfer& x = X[tl.k];
         unsigned nood;
         if (tl.variant == 2)
-            nood = eval_wave<2, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr);
+            nood = eval_wave<2, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af);
         else
-            nood = eval_wave<3, 2, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr);
+            nood = eval_wave<3, 2, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af);
         if (nood) atomicAdd(x.src_ood, (unsigned long long)nood);
     }
 }

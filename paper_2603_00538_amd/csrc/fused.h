@@ -11,13 +11,14 @@ namespace ft {
 
 // lane: index within the element's lane group [0, G); t >= E marks an idle
 // group (it still takes part in the wave-cooperative localization).  Adds the
-// lane's non-finite and out-of-domain counts to nf / nood.
+// lane's non-finite and out-of-domain counts to nf / nood.  c_af: the wave's
+// LDS candidate slots (kWaveSlots<D> doubles).
 template <int D, int G, int P, int FC>
 __device__ __forceinline__ void fused_elements(const SrcView& S, const double* __restrict__ X, int64_t n,
                                                const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                uint32_t E, uint32_t N, double alpha, SampleKey key,
                                                const double* __restrict__ g, double* __restrict__ beta, uint32_t t,
-                                               int lane, unsigned& nf, unsigned& nood) {
+                                               int lane, unsigned& nf, unsigned& nood, double* __restrict__ c_af) {
     // with one element per wave, its connectivity, vertices and control values
     // are wave-uniform: scalar loads into scalar registers
     if (G == 64) t = __builtin_amdgcn_readfirstlane(t);
@@ -65,7 +66,7 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
         }
         double best[P];
         int bid[P];
-        locate_wave<D, P>(S, pt, act, best, bid);
+        locate_wave<D, P>(S, pt, act, best, bid, c_af);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             if (!act[q]) continue;

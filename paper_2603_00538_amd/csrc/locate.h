@@ -189,11 +189,11 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
             }
 }
 
-// LDS slots for the candidates' affine forms: 64 per wave of a 256-thread
-// block, sized for 3D.  One array at namespace scope, so that a kernel that
-// inlines several localization variants (the batch) allocates it once.
-constexpr int kMaxAL = 16;
-__shared__ double g_cand_af[4 * 64 * kMaxAL];
+// LDS slots for the candidates' affine forms: 64 per wave, (D+1)^2 doubles
+// each.  Every kernel that localizes declares its block's slots (waves per
+// block x kWaveSlots<D> doubles) and hands each wave its own part.
+template <int D>
+constexpr int kWaveSlots = 64 * (D + 1) * (D + 1);
 
 // Inclusive prefix sum over the 64 lanes of the wave: a scan inside each row
 // of 16 lanes on the DPP crossbar (shifts by 1, 2, 4, 8; lanes shifted in
@@ -222,7 +222,7 @@ __device__ __forceinline__ int wave_scan_incl(int x) {
 // kFastTau, so inside), from the full rule for the others.
 template <int D, int P>
 __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[P][D], const bool (&active)[P],
-                                            double (&best)[P], int (&bid)[P]) {
+                                            double (&best)[P], int (&bid)[P], double* __restrict__ c_af) {
     constexpr int RS = RecSize<D>::value;
     constexpr int BS = BoxSize<D>::value;
     constexpr int MAX_SPAN = 64;   // bins a wave searches as one flat sequence (one per lane)
@@ -278,7 +278,6 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         // coordinates, first registration and count.  The candidate slots of all
         // these bins are then culled 64 at a time in one flat sequence.
         constexpr int AL = (D + 1) * (D + 1);   // affine form: D+1 constants, (D+1) x D gradients
-        double* c_af = g_cand_af + ((threadIdx.x >> 6) & 3) * (64 * kMaxAL);   // this wave's slots
         const int wx = b1[0] - b0[0] + 1, wy = b1[1] - b0[1] + 1;
         int64_t bstart = 0;
         int bcnt = 0;
@@ -390,7 +389,7 @@ __device__ __forceinline__ double p1_value(const SrcView& S, int bid, const doub
 template <int D, int P, bool IN_F32, bool OUT_F32>
 __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, int64_t lim,
                                               const void* __restrict__ pts_, int64_t ld, void* __restrict__ out_,
-                                              int64_t ld_out, int32_t* __restrict__ ids) {
+                                              int64_t ld_out, int32_t* __restrict__ ids, double* __restrict__ c_af) {
     const int lane = threadIdx.x & 63;
     double p[P][D];
     bool active[P];
@@ -408,7 +407,7 @@ __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, in
     }
     double best[P];
     int bid[P];
-    locate_wave<D, P>(S, p, active, best, bid);
+    locate_wave<D, P>(S, p, active, best, bid, c_af);
     unsigned int nood = 0;
 #pragma unroll
     for (int q = 0; q < P; ++q) {

@@ -33,8 +33,11 @@ __global__ __launch_bounds__(256) void k_plan_locate(SrcView S, const double* __
                                                      const int32_t* __restrict__ conn, uint32_t E, uint32_t N,
                                                      SampleKey key, int32_t* __restrict__ ids,
                                                      unsigned long long* __restrict__ n_ood) {
+    __shared__ double lds[4 * kWaveSlots<D>];
+    double* c_af = lds + (threadIdx.x >> 6) * kWaveSlots<D>;
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t t = gid / G;
+    uint32_t t = gid / G;
+    if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
     const int lane = int(gid & (G - 1));
     const bool valid = t < E;
     const uint32_t tt = valid ? t : 0u;
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(256) void k_plan_locate(SrcView S, const double* __
         }
         double best[P];
         int bid[P];
-        locate_wave<D, P>(S, pt, act, best, bid);
+        locate_wave<D, P>(S, pt, act, best, bid, c_af);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             if (!act[q]) continue;
@@ -114,7 +117,8 @@ __global__ __launch_bounds__(256) void k_plan_elements(const double* __restrict_
                                                        double* __restrict__ beta,
                                                        unsigned long long* __restrict__ nonfinite) {
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t t = gid / G;
+    uint32_t t = gid / G;
+    if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
     const int lane = int(gid & (G - 1));
     if (t >= E) return;   // the whole group leaves together
     int v[D + 1];

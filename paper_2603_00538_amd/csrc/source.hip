@@ -214,18 +214,26 @@ __global__ void k_sort_bins(const int64_t* __restrict__ ptr, int64_t nseg, int32
 }
 
 // Each wave owns 64*P consecutive points; lane l holds points base + q*64 + l.
-template <int D, int P, bool IN_F32, bool OUT_F32>
-__global__ __launch_bounds__(256) void k_src_eval(SrcView S, int64_t head, int64_t npts, const void* __restrict__ pts_,
-                                                  int64_t ld, void* __restrict__ out_, int64_t ld_out,
-                                                  int32_t* __restrict__ ids, unsigned long long* __restrict__ n_ood) {
+// WPB waves per block, each with its own LDS candidate slots: small blocks
+// release their slots as soon as their waves end (waves of a block finish at
+// very different times: early exit, fallback searches).
+template <int D, int P, bool IN_F32, bool OUT_F32, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_src_eval(SrcView S, int64_t head, int64_t npts,
+                                                       const void* __restrict__ pts_, int64_t ld,
+                                                       void* __restrict__ out_, int64_t ld_out,
+                                                       int32_t* __restrict__ ids,
+                                                       unsigned long long* __restrict__ n_ood) {
+    __shared__ double lds[WPB * kWaveSlots<D>];
+    const int wv = WPB == 1 ? 0 : int(threadIdx.x >> 6);
     // two segments, [0, head) and [head, npts), each starting on a wavefront boundary
     constexpr int64_t WP = 64 * P;
-    const int64_t wave = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int64_t wave = int64_t(blockIdx.x) * WPB + wv;
     const int64_t wh = (head + WP - 1) / WP;
     const int64_t base = wave < wh ? wave * WP : head + (wave - wh) * WP;
     const int64_t lim = wave < wh ? head : npts;
     if (base >= lim) return;   // wave-uniform
-    const unsigned nood = eval_wave<D, P, IN_F32, OUT_F32>(S, base, lim, pts_, ld, out_, ld_out, ids);
+    const unsigned nood =
+        eval_wave<D, P, IN_F32, OUT_F32>(S, base, lim, pts_, ld, out_, ld_out, ids, lds + wv * kWaveSlots<D>);
     if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
 
@@ -382,6 +390,8 @@ SrcView source_view(const ft_source* S) {
     return v;
 }
 
+constexpr int kEvalWavesPerBlock = 1;
+
 template <int D>
 static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec,
                              void* out, int64_t ld_out, int32_t* ids, hipStream_t s) {
@@ -390,12 +400,15 @@ static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const voi
     constexpr int P = D == 2 ? 4 : 2;
     constexpr int64_t WP = 64 * P;
     const SrcView v = source_view(S);
+    constexpr int WPB = kEvalWavesPerBlock;
     const int64_t waves = (head + WP - 1) / WP + (npts - head + WP - 1) / WP;
-    const unsigned grid = unsigned((waves + 3) / 4);
+    const unsigned grid = unsigned((waves + WPB - 1) / WPB);
     if (prec == FT_F64)
-        k_src_eval<D, P, false, false><<<grid, 256, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+        k_src_eval<D, P, false, false, WPB>
+            <<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
     else
-        k_src_eval<D, P, true, true><<<grid, 256, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+        k_src_eval<D, P, true, true, WPB>
+            <<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
 }
