@@ -20,15 +20,15 @@
 // element's box and direction ranges must meet the wave's.  Only the
 // survivors fetch the element's absolute affine barycentric form, and park it
 // in the wave's LDS; every lane then tests its points against each survivor
-// in lane order (broadcast LDS reads).  The selection test accepts an element once
-// its min mu exceeds 1e-9, far above that form's rounding, so an accepted
-// element truly contains the point and is the unique winner.  Points never
-// accepted (within 1e-9 of a face, or outside) are re-searched alone with the
-// full rule over the bins that can hold their elements.  The barycentrics
-// used to interpolate are always recomputed from the element origin.  Waves
-// whose points need more than 64 bins (scattered input) search point by
-// point.  Callers launch 256-thread blocks (four waves share the block's LDS
-// slots).
+// in lane order (broadcast LDS reads).  The selection test accepts an element
+// once mu_1..mu_D and mu_0 = 1 - their sum all exceed 1e-9, far above the
+// rounding of that form, so an accepted element truly contains the point and
+// is the unique winner; a wave stops when all its points are accepted.
+// Points never accepted (within 1e-9 of a face, or outside) are re-searched
+// alone with the full rule over the bins that can hold their elements.  The
+// barycentrics used to interpolate are always recomputed from the element
+// origin.  Waves whose points need more than 64 bins (scattered input) search
+// point by point.  Each wave brings its own LDS slots (kWaveSlots<D> doubles).
 #pragma once
 
 #include <cfloat>
@@ -149,18 +149,23 @@ __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int
     }
 }
 
-// min_k mu_k(p) from an affine form in LDS (wave-uniform address: a broadcast read).
+// Fast selection test from a parked form in LDS (wave-uniform address: a
+// broadcast read).  The form holds the constants of mu_1..mu_D, then their
+// gradients (mu_0 = 1 - sum of the others): true when every mu_k exceeds
+// kFastTau at p, i.e. p lies inside the element with that margin.
 template <int D>
-__device__ __forceinline__ double affine_min_mu_lds(const double* af, const double (&p)[D]) {
-    double mn = 0.0;
+__device__ __forceinline__ bool inside_lds(const double* af, const double (&p)[D]) {
+    bool in = true;
+    double s;
 #pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        double s = af[k];
+    for (int k = 0; k < D; ++k) {
+        double l = af[k];
 #pragma unroll
-        for (int c = 0; c < D; ++c) s = fma(af[D + 1 + k * D + c], p[c], s);
-        mn = k == 0 ? s : fmin(mn, s);
+        for (int c = 0; c < D; ++c) l = fma(af[D + k * D + c], p[c], l);
+        in &= l > kFastTau;
+        s = k == 0 ? l : s + l;
     }
-    return mn;
+    return in & (s < 1.0 - kFastTau);
 }
 
 // Own-bin search of one point with the full rule (absolute coordinates).
@@ -189,11 +194,11 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
             }
 }
 
-// LDS slots for the candidates' affine forms: 64 per wave, (D+1)^2 doubles
+// LDS slots for the candidates' parked forms: 64 per wave, D(D+1) doubles
 // each.  Every kernel that localizes declares its block's slots (waves per
 // block x kWaveSlots<D> doubles) and hands each wave its own part.
 template <int D>
-constexpr int kWaveSlots = 64 * (D + 1) * (D + 1);
+constexpr int kWaveSlots = 64 * D * (D + 1);
 
 // Inclusive prefix sum over the 64 lanes of the wave: a scan inside each row
 // of 16 lanes on the DPP crossbar (shifts by 1, 2, 4, 8; lanes shifted in
@@ -217,9 +222,9 @@ __device__ __forceinline__ int wave_scan_incl(int x) {
 // Rule winner for each of this lane's P points (see the file comment).  Every
 // lane of the wave must call it (points a lane does not own pass
 // active = false).  Returns bid = the winner's element id (INT_MAX if no
-// candidate was found) and best = its min-barycentric: from the candidates'
-// absolute affine forms for points the fast test accepted (then above
-// kFastTau, so inside), from the full rule for the others.
+// candidate was found) and best: 1 for points the fast test accepted (inside
+// their element with margin kFastTau), the full rule's max min-barycentric
+// for the others.
 template <int D, int P>
 __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[P][D], const bool (&active)[P],
                                             double (&best)[P], int (&bid)[P], double* __restrict__ c_af) {
@@ -250,12 +255,15 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         b1[c] = uniform_int(bin_of(whi[c] + S.g.hx[c], c, S.g));
         span *= b1[c] - b0[c] + 1;
     }
-    // inactive points start above the acceptance threshold so that the
-    // wave's exit test needs no activity mask
+    // fm[q]: the lanes whose point q is accepted (wave-uniform masks; inactive
+    // points count as accepted, so the wave's exit test needs no activity mask)
+    uint64_t fm[P];
+    const uint64_t wave_mask = __ballot(1);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        best[q] = active[q] ? -DBL_MAX : DBL_MAX;
+        best[q] = -DBL_MAX;
         bid[q] = INT_MAX;
+        fm[q] = __ballot(!active[q]);
     }
 
     if (span <= MAX_SPAN) {
@@ -277,7 +285,7 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         // Lane i < span describes bin i of the wave's bin box (x fastest): its
         // coordinates, first registration and count.  The candidate slots of all
         // these bins are then culled 64 at a time in one flat sequence.
-        constexpr int AL = (D + 1) * (D + 1);   // affine form: D+1 constants, (D+1) x D gradients
+        constexpr int AL = D * (D + 1);   // parked form: constants of mu_1..mu_D, then D x D gradients
         const int wx = b1[0] - b0[0] + 1, wy = b1[1] - b0[1] + 1;
         int64_t bstart = 0;
         int bcnt = 0;
@@ -314,12 +322,14 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 for (int k = 0; k < ND; ++k) ov &= (bx_[2 * D + k] <= fdhi[k]) & (bx_[2 * D + ND + k] >= fdlo[k]);
             }
             // only the survivors (a small fraction of the slots) fetch their affine
-            // form and park it in their own LDS slot; they are then read back in
-            // lane order
+            // form (mu_1..mu_D) and park it in their own LDS slot; they are then
+            // read back in lane order
             if (ov) {
-                const double* r = S.rec + int64_t(cid) * RS;
+                const double* r = S.rec + int64_t(cid) * RS + RecAffine<D>::value;
 #pragma unroll
-                for (int m = 0; m < AL; ++m) c_af[lane * AL + m] = r[RecAffine<D>::value + m];
+                for (int k = 0; k < D; ++k) c_af[lane * AL + k] = r[1 + k];
+#pragma unroll
+                for (int m = 0; m < D * D; ++m) c_af[lane * AL + D + m] = r[2 * D + 1 + m];
             }
             uint64_t mask = __ballot(ov);
             __builtin_amdgcn_wave_barrier();
@@ -328,26 +338,30 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 mask &= mask - 1;
                 const int e1 = read_lane(cid, l1);
                 const double* a1 = &c_af[l1 * AL];
-                bool done = true;
+                uint64_t all = wave_mask;
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    const double m1 = affine_min_mu_lds<D>(a1, p[q]);
-                    bid[q] = m1 > best[q] ? e1 : bid[q];
-                    best[q] = fmax(best[q], m1);
-                    done &= best[q] > kFastTau;
+                    const bool in = inside_lds<D>(a1, p[q]);
+                    bid[q] = in ? e1 : bid[q];
+                    fm[q] |= __builtin_amdgcn_ballot_w64(in);
+                    all &= fm[q];
                 }
-                if (__all(done)) {
+                if (all == wave_mask) {
                     finished = true;
                     break;
                 }
             }
             __builtin_amdgcn_wave_barrier();
         }
-        // points not accepted by the fast test (near a face, or outside): the full rule
-        // in the point's own bin
+        // accepted points lie inside their element with margin kFastTau; the others
+        // (near a face, or outside) take the full rule over the bins that can hold
+        // their elements
 #pragma unroll
-        for (int q = 0; q < P; ++q)
-            if (active[q] && !(best[q] > kFastTau)) locate_point<D>(S, p[q], best[q], bid[q]);
+        for (int q = 0; q < P; ++q) {
+            if (!active[q]) continue;
+            if ((fm[q] >> lane) & 1) best[q] = 1.0;
+            else locate_point<D>(S, p[q], best[q], bid[q]);
+        }
     } else {
 #pragma unroll
         for (int q = 0; q < P; ++q)
