@@ -100,12 +100,13 @@ template <int D, int G, int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 2 ? 3 : 2))) void k_batch_fused(
     const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles, int64_t first, int64_t last,
     unsigned long long* __restrict__ nonfinite) {
-    __shared__ double lds[4 * kWaveSlots<D>];
+    constexpr int WS = kWaveSlots<D> + kLamSlots<D, P>;
+    __shared__ double lds[4 * WS];
     const int lane = threadIdx.x & 63;
     const int64_t stride = int64_t(gridDim.x) * 4;
     // the wave index, uniform by construction: the tile and its descriptor load into scalar registers
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    double* c_af = lds + wv * kWaveSlots<D>;
+    double* c_af = lds + wv * WS;
     for (int64_t w = first + int64_t(blockIdx.x) * 4 + wv; w < last; w += stride) {
         const Tile tl = tiles[w];
         const BatchXfer& x = X[tl.k];

@@ -26,11 +26,12 @@ void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n, const int32_
                 const double* __restrict__ vol, uint32_t E, uint32_t N, double alpha, SampleKey key,
                 const double* __restrict__ g, double* __restrict__ beta, unsigned long long* __restrict__ nonfinite,
                 unsigned long long* __restrict__ n_ood) {
-    __shared__ double lds[4 * kWaveSlots<D>];
+    constexpr int WS = kWaveSlots<D> + kLamSlots<D, P>;
+    __shared__ double lds[4 * WS];
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
     unsigned nf = 0, nood = 0;
     fused_elements<D, G, P, FC>(S, X, n, conn, vol, E, N, alpha, key, g, beta, gid / G, int(gid & (G - 1)), nf, nood,
-                                lds + (threadIdx.x >> 6) * kWaveSlots<D>);
+                                lds + (threadIdx.x >> 6) * WS);
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
     if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
