@@ -47,10 +47,10 @@ constexpr double kOutTol = -1e-10;
 //   [AF + D + 1, VAL)         gradients g_k (D each), k = 0..D; g_1..g_D are the
 //                             rows of the inverse of J = [x1-x0 | ... | xd-x0]
 //   [VAL, VAL + D + 1)        vertex values of a one-field source (else zero)
-// The absolute affine form [c | g] selects the element (one contiguous block
-// the cull loads); the origin form mu_{k+1} = g_{k+1} . (x - x0) gives the
-// barycentrics used to interpolate, and for one field the vertex values sit
-// in the same record.
+// The absolute affine form selects the element (the cull parks c_1..c_D and
+// g_1..g_D; mu_0 follows as 1 minus the others); the origin form
+// mu_{k+1} = g_{k+1} . (x - x0) gives the barycentrics used to interpolate,
+// and for one field the vertex values sit in the same record.
 template <int D>
 struct RecSize { static constexpr int value = D == 2 ? 16 : 32; };
 template <int D>
