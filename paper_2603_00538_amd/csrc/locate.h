@@ -433,8 +433,25 @@ __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, in
         if (!out_) continue;   // localization only
         double mu[D + 1];
         winner_mu<D>(S, bid[q], p[q], mu);
+        if (S.F == 1) {
+            const double y = p1_value<D>(S, bid[q], mu, 0);
+            if (OUT_F32)
+                static_cast<float*>(out_)[i] = float(y);
+            else
+                static_cast<double*>(out_)[i] = y;
+            continue;
+        }
+        // many fields: the element's vertices once, then one gather per vertex and field
+        int vk[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) vk[k] = found ? S.conn[int64_t(bid[q]) * (D + 1) + k] : 0;
+#pragma unroll 4
         for (int f = 0; f < S.F; ++f) {
-            const double y = p1_value<D>(S, bid[q], mu, f);
+            const double* Fv = S.values + int64_t(f) * S.n;
+            double y = 0.0;
+            if (found)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) y = fma(mu[k], Fv[vk[k]], y);
             if (OUT_F32)
                 static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
             else

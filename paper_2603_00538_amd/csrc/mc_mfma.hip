@@ -15,9 +15,9 @@
 // (exact, undone when the step's products are added to binary64 running
 // sums); bf16 shares the binary32 exponent range and needs no scaling.
 //
-// One wavefront per element; the block's four waves stage their lambda
-// (recomputed from the same Philox counters as the emission, binary32 form),
-// the control values and a chunk of query values in LDS.  Every element sum
+// One wavefront per element stages its lambda (recomputed from the same
+// Philox counters as the emission, binary32 form), the control values and a
+// chunk of query values in LDS.  Every element sum
 // is a fixed sequence of MFMAs and binary64 adds, so results are reproducible
 // run to run.
 #include "sampling.h"
@@ -59,116 +59,130 @@ struct Split<true> {
     }
 };
 
-// One wavefront per element.  Values are read a field row at a time (64
-// consecutive samples, one per lane: fully coalesced) into the wave's LDS
-// chunk, then read back in the MFMA operand layout; every K step of 32
-// samples gets its own power-of-two row scaling (f16), and its products are
-// unscaled into binary64 running sums, so memory is read once.
-constexpr int MF_CHUNK = 64;   // samples staged per chunk (two K steps)
+// One wavefront (and workgroup) per element.  The values are staged 16 field
+// rows x 128 samples at a time (one chunk): 32 coalesced loads per lane, each
+// reading 64 consecutive samples of one row, all in flight together, and the
+// next chunk's loads are issued before this chunk's matrix-core work so that
+// memory and compute overlap.  Every K step of 32 samples gets its own
+// power-of-two row scaling (f16), and its products are unscaled into binary64
+// running sums, so memory is read once.
+constexpr int MF_CHUNK = 128;                   // samples per staged chunk (four K steps)
+constexpr int MF_LPL = 16 * MF_CHUNK / 64;      // staged floats per lane
 
 template <int D, bool BF16>
-__global__ __launch_bounds__(256) void k_consume_mfma(const float* __restrict__ values, int64_t ld, int F,
-                                                      const int32_t* __restrict__ conn, const double* __restrict__ vol,
-                                                      int64_t n, uint32_t E, uint32_t N, float alpha, SampleKey key,
-                                                      double* __restrict__ beta,
-                                                      unsigned long long* __restrict__ nonfinite) {
+__global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ values, int64_t ld, int F,
+                                                     const int32_t* __restrict__ conn, const double* __restrict__ vol,
+                                                     int64_t n, uint32_t E, uint32_t N, float alpha, SampleKey key,
+                                                     double* __restrict__ beta,
+                                                     unsigned long long* __restrict__ nonfinite) {
     using S = Split<BF16>;
-    __shared__ float lam_s[4][MF_NMAX][4];
-    __shared__ float g_s[4][4][64];
-    __shared__ float r_s[4][16][MF_CHUNK + 1];   // +1: row stride off the bank period
-    const int w = threadIdx.x >> 6;
+    __shared__ float lam_s[MF_NMAX][4];
+    __shared__ float g_s[4][64];
+    __shared__ float r_s[16][MF_CHUNK + 1];   // +1: row stride off the bank period
     const int lane = threadIdx.x & 63;
-    const uint32_t t = blockIdx.x * 4u + uint32_t(w);
-    const bool valid = t < E;
-    const uint32_t tt = valid ? t : 0u;
+    const uint32_t t = blockIdx.x;            // grid = E: every block has an element
     int v[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(tt) * (D + 1) + k];
+    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
     // stage lambda (binary32 sampling form) and the control values
     for (uint32_t j = lane; j < MF_NMAX; j += 64) {
         float lf[D + 1];
-        if (valid && j < N) {
-            sample_lambda_f32<D>(tt, j, key, lf);
+        if (j < N) {
+            sample_lambda_f32<D>(t, j, key, lf);
         } else {
 #pragma unroll
             for (int k = 0; k <= D; ++k) lf[k] = 0.0f;
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) lam_s[w][j][k] = k <= D ? lf[k < D + 1 ? k : 0] : 0.0f;
+        for (int k = 0; k < 4; ++k) lam_s[j][k] = k <= D ? lf[k < D + 1 ? k : 0] : 0.0f;
     }
     for (int idx = lane; idx < 4 * 64; idx += 64) {
         const int k = idx >> 6, f = idx & 63;
-        g_s[w][k][f] = (valid && k <= D && f < F) ? values[int64_t(f) * ld + v[k]] : 0.0f;
+        g_s[k][f] = (k <= D && f < F) ? values[int64_t(f) * ld + v[k]] : 0.0f;
     }
     __syncthreads();
 
     const int sg = lane >> 4;            // sample group within a K step (8 samples)
     const int col = lane & 15;           // A row (field in the tile) / B, C column
-    const int64_t qbase = n + int64_t(tt) * N;
+    const int64_t qbase = n + int64_t(t) * N;
+    const int nchunk = int((N + MF_CHUNK - 1) / MF_CHUNK);
+    const int nstep = ((F + 15) / 16) * nchunk;   // (field tile, sample chunk) pairs
     unsigned int nf = 0;
-    const double scale_out = valid ? vol[tt] / double(N) : 0.0;
-    for (int f0 = 0; f0 < F; f0 += 16) {
-        double run[4] = {0.0, 0.0, 0.0, 0.0};   // C[4 sg + i][col], unscaled
-        for (uint32_t c0 = 0; c0 < N; c0 += MF_CHUNK) {
-            // coalesced: row r's samples c0 .. c0+63, one per lane
-            for (int r = 0; r < 16; ++r) {
-                const uint32_t j = c0 + uint32_t(lane);
-                float y = 0.0f;
-                if (valid && f0 + r < F && j < N) {
-                    y = values[int64_t(f0 + r) * ld + qbase + j];
-                    nf += !isfinite(y);
-                }
-                r_s[w][r][lane] = y;
-            }
-            __builtin_amdgcn_wave_barrier();
-            for (int ks = 0; ks < MF_CHUNK / 32; ++ks) {
-                if (c0 + uint32_t(ks * 32) >= N) break;   // wave-uniform: no samples left in this chunk
-                const uint32_t jb = c0 + uint32_t(ks * 32 + sg * 8);
-                const int f = f0 + col;
-                float rv[8];
-                float mx = 0.0f;
+    const double scale_out = vol[t] / double(N);
+    // load m of chunk s: row m/2 of its field tile, samples (m%2)*64 + lane of its chunk
+    float pre[MF_LPL];
+    auto load_chunk = [&](int s_) {
+        const int f0 = (s_ / nchunk) * 16;
+        const uint32_t c0 = uint32_t(s_ % nchunk) * MF_CHUNK;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const uint32_t j = jb + uint32_t(i);
-                    float r = 0.0f;
-                    if (valid && f < F && j < N) {
-                        float gx = 0.0f;
-#pragma unroll
-                        for (int k = 0; k <= D; ++k) gx = fmaf(lam_s[w][j][k], g_s[w][k][f & 63], gx);
-                        r = r_s[w][col][ks * 32 + sg * 8 + i] - alpha * gx;
-                    }
-                    rv[i] = r;
-                    mx = fmaxf(mx, fabsf(r));
-                }
-                int e = 0;
-                if (!BF16) {   // row maximum over this K step's 32 samples -> [2^13, 2^14)
-                    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-                    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-                    if (mx > 0.0f && isfinite(mx)) e = 13 - ilogbf(mx);
-                }
-                const float sc = ldexpf(1.0f, e);
-                typename S::vec ahi, alo, bhi, blo;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const uint32_t j = jb + uint32_t(i);
-                    S::set(ahi, alo, i, rv[i] * sc);
-                    const float lv = (col <= D && j < MF_NMAX) ? lam_s[w][j < MF_NMAX ? j : 0][col & 3] : 0.0f;
-                    S::set(bhi, blo, i, lv);
-                }
-                v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                acc = S::mma(ahi, bhi, acc);
-                acc = S::mma(ahi, blo, acc);
-                acc = S::mma(alo, bhi, acc);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) run[i] += ldexp(double(acc[i]), -__shfl(e, 4 * sg + i, 64));
-            }
-            __builtin_amdgcn_wave_barrier();
+        for (int m = 0; m < MF_LPL; ++m) {
+            const int f = f0 + (m >> 1);
+            const uint32_t j = c0 + uint32_t((m & 1) * 64 + lane);
+            pre[m] = (f < F && j < N) ? values[int64_t(f) * ld + qbase + j] : 0.0f;
         }
-        // C[row][col]: row = 4*sg + i (field f0 + row), col = barycentric index
+    };
+    load_chunk(0);
+    double run[4] = {0.0, 0.0, 0.0, 0.0};   // C[4 sg + i][col] of the current field tile, unscaled
+    for (int s_ = 0; s_ < nstep; ++s_) {
+        const int f0 = (s_ / nchunk) * 16;
+        const uint32_t c0 = uint32_t(s_ % nchunk) * MF_CHUNK;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int fo = f0 + 4 * sg + i;
-            if (valid && col <= D && fo < F) beta[(int64_t(fo) * E + tt) * (D + 1) + col] = run[i] * scale_out;
+        for (int m = 0; m < MF_LPL; ++m) {
+            nf += !isfinite(pre[m]);
+            r_s[m >> 1][(m & 1) * 64 + lane] = pre[m];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (s_ + 1 < nstep) load_chunk(s_ + 1);   // in flight during this chunk's products
+        for (int ks = 0; ks < MF_CHUNK / 32; ++ks) {
+            if (c0 + uint32_t(ks * 32) >= N) break;   // wave-uniform: no samples left in this chunk
+            const uint32_t jb = c0 + uint32_t(ks * 32 + sg * 8);
+            const int f = f0 + col;
+            float rv[8];
+            float mx = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t j = jb + uint32_t(i);
+                float r = 0.0f;
+                if (f < F && j < N) {
+                    float gx = 0.0f;
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) gx = fmaf(lam_s[j][k], g_s[k][f & 63], gx);
+                    r = r_s[col][ks * 32 + sg * 8 + i] - alpha * gx;
+                }
+                rv[i] = r;
+                mx = fmaxf(mx, fabsf(r));
+            }
+            int e = 0;
+            if (!BF16) {   // row maximum over this K step's 32 samples -> [2^13, 2^14)
+                mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+                mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+                if (mx > 0.0f && isfinite(mx)) e = 13 - ilogbf(mx);
+            }
+            const float sc = ldexpf(1.0f, e);
+            typename S::vec ahi, alo, bhi, blo;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t j = jb + uint32_t(i);
+                S::set(ahi, alo, i, rv[i] * sc);
+                const float lv = (col <= D && j < MF_NMAX) ? lam_s[j < MF_NMAX ? j : 0][col & 3] : 0.0f;
+                S::set(bhi, blo, i, lv);
+            }
+            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = S::mma(ahi, bhi, acc);
+            acc = S::mma(ahi, blo, acc);
+            acc = S::mma(alo, bhi, acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) run[i] += ldexp(double(acc[i]), -__shfl(e, 4 * sg + i, 64));
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (s_ % nchunk == nchunk - 1) {
+            // C[row][col]: row = 4*sg + i (field f0 + row), col = barycentric index
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int fo = f0 + 4 * sg + i;
+                if (col <= D && fo < F) beta[(int64_t(fo) * E + t) * (D + 1) + col] = run[i] * scale_out;
+                run[i] = 0.0;
+            }
         }
     }
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
@@ -177,20 +191,21 @@ __global__ __launch_bounds__(256) void k_consume_mfma(const float* __restrict__ 
 ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
     const SampleKey key{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
     const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
-    const unsigned grid = grid_for(T->E, 4);
+    if (T->E == 0) return FT_OK;
+    const unsigned grid = unsigned(T->E);   // one element per workgroup
     const bool bf = cfg->precision == FT_SPLIT_BF16;
     const float* vals = static_cast<const float*>(values);
     const uint32_t N = uint32_t(cfg->samples_per_elem);
     const float a = float(cfg->alpha);
     if (T->dim == 2) {
-        if (bf) k_consume_mfma<2, true><<<grid, 256, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+        if (bf) k_consume_mfma<2, true><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
                                                              uint32_t(T->E), N, a, key, T->beta, T->counters);
-        else k_consume_mfma<2, false><<<grid, 256, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+        else k_consume_mfma<2, false><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
                                                            uint32_t(T->E), N, a, key, T->beta, T->counters);
     } else {
-        if (bf) k_consume_mfma<3, true><<<grid, 256, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+        if (bf) k_consume_mfma<3, true><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
                                                              uint32_t(T->E), N, a, key, T->beta, T->counters);
-        else k_consume_mfma<3, false><<<grid, 256, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+        else k_consume_mfma<3, false><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
                                                            uint32_t(T->E), N, a, key, T->beta, T->counters);
     }
     FT_TRY_HIP(hipGetLastError());

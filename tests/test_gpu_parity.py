@@ -334,7 +334,7 @@ def test_fused_route_matches_unfused_and_oracle(dim, N):
 
 # ---------------------------------------------------------------- split matrix-core form
 @pytest.mark.parametrize("prec", [ft.FT_SPLIT_F16, ft.FT_SPLIT_BF16])
-@pytest.mark.parametrize("dim,F,N", [(3, 20, 16), (3, 64, 128), (2, 9, 40), (2, 33, 256)])
+@pytest.mark.parametrize("dim,F,N", [(3, 20, 16), (3, 64, 128), (2, 9, 40), (2, 33, 256), (3, 17, 200)])
 def test_split_matrix_core_form_within_1e5(prec, dim, F, N):
     """Many fields at once through the split-product MFMA element sums."""
     tm, sm = _small_2d() if dim == 2 else _small_3d()
