@@ -227,6 +227,7 @@ struct ft_source {
     double* coords = nullptr;   // [dim][n]
     int32_t* conn = nullptr;    // [E][dim+1]
     double* values = nullptr;   // [F][n]
+    double* values_nm = nullptr;   // [n][F] node-major copy when F > 1 (a node's fields in one row)
     double* rec = nullptr;      // [E][RS]: origin + inverse Jacobian (barycentric map)
     float* box = nullptr;       // [E][8 | 6] outward-rounded boxes (2D also x+y, x-y ranges)
     int32_t nb[3] = {1, 1, 1};  // bins per axis

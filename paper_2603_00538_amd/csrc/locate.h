@@ -107,7 +107,8 @@ struct SrcView {
     const double* rec;
     const float* box;
     const int32_t* conn;
-    const double* values;
+    const double* values;      // [F][n]
+    const double* values_nm;   // [n][F] (F > 1)
     const int64_t* bin_ptr;
     const int32_t* bin_elems;
     int64_t n;

@@ -19,6 +19,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "locate.h"
@@ -237,6 +238,119 @@ __global__ __launch_bounds__(64 * WPB) void k_src_eval(SrcView S, int64_t head, 
     if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
 
+// Node-major copy of the nodal values: out[v * F + f] = values[f * n + v].
+__global__ void k_node_major(const double* __restrict__ values, int64_t n, int F, double* __restrict__ out) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n * F; i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t v = i / F;
+        const int f = int(i - v * F);
+        out[i] = values[int64_t(f) * n + v];
+    }
+}
+
+// Many fields (F > 1): localization as k_src_eval, then the interpolation with
+// the lanes over fields.  Each lane parks its points' winner barycentrics and
+// vertices in LDS; for a block of 16 fields, four points at a time are
+// evaluated by 16 lanes each (lane = field), reading a vertex's 16 field
+// values as one 128-byte row of the node-major copy; the values collect in an
+// LDS tile [16 fields][64 points] and leave as 16 coalesced row stores.
+constexpr int kManyFB = 16;   // fields per block
+
+template <int D, int P, bool OUT_F32>
+struct ManyLds {
+    using T = typename std::conditional<OUT_F32, float, double>::type;
+    static constexpr int kStashBytes = 64 * P * (D + 1) * 12;   // (mu double, vertex int) per point and vertex
+    static constexpr int kSlotBytes = kWaveSlots<D> * 8;
+    static constexpr int kRegionA = kStashBytes > kSlotBytes ? kStashBytes : kSlotBytes;
+    static constexpr int kTileBytes = kManyFB * 65 * int(sizeof(T));
+    static constexpr int kBytes = kRegionA + kTileBytes;
+};
+
+template <int D, int P, bool IN_F32, bool OUT_F32>
+__global__ __launch_bounds__(64) void k_src_eval_many(SrcView S, int64_t head, int64_t npts,
+                                                      const void* __restrict__ pts_, int64_t ld,
+                                                      void* __restrict__ out_, int64_t ld_out,
+                                                      int32_t* __restrict__ ids,
+                                                      unsigned long long* __restrict__ n_ood) {
+    using L = ManyLds<D, P, OUT_F32>;
+    using T = typename L::T;
+    __shared__ __align__(16) unsigned char lds[L::kBytes];
+    double* c_af = reinterpret_cast<double*>(lds);
+    double* st_mu = reinterpret_cast<double*>(lds);                                  // [64P][D+1]
+    int* st_v = reinterpret_cast<int*>(lds + 64 * P * (D + 1) * 8);                   // [64P][D+1]
+    T* tile = reinterpret_cast<T*>(lds + L::kRegionA);                                 // [16][65]
+    constexpr int64_t WP = 64 * P;
+    const int lane = int(threadIdx.x & 63);
+    const int64_t wave = int64_t(blockIdx.x);
+    const int64_t wh = (head + WP - 1) / WP;
+    const int64_t base = wave < wh ? wave * WP : head + (wave - wh) * WP;
+    const int64_t lim = wave < wh ? head : npts;
+    if (base >= lim) return;   // wave-uniform
+    double p[P][D];
+    bool active[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t i = base + q * 64 + lane;
+        active[q] = i < lim;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            if (IN_F32)
+                p[q][c] = active[q] ? double(static_cast<const float*>(pts_)[c * ld + i]) : 0.0;
+            else
+                p[q][c] = active[q] ? static_cast<const double*>(pts_)[c * ld + i] : 0.0;
+        }
+    }
+    double best[P];
+    int bid[P];
+    locate_wave<D, P>(S, p, active, best, bid, c_af);
+    unsigned nood = 0;
+    __builtin_amdgcn_wave_barrier();   // the candidate slots become the stash
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t i = base + q * 64 + lane;
+        const bool found = active[q] && bid[q] != INT_MAX;
+        if (active[q]) {
+            nood += !found || best[q] < kOutTol;
+            if (ids) ids[i] = found ? bid[q] : -1;
+        }
+        double mu[D + 1];
+        winner_mu<D>(S, found ? bid[q] : INT_MAX, p[q], mu);
+        const int slot = q * 64 + lane;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) {
+            st_mu[slot * (D + 1) + k] = mu[k];   // zero weights for missing / inactive points
+            st_v[slot * (D + 1) + k] = found ? S.conn[int64_t(bid[q]) * (D + 1) + k] : 0;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int fl = lane & (kManyFB - 1);   // field within the block
+    const int pg = lane >> 4;              // point within a group of four
+    for (int q = 0; q < P; ++q) {
+        const int64_t i0 = base + q * 64;
+        for (int f0 = 0; f0 < S.F; f0 += kManyFB) {
+            const int f = f0 + fl;
+            for (int it = 0; it < 16; ++it) {
+                const int j = it * 4 + pg;   // point of this slot
+                const int slot = q * 64 + j;
+                double y = 0.0;
+                if (f < S.F) {
+#pragma unroll
+                    for (int k = 0; k <= D; ++k)
+                        y = fma(st_mu[slot * (D + 1) + k], S.values_nm[int64_t(st_v[slot * (D + 1) + k]) * S.F + f], y);
+                }
+                tile[fl * 65 + j] = T(y);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int64_t i = i0 + lane;
+            if (i < lim) {
+                for (int r = 0; r < kManyFB && f0 + r < S.F; ++r)
+                    static_cast<T*>(out_)[int64_t(f0 + r) * ld_out + i] = tile[r * 65 + lane];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (nood) atomicAdd(n_ood, (unsigned long long)nood);
+}
+
 // ---------------------------------------------------------------- host side
 // (Re)build the bin grid: nb[c] > 0 fixes the cells on axis c; otherwise the
 // longest axis gets `per_axis` cells and the others proportionally fewer.
@@ -330,6 +444,10 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
     FT_TRY_HIP(hipMemcpyAsync(S->conn, conn, sizeof(int32_t) * (D + 1) * E, hipMemcpyDeviceToDevice, s));
     FT_TRY_HIP(hipMemcpyAsync(S->values, values, sizeof(double) * S->F * n, hipMemcpyDeviceToDevice, s));
     FT_TRY_HIP(hipMemsetAsync(S->counters, 0, 4 * sizeof(unsigned long long), s));
+    if (S->F > 1) {
+        FT_TRY(dev_alloc_n(&S->values_nm, size_t(S->F) * n));
+        k_node_major<<<grid_for(n * S->F, B), B, 0, s>>>(S->values, n, S->F, S->values_nm);
+    }
 
     unsigned long long* flags = nullptr;
     double* mm = nullptr;
@@ -380,7 +498,7 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
 }
 
 SrcView source_view(const ft_source* S) {
-    SrcView v{S->rec, S->box, S->conn, S->values, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
+    SrcView v{S->rec, S->box, S->conn, S->values, S->values_nm, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
         v.g.hx[c] = S->hx[c];
@@ -403,12 +521,19 @@ static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const voi
     constexpr int WPB = kEvalWavesPerBlock;
     const int64_t waves = (head + WP - 1) / WP + (npts - head + WP - 1) / WP;
     const unsigned grid = unsigned((waves + WPB - 1) / WPB);
-    if (prec == FT_F64)
+    if (S->F > 1 && out) {   // many fields: the lanes interpolate over fields
+        const unsigned gw = unsigned(waves);
+        if (prec == FT_F64)
+            k_src_eval_many<D, P, false, false><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+        else
+            k_src_eval_many<D, P, true, true><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+    } else if (prec == FT_F64) {
         k_src_eval<D, P, false, false, WPB>
             <<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
-    else
+    } else {
         k_src_eval<D, P, true, true, WPB>
             <<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+    }
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
 }
@@ -475,6 +600,7 @@ ft_status source_release(ft_source* S) {
     dev_free(S->coords);
     dev_free(S->conn);
     dev_free(S->values);
+    dev_free(S->values_nm);
     dev_free(S->rec);
     dev_free(S->box);
     dev_free(S->bin_ptr);
