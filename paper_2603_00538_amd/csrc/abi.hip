@@ -38,7 +38,7 @@ const ft_sample_cfg* plan_cfg(const ft_plan* p);
 static void target_release(ft_target* T) {
     void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
                   T->beta, T->g, T->bres, T->r, T->z, T->p, T->q, T->y, T->b, T->scal, T->partials,
-                  T->counters, T->val32, T->diag32, T->w32, T->scal32};
+                  T->counters, T->val32, T->diag32, T->w32, T->scal32, T->mf_vec, T->mf_sc, T->mf_part};
     for (void* p : ps) dev_free(p);
     if (T->h_scal) (void)hipHostFree(T->h_scal);
 }
@@ -59,6 +59,7 @@ ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
 }
 
 ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream) {
+    T->fields_inner = false;   // routes that keep the fields inner set it again
     if (F <= T->F_cap) return FT_OK;
     // buffers may still be read by queued work of an earlier transfer
     FT_TRY_HIP(hipStreamSynchronize(stream));

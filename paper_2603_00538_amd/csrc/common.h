@@ -200,9 +200,10 @@ struct ft_target {
     int32_t* inc = nullptr;     // [E*(dim+1)]
     // per-transfer state
     int F_cap = 0;
-    double* beta = nullptr;     // [F][E][dim+1]
-    double* g = nullptr;        // [F][n]
-    double* bres = nullptr;     // [F][n]
+    double* beta = nullptr;     // [F][E][dim+1], or [E][dim+1][F] when fields_inner
+    double* g = nullptr;        // [F][n], or [n][F] when fields_inner
+    double* bres = nullptr;     // [F][n], or [n][F] when fields_inner
+    bool fields_inner = false;  // layout of the last transfer (many-field matrix-core route)
     // solver work vectors and reduction scratch
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *y = nullptr, *b = nullptr;
     double* scal = nullptr;               // device scalars
@@ -214,6 +215,11 @@ struct ft_target {
     float* diag32 = nullptr;              // [n]
     float* w32 = nullptr;                 // [6n] r, z, p (2n), q, d in binary32
     double* scal32 = nullptr;             // inner-solve scalars
+    // batched many-field solve, allocated on first use and grown with the field count
+    int mf_Fp = 0;                        // field capacity (a power of two) of mf_vec
+    double* mf_vec = nullptr;             // 8 vectors [n][mf_Fp]: G, B, Y, R, Z, Q, P (two)
+    double* mf_sc = nullptr;              // per-field CG scalars
+    double* mf_part = nullptr;            // per-field block partials
     int reduce_blocks = 0;
     // call-order state
     bool consumed = false;

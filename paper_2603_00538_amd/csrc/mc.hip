@@ -166,6 +166,34 @@ __global__ void k_assemble(const double* __restrict__ beta, int64_t E, const int
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
 
+// Fields-inner node assembly (many fields, F <= 64): one wavefront per node,
+// lane = field; each incidence entry adds one contiguous row beta[t][k][0..F)
+// in ascending (element, vertex) order; bres[v][f] and g[v][f] come out as
+// coalesced rows.
+template <bool F32>
+__global__ __launch_bounds__(256) void k_assemble_fi(const double* __restrict__ beta, const int64_t* __restrict__ inc_ptr,
+                                                     const int32_t* __restrict__ inc, int64_t n, int F,
+                                                     const void* __restrict__ values_, int64_t ld,
+                                                     double* __restrict__ bres, double* __restrict__ g,
+                                                     unsigned long long* __restrict__ nonfinite) {
+    const int64_t v = __builtin_amdgcn_readfirstlane(int(blockIdx.x * 4u + (threadIdx.x >> 6)));
+    const int f = int(threadIdx.x & 63);
+    if (v >= n) return;   // wave-uniform
+    const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
+    double s = 0.0;
+    if (f < F)
+        for (int64_t i = b; i < e; ++i) s += beta[int64_t(inc[i]) * F + f];
+    unsigned nf = 0;
+    if (f < F) {
+        bres[v * F + f] = s;
+        const int64_t off = int64_t(f) * ld + v;
+        const double gv = F32 ? double(static_cast<const float*>(values_)[off]) : static_cast<const double*>(values_)[off];
+        nf = !isfinite(gv);
+        g[v * F + f] = gv;
+    }
+    if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
+}
+
 __global__ void k_zero_u64(unsigned long long* __restrict__ p, int n) {
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
@@ -252,6 +280,18 @@ ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld,
     return FT_OK;
 }
 
+static ft_status assemble_fields_inner(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s) {
+    const unsigned grid = grid_for(T->n, 4);
+    if (f32)
+        k_assemble_fi<true><<<grid, 256, 0, s>>>(T->beta, T->inc_ptr, T->inc, T->n, F, values, ld, T->bres, T->g,
+                                                 T->counters);
+    else
+        k_assemble_fi<false><<<grid, 256, 0, s>>>(T->beta, T->inc_ptr, T->inc, T->n, F, values, ld, T->bres, T->g,
+                                                  T->counters);
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
 ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s);
 constexpr int kMfmaMaxSamples = 256;   // the matrix-core form stages <= 256 samples
 constexpr int kMfmaMaxFields = 64;     // and <= 64 control values per vertex in LDS
@@ -262,9 +302,12 @@ static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void
     const bool f32 = cfg->precision != FT_F64;
     const bool split = cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16;
     zero_counter(T->counters, s);
-    if (split && cfg->samples_per_elem <= kMfmaMaxSamples && cfg->n_fields <= kMfmaMaxFields)
-        FT_TRY(consume_mfma(T, cfg, values, s));
-    else if (f32) consume_g<D, true>(T, cfg, values, ld, s);
+    if (split && cfg->samples_per_elem <= kMfmaMaxSamples && cfg->n_fields <= kMfmaMaxFields) {
+        FT_TRY(consume_mfma(T, cfg, values, s));   // element loads fields-inner
+        T->fields_inner = cfg->n_fields > 1;
+        return assemble_fields_inner(T, cfg->n_fields, values, ld, f32, s);
+    }
+    if (f32) consume_g<D, true>(T, cfg, values, ld, s);
     else consume_g<D, false>(T, cfg, values, ld, s);
     FT_TRY_HIP(hipGetLastError());
     return assemble_residual(T, cfg->n_fields, values, ld, f32, s);

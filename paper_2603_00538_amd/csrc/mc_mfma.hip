@@ -17,7 +17,8 @@
 //
 // One wavefront per element stages its lambda (recomputed from the same
 // Philox counters as the emission, binary32 form), the control values and a
-// chunk of query values in LDS.  Every element sum
+// chunk of query values in LDS.  The element loads are written fields-inner,
+// beta[t][k][f], for the node assembly that follows.  Every element sum
 // is a fixed sequence of MFMAs and binary64 adds, so results are reproducible
 // run to run.
 #include "sampling.h"
@@ -176,11 +177,12 @@ __global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ v
         }
         __builtin_amdgcn_wave_barrier();
         if (s_ % nchunk == nchunk - 1) {
-            // C[row][col]: row = 4*sg + i (field f0 + row), col = barycentric index
+            // C[row][col]: row = 4*sg + i (field f0 + row), col = barycentric index;
+            // beta[t][col][f], the fields of one (element, vertex) contiguous
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int fo = f0 + 4 * sg + i;
-                if (col <= D && fo < F) beta[(int64_t(fo) * E + t) * (D + 1) + col] = run[i] * scale_out;
+                if (col <= D && fo < F) beta[(int64_t(t) * (D + 1) + col) * F + fo] = run[i] * scale_out;
                 run[i] = 0.0;
             }
         }

@@ -12,9 +12,10 @@
 // Reductions without atomics: each block writes one partial per field (its
 // lanes of that field, in a fixed order); a kernel with one block per field
 // adds that field's partials in block order and updates its CG scalars.  One
-// iteration is four launches: (direction p = z + beta p_old formed on the fly,
-// q = M p, partial p.q), (alpha), (update y, r, z, partial r.z, r.r),
-// (stopping test, beta for the next direction).
+// iteration is five launches: (direction p = z + beta p_old), (q = M p,
+// partial p.q), (alpha), (update y, r, z, partial r.z, r.r), (stopping test,
+// beta for the next direction).  Forming p in its own pass halves the rows
+// the product gathers (one vector instead of two).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -77,6 +78,16 @@ __global__ __launch_bounds__(MB) void k_m_transpose_in(const double* __restrict_
     const int64_t i = idx / Fp;
     const int f = int(idx - i * Fp);
     dst[idx] = f < F ? src[int64_t(f) * n + i] : 0.0;
+}
+
+// dst[i*Fp + f] = src[i*F + f] (fields-inner source), zero padding
+__global__ __launch_bounds__(MB) void k_m_pad_in(const double* __restrict__ src, int64_t n, int F, int Fp,
+                                                 double* __restrict__ dst) {
+    const int64_t idx = int64_t(blockIdx.x) * MB + threadIdx.x;
+    if (idx >= n * Fp) return;
+    const int64_t i = idx / Fp;
+    const int f = int(idx - i * Fp);
+    dst[idx] = f < F ? src[i * F + f] : 0.0;
 }
 
 __global__ __launch_bounds__(MB) void k_m_transpose_out(const double* __restrict__ src, int64_t n, int F, int Fp,
@@ -193,36 +204,42 @@ __device__ __forceinline__ bool all_done(const MView& A, const double* __restric
     return true;
 }
 
-// direction and product over this thread's rows: P_new = Z + beta P_old (own
-// rows), Q = M P; returns the partial of p.q.  WAVE_ROW (64 fields): a
-// wavefront owns one row, so the row index and its matrix entries are
-// wave-uniform and load through the scalar cache.
+// New direction P_new = Z + beta P_old (elementwise; a converged field keeps
+// beta = 0, its lanes' values are not used again).
+__global__ __launch_bounds__(MB) void k_m_dir(MView A, const double* __restrict__ Z, const double* __restrict__ Pold,
+                                              double* __restrict__ Pnew, const double* __restrict__ sc) {
+    if (all_done(A, sc)) return;
+    FOR_ROWS(A, i, f) {
+        const bool live = f < A.F && sc[SC_DONE * A.Fp + f] == 0.0;
+        const double bt = live ? sc[SC_BETA * A.Fp + f] : 0.0;
+        const int64_t o = i * A.Fp + f;
+        Pnew[o] = fma(bt, Pold[o], Z[o]);
+    }
+}
+
+// Q = M P over this thread's rows; returns the partial of p.q.  WAVE_ROW (64
+// fields): a wavefront owns one row, so the row index and its matrix entries
+// are wave-uniform and load through the scalar cache, and each product reads
+// one 512-byte row of P per matrix entry.
 template <bool WAVE_ROW>
 __device__ __forceinline__ double spmv_rows(const MView& A, const int64_t* __restrict__ rowptr,
                                             const int32_t* __restrict__ colidx, const double* __restrict__ val,
-                                            const double* __restrict__ Z, const double* __restrict__ Pold,
-                                            double* __restrict__ Pnew, double* __restrict__ Qv,
+                                            const double* __restrict__ P, double* __restrict__ Qv,
                                             const double* __restrict__ sc) {
     const int f = int(threadIdx.x) & (A.Fp - 1);
     int64_t row0 = (int64_t(blockIdx.x) * MB + threadIdx.x) >> A.shift;
     if (WAVE_ROW) row0 = uniform_int(int(row0));
     const int64_t rstride = (int64_t(gridDim.x) * MB) >> A.shift;
     const bool live = f < A.F && sc[SC_DONE * A.Fp + f] == 0.0;
-    const double bt = live ? sc[SC_BETA * A.Fp + f] : 0.0;
     double pq = 0.0;
     for (int64_t i = row0; i < A.n; i += rstride) {
         double qi = 0.0;
         const int64_t k0 = rowptr[i], k1 = rowptr[i + 1];
 #pragma unroll 4
-        for (int64_t kk = k0; kk < k1; ++kk) {
-            const int64_t o = int64_t(colidx[kk]) * A.Fp + f;
-            qi = fma(val[kk], fma(bt, Pold[o], Z[o]), qi);
-        }
+        for (int64_t kk = k0; kk < k1; ++kk) qi = fma(val[kk], P[int64_t(colidx[kk]) * A.Fp + f], qi);
         const int64_t o = i * A.Fp + f;
-        const double pi = fma(bt, Pold[o], Z[o]);
-        Pnew[o] = pi;
         Qv[o] = qi;
-        if (live) pq = fma(pi, qi, pq);
+        if (live) pq = fma(P[o], qi, pq);
     }
     return pq;
 }
@@ -231,13 +248,12 @@ __device__ __forceinline__ double spmv_rows(const MView& A, const int64_t* __res
 // of them may use the scalar cache)
 __global__ __launch_bounds__(MB) void k_m_spmv(MView A, const int64_t* __restrict__ rowptr,
                                                const int32_t* __restrict__ colidx, const double* __restrict__ val,
-                                               const double* __restrict__ Z, const double* __restrict__ Pold,
-                                               double* __restrict__ Pnew, double* __restrict__ Qv,
+                                               const double* __restrict__ P, double* __restrict__ Qv,
                                                const double* __restrict__ sc, double* __restrict__ part) {
     if (all_done(A, sc)) return;
     double v[1];
-    v[0] = A.Fp == 64 ? spmv_rows<true>(A, rowptr, colidx, val, Z, Pold, Pnew, Qv, sc)
-                      : spmv_rows<false>(A, rowptr, colidx, val, Z, Pold, Pnew, Qv, sc);
+    v[0] = A.Fp == 64 ? spmv_rows<true>(A, rowptr, colidx, val, P, Qv, sc)
+                      : spmv_rows<false>(A, rowptr, colidx, val, P, Qv, sc);
     const int slot[1] = {PM_PQ};
     field_partials<1>(A, v, slot, part);
 }
@@ -302,27 +318,41 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
     const int nb = int(std::max<int64_t>(1, std::min<int64_t>(MAX_MBLOCKS, (n * Fp + MB - 1) / MB)));
     MView A{T->rowptr, T->col, T->val, T->diag, T->lumped, n, F, Fp, shift};
 
-    // work arrays (freed on return; the solve is synchronous)
-    double *G = nullptr, *B = nullptr, *Y = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Qv = nullptr;
-    double *sc = nullptr, *part = nullptr;
-    ScratchGuard guard;
-    for (double** p : {&G, &B, &Y, &R, &Z, &Qv}) {
-        guard.add((void**)p);
-        FT_TRY(dev_alloc_n(p, size_t(n) * Fp));
+    // work arrays: kept by the target and reused by later solves (grown when
+    // a solve needs more fields)
+    if (T->mf_Fp < Fp) {
+        dev_free(T->mf_vec);
+        dev_free(T->mf_sc);
+        dev_free(T->mf_part);
+        T->mf_vec = T->mf_sc = T->mf_part = nullptr;
+        T->mf_Fp = 0;
+        FT_TRY(dev_alloc_n(&T->mf_vec, size_t(8) * n * Fp));
+        FT_TRY(dev_alloc_n(&T->mf_sc, size_t(SC_COUNT) * 64));
+        FT_TRY(dev_alloc_n(&T->mf_part, size_t(PM_COUNT) * 64 * MAX_MBLOCKS));
+        T->mf_Fp = Fp;
     }
-    guard.add((void**)&P);
-    FT_TRY(dev_alloc_n(&P, size_t(2) * n * Fp));   // two direction buffers, alternating
-    guard.add((void**)&sc);
-    guard.add((void**)&part);
-    FT_TRY(dev_alloc_n(&sc, size_t(SC_COUNT) * Fp));
-    FT_TRY(dev_alloc_n(&part, size_t(PM_COUNT) * Fp * nb));
+    const size_t vn = size_t(n) * Fp;
+    double* G = T->mf_vec;
+    double* B = G + vn;
+    double* Y = B + vn;
+    double* R = Y + vn;
+    double* Z = R + vn;
+    double* Qv = Z + vn;
+    double* P = Qv + vn;   // two direction buffers, alternating
+    double* sc = T->mf_sc;
+    double* part = T->mf_part;
     std::vector<double> h(size_t(SC_COUNT) * Fp);
 
     unsigned long long nonfinite = 0;
     FT_TRY_HIP(hipMemcpyAsync(&nonfinite, T->counters, sizeof(nonfinite), hipMemcpyDeviceToHost, s));
     const unsigned gt = grid_for(n * Fp, MB);
-    k_m_transpose_in<<<gt, MB, 0, s>>>(T->g, n, F, Fp, G);
-    k_m_transpose_in<<<gt, MB, 0, s>>>(T->bres, n, F, Fp, R);
+    if (T->fields_inner) {   // the control and residual loads are already node-major
+        k_m_pad_in<<<gt, MB, 0, s>>>(T->g, n, F, Fp, G);
+        k_m_pad_in<<<gt, MB, 0, s>>>(T->bres, n, F, Fp, R);
+    } else {
+        k_m_transpose_in<<<gt, MB, 0, s>>>(T->g, n, F, Fp, G);
+        k_m_transpose_in<<<gt, MB, 0, s>>>(T->bres, n, F, Fp, R);
+    }
     k_m_rhs<<<nb, MB, 0, s>>>(A, G, alpha, R, B, part);
     k_m_scalars<<<F, MB, 0, s>>>(A, 0, 0, nb, cfg->rtol * cfg->rtol, part, sc);
     k_m_init<<<nb, MB, 0, s>>>(A, Y, R, Z, P, part);
@@ -335,7 +365,8 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
             const int kk = launched + it;
             double* Pold = P + ((kk & 1) ? n * Fp : 0);
             double* Pnew = P + ((kk & 1) ? 0 : n * Fp);
-            k_m_spmv<<<nb, MB, 0, s>>>(A, A.rowptr, A.col, A.val, Z, Pold, Pnew, Qv, sc, part);
+            k_m_dir<<<nb, MB, 0, s>>>(A, Z, Pold, Pnew, sc);
+            k_m_spmv<<<nb, MB, 0, s>>>(A, A.rowptr, A.col, A.val, Pnew, Qv, sc, part);
             k_m_scalars<<<F, MB, 0, s>>>(A, 2, kk, nb, 0.0, part, sc);
             k_m_update<<<nb, MB, 0, s>>>(A, Pnew, Qv, Y, R, Z, sc, part);
             k_m_scalars<<<F, MB, 0, s>>>(A, 1, kk + 1, nb, 0.0, part, sc);
