@@ -10,10 +10,12 @@
 // Layout: every source element e has a record rec[e*RS ...] holding its
 // origin, its barycentric map (absolute affine form, whose gradients g_1..g_D
 // are the rows of the inverse of J = [x1-x0 | ... | xd-x0]) and, for one
-// field, its vertex values (see locate.h); plus an outward-rounded binary32
-// bounding box.  Each element is registered once, in the bin holding the
-// centre of its box (CSR, ascending ids per bin); the largest half-extent of a
-// box tells a search how far around a region to look.
+// field, its vertex values (see locate.h); plus outward-rounded binary32
+// ranges along the axes and a few extra directions (its box).  Each element
+// is registered once, in the bin holding the centre of its box (CSR, ascending
+// ids per bin); the largest half-extent of a box tells a search how far
+// around a region to look.  A source of several fields also keeps a
+// node-major copy of its nodal values for the many-field evaluation.
 
 #include <algorithm>
 #include <cfloat>
