@@ -265,7 +265,12 @@ __global__ __launch_bounds__(BT) void k_batch_cg_init(const BatchXfer* __restric
     tile_partial(part, BP_RR, rr);
 }
 
-// p_new = z + beta p_old (own rows), q = M p; partial p.q
+// p_new = z + beta p_old (own rows), q = M p; partial p.q.  Eight lanes per
+// row walk its entries together (consecutive entries, so each load of the
+// matrix is a contiguous run per row) and add their parts with a butterfly;
+// the tile's 256 rows take eight passes of 32 rows.
+constexpr int kRowLanes = 8;
+
 __global__ __launch_bounds__(BT) void k_batch_cg_spmv(const BatchXfer* __restrict__ X, const Tile* __restrict__ rt,
                                                       const double* __restrict__ Z, const double* __restrict__ Pold,
                                                       double* __restrict__ Pnew, double* __restrict__ Qv,
@@ -274,20 +279,29 @@ __global__ __launch_bounds__(BT) void k_batch_cg_spmv(const BatchXfer* __restric
     if (sc[int64_t(tl.k) * BS_COUNT + BS_DONE] != 0.0) return;   // block-uniform
     const BatchXfer& x = X[tl.k];
     const double bt = sc[int64_t(tl.k) * BS_COUNT + BS_BETA];
-    const int64_t i = tl.start + threadIdx.x;
     const double* z = Z + x.row0;
     const double* po = Pold + x.row0;
+    const int sub = int(threadIdx.x) & (kRowLanes - 1);
     double pq = 0.0;
-    if (i < x.n) {
+    for (int r0 = 0; r0 < BT; r0 += BT / kRowLanes) {
+        const int64_t i = tl.start + r0 + int(threadIdx.x) / kRowLanes;
         double qi = 0.0;
-        for (int64_t k = x.rowptr[i]; k < x.rowptr[i + 1]; ++k) {
-            const int32_t j = x.col[k];
-            qi = fma(x.val[k], fma(bt, po[j], z[j]), qi);
+        if (i < x.n) {
+            const int64_t k1 = x.rowptr[i + 1];
+            for (int64_t k = x.rowptr[i] + sub; k < k1; k += kRowLanes) {
+                const int32_t j = x.col[k];
+                qi = fma(x.val[k], fma(bt, po[j], z[j]), qi);
+            }
         }
-        const double pi = fma(bt, po[i], z[i]);
-        Pnew[x.row0 + i] = pi;
-        Qv[x.row0 + i] = qi;
-        pq = pi * qi;
+        qi += __shfl_xor(qi, 1, kRowLanes);
+        qi += __shfl_xor(qi, 2, kRowLanes);
+        qi += __shfl_xor(qi, 4, kRowLanes);
+        if (i < x.n && sub == 0) {
+            const double pi = fma(bt, po[i], z[i]);
+            Pnew[x.row0 + i] = pi;
+            Qv[x.row0 + i] = qi;
+            pq = fma(pi, qi, pq);
+        }
     }
     tile_partial(part, BP_PQ, pq);
 }
