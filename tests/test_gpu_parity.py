@@ -98,6 +98,40 @@ def test_source_out_of_domain_counted():
     S.close()
 
 
+@pytest.mark.parametrize("dim,F,dtype", [(2, 5, "f64"), (3, 64, "f32"), (3, 17, "f64"), (2, 40, "f32")])
+def test_many_field_eval_matches_oracle(dim, F, dtype):
+    """Several fields per source (the lanes-over-fields evaluation): element ids,
+    values and the out-of-domain count against the oracle, with a ragged last
+    wave and points outside the domain."""
+    tm, sm = _small_2d() if dim == 2 else _small_3d()
+    rng = np.random.default_rng(40 + F)
+    sv = rng.standard_normal((F, sm[0].shape[0]))
+    inside = np.concatenate([oracle_query_points(tm, 7, 21, 0).T, rng.uniform(0, 1, (777, dim)), sm[0][:50]])
+    outside = np.concatenate([rng.uniform(1.2, 1.5, (5, dim)), -rng.uniform(0.2, 0.4, (4, dim))])
+    pts = np.concatenate([inside, outside]).T.copy()
+    log(f"many-field eval dim={dim} F={F} {dtype}: {pts.shape[1]} points")
+    S = ft.Source(*sm, sv)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    dp = torch.as_tensor(pts, device="cuda").to(tdt)
+    ids = torch.empty(pts.shape[1], dtype=torch.int32, device="cuda")
+    vals = S.eval(dp, ids=ids).double().cpu().numpy()
+    ids = ids.cpu().numpy()
+    assert vals.shape == (F, pts.shape[1])
+    assert S.take_out_of_domain() == outside.shape[0]
+    o = P1Source(*sm, sv)
+    qp = dp.double().cpu().numpy().T   # the points the kernel saw (binary32 rounded for f32)
+    oid, omu, ood = o.locate(qp)
+    n_in = inside.shape[0]
+    away = o.face_distance(oid[:n_in], omu[:n_in]) > 1e-12
+    assert away.sum() > 0.9 * n_in
+    assert np.array_equal(ids[:n_in][away], oid[:n_in][away])
+    ovals = o.evaluate_at(oid[:n_in], omu[:n_in])
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    scale = np.abs(ovals).max()
+    assert np.abs(vals[:, :n_in] - ovals).max() <= tol * scale
+    S.close()
+
+
 @pytest.mark.parametrize("bins", [None, (7, 5), (64, 64)])
 def test_source_bins_do_not_change_results(bins):
     tm, sm = _small_2d()
