@@ -256,18 +256,17 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         b1[c] = uniform_int(bin_of(whi[c] + S.g.hx[c], c, S.g));
         span *= b1[c] - b0[c] + 1;
     }
-    // fm[q]: the lanes whose point q is accepted (wave-uniform masks; inactive
-    // points count as accepted, so the wave's exit test needs no activity mask)
-    uint64_t fm[P];
-    const uint64_t wave_mask = __ballot(1);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         best[q] = -DBL_MAX;
         bid[q] = INT_MAX;
-        fm[q] = __ballot(!active[q]);
     }
 
     if (span <= MAX_SPAN) {
+        // during the fast search bid[q] != INT_MAX marks an accepted point; inactive
+        // points start marked (-1), so the wave's exit test needs no activity mask
+#pragma unroll
+        for (int q = 0; q < P; ++q) bid[q] = active[q] ? INT_MAX : -1;
         constexpr int ND = Dirs<D>::n;
         float fdlo[ND], fdhi[ND];   // wave ranges along the extra directions
 #pragma unroll
@@ -339,15 +338,14 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 mask &= mask - 1;
                 const int e1 = read_lane(cid, l1);
                 const double* a1 = &c_af[l1 * AL];
-                uint64_t all = wave_mask;
+                uint64_t pending = 0;   // lanes with a point not yet accepted
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const bool in = inside_lds<D>(a1, p[q]);
                     bid[q] = in ? e1 : bid[q];
-                    fm[q] |= __builtin_amdgcn_ballot_w64(in);
-                    all &= fm[q];
+                    pending |= __builtin_amdgcn_ballot_w64(bid[q] == INT_MAX);
                 }
-                if (all == wave_mask) {
+                if (pending == 0) {
                     finished = true;
                     break;
                 }
@@ -359,8 +357,8 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         // their elements
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            if (!active[q]) continue;
-            if ((fm[q] >> lane) & 1) best[q] = 1.0;
+            if (!active[q]) bid[q] = INT_MAX;
+            else if (bid[q] != INT_MAX) best[q] = 1.0;
             else locate_point<D>(S, p[q], best[q], bid[q]);
         }
     } else {
