@@ -440,7 +440,8 @@ __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, in
                 static_cast<double*>(out_)[i] = y;
             continue;
         }
-        // many fields: the element's vertices once, then one gather per vertex and field
+        // several fields (the evaluation kernel hands these to its lanes-over-fields
+        // variant): the element's vertices once, then one gather per vertex and field
         int vk[D + 1];
 #pragma unroll
         for (int k = 0; k <= D; ++k) vk[k] = found ? S.conn[int64_t(bid[q]) * (D + 1) + k] : 0;
