@@ -58,7 +58,8 @@ def source_mesh_bytes(dim, F, src):
 
 
 def algorithmic_bytes(phase, dim, E, n, N, F, p, src=None):
-    """Compulsory HBM bytes of one launch of a phase (measurement)."""
+    """Compulsory HBM bytes of one launch of a phase: what it must read and write
+    at least once (points, values, mesh data), not what its caches refetch."""
     Q = n + E * N
     if phase == "emit":
         # write d coordinates per query; read connectivity and vertex coordinates per element
