@@ -304,9 +304,9 @@ ft_status ft_plan_destroy(ft_plan* p);
  * Batches: many independent transfers from built-in P1 sources (one field
  * each, FT_F64), of mixed dimension, size and samples per element, run as
  * one sequence of launches.  Target elements of all transfers are the work
- * units of one persistent kernel (sec. 4.1: the element sums of step 5 are
- * independent), the node sums and the mass solves of all transfers share
- * their launches.  Each transfer gives exactly the samples and element sums
+ * units of persistent kernels, one launch per element-kernel variant (sec.
+ * 4.1: the element sums of step 5 are independent); the node sums and the
+ * mass solves of all transfers share their launches.  Each transfer gives exactly the samples and element sums
  * of ft_transfer_p1 on the same target, source and cfg (samples_per_elem > 8),
  * and a solution of the same M x = b to the same tolerance.
  */
@@ -322,8 +322,9 @@ enum { FT_BATCH_GRAPH = 1 };   /* capture a run as a HIP graph; later runs repla
  *   cfgs               host [count]: per-transfer sample configuration
  *                      (n_fields 1 = the source's field count, FT_F64)
  *   flags              0 or FT_BATCH_GRAPH
- * Builds the work lists (node, element and row tiles, elements ordered by
- * decreasing cost) and the batch's solver vectors on the device.
+ * Builds the work lists (node, element and row tiles; element tiles grouped
+ * by variant, the dearest variants first) and the batch's solver vectors on
+ * the device.
  * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Synchronizes `stream`.
  */
 ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* const* sources,
