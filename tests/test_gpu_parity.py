@@ -314,6 +314,44 @@ def test_call_order_and_status_errors():
     S.close()
 
 
+@pytest.mark.parametrize("dim,N", [(2, 5), (3, 3), (2, 300)])
+def test_single_element_target(dim, N):
+    """The smallest target (one element: grids of one block, one reduction
+    block, a partial wave) through the black-box and the fused routes."""
+    if dim == 2:
+        tm = (np.array([[0.1, 0.1], [0.9, 0.2], [0.3, 0.8]]), np.array([[0, 1, 2]], dtype=np.int32))
+        sm = _small_2d()[1]
+        sv = fields.evaluate("front_2d", np, sm[0])
+    else:
+        tm = (np.array([[0.1, 0.1, 0.1], [0.9, 0.2, 0.1], [0.2, 0.8, 0.2], [0.2, 0.3, 0.9]]),
+              np.array([[0, 1, 2, 3]], dtype=np.int32))
+        sm = _small_3d()[1]
+        sv = fields.evaluate("gaussian_bumps_3d", np, sm[0])
+    g = gpu_transfer(tm, sm, sv, N, 1.0, 77, 0)
+    o = oracle_transfer(tm, sm, sv, N, 1.0, 77, 0)
+    assert g["status"] == ft.FT_OK
+    assert rel_l2(g["b"], o["b"]) < 1e-12 and rel_l2(g["x"], o["x"]) < 1e-12
+    T, S = ft.Target(*tm), ft.Source(*sm, sv)
+    T.transfer_from(S, ft.SampleCfg(N, 1, 1.0, 77, 0, ft.FT_F64))
+    r = T.project(1)
+    assert rel_l2(r.x.cpu().numpy(), o["x"]) < 1e-12
+    T.close()
+    S.close()
+
+
+def test_empty_point_ranges():
+    """Evaluating no points is a no-op that leaves the output untouched."""
+    tm, sm = _small_2d()
+    S = ft.Source(*sm, fields.evaluate("smooth_2d", np, sm[0]))
+    pts = torch.zeros((2, 10), dtype=torch.float64, device="cuda")
+    out = torch.full((1, 10), 7.0, dtype=torch.float64, device="cuda")
+    S.eval(pts, out=out, start=3, count=0)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    assert S.take_out_of_domain() == 0
+    S.close()
+
+
 def test_degenerate_and_out_of_range_meshes_rejected():
     tc = np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0], [0.0, 1.0]])
     with pytest.raises(ft.FtError) as e:
