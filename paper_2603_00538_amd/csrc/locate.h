@@ -42,21 +42,23 @@ constexpr double kFastTau = 1e-9;      // accepted by the fast selection test (a
 constexpr double kOutTol = -1e-10;
 
 // Record of element e, rec[e*RS ...] (doubles; 128 B in 2D, 256 B in 3D):
-//   [0, D)                    origin x0 (vertex 0)
-//   [AF, AF + D + 1)          constants c_k of mu_k(x) = c_k + g_k . x, AF = D
-//   [AF + D + 1, VAL)         gradients g_k (D each), k = 0..D; g_1..g_D are the
-//                             rows of the inverse of J = [x1-x0 | ... | xd-x0]
+//   [0, D)                    constants c_k of mu_k(x) = c_k + g_k . x, k = 1..D
+//   [D, D + D*D)              gradients g_k (D each), k = 1..D: the rows of the
+//                             inverse of J = [x1-x0 | ... | xd-x0]
+//   [X0, X0 + D)              origin x0 (vertex 0), X0 = D + D*D
 //   [VAL, VAL + D + 1)        vertex values of a one-field source (else zero)
-// The absolute affine form selects the element (the cull parks c_1..c_D and
-// g_1..g_D; mu_0 follows as 1 minus the others); the origin form
-// mu_{k+1} = g_{k+1} . (x - x0) gives the barycentrics used to interpolate,
-// and for one field the vertex values sit in the same record.
+// The first D(D+1) doubles, the absolute affine form of mu_1..mu_D, are what
+// the cull parks in LDS (one aligned contiguous block; mu_0 = 1 - the others);
+// the origin form mu_{k+1} = g_{k+1} . (x - x0) gives the barycentrics used to
+// interpolate, and for one field the vertex values sit in the same record.
 template <int D>
 struct RecSize { static constexpr int value = D == 2 ? 16 : 32; };
 template <int D>
-struct RecAffine { static constexpr int value = D; };
+struct RecForm { static constexpr int value = D * (D + 1); };   // parked doubles
 template <int D>
-struct RecValues { static constexpr int value = D + (D + 1) * (D + 1); };
+struct RecX0 { static constexpr int value = D + D * D; };
+template <int D>
+struct RecValues { static constexpr int value = D + D * D + D; };
 static_assert(RecValues<2>::value + 3 <= RecSize<2>::value, "2D record overflow");
 static_assert(RecValues<3>::value + 4 <= RecSize<3>::value, "3D record overflow");
 
@@ -123,14 +125,14 @@ __device__ __forceinline__ double barycentric(const double* __restrict__ r, cons
                                               double (&mu)[D + 1]) {
     double d[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) d[c] = p[c] - r[c];
+    for (int c = 0; c < D; ++c) d[c] = p[c] - r[RecX0<D>::value + c];
     mu[0] = 1.0;
     double mn = INFINITY;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         double s = 0.0;
 #pragma unroll
-        for (int c = 0; c < D; ++c) s = fma(r[RecAffine<D>::value + D + 1 + (k + 1) * D + c], d[c], s);
+        for (int c = 0; c < D; ++c) s = fma(r[D + k * D + c], d[c], s);
         mu[k + 1] = s;
         mu[0] -= s;
         mn = fmin(mn, s);
@@ -196,10 +198,11 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
 }
 
 // LDS slots for the candidates' parked forms: 64 per wave, D(D+1) doubles
-// each.  Every kernel that localizes declares its block's slots (waves per
-// block x kWaveSlots<D> doubles) and hands each wave its own part.
+// each, then 64 ints of slot marks (see locate_wave).  Every kernel that
+// localizes declares its block's slots (waves per block x kWaveSlots<D>
+// doubles) and hands each wave its own part.
 template <int D>
-constexpr int kWaveSlots = 64 * D * (D + 1);
+constexpr int kWaveSlots = 64 * D * (D + 1) + 32;
 
 // Inclusive prefix sum over the 64 lanes of the wave: a scan inside each row
 // of 16 lanes on the DPP crossbar (shifts by 1, 2, 4, 8; lanes shifted in
@@ -208,6 +211,10 @@ template <int CTRL>
 __device__ __forceinline__ int dpp_shr_zero(int x) {
     return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, true);
 }
+
+// Inclusive prefix maximum over the 64 lanes of non-negative values (same
+// row-then-rows structure as the scan below).
+__device__ __forceinline__ int wave_prefix_max(int x);
 
 __device__ __forceinline__ int wave_scan_incl(int x) {
     const int lane = threadIdx.x & 63;
@@ -218,6 +225,20 @@ __device__ __forceinline__ int wave_scan_incl(int x) {
     const int r0 = __builtin_amdgcn_readlane(x, 15), r1 = __builtin_amdgcn_readlane(x, 31),
               r2 = __builtin_amdgcn_readlane(x, 47);
     return x + (lane >= 16 ? r0 : 0) + (lane >= 32 ? r1 : 0) + (lane >= 48 ? r2 : 0);
+}
+
+__device__ __forceinline__ int wave_prefix_max(int x) {
+    const int lane = threadIdx.x & 63;
+    x = max(x, dpp_shr_zero<0x111>(x));   // lanes shifted in from outside the row read zero
+    x = max(x, dpp_shr_zero<0x112>(x));
+    x = max(x, dpp_shr_zero<0x114>(x));
+    x = max(x, dpp_shr_zero<0x118>(x));
+    const int r0 = __builtin_amdgcn_readlane(x, 15), r1 = __builtin_amdgcn_readlane(x, 31),
+              r2 = __builtin_amdgcn_readlane(x, 47);
+    int c = lane >= 16 ? r0 : 0;
+    c = lane >= 32 ? max(c, r1) : c;
+    c = lane >= 48 ? max(c, r2) : c;
+    return max(x, c);
 }
 
 // Rule winner for each of this lane's P points (see the file comment).  Every
@@ -285,7 +306,7 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
         // Lane i < span describes bin i of the wave's bin box (x fastest): its
         // coordinates, first registration and count.  The candidate slots of all
         // these bins are then culled 64 at a time in one flat sequence.
-        constexpr int AL = D * (D + 1);   // parked form: constants of mu_1..mu_D, then D x D gradients
+        constexpr int AL = RecForm<D>::value;   // parked form: constants of mu_1..mu_D, then D x D gradients
         const int wx = b1[0] - b0[0] + 1, wy = b1[1] - b0[1] + 1;
         int64_t bstart = 0;
         int bcnt = 0;
@@ -296,23 +317,36 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             bcnt = int(S.bin_ptr[b + 1] - bstart);
         }
         const int incl = wave_scan_incl(bcnt);
+        const int excl = incl - bcnt;
         const int total = __builtin_amdgcn_readlane(incl, span - 1);
+        int* mark = reinterpret_cast<int*>(c_af + 64 * AL);   // 64 slot marks
         bool finished = false;
         for (int c0 = 0; c0 < total && !finished; c0 += 64) {
             const int sl = c0 + lane;
-            // bin of slot sl: the first lane whose inclusive count exceeds sl (binary search)
-            int i = 0, ihi = span - 1;
-#pragma unroll
-            for (int step = 0; step < 6; ++step) {
-                const int mid = (i + ihi) >> 1;
-                if (__shfl(incl, mid, 64) > sl) ihi = mid;
-                else i = mid + 1 <= ihi ? mid + 1 : ihi;
-            }
-            const int excl_i = __shfl(incl - bcnt, i, 64);
+            // bin of slot sl: every non-empty bin marks (lane + 1) the first slot
+            // of this chunk it fills, the bin running in from the previous chunk
+            // marks slot 0, and a prefix maximum carries the marks forward
+            mark[lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < span && bcnt > 0 && excl >= c0 && excl < c0 + 64) mark[excl - c0] = lane + 1;
+            const uint64_t run_in = __builtin_amdgcn_ballot_w64(lane < span && excl < c0 && incl > c0);
+            // lanes read marks other lanes wrote: the wavefront-scope fences keep the
+            // compiler from forwarding a lane's own store of 0 to its load
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int m = mark[lane];
+            if (lane == 0 && run_in) m = max(m, int(__ffsll((unsigned long long)run_in)));
+            m = wave_prefix_max(m);
+            const int i = m > 0 ? m - 1 : 0;
+            const int excl_i = __shfl(excl, i, 64);
+            const int cnt_i = __shfl(bcnt, i, 64);
             const int64_t st_i = __shfl((long long)bstart, i, 64);
             int cid = -1;
             bool ov = false;
-            if (sl < total) {
+            // (the slot lies in its bin's range by construction; the range test only
+            // guards the load)
+            if (sl < total && unsigned(sl - excl_i) < unsigned(cnt_i)) {
                 cid = S.bin_elems[st_i + (sl - excl_i)];
                 const float* bx_ = S.box + int64_t(cid) * BS;
                 ov = true;
@@ -325,11 +359,9 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             // form (mu_1..mu_D) and park it in their own LDS slot; they are then
             // read back in lane order
             if (ov) {
-                const double* r = S.rec + int64_t(cid) * RS + RecAffine<D>::value;
+                const double* r = S.rec + int64_t(cid) * RS;
 #pragma unroll
-                for (int k = 0; k < D; ++k) c_af[lane * AL + k] = r[1 + k];
-#pragma unroll
-                for (int m = 0; m < D * D; ++m) c_af[lane * AL + D + m] = r[2 * D + 1 + m];
+                for (int m = 0; m < AL; ++m) c_af[lane * AL + m] = r[m];
             }
             uint64_t mask = __ballot(ov);
             __builtin_amdgcn_wave_barrier();

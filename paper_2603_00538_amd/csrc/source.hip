@@ -8,8 +8,8 @@
 // Localization rule and search: see locate.h.
 //
 // Layout: every source element e has a record rec[e*RS ...] holding its
-// origin, its barycentric map (absolute affine form, whose gradients g_1..g_D
-// are the rows of the inverse of J = [x1-x0 | ... | xd-x0]) and, for one
+// barycentric map (absolute affine form of mu_1..mu_D, whose gradients are the
+// rows of the inverse of J = [x1-x0 | ... | xd-x0]), its origin and, for one
 // field, its vertex values (see locate.h); plus outward-rounded binary32
 // ranges along the axes and a few extra directions (its box).  Each element
 // is registered once, in the bin holding the centre of its box (CSR, ascending
@@ -95,23 +95,18 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
 #pragma unroll
     for (int i = 0; i < RS; ++i) r[i] = 0.0;
 #pragma unroll
-    for (int c = 0; c < D; ++c) r[c] = x[0][c];
-    // absolute affine form: g_{k+1} = A[k], c_{k+1} = -A[k] . x0; g_0 = -sum g, c_0 = 1 - sum c
-    constexpr int AF = RecAffine<D>::value;
-    double csum = 0.0;
+    for (int c = 0; c < D; ++c) r[RecX0<D>::value + c] = x[0][c];
+    // absolute affine form of mu_1..mu_D: g_{k+1} = A[k], c_{k+1} = -A[k] . x0
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         double ck = 0.0;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             ck = fma(-A[k][c], x[0][c], ck);
-            r[AF + D + 1 + (k + 1) * D + c] = A[k][c];
-            r[AF + D + 1 + c] -= A[k][c];
+            r[D + k * D + c] = A[k][c];
         }
-        r[AF + k + 1] = ck;
-        csum += ck;
+        r[k] = ck;
     }
-    r[AF] = 1.0 - csum;
     if (F == 1)
 #pragma unroll
         for (int k = 0; k <= D; ++k) r[RecValues<D>::value + k] = values[v[k]];
