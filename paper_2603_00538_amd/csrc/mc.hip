@@ -21,13 +21,15 @@
 
 namespace ft {
 
-template <int D, bool F32>
+// WU: N is a multiple of 64, so the 64 samples of a wave belong to one element
+// and its connectivity and vertex coordinates are scalar loads.
+template <int D, bool F32, bool WU>
 __global__ __launch_bounds__(256) void k_emit(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
                                               uint32_t total, uint32_t N, FastDiv divN, SampleKey key,
                                               void* __restrict__ out_, int64_t ld) {
     const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
-    if (idx >= total) return;
-    const uint32_t t = fast_div(idx, divN);
+    if (idx >= total) return;   // with WU, total is a multiple of 64: whole waves leave
+    const uint32_t t = WU ? fast_div(__builtin_amdgcn_readfirstlane(idx), divN) : fast_div(idx, divN);
     const uint32_t j = idx - t * N;
     int v[D + 1];
 #pragma unroll
@@ -76,9 +78,10 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
                                                  int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
                                                  double* __restrict__ beta, unsigned long long* __restrict__ nonfinite) {
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t t = gid / G;
+    uint32_t t = gid / G;
     const int lane = int(gid & (G - 1));
     if (t >= E) return;   // the whole group leaves together
+    if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
     int v[D + 1];
 #pragma unroll
     for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
@@ -217,10 +220,10 @@ static ft_status emit_impl(ft_target* T, const ft_sample_cfg* cfg, void* points,
         const FastDiv dv = make_fastdiv(N);
         const SampleKey key = make_key(cfg);
         const unsigned grid = grid_for(int64_t(total), 256);
-        if (f32)
-            k_emit<D, true><<<grid, 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(total), N, dv, key, points, ld);
-        else
-            k_emit<D, false><<<grid, 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(total), N, dv, key, points, ld);
+        const bool wu = N % 64 == 0;
+        auto kern = f32 ? (wu ? k_emit<D, true, true> : k_emit<D, true, false>)
+                        : (wu ? k_emit<D, false, true> : k_emit<D, false, false>);
+        kern<<<grid, 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(total), N, dv, key, points, ld);
     }
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;

@@ -19,13 +19,29 @@ struct SampleKey {
     uint32_t k0, k1, stream;
 };
 
+// Square root of a in [2^-53, 1]: the hardware reciprocal-square-root estimate,
+// one Goldschmidt step (g -> sqrt(a), h -> 1 / (2 sqrt(a))) and two Newton
+// corrections of g (Markstein's scheme).  The argument range needs none of the
+// general routine's rescaling or special cases.
+__device__ __forceinline__ double sqrt_unit(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    d = fma(-g, g, a);
+    return fma(d, h, g);
+}
+
 template <int D>
 __device__ __forceinline__ void sample_lambda(uint32_t t, uint32_t j, const SampleKey& key, double (&lam)[D + 1]) {
     const u32x4 w = philox4x32_10(u32x4{j, t, key.stream, 0u}, key.k0, key.k1);
     if constexpr (D == 2) {
         const double xi = uniform53(w.x, w.y);
         const double eta = uniform53(w.z, w.w);
-        const double r = sqrt(xi);
+        const double r = sqrt_unit(xi);
         lam[0] = 1.0 - r;
         lam[1] = r * (1.0 - eta);
         lam[2] = r * eta;
