@@ -64,6 +64,11 @@ inline unsigned int grid_for(int64_t n, int block) {
     return (unsigned int)(g < 1 ? 1 : g);
 }
 
+// Iterative solvers: CG iterations launched before the first host check, one
+// more than the previous solve of the same kind needed (launches after
+// convergence return at once), else 8.
+inline int first_chunk(int hint) { return hint > 0 ? (hint + 1 < 64 ? hint + 1 : 64) : 8; }
+
 // Exclusive scan of n int32 counts into n+1 int64 offsets (device arrays,
 // work enqueued on stream; `tmp` must hold scan_tmp_elems(n) int64).
 int64_t scan_tmp_elems(int64_t n);
@@ -221,6 +226,10 @@ struct ft_target {
     double* mf_sc = nullptr;              // per-field CG scalars
     double* mf_part = nullptr;            // per-field block partials
     int reduce_blocks = 0;
+    // iterations the last solve of each kind needed (binary64, binary32 inner,
+    // many-field): the first launch chunk of the next one, so that a repeated
+    // transfer waits on the host once
+    int cg_hint[3] = {0, 0, 0};
     // call-order state
     bool consumed = false;
     ft_sample_cfg consumed_cfg{};

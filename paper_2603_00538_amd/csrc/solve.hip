@@ -394,7 +394,7 @@ static ft_status project_mixed(ft_target* T, const ft_solve_cfg* cfg, double* x,
     bool done = rr <= tol2 || !std::isfinite(rr);
     for (int step = 0; step < cfg->refine_steps && !done; ++step) {
         k_m32_init<<<nb, RB, 0, s>>>(A32, T->r, r32, z32, d32, p32, T->partials, T->scal32);
-        int launched = 0, chunk = 8;
+        int launched = 0, chunk = first_chunk(T->cg_hint[1]);
         while (launched < cfg->max_iter) {
             const int k = std::min(chunk, cfg->max_iter - launched);
             for (int it = 0; it < k; ++it) {
@@ -412,6 +412,7 @@ static ft_status project_mixed(ft_target* T, const ft_solve_cfg* cfg, double* x,
             chunk = 4;
         }
         iters += int(T->h_scal[M_ITERS]);
+        T->cg_hint[1] = int(T->h_scal[M_ITERS]);
         k_mx_apply<<<grid_for(n, 256), 256, 0, s>>>(n, d32, T->y);
         k_mx_resid<<<nb, RB, 0, s>>>(A, T->bres, T->y, T->r, T->partials);
         k_mx_totals<<<1, RB, 0, s>>>(1, nb, 0.0, T->partials, T->scal);
@@ -465,7 +466,7 @@ ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_ou
     k_cg_init<<<nb, RB, 0, s>>>(A, bresf, rtol2, T->y, T->r, T->z, T->p, T->partials, T->scal);
     FT_TRY_HIP(hipGetLastError());
     int launched = 0;
-    int chunk = 8;
+    int chunk = first_chunk(T->cg_hint[0]);
     bool done = false;
     while (true) {
         const int k = std::min(chunk, cfg->max_iter - launched);
@@ -501,6 +502,7 @@ ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_ou
     R.cons_defect = h[S_SUMB] != 0.0 ? std::fabs(h[S_INTX] - h[S_SUMB]) / std::fabs(h[S_SUMB]) : std::fabs(h[S_INTX]);
     R.rel_resid = h[S_BB] > 0.0 ? std::sqrt(h[S_TRR] / h[S_BB]) : std::sqrt(h[S_TRR]);
     R.iters = int32_t(h[S_ITERS]);
+    T->cg_hint[0] = R.iters;
     R.n_nonfinite = int64_t(nonfinite);
     R.status = FT_OK;
     if (nonfinite) R.status = FT_E_NONFINITE;

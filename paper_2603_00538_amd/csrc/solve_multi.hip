@@ -358,7 +358,7 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
     k_m_init<<<nb, MB, 0, s>>>(A, Y, R, Z, P, part);
     k_m_scalars<<<F, MB, 0, s>>>(A, 1, 0, nb, 0.0, part, sc);
     FT_TRY_HIP(hipGetLastError());
-    int launched = 0, chunk = 8;
+    int launched = 0, chunk = first_chunk(T->cg_hint[2]);
     while (launched < cfg->max_iter) {
         const int k = std::min(chunk, cfg->max_iter - launched);
         for (int it = 0; it < k; ++it) {
@@ -390,6 +390,7 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
     FT_TRY_HIP(hipMemcpyAsync(h.data(), sc, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
     FT_TRY_HIP(hipStreamSynchronize(s));
     ft_status worst = FT_OK;
+    T->cg_hint[2] = 0;
     for (int f = 0; f < F; ++f) {
         ft_report& Rp = rep[f];
         const double bb = h[SC_BB * Fp + f], sb = h[SC_SUMB * Fp + f];
@@ -398,6 +399,7 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
         Rp.cons_defect = sb != 0.0 ? std::fabs(Rp.int_x - sb) / std::fabs(sb) : std::fabs(Rp.int_x);
         Rp.rel_resid = bb > 0.0 ? std::sqrt(h[SC_TRR * Fp + f] / bb) : std::sqrt(h[SC_TRR * Fp + f]);
         Rp.iters = int32_t(h[SC_ITERS * Fp + f]);
+        T->cg_hint[2] = std::max(T->cg_hint[2], int(Rp.iters));
         Rp.n_nonfinite = int64_t(nonfinite);
         Rp.status = nonfinite ? FT_E_NONFINITE : (h[SC_DONE * Fp + f] != 0.0 ? FT_OK : FT_E_NOCONV);
         if (Rp.status != FT_OK && (worst == FT_OK || Rp.status == FT_E_NONFINITE)) worst = ft_status(Rp.status);
