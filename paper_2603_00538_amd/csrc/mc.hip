@@ -21,20 +21,11 @@
 
 namespace ft {
 
-// WU: N is a multiple of 64, so the 64 samples of a wave belong to one element
-// and its connectivity and vertex coordinates are scalar loads.
-template <int D, bool F32, bool WU>
-__global__ __launch_bounds__(256) void k_emit(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
-                                              uint32_t total, uint32_t N, FastDiv divN, SampleKey key,
-                                              void* __restrict__ out_, int64_t ld) {
-    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
-    if (idx >= total) return;   // with WU, total is a multiple of 64: whole waves leave
-    const uint32_t t = WU ? fast_div(__builtin_amdgcn_readfirstlane(idx), divN) : fast_div(idx, divN);
-    const uint32_t j = idx - t * N;
-    int v[D + 1];
-#pragma unroll
-    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
-    const int64_t q = n + int64_t(idx);
+// Sample j of element t (vertices v) written to query q of the list.
+template <int D, bool F32>
+__device__ __forceinline__ void emit_sample(const double* __restrict__ X, int64_t n, const int (&v)[D + 1],
+                                            uint32_t t, uint32_t j, const SampleKey& key, void* __restrict__ out_,
+                                            int64_t ld, int64_t q) {
     if constexpr (!F32) {
         double lam[D + 1];
         sample_lambda<D>(t, j, key, lam);
@@ -60,6 +51,42 @@ __global__ __launch_bounds__(256) void k_emit(const double* __restrict__ X, int6
     }
 }
 
+// R == 0: one sample per lane, any N.  R > 0 (N a multiple of 64): every run
+// of 64 consecutive samples belongs to one element, whose connectivity and
+// vertex coordinates are then scalar loads, and each wave writes R runs.
+template <int D, bool F32, int R>
+__global__ __launch_bounds__(256) void k_emit(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
+                                              uint32_t total, uint32_t N, FastDiv divN, SampleKey key,
+                                              void* __restrict__ out_, int64_t ld) {
+    if constexpr (R == 0) {
+        const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+        if (idx >= total) return;
+        const uint32_t t = fast_div(idx, divN);
+        int v[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
+        emit_sample<D, F32>(X, n, v, t, idx - t * N, key, out_, ld, n + int64_t(idx));
+    } else {
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint64_t wave = uint64_t(blockIdx.x) * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t c0 = (wave * R + r) * 64u;   // first sample of the run (wave-uniform)
+            if (c0 >= total) break;
+            const uint32_t t = fast_div(uint32_t(c0), divN);
+            int v[D + 1];
+#pragma unroll
+            for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
+            emit_sample<D, F32>(X, n, v, t, uint32_t(c0) - t * N + lane, key, out_, ld, n + int64_t(c0) + lane);
+        }
+    }
+}
+
+// 64-sample runs per wave when N is a multiple of 64 (a tetrahedron sample
+// draws two Philox blocks, so half as many runs)
+template <int D>
+constexpr int kEmitRuns = D == 2 ? 8 : 4;
+
 template <bool F32>
 __global__ void k_emit_nodes(const double* __restrict__ X, int64_t n, int dim, void* __restrict__ out_, int64_t ld) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -72,16 +99,14 @@ __global__ void k_emit_nodes(const double* __restrict__ X, int64_t n, int dim, v
     }
 }
 
+// Element t's sums over its N samples (lanes stride over them, G lanes per
+// element); returns the number of non-finite values seen by this lane.
 template <int D, int G, int FC, bool F32>
-__global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, int64_t ld, int F,
-                                                 const int32_t* __restrict__ conn, const double* __restrict__ vol,
-                                                 int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
-                                                 double* __restrict__ beta, unsigned long long* __restrict__ nonfinite) {
-    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
-    uint32_t t = gid / G;
-    const int lane = int(gid & (G - 1));
-    if (t >= E) return;   // the whole group leaves together
-    if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
+__device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, const void* __restrict__ values_,
+                                                        int64_t ld, int F, const int32_t* __restrict__ conn,
+                                                        const double* __restrict__ vol, int64_t n, uint32_t E,
+                                                        uint32_t N, double alpha, const SampleKey& key,
+                                                        double* __restrict__ beta) {
     int v[D + 1];
 #pragma unroll
     for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
@@ -137,6 +162,34 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
                 for (int k = 0; k <= D; ++k) beta[(int64_t(f0 + f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
             }
         }
+    }
+    return nf;
+}
+
+// G lanes per element.  R > 1 (G == 64 only): each wave sums R consecutive
+// elements in turn, with their element data in scalar registers.
+template <int D, int G, int FC, bool F32, int R>
+__global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, int64_t ld, int F,
+                                                 const int32_t* __restrict__ conn, const double* __restrict__ vol,
+                                                 int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
+                                                 double* __restrict__ beta, unsigned long long* __restrict__ nonfinite) {
+    unsigned int nf = 0;
+    if constexpr (R > 1) {
+        static_assert(G == 64, "one element per wave");
+        const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lane = int(threadIdx.x & 63u);
+        for (int e = 0; e < R; ++e) {
+            const uint32_t t = wave * uint32_t(R) + uint32_t(e);
+            if (t >= E) break;
+            nf += consume_element<D, G, FC, F32>(t, lane, values_, ld, F, conn, vol, n, E, N, alpha, key, beta);
+        }
+    } else {
+        const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+        uint32_t t = gid / G;
+        const int lane = int(gid & (G - 1));
+        if (t >= E) return;   // the whole group leaves together
+        if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
+        nf = consume_element<D, G, FC, F32>(t, lane, values_, ld, F, conn, vol, n, E, N, alpha, key, beta);
     }
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
@@ -220,10 +273,14 @@ static ft_status emit_impl(ft_target* T, const ft_sample_cfg* cfg, void* points,
         const FastDiv dv = make_fastdiv(N);
         const SampleKey key = make_key(cfg);
         const unsigned grid = grid_for(int64_t(total), 256);
-        const bool wu = N % 64 == 0;
-        auto kern = f32 ? (wu ? k_emit<D, true, true> : k_emit<D, true, false>)
-                        : (wu ? k_emit<D, false, true> : k_emit<D, false, false>);
-        kern<<<grid, 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(total), N, dv, key, points, ld);
+        if (N % 64 == 0) {
+            auto kern = f32 ? k_emit<D, true, kEmitRuns<D>> : k_emit<D, false, kEmitRuns<D>>;
+            kern<<<grid_for(int64_t(total), 256 * kEmitRuns<D>), 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(total),
+                                                                            N, dv, key, points, ld);
+        } else {
+            auto kern = f32 ? k_emit<D, true, 0> : k_emit<D, false, 0>;
+            kern<<<grid, 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(total), N, dv, key, points, ld);
+        }
     }
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
@@ -233,13 +290,16 @@ ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipS
     return T->dim == 2 ? emit_impl<2>(T, cfg, points, s) : emit_impl<3>(T, cfg, points, s);
 }
 
+constexpr int kConsumeRuns = 4;   // elements per wave when G == 64
+
 template <int D, int G, int FC, bool F32>
 static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, hipStream_t s) {
     const SampleKey key = make_key(cfg);
-    const unsigned grid = grid_for(T->E * G, 256);
-    k_consume<D, G, FC, F32><<<grid, 256, 0, s>>>(values, ld, cfg->n_fields, T->conn, T->vol, T->n, uint32_t(T->E),
-                                                  uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->beta,
-                                                  T->counters);
+    constexpr int R = G == 64 ? kConsumeRuns : 1;
+    const unsigned grid = grid_for(T->E * G, 256 * R);
+    k_consume<D, G, FC, F32, R><<<grid, 256, 0, s>>>(values, ld, cfg->n_fields, T->conn, T->vol, T->n,
+                                                     uint32_t(T->E), uint32_t(cfg->samples_per_elem), cfg->alpha, key,
+                                                     T->beta, T->counters);
 }
 
 template <int D, int G, bool F32>

@@ -106,8 +106,9 @@ __global__ void k_plan_nodes(const double* __restrict__ rec, const int32_t* __re
 }
 
 // online, steps 3-5: residual element sums with cached elements; G lanes per
-// element, lane-stride sample order and butterfly as the fused route
-template <int D, int G, int FC>
+// element, lane-stride sample order and butterfly as the fused route.  R > 1
+// (G == 64 only): each wave sums R consecutive elements in turn.
+template <int D, int G, int FC, int R>
 __global__ __launch_bounds__(256) void k_plan_elements(const double* __restrict__ rec, const int32_t* __restrict__ sconn,
                                                        const double* __restrict__ vals, int64_t ns, int F,
                                                        const double* __restrict__ X, int64_t n,
@@ -116,69 +117,72 @@ __global__ __launch_bounds__(256) void k_plan_elements(const double* __restrict_
                                                        const int32_t* __restrict__ ids, const double* __restrict__ g,
                                                        double* __restrict__ beta,
                                                        unsigned long long* __restrict__ nonfinite) {
+    static_assert(R == 1 || G == 64, "several elements per wave need one element per wave");
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
-    uint32_t t = gid / G;
-    if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
     const int lane = int(gid & (G - 1));
-    if (t >= E) return;   // the whole group leaves together
-    int v[D + 1];
-    double xv[D + 1][D];
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        v[k] = conn[int64_t(t) * (D + 1) + k];
-#pragma unroll
-        for (int c = 0; c < D; ++c) xv[k][c] = X[c * n + v[k]];
-    }
     unsigned nf = 0;
-    for (int f0 = 0; f0 < F; f0 += FC) {
-        double gk[FC][D + 1], acc[FC][D + 1];
+    for (int e = 0; e < R; ++e) {
+        uint32_t t = R > 1 ? (blockIdx.x * 4u + (threadIdx.x >> 6)) * uint32_t(R) + uint32_t(e) : gid / G;
+        if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
+        if (t >= E) break;   // the whole group leaves together
+        int v[D + 1];
+        double xv[D + 1][D];
 #pragma unroll
-        for (int f = 0; f < FC; ++f)
+        for (int k = 0; k <= D; ++k) {
+            v[k] = conn[int64_t(t) * (D + 1) + k];
 #pragma unroll
-            for (int k = 0; k <= D; ++k) {
-                acc[f][k] = 0.0;
-                gk[f][k] = g[int64_t(f0 + f < F ? f0 + f : 0) * n + v[k]];
-            }
-        for (uint32_t j = lane; j < N; j += G) {
-            double lam[D + 1], pt[D], mu[D + 1];
-            sample_lambda<D>(t, j, key, lam);
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                double x = lam[0] * xv[0][c];
-#pragma unroll
-                for (int k = 1; k <= D; ++k) x = fma(lam[k], xv[k][c], x);
-                pt[c] = x;
-            }
-            const int id = ids[int64_t(t) * N + j];
-            if (id >= 0) (void)barycentric<D>(rec + int64_t(id) * RecSize<D>::value, pt, mu);
-#pragma unroll
-            for (int f = 0; f < FC; ++f) {
-                if (f0 + f >= F) break;
-                double y = 0.0;
-                if (id >= 0)
-#pragma unroll
-                    for (int k = 0; k <= D; ++k)
-                        y = fma(mu[k], vals[int64_t(f0 + f) * ns + sconn[int64_t(id) * (D + 1) + k]], y);
-                nf += !isfinite(y);
-                double gx = lam[0] * gk[f][0];
-#pragma unroll
-                for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
-                const double r = y - alpha * gx;
-#pragma unroll
-                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
-            }
+            for (int c = 0; c < D; ++c) xv[k][c] = X[c * n + v[k]];
         }
+        for (int f0 = 0; f0 < F; f0 += FC) {
+            double gk[FC][D + 1], acc[FC][D + 1];
 #pragma unroll
-        for (int f = 0; f < FC; ++f)
+            for (int f = 0; f < FC; ++f)
 #pragma unroll
-            for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
-        if (lane == 0) {
-            const double scale = vol[t] / double(N);
+                for (int k = 0; k <= D; ++k) {
+                    acc[f][k] = 0.0;
+                    gk[f][k] = g[int64_t(f0 + f < F ? f0 + f : 0) * n + v[k]];
+                }
+            for (uint32_t j = lane; j < N; j += G) {
+                double lam[D + 1], pt[D], mu[D + 1];
+                sample_lambda<D>(t, j, key, lam);
 #pragma unroll
-            for (int f = 0; f < FC; ++f) {
-                if (f0 + f >= F) break;
+                for (int c = 0; c < D; ++c) {
+                    double x = lam[0] * xv[0][c];
 #pragma unroll
-                for (int k = 0; k <= D; ++k) beta[(int64_t(f0 + f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+                    for (int k = 1; k <= D; ++k) x = fma(lam[k], xv[k][c], x);
+                    pt[c] = x;
+                }
+                const int id = ids[int64_t(t) * N + j];
+                if (id >= 0) (void)barycentric<D>(rec + int64_t(id) * RecSize<D>::value, pt, mu);
+#pragma unroll
+                for (int f = 0; f < FC; ++f) {
+                    if (f0 + f >= F) break;
+                    double y = 0.0;
+                    if (id >= 0)
+#pragma unroll
+                        for (int k = 0; k <= D; ++k)
+                            y = fma(mu[k], vals[int64_t(f0 + f) * ns + sconn[int64_t(id) * (D + 1) + k]], y);
+                    nf += !isfinite(y);
+                    double gx = lam[0] * gk[f][0];
+#pragma unroll
+                    for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
+                    const double r = y - alpha * gx;
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < FC; ++f)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
+            if (lane == 0) {
+                const double scale = vol[t] / double(N);
+#pragma unroll
+                for (int f = 0; f < FC; ++f) {
+                    if (f0 + f >= F) break;
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) beta[(int64_t(f0 + f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+                }
             }
         }
     }
@@ -234,14 +238,15 @@ static void launch_elements(ft_plan* pl, const double* vals, hipStream_t s) {
     const ft_source* S = pl->S;
     const SampleKey key{uint32_t(pl->cfg.seed & 0xFFFFFFFFu), uint32_t(pl->cfg.seed >> 32), pl->cfg.stream_id};
     const int F = pl->cfg.n_fields;
-    const unsigned grid = grid_for(T->E * G, 256);
+    constexpr int R = G == 64 && D == 2 ? 4 : 1;   // elements per wave (measured no gain for tetrahedra)
+    const unsigned grid = grid_for(T->E * G, 256 * R);
     const uint32_t N = uint32_t(pl->cfg.samples_per_elem);
     if (F == 1)
-        k_plan_elements<D, G, 1><<<grid, 256, 0, s>>>(S->rec, S->conn, vals, S->n, F, T->coords, T->n, T->conn,
+        k_plan_elements<D, G, 1, R><<<grid, 256, 0, s>>>(S->rec, S->conn, vals, S->n, F, T->coords, T->n, T->conn,
                                                       T->vol, uint32_t(T->E), N, pl->cfg.alpha, key, pl->ids + T->n,
                                                       T->g, T->beta, T->counters);
     else
-        k_plan_elements<D, G, 4><<<grid, 256, 0, s>>>(S->rec, S->conn, vals, S->n, F, T->coords, T->n, T->conn,
+        k_plan_elements<D, G, 4, R><<<grid, 256, 0, s>>>(S->rec, S->conn, vals, S->n, F, T->coords, T->n, T->conn,
                                                       T->vol, uint32_t(T->E), N, pl->cfg.alpha, key, pl->ids + T->n,
                                                       T->g, T->beta, T->counters);
 }
