@@ -91,9 +91,36 @@ __global__ __launch_bounds__(RB) void k_cg_spmv(Mat A, int k, const double* __re
     double pq = 0.0;
     FOR_ROW(i) {
         double qi = 0.0;
-        for (int64_t kk = A.rowptr[i]; kk < A.rowptr[i + 1]; ++kk) {
-            const int32_t j = A.col[kk];
-            qi = fma(A.val[kk], fma(bt, p_old[j], z[j]), qi);
+        const int64_t k1 = A.rowptr[i + 1];
+        int64_t kk = A.rowptr[i];
+        // four entries at a time: their loads are issued together (same order of sums)
+        for (; kk + 4 <= k1; kk += 4) {
+            int32_t j[4];
+            double a[4], pj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                j[u] = A.col[kk + u];
+                a[u] = A.val[kk + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pj[u] = fma(bt, p_old[j[u]], z[j[u]]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) qi = fma(a[u], pj[u], qi);
+        }
+        if (kk < k1) {   // the last one to three entries, also loaded together
+            int32_t j[3];
+            double a[3], pj[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int64_t ku = kk + u < k1 ? kk + u : kk;   // entries past the row reread kk
+                j[u] = A.col[ku];
+                a[u] = A.val[ku];
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u) pj[u] = fma(bt, p_old[j[u]], z[j[u]]);
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                if (kk + u < k1) qi = fma(a[u], pj[u], qi);
         }
         const double pi = fma(bt, p_old[i], z[i]);
         p_new[i] = pi;
