@@ -64,6 +64,33 @@ inline unsigned int grid_for(int64_t n, int block) {
     return (unsigned int)(g < 1 ? 1 : g);
 }
 
+// ---------------------------------------------------------------- sparse rows
+// sum over the entries kk in [k0, k1) of a row, in order, of val[kk] * x(col[kk]):
+// the column indices, values and x of four entries are loaded together (the last
+// one to three entries reread entry k0 for the slots past the row, unused).
+template <class T, class X>
+__device__ __forceinline__ T row_dot4(const int32_t* __restrict__ col, const T* __restrict__ val, int64_t k0,
+                                      int64_t k1, X&& x) {
+    T s = T(0);
+    int64_t kk = k0;
+    for (; kk < k1; kk += 4) {
+        int32_t j[4];
+        T a[4], xj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t ku = kk + u < k1 ? kk + u : k0;
+            j[u] = col[ku];
+            a[u] = val[ku];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xj[u] = x(j[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (kk + u < k1) s = fma(a[u], xj[u], s);
+    }
+    return s;
+}
+
 // Iterative solvers: CG iterations launched before the first host check, one
 // more than the previous solve of the same kind needed (launches after
 // convergence return at once), else 8.

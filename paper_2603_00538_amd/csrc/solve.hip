@@ -90,38 +90,8 @@ __global__ __launch_bounds__(RB) void k_cg_spmv(Mat A, int k, const double* __re
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_RHO0 + (k & 1)] = rz;
     double pq = 0.0;
     FOR_ROW(i) {
-        double qi = 0.0;
-        const int64_t k1 = A.rowptr[i + 1];
-        int64_t kk = A.rowptr[i];
-        // four entries at a time: their loads are issued together (same order of sums)
-        for (; kk + 4 <= k1; kk += 4) {
-            int32_t j[4];
-            double a[4], pj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                j[u] = A.col[kk + u];
-                a[u] = A.val[kk + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) pj[u] = fma(bt, p_old[j[u]], z[j[u]]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) qi = fma(a[u], pj[u], qi);
-        }
-        if (kk < k1) {   // the last one to three entries, also loaded together
-            int32_t j[3];
-            double a[3], pj[3];
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                const int64_t ku = kk + u < k1 ? kk + u : kk;   // entries past the row reread kk
-                j[u] = A.col[ku];
-                a[u] = A.val[ku];
-            }
-#pragma unroll
-            for (int u = 0; u < 3; ++u) pj[u] = fma(bt, p_old[j[u]], z[j[u]]);
-#pragma unroll
-            for (int u = 0; u < 3; ++u)
-                if (kk + u < k1) qi = fma(a[u], pj[u], qi);
-        }
+        const double qi = row_dot4(A.col, A.val, A.rowptr[i], A.rowptr[i + 1],
+                                   [&](int32_t j) { return fma(bt, p_old[j], z[j]); });
         const double pi = fma(bt, p_old[i], z[i]);
         p_new[i] = pi;
         q[i] = qi;
@@ -327,11 +297,8 @@ __global__ __launch_bounds__(RB) void k_m32_spmv(Mat32 A, int k, const float* __
     if (blockIdx.x == 0 && threadIdx.x == 0) sc[M_RHO0 + (k & 1)] = rz;
     double pq = 0.0;
     FOR_ROW(i) {
-        float qi = 0.0f;
-        for (int64_t kk = A.rowptr[i]; kk < A.rowptr[i + 1]; ++kk) {
-            const int32_t j = A.col[kk];
-            qi = fmaf(A.val[kk], fmaf(bt, p_old[j], z[j]), qi);
-        }
+        const float qi = row_dot4(A.col, A.val, A.rowptr[i], A.rowptr[i + 1],
+                                  [&](int32_t j) { return fmaf(bt, p_old[j], z[j]); });
         const float pi = fmaf(bt, p_old[i], z[i]);
         p_new[i] = pi;
         q[i] = qi;

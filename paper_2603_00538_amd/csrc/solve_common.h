@@ -44,9 +44,7 @@ __device__ __forceinline__ void write_partial(double* __restrict__ part, int slo
 
 __device__ __forceinline__ double csr_row(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                           const double* __restrict__ val, const double* __restrict__ x, int64_t i) {
-    double s = 0.0;
-    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) s = fma(val[k], x[col[k]], s);
-    return s;
+    return row_dot4(col, val, rowptr[i], rowptr[i + 1], [&](int32_t j) { return x[j]; });
 }
 
 struct Mat {
