@@ -279,6 +279,33 @@ def test_bitwise_deterministic(c1):
     assert not np.array_equal(a["x"], c["x"])
 
 
+def test_solver_launch_hint_keeps_results(c1):
+    """A target launches as many CG iterations as its previous solve of the same
+    kind needed before its first host check; the launches after convergence
+    must leave x, b and the iteration count as a fresh target computes them."""
+    w, tm, sm, sv = c1
+    T, T2, S = ft.Target(*tm), ft.Target(*tm), ft.Source(*sm, sv)
+    cfg = ft.SampleCfg(64, 1, 1.0, 5, 0, ft.FT_F64)
+    pts = T.sample_points(cfg)
+    T2.sample_points(cfg)
+    vals = S.eval_query_list(pts, tm[0].shape[0])
+    T.consume(cfg, vals)
+    T2.consume(cfg, vals)
+    hard = T.project(1, rtol=1e-14)
+    hx, hit = hard.x.clone(), hard.reports[0]["iters"]
+    easy = T.project(1, rtol=1e-6)   # first launch chunk longer than this solve needs
+    fresh = T2.project(1, rtol=1e-6)
+    assert easy.reports[0]["iters"] == fresh.reports[0]["iters"] < hit
+    assert torch.equal(easy.x, fresh.x) and torch.equal(easy.b, fresh.b)
+    again = T.project(1, rtol=1e-14)
+    assert torch.equal(again.x, hx) and again.reports[0]["iters"] == hit
+    m1 = T.project(1, refine_steps=3).x.clone()   # binary32 inner solves, then with their hint
+    m2 = T.project(1, refine_steps=3).x
+    assert torch.equal(m1, m2)
+    for h in (T, T2, S):
+        h.close()
+
+
 # ---------------------------------------------------------------- error paths
 def test_call_order_and_status_errors():
     tm, sm = _small_2d()
