@@ -86,3 +86,54 @@ def test_multi_field_evaluation():
     y = src(pts)
     assert y.shape == (5, 3)
     assert np.abs(y - vals[:, [3, 17, 40]]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- face distances
+# Elements whose heights h_k (distance from vertex k to the opposite face) are
+# known in closed form: the right triangle (0,0), (a,0), (0,b) has h_1 = a,
+# h_2 = b and h_0 = ab / sqrt(a^2 + b^2); the right tetrahedron with legs a, b,
+# c has h_1 = a, h_2 = b, h_3 = c and h_0 = 1 / sqrt(a^-2 + b^-2 + c^-2).  The
+# legs differ, so a height taken from the wrong face, or scaled wrongly, is
+# caught, and so is the exclusion decision at the 1e-12 cut of the element-id
+# comparison (points within 1e-12 of a face are left out of it).
+def _right_simplex(d, legs):
+    coords = np.zeros((d + 1, d))
+    for k in range(d):
+        coords[k + 1, k] = legs[k]
+    conn = np.arange(d + 1)[None, :]
+    h0 = 1.0 / np.sqrt(np.sum(1.0 / np.asarray(legs, dtype=float) ** 2))
+    return coords, conn, np.array([h0, *legs])
+
+
+@pytest.mark.parametrize("d,legs", [(2, (0.7, 0.2)), (3, (0.5, 0.3, 0.9)), (3, (3e-6, 7e-6, 2e-6))])
+def test_face_distance_closed_form(d, legs):
+    coords, conn, h = _right_simplex(d, legs)
+    src = P1Source(coords, conn, np.zeros(d + 1))
+    assert np.allclose(src.heights[0], h, rtol=1e-14, atol=0)
+    scale = min(legs)
+    # a point well inside: every face distance is mu_k h_k; at the centroid mu_k = 1/(d+1)
+    centroid = coords.mean(axis=0)
+    ids, mu, _ = src.locate(centroid[None, :])
+    assert np.isclose(src.face_distance(ids, mu)[0], h.min() / (d + 1), rtol=1e-13)
+    for k in range(d + 1):
+        # points at signed distance delta from face k (positive: inside), near
+        # the middle of that face; for k >= 1 the face is the coordinate plane
+        # x_{k-1} = 0, for k = 0 the hypotenuse face with outward normal n
+        if k == 0:
+            n = 1.0 / np.asarray(legs, dtype=float)
+            n /= np.linalg.norm(n)
+            on_face = coords[1:].mean(axis=0)
+            direction = -n
+        else:
+            others = [i for i in range(d + 1) if i != k]
+            on_face = coords[others].mean(axis=0)
+            direction = np.zeros(d)
+            direction[k - 1] = 1.0
+        for rel, inside in ((1e-13, False), (1e-11, True), (-1e-11, False), (0.05, True)):
+            delta = rel * (1.0 if rel < 1e-3 else scale)
+            p = on_face + delta * direction
+            ids, mu, _ = src.locate(p[None, :])
+            fd = src.face_distance(ids, mu)[0]
+            tol = 1e-15 * max(1.0, np.abs(p).max() / scale) + 1e-16 * abs(delta)
+            assert abs(fd - delta) <= max(tol, 2e-12 * abs(delta)), (k, rel, fd, delta)
+            assert (fd > 1e-12) == inside, (k, rel, fd)
