@@ -18,9 +18,11 @@ def log(msg):
 
 
 def gpu_transfer(tmesh, smesh, svals, N, alpha=1.0, seed=7, stream=0, precision=ft.FT_F64, bins=None,
-                 rtol=1e-14, max_iter=500, black_box=None):
+                 rtol=1e-14, max_iter=500, black_box=None, refine_steps=0):
     """Whole transfer through libft.  black_box: optional callable on the (d, Q)
-    device points returning (F, Q) device values (replaces the built-in source)."""
+    device points returning (F, Q) device values (replaces the built-in source).
+    refine_steps > 0 solves with binary32 inner PCG and that many binary64
+    refinement steps."""
     import torch
 
     tc, tconn = tmesh
@@ -42,7 +44,7 @@ def gpu_transfer(tmesh, smesh, svals, N, alpha=1.0, seed=7, stream=0, precision=
         F = vals.shape[0]
         cfg.n_fields = F
     T.consume(cfg, vals)
-    res = T.project(F, rtol=rtol, max_iter=max_iter)
+    res = T.project(F, rtol=rtol, max_iter=max_iter, refine_steps=refine_steps)
     torch.cuda.synchronize()
     out = {
         "points": pts.double().cpu().numpy(), "values": vals.double().cpu().numpy(), "ids": ids.cpu().numpy(),

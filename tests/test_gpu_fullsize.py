@@ -152,19 +152,37 @@ def test_fullsize_rerun_is_bitwise_identical(case, fp64):
 
 
 def test_fullsize_fp32_form(case, fp64):
+    """The binary32 form at full size: its load vector at the sampled nodes
+    against the binary64 oracle; its binary64 PCG solution and its binary32
+    PCG + binary64 refinement solution against the oracle's own CG solve of
+    the same load vector; conservation."""
     tm, sm, sv, osrc = case
+    tc, tconn = tm
     x64 = fp64[6].x.cpu().numpy()[0]
     log("tri2d_1m: GPU transfer FP32 form")
     T, S, cfg, pts, vals, ids, res = _run(tm, sm, sv, ft.FT_F32)
     x32 = res.x.cpu().numpy()[0]
     b32 = res.b.cpu().numpy()[0]
+    mixed = T.project(1, rtol=W.rtol, refine_steps=4)
+    torch.cuda.synchronize()
+    xr = mixed.x.cpu().numpy()[0]
+    assert mixed.status == ft.FT_OK and torch.equal(mixed.b, res.b)
     _, nodes = _sample_sets(tm)
-    g = np.atleast_2d(osrc(tm[0]))
+    g = np.atleast_2d(osrc(tc))
     ref = _oracle_b_at(tm, osrc, g, nodes)
     eb = np.linalg.norm(b32[nodes] - ref) / np.linalg.norm(ref)
-    ex = cvmc.rel_l2(x32, x64)
-    log(f"FP32 form: sampled b rel l2 {eb:.2e}; x vs FP64 path {ex:.2e}")
-    assert eb < 1e-5 and ex < 1e-5
+    M = geometry.mass_matrix(tc, tconn)
+    x_or = cvmc.jacobi_cg(M, b32, 1e-15)
+    es, er = cvmc.rel_l2(x32, x_or), cvmc.rel_l2(xr, x_or)
+    log(f"FP32 form: sampled b rel l2 {eb:.2e}; x vs oracle CG of the same b {es:.2e} (refined {er:.2e}); "
+        f"x vs binary64 route {cvmc.rel_l2(x32, x64):.2e}")
+    assert eb < 1e-5
+    assert es < 1e-12 and er < 1e-12
+    assert cvmc.rel_l2(x32, x64) < 1e-5
+    m = geometry.lumped_mass(tc, tconn)
+    for r, x in ((res.reports[0], x32), (mixed.reports[0], xr)):
+        assert abs(r["int_x"] - math.fsum(m * x)) <= 1e-13 * abs(r["int_x"])
+        assert r["cons_defect"] < 1e-13
     r64 = fp64[6].reports[0]
     assert abs(res.reports[0]["sum_b"] - r64["sum_b"]) <= 1e-6 * abs(r64["sum_b"])
     T.close()
