@@ -89,7 +89,9 @@ typedef struct {
                                 /* (binary64 dot products), stopping on the true residual          */
 } ft_solve_cfg;
 
-/* Per-field result of ft_project (conservation: sec. 2 Eq. conservation, App. B). */
+/* Per-field result of ft_project (conservation: sec. 2 Eq. conservation, App. B).
+ * sum_b and int_x are compensated sums (each addition's rounding error is
+ * carried along, as in Neumaier's summation). */
 typedef struct {
     double  sum_b;              /* sum_i b_i                                                       */
     double  int_x;              /* m^T x = integral of the transferred field, m = M 1             */
@@ -98,6 +100,10 @@ typedef struct {
     int32_t iters;              /* CG iterations taken                                             */
     int32_t status;             /* FT_OK, FT_E_NOCONV or FT_E_NONFINITE for this field             */
     int64_t n_nonfinite;        /* non-finite query values seen by the last consume                */
+    int64_t n_out_of_domain;    /* query points outside the source mesh (extrapolated), counted by  */
+                                /* the built-in source routes (ft_transfer_p1, plans, batches);    */
+                                /* -1 after ft_consume_queries: the caller's black box evaluated   */
+                                /* the points (ft_source_stats counts ft_source_eval's)            */
 } ft_report;
 
 /* Sizes of a target after setup. */
@@ -190,7 +196,8 @@ ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b
  * ft_consume_queries, fused into one pass over the samples.  Follow with
  * ft_project.  Requires cfg->precision == FT_F64, cfg->n_fields equal to the
  * source's field count (at most 4), and a source of the target's dimension.
- * Out-of-domain samples are counted in the source (ft_source_stats).
+ * Out-of-domain queries (nodes and samples) are counted for the transfer and
+ * reported by ft_project (ft_report.n_out_of_domain).
  * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Asynchronous on `stream`.
  */
 ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, hipStream_t stream);
@@ -207,7 +214,9 @@ ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
  * Localization rule: the element maximizing min_k mu_k(x) (mu: barycentric
  * coordinates); exact ties go to the lowest element id; a best min mu below
  * -1e-10 counts as out of domain and is evaluated by extrapolation from that
- * element.  Errors: FT_E_ARG, FT_E_MESH, FT_E_OOM.  Synchronizes `stream`.
+ * element, which is then searched among all elements (however far outside
+ * the point lies; such points cost a pass over the whole mesh).
+ * Errors: FT_E_ARG, FT_E_MESH, FT_E_OOM.  Synchronizes `stream`.
  */
 ft_status ft_source_create_p1(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems,
                               const int32_t* conn, int32_t n_fields, const double* nodal_values,
@@ -265,7 +274,9 @@ typedef struct {
 
 ft_status ft_source_get_info(const ft_source* s, ft_source_info* info /* host */);
 
-/* Out-of-domain points seen by ft_source_eval since the last call (then reset).
+/* Out-of-domain points seen by ft_source_eval and ft_source_eval_queries since
+ * the last call (then reset); the transfer routes report theirs in
+ * ft_report.n_out_of_domain.
  * Synchronizes `stream`. */
 ft_status ft_source_stats(ft_source* s, int64_t* n_out_of_domain /* host */, hipStream_t stream);
 
@@ -283,7 +294,8 @@ typedef struct ft_plan ft_plan;
  * target node and sample in source `s` once (the containing source element
  * of each query is kept on the device, 4 bytes per query).  cfg: FT_F64,
  * n_fields equal to the source's field count.  t and s are not owned and must
- * outlive the plan.  Out-of-domain queries are counted in the source.
+ * outlive the plan.  Out-of-domain queries are counted once here and reported
+ * by ft_project after every ft_plan_transfer (ft_report.n_out_of_domain).
  * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Synchronizes `stream`.
  */
 ft_status ft_plan_create(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, hipStream_t stream, ft_plan** out);

@@ -10,12 +10,12 @@ const char* last_error();
 ft_status target_setup(ft_target* T, const double* coords, const int32_t* conn, hipStream_t s);
 ft_status solver_alloc(ft_target* T, hipStream_t s);
 ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipStream_t s);
-ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s);
+ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s);
 ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep, hipStream_t s);
 ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, const double* values,
                        const int32_t* bins, hipStream_t s);
-ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
-                      int32_t* ids, hipStream_t s);
+ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
+                      int64_t ld_out, int32_t* ids, hipStream_t s, unsigned long long* ood);
 ft_status source_release(ft_source* S);
 ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, int ncand,
                           const int32_t* cand, hipStream_t s);
@@ -122,6 +122,9 @@ ft_status ft_target_create(int32_t dim, int64_t n_nodes, const double* coords, i
     T->E = n_elems;
     ft_status st = target_setup(T, coords, conn, stream);
     if (st == FT_OK) st = solver_alloc(T, stream);
+    // one field's transfer buffers up front, so that a first one-field
+    // transfer needs no allocation
+    if (st == FT_OK) st = ensure_field_buffers(T, 1, stream);
     if (st == FT_OK && hipStreamSynchronize(stream) != hipSuccess) {
         set_error("stream synchronization failed after setup");
         st = FT_E_DEVICE;
@@ -188,7 +191,7 @@ ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void*
     }
     FT_TRY(ensure_field_buffers(T, cfg->n_fields, stream));
     T->consumed = false;
-    FT_TRY(consume_values(T, cfg, values, stream));
+    FT_TRY(consume_values(T, cfg, values, T->beta, stream));
     T->consumed = true;
     T->consumed_cfg = *cfg;
     return FT_OK;
@@ -376,7 +379,7 @@ ft_status ft_source_eval(ft_source* s, int64_t n_points, const void* points, int
     FT_ARG_CHECK(ld >= n_points && ld_out >= n_points, "leading dimensions must be >= n_points");
     FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
     FT_ARG_CHECK(n_points < (int64_t(1) << 39), "n_points too large");
-    return source_eval(s, 0, n_points, points, ld, precision, values, ld_out, elem_ids, stream);
+    return source_eval(s, 0, n_points, points, ld, precision, values, ld_out, elem_ids, stream, nullptr);
     FT_GUARD_END
 }
 
@@ -392,7 +395,7 @@ ft_status ft_source_eval_queries(ft_source* s, int64_t n_nodes, int64_t n_points
     FT_ARG_CHECK(ld >= n_points && ld_out >= n_points, "leading dimensions must be >= n_points");
     FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
     FT_ARG_CHECK(n_points < (int64_t(1) << 39), "n_points too large");
-    return source_eval(s, n_nodes, n_points, points, ld, precision, values, ld_out, elem_ids, stream);
+    return source_eval(s, n_nodes, n_points, points, ld, precision, values, ld_out, elem_ids, stream, nullptr);
     FT_GUARD_END
 }
 

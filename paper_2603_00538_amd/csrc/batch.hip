@@ -26,6 +26,8 @@
 #include <numeric>
 #include <vector>
 
+#include <cstring>
+
 #include "fused.h"
 
 struct ft_batch;
@@ -53,7 +55,7 @@ struct BatchXfer {
     double* g;
     double* beta;
     double* bres;
-    unsigned long long* src_ood;   // the source's out-of-domain counter
+    unsigned long long* ood;       // this transfer's out-of-domain counter (batch-owned)
     int64_t n, E;
     int64_t row0;                  // first row in the concatenated solver vectors
     int32_t tile0, ntiles;         // this system's row tiles
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 2 ? 3 
         unsigned nf = 0, nood = 0;
         batch_elements<D, G, P>(x, tl.start, lane, nf, nood, c_af);
         if (nf) atomicAdd(nonfinite + tl.k, (unsigned long long)nf);
-        if (nood) atomicAdd(x.src_ood, (unsigned long long)nood);
+        if (nood) atomicAdd(x.ood, (unsigned long long)nood);
     }
 }
 
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict
             nood = eval_wave<2, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af);
         else
             nood = eval_wave<3, 2, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af);
-        if (nood) atomicAdd(x.src_ood, (unsigned long long)nood);
+        if (nood) atomicAdd(x.ood, (unsigned long long)nood);
     }
 }
 
@@ -435,7 +437,8 @@ struct ft_batch {
     double *B = nullptr, *Y = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
     double* part = nullptr;
     double* sc = nullptr;
-    unsigned long long* nonfinite = nullptr;
+    unsigned long long* nonfinite = nullptr;   // [2][count]: non-finite values, out-of-domain queries
+    std::vector<ft::BatchXfer> h_x;   // the descriptor table as last uploaded to d_x
     double** d_xs = nullptr;      // [2][count] pointer tables: x, then b
     double** h_xs = nullptr;      // pinned mirror
     double* h_sc = nullptr;       // pinned [count][BS_COUNT]
@@ -489,6 +492,30 @@ void batch_release(ft_batch* b) {
     if (b->h_nf) (void)hipHostFree(b->h_nf);
 }
 
+// The parts of a transfer's descriptor that point into its target and source.
+// They are read again before every run: a source's bins are rebuilt by
+// ft_source_autotune, and a target's field buffers are reallocated when a
+// transfer of more fields grows them.
+static void fill_live(ft_batch* b, int k, BatchXfer& x) {
+    ft_target* T = b->T[k];
+    ft_source* S = b->S[k];
+    x.src = source_view(S);
+    x.coords = T->coords;
+    x.conn = T->conn;
+    x.vol = T->vol;
+    x.inc_ptr = T->inc_ptr;
+    x.inc = T->inc;
+    x.rowptr = T->rowptr;
+    x.col = T->col;
+    x.val = T->val;
+    x.diag = T->diag;
+    x.lumped = T->lumped;
+    x.g = T->g;
+    x.beta = T->beta;
+    x.bres = T->bres;
+    x.ood = b->nonfinite + b->count + k;
+}
+
 static unsigned persistent_grid(int per_cu, int64_t waves) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
@@ -514,21 +541,7 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
         const ft_sample_cfg& c = b->cfg[k];
         FT_TRY(ensure_field_buffers(T, 1, s));
         BatchXfer& x = xs[k];
-        x.src = source_view(S);
-        x.coords = T->coords;
-        x.conn = T->conn;
-        x.vol = T->vol;
-        x.inc_ptr = T->inc_ptr;
-        x.inc = T->inc;
-        x.rowptr = T->rowptr;
-        x.col = T->col;
-        x.val = T->val;
-        x.diag = T->diag;
-        x.lumped = T->lumped;
-        x.g = T->g;
-        x.beta = T->beta;
-        x.bres = T->bres;
-        x.src_ood = S->counters;
+        (void)S;
         x.n = T->n;
         x.E = T->E;
         x.row0 = row0;
@@ -585,16 +598,18 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
     FT_TRY(dev_alloc_n(&b->P, size_t(2 * row0)));
     FT_TRY(dev_alloc_n(&b->part, size_t(row.size()) * BP_COUNT));
     FT_TRY(dev_alloc_n(&b->sc, size_t(K) * BS_COUNT));
-    FT_TRY(dev_alloc_n(&b->nonfinite, size_t(K)));
+    FT_TRY(dev_alloc_n(&b->nonfinite, size_t(2 * K)));
+    for (int k = 0; k < K; ++k) fill_live(b, k, xs[k]);
     FT_TRY(dev_alloc_n(&b->d_xs, size_t(2 * K)));
     FT_TRY_HIP(hipHostMalloc((void**)&b->h_xs, sizeof(double*) * 2 * K, hipHostMallocDefault));
     FT_TRY_HIP(hipHostMalloc((void**)&b->h_sc, sizeof(double) * BS_COUNT * K, hipHostMallocDefault));
-    FT_TRY_HIP(hipHostMalloc((void**)&b->h_nf, sizeof(unsigned long long) * K, hipHostMallocDefault));
+    FT_TRY_HIP(hipHostMalloc((void**)&b->h_nf, sizeof(unsigned long long) * 2 * K, hipHostMallocDefault));
     FT_TRY_HIP(hipMemcpyAsync(b->d_x, xs.data(), sizeof(BatchXfer) * K, hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipMemcpyAsync(b->d_elem, elem.data(), sizeof(Tile) * elem.size(), hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipMemcpyAsync(b->d_node, node.data(), sizeof(Tile) * node.size(), hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipMemcpyAsync(b->d_row, row.data(), sizeof(Tile) * row.size(), hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
+    b->h_x = xs;
     for (int i = 0; i < kCodes; ++i)
         b->code_grid[i] = persistent_grid(fused_per_cu(b->code_order[i]), b->code_first[i + 1] - b->code_first[i]);
     int node_per_cu = 0;
@@ -610,7 +625,7 @@ static ft_status enqueue_run(ft_batch* b, const ft_solve_cfg* cfg, hipStream_t s
     const int K = b->count;
     const unsigned nrt = unsigned(b->n_row_tiles);
     const int64_t rows = b->rows;
-    k_fill_u64<<<grid_for(K, 256), 256, 0, s>>>(b->nonfinite, K);
+    k_fill_u64<<<grid_for(2 * K, 256), 256, 0, s>>>(b->nonfinite, 2 * K);
     if (b->n_node_tiles) k_batch_nodes<<<b->grid_node, 256, 0, s>>>(b->d_x, b->d_node, b->n_node_tiles);
     for (int i = 0; i < kCodes; ++i)
         if (b->code_first[i + 1] > b->code_first[i])
@@ -639,6 +654,19 @@ static ft_status enqueue_run(ft_batch* b, const ft_solve_cfg* cfg, hipStream_t s
 ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec, ft_report* rep,
                     int32_t* status, hipStream_t s) {
     const int K = b->count;
+    // descriptors that point at memory a target or source has since replaced are
+    // refreshed (the kernels, and a captured graph, read the table at run time)
+    {
+        std::vector<BatchXfer> xs = b->h_x;
+        for (int k = 0; k < K; ++k) {
+            fill_live(b, k, xs[k]);
+            b->T[k]->fields_inner = false;   // the batch writes one field, [F][n] layout
+        }
+        if (std::memcmp(xs.data(), b->h_x.data(), sizeof(BatchXfer) * K) != 0) {
+            b->h_x = xs;
+            FT_TRY_HIP(hipMemcpyAsync(b->d_x, b->h_x.data(), sizeof(BatchXfer) * K, hipMemcpyHostToDevice, s));
+        }
+    }
     for (int k = 0; k < K; ++k) {
         b->h_xs[k] = x[k];
         b->h_xs[K + k] = bvec ? bvec[k] : nullptr;
@@ -670,7 +698,7 @@ ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, doub
         FT_TRY(enqueue_run(b, cfg, s));
     }
     FT_TRY_HIP(hipMemcpyAsync(b->h_sc, b->sc, sizeof(double) * BS_COUNT * K, hipMemcpyDeviceToHost, s));
-    FT_TRY_HIP(hipMemcpyAsync(b->h_nf, b->nonfinite, sizeof(unsigned long long) * K, hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipMemcpyAsync(b->h_nf, b->nonfinite, sizeof(unsigned long long) * 2 * K, hipMemcpyDeviceToHost, s));
     FT_TRY_HIP(hipStreamSynchronize(s));
     ft_status worst = FT_OK;
     for (int k = 0; k < K; ++k) {
@@ -683,6 +711,9 @@ ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, doub
         R.rel_resid = h[BS_BB] > 0.0 ? std::sqrt(h[BS_TRR] / h[BS_BB]) : std::sqrt(h[BS_TRR]);
         R.iters = int32_t(h[BS_ITERS]);
         R.n_nonfinite = int64_t(b->h_nf[k]);
+        R.n_out_of_domain = int64_t(b->h_nf[K + k]);
+        b->T[k]->ood_mode = 2;   // a later ft_project of this target reports the same count
+        b->T[k]->ood_host = R.n_out_of_domain;
         R.status = b->h_nf[k] ? FT_E_NONFINITE : (h[BS_DONE] != 0.0 ? FT_OK : FT_E_NOCONV);
         if (status) status[k] = R.status;
         if (R.status != FT_OK && (worst == FT_OK || R.status == FT_E_NONFINITE)) worst = ft_status(R.status);

@@ -240,7 +240,13 @@ struct ft_target {
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *y = nullptr, *b = nullptr;
     double* scal = nullptr;               // device scalars
     double* partials = nullptr;           // per-block partial sums
-    unsigned long long* counters = nullptr;  // [0] non-finite values seen by consume
+    // [0] non-finite values seen by the last consume; [1] out-of-domain queries of
+    // the last transfer from a built-in source, counted by its kernels
+    unsigned long long* counters = nullptr;
+    // where the report's out-of-domain count comes from: 0 unknown (black-box
+    // route), 1 counters[1], 2 the host value ood_host (a plan's fixed count)
+    int ood_mode = 0;
+    int64_t ood_host = 0;
     double* h_scal = nullptr;             // pinned host mirror
     // mixed-precision solve (binary32 inner PCG), allocated on first use
     float* val32 = nullptr;               // [nnz] binary32 copy of M
@@ -280,6 +286,15 @@ struct ft_source {
     int64_t* bin_ptr = nullptr; // [nbins+1]
     int32_t* bin_elems = nullptr;
     int64_t n_reg = 0;
-    unsigned long long* counters = nullptr;  // [0] out-of-domain points
+    double fast_tau = 1e-9;     // margin of the localization's fast selection test
+    unsigned long long* counters = nullptr;  // [0] out-of-domain points of ft_source_eval*
     unsigned long long* h_counters = nullptr;
 };
+
+namespace ft {
+// Out-of-domain queries of the target's last transfer for its report, from
+// its counters copied to the host: -1 when a caller's black box evaluated them.
+inline int64_t report_ood(const ft_target* T, const unsigned long long* cnt) {
+    return T->ood_mode == 1 ? int64_t(cnt[1]) : (T->ood_mode == 2 ? T->ood_host : int64_t(-1));
+}
+}  // namespace ft

@@ -37,10 +37,10 @@ void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n, const int32_
 }
 
 SrcView source_view(const ft_source* S);
-ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out, int64_t ld_out,
-                      int32_t* ids, hipStream_t s);
+ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
+                      int64_t ld_out, int32_t* ids, hipStream_t s, unsigned long long* ood);
 ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s);
-void zero_counter(unsigned long long* p, hipStream_t s);
+void zero_counters(unsigned long long* p, int n, hipStream_t s);
 
 template <int D, int G, int P, int FC>
 static void launch_fused(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
@@ -48,7 +48,7 @@ static void launch_fused(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, h
     const unsigned grid = grid_for(T->E * G, 256);
     k_fused_p1<D, G, P, FC><<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
                                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta,
-                                             T->counters, S->counters);
+                                             T->counters, T->counters + 1);
 }
 
 template <int D, int G, int P>
@@ -73,9 +73,11 @@ static void fused_g(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStr
 }
 
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
+    // non-finite values and out-of-domain queries of this transfer
+    zero_counters(T->counters, 2, s);
+    T->ood_mode = 1;
     // step 1: the control, f^s at the target nodes, straight into T->g
-    FT_TRY(source_eval(S, 0, T->n, T->coords, T->n, FT_F64, T->g, T->n, nullptr, s));
-    zero_counter(T->counters, s);
+    FT_TRY(source_eval(S, 0, T->n, T->coords, T->n, FT_F64, T->g, T->n, nullptr, s, T->counters + 1));
     if (T->dim == 2) fused_g<2>(T, S, cfg, s);
     else fused_g<3>(T, S, cfg, s);
     FT_TRY_HIP(hipGetLastError());

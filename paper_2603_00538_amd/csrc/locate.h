@@ -21,14 +21,19 @@
 // survivors fetch the element's absolute affine barycentric form, and park it
 // in the wave's LDS; every lane then tests its points against each survivor
 // in lane order (broadcast LDS reads).  The selection test accepts an element
-// once mu_1..mu_D and mu_0 = 1 - their sum all exceed 1e-9, far above the
-// rounding of that form, so an accepted element truly contains the point and
-// is the unique winner; a wave stops when all its points are accepted.
-// Points never accepted (within 1e-9 of a face, or outside) are re-searched
-// alone with the full rule over the bins that can hold their elements.  The
-// barycentrics used to interpolate are always recomputed from the element
-// origin.  Waves whose points need more than 64 bins (scattered input) search
-// point by point.  Each wave brings its own LDS slots (kWaveSlots<D> doubles).
+// once mu_1..mu_D and mu_0 = 1 - their sum all exceed the source's margin tau
+// (1e-9, or more for meshes whose affine forms carry large terms: tau bounds
+// the rounding of the form at any point of any element's box), so an
+// accepted element truly contains the point and is the unique winner; a wave
+// stops when all its points are accepted.  Points never accepted (within tau
+// of a face, or outside) are re-searched alone with the full rule over the
+// bins that can hold their elements; a point those bins leave outside the
+// domain (or without any candidate) takes the full rule over every element,
+// so the extrapolating element is the rule's winner however far out the
+// point lies.  The barycentrics used to interpolate are always recomputed
+// from the element origin.  Waves whose points need more than 64 bins
+// (scattered input) search point by point.  Each wave brings its own LDS
+// slots (kWaveSlots<D> doubles).
 #pragma once
 
 #include <cfloat>
@@ -38,7 +43,11 @@
 namespace ft {
 
 constexpr double kInsideTau = 1e-12;   // strictly inside (rule winner is unique)
-constexpr double kFastTau = 1e-9;      // accepted by the fast selection test (absolute affine form)
+constexpr double kFastTau = 1e-9;      // smallest margin of the fast selection test (absolute affine form)
+// The margin a source uses: kFastTau, or kFastTauUlps units of rounding of the
+// largest |c_k| + sum_c |g_kc x_c| over its elements' boxes when that is larger
+// (the form's value at a point is off by at most a few such units).
+constexpr double kFastTauUlps = 64.0 * 0x1p-53;
 constexpr double kOutTol = -1e-10;
 
 // Record of element e, rec[e*RS ...] (doubles; 128 B in 2D, 256 B in 3D):
@@ -116,6 +125,8 @@ struct SrcView {
     int64_t n;
     int F;
     GridView g;
+    int64_t E;        // elements (the whole-mesh search for points outside the domain)
+    double tau;       // margin of the fast selection test (>= kFastTau)
 };
 
 // Barycentric coordinates of p in the element of record r (origin x0 and the
@@ -155,9 +166,9 @@ __device__ __forceinline__ void test_candidate(const double* __restrict__ r, int
 // Fast selection test from a parked form in LDS (wave-uniform address: a
 // broadcast read).  The form holds the constants of mu_1..mu_D, then their
 // gradients (mu_0 = 1 - sum of the others): true when every mu_k exceeds
-// kFastTau at p, i.e. p lies inside the element with that margin.
+// tau at p, i.e. p lies inside the element with that margin.
 template <int D>
-__device__ __forceinline__ bool inside_lds(const double* af, const double (&p)[D]) {
+__device__ __forceinline__ bool inside_lds(const double* af, const double (&p)[D], double tau) {
     bool in = true;
     double s;
 #pragma unroll
@@ -165,10 +176,10 @@ __device__ __forceinline__ bool inside_lds(const double* af, const double (&p)[D
         double l = af[k];
 #pragma unroll
         for (int c = 0; c < D; ++c) l = fma(af[D + k * D + c], p[c], l);
-        in &= l > kFastTau;
+        in &= l > tau;
         s = k == 0 ? l : s + l;
     }
-    return in & (s < 1.0 - kFastTau);
+    return in & (s < 1.0 - tau);
 }
 
 // Own-bin search of one point with the full rule (absolute coordinates).
@@ -195,6 +206,14 @@ __device__ __forceinline__ void locate_point(const SrcView& S, const double (&p)
                     if (best > kInsideTau) return;   // strictly inside: the unique winner
                 }
             }
+    // outside the domain, or no candidate at all: the bins near p need not hold
+    // the rule's winner (for a point outside the mesh the maximizer of min mu
+    // can be any element), so every element is tested, in id order
+    if (bid == INT_MAX || best < kOutTol) {
+        best = -DBL_MAX;
+        bid = INT_MAX;
+        for (int64_t e = 0; e < S.E; ++e) test_candidate<D>(S.rec + e * RS, int(e), p, best, bid);
+    }
 }
 
 // LDS slots for the candidates' parked forms: 64 per wave, D(D+1) doubles
@@ -243,10 +262,10 @@ __device__ __forceinline__ int wave_prefix_max(int x) {
 
 // Rule winner for each of this lane's P points (see the file comment).  Every
 // lane of the wave must call it (points a lane does not own pass
-// active = false).  Returns bid = the winner's element id (INT_MAX if no
-// candidate was found) and best: 1 for points the fast test accepted (inside
-// their element with margin kFastTau), the full rule's max min-barycentric
-// for the others.
+// active = false).  Returns bid = the winner's element id (INT_MAX only for
+// inactive points) and best: 1 for points the fast test accepted (inside
+// their element with margin S.tau), the full rule's max min-barycentric for
+// the others.
 template <int D, int P>
 __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[P][D], const bool (&active)[P],
                                             double (&best)[P], int (&bid)[P], double* __restrict__ c_af) {
@@ -373,7 +392,7 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
                 uint64_t pending = 0;   // lanes with a point not yet accepted
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    const bool in = inside_lds<D>(a1, p[q]);
+                    const bool in = inside_lds<D>(a1, p[q], S.tau);
                     bid[q] = in ? e1 : bid[q];
                     pending |= __builtin_amdgcn_ballot_w64(bid[q] == INT_MAX);
                 }
@@ -384,7 +403,7 @@ __device__ __forceinline__ void locate_wave(const SrcView& S, const double (&p)[
             }
             __builtin_amdgcn_wave_barrier();
         }
-        // accepted points lie inside their element with margin kFastTau; the others
+        // accepted points lie inside their element with margin tau; the others
         // (near a face, or outside) take the full rule over the bins that can hold
         // their elements
 #pragma unroll

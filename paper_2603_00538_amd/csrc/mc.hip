@@ -293,91 +293,109 @@ ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipS
 constexpr int kConsumeRuns = 4;   // elements per wave when G == 64
 
 template <int D, int G, int FC, bool F32>
-static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, hipStream_t s) {
+static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, double* beta,
+                           hipStream_t s) {
     const SampleKey key = make_key(cfg);
     constexpr int R = G == 64 ? kConsumeRuns : 1;
     const unsigned grid = grid_for(T->E * G, 256 * R);
     k_consume<D, G, FC, F32, R><<<grid, 256, 0, s>>>(values, ld, cfg->n_fields, T->conn, T->vol, T->n,
                                                      uint32_t(T->E), uint32_t(cfg->samples_per_elem), cfg->alpha, key,
-                                                     T->beta, T->counters);
+                                                     beta, T->counters);
 }
 
 template <int D, int G, bool F32>
-static void consume_fc(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, hipStream_t s) {
+static void consume_fc(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, double* beta,
+                       hipStream_t s) {
     if (cfg->n_fields == 1)
-        launch_consume<D, G, 1, F32>(T, cfg, values, ld, s);
+        launch_consume<D, G, 1, F32>(T, cfg, values, ld, beta, s);
     else
-        launch_consume<D, G, 4, F32>(T, cfg, values, ld, s);
+        launch_consume<D, G, 4, F32>(T, cfg, values, ld, beta, s);
 }
 
 template <int D, bool F32>
-static void consume_g(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, hipStream_t s) {
+static void consume_g(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, double* beta,
+                      hipStream_t s) {
     const int N = cfg->samples_per_elem;
-    if (N >= 64) consume_fc<D, 64, F32>(T, cfg, values, ld, s);
-    else if (N > 16) consume_fc<D, 32, F32>(T, cfg, values, ld, s);
-    else if (N > 8) consume_fc<D, 16, F32>(T, cfg, values, ld, s);
-    else if (N > 4) consume_fc<D, 8, F32>(T, cfg, values, ld, s);
-    else if (N > 2) consume_fc<D, 4, F32>(T, cfg, values, ld, s);
-    else if (N > 1) consume_fc<D, 2, F32>(T, cfg, values, ld, s);
-    else consume_fc<D, 1, F32>(T, cfg, values, ld, s);
+    if (N >= 64) consume_fc<D, 64, F32>(T, cfg, values, ld, beta, s);
+    else if (N > 16) consume_fc<D, 32, F32>(T, cfg, values, ld, beta, s);
+    else if (N > 8) consume_fc<D, 16, F32>(T, cfg, values, ld, beta, s);
+    else if (N > 4) consume_fc<D, 8, F32>(T, cfg, values, ld, beta, s);
+    else if (N > 2) consume_fc<D, 4, F32>(T, cfg, values, ld, beta, s);
+    else if (N > 1) consume_fc<D, 2, F32>(T, cfg, values, ld, beta, s);
+    else consume_fc<D, 1, F32>(T, cfg, values, ld, beta, s);
 }
 
 void zero_counter(unsigned long long* p, hipStream_t s) {
     k_zero_u64<<<1, 64, 0, s>>>(p, 1);   // a kernel, not a memset: safe inside captured graphs
 }
 
+void zero_counters(unsigned long long* p, int n, hipStream_t s) { k_zero_u64<<<1, 64, 0, s>>>(p, n); }
+
 template <int D>
-static void launch_assemble(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s) {
+static void launch_assemble(ft_target* T, const double* beta, int F, const void* values, int64_t ld, bool f32,
+                            hipStream_t s) {
     if (f32)
-        k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
+        k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
                                                                ld, T->bres, T->g, T->counters);
     else
-        k_assemble<D, false><<<grid_for(T->n, 256), 256, 0, s>>>(T->beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
+        k_assemble<D, false><<<grid_for(T->n, 256), 256, 0, s>>>(beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
                                                                 ld, T->bres, T->g, T->counters);
 }
 
-ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s) {
-    if (T->dim == 2) launch_assemble<2>(T, F, values, ld, f32, s);
-    else launch_assemble<3>(T, F, values, ld, f32, s);
+static ft_status assemble_from(ft_target* T, const double* beta, int F, const void* values, int64_t ld, bool f32,
+                               hipStream_t s) {
+    if (T->dim == 2) launch_assemble<2>(T, beta, F, values, ld, f32, s);
+    else launch_assemble<3>(T, beta, F, values, ld, f32, s);
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
 }
 
-static ft_status assemble_fields_inner(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s) {
+ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s) {
+    return assemble_from(T, T->beta, F, values, ld, f32, s);
+}
+
+static ft_status assemble_fields_inner(ft_target* T, const double* beta, int F, const void* values, int64_t ld,
+                                       bool f32, hipStream_t s) {
     const unsigned grid = grid_for(T->n, 4);
     if (f32)
-        k_assemble_fi<true><<<grid, 256, 0, s>>>(T->beta, T->inc_ptr, T->inc, T->n, F, values, ld, T->bres, T->g,
+        k_assemble_fi<true><<<grid, 256, 0, s>>>(beta, T->inc_ptr, T->inc, T->n, F, values, ld, T->bres, T->g,
                                                  T->counters);
     else
-        k_assemble_fi<false><<<grid, 256, 0, s>>>(T->beta, T->inc_ptr, T->inc, T->n, F, values, ld, T->bres, T->g,
+        k_assemble_fi<false><<<grid, 256, 0, s>>>(beta, T->inc_ptr, T->inc, T->n, F, values, ld, T->bres, T->g,
                                                   T->counters);
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
 }
 
-ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s);
+ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s);
 constexpr int kMfmaMaxSamples = 256;   // the matrix-core form stages <= 256 samples
 constexpr int kMfmaMaxFields = 64;     // and <= 64 control values per vertex in LDS
 
 template <int D>
-static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
+static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta,
+                              hipStream_t s) {
     const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
     const bool f32 = cfg->precision != FT_F64;
     const bool split = cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16;
     zero_counter(T->counters, s);
+    T->ood_mode = 0;   // the caller's black box evaluated the points
     if (split && cfg->samples_per_elem <= kMfmaMaxSamples && cfg->n_fields <= kMfmaMaxFields) {
-        FT_TRY(consume_mfma(T, cfg, values, s));   // element loads fields-inner
+        FT_TRY(consume_mfma(T, cfg, values, beta, s));   // element loads fields-inner
         T->fields_inner = cfg->n_fields > 1;
-        return assemble_fields_inner(T, cfg->n_fields, values, ld, f32, s);
+        return assemble_fields_inner(T, beta, cfg->n_fields, values, ld, f32, s);
     }
-    if (f32) consume_g<D, true>(T, cfg, values, ld, s);
-    else consume_g<D, false>(T, cfg, values, ld, s);
+    if (f32) consume_g<D, true>(T, cfg, values, ld, beta, s);
+    else consume_g<D, false>(T, cfg, values, ld, beta, s);
     FT_TRY_HIP(hipGetLastError());
-    return assemble_residual(T, cfg->n_fields, values, ld, f32, s);
+    return assemble_from(T, beta, cfg->n_fields, values, ld, f32, s);
 }
 
-ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
-    return T->dim == 2 ? consume_impl<2>(T, cfg, values, s) : consume_impl<3>(T, cfg, values, s);
+// The element loads go to `beta` ([F][E][d+1], or [E][d+1][F] on the
+// many-field matrix-core route): the target's own buffer, or caller-provided
+// scratch of at least F E (d+1) doubles.  Only the element kernel and the
+// node assembly that follows it touch them.
+ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s) {
+    return T->dim == 2 ? consume_impl<2>(T, cfg, values, beta, s) : consume_impl<3>(T, cfg, values, beta, s);
 }
 
 }  // namespace ft

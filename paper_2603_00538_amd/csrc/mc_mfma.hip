@@ -190,7 +190,7 @@ __global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ v
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
 
-ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, hipStream_t s) {
+ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s) {
     const SampleKey key{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
     const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
     if (T->E == 0) return FT_OK;
@@ -201,14 +201,14 @@ ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* value
     const float a = float(cfg->alpha);
     if (T->dim == 2) {
         if (bf) k_consume_mfma<2, true><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
-                                                             uint32_t(T->E), N, a, key, T->beta, T->counters);
+                                                             uint32_t(T->E), N, a, key, beta, T->counters);
         else k_consume_mfma<2, false><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
-                                                           uint32_t(T->E), N, a, key, T->beta, T->counters);
+                                                           uint32_t(T->E), N, a, key, beta, T->counters);
     } else {
         if (bf) k_consume_mfma<3, true><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
-                                                             uint32_t(T->E), N, a, key, T->beta, T->counters);
+                                                             uint32_t(T->E), N, a, key, beta, T->counters);
         else k_consume_mfma<3, false><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
-                                                           uint32_t(T->E), N, a, key, T->beta, T->counters);
+                                                           uint32_t(T->E), N, a, key, beta, T->counters);
     }
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;

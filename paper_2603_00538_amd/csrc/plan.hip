@@ -22,9 +22,10 @@ namespace ft {
 
 SrcView source_view(const ft_source* S);
 ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
-                      int64_t ld_out, int32_t* ids, hipStream_t s);
+                      int64_t ld_out, int32_t* ids, hipStream_t s, unsigned long long* ood);
 ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s);
 void zero_counter(unsigned long long* p, hipStream_t s);
+void zero_counters(unsigned long long* p, int n, hipStream_t s);
 ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream);
 
 // setup: localize the samples of G-lane element groups, P per lane per round
@@ -197,6 +198,8 @@ struct ft_plan {
     ft_source* S = nullptr;
     ft_sample_cfg cfg{};
     int32_t* ids = nullptr;   // [n + E*N]
+    unsigned long long* ood = nullptr;   // out-of-domain queries found at setup (device)
+    int64_t n_ood = 0;                   // the same count on the host
 };
 
 namespace ft {
@@ -207,7 +210,7 @@ static void launch_locate(ft_plan* pl, hipStream_t s) {
     const SampleKey key{uint32_t(pl->cfg.seed & 0xFFFFFFFFu), uint32_t(pl->cfg.seed >> 32), pl->cfg.stream_id};
     k_plan_locate<D, G, P><<<grid_for(T->E * G, 256), 256, 0, s>>>(
         source_view(pl->S), T->coords, T->n, T->conn, uint32_t(T->E), uint32_t(pl->cfg.samples_per_elem), key,
-        pl->ids + T->n, pl->S->counters);
+        pl->ids + T->n, pl->ood);
 }
 
 template <int D>
@@ -224,11 +227,16 @@ ft_status plan_setup(ft_plan* pl, hipStream_t s) {
     ft_target* T = pl->T;
     const int64_t Q = T->n + T->E * int64_t(pl->cfg.samples_per_elem);
     FT_TRY(dev_alloc_n(&pl->ids, size_t(Q)));
-    FT_TRY(source_eval(pl->S, 0, T->n, T->coords, T->n, FT_F64, nullptr, T->n, pl->ids, s));
+    FT_TRY(dev_alloc_n(&pl->ood, 1));
+    zero_counters(pl->ood, 1, s);
+    FT_TRY(source_eval(pl->S, 0, T->n, T->coords, T->n, FT_F64, nullptr, T->n, pl->ids, s, pl->ood));
     if (T->dim == 2) locate_g<2>(pl, s);
     else locate_g<3>(pl, s);
     FT_TRY_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    FT_TRY_HIP(hipMemcpyAsync(&h, pl->ood, sizeof(h), hipMemcpyDeviceToHost, s));
     FT_TRY_HIP(hipStreamSynchronize(s));
+    pl->n_ood = int64_t(h);
     return FT_OK;
 }
 
@@ -269,6 +277,8 @@ ft_status plan_transfer(ft_plan* pl, const double* vals, hipStream_t s) {
     const double* v = vals ? vals : S->values;
     const int F = pl->cfg.n_fields;
     zero_counter(T->counters, s);
+    T->ood_mode = 2;   // the localization (and its out-of-domain count) was fixed at setup
+    T->ood_host = pl->n_ood;
     if (T->dim == 2) {
         k_plan_nodes<2><<<grid_for(T->n, 256), 256, 0, s>>>(S->rec, S->conn, v, S->n, F, T->coords, T->n, pl->ids,
                                                            T->g);
@@ -296,6 +306,7 @@ const ft_sample_cfg* plan_cfg(const ft_plan* p) { return &p->cfg; }
 void plan_delete(ft_plan* p) {
     if (!p) return;
     dev_free(p->ids);
+    dev_free(p->ood);
     delete p;
 }
 

@@ -27,18 +27,18 @@
 
 namespace ft {
 
-// b = alpha M g + b_res; partials of ||b||^2 and sum b.
+// b = alpha M g + b_res; partials of ||b||^2 and of sum b (compensated).
 __global__ __launch_bounds__(RB) void k_rhs(Mat A, const double* __restrict__ g, const double* __restrict__ bres,
                                             double alpha, double* __restrict__ b, double* __restrict__ part) {
-    double bb = 0.0, sb = 0.0;
+    double bb = 0.0, sb = 0.0, sbc = 0.0;
     FOR_ROW(i) {
         const double bi = alpha * csr_row(A.rowptr, A.col, A.val, g, i) + bres[i];
         b[i] = bi;
         bb = fma(bi, bi, bb);
-        sb += bi;
+        comp_add(sb, sbc, bi);
     }
     write_partial(part, P_BB, bb);
-    write_partial(part, P_SB, sb);
+    write_partial_comp(part, P_SB, sb, sbc);
 }
 
 // y = 0, r = b_res, z = D^-1 r, p_old = 0 (beta = 0 makes the first direction z);
@@ -139,25 +139,28 @@ __global__ __launch_bounds__(RB) void k_solution(int64_t n, const double* __rest
         x[i] = fma(alpha, g[i], y[i]);
 }
 
-// partials of the true residual ||b - M x||^2 and of m^T x
+// partials of the true residual ||b - M x||^2 and of m^T x (compensated: each
+// product m_i x_i is split exactly into its rounded value and error by an FMA)
 __global__ __launch_bounds__(RB) void k_report(Mat A, const double* __restrict__ b, const double* __restrict__ x,
                                                double* __restrict__ part) {
-    double trr = 0.0, mx = 0.0;
+    double trr = 0.0, mx = 0.0, mxc = 0.0;
     FOR_ROW(i) {
         const double ri = b[i] - csr_row(A.rowptr, A.col, A.val, x, i);
         trr = fma(ri, ri, trr);
-        mx = fma(A.lumped[i], x[i], mx);
+        const double pr = A.lumped[i] * x[i];
+        mxc += fma(A.lumped[i], x[i], -pr);
+        comp_add(mx, mxc, pr);
     }
     write_partial(part, P_TRR, trr);
-    write_partial(part, P_MX, mx);
+    write_partial_comp(part, P_MX, mx, mxc);
 }
 
 __global__ __launch_bounds__(RB) void k_report_totals(int nb, const double* __restrict__ part,
                                                       double* __restrict__ scal) {
     const double bb = partial_total(part, P_BB, nb);
-    const double sb = partial_total(part, P_SB, nb);
+    const double sb = partial_total_comp(part, P_SB, nb);
     const double trr = partial_total(part, P_TRR, nb);
-    const double mx = partial_total(part, P_MX, nb);
+    const double mx = partial_total_comp(part, P_MX, nb);
     if (threadIdx.x == 0) {
         scal[S_BB] = bb;
         scal[S_SUMB] = sb;
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(RB) void k_mx_totals(int mode, int nb, double rtol2
     const double rr = partial_total(part, P_RR, nb);
     if (mode == 0) {
         const double bb = partial_total(part, P_BB, nb);
-        const double sb = partial_total(part, P_SB, nb);
+        const double sb = partial_total_comp(part, P_SB, nb);
         if (threadIdx.x == 0) {
             scal[S_BB] = bb;
             scal[S_SUMB] = sb;
@@ -374,8 +377,8 @@ static ft_status project_mixed(ft_target* T, const ft_solve_cfg* cfg, double* x,
     float* p32 = z32 + n;   // two buffers
     float* q32 = p32 + 2 * n;
     float* d32 = q32 + n;
-    unsigned long long nonfinite = 0;
-    FT_TRY_HIP(hipMemcpyAsync(&nonfinite, T->counters, sizeof(nonfinite), hipMemcpyDeviceToHost, s));
+    unsigned long long cnt[2] = {0, 0};   // non-finite values, out-of-domain queries
+    FT_TRY_HIP(hipMemcpyAsync(cnt, T->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
     double* bf = b_out ? b_out : T->b;
     k_rhs<<<nb, RB, 0, s>>>(A, T->g, T->bres, alpha, bf, T->partials);
     k_mx_start<<<nb, RB, 0, s>>>(A, T->bres, T->y, T->r, T->partials);
@@ -427,9 +430,10 @@ static ft_status project_mixed(ft_target* T, const ft_solve_cfg* cfg, double* x,
     R.cons_defect = h[S_SUMB] != 0.0 ? std::fabs(h[S_INTX] - h[S_SUMB]) / std::fabs(h[S_SUMB]) : std::fabs(h[S_INTX]);
     R.rel_resid = h[S_BB] > 0.0 ? std::sqrt(h[S_TRR] / h[S_BB]) : std::sqrt(h[S_TRR]);
     R.iters = iters;
-    R.n_nonfinite = int64_t(nonfinite);
-    R.status = nonfinite ? FT_E_NONFINITE : (done ? FT_OK : FT_E_NOCONV);
-    if (R.status == FT_E_NONFINITE) set_error("%llu non-finite query value(s) were consumed", nonfinite);
+    R.n_nonfinite = int64_t(cnt[0]);
+    R.n_out_of_domain = report_ood(T, cnt);
+    R.status = cnt[0] ? FT_E_NONFINITE : (done ? FT_OK : FT_E_NOCONV);
+    if (R.status == FT_E_NONFINITE) set_error("%llu non-finite query value(s) were consumed", cnt[0]);
     else if (R.status == FT_E_NOCONV)
         set_error("refinement did not reach rtol=%g within %d steps", cfg->rtol, cfg->refine_steps);
     return ft_status(R.status);
@@ -450,9 +454,9 @@ ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_ou
     const int nb = T->reduce_blocks;
     Mat A{T->rowptr, T->col, T->val, T->diag, T->lumped, n};
     const double rtol2 = cfg->rtol * cfg->rtol;
-    // non-finite values seen by the last consume
-    unsigned long long nonfinite = 0;
-    FT_TRY_HIP(hipMemcpyAsync(&nonfinite, T->counters, sizeof(nonfinite), hipMemcpyDeviceToHost, s));
+    // non-finite values seen by the last consume, out-of-domain queries of the last transfer
+    unsigned long long cnt[2] = {0, 0};
+    FT_TRY_HIP(hipMemcpyAsync(cnt, T->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
     const double* gf = T->g;
     const double* bresf = T->bres;
     double* bf = b_out ? b_out : T->b;
@@ -497,11 +501,12 @@ ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_ou
     R.rel_resid = h[S_BB] > 0.0 ? std::sqrt(h[S_TRR] / h[S_BB]) : std::sqrt(h[S_TRR]);
     R.iters = int32_t(h[S_ITERS]);
     T->cg_hint[0] = R.iters;
-    R.n_nonfinite = int64_t(nonfinite);
+    R.n_nonfinite = int64_t(cnt[0]);
+    R.n_out_of_domain = report_ood(T, cnt);
     R.status = FT_OK;
-    if (nonfinite) R.status = FT_E_NONFINITE;
+    if (cnt[0]) R.status = FT_E_NONFINITE;
     else if (!done) R.status = FT_E_NOCONV;
-    if (R.status == FT_E_NONFINITE) set_error("%llu non-finite query value(s) were consumed", nonfinite);
+    if (R.status == FT_E_NONFINITE) set_error("%llu non-finite query value(s) were consumed", cnt[0]);
     else if (R.status == FT_E_NOCONV) set_error("CG did not reach rtol=%g within %d iterations", cfg->rtol, cfg->max_iter);
     return ft_status(R.status);
 }

@@ -343,8 +343,8 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
     double* part = T->mf_part;
     std::vector<double> h(size_t(SC_COUNT) * Fp);
 
-    unsigned long long nonfinite = 0;
-    FT_TRY_HIP(hipMemcpyAsync(&nonfinite, T->counters, sizeof(nonfinite), hipMemcpyDeviceToHost, s));
+    unsigned long long cnt[2] = {0, 0};   // non-finite values, out-of-domain queries
+    FT_TRY_HIP(hipMemcpyAsync(cnt, T->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
     const unsigned gt = grid_for(n * Fp, MB);
     if (T->fields_inner) {   // the control and residual loads are already node-major
         k_m_pad_in<<<gt, MB, 0, s>>>(T->g, n, F, Fp, G);
@@ -400,11 +400,12 @@ ft_status project_multi(ft_target* T, const ft_solve_cfg* cfg, double* x, double
         Rp.rel_resid = bb > 0.0 ? std::sqrt(h[SC_TRR * Fp + f] / bb) : std::sqrt(h[SC_TRR * Fp + f]);
         Rp.iters = int32_t(h[SC_ITERS * Fp + f]);
         T->cg_hint[2] = std::max(T->cg_hint[2], int(Rp.iters));
-        Rp.n_nonfinite = int64_t(nonfinite);
-        Rp.status = nonfinite ? FT_E_NONFINITE : (h[SC_DONE * Fp + f] != 0.0 ? FT_OK : FT_E_NOCONV);
+        Rp.n_nonfinite = int64_t(cnt[0]);
+        Rp.n_out_of_domain = report_ood(T, cnt);
+        Rp.status = cnt[0] ? FT_E_NONFINITE : (h[SC_DONE * Fp + f] != 0.0 ? FT_OK : FT_E_NOCONV);
         if (Rp.status != FT_OK && (worst == FT_OK || Rp.status == FT_E_NONFINITE)) worst = ft_status(Rp.status);
     }
-    if (worst == FT_E_NONFINITE) set_error("%llu non-finite query value(s) were consumed", nonfinite);
+    if (worst == FT_E_NONFINITE) set_error("%llu non-finite query value(s) were consumed", cnt[0]);
     else if (worst == FT_E_NOCONV) set_error("CG did not reach rtol=%g within %d iterations", cfg->rtol, cfg->max_iter);
     return worst;
 }

@@ -111,6 +111,7 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
 #pragma unroll
         for (int k = 0; k <= D; ++k) r[RecValues<D>::value + k] = values[v[k]];
     constexpr int BS = BoxSize<D>::value;
+    double xmax[D];   // largest |x_c| over the element's box
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         double lo = x[0][c], hi = x[0][c];
@@ -121,7 +122,19 @@ __global__ void k_src_geom(const double* __restrict__ X, int64_t n, const int32_
         }
         box[e * BS + c] = f32_down(lo);
         box[e * BS + D + c] = f32_up(hi);
+        xmax[c] = fmax(fabs(lo), fabs(hi));
     }
+    // largest term magnitude |c_k| + sum_c |g_kc x_c| of the absolute affine form
+    // over the box: it scales the rounding of the fast selection test
+    double mag = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double m = fabs(r[k]);
+#pragma unroll
+        for (int c = 0; c < D; ++c) m = fma(fabs(r[D + k * D + c]), xmax[c], m);
+        mag = fmax(mag, m);
+    }
+    atomicMax(&flags[2], (unsigned long long)__double_as_longlong(mag));
     constexpr int ND = Dirs<D>::n;
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
@@ -471,6 +484,9 @@ static ft_status build(ft_source* S, const double* coords, const int32_t* conn, 
         set_error("%llu degenerate source element(s): |det J| <= 1e-12 h^d", hf[1]);
         return FT_E_MESH;
     }
+    double mag = 0.0;
+    std::memcpy(&mag, &hf[2], sizeof(mag));
+    S->fast_tau = std::fmax(kFastTau, kFastTauUlps * mag);
     for (int c = 0; c < D; ++c) {
         S->dom_lo[c] = INFINITY;
         S->dom_hi[c] = -INFINITY;
@@ -495,7 +511,19 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
 }
 
 SrcView source_view(const ft_source* S) {
-    SrcView v{S->rec, S->box, S->conn, S->values, S->values_nm, S->bin_ptr, S->bin_elems, S->n, S->F, {}};
+    SrcView v;
+    std::memset(&v, 0, sizeof(v));   // padding too: batches compare views bytewise
+    v.rec = S->rec;
+    v.box = S->box;
+    v.conn = S->conn;
+    v.values = S->values;
+    v.values_nm = S->values_nm;
+    v.bin_ptr = S->bin_ptr;
+    v.bin_elems = S->bin_elems;
+    v.n = S->n;
+    v.F = S->F;
+    v.E = S->E;
+    v.tau = S->fast_tau;
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
         v.g.hx[c] = S->hx[c];
@@ -509,7 +537,7 @@ constexpr int kEvalWavesPerBlock = 1;
 
 template <int D>
 static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec,
-                             void* out, int64_t ld_out, int32_t* ids, hipStream_t s) {
+                             void* out, int64_t ld_out, int32_t* ids, unsigned long long* ood, hipStream_t s) {
     // points per lane: a wave covers 256 consecutive points in 2D, 128 in 3D
     // (one target element's samples at N = 256 / 128; fewer registers in 3D)
     constexpr int P = D == 2 ? 4 : 2;
@@ -521,15 +549,13 @@ static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const voi
     if (S->F > 1 && out) {   // many fields: the lanes interpolate over fields
         const unsigned gw = unsigned(waves);
         if (prec == FT_F64)
-            k_src_eval_many<D, P, false, false><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+            k_src_eval_many<D, P, false, false><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, ood);
         else
-            k_src_eval_many<D, P, true, true><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+            k_src_eval_many<D, P, true, true><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, ood);
     } else if (prec == FT_F64) {
-        k_src_eval<D, P, false, false, WPB>
-            <<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+        k_src_eval<D, P, false, false, WPB><<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, ood);
     } else {
-        k_src_eval<D, P, true, true, WPB>
-            <<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, S->counters);
+        k_src_eval<D, P, true, true, WPB><<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, ood);
     }
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
@@ -557,9 +583,10 @@ static ft_status autotune_impl(ft_source* S, int64_t head, int64_t npts, const v
     for (int c = 0; c < ncand && st == FT_OK; ++c) {
         st = build_bins<D>(S, none, double(cand[c]), s);
         if (st != FT_OK) break;
-        st = launch_eval<D>(S, head, npts, pts, ld, prec, out, npts, nullptr, s);
+        st = launch_eval<D>(S, head, npts, pts, ld, prec, out, npts, nullptr, S->counters, s);
         if (hipEventRecord(e0, s) != hipSuccess) st = FT_E_DEVICE;
-        for (int r = 0; r < 2 && st == FT_OK; ++r) st = launch_eval<D>(S, head, npts, pts, ld, prec, out, npts, nullptr, s);
+        for (int r = 0; r < 2 && st == FT_OK; ++r)
+            st = launch_eval<D>(S, head, npts, pts, ld, prec, out, npts, nullptr, S->counters, s);
         float ms = 0.0f;
         if (st == FT_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
@@ -586,11 +613,13 @@ ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* 
                        : autotune_impl<3>(S, head, npts, pts, ld, prec, ncand, cand, s);
 }
 
+// Out-of-domain points are counted into `ood` (the source's own counter when null).
 ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
-                      int64_t ld_out, int32_t* ids, hipStream_t s) {
+                      int64_t ld_out, int32_t* ids, hipStream_t s, unsigned long long* ood) {
     if (npts == 0) return FT_OK;
-    return S->dim == 2 ? launch_eval<2>(S, head, npts, pts, ld, prec, out, ld_out, ids, s)
-                       : launch_eval<3>(S, head, npts, pts, ld, prec, out, ld_out, ids, s);
+    if (!ood) ood = S->counters;
+    return S->dim == 2 ? launch_eval<2>(S, head, npts, pts, ld, prec, out, ld_out, ids, ood, s)
+                       : launch_eval<3>(S, head, npts, pts, ld, prec, out, ld_out, ids, ood, s);
 }
 
 ft_status source_release(ft_source* S) {

@@ -44,7 +44,7 @@ class SolveCfg(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("sum_b", ctypes.c_double), ("int_x", ctypes.c_double), ("cons_defect", ctypes.c_double),
                 ("rel_resid", ctypes.c_double), ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("n_nonfinite", ctypes.c_int64)]
+                ("n_nonfinite", ctypes.c_int64), ("n_out_of_domain", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
