@@ -171,6 +171,26 @@ ft_status ft_sample_points(ft_target* t, const ft_sample_cfg* cfg, void* points,
 ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void* values, hipStream_t stream);
 
 /*
+ * ft_consume_queries_noalloc - ft_consume_queries for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels and results
+ * (bitwise) as ft_consume_queries; it calls no allocation routine and does
+ * not synchronize.  The per-element loads (F * n_elems * (dim+1) binary64
+ * values, between the element kernel and the node assembly) live in a fixed
+ * 64 MiB device array of the library instead of the target: each GPU holds
+ * its own copy until the process ends, every call on a GPU shares it and
+ * leaves its contents behind, so calls that overlap on one GPU (any targets,
+ * any streams) race and must be ordered by the caller.  The control values
+ * and assembled loads go to the target's field buffers: a new target holds
+ * them for one field, and a larger field count needs one ft_consume_queries
+ * with that count first.
+ * Errors: FT_E_ARG (as ft_consume_queries; element loads larger than 64 MiB;
+ * n_fields above the target's field buffers), FT_E_ORDER, FT_E_UNSUPPORTED.
+ * Asynchronous on `stream` (which must belong to the current device).
+ */
+ft_status ft_consume_queries_noalloc(ft_target* t, const ft_sample_cfg* cfg, const void* values, hipStream_t stream);
+
+/*
  * ft_project - step 2 and step 7 of sec. 4.1 and the conservation report.
  * Several fields (F > 1, at most 64) are solved together by a batched PCG that
  * reads M once per iteration for all of them, each field with its own

@@ -34,6 +34,8 @@ ft_plan* plan_new(ft_target* T, ft_source* S, const ft_sample_cfg* cfg);
 void plan_delete(ft_plan* p);
 ft_target* plan_target(ft_plan* p);
 const ft_sample_cfg* plan_cfg(const ft_plan* p);
+size_t noalloc_scratch_bytes();
+ft_status noalloc_scratch(double** out);
 
 static void target_release(ft_target* T) {
     void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
@@ -123,7 +125,7 @@ ft_status ft_target_create(int32_t dim, int64_t n_nodes, const double* coords, i
     ft_status st = target_setup(T, coords, conn, stream);
     if (st == FT_OK) st = solver_alloc(T, stream);
     // one field's transfer buffers up front, so that a first one-field
-    // transfer needs no allocation
+    // transfer needs no allocation (ft_consume_queries_noalloc relies on it)
     if (st == FT_OK) st = ensure_field_buffers(T, 1, stream);
     if (st == FT_OK && hipStreamSynchronize(stream) != hipSuccess) {
         set_error("stream synchronization failed after setup");
@@ -192,6 +194,38 @@ ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void*
     FT_TRY(ensure_field_buffers(T, cfg->n_fields, stream));
     T->consumed = false;
     FT_TRY(consume_values(T, cfg, values, T->beta, stream));
+    T->consumed = true;
+    T->consumed_cfg = *cfg;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_consume_queries_noalloc(ft_target* t, const ft_sample_cfg* cfg, const void* values,
+                                     hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t, "target is null");
+    FT_TRY(check_sample_cfg(t, cfg));
+    FT_ARG_CHECK(values, "values is null");
+    auto* T = static_cast<ft_target_ext*>(t);
+    if (!T->sampled || !same_samples(T->sampled_cfg, *cfg)) {
+        set_error("consume needs a prior ft_sample_points with the same samples_per_elem, seed, stream_id and "
+                  "point precision");
+        return FT_E_ORDER;
+    }
+    const uint64_t need = uint64_t(cfg->n_fields) * uint64_t(T->E) * uint64_t(T->dim + 1) * sizeof(double);
+    FT_ARG_CHECK(need <= noalloc_scratch_bytes(),
+                 "the element loads of %d field(s) x %lld elements need %llu bytes; the scratch array holds %llu",
+                 cfg->n_fields, (long long)T->E, (unsigned long long)need,
+                 (unsigned long long)noalloc_scratch_bytes());
+    FT_ARG_CHECK(cfg->n_fields <= T->F_cap,
+                 "n_fields (%d) exceeds the %d field(s) the target holds buffers for (ft_consume_queries with "
+                 "that field count provisions them)", cfg->n_fields, T->F_cap);
+    double* scratch = nullptr;
+    FT_TRY(noalloc_scratch(&scratch));
+    T->fields_inner = false;   // the many-field route sets it again
+    T->consumed = false;
+    FT_TRY(consume_values(T, cfg, values, scratch, stream));
     T->consumed = true;
     T->consumed_cfg = *cfg;
     return FT_OK;

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
-            "ft_consume_queries", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval",
+            "ft_consume_queries", "ft_consume_queries_noalloc", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval",
             "ft_source_eval_queries", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_last_error"]
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
         "ft_query_count": (I64, [P, I32]),
         "ft_sample_points": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
         "ft_consume_queries": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
+        "ft_consume_queries_noalloc": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
         "ft_transfer_p1": (I32, [P, P, ctypes.POINTER(SampleCfg), P]),
         "ft_project": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P]),
         "ft_source_create_p1": (I32, [I32, I64, P, I64, P, I32, P, P, P, ctypes.POINTER(P)]),
@@ -144,6 +145,11 @@ def ft_sample_points(h, cfg: SampleCfg, points_ptr, stream):
 
 def ft_consume_queries(h, cfg: SampleCfg, values_ptr, stream):
     return _check(load().ft_consume_queries(h, ctypes.byref(cfg), values_ptr, stream), "ft_consume_queries")
+
+
+def ft_consume_queries_noalloc(h, cfg: SampleCfg, values_ptr, stream):
+    return _check(load().ft_consume_queries_noalloc(h, ctypes.byref(cfg), values_ptr, stream),
+                  "ft_consume_queries_noalloc")
 
 
 def ft_transfer_p1(h, src, cfg: SampleCfg, stream):
@@ -320,13 +326,15 @@ class Target:
         ft_sample_points(self.handle, cfg, _device_ptr(out, "points", (dt,)), current_stream())
         return out
 
-    def consume(self, cfg: SampleCfg, values):
+    def consume(self, cfg: SampleCfg, values, noalloc=False):
+        """ft_consume_queries, or ft_consume_queries_noalloc with noalloc=True."""
         torch = _torch()
         dt = torch.float64 if cfg.precision == FT_F64 else torch.float32
         Q = self.query_count(cfg.samples_per_elem)
         if values.numel() < cfg.n_fields * Q:
             raise ValueError(f"values hold {values.numel()} entries, need {cfg.n_fields * Q}")
-        ft_consume_queries(self.handle, cfg, _device_ptr(values, "values", (dt,)), current_stream())
+        fn = ft_consume_queries_noalloc if noalloc else ft_consume_queries
+        fn(self.handle, cfg, _device_ptr(values, "values", (dt,)), current_stream())
 
     def transfer_from(self, source, cfg: SampleCfg):
         """Fused steps 1 and 3-6 from a built-in Source (no query list in memory)."""
