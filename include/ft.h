@@ -294,6 +294,18 @@ typedef struct {
 
 ft_status ft_source_get_info(const ft_source* s, ft_source_info* info /* host */);
 
+/*
+ * ft_source_integral - the exact integral of each source field over the
+ * source mesh, the quantity a conservative transfer preserves (sec. 2, Eq.
+ * conservation; the relative conservation error of sec. 5.1 compares the
+ * transferred integral m^T x with it):
+ *     int f = sum_e |Omega_e| * (mean of f over e's vertices),
+ * summed with compensation (each addition's rounding error carried along).
+ *   integrals  host, [n_fields]
+ * Errors: FT_E_ARG, FT_E_OOM.  Synchronizes `stream`.
+ */
+ft_status ft_source_integral(ft_source* s, double* integrals, hipStream_t stream);
+
 /* Out-of-domain points seen by ft_source_eval and ft_source_eval_queries since
  * the last call (then reset); the transfer routes report theirs in
  * ft_report.n_out_of_domain.

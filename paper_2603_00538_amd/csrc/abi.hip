@@ -17,6 +17,7 @@ ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, 
 ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, void* out,
                       int64_t ld_out, int32_t* ids, hipStream_t s, unsigned long long* ood);
 ft_status source_release(ft_source* S);
+ft_status source_integral(ft_source* S, double* out, hipStream_t s);
 ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, int ncand,
                           const int32_t* cand, hipStream_t s);
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s);
@@ -464,6 +465,14 @@ ft_status ft_source_get_info(const ft_source* s, ft_source_info* info) {
     for (int c = 0; c < 3; ++c) info->bins[c] = s->nb[c];
     info->n_registrations = s->n_reg;
     return FT_OK;
+}
+
+ft_status ft_source_integral(ft_source* s, double* integrals, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(s && integrals, "null argument");
+    return source_integral(s, integrals, stream);
+    FT_GUARD_END
 }
 
 ft_status ft_source_stats(ft_source* s, int64_t* n_out_of_domain, hipStream_t stream) {

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "locate.h"
+#include "solve_common.h"
 
 namespace ft {
 
@@ -620,6 +621,81 @@ ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts,
     if (!ood) ood = S->counters;
     return S->dim == 2 ? launch_eval<2>(S, head, npts, pts, ld, prec, out, ld_out, ids, ood, s)
                        : launch_eval<3>(S, head, npts, pts, ld, prec, out, ld_out, ids, ood, s);
+}
+
+// Exact integral of each P1 field over the source mesh (sec. 2, Eq.
+// conservation: the quantity a conservative transfer preserves):
+//   int f = sum_e |Omega_e| (sum of e's vertex values) / (d + 1),
+// |Omega_e| = |det J_e| / d!.  Compensated sums per block, pairs [F][nb][2].
+template <int D>
+__global__ __launch_bounds__(RB) void k_src_integral(const double* __restrict__ X, int64_t n,
+                                                     const int32_t* __restrict__ conn, int64_t E,
+                                                     const double* __restrict__ values, int F,
+                                                     double* __restrict__ part) {
+    for (int f = 0; f < F; ++f) {
+        double s = 0.0, c = 0.0;
+        for (int64_t e = int64_t(blockIdx.x) * RB + threadIdx.x; e < E; e += int64_t(gridDim.x) * RB) {
+            int v[D + 1];
+            double x[D + 1][D], vs = 0.0;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) {
+                v[k] = conn[e * (D + 1) + k];
+                vs += values[int64_t(f) * n + v[k]];
+#pragma unroll
+                for (int cc = 0; cc < D; ++cc) x[k][cc] = X[cc * n + v[k]];
+            }
+            double det;
+            if constexpr (D == 2) {
+                det = (x[1][0] - x[0][0]) * (x[2][1] - x[0][1]) - (x[2][0] - x[0][0]) * (x[1][1] - x[0][1]);
+            } else {
+                double J[3][3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) J[a][b] = x[b + 1][a] - x[0][a];
+                det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            }
+            const double vol = fabs(det) / (D == 2 ? 2.0 : 6.0);
+            comp_add(s, c, vol * vs / double(D + 1));
+        }
+        block_total_comp(s, c);
+        if (threadIdx.x == 0) {
+            part[(int64_t(f) * gridDim.x + blockIdx.x) * 2] = s;
+            part[(int64_t(f) * gridDim.x + blockIdx.x) * 2 + 1] = c;
+        }
+    }
+}
+
+ft_status source_integral(ft_source* S, double* out, hipStream_t s) {
+    const int nb = int(std::min<int64_t>(256, (S->E + RB - 1) / RB));
+    double* part = nullptr;
+    ScratchGuard guard;
+    guard.add((void**)&part);
+    FT_TRY(dev_alloc_n(&part, size_t(S->F) * nb * 2));
+    if (S->dim == 2)
+        k_src_integral<2><<<nb, RB, 0, s>>>(S->coords, S->n, S->conn, S->E, S->values, S->F, part);
+    else
+        k_src_integral<3><<<nb, RB, 0, s>>>(S->coords, S->n, S->conn, S->E, S->values, S->F, part);
+    FT_TRY_HIP(hipGetLastError());
+    std::vector<double> h(size_t(S->F) * nb * 2);
+    FT_TRY_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    for (int f = 0; f < S->F; ++f) {
+        // the block pairs, added with the same compensation on the host
+        double sum = 0.0, c = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const double x = h[(size_t(f) * nb + b) * 2];
+            const double t = sum + x;
+            const double bp = t - sum;
+            c += (sum - (t - bp)) + (x - bp);
+            sum = t;
+            c += h[(size_t(f) * nb + b) * 2 + 1];
+        }
+        out[f] = sum + c;
+    }
+    return FT_OK;
 }
 
 ft_status source_release(ft_source* S) {

@@ -29,7 +29,7 @@ EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_q
             "ft_consume_queries", "ft_consume_queries_noalloc", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval",
             "ft_source_eval_queries", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
-            "ft_source_destroy", "ft_source_get_info", "ft_last_error"]
+            "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_last_error"]
 
 
 class SampleCfg(ctypes.Structure):
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "ft_source_stats": (I32, [P, ctypes.POINTER(I64), P]),
         "ft_source_destroy": (I32, [P]),
         "ft_source_get_info": (I32, [P, ctypes.POINTER(SourceInfo)]),
+        "ft_source_integral": (I32, [P, ctypes.POINTER(D), P]),
         "ft_batch_create": (I32, [I32, P, P, ctypes.POINTER(SampleCfg), I32, P, ctypes.POINTER(P)]),
         "ft_batch_run": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P, P]),
         "ft_batch_destroy": (I32, [P]),
@@ -236,6 +237,12 @@ def ft_source_stats(h, stream):
 
 def ft_source_destroy(h):
     return load().ft_source_destroy(h)
+
+
+def ft_source_integral(h, n_fields, stream):
+    out = (ctypes.c_double * n_fields)()
+    _check(load().ft_source_integral(h, out, stream), "ft_source_integral")
+    return list(out)
 
 
 def ft_source_get_info(h) -> SourceInfo:
@@ -440,6 +447,10 @@ class Source:
     @property
     def info(self):
         return ft_source_get_info(self.handle)
+
+    def integral(self):
+        """Exact integral of each field over the source mesh (ft_source_integral)."""
+        return ft_source_integral(self.handle, self.n_fields, current_stream())
 
     def take_out_of_domain(self):
         return ft_source_stats(self.handle, current_stream())

@@ -271,3 +271,26 @@ def test_report_sums_are_compensated(dim):
     assert abs(rep["int_x"] - exact_x) <= 1e-15 * abs(exact_x)
     T.close()
     S.close()
+
+
+@pytest.mark.parametrize("dim,F", [(2, 1), (3, 1), (3, 5)])
+def test_source_integral_matches_oracle(dim, F):
+    """ft_source_integral against the oracle's exact integral, and against
+    the closed form for an affine field (c0 + c . x over the unit square /
+    cube integrates to c0 + sum(c) / 2)."""
+    _, sm = _mesh_pair(dim)
+    if F == 1:
+        sv = _field(dim, sm[0])
+    else:
+        modes = fields.fourier_modes(seed=5, n_fields=F, n_modes=3, kmax=2)
+        sv = fields.fourier_fields_3d(np, sm[0][:, 0], sm[0][:, 1], sm[0][:, 2], modes) + 1.0
+    S = ft.Source(*sm, np.ascontiguousarray(sv))
+    got = np.array(S.integral())
+    ref = P1Source(*sm, sv).integral()
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+    S.close()
+    va = fields.evaluate("affine", np, sm[0])
+    S = ft.Source(*sm, va)
+    c0, c = 1.25, (0.75, -2.0, 0.5)
+    assert abs(S.integral()[0] - (c0 + 0.5 * sum(c[:dim]))) < 1e-14
+    S.close()
