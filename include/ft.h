@@ -223,6 +223,26 @@ ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b
 ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, hipStream_t stream);
 
 /*
+ * ft_transfer_supermesh - the exact load vector b_i = integral f^s psi_i of
+ * the built-in P1 source, by mesh intersection (sec. 3): every target
+ * element is intersected with every source element that meets it (the
+ * candidates come from the source's bin grid), each convex intersection
+ * polygon is split into triangles fanned from its first vertex and
+ * integrated with the degree-2 Gauss rule, which is exact for the quadratic
+ * f^s psi_i there.  The reference the Monte Carlo estimate converges to, and
+ * the paper's intersection-based comparator.  Follow with ft_project, which
+ * then solves M x = b with no control part (alpha = 0, start x = 0);
+ * ft_report.n_out_of_domain counts the target elements the source does not
+ * cover entirely.  Triangles only (FT_E_UNSUPPORTED in 3D), at most 4
+ * fields.
+ *   area   device, binary64, [n_elems] or null: per target element, the sum
+ *          of the areas of its intersections (= |Omega_t| where the source
+ *          covers it)
+ * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Asynchronous on `stream`.
+ */
+ft_status ft_transfer_supermesh(ft_target* t, ft_source* s, double* area, hipStream_t stream);
+
+/*
  * ft_source_create_p1 - a P1 field on a source mesh, evaluated at points by
  * uniform-grid localization (sec. 5.3: grid cells per axis int(L sqrt(#elements))).
  *   coords         device, binary64, [dim][n_nodes]

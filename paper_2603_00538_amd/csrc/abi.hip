@@ -21,6 +21,7 @@ ft_status source_integral(ft_source* S, double* out, hipStream_t s);
 ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, int ncand,
                           const int32_t* cand, hipStream_t s);
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s);
+ft_status transfer_supermesh(ft_target* T, ft_source* S, double* area, hipStream_t s);
 ft_status batch_setup(ft_batch* b, hipStream_t s);
 ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec, ft_report* rep,
                     int32_t* status, hipStream_t s);
@@ -250,6 +251,29 @@ ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
     FT_TRY(transfer_p1(t, s, cfg, stream));
     t->consumed = true;
     t->consumed_cfg = *cfg;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_transfer_supermesh(ft_target* t, ft_source* s, double* area, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t && s, "target and source must be non-null");
+    FT_ARG_CHECK(s->dim == t->dim, "source dimension %d differs from target dimension %d", s->dim, t->dim);
+    if (t->dim != 2 || s->F > 4) {
+        set_error("the intersection route supports triangles and at most 4 fields");
+        return FT_E_UNSUPPORTED;
+    }
+    FT_TRY(ensure_field_buffers(t, s->F, stream));
+    t->consumed = false;
+    FT_TRY(transfer_supermesh(t, s, area, stream));
+    ft_sample_cfg c{};
+    c.samples_per_elem = 0;
+    c.n_fields = s->F;
+    c.alpha = 0.0;   // exact load vector: no control part
+    c.precision = FT_F64;
+    t->consumed = true;
+    t->consumed_cfg = c;
     return FT_OK;
     FT_GUARD_END
 }

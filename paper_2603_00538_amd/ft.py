@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
-            "ft_consume_queries", "ft_consume_queries_noalloc", "ft_transfer_p1", "ft_project", "ft_source_create_p1", "ft_source_eval",
+            "ft_consume_queries", "ft_consume_queries_noalloc", "ft_transfer_p1",
+            "ft_transfer_supermesh", "ft_project", "ft_source_create_p1", "ft_source_eval",
             "ft_source_eval_queries", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_last_error"]
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
         "ft_consume_queries": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
         "ft_consume_queries_noalloc": (I32, [P, ctypes.POINTER(SampleCfg), P, P]),
         "ft_transfer_p1": (I32, [P, P, ctypes.POINTER(SampleCfg), P]),
+        "ft_transfer_supermesh": (I32, [P, P, P, P]),
         "ft_project": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P]),
         "ft_source_create_p1": (I32, [I32, I64, P, I64, P, I32, P, P, P, ctypes.POINTER(P)]),
         "ft_source_eval": (I32, [P, I64, P, I64, I32, P, I64, P, P]),
@@ -155,6 +157,10 @@ def ft_consume_queries_noalloc(h, cfg: SampleCfg, values_ptr, stream):
 
 def ft_transfer_p1(h, src, cfg: SampleCfg, stream):
     return _check(load().ft_transfer_p1(h, src, ctypes.byref(cfg), stream), "ft_transfer_p1")
+
+
+def ft_transfer_supermesh(h, src, area_ptr, stream):
+    return _check(load().ft_transfer_supermesh(h, src, area_ptr, stream), "ft_transfer_supermesh")
 
 
 def ft_project(h, cfg: SolveCfg, x_ptr, b_ptr, n_fields, stream, allow=(FT_E_NOCONV, FT_E_NONFINITE)):
@@ -346,6 +352,18 @@ class Target:
     def transfer_from(self, source, cfg: SampleCfg):
         """Fused steps 1 and 3-6 from a built-in Source (no query list in memory)."""
         ft_transfer_p1(self.handle, source.handle, cfg, current_stream())
+
+    def transfer_supermesh(self, source, area=None):
+        """Exact load vector by mesh intersection (ft_transfer_supermesh); returns
+        the per-element intersection areas when area=True."""
+        torch = _torch()
+        out = None
+        if area:
+            out = torch.empty(self.n_elems, dtype=torch.float64, device=self.coords.device)
+        ft_transfer_supermesh(self.handle, source.handle,
+                              _device_ptr(out, "area", (torch.float64,)) if out is not None else None,
+                              current_stream())
+        return out
 
     def project(self, n_fields=1, rtol=1e-14, max_iter=500, want_b=True, x=None, b=None, refine_steps=0):
         torch = _torch()
