@@ -67,10 +67,10 @@ def control_load(coords: np.ndarray, conn: np.ndarray, g: np.ndarray, alpha: flo
     return b
 
 
-def query_points(coords, conn, n_samples, seed, stream, elems=None):
+def query_points(coords, conn, n_samples, seed, stream, elems=None, stratified=False):
     """Step 3: samples of the given elements as (E', N, d) physical points."""
     dim = coords.shape[1]
-    lam = sampling.element_samples(dim, conn.shape[0], n_samples, seed, stream, elems)
+    lam = sampling.element_samples(dim, conn.shape[0], n_samples, seed, stream, elems, stratified)
     return lam, sampling.physical_points(coords, conn, lam, elems)
 
 
@@ -131,7 +131,7 @@ def jacobi_cg(M: sp.csr_matrix, b: np.ndarray, rtol: float, max_iter: int = 500)
     return x
 
 
-def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_elems=20_000):
+def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_elems=20_000, stratified=False):
     """Whole CV-MC transfer of a black-box ``query`` (points (n, d) -> values (F, n)).
 
     Returns a dict with g, b_g, b_res, b, x, the mass matrix, lumped mass and
@@ -147,7 +147,7 @@ def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_
     beta = np.empty((F, E, dim + 1))
     for s in range(0, E, chunk_elems):
         el = np.arange(s, min(E, s + chunk_elems))
-        lam, X = query_points(coords, conn, n_samples, seed, stream, el)      # step 3
+        lam, X = query_points(coords, conn, n_samples, seed, stream, el, stratified)   # step 3
         y = np.atleast_2d(query(X.reshape(-1, dim))).reshape(F, el.size, n_samples)  # step 4
         beta[:, el] = element_loads(coords, conn, g, y, lam, alpha, el)      # step 5
     b_res = assemble(conn, beta, n)                                  # step 6

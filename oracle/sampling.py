@@ -19,8 +19,23 @@ element index, j the sample index within the element.
   3D: blk 0 words (0,1) -> u1, words (2,3) -> u2; blk 1 words (0,1) -> u3.
 lambda_k multiplies vertex k of the element in connectivity order.
 
+Stratified (jittered) variant, a reading of the paper's suggestion of
+better sampling schemes (sec. 7): the d' uniforms of a sample (d' = 2 for
+triangles, 3 for tetrahedra) are stratified over the unit cube before the
+same maps.  With m = floor(N^(1/d')) cells per axis, sample j < m^d' of an
+element takes cell j (digits c_i = floor(j / m^i) mod m, lowest first) and
+u_i <- min((c_i + u_i) * (1/m), 1 - 2^-53), the same Philox uniform u_i
+placed in that cell; samples j >= m^d' stay plain.  Both maps are
+measure-preserving from the unit cube onto the simplex (the spacings map is
+6-to-1), so each sample is uniform on the image of its cell, the cells have
+equal volume, and the estimator stays unbiased; each element's first m^d'
+samples cover all cells once.  1/m is rounded once and the clamp keeps the
+result in (0, 1): the GPU computes the same expression in the same order.
+
 Parity: pinned by closed-form simplex moments and an equal-volume chi-square
-test (uniformity), plus exactness of the affine identity sum(lambda) = 1.
+test (uniformity), plus exactness of the affine identity sum(lambda) = 1;
+the stratified variant by its one-sample-per-cell structure (exact), the
+same moments, unbiased estimates and a smaller variance than plain sampling.
 """
 from __future__ import annotations
 
@@ -43,6 +58,32 @@ def uniforms(dim: int, t: np.ndarray, j: np.ndarray, seed: int, stream: int):
     return np.stack(u, axis=1)
 
 
+def strata_per_axis(dim: int, n_samples: int) -> int:
+    """m = floor(N^(1/d')) with d' = dim uniforms per sample (2 or 3), exactly."""
+    dp = 2 if dim == 2 else 3
+    m = max(1, int(round(n_samples ** (1.0 / dp))))
+    while m ** dp > n_samples:
+        m -= 1
+    while (m + 1) ** dp <= n_samples:
+        m += 1
+    return m
+
+
+def stratify(dim: int, u: np.ndarray, j: np.ndarray, n_samples: int) -> np.ndarray:
+    """Place the uniforms of samples j < m^d' in their cells (see the module text)."""
+    m = strata_per_axis(dim, n_samples)
+    dp = u.shape[1]
+    inv_m = 1.0 / m
+    j = np.asarray(j, dtype=np.int64)
+    out = u.copy()
+    strat = j < m ** dp
+    for i in range(dp):
+        cell = (j // m ** i) % m
+        v = np.minimum((cell.astype(np.float64) + u[:, i]) * inv_m, 1.0 - 2.0 ** -53)
+        out[:, i] = np.where(strat, v, u[:, i])
+    return out
+
+
 def barycentric_from_uniforms(dim: int, u: np.ndarray) -> np.ndarray:
     """Map d uniforms to d+1 barycentric weights, uniform on the simplex."""
     if dim == 2:
@@ -57,14 +98,17 @@ def barycentric_from_uniforms(dim: int, u: np.ndarray) -> np.ndarray:
 
 
 def element_samples(dim: int, n_elems: int, n_samples: int, seed: int, stream: int,
-                    elems: np.ndarray | None = None) -> np.ndarray:
+                    elems: np.ndarray | None = None, stratified: bool = False) -> np.ndarray:
     """Barycentric weights of every sample of the given elements, shape (len(elems), N, d+1)."""
     if elems is None:
         elems = np.arange(n_elems)
     elems = np.asarray(elems)
     t = np.repeat(elems, n_samples)
     j = np.tile(np.arange(n_samples), elems.size)
-    lam = barycentric_from_uniforms(dim, uniforms(dim, t, j, seed, stream))
+    u = uniforms(dim, t, j, seed, stream)
+    if stratified:
+        u = stratify(dim, u, j, n_samples)
+    lam = barycentric_from_uniforms(dim, u)
     return lam.reshape(elems.size, n_samples, dim + 1)
 
 
