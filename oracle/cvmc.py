@@ -91,6 +91,46 @@ def element_loads(coords, conn, g, y, lam, alpha, elems=None):
     return beta * (vol / n_samples)[None, :, None]
 
 
+ALPHA_ELEMENT_RANGE = (0.0, 2.0)
+
+
+def element_loads_own_alpha(coords, conn, g, y, lam, elems=None):
+    """Step 5 with each element's own control coefficient (reading: sec. 4.1
+    leaves alpha free and sec. 5.1 shows the error depends on it; the
+    coefficient that minimizes the sample variance of the residual terms
+    (f^s - alpha g) psi_k summed over k is the classic control-variate one).
+
+    With A_k = sum_j y_j l_jk, B_k = sum_j g_j l_jk, P = sum_j y_j g_j w_j,
+    Q = sum_j g_j^2 w_j and w_j = sum_k l_jk^2 (g_j = g(X_tj)):
+        alpha_t = (P/N - sum_k A_k B_k / N^2) / (Q/N - sum_k B_k^2 / N^2),
+    clipped to ALPHA_ELEMENT_RANGE (1 when the denominator is not positive);
+    then the element load includes its exact control part,
+        beta_tk = alpha_t (M_t g_t)_k + |Omega_t| / N (A_k - alpha_t B_k),
+    (M_t g_t)_k = |Omega_t| (sum_l g_l + g_k) / ((d+1)(d+2)).
+    Returns (beta (F, E', d+1), alpha (F, E')).
+    """
+    if elems is None:
+        elems = np.arange(conn.shape[0])
+    dim = coords.shape[1]
+    vol = geometry.element_measures(coords, conn[elems])
+    N = lam.shape[1]
+    gv = g[:, conn[elems]]                                           # (F, E', d+1) nodal control values
+    g_at = np.einsum("tjk,ftk->ftj", lam, gv)                        # g(X_tj)
+    w = (lam * lam).sum(axis=2)                                      # (E', N)
+    A = neumaier_sum(y[..., None] * lam[None], axis=2)               # (F, E', d+1)
+    B = neumaier_sum(g_at[..., None] * lam[None], axis=2)
+    P = neumaier_sum(y * g_at * w[None], axis=2)                     # (F, E')
+    Q = neumaier_sum(g_at * g_at * w[None], axis=2)
+    num = P / N - (A * B).sum(axis=2) / N ** 2
+    den = Q / N - (B * B).sum(axis=2) / N ** 2
+    ok = np.isfinite(num) & np.isfinite(den) & (den > 0)
+    alpha = np.where(ok, num / np.where(ok, den, 1.0), 1.0)
+    alpha = np.clip(alpha, *ALPHA_ELEMENT_RANGE)
+    control = vol[None, :, None] * (gv.sum(axis=2, keepdims=True) + gv) / ((dim + 1) * (dim + 2))
+    beta = alpha[..., None] * control + (vol / N)[None, :, None] * (A - alpha[..., None] * B)
+    return beta, alpha
+
+
 def assemble(conn: np.ndarray, beta: np.ndarray, n_nodes: int) -> np.ndarray:
     """Step 6 (residual part): b_res,v = sum of beta over (element, local vertex) at v."""
     b = np.zeros((beta.shape[0], n_nodes))
@@ -131,9 +171,12 @@ def jacobi_cg(M: sp.csr_matrix, b: np.ndarray, rtol: float, max_iter: int = 500)
     return x
 
 
-def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_elems=20_000, stratified=False):
+def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_elems=20_000, stratified=False,
+             own_alpha=False):
     """Whole CV-MC transfer of a black-box ``query`` (points (n, d) -> values (F, n)).
 
+    own_alpha: each element's own control coefficient (element_loads_own_alpha);
+    the control part is then inside the element loads and b_g is zero.
     Returns a dict with g, b_g, b_res, b, x, the mass matrix, lumped mass and
     the conservation report.
     """
@@ -143,13 +186,17 @@ def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_
     n, E = coords.shape[0], conn.shape[0]
     g = np.atleast_2d(query(coords))                                 # step 1
     F = g.shape[0]
-    b_g = control_load(coords, conn, g, alpha)                       # step 2
+    b_g = control_load(coords, conn, g, 0.0 if own_alpha else alpha)   # step 2
     beta = np.empty((F, E, dim + 1))
+    alphas = np.empty((F, E)) if own_alpha else None
     for s in range(0, E, chunk_elems):
         el = np.arange(s, min(E, s + chunk_elems))
         lam, X = query_points(coords, conn, n_samples, seed, stream, el, stratified)   # step 3
         y = np.atleast_2d(query(X.reshape(-1, dim))).reshape(F, el.size, n_samples)  # step 4
-        beta[:, el] = element_loads(coords, conn, g, y, lam, alpha, el)      # step 5
+        if own_alpha:                                                                  # step 5
+            beta[:, el], alphas[:, el] = element_loads_own_alpha(coords, conn, g, y, lam, el)
+        else:
+            beta[:, el] = element_loads(coords, conn, g, y, lam, alpha, el)
     b_res = assemble(conn, beta, n)                                  # step 6
     b = b_g + b_res
     M = geometry.mass_matrix(coords, conn)
@@ -157,7 +204,7 @@ def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_
     m = geometry.lumped_mass(coords, conn)
     return {
         "g": g, "b_g": b_g, "beta": beta, "b_res": b_res, "b": b, "x": x,
-        "M": M, "m": m, "report": conservation_report(b, x, m),
+        "M": M, "m": m, "report": conservation_report(b, x, m), "alpha_elements": alphas,
     }
 
 

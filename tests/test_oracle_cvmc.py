@@ -288,3 +288,70 @@ def test_stratified_estimator_unbiased_and_smaller_variance(sm_case):
         assert rms[True, N] < 0.7 * rms[False, N]
     slope = np.polyfit(np.log([16, 64, 256]), np.log([rms[True, N] for N in (16, 64, 256)]), 1)[0]
     assert slope < -0.8
+
+
+# ---- each element's own control coefficient ---------------------------------------------
+def _dirichlet_moment(a):
+    """E[prod l_k^a_k] for the uniform distribution on the triangle: 2! prod a_k! / (2 + sum a)!."""
+    return 2 * math.prod(math.factorial(x) for x in a) / math.factorial(2 + sum(a))
+
+
+def test_own_alpha_estimates_closed_form_coefficient():
+    """One reference triangle, f = x^2 (x = l_1), so g = l_1 and y = l_1^2.  The
+    variance-minimizing coefficient sum_k Cov(y l_k, g l_k) / sum_k Var(g l_k)
+    follows from the Dirichlet moments; the estimate from N = 200000 samples
+    must agree to within its sampling error."""
+    from oracle import sampling
+
+    e = lambda *a: _dirichlet_moment(a)   # noqa: E731
+    unit = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    # E[y g l_k^2] summed over k, y g = l_1^3
+    num = sum(e(*(u0 + 2 * uk for u0, uk in zip((0, 3, 0), u))) for u in unit)
+    num -= sum(e(*(u0 + uk for u0, uk in zip((0, 2, 0), u))) * e(*(u0 + uk for u0, uk in zip((0, 1, 0), u)))
+               for u in unit)
+    den = sum(e(*(u0 + 2 * uk for u0, uk in zip((0, 2, 0), u))) for u in unit)
+    den -= sum(e(*(u0 + uk for u0, uk in zip((0, 1, 0), u))) ** 2 for u in unit)
+    alpha_star = num / den
+    coords = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    conn = np.array([[0, 1, 2]])
+    N = 200_000
+    lam = sampling.element_samples(2, 1, N, seed=77, stream=0)
+    X = sampling.physical_points(coords, conn, lam)
+    y = (X[..., 0] ** 2)[None]
+    g = (coords[:, 0] ** 2)[None]
+    _, alpha = cvmc.element_loads_own_alpha(coords, conn, g, y, lam)
+    assert abs(alpha_star - 88 / 119) < 1e-15   # the same moments in exact rational arithmetic
+    assert abs(alpha[0, 0] - alpha_star) < 0.01
+
+
+@pytest.mark.parametrize("kind", ["2d", "3d"])
+def test_own_alpha_reproduces_affine_and_conserves_constant(kind):
+    """Affine f^s: y = g(X) exactly, so every element's coefficient is 1 and the
+    target reproduces f; constant f^s: sum b = c |domain| for any coefficient."""
+    tmesh, smesh = _pair(kind)
+    r = cvmc.transfer(*tmesh, _source(smesh, "affine"), 8, seed=3, own_alpha=True)
+    assert np.abs(r["alpha_elements"] - 1.0).max() < 1e-9
+    assert np.abs(r["x"][0] - fields.evaluate("affine", np, tmesh[0])[0]).max() < 1e-12
+    r = cvmc.transfer(*tmesh, _source(smesh, "constant"), 8, seed=4, own_alpha=True)
+    assert abs(r["b"].sum() - 2.5) < 1e-13
+
+
+def test_own_alpha_variance_no_larger_than_fixed(sm_case):
+    """Per-element coefficients lower the replicate RMS error against the exact
+    b below alpha = 1 and far below alpha = 0 (plain Monte Carlo), and the
+    estimate stays centred on the exact b at this N (its bias, of order 1/N,
+    is below the sampling error)."""
+    tmesh, smesh, pieces = sm_case
+    for name in ("paper_f2", "front_2d"):
+        sv = fields.evaluate(name, np, smesh[0])
+        exact = supermesh.supermesh_projection(*tmesh, *smesh, sv, pieces=pieces)["b"][0]
+        src = P1Source(*smesh, sv)
+        rms = {}
+        for mode in ("zero", "one", "own"):
+            bs = np.array([cvmc.transfer(*tmesh, src, 16, alpha=0.0 if mode == "zero" else 1.0, seed=500 + s,
+                                         stream=2, own_alpha=mode == "own")["b"][0] for s in range(40)])
+            rms[mode] = np.sqrt(np.mean(np.square(bs - exact)))
+            if mode == "own":
+                z = (bs.mean(axis=0) - exact) / (bs.std(axis=0, ddof=1) / math.sqrt(len(bs)))
+                assert np.mean(z ** 2) < 1.6
+        assert rms["own"] < rms["one"] < 0.2 * rms["zero"]
