@@ -731,7 +731,30 @@ def main():
                            "phases_ms": {"intersect": float(np.mean([a_ for a_, _ in ms])),
                                          "project": float(np.mean([c_ for _, c_ in ms]))},
                            "mc_load_vector_rel_l2_error": err}
-        del b_mc
+        # the variance variants on the same workload: their load vectors' distance
+        # from the exact one (one realization each) and their step times
+        exact = b.clone()
+        variants = {"plain": {"rel_l2_error": err}}
+        for name, strat, own in (("stratified", True, False), ("own_alpha", False, True),
+                                 ("stratified_own_alpha", True, True)):
+            c_ = ft.SampleCfg(N, F, w.alpha, w.philox_seed, 0, prec)
+            c_.sampling = ft.FT_SAMPLING_STRATIFIED if strat else ft.FT_SAMPLING_PLAIN
+            c_.alpha_mode = ft.FT_ALPHA_ELEMENT if own else ft.FT_ALPHA_FIXED
+            tms = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                T.sample_points(c_, out=pts)
+                S.eval_query_list(pts, n, out=vals)
+                T.consume(c_, vals)
+                T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
+                e1.record()
+                torch.cuda.synchronize()
+                tms.append(e0.elapsed_time(e1))
+            variants[name] = {"rel_l2_error": float(torch.linalg.norm(b - exact) / torch.linalg.norm(exact)),
+                              "ms_per_step": float(np.median(tms))}
+        supermesh_route["variance_variants"] = variants
+        del b_mc, exact
 
     si = S.info
     src_info = {"E": sconn.shape[0], "n": sc.shape[0], "n_reg": int(si.n_registrations),

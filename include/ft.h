@@ -67,10 +67,31 @@ typedef enum {
     FT_SPLIT_BF16 = 3      /* as FT_SPLIT_F16 with hi+lo bfloat16 products                    */
 } ft_precision;
 
+/* How the samples of an element are drawn (sec. 4.1 step 3; sec. 7 names better
+ * sampling schemes as the way forward). */
+typedef enum {
+    FT_SAMPLING_PLAIN = 0,       /* independent uniform samples                                     */
+    FT_SAMPLING_STRATIFIED = 1   /* the d' uniforms of the samples stratified over the unit cube:   */
+                                 /* m = floor(N^(1/d')) cells per axis (d' = 2 for triangles, 3 for */
+                                 /* tetrahedra); sample j < m^d' takes cell (j mod m, (j/m) mod m,  */
+                                 /* j/m^2), its uniforms u -> min((cell + u)/m, 1 - 2^-53), then the  */
+                                 /* same maps; samples j >= m^d' stay plain.  Unbiased.              */
+} ft_sampling;
+
+/* How the control-variate coefficient is chosen (sec. 4.1, Eq. cv_centered_integrand;
+ * sec. 5.1 studies alpha in [0, 1]). */
+typedef enum {
+    FT_ALPHA_FIXED = 0,          /* cfg.alpha for every element                                     */
+    FT_ALPHA_ELEMENT = 1         /* per element, the coefficient minimizing the sample variance of   */
+                                 /* the residual terms, estimated from that element's own samples   */
+                                 /* (see ft_consume_queries)                                        */
+} ft_alpha_mode;
+
 typedef struct ft_target ft_target;
 typedef struct ft_source ft_source;
 
-/* Sampling configuration of one transfer (sec. 4.1 steps 3-5). */
+/* Sampling configuration of one transfer (sec. 4.1 steps 3-5).  Zero-initialized
+ * sampling and alpha_mode give plain samples and a fixed alpha. */
 typedef struct {
     int32_t  samples_per_elem;  /* N >= 1: samples per target element (the paper uses N = 20)     */
     int32_t  n_fields;          /* F >= 1: fields transferred together, sharing the samples       */
@@ -78,6 +99,8 @@ typedef struct {
     uint64_t seed;              /* Philox4x32-10 key                                               */
     uint32_t stream_id;         /* realization id: Philox counter word 2                           */
     int32_t  precision;         /* ft_precision of the query points and values                     */
+    int32_t  sampling;          /* ft_sampling                                                     */
+    int32_t  alpha_mode;        /* ft_alpha_mode                                                   */
 } ft_sample_cfg;
 
 /* Mass solve configuration (sec. 4.1 step 7). */
@@ -163,7 +186,16 @@ ft_status ft_sample_points(ft_target* t, const ft_sample_cfg* cfg, void* points,
  * with lambda regenerated from the same Philox stream (cfg must match the
  * one given to ft_sample_points), then b_res,v = sum of beta_tk over the
  * (t, k) at node v in a fixed order (no floating-point atomics, so results
- * are bitwise reproducible).  The control values g (the first n_nodes
+ * are bitwise reproducible).  With cfg->alpha_mode == FT_ALPHA_ELEMENT (forms
+ * FT_F64 and FT_F32) each element uses its own coefficient, the one that
+ * minimizes the sample variance of its residual terms summed over k:
+ *   alpha_t = (P/N - sum_k A_k B_k / N^2) / (Q/N - sum_k B_k^2 / N^2),
+ * A_k = sum_j y_tj lambda_k, B_k = sum_j g(X_tj) lambda_k, P = sum_j y_tj g(X_tj) w_j,
+ * Q = sum_j g(X_tj)^2 w_j, w_j = sum_k lambda_k^2, clipped to [0, 2] (1 when the
+ * denominator is not positive), and beta_tk also carries the element's exact
+ * control part alpha_t (M_t g_t)_k; ft_project then adds no control and starts
+ * from x = 0.  Estimating alpha_t from the same samples biases the estimate by
+ * O(1/N).  The control values g (the first n_nodes
  * entries of each field) are copied into the target.  Non-finite values are
  * counted and reported by ft_project.
  * Errors: FT_E_ARG, FT_E_OOM.  Asynchronous on `stream`.

@@ -54,6 +54,10 @@ ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
     FT_ARG_CHECK(cfg->precision >= FT_F64 && cfg->precision <= FT_SPLIT_BF16, "precision out of range (%d)",
                  cfg->precision);
     FT_ARG_CHECK(std::isfinite(cfg->alpha), "alpha must be finite");
+    FT_ARG_CHECK(cfg->sampling == FT_SAMPLING_PLAIN || cfg->sampling == FT_SAMPLING_STRATIFIED,
+                 "sampling out of range (%d)", cfg->sampling);
+    FT_ARG_CHECK(cfg->alpha_mode == FT_ALPHA_FIXED || cfg->alpha_mode == FT_ALPHA_ELEMENT,
+                 "alpha_mode out of range (%d)", cfg->alpha_mode);
     if (uint64_t(T->E) * uint64_t(cfg->samples_per_elem) >= (uint64_t(1) << 32) ||
         uint64_t(T->E) * 64u >= (uint64_t(1) << 32)) {
         set_error("n_elems * max(samples_per_elem, 64) must stay below 2^32 per transfer");
@@ -84,7 +88,27 @@ static bool point_f32(int prec) { return prec != FT_F64; }
 
 static bool same_samples(const ft_sample_cfg& a, const ft_sample_cfg& b) {
     return a.samples_per_elem == b.samples_per_elem && a.seed == b.seed && a.stream_id == b.stream_id &&
-           point_f32(a.precision) == point_f32(b.precision);
+           a.sampling == b.sampling && point_f32(a.precision) == point_f32(b.precision);
+}
+
+// Each element's own control coefficient is computed by the black-box
+// consumption kernel only (binary64 and binary32 forms).
+static ft_status check_alpha_mode(const ft_sample_cfg* cfg, bool black_box) {
+    if (cfg->alpha_mode == FT_ALPHA_ELEMENT &&
+        (!black_box || cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16)) {
+        set_error("per-element control coefficients are computed by ft_consume_queries in the FT_F64 and FT_F32 "
+                  "forms only");
+        return FT_E_UNSUPPORTED;
+    }
+    return FT_OK;
+}
+
+// What ft_project needs of the last consumption: with per-element
+// coefficients the control part is inside the element loads (alpha = 0 there).
+static ft_sample_cfg consumed_view(const ft_sample_cfg& c) {
+    ft_sample_cfg v = c;
+    if (c.alpha_mode == FT_ALPHA_ELEMENT) v.alpha = 0.0;
+    return v;
 }
 
 }  // namespace ft
@@ -193,11 +217,12 @@ ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void*
                   "point precision");
         return FT_E_ORDER;
     }
+    FT_TRY(check_alpha_mode(cfg, true));
     FT_TRY(ensure_field_buffers(T, cfg->n_fields, stream));
     T->consumed = false;
     FT_TRY(consume_values(T, cfg, values, T->beta, stream));
     T->consumed = true;
-    T->consumed_cfg = *cfg;
+    T->consumed_cfg = consumed_view(*cfg);
     return FT_OK;
     FT_GUARD_END
 }
@@ -223,13 +248,14 @@ ft_status ft_consume_queries_noalloc(ft_target* t, const ft_sample_cfg* cfg, con
     FT_ARG_CHECK(cfg->n_fields <= T->F_cap,
                  "n_fields (%d) exceeds the %d field(s) the target holds buffers for (ft_consume_queries with "
                  "that field count provisions them)", cfg->n_fields, T->F_cap);
+    FT_TRY(check_alpha_mode(cfg, true));
     double* scratch = nullptr;
     FT_TRY(noalloc_scratch(&scratch));
     T->fields_inner = false;   // the many-field route sets it again
     T->consumed = false;
     FT_TRY(consume_values(T, cfg, values, scratch, stream));
     T->consumed = true;
-    T->consumed_cfg = *cfg;
+    T->consumed_cfg = consumed_view(*cfg);
     return FT_OK;
     FT_GUARD_END
 }
@@ -246,6 +272,7 @@ ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
         set_error("the fused built-in route supports FT_F64 and at most 4 fields");
         return FT_E_UNSUPPORTED;
     }
+    FT_TRY(check_alpha_mode(cfg, false));
     FT_TRY(ensure_field_buffers(t, cfg->n_fields, stream));
     t->consumed = false;
     FT_TRY(transfer_p1(t, s, cfg, stream));
@@ -308,6 +335,7 @@ ft_status ft_plan_create(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
         set_error("plans run the FT_F64 form");
         return FT_E_UNSUPPORTED;
     }
+    FT_TRY(check_alpha_mode(cfg, false));
     FT_TRY(ensure_field_buffers(t, cfg->n_fields, stream));
     ft_plan* p = plan_new(t, s, cfg);
     const ft_status st = plan_setup(p, stream);
@@ -356,6 +384,7 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
         FT_TRY(check_sample_cfg(t, &cfgs[k]));
         FT_ARG_CHECK(s->dim == t->dim, "transfer %d: source dimension %d differs from target dimension %d", k,
                      s->dim, t->dim);
+        FT_TRY(check_alpha_mode(&cfgs[k], false));
         if (cfgs[k].precision != FT_F64 || cfgs[k].n_fields != 1 || s->F != 1) {
             set_error("transfer %d: batches run FT_F64 transfers of one field from one-field sources", k);
             return FT_E_UNSUPPORTED;

@@ -549,7 +549,7 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
         x.dim = T->dim;
         x.N = uint32_t(c.samples_per_elem);
         x.alpha = c.alpha;
-        x.key = SampleKey{uint32_t(c.seed & 0xFFFFFFFFu), uint32_t(c.seed >> 32), c.stream_id};
+        x.key = make_sample_key(c, T->dim);
         for (int64_t v = 0; v < T->n; v += BT) row.push_back(Tile{k, T->dim, v});
         const int node_tile = T->dim == 2 ? 256 : 128;   // points per wavefront of the node stage
         for (int64_t v = 0; v < T->n; v += node_tile) node.push_back(Tile{k, T->dim, v});

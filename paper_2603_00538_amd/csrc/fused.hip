@@ -44,7 +44,7 @@ void zero_counters(unsigned long long* p, int n, hipStream_t s);
 
 template <int D, int G, int P, int FC>
 static void launch_fused(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
-    const SampleKey key{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
+    const SampleKey key = make_sample_key(*cfg, D);
     const unsigned grid = grid_for(T->E * G, 256);
     k_fused_p1<D, G, P, FC><<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
                                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta,

@@ -101,7 +101,14 @@ __global__ void k_emit_nodes(const double* __restrict__ X, int64_t n, int dim, v
 
 // Element t's sums over its N samples (lanes stride over them, G lanes per
 // element); returns the number of non-finite values seen by this lane.
-template <int D, int G, int FC, bool F32>
+// OWN: the element's own control coefficient (variance-minimizing, from its
+// samples): with A_k = sum y l_k, B_k = sum g l_k, P = sum y g w, Q = sum g^2 w,
+// w = sum_k l_k^2, alpha_t = (P/N - sum A_k B_k / N^2) / (Q/N - sum B_k^2 / N^2)
+// clipped to [0, 2] (1 unless the denominator is positive), and the load
+// carries the exact control part: beta_k = alpha_t (M_t g)_k + |Omega|/N (A_k - alpha_t B_k).
+constexpr double kOwnAlphaLo = 0.0, kOwnAlphaHi = 2.0;
+
+template <int D, int G, int FC, bool F32, bool OWN>
 __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, const void* __restrict__ values_,
                                                         int64_t ld, int F, const int32_t* __restrict__ conn,
                                                         const double* __restrict__ vol, int64_t n, uint32_t E,
@@ -113,9 +120,12 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
     const double scale = vol[t] / double(N);
     const int64_t qbase = n + int64_t(t) * N;
     unsigned int nf = 0;
+    constexpr int FO = OWN ? FC : 1;
     for (int f0 = 0; f0 < F; f0 += FC) {
         double gk[FC][D + 1];
-        double acc[FC][D + 1];
+        double acc[FC][D + 1];    // sum r l_k (fixed alpha) or sum y l_k (OWN)
+        double accb[FO][D + 1];   // OWN: sum g l_k
+        double pq[FO][2];         // OWN: sum y g w, sum g^2 w
 #pragma unroll
         for (int f = 0; f < FC; ++f)
 #pragma unroll
@@ -125,6 +135,12 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
                 gk[f][k] = F32 ? double(static_cast<const float*>(values_)[off])
                                : static_cast<const double*>(values_)[off];
             }
+#pragma unroll
+        for (int f = 0; f < FO; ++f) {
+            pq[f][0] = pq[f][1] = 0.0;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) accb[f][k] = 0.0;
+        }
         for (uint32_t j = lane; j < N; j += G) {
             double lam[D + 1];
             if constexpr (F32) {
@@ -134,6 +150,11 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
                 for (int k = 0; k <= D; ++k) lam[k] = lf[k];
             } else {
                 sample_lambda<D>(t, j, key, lam);
+            }
+            double w = 0.0;
+            if constexpr (OWN) {
+#pragma unroll
+                for (int k = 0; k <= D; ++k) w = fma(lam[k], lam[k], w);
             }
 #pragma unroll
             for (int f = 0; f < FC; ++f) {
@@ -145,21 +166,61 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
                 double gx = lam[0] * gk[f][0];
 #pragma unroll
                 for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
-                const double r = y - alpha * gx;
+                if constexpr (OWN) {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                    for (int k = 0; k <= D; ++k) {
+                        acc[f][k] = fma(y, lam[k], acc[f][k]);
+                        accb[f][k] = fma(gx, lam[k], accb[f][k]);
+                    }
+                    pq[f][0] = fma(y * gx, w, pq[f][0]);
+                    pq[f][1] = fma(gx * gx, w, pq[f][1]);
+                } else {
+                    const double r = y - alpha * gx;
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                }
             }
         }
 #pragma unroll
         for (int f = 0; f < FC; ++f)
 #pragma unroll
             for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
+        if constexpr (OWN) {
+#pragma unroll
+            for (int f = 0; f < FO; ++f) {
+#pragma unroll
+                for (int k = 0; k <= D; ++k) accb[f][k] = wave_sum_xor(accb[f][k], G);
+                pq[f][0] = wave_sum_xor(pq[f][0], G);
+                pq[f][1] = wave_sum_xor(pq[f][1], G);
+            }
+        }
         if (lane == 0) {
 #pragma unroll
             for (int f = 0; f < FC; ++f) {
                 if (f0 + f >= F) break;
+                double* bt = beta + (int64_t(f0 + f) * E + t) * (D + 1);
+                if constexpr (OWN) {
+                    const double Nd = double(N);
+                    double ab = 0.0, bb = 0.0, gs = 0.0;
 #pragma unroll
-                for (int k = 0; k <= D; ++k) beta[(int64_t(f0 + f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+                    for (int k = 0; k <= D; ++k) {
+                        ab = fma(acc[f][k], accb[f][k], ab);
+                        bb = fma(accb[f][k], accb[f][k], bb);
+                        gs += gk[f][k];
+                    }
+                    const double num = pq[f][0] / Nd - ab / (Nd * Nd);
+                    const double den = pq[f][1] / Nd - bb / (Nd * Nd);
+                    double a = (isfinite(num) && isfinite(den) && den > 0.0) ? num / den : 1.0;
+                    a = fmin(fmax(a, kOwnAlphaLo), kOwnAlphaHi);
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) {
+                        const double ctrl = vol[t] * (gs + gk[f][k]) / double((D + 1) * (D + 2));
+                        bt[k] = a * ctrl + scale * (acc[f][k] - a * accb[f][k]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) bt[k] = acc[f][k] * scale;
+                }
             }
         }
     }
@@ -168,7 +229,7 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
 
 // G lanes per element.  R > 1 (G == 64 only): each wave sums R consecutive
 // elements in turn, with their element data in scalar registers.
-template <int D, int G, int FC, bool F32, int R>
+template <int D, int G, int FC, bool F32, int R, bool OWN>
 __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, int64_t ld, int F,
                                                  const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                  int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
@@ -181,7 +242,7 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         for (int e = 0; e < R; ++e) {
             const uint32_t t = wave * uint32_t(R) + uint32_t(e);
             if (t >= E) break;
-            nf += consume_element<D, G, FC, F32>(t, lane, values_, ld, F, conn, vol, n, E, N, alpha, key, beta);
+            nf += consume_element<D, G, FC, F32, OWN>(t, lane, values_, ld, F, conn, vol, n, E, N, alpha, key, beta);
         }
     } else {
         const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
@@ -189,7 +250,7 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         const int lane = int(gid & (G - 1));
         if (t >= E) return;   // the whole group leaves together
         if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
-        nf = consume_element<D, G, FC, F32>(t, lane, values_, ld, F, conn, vol, n, E, N, alpha, key, beta);
+        nf = consume_element<D, G, FC, F32, OWN>(t, lane, values_, ld, F, conn, vol, n, E, N, alpha, key, beta);
     }
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
@@ -255,9 +316,7 @@ __global__ void k_zero_u64(unsigned long long* __restrict__ p, int n) {
 }
 
 // ---------------------------------------------------------------- host side
-static SampleKey make_key(const ft_sample_cfg* cfg) {
-    return SampleKey{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
-}
+static SampleKey make_key(const ft_target* T, const ft_sample_cfg* cfg) { return make_sample_key(*cfg, T->dim); }
 
 template <int D>
 static ft_status emit_impl(ft_target* T, const ft_sample_cfg* cfg, void* points, hipStream_t s) {
@@ -271,7 +330,7 @@ static ft_status emit_impl(ft_target* T, const ft_sample_cfg* cfg, void* points,
         k_emit_nodes<false><<<grid_for(T->n, 256), 256, 0, s>>>(T->coords, T->n, D, points, ld);
     if (total) {
         const FastDiv dv = make_fastdiv(N);
-        const SampleKey key = make_key(cfg);
+        const SampleKey key = make_key(T, cfg);
         const unsigned grid = grid_for(int64_t(total), 256);
         if (N % 64 == 0) {
             auto kern = f32 ? k_emit<D, true, kEmitRuns<D>> : k_emit<D, false, kEmitRuns<D>>;
@@ -295,12 +354,13 @@ constexpr int kConsumeRuns = 4;   // elements per wave when G == 64
 template <int D, int G, int FC, bool F32>
 static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, double* beta,
                            hipStream_t s) {
-    const SampleKey key = make_key(cfg);
+    const SampleKey key = make_key(T, cfg);
     constexpr int R = G == 64 ? kConsumeRuns : 1;
     const unsigned grid = grid_for(T->E * G, 256 * R);
-    k_consume<D, G, FC, F32, R><<<grid, 256, 0, s>>>(values, ld, cfg->n_fields, T->conn, T->vol, T->n,
-                                                     uint32_t(T->E), uint32_t(cfg->samples_per_elem), cfg->alpha, key,
-                                                     beta, T->counters);
+    auto kern = cfg->alpha_mode == FT_ALPHA_ELEMENT ? k_consume<D, G, FC, F32, R, true>
+                                                    : k_consume<D, G, FC, F32, R, false>;
+    kern<<<grid, 256, 0, s>>>(values, ld, cfg->n_fields, T->conn, T->vol, T->n, uint32_t(T->E),
+                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, beta, T->counters);
 }
 
 template <int D, int G, bool F32>

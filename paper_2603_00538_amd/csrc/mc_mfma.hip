@@ -191,7 +191,7 @@ __global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ v
 }
 
 ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s) {
-    const SampleKey key{uint32_t(cfg->seed & 0xFFFFFFFFu), uint32_t(cfg->seed >> 32), cfg->stream_id};
+    const SampleKey key = make_sample_key(*cfg, T->dim);
     const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
     if (T->E == 0) return FT_OK;
     const unsigned grid = unsigned(T->E);   // one element per workgroup

@@ -207,7 +207,7 @@ namespace ft {
 template <int D, int G, int P>
 static void launch_locate(ft_plan* pl, hipStream_t s) {
     const ft_target* T = pl->T;
-    const SampleKey key{uint32_t(pl->cfg.seed & 0xFFFFFFFFu), uint32_t(pl->cfg.seed >> 32), pl->cfg.stream_id};
+    const SampleKey key = make_sample_key(pl->cfg, D);
     k_plan_locate<D, G, P><<<grid_for(T->E * G, 256), 256, 0, s>>>(
         source_view(pl->S), T->coords, T->n, T->conn, uint32_t(T->E), uint32_t(pl->cfg.samples_per_elem), key,
         pl->ids + T->n, pl->ood);
@@ -244,7 +244,7 @@ template <int D, int G>
 static void launch_elements(ft_plan* pl, const double* vals, hipStream_t s) {
     ft_target* T = pl->T;
     const ft_source* S = pl->S;
-    const SampleKey key{uint32_t(pl->cfg.seed & 0xFFFFFFFFu), uint32_t(pl->cfg.seed >> 32), pl->cfg.stream_id};
+    const SampleKey key = make_sample_key(pl->cfg, D);
     const int F = pl->cfg.n_fields;
     constexpr int R = G == 64 && D == 2 ? 4 : 1;   // elements per wave (measured no gain for tetrahedra)
     const unsigned grid = grid_for(T->E * G, 256 * R);

@@ -9,6 +9,13 @@
 //    the spacings (s1, s2 - s1, s3 - s2, 1 - s3) are uniform on the simplex.
 // lambda_k belongs to vertex k of the element in connectivity order; the
 // physical point is sum_k lambda_k x_{v_k}.
+// Stratified samples (FT_SAMPLING_STRATIFIED): with m = floor(N^(1/d')) cells
+// per axis of the d' uniforms (2 for triangles, 3 for tetrahedra), sample
+// j < m^d' takes cell (j mod m, (j / m) mod m, j / m^2) and its uniforms become
+// min((cell_i + u_i) (1/m), 1 - 2^-53) (binary32: 1/m and 1 - 2^-24 in binary32)
+// before the same maps; the other samples stay plain.  Each cell maps onto an
+// equal-volume part of the simplex, so every sample stays uniform on its part
+// and the estimate unbiased.
 #pragma once
 
 #include "common.h"
@@ -17,7 +24,52 @@ namespace ft {
 
 struct SampleKey {
     uint32_t k0, k1, stream;
+    uint32_t strat_n;   // samples j < strat_n are stratified (m^d' of them); 0: plain sampling
+    FastDiv m_div;      // division by m, the cells per axis
+    double inv_m;       // 1/m rounded to binary64
+    float inv_m_f;      // 1/m rounded to binary32
 };
+
+// Key of a transfer's samples: Philox key and counter word 2, and the strata.
+inline SampleKey make_sample_key(const ft_sample_cfg& c, int dim) {
+    SampleKey k{};
+    k.k0 = uint32_t(c.seed & 0xFFFFFFFFu);
+    k.k1 = uint32_t(c.seed >> 32);
+    k.stream = c.stream_id;
+    k.strat_n = 0;
+    k.m_div = make_fastdiv(1);
+    k.inv_m = 1.0;
+    k.inv_m_f = 1.0f;
+    if (c.sampling == FT_SAMPLING_STRATIFIED && c.samples_per_elem > 0) {
+        const int dp = dim == 2 ? 2 : 3;
+        const uint64_t N = uint64_t(c.samples_per_elem);
+        uint64_t m = 1;
+        auto pw = [dp](uint64_t x) { return dp == 2 ? x * x : x * x * x; };
+        while (pw(m + 1) <= N) ++m;
+        k.strat_n = uint32_t(pw(m));
+        k.m_div = make_fastdiv(uint32_t(m));
+        k.inv_m = 1.0 / double(m);
+        k.inv_m_f = 1.0f / float(m);
+    }
+    return k;
+}
+
+constexpr double kBelowOne = 0x1.fffffffffffffp-1;   // 1 - 2^-53
+constexpr float kBelowOneF = 0x1.fffffep-1f;         // 1 - 2^-24
+
+// The stratum of sample j < strat_n: its cell per axis.
+template <int DP>
+__device__ __forceinline__ void sample_cell(uint32_t j, const SampleKey& key, uint32_t (&cell)[DP]) {
+    const uint32_t q = fast_div(j, key.m_div);
+    cell[0] = j - q * key.m_div.d;
+    if (DP == 2) {
+        cell[1] = q;
+    } else {
+        const uint32_t q2 = fast_div(q, key.m_div);
+        cell[1] = q - q2 * key.m_div.d;
+        cell[DP - 1] = q2;
+    }
+}
 
 // Square root of a in [2^-53, 1]: the hardware reciprocal-square-root estimate,
 // one Goldschmidt step (g -> sqrt(a), h -> 1 / (2 sqrt(a))) and two Newton
@@ -39,8 +91,14 @@ template <int D>
 __device__ __forceinline__ void sample_lambda(uint32_t t, uint32_t j, const SampleKey& key, double (&lam)[D + 1]) {
     const u32x4 w = philox4x32_10(u32x4{j, t, key.stream, 0u}, key.k0, key.k1);
     if constexpr (D == 2) {
-        const double xi = uniform53(w.x, w.y);
-        const double eta = uniform53(w.z, w.w);
+        double xi = uniform53(w.x, w.y);
+        double eta = uniform53(w.z, w.w);
+        if (j < key.strat_n) {
+            uint32_t cell[2];
+            sample_cell<2>(j, key, cell);
+            xi = fmin((double(cell[0]) + xi) * key.inv_m, kBelowOne);
+            eta = fmin((double(cell[1]) + eta) * key.inv_m, kBelowOne);
+        }
         const double r = sqrt_unit(xi);
         lam[0] = 1.0 - r;
         lam[1] = r * (1.0 - eta);
@@ -48,6 +106,13 @@ __device__ __forceinline__ void sample_lambda(uint32_t t, uint32_t j, const Samp
     } else {
         const u32x4 w1 = philox4x32_10(u32x4{j, t, key.stream, 1u}, key.k0, key.k1);
         double a = uniform53(w.x, w.y), b = uniform53(w.z, w.w), c = uniform53(w1.x, w1.y);
+        if (j < key.strat_n) {
+            uint32_t cell[3];
+            sample_cell<3>(j, key, cell);
+            a = fmin((double(cell[0]) + a) * key.inv_m, kBelowOne);
+            b = fmin((double(cell[1]) + b) * key.inv_m, kBelowOne);
+            c = fmin((double(cell[2]) + c) * key.inv_m, kBelowOne);
+        }
         // three-comparator sorting network
         double lo = fmin(a, b), hi = fmax(a, b);
         a = lo; b = hi;
@@ -68,8 +133,14 @@ template <int D>
 __device__ __forceinline__ void sample_lambda_f32(uint32_t t, uint32_t j, const SampleKey& key, float (&lam)[D + 1]) {
     const u32x4 w = philox4x32_10(u32x4{j, t, key.stream, 0u}, key.k0, key.k1);
     if constexpr (D == 2) {
-        const float xi = uniform24(w.x);
-        const float eta = uniform24(w.z);
+        float xi = uniform24(w.x);
+        float eta = uniform24(w.z);
+        if (j < key.strat_n) {
+            uint32_t cell[2];
+            sample_cell<2>(j, key, cell);
+            xi = fminf((float(cell[0]) + xi) * key.inv_m_f, kBelowOneF);
+            eta = fminf((float(cell[1]) + eta) * key.inv_m_f, kBelowOneF);
+        }
         const float r = sqrtf(xi);
         lam[0] = 1.0f - r;
         lam[1] = r * (1.0f - eta);
@@ -77,6 +148,13 @@ __device__ __forceinline__ void sample_lambda_f32(uint32_t t, uint32_t j, const 
     } else {
         const u32x4 w1 = philox4x32_10(u32x4{j, t, key.stream, 1u}, key.k0, key.k1);
         float a = uniform24(w.x), b = uniform24(w.z), c = uniform24(w1.x);
+        if (j < key.strat_n) {
+            uint32_t cell[3];
+            sample_cell<3>(j, key, cell);
+            a = fminf((float(cell[0]) + a) * key.inv_m_f, kBelowOneF);
+            b = fminf((float(cell[1]) + b) * key.inv_m_f, kBelowOneF);
+            c = fminf((float(cell[2]) + c) * key.inv_m_f, kBelowOneF);
+        }
         float lo = fminf(a, b), hi = fmaxf(a, b);
         a = lo; b = hi;
         lo = fminf(b, c); hi = fmaxf(b, c);

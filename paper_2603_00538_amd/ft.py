@@ -22,6 +22,8 @@ FT_OK, FT_E_ARG, FT_E_MESH, FT_E_ORDER, FT_E_DEVICE, FT_E_NOCONV, FT_E_NONFINITE
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FT_F64, FT_F32, FT_SPLIT_F16, FT_SPLIT_BF16 = 0, 1, 2, 3
 FT_BATCH_GRAPH = 1
+FT_SAMPLING_PLAIN, FT_SAMPLING_STRATIFIED = 0, 1
+FT_ALPHA_FIXED, FT_ALPHA_ELEMENT = 0, 1
 STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -4: "FT_E_DEVICE",
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
@@ -35,7 +37,8 @@ EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_q
 
 class SampleCfg(ctypes.Structure):
     _fields_ = [("samples_per_elem", ctypes.c_int32), ("n_fields", ctypes.c_int32), ("alpha", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("precision", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("sampling", ctypes.c_int32), ("alpha_mode", ctypes.c_int32)]
 
 
 class SolveCfg(ctypes.Structure):
