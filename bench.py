@@ -482,8 +482,12 @@ def counter_records(dirs, workload, precision):
                     disp = per.setdefault(k, {}).setdefault((path, row["Dispatch_Id"]), {})
                     disp[row["Counter_Name"]] = disp.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
                     disp["ns"] = float(row["End_Timestamp"]) - float(row["Start_Timestamp"])
+                    disp["grid"] = int(row["Grid_Size"])
     lines = []
     for k, disps in per.items():
+        # the step's own launch: the largest grid (smaller ones are tuning samples)
+        gmax = max(x["grid"] for x in disps.values())
+        disps = {key: x for key, x in disps.items() if x["grid"] == gmax}
         def mean(c):
             v = [x[c] for x in disps.values() if c in x]
             return sum(v) / len(v) if v else None
@@ -528,6 +532,9 @@ def main():
                     help="blackbox: sample -> source eval -> consume through the point-query list; "
                          "fused: ft_transfer_p1 (built-in source, no query list)")
     ap.add_argument("--no-fused", action="store_true", help="skip the extra fused-route and plan-route measurements")
+    ap.add_argument("--layout", default="auto", choices=["auto", "field-major", "tiles"],
+                    help="layout of the query values: field-major [F][Q] or element tiles (ft_source_eval_tiles); "
+                         "auto: tiles for several fields")
     ap.add_argument("--bins", type=int, default=0, help="source bin cells per axis (0: the workload's choice)")
     ap.add_argument("--refine-steps", type=int, default=0,
                     help="mass solve: 0 = binary64 PCG; k > 0 = binary32 inner PCG with k binary64 refinement steps")
@@ -618,6 +625,8 @@ def main():
         tuned["ms"] = (time.perf_counter() - t0) * 1e3
         log(f"autotuned bins {tuned['chosen']} from {cands} in {tuned['ms']:.0f} ms")
     cfg = ft.SampleCfg(N, F, w.alpha, w.philox_seed, 0, prec)
+    tiles = args.layout == "tiles" or (args.layout == "auto" and F > 1)
+    cfg.values_layout = ft.FT_VALUES_ELEMENT_TILES if tiles else ft.FT_VALUES_FIELD_MAJOR
     pts = torch.empty((dim, Q), dtype=dt_, device=dev)
     vals = torch.empty((F, Q), dtype=dt_, device=dev)
     x = torch.empty((F, n), dtype=torch.float64, device=dev)
@@ -638,7 +647,10 @@ def main():
             T.sample_points(cfg, out=pts)
             if record:
                 ev[1].record()
-            S.eval_query_list(pts, n, out=vals)
+            if tiles:
+                S.eval_tiles(pts, n, E, N, out=vals.view(-1))
+            else:
+                S.eval_query_list(pts, n, out=vals)
             if record:
                 ev[2].record()
             T.consume(cfg, vals)
@@ -809,6 +821,7 @@ def main():
                    "source_elements": int(sconn.shape[0]), "samples_per_elem": N, "n_fields": F,
                    "queries": Q, "alpha": w.alpha, "rtol": w.rtol,
                    "bins": list(w.bins[:dim]) if any(w.bins) else "default", "precision": args.precision,
+                   "values_layout": "element tiles" if tiles else "field-major",
                    "solve": "binary64 PCG" if args.refine_steps == 0 else
                             f"binary32 PCG + {args.refine_steps} binary64 refinement steps"},
         "queries_per_s": Q / (ms_step * 1e-3),

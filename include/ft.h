@@ -87,6 +87,16 @@ typedef enum {
                                  /* (see ft_consume_queries)                                        */
 } ft_alpha_mode;
 
+/* Layout of the query values handed to ft_consume_queries (field f at query q). */
+typedef enum {
+    FT_VALUES_FIELD_MAJOR = 0,   /* values[f * Q + q] (q in the query-list order)                   */
+    FT_VALUES_ELEMENT_TILES = 1  /* node v: values[f * n_nodes + v]; sample j of element t:         */
+                                 /* values[F * n_nodes + (t * F + f) * N + j], i.e. [F][n_nodes]      */
+                                 /* then one F x N tile per element (one field: the same as          */
+                                 /* FT_VALUES_FIELD_MAJOR).  Many fields read and write one element's */
+                                 /* values as one contiguous block.                                  */
+} ft_values_layout;
+
 typedef struct ft_target ft_target;
 typedef struct ft_source ft_source;
 
@@ -101,6 +111,8 @@ typedef struct {
     int32_t  precision;         /* ft_precision of the query points and values                     */
     int32_t  sampling;          /* ft_sampling                                                     */
     int32_t  alpha_mode;        /* ft_alpha_mode                                                   */
+    int32_t  values_layout;     /* ft_values_layout of the values given to ft_consume_queries      */
+    int32_t  reserved;          /* 0                                                               */
 } ft_sample_cfg;
 
 /* Mass solve configuration (sec. 4.1 step 7). */
@@ -179,8 +191,9 @@ ft_status ft_sample_points(ft_target* t, const ft_sample_cfg* cfg, void* points,
 
 /*
  * ft_consume_queries - steps 4-6 of sec. 4.1 for the caller's point values.
- *   values   device, [F][Q] in cfg->precision: f^s at every query point, in
- *            the layout of ft_sample_points (nodes first, then samples)
+ *   values   device, F*Q values in cfg->precision: f^s at every query point,
+ *            [F][Q] in the order of ft_sample_points (nodes first, then
+ *            samples), or element tiles (cfg->values_layout)
  * For every element t and local vertex k:
  *   beta_tk = |Omega_t| / N * sum_j (y_tj - alpha sum_l lambda_l g_{v_l}) lambda_k,
  * with lambda regenerated from the same Philox stream (cfg must match the
@@ -318,6 +331,21 @@ ft_status ft_source_eval(ft_source* s, int64_t n_points, const void* points, int
 ft_status ft_source_eval_queries(ft_source* s, int64_t n_nodes, int64_t n_points, const void* points, int64_t ld,
                                  int32_t precision, void* values, int64_t ld_out, int32_t* elem_ids,
                                  hipStream_t stream);
+
+/*
+ * ft_source_eval_tiles - ft_source_eval_queries over the query list of a
+ * transfer (n_nodes nodes, then n_elems x samples_per_elem samples), the
+ * values written as FT_VALUES_ELEMENT_TILES: [F][n_nodes], then one F x N
+ * tile per element (one element's samples of all fields contiguous, for
+ * ft_consume_queries with cfg->values_layout = FT_VALUES_ELEMENT_TILES).
+ *   points   device, [dim][ld] in `precision` (ld >= n_nodes + n_elems N)
+ *   values   device, F (n_nodes + n_elems N) values in `precision`
+ *   elem_ids device, int32, [n_nodes + n_elems N], or null
+ * Errors: FT_E_ARG.  Asynchronous on `stream`.
+ */
+ft_status ft_source_eval_tiles(ft_source* s, int64_t n_nodes, int64_t n_elems, int32_t samples_per_elem,
+                               const void* points, int64_t ld, int32_t precision, void* values, int32_t* elem_ids,
+                               hipStream_t stream);
 
 /*
  * ft_source_autotune - choose the bin grid for a query distribution.  For

@@ -18,6 +18,8 @@ ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts,
                       int64_t ld_out, int32_t* ids, hipStream_t s, unsigned long long* ood);
 ft_status source_release(ft_source* S);
 ft_status source_integral(ft_source* S, double* out, hipStream_t s);
+ft_status source_eval_tiles(ft_source* S, int64_t n_nodes, int64_t n_elems, int N, const void* pts, int64_t ld,
+                            int prec, void* out, int32_t* ids, hipStream_t s);
 ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, int ncand,
                           const int32_t* cand, hipStream_t s);
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s);
@@ -58,6 +60,8 @@ ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
                  "sampling out of range (%d)", cfg->sampling);
     FT_ARG_CHECK(cfg->alpha_mode == FT_ALPHA_FIXED || cfg->alpha_mode == FT_ALPHA_ELEMENT,
                  "alpha_mode out of range (%d)", cfg->alpha_mode);
+    FT_ARG_CHECK(cfg->values_layout == FT_VALUES_FIELD_MAJOR || cfg->values_layout == FT_VALUES_ELEMENT_TILES,
+                 "values_layout out of range (%d)", cfg->values_layout);
     if (uint64_t(T->E) * uint64_t(cfg->samples_per_elem) >= (uint64_t(1) << 32) ||
         uint64_t(T->E) * 64u >= (uint64_t(1) << 32)) {
         set_error("n_elems * max(samples_per_elem, 64) must stay below 2^32 per transfer");
@@ -484,6 +488,23 @@ ft_status ft_source_eval_queries(ft_source* s, int64_t n_nodes, int64_t n_points
     FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
     FT_ARG_CHECK(n_points < (int64_t(1) << 39), "n_points too large");
     return source_eval(s, n_nodes, n_points, points, ld, precision, values, ld_out, elem_ids, stream, nullptr);
+    FT_GUARD_END
+}
+
+ft_status ft_source_eval_tiles(ft_source* s, int64_t n_nodes, int64_t n_elems, int32_t samples_per_elem,
+                               const void* points, int64_t ld, int32_t precision, void* values, int32_t* elem_ids,
+                               hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(s, "source is null");
+    FT_ARG_CHECK(n_nodes >= 0 && n_elems >= 0 && samples_per_elem >= 1, "sizes out of range");
+    FT_ARG_CHECK(uint64_t(n_elems) * uint64_t(samples_per_elem) < (uint64_t(1) << 32),
+                 "n_elems * samples_per_elem must stay below 2^32");
+    const int64_t npts = n_nodes + n_elems * int64_t(samples_per_elem);
+    FT_ARG_CHECK(npts == 0 || (points && values), "points and values must be device pointers");
+    FT_ARG_CHECK(ld >= npts, "ld must be >= n_nodes + n_elems * samples_per_elem");
+    FT_ARG_CHECK(precision == FT_F64 || precision == FT_F32, "precision must be FT_F64 or FT_F32");
+    return source_eval_tiles(s, n_nodes, n_elems, samples_per_elem, points, ld, precision, values, elem_ids, stream);
     FT_GUARD_END
 }
 

@@ -159,6 +159,27 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv& f) {
     return (t + ((n - t) >> f.sh1)) >> f.sh2;
 }
 
+// ---------------------------------------------------------------- query value layouts
+// Where the value of field f at a query lives.  Node v: values[f * node_ld + v].
+// Sample j of element t: values[samp0 + t * samp_elem + f * samp_fld + j].
+//   field-major [F][Q]:       node_ld = samp_fld = Q, samp0 = n, samp_elem = N
+//   element tiles (F x N per  node_ld = n, samp0 = F n, samp_fld = N, samp_elem = F N
+//   element, after [F][n]):
+// A run of points without elements (plain evaluation) is field-major with
+// N = 1 (each point its own "element").
+struct ValueLayout {
+    int64_t node_ld, samp0, samp_fld, samp_elem;
+    FastDiv ndiv;   // division by N (samples per element)
+};
+
+inline ValueLayout field_major_layout(int64_t Q, int64_t n, int64_t N) {
+    return ValueLayout{Q, n, Q, N, make_fastdiv(uint32_t(N))};
+}
+
+inline ValueLayout element_tile_layout(int64_t n, int64_t N, int F) {
+    return ValueLayout{n, int64_t(F) * n, N, int64_t(F) * N, make_fastdiv(uint32_t(N))};
+}
+
 // ---------------------------------------------------------------- wave helpers (wave64)
 __device__ __forceinline__ double wave_sum_xor(double v, int width) {
     for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);

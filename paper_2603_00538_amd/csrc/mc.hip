@@ -110,7 +110,7 @@ constexpr double kOwnAlphaLo = 0.0, kOwnAlphaHi = 2.0;
 
 template <int D, int G, int FC, bool F32, bool OWN>
 __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, const void* __restrict__ values_,
-                                                        int64_t ld, int F, const int32_t* __restrict__ conn,
+                                                        const ValueLayout& L, int F, const int32_t* __restrict__ conn,
                                                         const double* __restrict__ vol, int64_t n, uint32_t E,
                                                         uint32_t N, double alpha, const SampleKey& key,
                                                         double* __restrict__ beta) {
@@ -118,7 +118,7 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
 #pragma unroll
     for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
     const double scale = vol[t] / double(N);
-    const int64_t qbase = n + int64_t(t) * N;
+    const int64_t qbase = L.samp0 + int64_t(t) * L.samp_elem;
     unsigned int nf = 0;
     constexpr int FO = OWN ? FC : 1;
     for (int f0 = 0; f0 < F; f0 += FC) {
@@ -131,7 +131,7 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
 #pragma unroll
             for (int k = 0; k <= D; ++k) {
                 acc[f][k] = 0.0;
-                const int64_t off = int64_t(f0 + f < F ? f0 + f : 0) * ld + v[k];
+                const int64_t off = int64_t(f0 + f < F ? f0 + f : 0) * L.node_ld + v[k];
                 gk[f][k] = F32 ? double(static_cast<const float*>(values_)[off])
                                : static_cast<const double*>(values_)[off];
             }
@@ -159,7 +159,7 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
 #pragma unroll
             for (int f = 0; f < FC; ++f) {
                 if (f0 + f >= F) break;
-                const int64_t off = int64_t(f0 + f) * ld + qbase + j;
+                const int64_t off = int64_t(f0 + f) * L.samp_fld + qbase + j;
                 const double y = F32 ? double(static_cast<const float*>(values_)[off])
                                      : static_cast<const double*>(values_)[off];
                 nf += !isfinite(y);
@@ -230,7 +230,7 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
 // G lanes per element.  R > 1 (G == 64 only): each wave sums R consecutive
 // elements in turn, with their element data in scalar registers.
 template <int D, int G, int FC, bool F32, int R, bool OWN>
-__global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, int64_t ld, int F,
+__global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, ValueLayout L, int F,
                                                  const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                  int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
                                                  double* __restrict__ beta, unsigned long long* __restrict__ nonfinite) {
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         for (int e = 0; e < R; ++e) {
             const uint32_t t = wave * uint32_t(R) + uint32_t(e);
             if (t >= E) break;
-            nf += consume_element<D, G, FC, F32, OWN>(t, lane, values_, ld, F, conn, vol, n, E, N, alpha, key, beta);
+            nf += consume_element<D, G, FC, F32, OWN>(t, lane, values_, L, F, conn, vol, n, E, N, alpha, key, beta);
         }
     } else {
         const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         const int lane = int(gid & (G - 1));
         if (t >= E) return;   // the whole group leaves together
         if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
-        nf = consume_element<D, G, FC, F32, OWN>(t, lane, values_, ld, F, conn, vol, n, E, N, alpha, key, beta);
+        nf = consume_element<D, G, FC, F32, OWN>(t, lane, values_, L, F, conn, vol, n, E, N, alpha, key, beta);
     }
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
@@ -352,37 +352,44 @@ ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipS
 constexpr int kConsumeRuns = 4;   // elements per wave when G == 64
 
 template <int D, int G, int FC, bool F32>
-static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, double* beta,
-                           hipStream_t s) {
+static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
+                           double* beta, hipStream_t s) {
     const SampleKey key = make_key(T, cfg);
     constexpr int R = G == 64 ? kConsumeRuns : 1;
     const unsigned grid = grid_for(T->E * G, 256 * R);
     auto kern = cfg->alpha_mode == FT_ALPHA_ELEMENT ? k_consume<D, G, FC, F32, R, true>
                                                     : k_consume<D, G, FC, F32, R, false>;
-    kern<<<grid, 256, 0, s>>>(values, ld, cfg->n_fields, T->conn, T->vol, T->n, uint32_t(T->E),
+    kern<<<grid, 256, 0, s>>>(values, L, cfg->n_fields, T->conn, T->vol, T->n, uint32_t(T->E),
                               uint32_t(cfg->samples_per_elem), cfg->alpha, key, beta, T->counters);
 }
 
 template <int D, int G, bool F32>
-static void consume_fc(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, double* beta,
-                       hipStream_t s) {
+static void consume_fc(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
+                       double* beta, hipStream_t s) {
     if (cfg->n_fields == 1)
-        launch_consume<D, G, 1, F32>(T, cfg, values, ld, beta, s);
+        launch_consume<D, G, 1, F32>(T, cfg, values, L, beta, s);
     else
-        launch_consume<D, G, 4, F32>(T, cfg, values, ld, beta, s);
+        launch_consume<D, G, 4, F32>(T, cfg, values, L, beta, s);
 }
 
 template <int D, bool F32>
-static void consume_g(ft_target* T, const ft_sample_cfg* cfg, const void* values, int64_t ld, double* beta,
-                      hipStream_t s) {
+static void consume_g(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
+                      double* beta, hipStream_t s) {
     const int N = cfg->samples_per_elem;
-    if (N >= 64) consume_fc<D, 64, F32>(T, cfg, values, ld, beta, s);
-    else if (N > 16) consume_fc<D, 32, F32>(T, cfg, values, ld, beta, s);
-    else if (N > 8) consume_fc<D, 16, F32>(T, cfg, values, ld, beta, s);
-    else if (N > 4) consume_fc<D, 8, F32>(T, cfg, values, ld, beta, s);
-    else if (N > 2) consume_fc<D, 4, F32>(T, cfg, values, ld, beta, s);
-    else if (N > 1) consume_fc<D, 2, F32>(T, cfg, values, ld, beta, s);
-    else consume_fc<D, 1, F32>(T, cfg, values, ld, beta, s);
+    if (N >= 64) consume_fc<D, 64, F32>(T, cfg, values, L, beta, s);
+    else if (N > 16) consume_fc<D, 32, F32>(T, cfg, values, L, beta, s);
+    else if (N > 8) consume_fc<D, 16, F32>(T, cfg, values, L, beta, s);
+    else if (N > 4) consume_fc<D, 8, F32>(T, cfg, values, L, beta, s);
+    else if (N > 2) consume_fc<D, 4, F32>(T, cfg, values, L, beta, s);
+    else if (N > 1) consume_fc<D, 2, F32>(T, cfg, values, L, beta, s);
+    else consume_fc<D, 1, F32>(T, cfg, values, L, beta, s);
+}
+
+// The layout of the caller's query values (ft_sample_cfg.values_layout).
+ValueLayout query_layout(const ft_target* T, const ft_sample_cfg* cfg) {
+    const int64_t N = cfg->samples_per_elem;
+    return cfg->values_layout == FT_VALUES_ELEMENT_TILES ? element_tile_layout(T->n, N, cfg->n_fields)
+                                                         : field_major_layout(T->n + T->E * N, T->n, N);
 }
 
 void zero_counter(unsigned long long* p, hipStream_t s) {
@@ -427,27 +434,28 @@ static ft_status assemble_fields_inner(ft_target* T, const double* beta, int F, 
     return FT_OK;
 }
 
-ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s);
+ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
+                       double* beta, hipStream_t s);
 constexpr int kMfmaMaxSamples = 256;   // the matrix-core form stages <= 256 samples
 constexpr int kMfmaMaxFields = 64;     // and <= 64 control values per vertex in LDS
 
 template <int D>
 static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta,
                               hipStream_t s) {
-    const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
+    const ValueLayout L = query_layout(T, cfg);
     const bool f32 = cfg->precision != FT_F64;
     const bool split = cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16;
     zero_counter(T->counters, s);
     T->ood_mode = 0;   // the caller's black box evaluated the points
     if (split && cfg->samples_per_elem <= kMfmaMaxSamples && cfg->n_fields <= kMfmaMaxFields) {
-        FT_TRY(consume_mfma(T, cfg, values, beta, s));   // element loads fields-inner
+        FT_TRY(consume_mfma(T, cfg, values, L, beta, s));   // element loads fields-inner
         T->fields_inner = cfg->n_fields > 1;
-        return assemble_fields_inner(T, beta, cfg->n_fields, values, ld, f32, s);
+        return assemble_fields_inner(T, beta, cfg->n_fields, values, L.node_ld, f32, s);
     }
-    if (f32) consume_g<D, true>(T, cfg, values, ld, beta, s);
-    else consume_g<D, false>(T, cfg, values, ld, beta, s);
+    if (f32) consume_g<D, true>(T, cfg, values, L, beta, s);
+    else consume_g<D, false>(T, cfg, values, L, beta, s);
     FT_TRY_HIP(hipGetLastError());
-    return assemble_from(T, beta, cfg->n_fields, values, ld, f32, s);
+    return assemble_from(T, beta, cfg->n_fields, values, L.node_ld, f32, s);
 }
 
 // The element loads go to `beta` ([F][E][d+1], or [E][d+1][F] on the

@@ -71,7 +71,7 @@ constexpr int MF_CHUNK = 128;                   // samples per staged chunk (fou
 constexpr int MF_LPL = 16 * MF_CHUNK / 64;      // staged floats per lane
 
 template <int D, bool BF16>
-__global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ values, int64_t ld, int F,
+__global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ values, ValueLayout L, int F,
                                                      const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                      int64_t n, uint32_t E, uint32_t N, float alpha, SampleKey key,
                                                      double* __restrict__ beta,
@@ -99,13 +99,13 @@ __global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ v
     }
     for (int idx = lane; idx < 4 * 64; idx += 64) {
         const int k = idx >> 6, f = idx & 63;
-        g_s[k][f] = (k <= D && f < F) ? values[int64_t(f) * ld + v[k]] : 0.0f;
+        g_s[k][f] = (k <= D && f < F) ? values[int64_t(f) * L.node_ld + v[k]] : 0.0f;
     }
     __syncthreads();
 
     const int sg = lane >> 4;            // sample group within a K step (8 samples)
     const int col = lane & 15;           // A row (field in the tile) / B, C column
-    const int64_t qbase = n + int64_t(t) * N;
+    const int64_t qbase = L.samp0 + int64_t(t) * L.samp_elem;
     const int nchunk = int((N + MF_CHUNK - 1) / MF_CHUNK);
     const int nstep = ((F + 15) / 16) * nchunk;   // (field tile, sample chunk) pairs
     unsigned int nf = 0;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ v
         for (int m = 0; m < MF_LPL; ++m) {
             const int f = f0 + (m >> 1);
             const uint32_t j = c0 + uint32_t((m & 1) * 64 + lane);
-            pre[m] = (f < F && j < N) ? values[int64_t(f) * ld + qbase + j] : 0.0f;
+            pre[m] = (f < F && j < N) ? values[int64_t(f) * L.samp_fld + qbase + j] : 0.0f;
         }
     };
     load_chunk(0);
@@ -190,9 +190,9 @@ __global__ __launch_bounds__(64) void k_consume_mfma(const float* __restrict__ v
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
 
-ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s) {
+ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
+                       double* beta, hipStream_t s) {
     const SampleKey key = make_sample_key(*cfg, T->dim);
-    const int64_t ld = T->n + T->E * int64_t(cfg->samples_per_elem);
     if (T->E == 0) return FT_OK;
     const unsigned grid = unsigned(T->E);   // one element per workgroup
     const bool bf = cfg->precision == FT_SPLIT_BF16;
@@ -200,14 +200,14 @@ ft_status consume_mfma(ft_target* T, const ft_sample_cfg* cfg, const void* value
     const uint32_t N = uint32_t(cfg->samples_per_elem);
     const float a = float(cfg->alpha);
     if (T->dim == 2) {
-        if (bf) k_consume_mfma<2, true><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+        if (bf) k_consume_mfma<2, true><<<grid, 64, 0, s>>>(vals, L, cfg->n_fields, T->conn, T->vol, T->n,
                                                              uint32_t(T->E), N, a, key, beta, T->counters);
-        else k_consume_mfma<2, false><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+        else k_consume_mfma<2, false><<<grid, 64, 0, s>>>(vals, L, cfg->n_fields, T->conn, T->vol, T->n,
                                                            uint32_t(T->E), N, a, key, beta, T->counters);
     } else {
-        if (bf) k_consume_mfma<3, true><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+        if (bf) k_consume_mfma<3, true><<<grid, 64, 0, s>>>(vals, L, cfg->n_fields, T->conn, T->vol, T->n,
                                                              uint32_t(T->E), N, a, key, beta, T->counters);
-        else k_consume_mfma<3, false><<<grid, 64, 0, s>>>(vals, ld, cfg->n_fields, T->conn, T->vol, T->n,
+        else k_consume_mfma<3, false><<<grid, 64, 0, s>>>(vals, L, cfg->n_fields, T->conn, T->vol, T->n,
                                                            uint32_t(T->E), N, a, key, beta, T->counters);
     }
     FT_TRY_HIP(hipGetLastError());

@@ -279,7 +279,7 @@ struct ManyLds {
 template <int D, int P, bool IN_F32, bool OUT_F32>
 __global__ __launch_bounds__(64) void k_src_eval_many(SrcView S, int64_t head, int64_t npts,
                                                       const void* __restrict__ pts_, int64_t ld,
-                                                      void* __restrict__ out_, int64_t ld_out,
+                                                      void* __restrict__ out_, ValueLayout VL,
                                                       int32_t* __restrict__ ids,
                                                       unsigned long long* __restrict__ n_ood) {
     using L = ManyLds<D, P, OUT_F32>;
@@ -337,6 +337,19 @@ __global__ __launch_bounds__(64) void k_src_eval_many(SrcView S, int64_t head, i
     const int pg = lane >> 4;              // point within a group of four
     for (int q = 0; q < P; ++q) {
         const int64_t i0 = base + q * 64;
+        // this lane's point in the output: field 0 at a_base, fields a_fs apart
+        const int64_t iq = i0 + lane;
+        int64_t a_base = iq, a_fs = VL.node_ld;
+        if (iq >= head) {
+            const int64_t sq = iq - head;
+            int64_t te = sq, je = 0;
+            if (VL.ndiv.d != 1) {
+                te = int64_t(fast_div(uint32_t(sq), VL.ndiv));
+                je = sq - te * int64_t(VL.ndiv.d);
+            }
+            a_base = VL.samp0 + te * VL.samp_elem + je;
+            a_fs = VL.samp_fld;
+        }
         for (int f0 = 0; f0 < S.F; f0 += kManyFB) {
             const int f = f0 + fl;
             for (int it = 0; it < 16; ++it) {
@@ -354,7 +367,7 @@ __global__ __launch_bounds__(64) void k_src_eval_many(SrcView S, int64_t head, i
             const int64_t i = i0 + lane;
             if (i < lim) {
                 for (int r = 0; r < kManyFB && f0 + r < S.F; ++r)
-                    static_cast<T*>(out_)[int64_t(f0 + r) * ld_out + i] = tile[r * 65 + lane];
+                    static_cast<T*>(out_)[a_base + int64_t(f0 + r) * a_fs] = tile[r * 65 + lane];
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -538,7 +551,8 @@ constexpr int kEvalWavesPerBlock = 1;
 
 template <int D>
 static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec,
-                             void* out, int64_t ld_out, int32_t* ids, unsigned long long* ood, hipStream_t s) {
+                             void* out, int64_t ld_out, int32_t* ids, unsigned long long* ood, hipStream_t s,
+                             const ValueLayout* tiles = nullptr) {
     // points per lane: a wave covers 256 consecutive points in 2D, 128 in 3D
     // (one target element's samples at N = 256 / 128; fewer registers in 3D)
     constexpr int P = D == 2 ? 4 : 2;
@@ -549,10 +563,11 @@ static ft_status launch_eval(ft_source* S, int64_t head, int64_t npts, const voi
     const unsigned grid = unsigned((waves + WPB - 1) / WPB);
     if (S->F > 1 && out) {   // many fields: the lanes interpolate over fields
         const unsigned gw = unsigned(waves);
+        const ValueLayout L = tiles ? *tiles : field_major_layout(ld_out, head, 1);
         if (prec == FT_F64)
-            k_src_eval_many<D, P, false, false><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, ood);
+            k_src_eval_many<D, P, false, false><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, L, ids, ood);
         else
-            k_src_eval_many<D, P, true, true><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, ood);
+            k_src_eval_many<D, P, true, true><<<gw, 64, 0, s>>>(v, head, npts, pts, ld, out, L, ids, ood);
     } else if (prec == FT_F64) {
         k_src_eval<D, P, false, false, WPB><<<grid, 64 * WPB, 0, s>>>(v, head, npts, pts, ld, out, ld_out, ids, ood);
     } else {
@@ -621,6 +636,18 @@ ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts,
     if (!ood) ood = S->counters;
     return S->dim == 2 ? launch_eval<2>(S, head, npts, pts, ld, prec, out, ld_out, ids, ood, s)
                        : launch_eval<3>(S, head, npts, pts, ld, prec, out, ld_out, ids, ood, s);
+}
+
+// A query list (n_nodes nodes, then n_elems x N samples) with the values
+// written as element tiles: [F][n_nodes], then an F x N tile per element.
+// With one field the tiles are the field-major list.
+ft_status source_eval_tiles(ft_source* S, int64_t n_nodes, int64_t n_elems, int N, const void* pts, int64_t ld,
+                            int prec, void* out, int32_t* ids, hipStream_t s) {
+    const int64_t npts = n_nodes + n_elems * int64_t(N);
+    if (npts == 0) return FT_OK;
+    const ValueLayout L = element_tile_layout(n_nodes, N, S->F);
+    return S->dim == 2 ? launch_eval<2>(S, n_nodes, npts, pts, ld, prec, out, npts, ids, S->counters, s, &L)
+                       : launch_eval<3>(S, n_nodes, npts, pts, ld, prec, out, npts, ids, S->counters, s, &L);
 }
 
 // Exact integral of each P1 field over the source mesh (sec. 2, Eq.

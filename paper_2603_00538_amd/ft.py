@@ -24,13 +24,14 @@ FT_F64, FT_F32, FT_SPLIT_F16, FT_SPLIT_BF16 = 0, 1, 2, 3
 FT_BATCH_GRAPH = 1
 FT_SAMPLING_PLAIN, FT_SAMPLING_STRATIFIED = 0, 1
 FT_ALPHA_FIXED, FT_ALPHA_ELEMENT = 0, 1
+FT_VALUES_FIELD_MAJOR, FT_VALUES_ELEMENT_TILES = 0, 1
 STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -4: "FT_E_DEVICE",
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
             "ft_consume_queries", "ft_consume_queries_noalloc", "ft_transfer_p1",
             "ft_transfer_supermesh", "ft_project", "ft_source_create_p1", "ft_source_eval",
-            "ft_source_eval_queries", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
+            "ft_source_eval_queries", "ft_source_eval_tiles", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_last_error"]
 
@@ -38,7 +39,8 @@ EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_q
 class SampleCfg(ctypes.Structure):
     _fields_ = [("samples_per_elem", ctypes.c_int32), ("n_fields", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("sampling", ctypes.c_int32), ("alpha_mode", ctypes.c_int32)]
+                ("sampling", ctypes.c_int32), ("alpha_mode", ctypes.c_int32), ("values_layout", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SolveCfg(ctypes.Structure):
@@ -97,6 +99,7 @@ def load(path: str = LIB_PATH):
         "ft_source_eval": (I32, [P, I64, P, I64, I32, P, I64, P, P]),
         "ft_source_eval_queries": (I32, [P, I64, I64, P, I64, I32, P, I64, P, P]),
         "ft_source_autotune": (I32, [P, I64, I64, P, I64, I32, I32, P, P, P]),
+        "ft_source_eval_tiles": (I32, [P, I64, I64, I32, P, I64, I32, P, P, P]),
         "ft_source_stats": (I32, [P, ctypes.POINTER(I64), P]),
         "ft_source_destroy": (I32, [P]),
         "ft_source_get_info": (I32, [P, ctypes.POINTER(SourceInfo)]),
@@ -236,6 +239,11 @@ def ft_source_eval(h, n_points, points_ptr, ld, precision, values_ptr, ld_out, i
 def ft_source_eval_queries(h, n_nodes, n_points, points_ptr, ld, precision, values_ptr, ld_out, ids_ptr, stream):
     return _check(load().ft_source_eval_queries(h, n_nodes, n_points, points_ptr, ld, precision, values_ptr, ld_out,
                                                 ids_ptr, stream), "ft_source_eval_queries")
+
+
+def ft_source_eval_tiles(h, n_nodes, n_elems, N, points_ptr, ld, precision, values_ptr, ids_ptr, stream):
+    return _check(load().ft_source_eval_tiles(h, n_nodes, n_elems, N, points_ptr, ld, precision, values_ptr,
+                                              ids_ptr, stream), "ft_source_eval_tiles")
 
 
 def ft_source_stats(h, stream):
@@ -455,6 +463,29 @@ class Source:
         ft_source_eval_queries(self.handle, int(n_nodes), ld, _device_ptr(points, "points", (torch.float32, torch.float64)),
                                ld, prec, _device_ptr(out, "out"), int(out.shape[1]),
                                _device_ptr(ids, "ids") if ids is not None else None, current_stream())
+        return out
+
+    def eval_tiles(self, points, n_nodes, n_elems, N, out=None, ids=None):
+        """Evaluate a transfer's (d, Q) query list, values as element tiles
+        (FT_VALUES_ELEMENT_TILES): a flat tensor of F*Q values."""
+        torch = _torch()
+        if points.ndim != 2 or points.shape[0] != self.dim:
+            raise ValueError(f"points must have shape ({self.dim}, n)")
+        Q = n_nodes + n_elems * N
+        ld = int(points.shape[1])
+        if ld < Q:
+            raise ValueError("points hold fewer than n_nodes + n_elems * N queries")
+        prec = FT_F32 if points.dtype == torch.float32 else FT_F64
+        if out is None:
+            out = torch.empty(self.n_fields * Q, dtype=points.dtype, device=points.device)
+        if out.numel() < self.n_fields * Q or out.dtype != points.dtype:
+            raise ValueError("out must hold n_fields * Q values of the dtype of points")
+        if ids is not None and (ids.dtype != torch.int32 or ids.numel() < Q):
+            raise ValueError("ids must be int32 with at least Q entries")
+        ft_source_eval_tiles(self.handle, int(n_nodes), int(n_elems), int(N),
+                             _device_ptr(points, "points", (torch.float32, torch.float64)), ld, prec,
+                             _device_ptr(out, "out"), _device_ptr(ids, "ids") if ids is not None else None,
+                             current_stream())
         return out
 
     def autotune(self, points, n_nodes, candidates):
