@@ -368,11 +368,28 @@ def bench_batch(args):
     t0 = time.perf_counter()
     targets = [ft.Target(tc, tconn) for tc, tconn, _, _, _ in host]
     sources = [ft.Source(sc, sconn, sv) for _, _, sc, sconn, sv in host]
-    cfgs = [ft.SampleCfg(it.samples_per_elem, 1, 1.0, configs.BATCH_PHILOX_SEED, it.stream_id, ft.FT_F64)
+    prec = ft.FT_F32 if args.precision == "f32" else ft.FT_F64
+    if args.precision not in ("f64", "f32"):
+        raise SystemExit("batch256 runs the f64 and f32 forms")
+    cfgs = [ft.SampleCfg(it.samples_per_elem, 1, 1.0, configs.BATCH_PHILOX_SEED, it.stream_id, prec)
             for it in items]
     B = ft.Batch(targets, sources, cfgs, graph=True)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    tune = None
+    if args.autotune != "off":
+        # element variants and bin grids timed per kind of transfer (cached in a
+        # JSON file when --tune-cache names one)
+        t0 = time.perf_counter()
+        n_tuned = B.autotune(args.tune_cache or None)
+        torch.cuda.synchronize()
+        hist = {}
+        for k in range(len(items)):
+            g_, p_ = B.variant(k)
+            hist[f"G{g_}xP{p_}"] = hist.get(f"G{g_}xP{p_}", 0) + 1
+        tune = {"kinds_timed": n_tuned, "ms": (time.perf_counter() - t0) * 1e3, "variants": hist,
+                "cache": args.tune_cache or None}
+        log(f"batch autotune: {n_tuned} kinds timed in {tune['ms']:.0f} ms; variants {hist}")
     E_tot = int(sum(t.n_elems for t in targets))
     S_tot = int(sum(t.n_elems * it.samples_per_elem for t, it in zip(targets, items)))
     xs = [torch.empty(t.n_nodes, dtype=torch.float64, device="cuda") for t in targets]
@@ -409,7 +426,8 @@ def bench_batch(args):
         "value": E_tot / (ms * 1e-3),
         "unit": "target elements/s (aggregate over the batch)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+        "data": "synthetic",
         "config": {"workload": "batch256", "transfers": len(items), "target_elements": E_tot, "samples": S_tot,
                    "dims": {"2": sum(1 for it in items if it.dim == 2), "3": sum(1 for it in items if it.dim == 3)},
                    "samples_per_elem": "per transfer from {32, 64, 128, 256}", "alpha": 1.0, "rtol": 1e-14,
@@ -417,6 +435,7 @@ def bench_batch(args):
         "queries_per_s": S_tot / (ms * 1e-3),
         "event_ms": float(np.mean(times)),
         "setup_ms": setup_s * 1e3,
+        "autotune": tune,
         "cg_iters_max": int(max(r["iters"] for r in reps)),
         "cons_defect_max": float(max(r["cons_defect"] for r in reps)),
         "status": ft.STATUS_NAMES[st],
@@ -539,7 +558,9 @@ def main():
     ap.add_argument("--refine-steps", type=int, default=0,
                     help="mass solve: 0 = binary64 PCG; k > 0 = binary32 inner PCG with k binary64 refinement steps")
     ap.add_argument("--autotune", default="auto", choices=["auto", "on", "off"],
-                    help="tune the source bin grid on a sample of the queries (auto: when the workload fixes none)")
+                    help="tune the source bin grid on a sample of the queries (auto: when the workload fixes none); "
+                         "batch256: the element variants and bin grids per kind of transfer")
+    ap.add_argument("--tune-cache", default="", help="batch256: JSON file of the batch autotuner's choices")
     ap.add_argument("--sequential", action="store_true",
                     help="multi-field workloads: also time F sequential one-field FP64 transfers; "
                          "batch256: also time the transfers one after another")

@@ -259,7 +259,9 @@ ft_status ft_project(ft_target* t, const ft_solve_cfg* cfg, double* x, double* b
  * the same samples (Philox counters of cfg), the same localization rule and
  * the same element sums as ft_sample_points + ft_source_eval +
  * ft_consume_queries, fused into one pass over the samples.  Follow with
- * ft_project.  Requires cfg->precision == FT_F64, cfg->n_fields equal to the
+ * ft_project.  Requires cfg->precision FT_F64 or FT_F32 (the binary32 form:
+ * binary32 samples and points, values rounded to binary32, as the query list
+ * of that form holds them; sums in binary64), cfg->n_fields equal to the
  * source's field count (at most 4), and a source of the target's dimension.
  * Out-of-domain queries (nodes and samples) are counted for the transfer and
  * reported by ft_project (ft_report.n_out_of_domain).
@@ -426,8 +428,8 @@ ft_status ft_plan_destroy(ft_plan* p);
 
 /*
  * Batches: many independent transfers from built-in P1 sources (one field
- * each, FT_F64), of mixed dimension, size and samples per element, run as
- * one sequence of launches.  Target elements of all transfers are the work
+ * each, FT_F64 or FT_F32 as ft_transfer_p1), of mixed dimension, size and
+ * samples per element, run as one sequence of launches.  Target elements of all transfers are the work
  * units of persistent kernels, one launch per element-kernel variant (sec.
  * 4.1: the element sums of step 5 are independent); the node sums and the
  * mass solves of all transfers share their launches.  Each transfer gives exactly the samples and element sums
@@ -444,7 +446,7 @@ enum { FT_BATCH_GRAPH = 1 };   /* capture a run as a HIP graph; later runs repla
  *                      outlive the batch, and no other call may use them while
  *                      ft_batch_run runs.  Targets must be distinct.
  *   cfgs               host [count]: per-transfer sample configuration
- *                      (n_fields 1 = the source's field count, FT_F64)
+ *                      (n_fields 1 = the source's field count, FT_F64 or FT_F32)
  *   flags              0 or FT_BATCH_GRAPH
  * Builds the work lists (node, element and row tiles; element tiles grouped
  * by variant, the dearest variants first) and the batch's solver vectors on
@@ -471,6 +473,33 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
  */
 ft_status ft_batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec,
                        ft_report* reports, int32_t* status, hipStream_t stream);
+
+/*
+ * ft_batch_autotune - pick, for each kind of transfer in the batch, the
+ * element-stage variant and the bin grid of its source by timing them (a
+ * kind: architecture, dimension, form, N, fields and the power-of-two
+ * buckets of the target and source element counts).  For the largest
+ * transfer of each kind not found in the cache: ft_source_autotune on a run
+ * of that transfer's own samples (cells along the longest axis 0.6 to 1.6
+ * times the default of ft_source_create_p1), then each of the five (lanes per element, samples per
+ * lane) variants (64,4) (64,2) (64,1) (32,1) (16,1) of the batch's element
+ * kernel on that transfer, the fastest kept; the other transfers of the kind
+ * take the same variant and the same factor on their sources' cells.
+ * Results stay those of the same transfers with other variants to rounding
+ * (the variant fixes the order of each element's sums).
+ *   cache_path  host, a JSON file (one entry per line) read before tuning and
+ *               rewritten with every entry after it, or null (no cache)
+ *   n_tuned     host, or null: kinds timed in this call (0 when all came
+ *               from the cache)
+ * Rebuilds the bins of the batch's sources and the element work lists; a
+ * captured graph is captured again by the next run.  Uses temporary device
+ * memory for the samples.  Errors: FT_E_ARG (cache not writable), FT_E_OOM,
+ * FT_E_DEVICE.  Synchronizes `stream`.
+ */
+ft_status ft_batch_autotune(ft_batch* b, const char* cache_path, int32_t* n_tuned, hipStream_t stream);
+
+/* The element-stage variant of transfer k: lanes per element and samples per lane per round. */
+ft_status ft_batch_variant(const ft_batch* b, int32_t k, int32_t* lanes_per_elem, int32_t* samples_per_lane);
 
 ft_status ft_batch_destroy(ft_batch* b);
 

@@ -32,6 +32,9 @@ ft_batch* batch_new(int count, ft_target* const* targets, ft_source* const* sour
                     bool graph);
 void batch_delete(ft_batch* b);
 void batch_mark_consumed(ft_batch* b);
+ft_status batch_autotune(ft_batch* b, const char* cache_path, int32_t* n_tuned, hipStream_t s);
+void batch_variant(const ft_batch* b, int k, int32_t* G, int32_t* P);
+int batch_count(const ft_batch* b);
 ft_status plan_setup(ft_plan* pl, hipStream_t s);
 ft_status plan_transfer(ft_plan* pl, const double* vals, hipStream_t s);
 ft_plan* plan_new(ft_target* T, ft_source* S, const ft_sample_cfg* cfg);
@@ -272,8 +275,8 @@ ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
     FT_ARG_CHECK(s->dim == t->dim, "source dimension %d differs from target dimension %d", s->dim, t->dim);
     FT_ARG_CHECK(cfg->n_fields == s->F, "n_fields (%d) must equal the source's field count (%d)", cfg->n_fields,
                  s->F);
-    if (cfg->precision != FT_F64 || cfg->n_fields > 4) {
-        set_error("the fused built-in route supports FT_F64 and at most 4 fields");
+    if ((cfg->precision != FT_F64 && cfg->precision != FT_F32) || cfg->n_fields > 4) {
+        set_error("the fused built-in route supports FT_F64 and FT_F32 and at most 4 fields");
         return FT_E_UNSUPPORTED;
     }
     FT_TRY(check_alpha_mode(cfg, false));
@@ -389,8 +392,8 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
         FT_ARG_CHECK(s->dim == t->dim, "transfer %d: source dimension %d differs from target dimension %d", k,
                      s->dim, t->dim);
         FT_TRY(check_alpha_mode(&cfgs[k], false));
-        if (cfgs[k].precision != FT_F64 || cfgs[k].n_fields != 1 || s->F != 1) {
-            set_error("transfer %d: batches run FT_F64 transfers of one field from one-field sources", k);
+        if ((cfgs[k].precision != FT_F64 && cfgs[k].precision != FT_F32) || cfgs[k].n_fields != 1 || s->F != 1) {
+            set_error("transfer %d: batches run FT_F64 or FT_F32 transfers of one field from one-field sources", k);
             return FT_E_UNSUPPORTED;
         }
         for (int j = 0; j < k; ++j)
@@ -421,6 +424,22 @@ ft_status ft_batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, d
     if (st == FT_OK || st == FT_E_NOCONV || st == FT_E_NONFINITE) batch_mark_consumed(b);
     return st;
     FT_GUARD_END
+}
+
+ft_status ft_batch_autotune(ft_batch* b, const char* cache_path, int32_t* n_tuned, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(b, "batch is null");
+    return batch_autotune(b, cache_path, n_tuned, stream);
+    FT_GUARD_END
+}
+
+ft_status ft_batch_variant(const ft_batch* b, int32_t k, int32_t* lanes_per_elem, int32_t* samples_per_lane) {
+    clear_error();
+    FT_ARG_CHECK(b && lanes_per_elem && samples_per_lane, "null argument");
+    FT_ARG_CHECK(k >= 0 && k < batch_count(b), "transfer index %d out of range", k);
+    batch_variant(b, k, lanes_per_elem, samples_per_lane);
+    return FT_OK;
 }
 
 ft_status ft_batch_destroy(ft_batch* b) {

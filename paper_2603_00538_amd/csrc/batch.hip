@@ -1,7 +1,8 @@
 // Many transfers at once: target/source pairs of mixed dimension and size,
 // each with its own samples per element, run as one sequence of launches
 // (sec. 4.1 steps 1-7 for every pair; the pairs are independent work units,
-// sec. 4.1 last paragraph).  Built-in P1 sources, one field per transfer.
+// sec. 4.1 last paragraph).  Built-in P1 sources, one field per transfer, in
+// the binary64 or the binary32 form of the fused route.
 //
 // Work lists built once at creation:
 //   node tiles     (transfer, 256 / 128 target nodes) step 1, the control g
@@ -9,8 +10,9 @@
 //   row tiles      (transfer, 256 rows)              steps 2, 6, 7 and the report
 // The node and element stages are persistent kernels: a grid sized to the
 // device walks its list with a fixed stride.  Each element tile is one
-// wavefront; its (dimension, lanes per element G, samples per lane P) variant
-// is chosen per transfer exactly as the single-transfer route chooses it, and
+// wavefront; its (dimension, form, lanes per element G, samples per lane P)
+// variant is chosen per transfer (by default as the single-transfer route
+// chooses G and P from N; ft_batch_autotune times the candidates), and
 // every variant runs as a launch of its own (each with its own register
 // budget, hence occupancy), the dearest variants (largest N, 3D) first.
 //
@@ -23,10 +25,13 @@
 // on every later call.
 #include <algorithm>
 #include <cmath>
-#include <numeric>
-#include <vector>
-
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <numeric>
+#include <set>
+#include <string>
+#include <vector>
 
 #include "fused.h"
 
@@ -60,6 +65,7 @@ struct BatchXfer {
     int64_t row0;                  // first row in the concatenated solver vectors
     int32_t tile0, ntiles;         // this system's row tiles
     int32_t dim;
+    int32_t f32;                   // binary32 form of the fused route
     uint32_t N;
     double alpha;
     SampleKey key;
@@ -76,8 +82,8 @@ enum { BP_BB = 0, BP_SB, BP_RZ, BP_RR, BP_PQ, BP_TRR, BP_MX, BP_COUNT };
 enum { BS_RHO = 0, BS_ALPHA, BS_BETA, BS_TOL2, BS_DONE, BS_ITERS, BS_BB, BS_SUMB, BS_INTX, BS_TRR, BS_COUNT };
 
 // ---------------------------------------------------------------- variants
-// G lanes per element and P samples per lane per round, as the single-transfer
-// fused route picks them (N <= 8 uses G = 16 here).
+// G lanes per element and P samples per lane per round: by default as the
+// single-transfer fused route picks them (N <= 8 uses G = 16 here).
 constexpr int kVariants = 5;
 static int variant_of(int N) {
     if (N >= 256) return 0;   // G 64, P 4
@@ -87,18 +93,21 @@ static int variant_of(int N) {
     return 4;                 // G 16
 }
 static int lanes_of(int v) { return v <= 2 ? 64 : (v == 3 ? 32 : 16); }
+static int per_lane_of(int v) { return v == 0 ? 4 : (v == 1 ? 2 : 1); }
+// launch code of (variant, dimension, form)
+static int code_of(int v, int dim, bool f32) { return v + (dim == 3 ? kVariants : 0) + (f32 ? 2 * kVariants : 0); }
 
-template <int D, int G, int P>
+template <int D, int G, int P, bool F32>
 __device__ __forceinline__ void batch_elements(const BatchXfer& x, int64_t start, int lane, unsigned& nf,
                                                unsigned& nood, double* c_af) {
     const uint32_t t = uint32_t(start) + uint32_t(lane / G);
-    fused_elements<D, G, P, 1>(x.src, x.coords, x.n, x.conn, x.vol, uint32_t(x.E), x.N, x.alpha, x.key, x.g,
-                               x.beta, t, lane % G, nf, nood, c_af);
+    fused_elements<D, G, P, 1, F32>(x.src, x.coords, x.n, x.conn, x.vol, uint32_t(x.E), x.N, x.alpha, x.key, x.g,
+                                    x.beta, t, lane % G, nf, nood, c_af);
 }
 
 // One launch per (dimension, G, P) variant over that variant's tiles
 // [first, last), so that each variant gets its own register budget.
-template <int D, int G, int P>
+template <int D, int G, int P, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 2 ? 3 : 2))) void k_batch_fused(
     const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles, int64_t first, int64_t last,
     unsigned long long* __restrict__ nonfinite) {
@@ -113,60 +122,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 2 ? 3 
         const Tile tl = tiles[w];
         const BatchXfer& x = X[tl.k];
         unsigned nf = 0, nood = 0;
-        batch_elements<D, G, P>(x, tl.start, lane, nf, nood, c_af);
+        batch_elements<D, G, P, F32>(x, tl.start, lane, nf, nood, c_af);
         if (nf) atomicAdd(nonfinite + tl.k, (unsigned long long)nf);
         if (nood) atomicAdd(x.ood, (unsigned long long)nood);
     }
 }
 
-constexpr int kCodes = 2 * kVariants;   // variant + kVariants for 3D
+constexpr int kCodes = 4 * kVariants;   // variant, + kVariants for 3D, + 2 kVariants for binary32
 
-template <int D, int G, int P>
+template <int D, int G, int P, bool F32>
 static void launch_fused_v(unsigned grid, hipStream_t s, const BatchXfer* X, const Tile* tiles, int64_t first,
                            int64_t last, unsigned long long* nf) {
-    k_batch_fused<D, G, P><<<grid, 256, 0, s>>>(X, tiles, first, last, nf);
+    k_batch_fused<D, G, P, F32><<<grid, 256, 0, s>>>(X, tiles, first, last, nf);
 }
 
-template <int D, int G, int P>
+template <int D, int G, int P, bool F32>
 static int fused_blocks_per_cu() {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<D, G, P>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<D, G, P, F32>, 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu;
 }
 
-// (launch, resident blocks per CU) of element-stage code c
-static void launch_fused(int c, unsigned grid, hipStream_t s, const BatchXfer* X, const Tile* tiles, int64_t first,
-                         int64_t last, unsigned long long* nf) {
-    switch (c) {
-        case 0: launch_fused_v<2, 64, 4>(grid, s, X, tiles, first, last, nf); break;
-        case 1: launch_fused_v<2, 64, 2>(grid, s, X, tiles, first, last, nf); break;
-        case 2: launch_fused_v<2, 64, 1>(grid, s, X, tiles, first, last, nf); break;
-        case 3: launch_fused_v<2, 32, 1>(grid, s, X, tiles, first, last, nf); break;
-        case 4: launch_fused_v<2, 16, 1>(grid, s, X, tiles, first, last, nf); break;
-        case kVariants + 0: launch_fused_v<3, 64, 4>(grid, s, X, tiles, first, last, nf); break;
-        case kVariants + 1: launch_fused_v<3, 64, 2>(grid, s, X, tiles, first, last, nf); break;
-        case kVariants + 2: launch_fused_v<3, 64, 1>(grid, s, X, tiles, first, last, nf); break;
-        case kVariants + 3: launch_fused_v<3, 32, 1>(grid, s, X, tiles, first, last, nf); break;
-        default: launch_fused_v<3, 16, 1>(grid, s, X, tiles, first, last, nf); break;
+// launch (op 0) or resident blocks per CU (op 1) of element-stage code c
+template <int D, bool F32>
+static int fused_code_dv(int v, int op, unsigned grid, hipStream_t s, const BatchXfer* X, const Tile* tiles,
+                         int64_t first, int64_t last, unsigned long long* nf) {
+    switch (v) {
+        case 0: return op ? fused_blocks_per_cu<D, 64, 4, F32>() : (launch_fused_v<D, 64, 4, F32>(grid, s, X, tiles, first, last, nf), 0);
+        case 1: return op ? fused_blocks_per_cu<D, 64, 2, F32>() : (launch_fused_v<D, 64, 2, F32>(grid, s, X, tiles, first, last, nf), 0);
+        case 2: return op ? fused_blocks_per_cu<D, 64, 1, F32>() : (launch_fused_v<D, 64, 1, F32>(grid, s, X, tiles, first, last, nf), 0);
+        case 3: return op ? fused_blocks_per_cu<D, 32, 1, F32>() : (launch_fused_v<D, 32, 1, F32>(grid, s, X, tiles, first, last, nf), 0);
+        default: return op ? fused_blocks_per_cu<D, 16, 1, F32>() : (launch_fused_v<D, 16, 1, F32>(grid, s, X, tiles, first, last, nf), 0);
     }
 }
 
-static int fused_per_cu(int c) {
-    switch (c) {
-        case 0: return fused_blocks_per_cu<2, 64, 4>();
-        case 1: return fused_blocks_per_cu<2, 64, 2>();
-        case 2: return fused_blocks_per_cu<2, 64, 1>();
-        case 3: return fused_blocks_per_cu<2, 32, 1>();
-        case 4: return fused_blocks_per_cu<2, 16, 1>();
-        case kVariants + 0: return fused_blocks_per_cu<3, 64, 4>();
-        case kVariants + 1: return fused_blocks_per_cu<3, 64, 2>();
-        case kVariants + 2: return fused_blocks_per_cu<3, 64, 1>();
-        case kVariants + 3: return fused_blocks_per_cu<3, 32, 1>();
-        default: return fused_blocks_per_cu<3, 16, 1>();
-    }
+static int fused_code(int c, int op, unsigned grid, hipStream_t s, const BatchXfer* X, const Tile* tiles,
+                      int64_t first, int64_t last, unsigned long long* nf) {
+    const int v = c % kVariants;
+    const bool d3 = ((c / kVariants) & 1) != 0;
+    const bool f32 = c >= 2 * kVariants;
+    if (!d3) return f32 ? fused_code_dv<2, true>(v, op, grid, s, X, tiles, first, last, nf)
+                        : fused_code_dv<2, false>(v, op, grid, s, X, tiles, first, last, nf);
+    return f32 ? fused_code_dv<3, true>(v, op, grid, s, X, tiles, first, last, nf)
+               : fused_code_dv<3, false>(v, op, grid, s, X, tiles, first, last, nf);
 }
+
+static void launch_fused(int c, unsigned grid, hipStream_t s, const BatchXfer* X, const Tile* tiles, int64_t first,
+                         int64_t last, unsigned long long* nf) {
+    (void)fused_code(c, 0, grid, s, X, tiles, first, last, nf);
+}
+
+static int fused_per_cu(int c) { return fused_code(c, 1, 0, nullptr, nullptr, nullptr, 0, 0, nullptr); }
 
 // step 1: g = f^s at the target nodes, 256 (2D) or 128 (3D) nodes per wavefront
 __global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict__ X, const Tile* __restrict__ tiles,
@@ -180,9 +188,11 @@ __global__ __launch_bounds__(256) void k_batch_nodes(const BatchXfer* __restrict
         const BatchXfer& x = X[tl.k];
         unsigned nood;
         if (tl.variant == 2)
-            nood = eval_wave<2, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af);
+            nood = x.f32 ? eval_wave<2, 4, false, false, true>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af)
+                         : eval_wave<2, 4, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af);
         else
-            nood = eval_wave<3, 2, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af);
+            nood = x.f32 ? eval_wave<3, 2, false, false, true>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af)
+                         : eval_wave<3, 2, false, false>(x.src, tl.start, x.n, x.coords, x.n, x.g, x.n, nullptr, c_af);
         if (nood) atomicAdd(x.ood, (unsigned long long)nood);
     }
 }
@@ -428,7 +438,9 @@ struct ft_batch {
     std::vector<ft_target*> T;
     std::vector<ft_source*> S;
     std::vector<ft_sample_cfg> cfg;
+    std::vector<int> var;         // element-stage variant (G, P) of each transfer
     int64_t rows = 0;
+    size_t elem_cap = 0;          // element tiles d_elem can hold
     int64_t n_elem_tiles = 0, n_node_tiles = 0, n_row_tiles = 0;
     ft::BatchXfer* d_x = nullptr;
     ft::Tile* d_elem = nullptr;
@@ -465,6 +477,8 @@ ft_batch* batch_new(int count, ft_target* const* targets, ft_source* const* sour
     b->T.assign(targets, targets + count);
     b->S.assign(sources, sources + count);
     b->cfg.assign(cfgs, cfgs + count);
+    b->var.resize(count);
+    for (int k = 0; k < count; ++k) b->var[k] = variant_of(cfgs[k].samples_per_elem);
     b->use_graph = graph;
     return b;
 }
@@ -525,28 +539,73 @@ static unsigned persistent_grid(int per_cu, int64_t waves) {
     return unsigned(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(cus) * std::max(1, per_cu))));
 }
 
-ft_status batch_setup(ft_batch* b, hipStream_t s) {
+// Element tiles of every transfer with its variant, grouped by launch code;
+// codes in the order of their dearest transfer (samples a tile draws, 3D
+// about 1.5x dearer).  Uploads the list and sizes each code's persistent grid.
+static ft_status build_element_tiles(ft_batch* b, hipStream_t s) {
     const int K = b->count;
-    std::vector<BatchXfer> xs(K);
-    std::vector<Tile> elem, node, row;
     struct Group {
         double cost;
         int k;
     };
     std::vector<Group> order;
+    for (int k = 0; k < K; ++k) {
+        const int epw = 64 / lanes_of(b->var[k]);   // elements per wavefront
+        order.push_back(Group{double(epw) * b->cfg[k].samples_per_elem * (b->T[k]->dim == 3 ? 1.5 : 1.0), k});
+    }
+    std::stable_sort(order.begin(), order.end(), [](const Group& a, const Group& c) { return a.cost > c.cost; });
+    std::vector<std::vector<Tile>> by_code(kCodes);
+    bool seen[kCodes] = {};
+    int n_order = 0;
+    for (const Group& gp : order) {
+        const int k = gp.k;
+        const int epw = 64 / lanes_of(b->var[k]);
+        const int code = code_of(b->var[k], b->T[k]->dim, b->cfg[k].precision == FT_F32);
+        if (!seen[code]) b->code_order[n_order++] = code;
+        seen[code] = true;
+        for (int64_t t = 0; t < b->T[k]->E; t += epw) by_code[code].push_back(Tile{k, code, t});
+    }
+    for (int c = 0; c < kCodes; ++c)
+        if (!seen[c]) b->code_order[n_order++] = c;
+    std::vector<Tile> elem;
+    for (int i = 0; i < kCodes; ++i) {
+        const int c = b->code_order[i];
+        b->code_first[i] = int64_t(elem.size());
+        elem.insert(elem.end(), by_code[c].begin(), by_code[c].end());
+    }
+    b->code_first[kCodes] = int64_t(elem.size());
+    b->n_elem_tiles = int64_t(elem.size());
+    if (elem.size() > b->elem_cap) {
+        FT_TRY_HIP(hipStreamSynchronize(s));
+        dev_free(b->d_elem);
+        b->d_elem = nullptr;
+        b->elem_cap = 0;
+        FT_TRY(dev_alloc_n(&b->d_elem, elem.size()));
+        b->elem_cap = elem.size();
+    }
+    FT_TRY_HIP(hipMemcpyAsync(b->d_elem, elem.data(), sizeof(Tile) * elem.size(), hipMemcpyHostToDevice, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));   // the host list goes out of scope
+    for (int i = 0; i < kCodes; ++i)
+        b->code_grid[i] = persistent_grid(fused_per_cu(b->code_order[i]), b->code_first[i + 1] - b->code_first[i]);
+    return FT_OK;
+}
+
+ft_status batch_setup(ft_batch* b, hipStream_t s) {
+    const int K = b->count;
+    std::vector<BatchXfer> xs(K);
+    std::vector<Tile> node, row;
     int64_t row0 = 0;
     for (int k = 0; k < K; ++k) {
         ft_target* T = b->T[k];
-        ft_source* S = b->S[k];
         const ft_sample_cfg& c = b->cfg[k];
         FT_TRY(ensure_field_buffers(T, 1, s));
         BatchXfer& x = xs[k];
-        (void)S;
         x.n = T->n;
         x.E = T->E;
         x.row0 = row0;
         x.tile0 = int32_t(row.size());
         x.dim = T->dim;
+        x.f32 = c.precision == FT_F32 ? 1 : 0;
         x.N = uint32_t(c.samples_per_elem);
         x.alpha = c.alpha;
         x.key = make_sample_key(c, T->dim);
@@ -555,43 +614,15 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
         for (int64_t v = 0; v < T->n; v += node_tile) node.push_back(Tile{k, T->dim, v});
         x.ntiles = int32_t(row.size()) - x.tile0;
         row0 += T->n;
-        const int var = variant_of(c.samples_per_elem);
-        const int epw = 64 / lanes_of(var);   // elements per wavefront
-        // cost of one tile ~ samples it draws, 3D localization about 1.5x dearer
-        order.push_back(Group{double(epw) * c.samples_per_elem * (T->dim == 3 ? 1.5 : 1.0), k});
     }
-    std::stable_sort(order.begin(), order.end(), [](const Group& a, const Group& c) { return a.cost > c.cost; });
-    // element tiles grouped by code; codes in the order of their dearest transfer
-    std::vector<std::vector<Tile>> by_code(kCodes);
-    bool seen[kCodes] = {};
-    int n_order = 0;
-    for (const Group& gp : order) {
-        const int k = gp.k;
-        const int var = variant_of(b->cfg[k].samples_per_elem);
-        const int epw = 64 / lanes_of(var);
-        const int code = var + (b->T[k]->dim == 3 ? kVariants : 0);
-        if (!seen[code]) b->code_order[n_order++] = code;
-        seen[code] = true;
-        for (int64_t t = 0; t < b->T[k]->E; t += epw) by_code[code].push_back(Tile{k, code, t});
-    }
-    for (int c = 0; c < kCodes; ++c)
-        if (!seen[c]) b->code_order[n_order++] = c;
-    for (int i = 0; i < kCodes; ++i) {
-        const int c = b->code_order[i];
-        b->code_first[i] = int64_t(elem.size());
-        elem.insert(elem.end(), by_code[c].begin(), by_code[c].end());
-    }
-    b->code_first[kCodes] = int64_t(elem.size());
     if (row.size() >= (size_t(1) << 31)) {
         set_error("batch too large (%zu row tiles)", row.size());
         return FT_E_UNSUPPORTED;
     }
     b->rows = row0;
-    b->n_elem_tiles = int64_t(elem.size());
     b->n_node_tiles = int64_t(node.size());
     b->n_row_tiles = int64_t(row.size());
     FT_TRY(dev_alloc_n(&b->d_x, size_t(K)));
-    FT_TRY(dev_alloc_n(&b->d_elem, elem.size()));
     FT_TRY(dev_alloc_n(&b->d_node, node.size()));
     FT_TRY(dev_alloc_n(&b->d_row, row.size()));
     for (double** p : {&b->B, &b->Y, &b->R, &b->Z, &b->Q}) FT_TRY(dev_alloc_n(p, size_t(row0)));
@@ -605,13 +636,11 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
     FT_TRY_HIP(hipHostMalloc((void**)&b->h_sc, sizeof(double) * BS_COUNT * K, hipHostMallocDefault));
     FT_TRY_HIP(hipHostMalloc((void**)&b->h_nf, sizeof(unsigned long long) * 2 * K, hipHostMallocDefault));
     FT_TRY_HIP(hipMemcpyAsync(b->d_x, xs.data(), sizeof(BatchXfer) * K, hipMemcpyHostToDevice, s));
-    FT_TRY_HIP(hipMemcpyAsync(b->d_elem, elem.data(), sizeof(Tile) * elem.size(), hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipMemcpyAsync(b->d_node, node.data(), sizeof(Tile) * node.size(), hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipMemcpyAsync(b->d_row, row.data(), sizeof(Tile) * row.size(), hipMemcpyHostToDevice, s));
     FT_TRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
     b->h_x = xs;
-    for (int i = 0; i < kCodes; ++i)
-        b->code_grid[i] = persistent_grid(fused_per_cu(b->code_order[i]), b->code_first[i + 1] - b->code_first[i]);
+    FT_TRY(build_element_tiles(b, s));
     int node_per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&node_per_cu, k_batch_nodes, 256, 0) != hipSuccess)
         node_per_cu = 1;
@@ -651,22 +680,234 @@ static ft_status enqueue_run(ft_batch* b, const ft_solve_cfg* cfg, hipStream_t s
     return FT_OK;
 }
 
+// Descriptors that point at memory a target or source has since replaced are
+// refreshed (the kernels, and a captured graph, read the table at run time).
+static ft_status refresh_descriptors(ft_batch* b, hipStream_t s) {
+    const int K = b->count;
+    std::vector<BatchXfer> xs = b->h_x;
+    for (int k = 0; k < K; ++k) {
+        fill_live(b, k, xs[k]);
+        b->T[k]->fields_inner = false;   // the batch writes one field, [F][n] layout
+    }
+    if (std::memcmp(xs.data(), b->h_x.data(), sizeof(BatchXfer) * K) != 0) {
+        b->h_x = xs;
+        FT_TRY_HIP(hipMemcpyAsync(b->d_x, b->h_x.data(), sizeof(BatchXfer) * K, hipMemcpyHostToDevice, s));
+    }
+    return FT_OK;
+}
+
+// ---------------------------------------------------------------- autotuning
+ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipStream_t s);
+ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, int ncand,
+                          const int32_t* cand, hipStream_t s);
+ft_status source_rebin(ft_source* S, int32_t per_axis, hipStream_t s);
+int32_t source_cells_longest(const ft_source* S);
+int32_t source_default_cells(const ft_source* S);
+
+// Tuned choice for one kind of transfer: its element variant and its bin
+// grid as a factor on the source's default cells along the longest axis.
+struct TuneEntry {
+    int var = 2;
+    double bins_scale = 1.0;
+    double ms = 0.0;
+};
+
+// Cache file: JSON, one entry per line,
+//   "<key>": {"G": 64, "P": 2, "bins_scale": 1.25, "ms": 0.4321}
+// keyed by architecture, dimension, form, N, fields and the power-of-two
+// buckets of the target and source element counts.
+static std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
+    std::map<std::string, TuneEntry> out;
+    if (!path) return out;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+        char key[512];
+        int G = 0, P = 0;
+        double sc = 0.0, ms = 0.0;
+        if (std::sscanf(line, " \"%511[^\"]\": {\"G\": %d, \"P\": %d, \"bins_scale\": %lf, \"ms\": %lf", key, &G, &P,
+                        &sc, &ms) == 5) {
+            int v = -1;
+            for (int c = 0; c < kVariants; ++c)
+                if (lanes_of(c) == G && per_lane_of(c) == P) v = c;
+            if (v >= 0 && sc > 0.0 && sc < 100.0) out[key] = TuneEntry{v, sc, ms};
+        }
+    }
+    std::fclose(f);
+    return out;
+}
+
+static bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& c) {
+    if (!path) return true;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n  \"format\": \"ft batch autotune cache, one entry per line\",\n  \"entries\": {\n");
+    size_t i = 0;
+    for (const auto& kv : c) {
+        std::fprintf(f, "    \"%s\": {\"G\": %d, \"P\": %d, \"bins_scale\": %.6g, \"ms\": %.6g}%s\n", kv.first.c_str(),
+                     lanes_of(kv.second.var), per_lane_of(kv.second.var), kv.second.bins_scale, kv.second.ms,
+                     ++i < c.size() ? "," : "");
+    }
+    std::fprintf(f, "  }\n}\n");
+    return std::fclose(f) == 0;
+}
+
+static int ilog2(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << (l + 1)) <= x) ++l;
+    return l;
+}
+
+static std::string tune_key(const char* arch, const ft_batch* b, int k) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s|d=%d|%s|N=%d|F=%d|E=2^%d|Es=2^%d", arch, b->T[k]->dim,
+                  b->cfg[k].precision == FT_F32 ? "f32" : "f64", b->cfg[k].samples_per_elem, b->cfg[k].n_fields,
+                  ilog2(b->T[k]->E), ilog2(b->S[k]->E));
+    return buf;
+}
+
+// Element-stage time of transfer k alone with variant v (a warm-up launch,
+// then two timed ones).
+static ft_status time_variant(ft_batch* b, int k, int v, Tile* d_tiles, hipEvent_t e0, hipEvent_t e1, hipStream_t s,
+                              float* ms) {
+    const int epw = 64 / lanes_of(v);
+    const int code = code_of(v, b->T[k]->dim, b->cfg[k].precision == FT_F32);
+    std::vector<Tile> tiles;
+    for (int64_t t = 0; t < b->T[k]->E; t += epw) tiles.push_back(Tile{k, code, t});
+    const int64_t nt = int64_t(tiles.size());   // <= E, what d_tiles holds
+    FT_TRY_HIP(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s));
+    const unsigned grid = persistent_grid(fused_per_cu(code), nt);
+    launch_fused(code, grid, s, b->d_x, d_tiles, 0, nt, b->nonfinite);
+    FT_TRY_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 2; ++r) launch_fused(code, grid, s, b->d_x, d_tiles, 0, nt, b->nonfinite);
+    FT_TRY_HIP(hipEventRecord(e1, s));
+    FT_TRY_HIP(hipEventSynchronize(e1));
+    FT_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
+    *ms *= 0.5f;
+    return FT_OK;
+}
+
+ft_status batch_autotune(ft_batch* b, const char* cache_path, int32_t* n_tuned, hipStream_t s) {
+    const int K = b->count;
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    FT_TRY_HIP(hipGetDevice(&dev));
+    FT_TRY_HIP(hipGetDeviceProperties(&prop, dev));
+    char arch[64];
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+        if (*c == ':') *c = 0;
+    std::map<std::string, TuneEntry> cache = read_tune_cache(cache_path);
+    std::map<std::string, std::vector<int>> groups;
+    for (int k = 0; k < K; ++k) groups[tune_key(arch, b, k)].push_back(k);
+    int tuned = 0;
+    std::set<const ft_source*> rebinned;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    void* pts = nullptr;
+    Tile* d_tiles = nullptr;
+    ScratchGuard guard;
+    guard.add(&pts);
+    guard.add((void**)&d_tiles);
+    ft_status st = FT_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        set_error("event creation failed while tuning the batch");
+        st = FT_E_DEVICE;
+    }
+    for (auto& g : groups) {
+        if (st != FT_OK) break;
+        auto it = cache.find(g.first);
+        TuneEntry e;
+        if (it != cache.end()) {
+            e = it->second;
+        } else {
+            int rep = g.second[0];
+            for (int k : g.second)
+                if (b->T[k]->E > b->T[rep]->E) rep = k;
+            ft_target* T = b->T[rep];
+            ft_source* S = b->S[rep];
+            const ft_sample_cfg& c = b->cfg[rep];
+            // bins: the source autotuner on a run of this transfer's own samples
+            const int64_t N = c.samples_per_elem;
+            const int64_t Q = T->n + T->E * N;
+            const size_t psz = c.precision == FT_F32 ? 4 : 8;
+            dev_free(pts);
+            pts = nullptr;
+            if ((st = dev_alloc(&pts, size_t(T->dim) * size_t(Q) * psz)) != FT_OK) break;
+            if ((st = emit_points(T, &c, pts, s)) != FT_OK) break;
+            const int64_t m = std::max<int64_t>(1, std::min<int64_t>(T->E, (int64_t(1) << 21) / N));
+            const int64_t t0 = (T->E - m) / 2;
+            const int32_t base = source_default_cells(S);
+            std::vector<int32_t> cand;
+            for (double f : {0.6, 0.8, 1.0, 1.25, 1.6}) {
+                const int32_t v = std::max<int32_t>(2, int32_t(std::lround(base * f)));
+                if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+            }
+            const char* sample = static_cast<const char*>(pts) + (T->n + t0 * N) * psz;
+            if ((st = source_autotune(S, 0, m * N, sample, Q, c.precision == FT_F32 ? FT_F32 : FT_F64,
+                                      int(cand.size()), cand.data(), s)) != FT_OK)
+                break;
+            e.bins_scale = double(source_cells_longest(S)) / double(base);
+            rebinned.insert(S);
+            // element variant: the batch kernel of each candidate on this transfer's tiles
+            if ((st = refresh_descriptors(b, s)) != FT_OK) break;
+            dev_free(d_tiles);
+            d_tiles = nullptr;
+            // one tile per wavefront: E tiles for one element per wave, fewer otherwise
+            if ((st = dev_alloc_n(&d_tiles, size_t(T->E))) != FT_OK) break;
+            float best = INFINITY;
+            for (int v = 0; v < kVariants && st == FT_OK; ++v) {
+                float ms = 0.0f;
+                st = time_variant(b, rep, v, d_tiles, e0, e1, s, &ms);
+                if (st == FT_OK && ms < best) {
+                    best = ms;
+                    e.var = v;
+                }
+            }
+            e.ms = best;
+            cache[g.first] = e;
+            ++tuned;
+        }
+        // the group's choices for all its transfers
+        for (int k : g.second) {
+            b->var[k] = e.var;
+            ft_source* S = b->S[k];
+            if (rebinned.count(S)) continue;
+            const int32_t cells = std::max<int32_t>(2, int32_t(std::lround(source_default_cells(S) * e.bins_scale)));
+            if (cells != source_cells_longest(S) && (st = source_rebin(S, cells, s)) != FT_OK) break;
+            rebinned.insert(S);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != FT_OK) return st;
+    FT_TRY(build_element_tiles(b, s));
+    FT_TRY(refresh_descriptors(b, s));
+    if (b->exec) {   // the launches changed: the next run captures again
+        FT_TRY_HIP(hipGraphExecDestroy(b->exec));
+        b->exec = nullptr;
+    }
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    if (!write_tune_cache(cache_path, cache)) {
+        set_error("cannot write the autotuning cache %s", cache_path);
+        return FT_E_ARG;
+    }
+    if (n_tuned) *n_tuned = tuned;
+    return FT_OK;
+}
+
+int batch_count(const ft_batch* b) { return b->count; }
+
+// The element-stage variant of transfer k as (G, P).
+void batch_variant(const ft_batch* b, int k, int32_t* G, int32_t* P) {
+    *G = lanes_of(b->var[k]);
+    *P = per_lane_of(b->var[k]);
+}
+
 ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec, ft_report* rep,
                     int32_t* status, hipStream_t s) {
     const int K = b->count;
-    // descriptors that point at memory a target or source has since replaced are
-    // refreshed (the kernels, and a captured graph, read the table at run time)
-    {
-        std::vector<BatchXfer> xs = b->h_x;
-        for (int k = 0; k < K; ++k) {
-            fill_live(b, k, xs[k]);
-            b->T[k]->fields_inner = false;   // the batch writes one field, [F][n] layout
-        }
-        if (std::memcmp(xs.data(), b->h_x.data(), sizeof(BatchXfer) * K) != 0) {
-            b->h_x = xs;
-            FT_TRY_HIP(hipMemcpyAsync(b->d_x, b->h_x.data(), sizeof(BatchXfer) * K, hipMemcpyHostToDevice, s));
-        }
-    }
+    FT_TRY(refresh_descriptors(b, s));
     for (int k = 0; k < K; ++k) {
         b->h_xs[k] = x[k];
         b->h_xs[K + k] = bvec ? bvec[k] : nullptr;

@@ -23,7 +23,11 @@ constexpr int kLamSlots = kStashLambda<D, P> ? 64 * P * (D + 1) : 0;
 // lane's non-finite and out-of-domain counts to nf / nood.  c_af: the wave's
 // LDS candidate slots (kWaveSlots<D> doubles), followed by its weight stash
 // (kLamSlots<D, P> doubles).
-template <int D, int G, int P, int FC>
+// F32: the binary32 form of the black-box route with the query list kept in
+// registers: weights from the binary32 sampling, the point formed in binary32
+// from binary32 vertex coordinates, the value rounded to binary32 (the
+// control values g must hold binary32-rounded values too); sums in binary64.
+template <int D, int G, int P, int FC, bool F32 = false>
 __device__ __forceinline__ void fused_elements(const SrcView& S, const double* __restrict__ X, int64_t n,
                                                const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                uint32_t E, uint32_t N, double alpha, SampleKey key,
@@ -60,11 +64,21 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
             const uint32_t j = j0 + q * G + lane;
             act[q] = valid && j < N;
             double lam[D + 1];
+            float lf[D + 1];
             if (act[q]) {
-                sample_lambda<D>(tt, j, key, lam);
+                if (F32) {
+                    sample_lambda_f32<D>(tt, j, key, lf);
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) lam[k] = lf[k];
+                } else {
+                    sample_lambda<D>(tt, j, key, lam);
+                }
             } else {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) lam[k] = 0.0;
+                for (int k = 0; k <= D; ++k) {
+                    lam[k] = 0.0;
+                    lf[k] = 0.0f;
+                }
             }
             if (kStashLambda<D, P>) {
                 double* st = c_af + kWaveSlots<D> + (q * (D + 1)) * 64 + (threadIdx.x & 63);
@@ -73,10 +87,17 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
             }
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                double x = lam[0] * xv[0][c];
+                if (F32) {
+                    float x = lf[0] * float(xv[0][c]);
 #pragma unroll
-                for (int k = 1; k <= D; ++k) x = fma(lam[k], xv[k][c], x);
-                pt[q][c] = x;
+                    for (int k = 1; k <= D; ++k) x = fmaf(lf[k], float(xv[k][c]), x);
+                    pt[q][c] = x;
+                } else {
+                    double x = lam[0] * xv[0][c];
+#pragma unroll
+                    for (int k = 1; k <= D; ++k) x = fma(lam[k], xv[k][c], x);
+                    pt[q][c] = x;
+                }
             }
         }
         double best[P];
@@ -96,13 +117,19 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
                 const double* st = c_af + kWaveSlots<D> + (q * (D + 1)) * 64 + (threadIdx.x & 63);
 #pragma unroll
                 for (int k = 0; k <= D; ++k) lam[k] = st[k * 64];
+            } else if (F32) {
+                float lf[D + 1];
+                sample_lambda_f32<D>(tt, j0 + q * G + lane, key, lf);
+#pragma unroll
+                for (int k = 0; k <= D; ++k) lam[k] = lf[k];
             } else {
                 sample_lambda<D>(tt, j0 + q * G + lane, key, lam);
             }
 #pragma unroll
             for (int f = 0; f < FC; ++f) {
                 if (f >= S.F) break;
-                const double y = p1_value<D>(S, bid[q], mu, f);
+                double y = p1_value<D>(S, bid[q], mu, f);
+                if (F32) y = double(float(y));
                 nf += !isfinite(y);
                 double gx = lam[0] * gk[f][0];
 #pragma unroll

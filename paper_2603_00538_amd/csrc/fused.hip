@@ -19,7 +19,7 @@ namespace ft {
 // with one element per wave and at most two samples per lane (the other 3D
 // variants would spill at three and keep two).  The unconstrained allocation
 // leaves two waves per SIMD (2D: 21% slower).
-template <int D, int G, int P, int FC>
+template <int D, int G, int P, int FC, bool F32>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(FC != 1 ? 1 : (D == 2 ? 4 : (G == 64 && P <= 2 ? 3 : 2)))))
 void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
@@ -30,8 +30,8 @@ void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n, const int32_
     __shared__ double lds[4 * WS];
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
     unsigned nf = 0, nood = 0;
-    fused_elements<D, G, P, FC>(S, X, n, conn, vol, E, N, alpha, key, g, beta, gid / G, int(gid & (G - 1)), nf, nood,
-                                lds + (threadIdx.x >> 6) * WS);
+    fused_elements<D, G, P, FC, F32>(S, X, n, conn, vol, E, N, alpha, key, g, beta, gid / G, int(gid & (G - 1)), nf,
+                                     nood, lds + (threadIdx.x >> 6) * WS);
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
     if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
@@ -46,9 +46,23 @@ template <int D, int G, int P, int FC>
 static void launch_fused(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
     const SampleKey key = make_sample_key(*cfg, D);
     const unsigned grid = grid_for(T->E * G, 256);
-    k_fused_p1<D, G, P, FC><<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
-                                             uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta,
-                                             T->counters, T->counters + 1);
+    auto kern = cfg->precision == FT_F32 ? k_fused_p1<D, G, P, FC, true> : k_fused_p1<D, G, P, FC, false>;
+    kern<<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
+                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta, T->counters,
+                              T->counters + 1);
+}
+
+// The control of the binary32 form: the source at the target nodes rounded to
+// binary32, the values rounded to binary32 (as its query list holds them).
+template <int D>
+__global__ __launch_bounds__(64) void k_nodes_rounded(SrcView S, const double* __restrict__ X, int64_t n,
+                                                      double* __restrict__ g, unsigned long long* __restrict__ n_ood) {
+    constexpr int P = D == 2 ? 4 : 2;
+    __shared__ double lds[kWaveSlots<D>];
+    const int64_t base = int64_t(blockIdx.x) * 64 * P;
+    if (base >= n) return;
+    const unsigned nood = eval_wave<D, P, false, false, true>(S, base, n, X, n, g, n, nullptr, lds);
+    if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
 
 template <int D, int G, int P>
@@ -77,7 +91,13 @@ ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipS
     zero_counters(T->counters, 2, s);
     T->ood_mode = 1;
     // step 1: the control, f^s at the target nodes, straight into T->g
-    FT_TRY(source_eval(S, 0, T->n, T->coords, T->n, FT_F64, T->g, T->n, nullptr, s, T->counters + 1));
+    if (cfg->precision == FT_F32) {
+        const unsigned gw = grid_for(T->n, 64 * (T->dim == 2 ? 4 : 2));
+        if (T->dim == 2) k_nodes_rounded<2><<<gw, 64, 0, s>>>(source_view(S), T->coords, T->n, T->g, T->counters + 1);
+        else k_nodes_rounded<3><<<gw, 64, 0, s>>>(source_view(S), T->coords, T->n, T->g, T->counters + 1);
+    } else {
+        FT_TRY(source_eval(S, 0, T->n, T->coords, T->n, FT_F64, T->g, T->n, nullptr, s, T->counters + 1));
+    }
     if (T->dim == 2) fused_g<2>(T, S, cfg, s);
     else fused_g<3>(T, S, cfg, s);
     FT_TRY_HIP(hipGetLastError());

@@ -450,7 +450,10 @@ __device__ __forceinline__ double p1_value(const SrcView& S, int bid, const doub
 // Localize and evaluate the points [base, min(base + 64P, lim)) of a (d, ld)
 // point array: lane l takes points base + q*64 + l.  Writes values (and ids
 // if non-null) and returns this lane's count of out-of-domain points.
-template <int D, int P, bool IN_F32, bool OUT_F32>
+// ROUND (binary64 points and values): the points are rounded to binary32
+// before the search and the values to binary32 when stored, as the binary32
+// form's query list holds them.
+template <int D, int P, bool IN_F32, bool OUT_F32, bool ROUND = false>
 __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, int64_t lim,
                                               const void* __restrict__ pts_, int64_t ld, void* __restrict__ out_,
                                               int64_t ld_out, int32_t* __restrict__ ids, double* __restrict__ c_af) {
@@ -465,6 +468,8 @@ __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, in
         for (int c = 0; c < D; ++c) {
             if (IN_F32)
                 p[q][c] = active[q] ? double(static_cast<const float*>(pts_)[c * ld + i]) : 0.0;
+            else if (ROUND)
+                p[q][c] = active[q] ? double(float(static_cast<const double*>(pts_)[c * ld + i])) : 0.0;
             else
                 p[q][c] = active[q] ? static_cast<const double*>(pts_)[c * ld + i] : 0.0;
         }
@@ -484,7 +489,8 @@ __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, in
         double mu[D + 1];
         winner_mu<D>(S, bid[q], p[q], mu);
         if (S.F == 1) {
-            const double y = p1_value<D>(S, bid[q], mu, 0);
+            double y = p1_value<D>(S, bid[q], mu, 0);
+            if (ROUND) y = double(float(y));
             if (OUT_F32)
                 static_cast<float*>(out_)[i] = float(y);
             else
@@ -503,6 +509,7 @@ __device__ __forceinline__ unsigned eval_wave(const SrcView& S, int64_t base, in
             if (found)
 #pragma unroll
                 for (int k = 0; k <= D; ++k) y = fma(mu[k], Fv[vk[k]], y);
+            if (ROUND) y = double(float(y));
             if (OUT_F32)
                 static_cast<float*>(out_)[int64_t(f) * ld_out + i] = float(y);
             else

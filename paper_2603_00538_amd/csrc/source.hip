@@ -725,6 +725,26 @@ ft_status source_integral(ft_source* S, double* out, hipStream_t s) {
     return FT_OK;
 }
 
+// Rebuild the bins with per_axis cells along the longest axis (the others
+// proportionally fewer); the current count along the longest axis.
+ft_status source_rebin(ft_source* S, int32_t per_axis, hipStream_t s) {
+    const int32_t none[3] = {0, 0, 0};
+    return S->dim == 2 ? build_bins<2>(S, none, double(per_axis), s) : build_bins<3>(S, none, double(per_axis), s);
+}
+
+// The default cells along the longest axis (sec. 5.3: int(sqrt(E)) in 2D;
+// round(0.75 cbrt(E / 6)) in 3D).
+int32_t source_default_cells(const ft_source* S) {
+    const double E = double(S->E);
+    return int32_t(S->dim == 2 ? std::floor(std::sqrt(E)) : std::max(1.0, std::round(0.75 * std::cbrt(E / 6.0))));
+}
+
+int32_t source_cells_longest(const ft_source* S) {
+    int32_t m = 1;
+    for (int c = 0; c < S->dim; ++c) m = std::max(m, S->nb[c]);
+    return m;
+}
+
 ft_status source_release(ft_source* S) {
     dev_free(S->coords);
     dev_free(S->conn);

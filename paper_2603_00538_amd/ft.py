@@ -31,7 +31,8 @@ STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -
 EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
             "ft_consume_queries", "ft_consume_queries_noalloc", "ft_transfer_p1",
             "ft_transfer_supermesh", "ft_project", "ft_source_create_p1", "ft_source_eval",
-            "ft_source_eval_queries", "ft_source_eval_tiles", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_destroy",
+            "ft_source_eval_queries", "ft_source_eval_tiles", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_autotune", "ft_batch_variant",
+            "ft_batch_destroy",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_last_error"]
 
@@ -107,6 +108,8 @@ def load(path: str = LIB_PATH):
         "ft_batch_create": (I32, [I32, P, P, ctypes.POINTER(SampleCfg), I32, P, ctypes.POINTER(P)]),
         "ft_batch_run": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P, P]),
         "ft_batch_destroy": (I32, [P]),
+        "ft_batch_autotune": (I32, [P, ctypes.c_char_p, ctypes.POINTER(I32), P]),
+        "ft_batch_variant": (I32, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "ft_plan_create": (I32, [P, P, ctypes.POINTER(SampleCfg), P, ctypes.POINTER(P)]),
         "ft_plan_transfer": (I32, [P, P, P]),
         "ft_plan_destroy": (I32, [P]),
@@ -215,6 +218,19 @@ def ft_plan_transfer(h, values_ptr, stream):
 
 def ft_plan_destroy(h):
     return _check(load().ft_plan_destroy(h), "ft_plan_destroy")
+
+
+def ft_batch_autotune(h, cache_path, stream):
+    n = ctypes.c_int32(0)
+    _check(load().ft_batch_autotune(h, cache_path.encode() if cache_path else None, ctypes.byref(n), stream),
+           "ft_batch_autotune")
+    return n.value
+
+
+def ft_batch_variant(h, k):
+    g, p = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load().ft_batch_variant(h, k, ctypes.byref(g), ctypes.byref(p)), "ft_batch_variant")
+    return g.value, p.value
 
 
 def ft_batch_destroy(h):
@@ -535,6 +551,14 @@ class Batch:
         bp = [_device_ptr(b, "b", f64) for b in bs] if want_b else None
         st, reps, sts = ft_batch_run(self.handle, SolveCfg(rtol, max_iter), xp, bp, current_stream())
         return xs, bs, reps, sts, st
+
+    def autotune(self, cache_path=None):
+        """ft_batch_autotune: returns the number of transfer kinds timed (0: all from the cache)."""
+        return ft_batch_autotune(self.handle, cache_path, current_stream())
+
+    def variant(self, k):
+        """(lanes per element, samples per lane) of transfer k's element stage."""
+        return ft_batch_variant(self.handle, k)
 
     def close(self):
         if getattr(self, "handle", None):

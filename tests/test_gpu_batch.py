@@ -122,7 +122,7 @@ def test_batch_rejects_bad_configurations(batch_case):
     with pytest.raises(ft.FtError) as e:
         ft.Batch([targets[0], targets[0]], [sources[0], sources[0]], [cfgs[0], cfgs[0]])
     assert e.value.status == ft.FT_E_ARG
-    bad = ft.SampleCfg(cfgs[0].samples_per_elem, 1, 1.0, SEED, 0, ft.FT_F32)
+    bad = ft.SampleCfg(cfgs[0].samples_per_elem, 1, 1.0, SEED, 0, ft.FT_SPLIT_F16)   # matrix-core form: not batched
     with pytest.raises(ft.FtError) as e:
         ft.Batch([targets[0]], [sources[0]], [bad])
     assert e.value.status == ft.FT_E_UNSUPPORTED

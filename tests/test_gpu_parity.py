@@ -426,8 +426,8 @@ def test_fused_route_matches_unfused_and_oracle(dim, N):
     o = oracle_transfer(tm, sm, sv, N, 1.0, 77, 1)
     assert rel_l2(b, o["b"]) < 1e-12 and rel_l2(x, o["x"]) < 1e-12
     assert S.take_out_of_domain() == 0
-    with pytest.raises(ft.FtError) as e:
-        T.transfer_from(S, ft.SampleCfg(N, 1, 1.0, 77, 1, ft.FT_F32))
+    with pytest.raises(ft.FtError) as e:   # the matrix-core forms have no fused route
+        T.transfer_from(S, ft.SampleCfg(N, 1, 1.0, 77, 1, ft.FT_SPLIT_BF16))
     assert e.value.status == ft.FT_E_UNSUPPORTED
     T.close()
     S.close()
