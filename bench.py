@@ -741,7 +741,7 @@ def main():
         plan.close()
 
     supermesh_route = None
-    if args.route == "blackbox" and not args.no_fused and dim == 2 and F <= 4:
+    if args.route == "blackbox" and not args.no_fused and F <= 4:
         # the exact load vector by mesh intersection (the paper's comparator):
         # its time, and the Monte Carlo load vector's distance from it
         b_mc = b.clone()

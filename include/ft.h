@@ -139,6 +139,16 @@ typedef struct {
                                 /* the built-in source routes (ft_transfer_p1, plans, batches);    */
                                 /* -1 after ft_consume_queries: the caller's black box evaluated   */
                                 /* the points (ft_source_stats counts ft_source_eval's)            */
+    double  sum_b_stderr;       /* estimated standard error of sum_b from the samples themselves    */
+                                /* (App. B, Eq. cv_global_integral_estimator: the element totals    */
+                                /* |Omega_t|/N sum_j r_tj are independent, so Var(sum b) is the     */
+                                /* sum of |Omega_t|^2 s_t^2 / N, s_t^2 the unbiased sample variance */
+                                /* of element t's residuals r = y - alpha g; with each element's    */
+                                /* own alpha, that alpha).  Its square estimates E[E_cons^2] of     */
+                                /* Eq. conservation_residual_bound.  Reported after                 */
+                                /* ft_consume_queries (FT_F64, FT_F32), ft_transfer_p1 and plans    */
+                                /* with N >= 2; 0 after ft_transfer_supermesh (exact b); -1 where   */
+                                /* not estimated (N = 1, the split matrix-core forms, batches)      */
 } ft_report;
 
 /* Sizes of a target after setup. */
@@ -273,18 +283,20 @@ ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
  * ft_transfer_supermesh - the exact load vector b_i = integral f^s psi_i of
  * the built-in P1 source, by mesh intersection (sec. 3): every target
  * element is intersected with every source element that meets it (the
- * candidates come from the source's bin grid), each convex intersection
- * polygon is split into triangles fanned from its first vertex and
- * integrated with the degree-2 Gauss rule, which is exact for the quadratic
- * f^s psi_i there.  The reference the Monte Carlo estimate converges to, and
- * the paper's intersection-based comparator.  Follow with ft_project, which
- * then solves M x = b with no control part (alpha = 0, start x = 0);
- * ft_report.n_out_of_domain counts the target elements the source does not
- * cover entirely.  Triangles only (FT_E_UNSUPPORTED in 3D), at most 4
- * fields.
+ * candidates come from the source's bin grid) and f^s psi_i, quadratic on
+ * each intersection, is integrated exactly by a degree-2 rule.  Triangles:
+ * the intersection polygon (target clipped by the three edge half-planes of
+ * the source) is fanned from its first vertex, three-point rule per
+ * sub-triangle.  Tetrahedra: the target is cut by the four face half-spaces
+ * of the source, each cut leaving tetrahedra (a corner, or a prism split in
+ * three), four-point rule per tetrahedron.  The reference the Monte Carlo
+ * estimate converges to, and the paper's intersection-based comparator.
+ * Follow with ft_project, which then solves M x = b with no control part
+ * (alpha = 0, start x = 0); ft_report.n_out_of_domain counts the target
+ * elements the source does not cover entirely.  At most 4 fields.
  *   area   device, binary64, [n_elems] or null: per target element, the sum
- *          of the areas of its intersections (= |Omega_t| where the source
- *          covers it)
+ *          of the areas (volumes) of its intersections (= |Omega_t| where the
+ *          source covers it)
  * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Asynchronous on `stream`.
  */
 ft_status ft_transfer_supermesh(ft_target* t, ft_source* s, double* area, hipStream_t stream);
@@ -502,6 +514,17 @@ ft_status ft_batch_autotune(ft_batch* b, const char* cache_path, int32_t* n_tune
 ft_status ft_batch_variant(const ft_batch* b, int32_t k, int32_t* lanes_per_elem, int32_t* samples_per_lane);
 
 ft_status ft_batch_destroy(ft_batch* b);
+
+/* Samples per element for a target relative standard error of sum b
+ * (App. B, Eq. conservation_residual_bound: E[E_cons^2] falls as 1/N):
+ * ceil(N (sum_b_stderr / (rel_tol |sum_b|))^2), at least 1, at most 2^20.
+ *   rep               host, a report of a transfer made with N samples per element
+ *   samples_per_elem  that N
+ *   rel_tol           the target standard error relative to |sum_b| (> 0)
+ * Returns 1 when the report's standard error is 0 (no sampling error) or
+ * sum_b is 0; -1 when the report carries no estimate (sum_b_stderr < 0) or
+ * an argument is invalid.  Host-only, touches no device memory. */
+int32_t ft_samples_for_tolerance(const ft_report* rep, int32_t samples_per_elem, double rel_tol);
 
 /* Message describing the last failure on this thread ("" if none). */
 const char* ft_last_error(void);

@@ -27,7 +27,10 @@ Parity: pinned by special cases (affine source is reproduced exactly with
 alpha = 1; constant source conserves sum(b) = c |domain| for every alpha;
 source mesh == target mesh reproduces the nodal field), the discrete
 conservation identity m^T x = sum(b), unbiasedness against the exact
-supermesh load vector, and the N^-1/2 decay of the error.
+supermesh load vector, and the N^-1/2 decay of the error.  The standard
+error of sum b (App. B) is pinned by a closed-form residual variance (Dirichlet
+moments of the barycentric weights), by the spread of sum b over independent
+realizations, and by an affine source (zero residual, zero error).
 """
 from __future__ import annotations
 
@@ -131,6 +134,34 @@ def element_loads_own_alpha(coords, conn, g, y, lam, elems=None):
     return beta, alpha
 
 
+def element_variance_terms(coords, conn, r, elems=None):
+    """Variance of each element's Monte Carlo total |Omega_t|/N sum_j r_tj
+    (the part of sum_k b^t_k the samples estimate; sum_k psi_k = 1), estimated
+    from its own residuals: |Omega_t|^2 s_t^2 / N with s_t^2 the unbiased
+    sample variance of r_tj over j.  r: (F, E', N).  Returns (F, E'), zeros
+    for N < 2.  Summed over the elements (independent samples) it is the
+    variance of the estimate of sum_i b_i = integral f^s (App. B,
+    Eq. cv_global_integral_estimator; its expectation is the E[E_cons^2] that
+    Eq. conservation_residual_bound bounds)."""
+    if elems is None:
+        elems = np.arange(conn.shape[0])
+    vol = geometry.element_measures(coords, conn[elems])
+    N = r.shape[2]
+    if N < 2:
+        return np.zeros(r.shape[:2])
+    s2 = r.var(axis=2, ddof=1)
+    return (vol ** 2)[None, :] * s2 / N
+
+
+def samples_for_tolerance(stderr: float, sum_b: float, n_samples: int, rel_tol: float) -> int:
+    """Samples per element for which the standard error of sum b, which falls
+    as N^-1/2, reaches rel_tol |sum b|: ceil(N (stderr / (rel_tol |sum b|))^2)."""
+    target = rel_tol * abs(sum_b)
+    if target <= 0.0 or stderr <= 0.0:
+        return 1
+    return int(min(1 << 20, max(1, math.ceil(n_samples * (stderr / target) ** 2))))
+
+
 def assemble(conn: np.ndarray, beta: np.ndarray, n_nodes: int) -> np.ndarray:
     """Step 6 (residual part): b_res,v = sum of beta over (element, local vertex) at v."""
     b = np.zeros((beta.shape[0], n_nodes))
@@ -177,8 +208,9 @@ def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_
 
     own_alpha: each element's own control coefficient (element_loads_own_alpha);
     the control part is then inside the element loads and b_g is zero.
-    Returns a dict with g, b_g, b_res, b, x, the mass matrix, lumped mass and
-    the conservation report.
+    Returns a dict with g, b_g, b_res, b, x, the mass matrix, lumped mass, the
+    conservation report (with sum_b_stderr: the standard error of sum b from
+    the element variance terms, -1 for N = 1) and var_terms (F, E).
     """
     coords = np.asarray(coords, dtype=np.float64)
     conn = np.asarray(conn, dtype=np.int64)
@@ -188,6 +220,7 @@ def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_
     F = g.shape[0]
     b_g = control_load(coords, conn, g, 0.0 if own_alpha else alpha)   # step 2
     beta = np.empty((F, E, dim + 1))
+    var_terms = np.empty((F, E))
     alphas = np.empty((F, E)) if own_alpha else None
     for s in range(0, E, chunk_elems):
         el = np.arange(s, min(E, s + chunk_elems))
@@ -195,16 +228,24 @@ def transfer(coords, conn, query, n_samples, alpha=1.0, seed=0, stream=0, chunk_
         y = np.atleast_2d(query(X.reshape(-1, dim))).reshape(F, el.size, n_samples)  # step 4
         if own_alpha:                                                                  # step 5
             beta[:, el], alphas[:, el] = element_loads_own_alpha(coords, conn, g, y, lam, el)
+            a_el = alphas[:, el][..., None]
         else:
             beta[:, el] = element_loads(coords, conn, g, y, lam, alpha, el)
+            a_el = alpha
+        g_at = np.einsum("tjk,ftk->ftj", lam, g[:, conn[el]])
+        var_terms[:, el] = element_variance_terms(coords, conn, y - a_el * g_at, el)
     b_res = assemble(conn, beta, n)                                  # step 6
     b = b_g + b_res
     M = geometry.mass_matrix(coords, conn)
     x = solve_mass(M, b, dim)                                        # step 7
     m = geometry.lumped_mass(coords, conn)
+    report = conservation_report(b, x, m)
+    for f, rep in enumerate(report):
+        # no spread to estimate from a single sample per element
+        rep["sum_b_stderr"] = math.sqrt(math.fsum(var_terms[f])) if n_samples >= 2 else -1.0
     return {
         "g": g, "b_g": b_g, "beta": beta, "b_res": b_res, "b": b, "x": x,
-        "M": M, "m": m, "report": conservation_report(b, x, m), "alpha_elements": alphas,
+        "M": M, "m": m, "report": report, "alpha_elements": alphas, "var_terms": var_terms,
     }
 
 

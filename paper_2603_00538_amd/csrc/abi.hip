@@ -47,9 +47,11 @@ ft_status noalloc_scratch(double** out);
 static void target_release(ft_target* T) {
     void* ps[] = {T->coords, T->conn, T->vol, T->rowptr, T->col, T->val, T->diag, T->lumped, T->inc_ptr, T->inc,
                   T->beta, T->g, T->bres, T->r, T->z, T->p, T->q, T->y, T->b, T->scal, T->partials,
-                  T->counters, T->val32, T->diag32, T->w32, T->scal32, T->mf_vec, T->mf_sc, T->mf_part};
+                  T->counters, T->val32, T->diag32, T->w32, T->scal32, T->mf_vec, T->mf_sc, T->mf_part,
+                  T->var_el, T->var_tot, T->var_part};
     for (void* p : ps) dev_free(p);
     if (T->h_scal) (void)hipHostFree(T->h_scal);
+    if (T->h_var) (void)hipHostFree(T->h_var);
 }
 
 ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
@@ -81,11 +83,20 @@ ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream) {
     dev_free(T->beta);
     dev_free(T->g);
     dev_free(T->bres);
-    T->beta = T->g = T->bres = nullptr;
+    dev_free(T->var_el);
+    dev_free(T->var_tot);
+    dev_free(T->var_part);
+    if (T->h_var) (void)hipHostFree(T->h_var);
+    T->beta = T->g = T->bres = T->var_el = T->var_tot = T->var_part = T->h_var = nullptr;
     T->F_cap = 0;
+    T->var_mode = VAR_NONE;
     FT_TRY(dev_alloc_n(&T->beta, size_t(F) * size_t(T->E) * (T->dim + 1)));
     FT_TRY(dev_alloc_n(&T->g, size_t(F) * size_t(T->n)));
     FT_TRY(dev_alloc_n(&T->bres, size_t(F) * size_t(T->n)));
+    FT_TRY(dev_alloc_n(&T->var_el, size_t(F) * size_t(T->E)));
+    FT_TRY(dev_alloc_n(&T->var_tot, size_t(F)));
+    FT_TRY(dev_alloc_n(&T->var_part, size_t(F) * kVarBlocks * 2));
+    FT_TRY_HIP(hipHostMalloc((void**)&T->h_var, size_t(F) * sizeof(double), hipHostMallocDefault));
     T->F_cap = F;
     return FT_OK;
 }
@@ -294,8 +305,8 @@ ft_status ft_transfer_supermesh(ft_target* t, ft_source* s, double* area, hipStr
     clear_error();
     FT_ARG_CHECK(t && s, "target and source must be non-null");
     FT_ARG_CHECK(s->dim == t->dim, "source dimension %d differs from target dimension %d", s->dim, t->dim);
-    if (t->dim != 2 || s->F > 4) {
-        set_error("the intersection route supports triangles and at most 4 fields");
+    if (s->F > 4) {
+        set_error("the intersection route supports at most 4 fields");
         return FT_E_UNSUPPORTED;
     }
     FT_TRY(ensure_field_buffers(t, s->F, stream));
@@ -585,6 +596,17 @@ ft_status ft_source_destroy(ft_source* s) {
     source_release(s);
     delete s;
     return FT_OK;
+}
+
+int32_t ft_samples_for_tolerance(const ft_report* rep, int32_t samples_per_elem, double rel_tol) {
+    if (!rep || samples_per_elem < 1 || !(rel_tol > 0.0) || std::isnan(rep->sum_b_stderr) || rep->sum_b_stderr < 0.0)
+        return -1;
+    const double target = rel_tol * std::fabs(rep->sum_b);
+    if (rep->sum_b_stderr == 0.0 || !(target > 0.0)) return 1;
+    const double r = rep->sum_b_stderr / target;
+    const double n = std::ceil(double(samples_per_elem) * r * r);
+    if (!(n < double(1 << 20))) return 1 << 20;
+    return n < 1.0 ? 1 : int32_t(n);
 }
 
 const char* ft_last_error(void) { return ft::last_error(); }

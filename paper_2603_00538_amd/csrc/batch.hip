@@ -954,6 +954,8 @@ ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, doub
         R.n_nonfinite = int64_t(b->h_nf[k]);
         R.n_out_of_domain = int64_t(b->h_nf[K + k]);
         b->T[k]->ood_mode = 2;   // a later ft_project of this target reports the same count
+        b->T[k]->var_mode = VAR_NONE;
+        R.sum_b_stderr = -1.0;
         b->T[k]->ood_host = R.n_out_of_domain;
         R.status = b->h_nf[k] ? FT_E_NONFINITE : (h[BS_DONE] != 0.0 ? FT_OK : FT_E_NOCONV);
         if (status) status[k] = R.status;

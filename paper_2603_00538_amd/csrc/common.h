@@ -186,6 +186,86 @@ __device__ __forceinline__ double wave_sum_xor(double v, int width) {
     return v;
 }
 
+// ---- totals of K binary64 values over the 64 lanes, returned wave-uniform.
+// First the values are folded into rows of 16 lanes with the gfx950 lane-swap
+// instructions: v_permlane32_swap exchanges the upper 32 lanes of one value
+// with the lower 32 lanes of another, so one add leaves value i's partial sums
+// in lanes 0-31 and value i+A's in lanes 32-63; v_permlane16_swap does the
+// same between 16-lane rows, after which each row holds partial sums of a
+// different value.  Each row is then summed on the DPP crossbar (quad
+// permutations for lanes i^1 and i^2, the half-row and row mirrors; every lane
+// of a row ends with the same total, since binary64 addition commutes), and
+// the totals are read from lanes 0, 16, 32, 48.  No LDS traffic, and a fixed
+// order of additions: the same totals every run.
+__device__ __forceinline__ void swap_halves32(double& x, double& y) {
+    const unsigned long long xb = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long yb = __builtin_bit_cast(unsigned long long, y);
+    const auto lo = __builtin_amdgcn_permlane32_swap(unsigned(xb), unsigned(yb), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(unsigned(xb >> 32), unsigned(yb >> 32), false, false);
+    x = __builtin_bit_cast(double, (static_cast<unsigned long long>(hi[0]) << 32) | lo[0]);
+    y = __builtin_bit_cast(double, (static_cast<unsigned long long>(hi[1]) << 32) | lo[1]);
+}
+
+__device__ __forceinline__ void swap_rows16(double& x, double& y) {
+    const unsigned long long xb = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long yb = __builtin_bit_cast(unsigned long long, y);
+    const auto lo = __builtin_amdgcn_permlane16_swap(unsigned(xb), unsigned(yb), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(unsigned(xb >> 32), unsigned(yb >> 32), false, false);
+    x = __builtin_bit_cast(double, (static_cast<unsigned long long>(hi[0]) << 32) | lo[0]);
+    y = __builtin_bit_cast(double, (static_cast<unsigned long long>(hi[1]) << 32) | lo[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(int(unsigned(u)), int(unsigned(u)), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(int(unsigned(u >> 32)), int(unsigned(u >> 32)), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo));
+}
+
+__device__ __forceinline__ double row_sum_f64(double v) {
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror: the two quads of each half-row
+    v += dpp_f64<0x140>(v);   // row_mirror: the two halves of the row
+    return v;
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readlane(unsigned(u), lane);
+    const unsigned hi = __builtin_amdgcn_readlane(unsigned(u >> 32), lane);
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// All 64 lanes must be active.  v[i] becomes the wave-uniform total of v[i].
+template <int K>
+__device__ __forceinline__ void wave_totals(double (&v)[K]) {
+    constexpr int A = (K + 1) / 2;   // values after the 32-lane fold
+    constexpr int B = (A + 1) / 2;   // after the 16-lane fold: one per row
+    double a[A];
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+        double x = v[i], y = i + A < K ? v[i + A] : 0.0;
+        swap_halves32(x, y);
+        a[i] = x + y;   // lanes 0-31: value i, lanes 32-63: value i + A
+    }
+    double b[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        double x = a[i], y = i + B < A ? a[i + B] : 0.0;
+        swap_rows16(x, y);
+        b[i] = row_sum_f64(x + y);   // rows 0..3: values i, i + B, i + A, i + A + B
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        v[i] = lane_f64(b[i], 0);
+        if (i + B < A) v[i + B] = lane_f64(b[i], 16);
+        if (i + A < K) v[i + A] = lane_f64(b[i], 32);
+        if (i + A + B < K && i + B < A) v[i + A + B] = lane_f64(b[i], 48);
+    }
+}
+
 // Binary32 minimum / maximum over the 64 lanes, returned wave-uniform (in
 // scalar registers): butterflies inside each row of 16 lanes on the DPP
 // crossbar (quad permutations for lanes i^1 and i^2, row rotations by 4 and 8),
@@ -224,6 +304,15 @@ __device__ __forceinline__ int uniform_int(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// The variance of an element's Monte Carlo total |Omega|/N sum_j r_j from the
+// sum s1 and the sum of squares s2 of its N residuals (shifted by any
+// constant): |Omega|^2 s^2 / N, s^2 the unbiased sample variance.  inv_n =
+// 1/N, inv_var = 1/(N (N - 1)) (0 for N < 2, which gives 0).
+__device__ __forceinline__ double element_variance(double vol, double s1, double s2, double inv_n, double inv_var) {
+    const double ss = fmax(s2 - s1 * (s1 * inv_n), 0.0);   // sum of squared deviations
+    return vol * vol * ss * inv_var;
+}
+
 // A value known to be equal in every lane, moved to scalar registers.
 __device__ __forceinline__ double uniform_double(double v) {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
@@ -235,6 +324,11 @@ __device__ __forceinline__ double uniform_double(double v) {
 }  // namespace ft
 
 // ---------------------------------------------------------------- handles
+// blocks of the per-field reduction of the element variances
+constexpr int kVarBlocks = 64;
+// what the last transfer says about the standard error of sum b
+enum { VAR_NONE = 0, VAR_ESTIMATED = 1, VAR_EXACT = 2 };
+
 struct ft_target {
     int dim = 0;
     int64_t n = 0, E = 0, nnz = 0, n_inverted = 0;
@@ -257,6 +351,14 @@ struct ft_target {
     double* g = nullptr;        // [F][n], or [n][F] when fields_inner
     double* bres = nullptr;     // [F][n], or [n][F] when fields_inner
     bool fields_inner = false;  // layout of the last transfer (many-field matrix-core route)
+    // the variance of each element's Monte Carlo total, [F][E] (written by the
+    // black-box consumption, the fused route and plans: VAR_ESTIMATED after
+    // them), its per-field sums [F] and their block partials [F][kVarBlocks][2]
+    double* var_el = nullptr;
+    double* var_tot = nullptr;
+    double* var_part = nullptr;
+    double* h_var = nullptr;    // pinned host copy of var_tot
+    int var_mode = 0;           // VAR_NONE, VAR_ESTIMATED or VAR_EXACT (no sampling error)
     // solver work vectors and reduction scratch
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *y = nullptr, *b = nullptr;
     double* scal = nullptr;               // device scalars

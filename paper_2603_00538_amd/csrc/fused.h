@@ -27,12 +27,15 @@ constexpr int kLamSlots = kStashLambda<D, P> ? 64 * P * (D + 1) : 0;
 // registers: weights from the binary32 sampling, the point formed in binary32
 // from binary32 vertex coordinates, the value rounded to binary32 (the
 // control values g must hold binary32-rounded values too); sums in binary64.
+// var_el (unless null): each element's variance term, as the consumption
+// kernel writes it (sum and sum of squares of r - (1 - alpha) gbar).
 template <int D, int G, int P, int FC, bool F32 = false>
 __device__ __forceinline__ void fused_elements(const SrcView& S, const double* __restrict__ X, int64_t n,
                                                const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                uint32_t E, uint32_t N, double alpha, SampleKey key,
                                                const double* __restrict__ g, double* __restrict__ beta, uint32_t t,
-                                               int lane, unsigned& nf, unsigned& nood, double* __restrict__ c_af) {
+                                               int lane, unsigned& nf, unsigned& nood, double* __restrict__ c_af,
+                                               double* __restrict__ var_el = nullptr) {
     // with one element per wave, its connectivity, vertices and control values
     // are wave-uniform: scalar loads into scalar registers
     if (G == 64) t = __builtin_amdgcn_readfirstlane(t);
@@ -46,14 +49,19 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
     for (int k = 0; k <= D; ++k)
 #pragma unroll
         for (int c = 0; c < D; ++c) xv[k][c] = X[c * n + v[k]];
-    double gk[FC][D + 1], acc[FC][D + 1];
+    double gk[FC][D + 1], acc[FC][D + 1], vs[FC], sh[FC];
 #pragma unroll
-    for (int f = 0; f < FC; ++f)
+    for (int f = 0; f < FC; ++f) {
+        vs[f] = 0.0;
+        double gs = 0.0;   // summed in vertex order, as the consumption kernel does
 #pragma unroll
         for (int k = 0; k <= D; ++k) {
             acc[f][k] = 0.0;
             gk[f][k] = f < S.F ? g[int64_t(f) * n + v[k]] : 0.0;
+            gs += gk[f][k];
         }
+        sh[f] = (alpha - 1.0) * (gs * (1.0 / double(D + 1)));   // (alpha - 1) gbar
+    }
     // every lane runs the same number of rounds: the localization is wave-cooperative.
     // Round r, slot q of a lane holds sample j = r*G*P + q*G + lane.
     for (uint32_t j0 = 0; j0 < N; j0 += G * P) {
@@ -137,20 +145,50 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
                 const double r = y - alpha * gx;
 #pragma unroll
                 for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                if (var_el) {
+                    const double sv = r + sh[f];
+                    vs[f] = fma(sv, sv, vs[f]);
+                }
             }
         }
     }
+    // element totals as the consumption kernel forms them (lane-swap / DPP
+    // path with one element per wave, else butterflies over G lanes)
+    constexpr int K = FC * (D + 2);
+    double red[K];
 #pragma unroll
-    for (int f = 0; f < FC; ++f)
+    for (int f = 0; f < FC; ++f) {
 #pragma unroll
-        for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
+        for (int k = 0; k <= D; ++k) red[f * (D + 1) + k] = acc[f][k];
+        red[FC * (D + 1) + f] = vs[f];
+    }
+    if constexpr (G == 64) {
+        wave_totals<K>(red);
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) red[i] = wave_sum_xor(red[i], G);
+    }
+#pragma unroll
+    for (int f = 0; f < FC; ++f) {
+#pragma unroll
+        for (int k = 0; k <= D; ++k) acc[f][k] = red[f * (D + 1) + k];
+        vs[f] = red[FC * (D + 1) + f];
+    }
     if (valid && lane == 0) {
         const double scale = vol[t] / double(N);
+        const double Nd = double(N);
+        const double inv_n = 1.0 / Nd, inv_var = N > 1 ? inv_n / (Nd - 1.0) : 0.0;
 #pragma unroll
         for (int f = 0; f < FC; ++f) {
             if (f >= S.F) break;
 #pragma unroll
             for (int k = 0; k <= D; ++k) beta[(int64_t(f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+            if (var_el) {
+                double sa = 0.0;   // the plain sum of the residuals (the weights add up to 1)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) sa += acc[f][k];
+                var_el[int64_t(f) * E + t] = element_variance(vol[t], fma(Nd, sh[f], sa), vs[f], inv_n, inv_var);
+            }
         }
     }
 }

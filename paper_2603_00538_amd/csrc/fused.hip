@@ -24,14 +24,14 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(FC != 1 ? 1 : (D == 2 ? 4 : (G == 64 && P <= 2 ? 3 : 2)))))
 void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
                 const double* __restrict__ vol, uint32_t E, uint32_t N, double alpha, SampleKey key,
-                const double* __restrict__ g, double* __restrict__ beta, unsigned long long* __restrict__ nonfinite,
-                unsigned long long* __restrict__ n_ood) {
+                const double* __restrict__ g, double* __restrict__ beta, double* __restrict__ var_el,
+                unsigned long long* __restrict__ nonfinite, unsigned long long* __restrict__ n_ood) {
     constexpr int WS = kWaveSlots<D> + kLamSlots<D, P>;
     __shared__ double lds[4 * WS];
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
     unsigned nf = 0, nood = 0;
     fused_elements<D, G, P, FC, F32>(S, X, n, conn, vol, E, N, alpha, key, g, beta, gid / G, int(gid & (G - 1)), nf,
-                                     nood, lds + (threadIdx.x >> 6) * WS);
+                                     nood, lds + (threadIdx.x >> 6) * WS, var_el);
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
     if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
@@ -48,8 +48,8 @@ static void launch_fused(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, h
     const unsigned grid = grid_for(T->E * G, 256);
     auto kern = cfg->precision == FT_F32 ? k_fused_p1<D, G, P, FC, true> : k_fused_p1<D, G, P, FC, false>;
     kern<<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
-                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta, T->counters,
-                              T->counters + 1);
+                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta, T->var_el,
+                              T->counters, T->counters + 1);
 }
 
 // The control of the binary32 form: the source at the target nodes rounded to
@@ -90,6 +90,7 @@ ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipS
     // non-finite values and out-of-domain queries of this transfer
     zero_counters(T->counters, 2, s);
     T->ood_mode = 1;
+    T->var_mode = VAR_NONE;
     // step 1: the control, f^s at the target nodes, straight into T->g
     if (cfg->precision == FT_F32) {
         const unsigned gw = grid_for(T->n, 64 * (T->dim == 2 ? 4 : 2));
@@ -101,6 +102,7 @@ ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipS
     if (T->dim == 2) fused_g<2>(T, S, cfg, s);
     else fused_g<3>(T, S, cfg, s);
     FT_TRY_HIP(hipGetLastError());
+    T->var_mode = cfg->samples_per_elem >= 2 ? VAR_ESTIMATED : VAR_NONE;
     return assemble_residual(T, cfg->n_fields, nullptr, 0, false, s);
 }
 

@@ -106,14 +106,26 @@ __global__ void k_emit_nodes(const double* __restrict__ X, int64_t n, int dim, v
 // w = sum_k l_k^2, alpha_t = (P/N - sum A_k B_k / N^2) / (Q/N - sum B_k^2 / N^2)
 // clipped to [0, 2] (1 unless the denominator is positive), and the load
 // carries the exact control part: beta_k = alpha_t (M_t g)_k + |Omega|/N (A_k - alpha_t B_k).
+// var_el[f][t] (when non-null): the variance of the element's Monte Carlo
+// total |Omega|/N sum_j r_j (sum_k l_k = 1), |Omega|^2 s^2 / N with s^2 the
+// unbiased sample variance of the residuals r_j = y_j - alpha g(X_j); 0 for
+// N < 2.  The moments are taken of residuals shifted by a constant of the
+// element, which leaves s^2 unchanged and keeps the one-pass form free of
+// cancellation: s = r - (1 - alpha) gbar for a fixed alpha (gbar: the mean of
+// the element's vertex controls, so s = y - g at alpha = 1, y - gbar at 0);
+// with the element's own alpha (not known until its sums are complete) the
+// moments of d = y - g and u = g - gbar, and r - (1 - alpha) gbar = d + (1 - alpha) u.
+// Only the squares and products need sums of their own: the plain sums follow
+// from the element sums, since the weights of a sample add up to 1.
 constexpr double kOwnAlphaLo = 0.0, kOwnAlphaHi = 2.0;
+
 
 template <int D, int G, int FC, bool F32, bool OWN>
 __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, const void* __restrict__ values_,
                                                         const ValueLayout& L, int F, const int32_t* __restrict__ conn,
                                                         const double* __restrict__ vol, int64_t n, uint32_t E,
                                                         uint32_t N, double alpha, const SampleKey& key,
-                                                        double* __restrict__ beta) {
+                                                        double* __restrict__ beta, double* __restrict__ var_el) {
     int v[D + 1];
 #pragma unroll
     for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
@@ -121,23 +133,35 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
     const int64_t qbase = L.samp0 + int64_t(t) * L.samp_elem;
     unsigned int nf = 0;
     constexpr int FO = OWN ? FC : 1;
+    const double Nd = double(N);
+    const double inv_n = 1.0 / Nd, inv_var = N > 1 ? inv_n / (Nd - 1.0) : 0.0;
     for (int f0 = 0; f0 < F; f0 += FC) {
         double gk[FC][D + 1];
         double acc[FC][D + 1];    // sum r l_k (fixed alpha) or sum y l_k (OWN)
         double accb[FO][D + 1];   // OWN: sum g l_k
         double pq[FO][2];         // OWN: sum y g w, sum g^2 w
+        double vs[FC];            // sum s^2 (fixed alpha) or sum d^2 (OWN)
+        double vm[FO][2];         // OWN: sum d u, sum u^2
+        double gbar[FC], sh[FC];
 #pragma unroll
-        for (int f = 0; f < FC; ++f)
+        for (int f = 0; f < FC; ++f) {
+            gbar[f] = 0.0;
+            vs[f] = 0.0;
 #pragma unroll
             for (int k = 0; k <= D; ++k) {
                 acc[f][k] = 0.0;
                 const int64_t off = int64_t(f0 + f < F ? f0 + f : 0) * L.node_ld + v[k];
                 gk[f][k] = F32 ? double(static_cast<const float*>(values_)[off])
                                : static_cast<const double*>(values_)[off];
+                gbar[f] += gk[f][k];
             }
+            gbar[f] *= 1.0 / double(D + 1);
+            sh[f] = (alpha - 1.0) * gbar[f];
+        }
 #pragma unroll
         for (int f = 0; f < FO; ++f) {
             pq[f][0] = pq[f][1] = 0.0;
+            vm[f][0] = vm[f][1] = 0.0;
 #pragma unroll
             for (int k = 0; k <= D; ++k) accb[f][k] = 0.0;
         }
@@ -174,24 +198,62 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
                     }
                     pq[f][0] = fma(y * gx, w, pq[f][0]);
                     pq[f][1] = fma(gx * gx, w, pq[f][1]);
+                    const double d = y - gx, u = gx - gbar[f];
+                    vs[f] = fma(d, d, vs[f]);
+                    vm[f][0] = fma(d, u, vm[f][0]);
+                    vm[f][1] = fma(u, u, vm[f][1]);
                 } else {
                     const double r = y - alpha * gx;
 #pragma unroll
                     for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                    const double sv = r + sh[f];
+                    vs[f] = fma(sv, sv, vs[f]);
                 }
             }
         }
+        // element totals: with one element per wave on the lane-swap / DPP
+        // path, else butterflies over the element's G lanes
+        constexpr int KA = FC * (D + 1) + FC;   // acc, vs
+        constexpr int K = OWN ? KA + FO * (D + 1) + FO * 4 : KA;
+        double red[K];
 #pragma unroll
-        for (int f = 0; f < FC; ++f)
+        for (int f = 0; f < FC; ++f) {
 #pragma unroll
-            for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
+            for (int k = 0; k <= D; ++k) red[f * (D + 1) + k] = acc[f][k];
+            red[FC * (D + 1) + f] = vs[f];
+        }
         if constexpr (OWN) {
 #pragma unroll
             for (int f = 0; f < FO; ++f) {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) accb[f][k] = wave_sum_xor(accb[f][k], G);
-                pq[f][0] = wave_sum_xor(pq[f][0], G);
-                pq[f][1] = wave_sum_xor(pq[f][1], G);
+                for (int k = 0; k <= D; ++k) red[KA + f * (D + 5) + k] = accb[f][k];
+                red[KA + f * (D + 5) + D + 1] = pq[f][0];
+                red[KA + f * (D + 5) + D + 2] = pq[f][1];
+                red[KA + f * (D + 5) + D + 3] = vm[f][0];
+                red[KA + f * (D + 5) + D + 4] = vm[f][1];
+            }
+        }
+        if constexpr (G == 64) {
+            wave_totals<K>(red);
+        } else {
+#pragma unroll
+            for (int i = 0; i < K; ++i) red[i] = wave_sum_xor(red[i], G);
+        }
+#pragma unroll
+        for (int f = 0; f < FC; ++f) {
+#pragma unroll
+            for (int k = 0; k <= D; ++k) acc[f][k] = red[f * (D + 1) + k];
+            vs[f] = red[FC * (D + 1) + f];
+        }
+        if constexpr (OWN) {
+#pragma unroll
+            for (int f = 0; f < FO; ++f) {
+#pragma unroll
+                for (int k = 0; k <= D; ++k) accb[f][k] = red[KA + f * (D + 5) + k];
+                pq[f][0] = red[KA + f * (D + 5) + D + 1];
+                pq[f][1] = red[KA + f * (D + 5) + D + 2];
+                vm[f][0] = red[KA + f * (D + 5) + D + 3];
+                vm[f][1] = red[KA + f * (D + 5) + D + 4];
             }
         }
         if (lane == 0) {
@@ -199,14 +261,17 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
             for (int f = 0; f < FC; ++f) {
                 if (f0 + f >= F) break;
                 double* bt = beta + (int64_t(f0 + f) * E + t) * (D + 1);
+                double sa = 0.0;   // sum_k of the element sums: the plain sum over the samples
+#pragma unroll
+                for (int k = 0; k <= D; ++k) sa += acc[f][k];
                 if constexpr (OWN) {
-                    const double Nd = double(N);
-                    double ab = 0.0, bb = 0.0, gs = 0.0;
+                    double ab = 0.0, bb = 0.0, gs = 0.0, sb = 0.0;
 #pragma unroll
                     for (int k = 0; k <= D; ++k) {
                         ab = fma(acc[f][k], accb[f][k], ab);
                         bb = fma(accb[f][k], accb[f][k], bb);
                         gs += gk[f][k];
+                        sb += accb[f][k];
                     }
                     const double num = pq[f][0] / Nd - ab / (Nd * Nd);
                     const double den = pq[f][1] / Nd - bb / (Nd * Nd);
@@ -217,9 +282,20 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
                         const double ctrl = vol[t] * (gs + gk[f][k]) / double((D + 1) * (D + 2));
                         bt[k] = a * ctrl + scale * (acc[f][k] - a * accb[f][k]);
                     }
+                    if (var_el) {
+                        // r - (1 - a) gbar = d + c u, c = 1 - a; sum d = sum y - sum g, sum u = sum g - N gbar
+                        const double c = 1.0 - a;
+                        const double s1 = (sa - sb) + c * fma(-Nd, gbar[f], sb);
+                        const double s2 = fma(c * c, vm[f][1], fma(2.0 * c, vm[f][0], vs[f]));
+                        var_el[int64_t(f0 + f) * E + t] = element_variance(vol[t], s1, s2, inv_n, inv_var);
+                    }
                 } else {
 #pragma unroll
                     for (int k = 0; k <= D; ++k) bt[k] = acc[f][k] * scale;
+                    // sum s = sum r + N (alpha - 1) gbar
+                    if (var_el)
+                        var_el[int64_t(f0 + f) * E + t] =
+                            element_variance(vol[t], fma(Nd, sh[f], sa), vs[f], inv_n, inv_var);
                 }
             }
         }
@@ -233,7 +309,8 @@ template <int D, int G, int FC, bool F32, int R, bool OWN>
 __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, ValueLayout L, int F,
                                                  const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                  int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
-                                                 double* __restrict__ beta, unsigned long long* __restrict__ nonfinite) {
+                                                 double* __restrict__ beta, double* __restrict__ var_el,
+                                                 unsigned long long* __restrict__ nonfinite) {
     unsigned int nf = 0;
     if constexpr (R > 1) {
         static_assert(G == 64, "one element per wave");
@@ -242,7 +319,8 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         for (int e = 0; e < R; ++e) {
             const uint32_t t = wave * uint32_t(R) + uint32_t(e);
             if (t >= E) break;
-            nf += consume_element<D, G, FC, F32, OWN>(t, lane, values_, L, F, conn, vol, n, E, N, alpha, key, beta);
+            nf += consume_element<D, G, FC, F32, OWN>(t, lane, values_, L, F, conn, vol, n, E, N, alpha, key, beta,
+                                                      var_el);
         }
     } else {
         const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
@@ -250,7 +328,8 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         const int lane = int(gid & (G - 1));
         if (t >= E) return;   // the whole group leaves together
         if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
-        nf = consume_element<D, G, FC, F32, OWN>(t, lane, values_, L, F, conn, vol, n, E, N, alpha, key, beta);
+        nf = consume_element<D, G, FC, F32, OWN>(t, lane, values_, L, F, conn, vol, n, E, N, alpha, key, beta,
+                                                 var_el);
     }
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
@@ -360,7 +439,7 @@ static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* v
     auto kern = cfg->alpha_mode == FT_ALPHA_ELEMENT ? k_consume<D, G, FC, F32, R, true>
                                                     : k_consume<D, G, FC, F32, R, false>;
     kern<<<grid, 256, 0, s>>>(values, L, cfg->n_fields, T->conn, T->vol, T->n, uint32_t(T->E),
-                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, beta, T->counters);
+                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, beta, T->var_el, T->counters);
 }
 
 template <int D, int G, bool F32>
@@ -447,6 +526,7 @@ static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void
     const bool split = cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16;
     zero_counter(T->counters, s);
     T->ood_mode = 0;   // the caller's black box evaluated the points
+    T->var_mode = VAR_NONE;
     if (split && cfg->samples_per_elem <= kMfmaMaxSamples && cfg->n_fields <= kMfmaMaxFields) {
         FT_TRY(consume_mfma(T, cfg, values, L, beta, s));   // element loads fields-inner
         T->fields_inner = cfg->n_fields > 1;
@@ -455,6 +535,7 @@ static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void
     if (f32) consume_g<D, true>(T, cfg, values, L, beta, s);
     else consume_g<D, false>(T, cfg, values, L, beta, s);
     FT_TRY_HIP(hipGetLastError());
+    T->var_mode = cfg->samples_per_elem >= 2 ? VAR_ESTIMATED : VAR_NONE;
     return assemble_from(T, beta, cfg->n_fields, values, L.node_ld, f32, s);
 }
 

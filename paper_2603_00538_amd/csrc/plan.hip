@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_plan_elements(const double* __restrict_
                                                        const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                        uint32_t E, uint32_t N, double alpha, SampleKey key,
                                                        const int32_t* __restrict__ ids, const double* __restrict__ g,
-                                                       double* __restrict__ beta,
+                                                       double* __restrict__ beta, double* __restrict__ var_el,
                                                        unsigned long long* __restrict__ nonfinite) {
     static_assert(R == 1 || G == 64, "several elements per wave need one element per wave");
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
@@ -135,14 +135,20 @@ __global__ __launch_bounds__(256) void k_plan_elements(const double* __restrict_
             for (int c = 0; c < D; ++c) xv[k][c] = X[c * n + v[k]];
         }
         for (int f0 = 0; f0 < F; f0 += FC) {
-            double gk[FC][D + 1], acc[FC][D + 1];
+            // vs: sum and sum of squares of r - (1 - alpha) gbar (the element variance)
+            double gk[FC][D + 1], acc[FC][D + 1], vs[FC], sh[FC];
 #pragma unroll
-            for (int f = 0; f < FC; ++f)
+            for (int f = 0; f < FC; ++f) {
+                vs[f] = 0.0;
+                double gs = 0.0;
 #pragma unroll
                 for (int k = 0; k <= D; ++k) {
                     acc[f][k] = 0.0;
                     gk[f][k] = g[int64_t(f0 + f < F ? f0 + f : 0) * n + v[k]];
+                    gs += gk[f][k];
                 }
+                sh[f] = (alpha - 1.0) * (gs * (1.0 / double(D + 1)));
+            }
             for (uint32_t j = lane; j < N; j += G) {
                 double lam[D + 1], pt[D], mu[D + 1];
                 sample_lambda<D>(t, j, key, lam);
@@ -170,19 +176,45 @@ __global__ __launch_bounds__(256) void k_plan_elements(const double* __restrict_
                     const double r = y - alpha * gx;
 #pragma unroll
                     for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                    const double sv = r + sh[f];
+                    vs[f] = fma(sv, sv, vs[f]);
                 }
             }
+            // element totals in the fused route's order
+            constexpr int K = FC * (D + 2);
+            double red[K];
 #pragma unroll
-            for (int f = 0; f < FC; ++f)
+            for (int f = 0; f < FC; ++f) {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) acc[f][k] = wave_sum_xor(acc[f][k], G);
+                for (int k = 0; k <= D; ++k) red[f * (D + 1) + k] = acc[f][k];
+                red[FC * (D + 1) + f] = vs[f];
+            }
+            if constexpr (G == 64) {
+                wave_totals<K>(red);
+            } else {
+#pragma unroll
+                for (int i = 0; i < K; ++i) red[i] = wave_sum_xor(red[i], G);
+            }
+#pragma unroll
+            for (int f = 0; f < FC; ++f) {
+#pragma unroll
+                for (int k = 0; k <= D; ++k) acc[f][k] = red[f * (D + 1) + k];
+                vs[f] = red[FC * (D + 1) + f];
+            }
             if (lane == 0) {
                 const double scale = vol[t] / double(N);
+                const double Nd = double(N);
+                const double inv_n = 1.0 / Nd, inv_var = N > 1 ? inv_n / (Nd - 1.0) : 0.0;
 #pragma unroll
                 for (int f = 0; f < FC; ++f) {
                     if (f0 + f >= F) break;
 #pragma unroll
                     for (int k = 0; k <= D; ++k) beta[(int64_t(f0 + f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+                    double sa = 0.0;   // the plain sum of the residuals (the weights add up to 1)
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) sa += acc[f][k];
+                    var_el[int64_t(f0 + f) * E + t] =
+                        element_variance(vol[t], fma(Nd, sh[f], sa), vs[f], inv_n, inv_var);
                 }
             }
         }
@@ -252,11 +284,11 @@ static void launch_elements(ft_plan* pl, const double* vals, hipStream_t s) {
     if (F == 1)
         k_plan_elements<D, G, 1, R><<<grid, 256, 0, s>>>(S->rec, S->conn, vals, S->n, F, T->coords, T->n, T->conn,
                                                       T->vol, uint32_t(T->E), N, pl->cfg.alpha, key, pl->ids + T->n,
-                                                      T->g, T->beta, T->counters);
+                                                      T->g, T->beta, T->var_el, T->counters);
     else
         k_plan_elements<D, G, 4, R><<<grid, 256, 0, s>>>(S->rec, S->conn, vals, S->n, F, T->coords, T->n, T->conn,
                                                       T->vol, uint32_t(T->E), N, pl->cfg.alpha, key, pl->ids + T->n,
-                                                      T->g, T->beta, T->counters);
+                                                      T->g, T->beta, T->var_el, T->counters);
 }
 
 template <int D>
@@ -278,6 +310,7 @@ ft_status plan_transfer(ft_plan* pl, const double* vals, hipStream_t s) {
     const int F = pl->cfg.n_fields;
     zero_counter(T->counters, s);
     T->ood_mode = 2;   // the localization (and its out-of-domain count) was fixed at setup
+    T->var_mode = VAR_NONE;
     T->ood_host = pl->n_ood;
     if (T->dim == 2) {
         k_plan_nodes<2><<<grid_for(T->n, 256), 256, 0, s>>>(S->rec, S->conn, v, S->n, F, T->coords, T->n, pl->ids,
@@ -289,6 +322,7 @@ ft_status plan_transfer(ft_plan* pl, const double* vals, hipStream_t s) {
         elements_g<3>(pl, v, s);
     }
     FT_TRY_HIP(hipGetLastError());
+    T->var_mode = pl->cfg.samples_per_elem >= 2 ? VAR_ESTIMATED : VAR_NONE;
     return assemble_residual(T, F, nullptr, 0, false, s);
 }
 

@@ -169,6 +169,52 @@ __global__ __launch_bounds__(RB) void k_report_totals(int nb, const double* __re
     }
 }
 
+// ---- the standard error of sum b (App. B, Eq. cv_global_integral_estimator:
+// the element totals are independent, so the variance of sum b is the sum of
+// the element variances).  Per field: block partials over contiguous element
+// ranges, then their total in block order; compensated throughout.
+__global__ __launch_bounds__(RB) void k_var_partials(const double* __restrict__ var_el, int64_t E,
+                                                     double* __restrict__ part) {
+    const int f = blockIdx.y;
+    const int64_t chunk = (E + kVarBlocks - 1) / kVarBlocks;
+    const int64_t b0 = int64_t(blockIdx.x) * chunk, b1 = b0 + chunk < E ? b0 + chunk : E;
+    double s = 0.0, c = 0.0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += RB) comp_add(s, c, var_el[int64_t(f) * E + i]);
+    block_total_comp(s, c);
+    if (threadIdx.x == 0) {
+        part[(int64_t(f) * kVarBlocks + blockIdx.x) * 2] = s;
+        part[(int64_t(f) * kVarBlocks + blockIdx.x) * 2 + 1] = c;
+    }
+}
+
+__global__ __launch_bounds__(RB) void k_var_total(const double* __restrict__ part, double* __restrict__ tot) {
+    const int f = blockIdx.x;
+    double s = 0.0, c = 0.0;
+    if (threadIdx.x < kVarBlocks) {
+        s = part[(int64_t(f) * kVarBlocks + threadIdx.x) * 2];
+        c = part[(int64_t(f) * kVarBlocks + threadIdx.x) * 2 + 1];
+    }
+    block_total_comp(s, c);
+    if (threadIdx.x == 0) tot[f] = s + c;
+}
+
+ft_status stderr_launch(ft_target* T, int F, hipStream_t s) {
+    if (T->var_mode != VAR_ESTIMATED) return FT_OK;
+    k_var_partials<<<dim3(kVarBlocks, unsigned(F)), RB, 0, s>>>(T->var_el, T->E, T->var_part);
+    k_var_total<<<unsigned(F), RB, 0, s>>>(T->var_part, T->var_tot);
+    FT_TRY_HIP(hipGetLastError());
+    FT_TRY_HIP(hipMemcpyAsync(T->h_var, T->var_tot, size_t(F) * sizeof(double), hipMemcpyDeviceToHost, s));
+    return FT_OK;
+}
+
+// after the stream has been synchronized
+void stderr_fill(const ft_target* T, int F, ft_report* rep) {
+    for (int f = 0; f < F; ++f)
+        rep[f].sum_b_stderr = T->var_mode == VAR_ESTIMATED ? std::sqrt(T->h_var[f])
+                              : T->var_mode == VAR_EXACT   ? 0.0
+                                                           : -1.0;
+}
+
 ft_status solver_alloc(ft_target* T, hipStream_t s) {
     const int64_t n = T->n;
     T->reduce_blocks = int(std::min<int64_t>(MAX_RBLOCKS, (n + RB - 1) / RB));
@@ -439,7 +485,8 @@ static ft_status project_mixed(ft_target* T, const ft_solve_cfg* cfg, double* x,
     return ft_status(R.status);
 }
 
-ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep, hipStream_t s) {
+static ft_status project_one(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep,
+                             hipStream_t s) {
     const int F = T->consumed_cfg.n_fields;
     if (cfg->refine_steps > 0) {
         if (F > 1) {
@@ -509,6 +556,17 @@ ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_ou
     if (R.status == FT_E_NONFINITE) set_error("%llu non-finite query value(s) were consumed", cnt[0]);
     else if (R.status == FT_E_NOCONV) set_error("CG did not reach rtol=%g within %d iterations", cfg->rtol, cfg->max_iter);
     return ft_status(R.status);
+}
+
+// Every form of the solve, then the standard error of sum b per field (the
+// element variances are summed on the stream before the solve; each form
+// synchronizes before it fills its reports).
+ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep, hipStream_t s) {
+    const int F = T->consumed_cfg.n_fields;
+    FT_TRY(stderr_launch(T, F, s));
+    const ft_status st = project_one(T, cfg, x, b_out, rep, s);
+    if (st == FT_OK || st == FT_E_NOCONV || st == FT_E_NONFINITE) stderr_fill(T, F, rep);
+    return st;
 }
 
 }  // namespace ft

@@ -34,7 +34,8 @@ EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_q
             "ft_source_eval_queries", "ft_source_eval_tiles", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_autotune", "ft_batch_variant",
             "ft_batch_destroy",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
-            "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_last_error"]
+            "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_samples_for_tolerance",
+            "ft_last_error"]
 
 
 class SampleCfg(ctypes.Structure):
@@ -51,7 +52,8 @@ class SolveCfg(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("sum_b", ctypes.c_double), ("int_x", ctypes.c_double), ("cons_defect", ctypes.c_double),
                 ("rel_resid", ctypes.c_double), ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("n_nonfinite", ctypes.c_int64), ("n_out_of_domain", ctypes.c_int64)]
+                ("n_nonfinite", ctypes.c_int64), ("n_out_of_domain", ctypes.c_int64),
+                ("sum_b_stderr", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -113,6 +115,7 @@ def load(path: str = LIB_PATH):
         "ft_plan_create": (I32, [P, P, ctypes.POINTER(SampleCfg), P, ctypes.POINTER(P)]),
         "ft_plan_transfer": (I32, [P, P, P]),
         "ft_plan_destroy": (I32, [P]),
+        "ft_samples_for_tolerance": (I32, [ctypes.POINTER(Report), I32, D]),
         "ft_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -235,6 +238,17 @@ def ft_batch_variant(h, k):
 
 def ft_batch_destroy(h):
     return _check(load().ft_batch_destroy(h), "ft_batch_destroy")
+
+
+def ft_samples_for_tolerance(report, samples_per_elem, rel_tol):
+    """Samples per element for a target standard error of sum b (-1: the
+    report carries no estimate).  report: a Report or its dict form."""
+    if isinstance(report, dict):
+        r = Report()
+        for k, _ in Report._fields_:
+            setattr(r, k, report[k])
+        report = r
+    return int(load().ft_samples_for_tolerance(ctypes.byref(report), samples_per_elem, rel_tol))
 
 
 def ft_source_create_p1(dim, n_nodes, coords_ptr, n_elems, conn_ptr, n_fields, values_ptr, bins, stream):

@@ -8,6 +8,7 @@ import re
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2603_00538_amd import ft
@@ -25,7 +26,7 @@ def lib():
 
 def _declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:ft_status|int64_t|const char\*)\s+(ft_\w+)\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:ft_status|int64_t|int32_t|const char\*)\s+(ft_\w+)\(", text, re.M)))
 
 
 def test_header_declares_the_binding_names():
@@ -56,7 +57,8 @@ def test_struct_layouts_match_header(tmp_path):
                    'printf("ft_target_info %zu\\n", sizeof(ft_target_info));\n'
                    "P(ft_sample_cfg, alpha); P(ft_sample_cfg, seed); P(ft_sample_cfg, stream_id); "
                    "P(ft_sample_cfg, precision);\n"
-                   "P(ft_report, iters); P(ft_report, status); P(ft_report, n_nonfinite);\n"
+                   "P(ft_report, iters); P(ft_report, status); P(ft_report, n_nonfinite); "
+                   "P(ft_report, sum_b_stderr);\n"
                    "P(ft_target_info, n_nodes); P(ft_target_info, n_inverted);\n"
                    "return 0;}\n")
     exe = tmp_path / "layout"
@@ -103,6 +105,32 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.ft_source_get_info(None, None) == ft.FT_E_ARG
     assert lib.ft_target_destroy(None) == ft.FT_OK
     assert lib.ft_source_destroy(None) == ft.FT_OK
+
+
+def test_samples_for_tolerance_matches_oracle(lib):
+    """Host-only entry point: the samples per element that bring the standard
+    error of sum b to a relative target (it falls as N^-1/2), as the oracle's
+    samples_for_tolerance computes it; the edge cases the header states."""
+    from oracle import cvmc
+
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        sb = float(rng.choice([-1.0, 1.0]) * 10 ** rng.uniform(-3, 3))
+        se = abs(sb) * 10 ** rng.uniform(-7, -1)
+        N = int(rng.integers(1, 512))
+        tol = 10 ** rng.uniform(-6, -1)
+        rep = ft.Report(sum_b=sb, sum_b_stderr=se)
+        assert ft.ft_samples_for_tolerance(rep, N, tol) == cvmc.samples_for_tolerance(se, sb, N, tol)
+    # halving the error takes four times the samples
+    assert ft.ft_samples_for_tolerance({**ft.Report().as_dict(), "sum_b": 2.0, "sum_b_stderr": 1e-4}, 64,
+                                       0.25e-4 * (1 + 1e-12)) == 256
+    assert ft.ft_samples_for_tolerance(ft.Report(sum_b=1.0, sum_b_stderr=0.0), 64, 1e-6) == 1   # exact b
+    assert ft.ft_samples_for_tolerance(ft.Report(sum_b=0.0, sum_b_stderr=1e-3), 64, 1e-6) == 1
+    assert ft.ft_samples_for_tolerance(ft.Report(sum_b=1.0, sum_b_stderr=-1.0), 64, 1e-6) == -1  # no estimate
+    assert ft.ft_samples_for_tolerance(ft.Report(sum_b=1.0, sum_b_stderr=1e-3), 0, 1e-6) == -1
+    assert ft.ft_samples_for_tolerance(ft.Report(sum_b=1.0, sum_b_stderr=1e-3), 64, 0.0) == -1
+    assert ft.ft_samples_for_tolerance(ft.Report(sum_b=1.0, sum_b_stderr=1.0), 64, 1e-9) == 1 << 20
+    assert lib.ft_samples_for_tolerance(None, 64, 1e-3) == -1
 
 
 def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):

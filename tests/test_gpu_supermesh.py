@@ -1,7 +1,8 @@
 """GPU parity of the intersection-based (supermesh) load vector,
 ft_transfer_supermesh, against the oracle's exact supermesh projection
 (oracle/supermesh.py: Sutherland-Hodgman clip, fan, degree-2 rule per
-sub-triangle), and its identities: the intersection areas of a target element
+sub-triangle; oracle/supermesh3d.py: vertex enumeration and a Delaunay split
+of each tetrahedral intersection), and its identities: the intersection areas of a target element
 add up to its area, sum b = integral f^s, an identical source gives b = M F,
 an affine source gives x = f.  It is also the exact reference the Monte Carlo
 estimate converges to: at small size the mean over realizations, at the
@@ -11,7 +12,7 @@ import numpy as np
 import pytest
 
 from gpu_cases import log, rel_l2
-from oracle import cvmc, geometry, supermesh
+from oracle import cvmc, geometry, supermesh, supermesh3d
 from paper_2603_00538_amd import ft
 from workloads import configs, fields, meshes
 
@@ -77,7 +78,7 @@ def test_supermesh_identities():
     assert np.abs(got["x"] - fields.evaluate("affine", np, tm[0])).max() < 1e-12
 
 
-def test_supermesh_partial_cover_and_3d_rejected():
+def test_supermesh_partial_cover():
     """A target reaching outside the source: the covered part of each element
     is integrated (as the oracle does), and the elements not entirely covered
     are counted."""
@@ -92,13 +93,81 @@ def test_supermesh_partial_cover_and_3d_rejected():
     vol = geometry.element_measures(tm[0], np.asarray(tconn, dtype=np.int64))
     partial = int((ref["area_sum"] < vol * (1 - 1e-12)).sum())
     assert partial > 0 and got["reports"][0]["n_out_of_domain"] == partial
-    # tetrahedra are not supported by the intersection route
-    t3 = meshes.kuhn_tet_mesh(3, 0.08, 135)
-    T = ft.Target(*t3)
-    S = ft.Source(*t3, fields.evaluate("gaussian_bumps_3d", np, t3[0]))
+    # more than four fields are not supported by the intersection route
+    S5 = ft.Source(*sm, np.ascontiguousarray(np.stack([sv[0]] * 5)))
+    T = ft.Target(*tm)
     with pytest.raises(ft.FtError) as e:
-        T.transfer_supermesh(S)
+        T.transfer_supermesh(S5)
     assert e.value.status == ft.FT_E_UNSUPPORTED
+    T.close()
+    S5.close()
+
+
+# ---- tetrahedra: against the oracle's vertex-enumeration supermesh -------------------------
+@pytest.mark.parametrize("kt,ks,F,jt,js", [(4, 5, 1, 0.08, 0.08), (5, 3, 1, 0.08, 0.08), (4, 5, 3, 0.08, 0.05),
+                                           (3, 5, 1, 0.0, 0.0)])
+def test_supermesh3d_matches_oracle(kt, ks, F, jt, js):
+    """Perturbed Kuhn meshes both ways round (finer and coarser source), several
+    fields, and unperturbed meshes whose faces lie in common planes (pieces
+    touch along faces and edges)."""
+    tm, sm = meshes.kuhn_tet_mesh(kt, jt, 210 + kt), meshes.kuhn_tet_mesh(ks, js, 220 + ks)
+    rows = [fields.evaluate("gaussian_bumps_3d", np, sm[0])[0], np.cos(3 * sm[0][:, 0]) + sm[0][:, 2],
+            np.sin(2 * sm[0][:, 1]) * sm[0][:, 0]]
+    sv = np.ascontiguousarray(np.stack(rows[:F]))
+    log(f"supermesh 3D target {kt} source {ks} F={F}")
+    got = _gpu_supermesh(tm, sm, sv)
+    ref = supermesh3d.supermesh_projection(*tm, *sm, sv)
+    assert got["status"] == ft.FT_OK
+    assert rel_l2(got["b"], ref["b"]) < 1e-12
+    vol = geometry.element_measures(np.asarray(tm[0]), np.asarray(tm[1], dtype=np.int64))
+    assert np.abs(got["area"] - vol).max() <= 1e-13 * vol.max()
+    M = geometry.mass_matrix(np.asarray(tm[0]), np.asarray(tm[1], dtype=np.int64))
+    assert rel_l2(got["x"], cvmc.solve_mass(M, ref["b"], 3)) < 1e-12
+    for f in range(F):
+        assert abs(got["b"][f].sum() - got["integral"][f]) <= 1e-13 * max(1.0, abs(got["integral"][f]))
+        assert got["reports"][f]["n_out_of_domain"] == 0
+        assert got["reports"][f]["sum_b_stderr"] == 0.0
+
+
+def test_supermesh3d_identities_and_partial_cover():
+    tm = meshes.kuhn_tet_mesh(4, 0.08, 230)
+    F = fields.evaluate("gaussian_bumps_3d", np, tm[0])
+    got = _gpu_supermesh(tm, tm, F)           # identical source: b = M F
+    assert rel_l2(got["x"], F) < 1e-12
+    sm = meshes.kuhn_tet_mesh(6, 0.08, 231)   # affine source: reproduced exactly
+    got = _gpu_supermesh(tm, sm, fields.evaluate("affine", np, sm[0]))
+    assert np.abs(got["x"] - fields.evaluate("affine", np, tm[0])).max() < 1e-12
+    # a target reaching outside the source
+    tc, tconn = meshes.kuhn_tet_mesh(4, 0.08, 232)
+    tm2 = (tc * 1.2 - 0.1, tconn)
+    sm = meshes.kuhn_tet_mesh(5, 0.08, 235)
+    sv = fields.evaluate("gaussian_bumps_3d", np, sm[0])
+    got = _gpu_supermesh(tm2, sm, sv)
+    ref = supermesh3d.supermesh_projection(*tm2, *sm, sv)
+    assert rel_l2(got["b"], ref["b"]) < 1e-12
+    assert np.abs(got["area"] - ref["vol_sum"]).max() < 1e-14
+    vol = geometry.element_measures(tm2[0], np.asarray(tconn, dtype=np.int64))
+    partial = int((ref["vol_sum"] < vol * (1 - 1e-12)).sum())
+    assert partial > 0 and got["reports"][0]["n_out_of_domain"] == partial
+
+
+def test_monte_carlo_mean_converges_to_supermesh3d():
+    """The tetrahedral CV-MC load vector is unbiased: its mean over R
+    realizations approaches the exact b within a few standard errors."""
+    tm, sm = meshes.kuhn_tet_mesh(4, 0.08, 233), meshes.kuhn_tet_mesh(5, 0.08, 234)
+    sv = fields.evaluate("gaussian_bumps_3d", np, sm[0])
+    exact = _gpu_supermesh(tm, sm, sv)["b"][0]
+    T = ft.Target(*tm)
+    S = ft.Source(*sm, sv)
+    bs = []
+    for r in range(200):
+        T.transfer_from(S, ft.SampleCfg(16, 1, 0.5, SEED, 300 + r, ft.FT_F64))
+        bs.append(T.project(1).b[0].cpu().numpy())
+    bs = np.array(bs)
+    z = np.abs(bs.mean(axis=0) - exact) / (bs.std(axis=0, ddof=1) / np.sqrt(len(bs)))
+    log(f"3D MC mean vs supermesh: max z {z.max():.2f} over {z.size} nodes")
+    assert z.max() < 5.0
+    assert np.mean(z ** 2) < 1.5
     T.close()
     S.close()
 

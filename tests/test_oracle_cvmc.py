@@ -355,3 +355,54 @@ def test_own_alpha_variance_no_larger_than_fixed(sm_case):
                 z = (bs.mean(axis=0) - exact) / (bs.std(axis=0, ddof=1) / math.sqrt(len(bs)))
                 assert np.mean(z ** 2) < 1.6
         assert rms["own"] < rms["one"] < 0.2 * rms["zero"]
+
+
+# ---- the standard error of sum b and the samples an error target needs --------------------
+def test_variance_term_closed_form():
+    """One reference triangle, f = x^2, alpha = 0: the residual is l_1^2 and its
+    variance is E[l_1^4] - E[l_1^2]^2 = 1/15 - 1/36 = 7/180 (Dirichlet moments),
+    so the variance term is |T|^2 (7/180) / N with |T| = 1/2."""
+    from oracle import sampling
+
+    coords = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    conn = np.array([[0, 1, 2]])
+    N = 200_000
+    lam = sampling.element_samples(2, 1, N, seed=5, stream=0)
+    X = sampling.physical_points(coords, conn, lam)
+    r = (X[..., 0] ** 2)[None]
+    v = cvmc.element_variance_terms(coords, conn, r)
+    assert abs(v[0, 0] * N / 0.25 - 7.0 / 180.0) < 0.01 * 7.0 / 180.0
+    # with three samples per element the sample variance is unbiased only with
+    # the N - 1 divisor: averaged over many copies of the element it is still
+    # 7/180 (the N divisor would give two thirds of it)
+    Ec, n3 = 200_000, 3
+    conn_c = np.tile(conn, (Ec, 1))
+    lam = sampling.element_samples(2, Ec, n3, seed=6, stream=0)
+    X = sampling.physical_points(coords, conn_c, lam)
+    v = cvmc.element_variance_terms(coords, conn_c, (X[..., 0] ** 2)[None])
+    assert abs(v.mean() * n3 / 0.25 - 7.0 / 180.0) < 0.02 * 7.0 / 180.0
+
+
+def test_stderr_matches_replicate_spread(sm_case):
+    """Over 200 realizations the spread of sum b matches the reported standard
+    error, sum b centres on the exact integral of f^s (z-scores), an affine
+    source has standard error 0, and samples_for_tolerance follows N^-1/2."""
+    tmesh, smesh, pieces = sm_case
+    sv = fields.evaluate("paper_f3", np, smesh[0])
+    src = P1Source(*smesh, sv)
+    exact = src.integral()[0]
+    sums, errs = [], []
+    for s in range(200):
+        rep = cvmc.transfer(*tmesh, src, 8, alpha=0.5, seed=900 + s, stream=1)["report"][0]
+        sums.append(rep["sum_b"])
+        errs.append(rep["sum_b_stderr"])
+    sums, errs = np.array(sums), np.array(errs)
+    assert 0.85 < sums.std(ddof=1) / np.sqrt(np.mean(errs ** 2)) < 1.15
+    z = (sums - exact) / errs
+    assert 0.7 < np.mean(z ** 2) < 1.4
+    aff = cvmc.transfer(*tmesh, _source(smesh, "affine"), 8, seed=3)["report"][0]
+    assert aff["sum_b_stderr"] < 1e-15
+    N2 = cvmc.samples_for_tolerance(errs[0], sums[0], 8, 0.25 * (1 + 1e-12) * errs[0] / abs(sums[0]))
+    assert N2 == 8 * 16
+    # one sample per element: no spread to estimate from
+    assert cvmc.transfer(*tmesh, src, 1, alpha=0.5, seed=4)["report"][0]["sum_b_stderr"] == -1.0
