@@ -158,6 +158,7 @@ typedef struct {
     int64_t n_elems;
     int64_t nnz;                /* stored entries of M (CSR)                                        */
     int64_t n_inverted;         /* elements with negative orientation (accepted; |det J| is used) */
+    int32_t order;              /* polynomial degree of the target elements: 1 or 2                */
 } ft_target_info;
 
 /*
@@ -176,6 +177,32 @@ typedef struct {
  */
 ft_status ft_target_create(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems,
                            const int32_t* conn, hipStream_t stream, ft_target** out);
+
+/*
+ * ft_target_create_p2 - setup of a target of quadratic (P2) Lagrange elements
+ * on straight-sided triangles or tetrahedra (sec. 2 states the projection for
+ * any target space V_t = span{psi_i}; App. A bounds its error for degree p).
+ * Every transfer then follows sec. 4.1 with the P2 basis: the query list's
+ * node block holds every P2 node (the control g = I_h f^s is f^s there), the
+ * samples are drawn from the element's vertices exactly as for P1, and
+ * g(X) = sum_i g_i psi_i(X) and the element loads use the P2 basis
+ *   vertex k: l_k (2 l_k - 1),   edge e = (a, b): 4 l_a l_b,
+ * (l: barycentric coordinates of the sample), which adds up to 1, so the
+ * conservation identity holds as for P1.  M is assembled exactly from the
+ * simplex moments.
+ *   coords   device, binary64, [dim][n_nodes] (SoA): vertices and edge nodes
+ *   conn     device, int32, [n_elems][(dim+1)(dim+2)/2]: the element's dim+1
+ *            vertices, then its edge nodes in the order of the vertex pairs
+ *            (0,1) (0,2) (1,2) for triangles, (0,1) (0,2) (0,3) (1,2) (1,3)
+ *            (2,3) for tetrahedra; each edge node at the midpoint of its edge
+ * Supported for P2 targets: ft_sample_points, ft_consume_queries (FT_F64 and
+ * FT_F32, one fixed alpha, either value layout), ft_transfer_p1, ft_project;
+ * the other routes return FT_E_UNSUPPORTED.
+ * Errors: as ft_target_create; FT_E_MESH also for an edge node off its
+ * edge's midpoint (relative 1e-10).  Synchronizes `stream`.
+ */
+ft_status ft_target_create_p2(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems,
+                              const int32_t* conn, hipStream_t stream, ft_target** out);
 
 /* Release a target and all its device memory (null is accepted).  The
  * caller must make sure no work using it is still pending on any stream. */

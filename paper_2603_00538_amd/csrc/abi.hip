@@ -50,6 +50,7 @@ static void target_release(ft_target* T) {
                   T->counters, T->val32, T->diag32, T->w32, T->scal32, T->mf_vec, T->mf_sc, T->mf_part,
                   T->var_el, T->var_tot, T->var_part};
     for (void* p : ps) dev_free(p);
+    if (T->dofs != T->conn) dev_free(T->dofs);
     if (T->h_scal) (void)hipHostFree(T->h_scal);
     if (T->h_var) (void)hipHostFree(T->h_var);
 }
@@ -90,7 +91,7 @@ ft_status ensure_field_buffers(ft_target* T, int F, hipStream_t stream) {
     T->beta = T->g = T->bres = T->var_el = T->var_tot = T->var_part = T->h_var = nullptr;
     T->F_cap = 0;
     T->var_mode = VAR_NONE;
-    FT_TRY(dev_alloc_n(&T->beta, size_t(F) * size_t(T->E) * (T->dim + 1)));
+    FT_TRY(dev_alloc_n(&T->beta, size_t(F) * size_t(T->E) * T->nb));
     FT_TRY(dev_alloc_n(&T->g, size_t(F) * size_t(T->n)));
     FT_TRY(dev_alloc_n(&T->bres, size_t(F) * size_t(T->n)));
     FT_TRY(dev_alloc_n(&T->var_el, size_t(F) * size_t(T->E)));
@@ -110,12 +111,16 @@ static bool same_samples(const ft_sample_cfg& a, const ft_sample_cfg& b) {
 }
 
 // Each element's own control coefficient is computed by the black-box
-// consumption kernel only (binary64 and binary32 forms).
-static ft_status check_alpha_mode(const ft_sample_cfg* cfg, bool black_box) {
+// consumption kernel only (binary64 and binary32 forms, P1 targets).
+static ft_status check_alpha_mode(const ft_target* T, const ft_sample_cfg* cfg, bool black_box) {
     if (cfg->alpha_mode == FT_ALPHA_ELEMENT &&
-        (!black_box || cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16)) {
+        (!black_box || cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16 || T->order != 1)) {
         set_error("per-element control coefficients are computed by ft_consume_queries in the FT_F64 and FT_F32 "
-                  "forms only");
+                  "forms on P1 targets only");
+        return FT_E_UNSUPPORTED;
+    }
+    if (T->order != 1 && cfg->precision != FT_F64 && cfg->precision != FT_F32) {
+        set_error("P2 targets take the FT_F64 and FT_F32 forms");
         return FT_E_UNSUPPORTED;
     }
     return FT_OK;
@@ -152,18 +157,18 @@ struct ft_target_ext : ft_target {
 
 extern "C" {
 
-ft_status ft_target_create(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems, const int32_t* conn,
-                           hipStream_t stream, ft_target** out) {
-    FT_GUARD_BEGIN
-    clear_error();
+static ft_status target_create(int32_t dim, int order, int64_t n_nodes, const double* coords, int64_t n_elems,
+                               const int32_t* conn, hipStream_t stream, ft_target** out) {
     FT_ARG_CHECK(out, "out is null");
     *out = nullptr;
     FT_ARG_CHECK(dim == 2 || dim == 3, "dim must be 2 or 3 (got %d)", dim);
     FT_ARG_CHECK(coords && conn, "coords and conn must be device pointers");
-    FT_ARG_CHECK(n_nodes >= dim + 1 && n_nodes < INT32_MAX, "n_nodes out of range (%lld)", (long long)n_nodes);
-    FT_ARG_CHECK(n_elems >= 1 && n_elems * (dim + 1) < INT32_MAX, "n_elems out of range (%lld)", (long long)n_elems);
+    const int nb = order == 1 ? dim + 1 : (dim + 1) * (dim + 2) / 2;
+    FT_ARG_CHECK(n_nodes >= nb && n_nodes < INT32_MAX, "n_nodes out of range (%lld)", (long long)n_nodes);
+    FT_ARG_CHECK(n_elems >= 1 && n_elems * nb < INT32_MAX, "n_elems out of range (%lld)", (long long)n_elems);
     auto* T = new ft_target_ext();
     T->dim = dim;
+    T->order = order;
     T->n = n_nodes;
     T->E = n_elems;
     ft_status st = target_setup(T, coords, conn, stream);
@@ -183,6 +188,21 @@ ft_status ft_target_create(int32_t dim, int64_t n_nodes, const double* coords, i
     }
     *out = T;
     return FT_OK;
+}
+
+ft_status ft_target_create(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems, const int32_t* conn,
+                           hipStream_t stream, ft_target** out) {
+    FT_GUARD_BEGIN
+    clear_error();
+    return target_create(dim, 1, n_nodes, coords, n_elems, conn, stream, out);
+    FT_GUARD_END
+}
+
+ft_status ft_target_create_p2(int32_t dim, int64_t n_nodes, const double* coords, int64_t n_elems,
+                              const int32_t* conn, hipStream_t stream, ft_target** out) {
+    FT_GUARD_BEGIN
+    clear_error();
+    return target_create(dim, 2, n_nodes, coords, n_elems, conn, stream, out);
     FT_GUARD_END
 }
 
@@ -201,6 +221,7 @@ ft_status ft_target_get_info(const ft_target* t, ft_target_info* info) {
     info->n_elems = t->E;
     info->nnz = t->nnz;
     info->n_inverted = t->n_inverted;
+    info->order = t->order;
     return FT_OK;
 }
 
@@ -235,7 +256,7 @@ ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void*
                   "point precision");
         return FT_E_ORDER;
     }
-    FT_TRY(check_alpha_mode(cfg, true));
+    FT_TRY(check_alpha_mode(T, cfg, true));
     FT_TRY(ensure_field_buffers(T, cfg->n_fields, stream));
     T->consumed = false;
     FT_TRY(consume_values(T, cfg, values, T->beta, stream));
@@ -258,7 +279,7 @@ ft_status ft_consume_queries_noalloc(ft_target* t, const ft_sample_cfg* cfg, con
                   "point precision");
         return FT_E_ORDER;
     }
-    const uint64_t need = uint64_t(cfg->n_fields) * uint64_t(T->E) * uint64_t(T->dim + 1) * sizeof(double);
+    const uint64_t need = uint64_t(cfg->n_fields) * uint64_t(T->E) * uint64_t(T->nb) * sizeof(double);
     FT_ARG_CHECK(need <= noalloc_scratch_bytes(),
                  "the element loads of %d field(s) x %lld elements need %llu bytes; the scratch array holds %llu",
                  cfg->n_fields, (long long)T->E, (unsigned long long)need,
@@ -266,7 +287,7 @@ ft_status ft_consume_queries_noalloc(ft_target* t, const ft_sample_cfg* cfg, con
     FT_ARG_CHECK(cfg->n_fields <= T->F_cap,
                  "n_fields (%d) exceeds the %d field(s) the target holds buffers for (ft_consume_queries with "
                  "that field count provisions them)", cfg->n_fields, T->F_cap);
-    FT_TRY(check_alpha_mode(cfg, true));
+    FT_TRY(check_alpha_mode(T, cfg, true));
     double* scratch = nullptr;
     FT_TRY(noalloc_scratch(&scratch));
     T->fields_inner = false;   // the many-field route sets it again
@@ -290,7 +311,7 @@ ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
         set_error("the fused built-in route supports FT_F64 and FT_F32 and at most 4 fields");
         return FT_E_UNSUPPORTED;
     }
-    FT_TRY(check_alpha_mode(cfg, false));
+    FT_TRY(check_alpha_mode(t, cfg, false));
     FT_TRY(ensure_field_buffers(t, cfg->n_fields, stream));
     t->consumed = false;
     FT_TRY(transfer_p1(t, s, cfg, stream));
@@ -305,8 +326,8 @@ ft_status ft_transfer_supermesh(ft_target* t, ft_source* s, double* area, hipStr
     clear_error();
     FT_ARG_CHECK(t && s, "target and source must be non-null");
     FT_ARG_CHECK(s->dim == t->dim, "source dimension %d differs from target dimension %d", s->dim, t->dim);
-    if (s->F > 4) {
-        set_error("the intersection route supports at most 4 fields");
+    if (s->F > 4 || t->order != 1) {
+        set_error("the intersection route supports P1 targets and at most 4 fields");
         return FT_E_UNSUPPORTED;
     }
     FT_TRY(ensure_field_buffers(t, s->F, stream));
@@ -349,11 +370,11 @@ ft_status ft_plan_create(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
     FT_ARG_CHECK(s->dim == t->dim, "source dimension %d differs from target dimension %d", s->dim, t->dim);
     FT_ARG_CHECK(cfg->n_fields == s->F, "n_fields (%d) must equal the source's field count (%d)", cfg->n_fields,
                  s->F);
-    if (cfg->precision != FT_F64) {
-        set_error("plans run the FT_F64 form");
+    if (cfg->precision != FT_F64 || t->order != 1) {
+        set_error("plans run the FT_F64 form on P1 targets");
         return FT_E_UNSUPPORTED;
     }
-    FT_TRY(check_alpha_mode(cfg, false));
+    FT_TRY(check_alpha_mode(t, cfg, false));
     FT_TRY(ensure_field_buffers(t, cfg->n_fields, stream));
     ft_plan* p = plan_new(t, s, cfg);
     const ft_status st = plan_setup(p, stream);
@@ -402,9 +423,11 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
         FT_TRY(check_sample_cfg(t, &cfgs[k]));
         FT_ARG_CHECK(s->dim == t->dim, "transfer %d: source dimension %d differs from target dimension %d", k,
                      s->dim, t->dim);
-        FT_TRY(check_alpha_mode(&cfgs[k], false));
-        if ((cfgs[k].precision != FT_F64 && cfgs[k].precision != FT_F32) || cfgs[k].n_fields != 1 || s->F != 1) {
-            set_error("transfer %d: batches run FT_F64 or FT_F32 transfers of one field from one-field sources", k);
+        FT_TRY(check_alpha_mode(t, &cfgs[k], false));
+        if ((cfgs[k].precision != FT_F64 && cfgs[k].precision != FT_F32) || cfgs[k].n_fields != 1 || s->F != 1 ||
+            t->order != 1) {
+            set_error("transfer %d: batches run FT_F64 or FT_F32 transfers of one field from one-field sources to "
+                      "P1 targets", k);
             return FT_E_UNSUPPORTED;
         }
         for (int j = 0; j < k; ++j)

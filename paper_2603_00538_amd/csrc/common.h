@@ -180,6 +180,36 @@ inline ValueLayout element_tile_layout(int64_t n, int64_t N, int F) {
     return ValueLayout{n, int64_t(F) * n, N, int64_t(F) * N, make_fastdiv(uint32_t(N))};
 }
 
+// ---------------------------------------------------------------- element basis
+// Local edges of a P2 element: vertex pairs a < b in lexicographic order,
+// d = 2: (0,1) (0,2) (1,2); d = 3: (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).
+__host__ __device__ constexpr int p2_edge(int d, int e, int end) {
+    return d == 2 ? (end == 0 ? (e < 2 ? 0 : 1) : (e == 0 ? 1 : 2))
+                  : (end == 0 ? (e < 3 ? 0 : (e < 5 ? 1 : 2)) : (e < 3 ? e + 1 : (e == 3 ? 2 : 3)));
+}
+
+// Lagrange basis of degree P on a straight-sided simplex, from the barycentric
+// coordinates of the point: P1 psi_k = l_k; P2 vertex k: l_k (2 l_k - 1),
+// edge e = (a, b): 4 l_a l_b.  Both sets add up to 1.
+template <int D, int P>
+struct Basis {
+    static constexpr int n = P == 1 ? D + 1 : (D + 1) * (D + 2) / 2;
+};
+
+template <int D, int P>
+__device__ __forceinline__ void basis_at(const double (&lam)[D + 1], double (&psi)[Basis<D, P>::n]) {
+    if constexpr (P == 1) {
+#pragma unroll
+        for (int k = 0; k <= D; ++k) psi[k] = lam[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k <= D; ++k) psi[k] = lam[k] * (2.0 * lam[k] - 1.0);
+#pragma unroll
+        for (int e = 0; e < Basis<D, P>::n - D - 1; ++e)
+            psi[D + 1 + e] = 4.0 * lam[p2_edge(D, e, 0)] * lam[p2_edge(D, e, 1)];
+    }
+}
+
 // ---------------------------------------------------------------- wave helpers (wave64)
 __device__ __forceinline__ double wave_sum_xor(double v, int width) {
     for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
@@ -331,10 +361,13 @@ enum { VAR_NONE = 0, VAR_ESTIMATED = 1, VAR_EXACT = 2 };
 
 struct ft_target {
     int dim = 0;
+    int order = 1;              // 1: P1 (nodes = vertices); 2: P2 (vertices, then edge nodes)
+    int nb = 0;                 // basis functions per element: dim+1, or (dim+1)(dim+2)/2 for P2
     int64_t n = 0, E = 0, nnz = 0, n_inverted = 0;
     // mesh copies
-    double* coords = nullptr;   // [dim][n]
-    int32_t* conn = nullptr;    // [E][dim+1]
+    double* coords = nullptr;   // [dim][n] every node (the vertices among them)
+    int32_t* conn = nullptr;    // [E][dim+1] vertices: the element geometry and its samples
+    int32_t* dofs = nullptr;    // [E][nb] the element's nodes (== conn for P1)
     double* vol = nullptr;      // [E]
     // mass matrix (CSR) and derived vectors
     int64_t* rowptr = nullptr;  // [n+1]
@@ -342,12 +375,12 @@ struct ft_target {
     double* val = nullptr;      // [nnz]
     double* diag = nullptr;     // [n]
     double* lumped = nullptr;   // [n] m = M 1
-    // node -> (element, local vertex) incidence, entries t*(dim+1)+k ascending
+    // node -> (element, local node) incidence, entries t*nb+k ascending
     int64_t* inc_ptr = nullptr; // [n+1]
-    int32_t* inc = nullptr;     // [E*(dim+1)]
+    int32_t* inc = nullptr;     // [E*nb]
     // per-transfer state
     int F_cap = 0;
-    double* beta = nullptr;     // [F][E][dim+1], or [E][dim+1][F] when fields_inner
+    double* beta = nullptr;     // [F][E][nb], or [E][nb][F] when fields_inner
     double* g = nullptr;        // [F][n], or [n][F] when fields_inner
     double* bres = nullptr;     // [F][n], or [n][F] when fields_inner
     bool fields_inner = false;  // layout of the last transfer (many-field matrix-core route)

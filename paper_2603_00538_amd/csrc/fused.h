@@ -29,13 +29,17 @@ constexpr int kLamSlots = kStashLambda<D, P> ? 64 * P * (D + 1) : 0;
 // control values g must hold binary32-rounded values too); sums in binary64.
 // var_el (unless null): each element's variance term, as the consumption
 // kernel writes it (sum and sum of squares of r - (1 - alpha) gbar).
-template <int D, int G, int P, int FC, bool F32 = false>
+// ORD: degree of the target elements; for P2 dofs lists each element's
+// nodes ([E][nb]: vertices, then edge nodes), where g and the loads live.
+template <int D, int G, int P, int FC, bool F32 = false, int ORD = 1>
 __device__ __forceinline__ void fused_elements(const SrcView& S, const double* __restrict__ X, int64_t n,
                                                const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                uint32_t E, uint32_t N, double alpha, SampleKey key,
                                                const double* __restrict__ g, double* __restrict__ beta, uint32_t t,
                                                int lane, unsigned& nf, unsigned& nood, double* __restrict__ c_af,
-                                               double* __restrict__ var_el = nullptr) {
+                                               double* __restrict__ var_el = nullptr,
+                                               const int32_t* __restrict__ dofs = nullptr) {
+    constexpr int NB = Basis<D, ORD>::n;
     // with one element per wave, its connectivity, vertices and control values
     // are wave-uniform: scalar loads into scalar registers
     if (G == 64) t = __builtin_amdgcn_readfirstlane(t);
@@ -49,18 +53,21 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
     for (int k = 0; k <= D; ++k)
 #pragma unroll
         for (int c = 0; c < D; ++c) xv[k][c] = X[c * n + v[k]];
-    double gk[FC][D + 1], acc[FC][D + 1], vs[FC], sh[FC];
+    int gv[NB];   // the element's nodes
+#pragma unroll
+    for (int k = 0; k < NB; ++k) gv[k] = ORD == 1 ? v[k < D + 1 ? k : 0] : dofs[int64_t(tt) * NB + k];
+    double gk[FC][NB], acc[FC][NB], vs[FC], sh[FC];
 #pragma unroll
     for (int f = 0; f < FC; ++f) {
         vs[f] = 0.0;
-        double gs = 0.0;   // summed in vertex order, as the consumption kernel does
+        double gs = 0.0;   // summed in node order, as the consumption kernel does
 #pragma unroll
-        for (int k = 0; k <= D; ++k) {
+        for (int k = 0; k < NB; ++k) {
             acc[f][k] = 0.0;
-            gk[f][k] = f < S.F ? g[int64_t(f) * n + v[k]] : 0.0;
+            gk[f][k] = f < S.F ? g[int64_t(f) * n + gv[k]] : 0.0;
             gs += gk[f][k];
         }
-        sh[f] = (alpha - 1.0) * (gs * (1.0 / double(D + 1)));   // (alpha - 1) gbar
+        sh[f] = (alpha - 1.0) * (gs * (1.0 / double(NB)));   // (alpha - 1) gbar
     }
     // every lane runs the same number of rounds: the localization is wave-cooperative.
     // Round r, slot q of a lane holds sample j = r*G*P + q*G + lane.
@@ -133,18 +140,20 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
             } else {
                 sample_lambda<D>(tt, j0 + q * G + lane, key, lam);
             }
+            double psi[NB];
+            basis_at<D, ORD>(lam, psi);
 #pragma unroll
             for (int f = 0; f < FC; ++f) {
                 if (f >= S.F) break;
                 double y = p1_value<D>(S, bid[q], mu, f);
                 if (F32) y = double(float(y));
                 nf += !isfinite(y);
-                double gx = lam[0] * gk[f][0];
+                double gx = psi[0] * gk[f][0];
 #pragma unroll
-                for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
+                for (int k = 1; k < NB; ++k) gx = fma(psi[k], gk[f][k], gx);
                 const double r = y - alpha * gx;
 #pragma unroll
-                for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                for (int k = 0; k < NB; ++k) acc[f][k] = fma(r, psi[k], acc[f][k]);
                 if (var_el) {
                     const double sv = r + sh[f];
                     vs[f] = fma(sv, sv, vs[f]);
@@ -154,13 +163,13 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
     }
     // element totals as the consumption kernel forms them (lane-swap / DPP
     // path with one element per wave, else butterflies over G lanes)
-    constexpr int K = FC * (D + 2);
+    constexpr int K = FC * (NB + 1);
     double red[K];
 #pragma unroll
     for (int f = 0; f < FC; ++f) {
 #pragma unroll
-        for (int k = 0; k <= D; ++k) red[f * (D + 1) + k] = acc[f][k];
-        red[FC * (D + 1) + f] = vs[f];
+        for (int k = 0; k < NB; ++k) red[f * NB + k] = acc[f][k];
+        red[FC * NB + f] = vs[f];
     }
     if constexpr (G == 64) {
         wave_totals<K>(red);
@@ -171,8 +180,8 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
 #pragma unroll
     for (int f = 0; f < FC; ++f) {
 #pragma unroll
-        for (int k = 0; k <= D; ++k) acc[f][k] = red[f * (D + 1) + k];
-        vs[f] = red[FC * (D + 1) + f];
+        for (int k = 0; k < NB; ++k) acc[f][k] = red[f * NB + k];
+        vs[f] = red[FC * NB + f];
     }
     if (valid && lane == 0) {
         const double scale = vol[t] / double(N);
@@ -182,11 +191,11 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
         for (int f = 0; f < FC; ++f) {
             if (f >= S.F) break;
 #pragma unroll
-            for (int k = 0; k <= D; ++k) beta[(int64_t(f) * E + t) * (D + 1) + k] = acc[f][k] * scale;
+            for (int k = 0; k < NB; ++k) beta[(int64_t(f) * E + t) * NB + k] = acc[f][k] * scale;
             if (var_el) {
                 double sa = 0.0;   // the plain sum of the residuals (the weights add up to 1)
 #pragma unroll
-                for (int k = 0; k <= D; ++k) sa += acc[f][k];
+                for (int k = 0; k < NB; ++k) sa += acc[f][k];
                 var_el[int64_t(f) * E + t] = element_variance(vol[t], fma(Nd, sh[f], sa), vs[f], inv_n, inv_var);
             }
         }

@@ -15,23 +15,28 @@
 
 namespace ft {
 
-// One field: register targets for four waves per SIMD in 2D and three in 3D
-// with one element per wave and at most two samples per lane (the other 3D
-// variants would spill at three and keep two).  The unconstrained allocation
-// leaves two waves per SIMD (2D: 21% slower).
-template <int D, int G, int P, int FC, bool F32>
+// One field: register targets for four waves per SIMD in 2D and in the
+// binary64 3D form with one element per wave and at most two samples per lane
+// (128 registers, no spill), three for its binary32 form (which would spill
+// at four), two for the other 3D variants (which would spill at three).  The
+// unconstrained allocation leaves two waves per SIMD (2D: 21% slower).  P2
+// targets (ORD = 2, more basis functions per element): two waves.
+template <int D, int G, int P, int FC, bool F32, int ORD>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(FC != 1 ? 1 : (D == 2 ? 4 : (G == 64 && P <= 2 ? 3 : 2)))))
+__attribute__((amdgpu_waves_per_eu(FC != 1 || ORD != 1 ? (ORD != 1 ? 2 : 1)
+                                                       : (D == 2 ? 4 : (G == 64 && P <= 2 ? (F32 ? 3 : 4) : 2)))))
 void k_fused_p1(SrcView S, const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn,
-                const double* __restrict__ vol, uint32_t E, uint32_t N, double alpha, SampleKey key,
-                const double* __restrict__ g, double* __restrict__ beta, double* __restrict__ var_el,
-                unsigned long long* __restrict__ nonfinite, unsigned long long* __restrict__ n_ood) {
+                const int32_t* __restrict__ dofs, const double* __restrict__ vol, uint32_t E, uint32_t N,
+                double alpha, SampleKey key, const double* __restrict__ g, double* __restrict__ beta,
+                double* __restrict__ var_el, unsigned long long* __restrict__ nonfinite,
+                unsigned long long* __restrict__ n_ood) {
     constexpr int WS = kWaveSlots<D> + kLamSlots<D, P>;
     __shared__ double lds[4 * WS];
     const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
     unsigned nf = 0, nood = 0;
-    fused_elements<D, G, P, FC, F32>(S, X, n, conn, vol, E, N, alpha, key, g, beta, gid / G, int(gid & (G - 1)), nf,
-                                     nood, lds + (threadIdx.x >> 6) * WS, var_el);
+    fused_elements<D, G, P, FC, F32, ORD>(S, X, n, conn, vol, E, N, alpha, key, g, beta, gid / G,
+                                          int(gid & (G - 1)), nf, nood, lds + (threadIdx.x >> 6) * WS, var_el,
+                                          dofs);
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
     if (nood) atomicAdd(n_ood, (unsigned long long)nood);
 }
@@ -42,12 +47,12 @@ ft_status source_eval(ft_source* S, int64_t head, int64_t npts, const void* pts,
 ft_status assemble_residual(ft_target* T, int F, const void* values, int64_t ld, bool f32, hipStream_t s);
 void zero_counters(unsigned long long* p, int n, hipStream_t s);
 
-template <int D, int G, int P, int FC>
+template <int D, int G, int P, int FC, int ORD = 1>
 static void launch_fused(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
     const SampleKey key = make_sample_key(*cfg, D);
     const unsigned grid = grid_for(T->E * G, 256);
-    auto kern = cfg->precision == FT_F32 ? k_fused_p1<D, G, P, FC, true> : k_fused_p1<D, G, P, FC, false>;
-    kern<<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->vol, uint32_t(T->E),
+    auto kern = cfg->precision == FT_F32 ? k_fused_p1<D, G, P, FC, true, ORD> : k_fused_p1<D, G, P, FC, false, ORD>;
+    kern<<<grid, 256, 0, s>>>(source_view(S), T->coords, T->n, T->conn, T->dofs, T->vol, uint32_t(T->E),
                               uint32_t(cfg->samples_per_elem), cfg->alpha, key, T->g, T->beta, T->var_el,
                               T->counters, T->counters + 1);
 }
@@ -71,10 +76,23 @@ static void fused_fc(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipSt
     else launch_fused<D, G, P, 4>(T, S, cfg, s);
 }
 
-// lanes per element G and samples per lane per round P
+// lanes per element G and samples per lane per round P (P2 targets: one
+// element per wave for N >= 64, else 16 lanes per element; one sample per
+// lane per round)
 template <int D>
 static void fused_g(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s) {
     const int N = cfg->samples_per_elem;
+    if (T->order == 2) {
+        const bool one = cfg->n_fields == 1;
+        if (N >= 64) {
+            if (one) launch_fused<D, 64, 1, 1, 2>(T, S, cfg, s);
+            else launch_fused<D, 64, 1, 4, 2>(T, S, cfg, s);
+        } else {
+            if (one) launch_fused<D, 16, 1, 1, 2>(T, S, cfg, s);
+            else launch_fused<D, 16, 1, 4, 2>(T, S, cfg, s);
+        }
+        return;
+    }
     if (N >= 256) fused_fc<D, 64, 4>(T, S, cfg, s);
     else if (N >= 128) fused_fc<D, 64, 2>(T, S, cfg, s);
     else if (N >= 64) fused_fc<D, 64, 1>(T, S, cfg, s);

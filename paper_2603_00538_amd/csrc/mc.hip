@@ -120,15 +120,18 @@ __global__ void k_emit_nodes(const double* __restrict__ X, int64_t n, int dim, v
 constexpr double kOwnAlphaLo = 0.0, kOwnAlphaHi = 2.0;
 
 
-template <int D, int G, int FC, bool F32, bool OWN>
+// P: degree of the target elements; dofs: the element's nodes, [E][nb].
+template <int D, int P, int G, int FC, bool F32, bool OWN>
 __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, const void* __restrict__ values_,
-                                                        const ValueLayout& L, int F, const int32_t* __restrict__ conn,
+                                                        const ValueLayout& L, int F, const int32_t* __restrict__ dofs,
                                                         const double* __restrict__ vol, int64_t n, uint32_t E,
                                                         uint32_t N, double alpha, const SampleKey& key,
                                                         double* __restrict__ beta, double* __restrict__ var_el) {
-    int v[D + 1];
+    static_assert(P == 1 || !OWN, "each element's own coefficient: P1 targets");
+    constexpr int NB = Basis<D, P>::n;
+    int v[NB];
 #pragma unroll
-    for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
+    for (int k = 0; k < NB; ++k) v[k] = dofs[int64_t(t) * NB + k];
     const double scale = vol[t] / double(N);
     const int64_t qbase = L.samp0 + int64_t(t) * L.samp_elem;
     unsigned int nf = 0;
@@ -136,9 +139,9 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
     const double Nd = double(N);
     const double inv_n = 1.0 / Nd, inv_var = N > 1 ? inv_n / (Nd - 1.0) : 0.0;
     for (int f0 = 0; f0 < F; f0 += FC) {
-        double gk[FC][D + 1];
-        double acc[FC][D + 1];    // sum r l_k (fixed alpha) or sum y l_k (OWN)
-        double accb[FO][D + 1];   // OWN: sum g l_k
+        double gk[FC][NB];
+        double acc[FC][NB];       // sum r psi_k (fixed alpha) or sum y l_k (OWN)
+        double accb[FO][NB];      // OWN: sum g l_k
         double pq[FO][2];         // OWN: sum y g w, sum g^2 w
         double vs[FC];            // sum s^2 (fixed alpha) or sum d^2 (OWN)
         double vm[FO][2];         // OWN: sum d u, sum u^2
@@ -148,14 +151,14 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
             gbar[f] = 0.0;
             vs[f] = 0.0;
 #pragma unroll
-            for (int k = 0; k <= D; ++k) {
+            for (int k = 0; k < NB; ++k) {
                 acc[f][k] = 0.0;
                 const int64_t off = int64_t(f0 + f < F ? f0 + f : 0) * L.node_ld + v[k];
                 gk[f][k] = F32 ? double(static_cast<const float*>(values_)[off])
                                : static_cast<const double*>(values_)[off];
                 gbar[f] += gk[f][k];
             }
-            gbar[f] *= 1.0 / double(D + 1);
+            gbar[f] *= 1.0 / double(NB);
             sh[f] = (alpha - 1.0) * gbar[f];
         }
 #pragma unroll
@@ -163,7 +166,7 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
             pq[f][0] = pq[f][1] = 0.0;
             vm[f][0] = vm[f][1] = 0.0;
 #pragma unroll
-            for (int k = 0; k <= D; ++k) accb[f][k] = 0.0;
+            for (int k = 0; k < NB; ++k) accb[f][k] = 0.0;
         }
         for (uint32_t j = lane; j < N; j += G) {
             double lam[D + 1];
@@ -175,10 +178,12 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
             } else {
                 sample_lambda<D>(t, j, key, lam);
             }
+            double psi[NB];
+            basis_at<D, P>(lam, psi);
             double w = 0.0;
             if constexpr (OWN) {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) w = fma(lam[k], lam[k], w);
+                for (int k = 0; k < NB; ++k) w = fma(psi[k], psi[k], w);
             }
 #pragma unroll
             for (int f = 0; f < FC; ++f) {
@@ -187,14 +192,14 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
                 const double y = F32 ? double(static_cast<const float*>(values_)[off])
                                      : static_cast<const double*>(values_)[off];
                 nf += !isfinite(y);
-                double gx = lam[0] * gk[f][0];
+                double gx = psi[0] * gk[f][0];
 #pragma unroll
-                for (int k = 1; k <= D; ++k) gx = fma(lam[k], gk[f][k], gx);
+                for (int k = 1; k < NB; ++k) gx = fma(psi[k], gk[f][k], gx);
                 if constexpr (OWN) {
 #pragma unroll
-                    for (int k = 0; k <= D; ++k) {
-                        acc[f][k] = fma(y, lam[k], acc[f][k]);
-                        accb[f][k] = fma(gx, lam[k], accb[f][k]);
+                    for (int k = 0; k < NB; ++k) {
+                        acc[f][k] = fma(y, psi[k], acc[f][k]);
+                        accb[f][k] = fma(gx, psi[k], accb[f][k]);
                     }
                     pq[f][0] = fma(y * gx, w, pq[f][0]);
                     pq[f][1] = fma(gx * gx, w, pq[f][1]);
@@ -205,7 +210,7 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
                 } else {
                     const double r = y - alpha * gx;
 #pragma unroll
-                    for (int k = 0; k <= D; ++k) acc[f][k] = fma(r, lam[k], acc[f][k]);
+                    for (int k = 0; k < NB; ++k) acc[f][k] = fma(r, psi[k], acc[f][k]);
                     const double sv = r + sh[f];
                     vs[f] = fma(sv, sv, vs[f]);
                 }
@@ -213,24 +218,25 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
         }
         // element totals: with one element per wave on the lane-swap / DPP
         // path, else butterflies over the element's G lanes
-        constexpr int KA = FC * (D + 1) + FC;   // acc, vs
-        constexpr int K = OWN ? KA + FO * (D + 1) + FO * 4 : KA;
+        constexpr int KA = FC * NB + FC;   // acc, vs
+        constexpr int KO = NB + 4;         // OWN, per field: accb, pq, vm
+        constexpr int K = OWN ? KA + FO * KO : KA;
         double red[K];
 #pragma unroll
         for (int f = 0; f < FC; ++f) {
 #pragma unroll
-            for (int k = 0; k <= D; ++k) red[f * (D + 1) + k] = acc[f][k];
-            red[FC * (D + 1) + f] = vs[f];
+            for (int k = 0; k < NB; ++k) red[f * NB + k] = acc[f][k];
+            red[FC * NB + f] = vs[f];
         }
         if constexpr (OWN) {
 #pragma unroll
             for (int f = 0; f < FO; ++f) {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) red[KA + f * (D + 5) + k] = accb[f][k];
-                red[KA + f * (D + 5) + D + 1] = pq[f][0];
-                red[KA + f * (D + 5) + D + 2] = pq[f][1];
-                red[KA + f * (D + 5) + D + 3] = vm[f][0];
-                red[KA + f * (D + 5) + D + 4] = vm[f][1];
+                for (int k = 0; k < NB; ++k) red[KA + f * KO + k] = accb[f][k];
+                red[KA + f * KO + NB] = pq[f][0];
+                red[KA + f * KO + NB + 1] = pq[f][1];
+                red[KA + f * KO + NB + 2] = vm[f][0];
+                red[KA + f * KO + NB + 3] = vm[f][1];
             }
         }
         if constexpr (G == 64) {
@@ -242,28 +248,28 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
 #pragma unroll
         for (int f = 0; f < FC; ++f) {
 #pragma unroll
-            for (int k = 0; k <= D; ++k) acc[f][k] = red[f * (D + 1) + k];
-            vs[f] = red[FC * (D + 1) + f];
+            for (int k = 0; k < NB; ++k) acc[f][k] = red[f * NB + k];
+            vs[f] = red[FC * NB + f];
         }
         if constexpr (OWN) {
 #pragma unroll
             for (int f = 0; f < FO; ++f) {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) accb[f][k] = red[KA + f * (D + 5) + k];
-                pq[f][0] = red[KA + f * (D + 5) + D + 1];
-                pq[f][1] = red[KA + f * (D + 5) + D + 2];
-                vm[f][0] = red[KA + f * (D + 5) + D + 3];
-                vm[f][1] = red[KA + f * (D + 5) + D + 4];
+                for (int k = 0; k < NB; ++k) accb[f][k] = red[KA + f * KO + k];
+                pq[f][0] = red[KA + f * KO + NB];
+                pq[f][1] = red[KA + f * KO + NB + 1];
+                vm[f][0] = red[KA + f * KO + NB + 2];
+                vm[f][1] = red[KA + f * KO + NB + 3];
             }
         }
         if (lane == 0) {
 #pragma unroll
             for (int f = 0; f < FC; ++f) {
                 if (f0 + f >= F) break;
-                double* bt = beta + (int64_t(f0 + f) * E + t) * (D + 1);
+                double* bt = beta + (int64_t(f0 + f) * E + t) * NB;
                 double sa = 0.0;   // sum_k of the element sums: the plain sum over the samples
 #pragma unroll
-                for (int k = 0; k <= D; ++k) sa += acc[f][k];
+                for (int k = 0; k < NB; ++k) sa += acc[f][k];
                 if constexpr (OWN) {
                     double ab = 0.0, bb = 0.0, gs = 0.0, sb = 0.0;
 #pragma unroll
@@ -291,7 +297,7 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
                     }
                 } else {
 #pragma unroll
-                    for (int k = 0; k <= D; ++k) bt[k] = acc[f][k] * scale;
+                    for (int k = 0; k < NB; ++k) bt[k] = acc[f][k] * scale;
                     // sum s = sum r + N (alpha - 1) gbar
                     if (var_el)
                         var_el[int64_t(f0 + f) * E + t] =
@@ -305,9 +311,9 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
 
 // G lanes per element.  R > 1 (G == 64 only): each wave sums R consecutive
 // elements in turn, with their element data in scalar registers.
-template <int D, int G, int FC, bool F32, int R, bool OWN>
+template <int D, int P, int G, int FC, bool F32, int R, bool OWN>
 __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, ValueLayout L, int F,
-                                                 const int32_t* __restrict__ conn, const double* __restrict__ vol,
+                                                 const int32_t* __restrict__ dofs, const double* __restrict__ vol,
                                                  int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
                                                  double* __restrict__ beta, double* __restrict__ var_el,
                                                  unsigned long long* __restrict__ nonfinite) {
@@ -319,8 +325,8 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         for (int e = 0; e < R; ++e) {
             const uint32_t t = wave * uint32_t(R) + uint32_t(e);
             if (t >= E) break;
-            nf += consume_element<D, G, FC, F32, OWN>(t, lane, values_, L, F, conn, vol, n, E, N, alpha, key, beta,
-                                                      var_el);
+            nf += consume_element<D, P, G, FC, F32, OWN>(t, lane, values_, L, F, dofs, vol, n, E, N, alpha, key,
+                                                         beta, var_el);
         }
     } else {
         const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
@@ -328,8 +334,8 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         const int lane = int(gid & (G - 1));
         if (t >= E) return;   // the whole group leaves together
         if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
-        nf = consume_element<D, G, FC, F32, OWN>(t, lane, values_, L, F, conn, vol, n, E, N, alpha, key, beta,
-                                                 var_el);
+        nf = consume_element<D, P, G, FC, F32, OWN>(t, lane, values_, L, F, dofs, vol, n, E, N, alpha, key, beta,
+                                                    var_el);
     }
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
@@ -338,7 +344,7 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
 // keeps g_v = values[f][v] (the control at the nodes) for the solve, unless
 // values is null (the fused route writes g itself).
 template <int D, bool F32>
-__global__ void k_assemble(const double* __restrict__ beta, int64_t E, const int64_t* __restrict__ inc_ptr,
+__global__ void k_assemble(const double* __restrict__ beta, int64_t E, int nb, const int64_t* __restrict__ inc_ptr,
                            const int32_t* __restrict__ inc, int64_t n, int F, const void* __restrict__ values_,
                            int64_t ld, double* __restrict__ bres, double* __restrict__ g,
                            unsigned long long* __restrict__ nonfinite) {
@@ -347,7 +353,7 @@ __global__ void k_assemble(const double* __restrict__ beta, int64_t E, const int
     const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
     unsigned int nf = 0;
     for (int f = 0; f < F; ++f) {
-        const double* bf = beta + int64_t(f) * E * (D + 1);
+        const double* bf = beta + int64_t(f) * E * nb;
         double s = 0.0;
         for (int64_t i = b; i < e; ++i) s += bf[inc[i]];
         bres[int64_t(f) * n + v] = s;
@@ -430,38 +436,46 @@ ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipS
 
 constexpr int kConsumeRuns = 4;   // elements per wave when G == 64
 
-template <int D, int G, int FC, bool F32>
+template <int D, int P, int G, int FC, bool F32>
 static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
                            double* beta, hipStream_t s) {
     const SampleKey key = make_key(T, cfg);
     constexpr int R = G == 64 ? kConsumeRuns : 1;
     const unsigned grid = grid_for(T->E * G, 256 * R);
-    auto kern = cfg->alpha_mode == FT_ALPHA_ELEMENT ? k_consume<D, G, FC, F32, R, true>
-                                                    : k_consume<D, G, FC, F32, R, false>;
-    kern<<<grid, 256, 0, s>>>(values, L, cfg->n_fields, T->conn, T->vol, T->n, uint32_t(T->E),
+    auto kern = k_consume<D, P, G, FC, F32, R, false>;
+    if constexpr (P == 1)
+        if (cfg->alpha_mode == FT_ALPHA_ELEMENT) kern = k_consume<D, P, G, FC, F32, R, true>;
+    kern<<<grid, 256, 0, s>>>(values, L, cfg->n_fields, T->dofs, T->vol, T->n, uint32_t(T->E),
                               uint32_t(cfg->samples_per_elem), cfg->alpha, key, beta, T->var_el, T->counters);
 }
 
-template <int D, int G, bool F32>
+template <int D, int P, int G, bool F32>
 static void consume_fc(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
                        double* beta, hipStream_t s) {
     if (cfg->n_fields == 1)
-        launch_consume<D, G, 1, F32>(T, cfg, values, L, beta, s);
+        launch_consume<D, P, G, 1, F32>(T, cfg, values, L, beta, s);
     else
-        launch_consume<D, G, 4, F32>(T, cfg, values, L, beta, s);
+        launch_consume<D, P, G, 4, F32>(T, cfg, values, L, beta, s);
 }
 
+// Lanes per element G from N (P2 targets: one element per wave for N >= 64,
+// else 16 lanes per element).
 template <int D, bool F32>
 static void consume_g(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
                       double* beta, hipStream_t s) {
     const int N = cfg->samples_per_elem;
-    if (N >= 64) consume_fc<D, 64, F32>(T, cfg, values, L, beta, s);
-    else if (N > 16) consume_fc<D, 32, F32>(T, cfg, values, L, beta, s);
-    else if (N > 8) consume_fc<D, 16, F32>(T, cfg, values, L, beta, s);
-    else if (N > 4) consume_fc<D, 8, F32>(T, cfg, values, L, beta, s);
-    else if (N > 2) consume_fc<D, 4, F32>(T, cfg, values, L, beta, s);
-    else if (N > 1) consume_fc<D, 2, F32>(T, cfg, values, L, beta, s);
-    else consume_fc<D, 1, F32>(T, cfg, values, L, beta, s);
+    if (T->order == 2) {
+        if (N >= 64) consume_fc<D, 2, 64, F32>(T, cfg, values, L, beta, s);
+        else consume_fc<D, 2, 16, F32>(T, cfg, values, L, beta, s);
+        return;
+    }
+    if (N >= 64) consume_fc<D, 1, 64, F32>(T, cfg, values, L, beta, s);
+    else if (N > 16) consume_fc<D, 1, 32, F32>(T, cfg, values, L, beta, s);
+    else if (N > 8) consume_fc<D, 1, 16, F32>(T, cfg, values, L, beta, s);
+    else if (N > 4) consume_fc<D, 1, 8, F32>(T, cfg, values, L, beta, s);
+    else if (N > 2) consume_fc<D, 1, 4, F32>(T, cfg, values, L, beta, s);
+    else if (N > 1) consume_fc<D, 1, 2, F32>(T, cfg, values, L, beta, s);
+    else consume_fc<D, 1, 1, F32>(T, cfg, values, L, beta, s);
 }
 
 // The layout of the caller's query values (ft_sample_cfg.values_layout).
@@ -481,10 +495,10 @@ template <int D>
 static void launch_assemble(ft_target* T, const double* beta, int F, const void* values, int64_t ld, bool f32,
                             hipStream_t s) {
     if (f32)
-        k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
+        k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(beta, T->E, T->nb, T->inc_ptr, T->inc, T->n, F, values,
                                                                ld, T->bres, T->g, T->counters);
     else
-        k_assemble<D, false><<<grid_for(T->n, 256), 256, 0, s>>>(beta, T->E, T->inc_ptr, T->inc, T->n, F, values,
+        k_assemble<D, false><<<grid_for(T->n, 256), 256, 0, s>>>(beta, T->E, T->nb, T->inc_ptr, T->inc, T->n, F, values,
                                                                 ld, T->bres, T->g, T->counters);
 }
 

@@ -1,16 +1,87 @@
-// Target setup: element measures, node -> element incidence, P1 mass matrix.
+// Target setup: element measures, node -> element incidence, mass matrix.
 //
-// Sec. 2: M_ki = int psi_k psi_i, assembled element by element.  For P1
-// simplices the element matrix is exact in closed form,
+// Sec. 2: M_ki = int psi_k psi_i, assembled element by element.  On a
+// straight-sided simplex the element matrix is |Omega_t| times a reference
+// matrix of integrals of products of the basis polynomials in the
+// barycentric coordinates: for P1 in closed form,
 //   M^t_kl = |Omega_t| (1 + delta_kl) / ((d+1)(d+2)),
-// which a degree-2 Gauss rule reproduces exactly.  |Omega_t| = |det J_t| / d!.
+// for P2 (vertex functions l_k (2 l_k - 1), edge functions 4 l_a l_b) from
+// the exact simplex moments int l^a = d! a_0! ... a_d! |T| / (d + |a|)!.
+// |Omega_t| = |det J_t| / d!.
 //
 // Everything is built on the device and is deterministic: incidence lists
 // are sorted by (element, local vertex), CSR rows by column, and every
 // floating-point sum runs in ascending element order.
+#include <cstring>
+
 #include "common.h"
 
 namespace ft {
+
+// The element mass matrix divided by |Omega_t| and its row sums (the
+// integrals of the basis functions over a unit-measure element).
+struct RefMass {
+    double m[10][10];
+    double rs[10];
+};
+
+static double simplex_moment(int d, const int* a) {   // int l^a over a unit-measure simplex
+    double num = 1.0, den = 1.0;
+    int s = 0;
+    for (int k = 0; k <= d; ++k) {
+        for (int i = 2; i <= a[k]; ++i) num *= i;
+        s += a[k];
+    }
+    for (int i = 2; i <= d; ++i) num *= i;
+    for (int i = 2; i <= d + s; ++i) den *= i;
+    return num / den;
+}
+
+static RefMass reference_mass(int d, int order) {
+    RefMass R{};
+    const int nb = order == 1 ? d + 1 : (d + 1) * (d + 2) / 2;
+    if (order == 1) {
+        const double c = 1.0 / ((d + 1) * (d + 2));
+        for (int k = 0; k < nb; ++k)
+            for (int l = 0; l < nb; ++l) R.m[k][l] = k == l ? 2.0 * c : c;
+    } else {
+        // basis polynomials: up to two terms (coefficient, exponents)
+        double cf[10][2];
+        int ex[10][2][4];
+        int nt[10];
+        std::memset(ex, 0, sizeof(ex));
+        for (int k = 0; k <= d; ++k) {
+            nt[k] = 2;
+            cf[k][0] = 2.0;
+            ex[k][0][k] = 2;
+            cf[k][1] = -1.0;
+            ex[k][1][k] = 1;
+        }
+        for (int e = 0; e < nb - d - 1; ++e) {
+            nt[d + 1 + e] = 1;
+            cf[d + 1 + e][0] = 4.0;
+            ex[d + 1 + e][0][p2_edge(d, e, 0)] = 1;
+            ex[d + 1 + e][0][p2_edge(d, e, 1)] = 1;
+        }
+        for (int i = 0; i < nb; ++i)
+            for (int j = 0; j < nb; ++j) {
+                double v = 0.0;
+                for (int p = 0; p < nt[i]; ++p)
+                    for (int q = 0; q < nt[j]; ++q) {
+                        int a[4];
+                        for (int k = 0; k < 4; ++k) a[k] = ex[i][p][k] + ex[j][q][k];
+                        v += cf[i][p] * cf[j][q] * simplex_moment(d, a);
+                    }
+                R.m[i][j] = v;
+            }
+    }
+    for (int k = 0; k < nb; ++k) {
+        double r = 0.0;
+        for (int l = 0; l < nb; ++l) r += R.m[k][l];
+        R.rs[k] = r;
+    }
+    return R;
+}
 
 template <int D>
 __global__ void k_elem_geom(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
@@ -63,21 +134,59 @@ __global__ void k_elem_geom(const double* __restrict__ X, int64_t n, const int32
     vol[t] = fabs(det) / fact;
 }
 
-template <int D>
-__global__ void k_count_incidence(const int32_t* __restrict__ conn, int64_t E, int32_t* __restrict__ cnt) {
+__global__ void k_count_incidence(const int32_t* __restrict__ dofs, int64_t NI, int32_t* __restrict__ cnt) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= E * (D + 1)) return;
-    atomicAdd(&cnt[conn[i]], 1);
+    if (i >= NI) return;
+    atomicAdd(&cnt[dofs[i]], 1);
 }
 
-template <int D>
-__global__ void k_fill_incidence(const int32_t* __restrict__ conn, int64_t E, const int64_t* __restrict__ ptr,
+__global__ void k_fill_incidence(const int32_t* __restrict__ dofs, int64_t NI, const int64_t* __restrict__ ptr,
                                  int32_t* __restrict__ slot, int32_t* __restrict__ inc) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= E * (D + 1)) return;
-    const int v = conn[i];
+    if (i >= NI) return;
+    const int v = dofs[i];
     const int pos = atomicAdd(&slot[v], 1);
-    inc[ptr[v] + pos] = int32_t(i);   // i = t*(D+1) + k
+    inc[ptr[v] + pos] = int32_t(i);   // i = t*nb + k
+}
+
+// P2: the vertex ids of each element (its first d+1 nodes); every node id in
+// range and every edge node at the midpoint of its edge (straight-sided
+// elements), else flags[0] / flags[4].
+template <int D>
+__global__ void k_p2_vertices(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ dofs, int64_t E,
+                              int32_t* __restrict__ conn, unsigned long long* __restrict__ flags) {
+    constexpr int NB = (D + 1) * (D + 2) / 2;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= E) return;
+    int v[NB];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        v[k] = dofs[t * NB + k];
+        bad |= (v[k] < 0) | (int64_t(v[k]) >= n);
+    }
+#pragma unroll
+    for (int k = 0; k <= D; ++k) conn[t * (D + 1) + k] = bad ? 0 : v[k];
+    if (bad) {
+        atomicAdd(&flags[0], 1ull);
+        return;
+    }
+    bool off = false;
+#pragma unroll
+    for (int e = 0; e < NB - D - 1; ++e) {
+        const int a = v[p2_edge(D, e, 0)];
+        const int b = v[p2_edge(D, e, 1)];
+        double len2 = 0.0, dev2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const double xa = X[c * n + a], xb = X[c * n + b], xm = X[c * n + v[D + 1 + e]];
+            len2 += (xb - xa) * (xb - xa);
+            const double dm = xm - 0.5 * (xa + xb);
+            dev2 += dm * dm;
+        }
+        off |= !(dev2 <= 1e-20 * len2);
+    }
+    if (off) atomicAdd(&flags[4], 1ull);
 }
 
 __global__ void k_count_unused(const int32_t* __restrict__ cnt, int64_t n, unsigned long long* __restrict__ flag) {
@@ -103,30 +212,33 @@ __global__ void k_sort_segments(const int64_t* __restrict__ ptr, int64_t nseg, i
     insertion_sort(data + ptr[s], ptr[s + 1] - ptr[s]);
 }
 
-// Candidate columns of row v: every vertex of every element touching v.
-// Written to cand[(D+1)*inc_ptr[v] ...], sorted, unique count -> rowlen[v].
-template <int D>
-__global__ void k_row_candidates(const int32_t* __restrict__ conn, const int64_t* __restrict__ inc_ptr,
+// Candidate columns of row v: every node of every element touching v.
+// Written to cand[nb*inc_ptr[v] ...], sorted, unique count -> rowlen[v].
+__global__ void k_row_candidates(const int32_t* __restrict__ dofs, int nb, const int64_t* __restrict__ inc_ptr,
                                  const int32_t* __restrict__ inc, int64_t n, int32_t* __restrict__ cand,
                                  int32_t* __restrict__ rowlen) {
     const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
-    int32_t* seg = cand + (D + 1) * b;
+    int32_t* seg = cand + nb * b;
     for (int64_t i = b; i < e; ++i) {
-        const int t = inc[i] / (D + 1);
-#pragma unroll
-        for (int l = 0; l <= D; ++l) seg[(D + 1) * (i - b) + l] = conn[int64_t(t) * (D + 1) + l];
+        const int t = inc[i] / nb;
+        for (int l = 0; l < nb; ++l) seg[nb * (i - b) + l] = dofs[int64_t(t) * nb + l];
     }
-    const int64_t len = (D + 1) * (e - b);
+    const int64_t len = nb * (e - b);
     insertion_sort(seg, len);
     int32_t u = len > 0 ? 1 : 0;
     for (int64_t i = 1; i < len; ++i) u += seg[i] != seg[i - 1];
     rowlen[v] = u;
 }
 
+// Row v of M: for every (element t, local node k) at v, vol_t * R.m[k][l]
+// added at column dofs[t][l], in ascending (t, k) order.  The row sum (the
+// lumped mass m_v = int psi_v) is vol_t / (d+1) per element for P1, and
+// vol_t * R.rs[k] for P2.
 template <int D>
-__global__ void k_fill_csr(const int32_t* __restrict__ conn, const double* __restrict__ vol,
+__global__ void k_fill_csr(const int32_t* __restrict__ dofs, int nb, int order, RefMass R,
+                           const double* __restrict__ vol,
                            const int64_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
                            const int32_t* __restrict__ cand, int64_t n, const int64_t* __restrict__ rowptr,
                            int32_t* __restrict__ col, double* __restrict__ val, double* __restrict__ diag,
@@ -134,8 +246,8 @@ __global__ void k_fill_csr(const int32_t* __restrict__ conn, const double* __res
     const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
-    const int32_t* seg = cand + (D + 1) * b;
-    const int64_t len = (D + 1) * (e - b);
+    const int32_t* seg = cand + nb * b;
+    const int64_t len = nb * (e - b);
     const int64_t r0 = rowptr[v];
     int64_t w = r0;
     for (int64_t i = 0; i < len; ++i)
@@ -145,21 +257,20 @@ __global__ void k_fill_csr(const int32_t* __restrict__ conn, const double* __res
             ++w;
         }
     const int64_t r1 = w;
-    const double c = 1.0 / ((D + 1) * (D + 2));
     double m = 0.0;
     for (int64_t i = b; i < e; ++i) {
-        const int64_t t = inc[i] / (D + 1);
+        const int64_t t = inc[i] / nb;
+        const int kv = int(inc[i] - t * nb);
         const double vt = vol[t];
-        m += vt / (D + 1);
-#pragma unroll
-        for (int l = 0; l <= D; ++l) {
-            const int32_t cw = conn[t * (D + 1) + l];
+        m += order == 1 ? vt / (D + 1) : vt * R.rs[kv];
+        for (int l = 0; l < nb; ++l) {
+            const int32_t cw = dofs[t * nb + l];
             int64_t lo = r0, hi = r1 - 1;   // binary search in the sorted row
             while (lo < hi) {
                 const int64_t mid = (lo + hi) >> 1;
                 if (col[mid] < cw) lo = mid + 1; else hi = mid;
             }
-            val[lo] += (cw == v ? 2.0 : 1.0) * vt * c;
+            val[lo] += vt * R.m[kv][l];
         }
     }
     for (int64_t i = r0; i < r1; ++i)
@@ -169,13 +280,14 @@ __global__ void k_fill_csr(const int32_t* __restrict__ conn, const double* __res
 
 template <int D>
 static ft_status build(ft_target* T, const double* coords_in, const int32_t* conn_in, hipStream_t s) {
-    const int64_t n = T->n, E = T->E, NI = E * (D + 1);
+    const int nb = T->order == 1 ? D + 1 : (D + 1) * (D + 2) / 2;
+    T->nb = nb;
+    const int64_t n = T->n, E = T->E, NI = E * nb;
     constexpr int B = 256;
     FT_TRY(dev_alloc_n(&T->coords, size_t(D) * n));
-    FT_TRY(dev_alloc_n(&T->conn, size_t(NI)));
+    FT_TRY(dev_alloc_n(&T->conn, size_t(E) * (D + 1)));
     FT_TRY(dev_alloc_n(&T->vol, size_t(E)));
     FT_TRY_HIP(hipMemcpyAsync(T->coords, coords_in, sizeof(double) * D * n, hipMemcpyDeviceToDevice, s));
-    FT_TRY_HIP(hipMemcpyAsync(T->conn, conn_in, sizeof(int32_t) * NI, hipMemcpyDeviceToDevice, s));
 
     // scratch: flags, counters, scan temp
     unsigned long long* flags = nullptr;
@@ -187,15 +299,24 @@ static ft_status build(ft_target* T, const double* coords_in, const int32_t* con
     guard.add((void**)&rowlen);
     guard.add((void**)&cand);
     guard.add((void**)&tmp);
-    FT_TRY(dev_alloc_n(&flags, 4));
+    FT_TRY(dev_alloc_n(&flags, 5));
     FT_TRY(dev_alloc_n(&cnt, size_t(n)));
     FT_TRY(dev_alloc_n(&rowlen, size_t(n)));
     FT_TRY(dev_alloc_n(&tmp, size_t(scan_tmp_elems(n))));
-    FT_TRY_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned long long), s));
+    FT_TRY_HIP(hipMemsetAsync(flags, 0, 5 * sizeof(unsigned long long), s));
 
+    if (T->order == 1) {
+        FT_TRY_HIP(hipMemcpyAsync(T->conn, conn_in, sizeof(int32_t) * NI, hipMemcpyDeviceToDevice, s));
+        T->dofs = T->conn;
+    } else {
+        FT_TRY(dev_alloc_n(&T->dofs, size_t(NI)));
+        FT_TRY_HIP(hipMemcpyAsync(T->dofs, conn_in, sizeof(int32_t) * NI, hipMemcpyDeviceToDevice, s));
+        k_p2_vertices<D><<<grid_for(E, B), B, 0, s>>>(T->coords, n, T->dofs, E, T->conn, flags);
+        FT_TRY_HIP(hipGetLastError());
+    }
     k_elem_geom<D><<<grid_for(E, B), B, 0, s>>>(T->coords, n, T->conn, E, T->vol, flags);
     FT_TRY_HIP(hipGetLastError());
-    unsigned long long hf[4];
+    unsigned long long hf[5];
     FT_TRY_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     FT_TRY_HIP(hipStreamSynchronize(s));
     if (hf[0]) {
@@ -206,23 +327,27 @@ static ft_status build(ft_target* T, const double* coords_in, const int32_t* con
         set_error("%llu degenerate element(s): |det J| <= 1e-12 h^d", hf[1]);
         return FT_E_MESH;
     }
+    if (hf[4]) {
+        set_error("%llu element(s) have an edge node off the midpoint of its edge (straight-sided P2 only)", hf[4]);
+        return FT_E_MESH;
+    }
     T->n_inverted = (int64_t)hf[2];
 
-    // incidence CSR, entries t*(D+1)+k sorted ascending per node
+    // incidence CSR, entries t*nb+k sorted ascending per node
     FT_TRY(dev_alloc_n(&T->inc_ptr, size_t(n + 1)));
     FT_TRY(dev_alloc_n(&T->inc, size_t(NI)));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * n, s));
-    k_count_incidence<D><<<grid_for(NI, B), B, 0, s>>>(T->conn, E, cnt);
+    k_count_incidence<<<grid_for(NI, B), B, 0, s>>>(T->dofs, NI, cnt);
     k_count_unused<<<grid_for(n, B), B, 0, s>>>(cnt, n, flags + 3);
     FT_TRY(exclusive_scan(cnt, T->inc_ptr, n, tmp, s));
     FT_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * n, s));
-    k_fill_incidence<D><<<grid_for(NI, B), B, 0, s>>>(T->conn, E, T->inc_ptr, cnt, T->inc);
+    k_fill_incidence<<<grid_for(NI, B), B, 0, s>>>(T->dofs, NI, T->inc_ptr, cnt, T->inc);
     k_sort_segments<<<grid_for(n, B), B, 0, s>>>(T->inc_ptr, n, T->inc);
     FT_TRY_HIP(hipGetLastError());
 
     // CSR pattern and values
-    FT_TRY(dev_alloc_n(&cand, size_t(NI) * (D + 1)));
-    k_row_candidates<D><<<grid_for(n, B), B, 0, s>>>(T->conn, T->inc_ptr, T->inc, n, cand, rowlen);
+    FT_TRY(dev_alloc_n(&cand, size_t(NI) * nb));
+    k_row_candidates<<<grid_for(n, B), B, 0, s>>>(T->dofs, nb, T->inc_ptr, T->inc, n, cand, rowlen);
     FT_TRY(dev_alloc_n(&T->rowptr, size_t(n + 1)));
     FT_TRY(exclusive_scan(rowlen, T->rowptr, n, tmp, s));
     int64_t nnz = 0;
@@ -238,8 +363,8 @@ static ft_status build(ft_target* T, const double* coords_in, const int32_t* con
     FT_TRY(dev_alloc_n(&T->val, size_t(nnz)));
     FT_TRY(dev_alloc_n(&T->diag, size_t(n)));
     FT_TRY(dev_alloc_n(&T->lumped, size_t(n)));
-    k_fill_csr<D><<<grid_for(n, B), B, 0, s>>>(T->conn, T->vol, T->inc_ptr, T->inc, cand, n, T->rowptr, T->col,
-                                              T->val, T->diag, T->lumped);
+    k_fill_csr<D><<<grid_for(n, B), B, 0, s>>>(T->dofs, nb, T->order, reference_mass(D, T->order), T->vol, T->inc_ptr,
+                                              T->inc, cand, n, T->rowptr, T->col, T->val, T->diag, T->lumped);
     FT_TRY_HIP(hipGetLastError());
     FT_TRY_HIP(hipStreamSynchronize(s));
     return FT_OK;

@@ -28,7 +28,7 @@ FT_VALUES_FIELD_MAJOR, FT_VALUES_ELEMENT_TILES = 0, 1
 STATUS_NAMES = {0: "FT_OK", -1: "FT_E_ARG", -2: "FT_E_MESH", -3: "FT_E_ORDER", -4: "FT_E_DEVICE",
                 -5: "FT_E_NOCONV", -6: "FT_E_NONFINITE", -7: "FT_E_OOM", -8: "FT_E_UNSUPPORTED"}
 
-EXPORTED = ["ft_target_create", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
+EXPORTED = ["ft_target_create", "ft_target_create_p2", "ft_target_destroy", "ft_target_get_info", "ft_query_count", "ft_sample_points",
             "ft_consume_queries", "ft_consume_queries_noalloc", "ft_transfer_p1",
             "ft_transfer_supermesh", "ft_project", "ft_source_create_p1", "ft_source_eval",
             "ft_source_eval_queries", "ft_source_eval_tiles", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_autotune", "ft_batch_variant",
@@ -61,7 +61,7 @@ class Report(ctypes.Structure):
 
 class TargetInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int64),
-                ("nnz", ctypes.c_int64), ("n_inverted", ctypes.c_int64)]
+                ("nnz", ctypes.c_int64), ("n_inverted", ctypes.c_int64), ("order", ctypes.c_int32)]
 
 
 class SourceInfo(ctypes.Structure):
@@ -89,6 +89,7 @@ def load(path: str = LIB_PATH):
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
         "ft_target_create": (I32, [I32, I64, P, I64, P, P, ctypes.POINTER(P)]),
+        "ft_target_create_p2": (I32, [I32, I64, P, I64, P, P, ctypes.POINTER(P)]),
         "ft_target_destroy": (I32, [P]),
         "ft_target_get_info": (I32, [P, ctypes.POINTER(TargetInfo)]),
         "ft_query_count": (I64, [P, I32]),
@@ -137,6 +138,13 @@ def ft_target_create(dim, n_nodes, coords_ptr, n_elems, conn_ptr, stream):
     h = ctypes.c_void_p()
     _check(load().ft_target_create(dim, n_nodes, coords_ptr, n_elems, conn_ptr, stream, ctypes.byref(h)),
            "ft_target_create")
+    return h
+
+
+def ft_target_create_p2(dim, n_nodes, coords_ptr, n_elems, conn_ptr, stream):
+    h = ctypes.c_void_p()
+    _check(load().ft_target_create_p2(dim, n_nodes, coords_ptr, n_elems, conn_ptr, stream, ctypes.byref(h)),
+           "ft_target_create_p2")
     return h
 
 
@@ -339,17 +347,21 @@ class Transfer:
 
 
 class Target:
-    """A P1 target mesh on the device (ft_target_create ... ft_target_destroy)."""
+    """A target mesh on the device (ft_target_create / ft_target_create_p2 ...
+    ft_target_destroy).  order 2: conn lists each element's vertices, then its
+    edge nodes (ft_target_create_p2)."""
 
-    def __init__(self, coords, conn, device="cuda"):
+    def __init__(self, coords, conn, device="cuda", order=1):
         torch = _torch()
         self.dim = int(coords.shape[1])
+        self.order = int(order)
         self.coords = _soa(coords, device)                                  # (d, n)
         self.conn = torch.as_tensor(conn, dtype=torch.int32).contiguous().to(device)
         self.n_nodes = int(coords.shape[0])
         self.n_elems = int(conn.shape[0])
-        self.handle = ft_target_create(self.dim, self.n_nodes, self.coords.data_ptr(), self.n_elems,
-                                       self.conn.data_ptr(), current_stream())
+        create = ft_target_create_p2 if self.order == 2 else ft_target_create
+        self.handle = create(self.dim, self.n_nodes, self.coords.data_ptr(), self.n_elems, self.conn.data_ptr(),
+                             current_stream())
 
     def close(self):
         if getattr(self, "handle", None):

@@ -59,7 +59,7 @@ def test_struct_layouts_match_header(tmp_path):
                    "P(ft_sample_cfg, precision);\n"
                    "P(ft_report, iters); P(ft_report, status); P(ft_report, n_nonfinite); "
                    "P(ft_report, sum_b_stderr);\n"
-                   "P(ft_target_info, n_nodes); P(ft_target_info, n_inverted);\n"
+                   "P(ft_target_info, n_nodes); P(ft_target_info, n_inverted); P(ft_target_info, order);\n"
                    "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
@@ -87,6 +87,8 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.ft_target_create(2, 2, fake, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
     assert lib.ft_target_create(2, 10, fake, 0, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
     assert lib.ft_target_create(2, 10, fake, 4, fake, None, None) == ft.FT_E_ARG
+    assert lib.ft_target_create_p2(4, 10, fake, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert lib.ft_target_create_p2(2, 5, fake, 1, fake, None, ctypes.byref(h)) == ft.FT_E_ARG   # < 6 nodes
     assert lib.ft_query_count(None, 4) == -1
     cfg = ft.SampleCfg(0, 1, 1.0, 0, 0, ft.FT_F64)
     assert lib.ft_sample_points(None, ctypes.byref(cfg), fake, None) == ft.FT_E_ARG

@@ -12,6 +12,8 @@ tri2d_4k                2    Delaunay 45^2       3,872      Delaunay 70^2       
 tri2d_1m                2    structured 708^2    999,698    structured 1415^2    3,998,792   256   1
 tet3d_2m                3    Kuhn 71^3 nodes     2,058,000  Kuhn 111^3 nodes     7,986,000   128   1
 tet3d_1m_64f            3    Kuhn 56^3 nodes     998,250    Kuhn 88^3 nodes      3,951,018   128   64
+tri2d_1m_p2             2    as tri2d_1m, P2     999,698    as tri2d_1m          3,998,792   256   1
+tet3d_2m_p2             3    as tet3d_2m, P2     2,058,000  as tet3d_2m          7,986,000   128   1
 ======================  ===  ==================  =========  ===================  ==========  ====  ==
 
 Seeds: target jitter 11, source jitter 12, field parameters 13, Philox key
@@ -62,6 +64,7 @@ class Workload:
     index: int = 0
     bins: tuple = (0, 0, 0)      # 0 = library default
     rtol: float = 1e-14
+    order: int = 1               # target elements: 1 (P1) or 2 (P2, midpoints added by meshes.p2_mesh)
 
     @property
     def philox_seed(self) -> int:
@@ -85,7 +88,24 @@ WORKLOADS = {
         "tet3d_1m_64f", 3,
         MeshSpec("kuhn_tet", 56, 0.08, 11), MeshSpec("kuhn_tet", 88, 0.08, 12),
         "fourier_fields_3d", 128, n_fields=64, index=4),
+    # the same meshes with quadratic target elements
+    "tri2d_1m_p2": Workload(
+        "tri2d_1m_p2", 2,
+        MeshSpec("structured_tri", 708, 0.2, 11), MeshSpec("structured_tri", 1415, 0.2, 12),
+        "front_2d", 256, index=6, bins=(512, 512, 0), order=2),
+    "tet3d_2m_p2": Workload(
+        "tet3d_2m_p2", 3,
+        MeshSpec("kuhn_tet", 71, 0.08, 11), MeshSpec("kuhn_tet", 111, 0.08, 12),
+        "gaussian_bumps_3d", 128, index=7, order=2),
 }
+
+
+def target_mesh(w: Workload):
+    """The workload's target mesh: P1 as built, or with edge nodes for P2."""
+    coords, conn = build_mesh(w.target)
+    if w.order == 1:
+        return coords, conn
+    return _meshes.p2_mesh(coords, conn)
 
 
 @lru_cache(maxsize=8)

@@ -125,3 +125,26 @@ def make_mesh(kind: str, k: int, jitter: float, seed: int):
     if kind == "kuhn_tet":
         return kuhn_tet_mesh(k, jitter, seed)
     raise ValueError(f"unknown mesh kind {kind!r}")
+
+
+# local edges of a P2 element, vertex pairs a < b in lexicographic order
+P2_LOCAL_EDGES = {2: ((0, 1), (0, 2), (1, 2)), 3: ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))}
+
+
+def p2_mesh(coords: np.ndarray, conn: np.ndarray):
+    """Straight-sided P2 mesh on a P1 mesh: the vertices keep their ids, the
+    edge midpoints follow them, numbered in ascending (lower, higher vertex
+    id) order; each element lists its d+1 vertices, then its edge nodes in
+    the order of P2_LOCAL_EDGES.  Returns (coords2, conn2)."""
+    coords = np.asarray(coords, dtype=np.float64)
+    conn = np.asarray(conn, dtype=np.int64)
+    dim = coords.shape[1]
+    n = coords.shape[0]
+    pairs = np.stack([np.sort(conn[:, [a, b]], axis=1) for a, b in P2_LOCAL_EDGES[dim]], axis=1)  # (E, ne, 2)
+    keys = pairs[..., 0] * n + pairs[..., 1]
+    uniq, inv = np.unique(keys.ravel(), return_inverse=True)
+    lo, hi = uniq // n, uniq % n
+    mid = 0.5 * (coords[lo] + coords[hi])
+    coords2 = np.concatenate([coords, mid])
+    conn2 = np.concatenate([conn, n + inv.reshape(keys.shape)], axis=1)
+    return coords2, conn2.astype(np.int32)
