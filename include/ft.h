@@ -483,10 +483,13 @@ enum { FT_BATCH_GRAPH = 1 };   /* capture a run as a HIP graph; later runs repla
  * ft_batch_create - set up a batch of `count` transfers.
  *   targets, sources   host arrays [count] of handles; not owned: they must
  *                      outlive the batch, and no other call may use them while
- *                      ft_batch_run runs.  Targets must be distinct.
+ *                      ft_batch_run runs.  Targets must be distinct (P1).
  *   cfgs               host [count]: per-transfer sample configuration
- *                      (n_fields 1 = the source's field count, FT_F64 or FT_F32)
+ *                      (n_fields = the source's field count, FT_F64 or FT_F32)
  *   flags              0 or FT_BATCH_GRAPH
+ * A transfer of F fields runs as F systems, one per field, sharing its
+ * target's mass matrix and samples (each field localizes its samples again:
+ * a multi-field transfer costs about F one-field ones in the element stage).
  * Builds the work lists (node, element and row tiles; element tiles grouped
  * by variant, the dearest variants first) and the batch's solver vectors on
  * the device.
@@ -498,10 +501,10 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
 /*
  * ft_batch_run - sec. 4.1 steps 1-7 for every transfer of the batch
  * (binary64 solve: cfg->refine_steps must be 0).
- *   x        host array [count] of device pointers: x[k] binary64 [n_nodes of target k]
- *   b        host array [count] of device pointers (load vectors) or null entries, or null
- *   reports  host [count], one report per transfer
- *   status   host [count] or null: per-transfer status
+ *   x        host array [count] of device pointers: x[k] binary64 [n_fields][n_nodes] of transfer k
+ *   b        host array [count] of device pointers (load vectors, as x) or null entries, or null
+ *   reports  host [sum of n_fields], one report per field: transfer 0's fields, then transfer 1's, ...
+ *   status   host [sum of n_fields] or null: per-field status
  * The solve launches exactly cfg->max_iter Jacobi-PCG iterations (a converged
  * system's tiles return at once), so a run has no host synchronization until
  * its end; with FT_BATCH_GRAPH the first run with a given (rtol, max_iter) is

@@ -416,6 +416,7 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
     FT_ARG_CHECK(count >= 1 && count <= (1 << 20), "count out of range (%d)", count);
     FT_ARG_CHECK(targets && sources && cfgs, "targets, sources and cfgs must be host arrays");
     FT_ARG_CHECK((flags & ~FT_BATCH_GRAPH) == 0, "unknown flags 0x%x", flags);
+    int64_t systems = 0;
     for (int k = 0; k < count; ++k) {
         const ft_target* t = targets[k];
         const ft_source* s = sources[k];
@@ -424,12 +425,14 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
         FT_ARG_CHECK(s->dim == t->dim, "transfer %d: source dimension %d differs from target dimension %d", k,
                      s->dim, t->dim);
         FT_TRY(check_alpha_mode(t, &cfgs[k], false));
-        if ((cfgs[k].precision != FT_F64 && cfgs[k].precision != FT_F32) || cfgs[k].n_fields != 1 || s->F != 1 ||
-            t->order != 1) {
-            set_error("transfer %d: batches run FT_F64 or FT_F32 transfers of one field from one-field sources to "
-                      "P1 targets", k);
+        FT_ARG_CHECK(cfgs[k].n_fields == s->F, "transfer %d: n_fields (%d) must equal the source's field count (%d)",
+                     k, cfgs[k].n_fields, s->F);
+        if ((cfgs[k].precision != FT_F64 && cfgs[k].precision != FT_F32) || t->order != 1) {
+            set_error("transfer %d: batches run FT_F64 or FT_F32 transfers to P1 targets", k);
             return FT_E_UNSUPPORTED;
         }
+        systems += cfgs[k].n_fields;
+        FT_ARG_CHECK(systems <= (1 << 20), "more than 2^20 fields in the batch");
         for (int j = 0; j < k; ++j)
             FT_ARG_CHECK(targets[j] != t, "transfers %d and %d share a target (its work buffers)", j, k);
     }

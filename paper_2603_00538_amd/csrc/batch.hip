@@ -1,8 +1,11 @@
 // Many transfers at once: target/source pairs of mixed dimension and size,
 // each with its own samples per element, run as one sequence of launches
 // (sec. 4.1 steps 1-7 for every pair; the pairs are independent work units,
-// sec. 4.1 last paragraph).  Built-in P1 sources, one field per transfer, in
-// the binary64 or the binary32 form of the fused route.
+// sec. 4.1 last paragraph).  Built-in P1 sources in the binary64 or the
+// binary32 form of the fused route.  A transfer of F fields runs as F
+// systems, one per field, that share the transfer's target (mass matrix,
+// incidence, samples) and write their own slice of its field buffers; the
+// kernels below work on systems.
 //
 // Work lists built once at creation:
 //   node tiles     (transfer, 256 / 128 target nodes) step 1, the control g
@@ -434,10 +437,14 @@ __global__ __launch_bounds__(64) void k_batch_scalars(const BatchXfer* __restric
 
 // ---------------------------------------------------------------- host side
 struct ft_batch {
-    int count = 0;
-    std::vector<ft_target*> T;
+    int count = 0;                      // systems: one per field of each transfer
+    int n_xfer = 0;                     // transfers
+    std::vector<ft_target*> T;          // per system
     std::vector<ft_source*> S;
-    std::vector<ft_sample_cfg> cfg;
+    std::vector<ft_sample_cfg> cfg;     // per system (one field)
+    std::vector<int> xfer, field;       // per system: its transfer and field
+    std::vector<int> first;             // per transfer: its first system
+    std::vector<ft_sample_cfg> xcfg;    // per transfer, as given
     std::vector<int> var;         // element-stage variant (G, P) of each transfer
     int64_t rows = 0;
     size_t elem_cap = 0;          // element tiles d_elem can hold
@@ -473,12 +480,22 @@ namespace ft {
 ft_batch* batch_new(int count, ft_target* const* targets, ft_source* const* sources, const ft_sample_cfg* cfgs,
                     bool graph) {
     auto* b = new ft_batch();
-    b->count = count;
-    b->T.assign(targets, targets + count);
-    b->S.assign(sources, sources + count);
-    b->cfg.assign(cfgs, cfgs + count);
-    b->var.resize(count);
-    for (int k = 0; k < count; ++k) b->var[k] = variant_of(cfgs[k].samples_per_elem);
+    b->n_xfer = count;
+    b->xcfg.assign(cfgs, cfgs + count);
+    for (int k = 0; k < count; ++k) {
+        b->first.push_back(int(b->T.size()));
+        for (int f = 0; f < cfgs[k].n_fields; ++f) {
+            ft_sample_cfg c = cfgs[k];
+            c.n_fields = 1;
+            b->T.push_back(targets[k]);
+            b->S.push_back(sources[k]);
+            b->cfg.push_back(c);
+            b->xfer.push_back(k);
+            b->field.push_back(f);
+            b->var.push_back(variant_of(c.samples_per_elem));
+        }
+    }
+    b->count = int(b->T.size());
     b->use_graph = graph;
     return b;
 }
@@ -488,9 +505,10 @@ void batch_delete(ft_batch* b) { delete b; }
 // after a run every target holds g, beta and b_res of its transfer, as after
 // ft_transfer_p1: ft_project may re-solve it on its own
 void batch_mark_consumed(ft_batch* b) {
-    for (int k = 0; k < b->count; ++k) {
-        b->T[k]->consumed = true;
-        b->T[k]->consumed_cfg = b->cfg[k];
+    for (int k = 0; k < b->n_xfer; ++k) {
+        ft_target* T = b->T[b->first[k]];
+        T->consumed = true;
+        T->consumed_cfg = b->xcfg[k];
     }
 }
 
@@ -513,7 +531,13 @@ void batch_release(ft_batch* b) {
 static void fill_live(ft_batch* b, int k, BatchXfer& x) {
     ft_target* T = b->T[k];
     ft_source* S = b->S[k];
+    const int f = b->field[k];
     x.src = source_view(S);
+    if (S->F > 1) {   // this system's field: the source seen as one field in its values array
+        x.src.values += int64_t(f) * S->n;
+        x.src.F = 1;
+        x.src.rec_values = 0;
+    }
     x.coords = T->coords;
     x.conn = T->conn;
     x.vol = T->vol;
@@ -524,9 +548,9 @@ static void fill_live(ft_batch* b, int k, BatchXfer& x) {
     x.val = T->val;
     x.diag = T->diag;
     x.lumped = T->lumped;
-    x.g = T->g;
-    x.beta = T->beta;
-    x.bres = T->bres;
+    x.g = T->g + int64_t(f) * T->n;
+    x.beta = T->beta + int64_t(f) * T->E * (T->dim + 1);
+    x.bres = T->bres + int64_t(f) * T->n;
     x.ood = b->nonfinite + b->count + k;
 }
 
@@ -598,7 +622,7 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
     for (int k = 0; k < K; ++k) {
         ft_target* T = b->T[k];
         const ft_sample_cfg& c = b->cfg[k];
-        FT_TRY(ensure_field_buffers(T, 1, s));
+        FT_TRY(ensure_field_buffers(T, b->xcfg[b->xfer[k]].n_fields, s));
         BatchXfer& x = xs[k];
         x.n = T->n;
         x.E = T->E;
@@ -896,21 +920,23 @@ ft_status batch_autotune(ft_batch* b, const char* cache_path, int32_t* n_tuned, 
     return FT_OK;
 }
 
-int batch_count(const ft_batch* b) { return b->count; }
+int batch_count(const ft_batch* b) { return b->n_xfer; }
+int batch_systems(const ft_batch* b) { return b->count; }
 
-// The element-stage variant of transfer k as (G, P).
+// The element-stage variant of transfer k as (G, P) (that of its first field).
 void batch_variant(const ft_batch* b, int k, int32_t* G, int32_t* P) {
-    *G = lanes_of(b->var[k]);
-    *P = per_lane_of(b->var[k]);
+    *G = lanes_of(b->var[b->first[k]]);
+    *P = per_lane_of(b->var[b->first[k]]);
 }
 
 ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec, ft_report* rep,
                     int32_t* status, hipStream_t s) {
     const int K = b->count;
     FT_TRY(refresh_descriptors(b, s));
-    for (int k = 0; k < K; ++k) {
-        b->h_xs[k] = x[k];
-        b->h_xs[K + k] = bvec ? bvec[k] : nullptr;
+    for (int k = 0; k < K; ++k) {   // system k: field f of transfer xfer[k], rows [f n, (f + 1) n)
+        const int64_t off = int64_t(b->field[k]) * b->T[k]->n;
+        b->h_xs[k] = x[b->xfer[k]] + off;
+        b->h_xs[K + k] = bvec ? bvec[b->xfer[k]] + off : nullptr;
     }
     FT_TRY_HIP(hipMemcpyAsync(b->d_xs, b->h_xs, sizeof(double*) * 2 * K, hipMemcpyHostToDevice, s));
     if (b->use_graph) {
@@ -956,7 +982,7 @@ ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, doub
         b->T[k]->ood_mode = 2;   // a later ft_project of this target reports the same count
         b->T[k]->var_mode = VAR_NONE;
         R.sum_b_stderr = -1.0;
-        b->T[k]->ood_host = R.n_out_of_domain;
+        if (b->field[k] == 0) b->T[k]->ood_host = R.n_out_of_domain;
         R.status = b->h_nf[k] ? FT_E_NONFINITE : (h[BS_DONE] != 0.0 ? FT_OK : FT_E_NOCONV);
         if (status) status[k] = R.status;
         if (R.status != FT_OK && (worst == FT_OK || R.status == FT_E_NONFINITE)) worst = ft_status(R.status);

@@ -127,6 +127,7 @@ struct SrcView {
     GridView g;
     int64_t E;        // elements (the whole-mesh search for points outside the domain)
     double tau;       // margin of the fast selection test (>= kFastTau)
+    int32_t rec_values;   // 1: the (one) field's vertex values sit in the element records
 };
 
 // Barycentric coordinates of p in the element of record r (origin x0 and the
@@ -435,7 +436,7 @@ template <int D>
 __device__ __forceinline__ double p1_value(const SrcView& S, int bid, const double (&bmu)[D + 1], int f) {
     if (bid == INT_MAX) return 0.0;
     double y = 0.0;
-    if (S.F == 1) {   // vertex values in the element's record
+    if (S.rec_values) {   // vertex values in the element's record
         const double* rv = S.rec + int64_t(bid) * RecSize<D>::value + RecValues<D>::value;
 #pragma unroll
         for (int k = 0; k <= D; ++k) y = fma(bmu[k], rv[k], y);

@@ -538,6 +538,7 @@ SrcView source_view(const ft_source* S) {
     v.F = S->F;
     v.E = S->E;
     v.tau = S->fast_tau;
+    v.rec_values = S->F == 1 ? 1 : 0;
     for (int c = 0; c < 3; ++c) {
         v.g.nb[c] = S->nb[c];
         v.g.hx[c] = S->hx[c];

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_supermesh2d(SrcView S, const double* __
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
                         fv[f][k] = f >= S.F ? 0.0
-                                            : (S.F == 1 ? r[RecValues<2>::value + k]
+                                            : (S.rec_values ? r[RecValues<2>::value + k]
                                                         : S.values[int64_t(f) * S.n + sv[k]]);
                 for (int i = 1; i + 1 < m; ++i) {
                     const double ar =
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(256) void k_supermesh3d(SrcView S, const double* __
 #pragma unroll
                         for (int k = 0; k < 4; ++k)
                             fv[f][k] = f >= S.F ? 0.0
-                                                : (S.F == 1 ? r[RecValues<3>::value + k]
+                                                : (S.rec_values ? r[RecValues<3>::value + k]
                                                             : S.values[int64_t(f) * S.n + S.conn[int64_t(e) * 4 + k]]);
                     // depth-first over the cuts by mu_0 .. mu_3 >= 0
 #pragma unroll

@@ -199,12 +199,13 @@ def ft_batch_create(targets, sources, cfgs, flags, stream):
     return out
 
 
-def ft_batch_run(h, cfg: SolveCfg, x_ptrs, b_ptrs, stream, allow=(FT_E_NOCONV, FT_E_NONFINITE)):
+def ft_batch_run(h, cfg: SolveCfg, x_ptrs, b_ptrs, stream, n_systems=None, allow=(FT_E_NOCONV, FT_E_NONFINITE)):
     K = len(x_ptrs)
     xs = (ctypes.c_void_p * K)(*x_ptrs)
     bs = (ctypes.c_void_p * K)(*b_ptrs) if b_ptrs is not None else None
-    reps = (Report * K)()
-    sts = (ctypes.c_int32 * K)()
+    R = n_systems or K   # one report per field of every transfer
+    reps = (Report * R)()
+    sts = (ctypes.c_int32 * R)()
     st = _check(load().ft_batch_run(h, ctypes.byref(cfg), xs, bs, reps, sts, stream), "ft_batch_run", allow)
     return st, [r.as_dict() for r in reps], list(sts)
 
@@ -555,8 +556,9 @@ class Batch:
 
     targets, sources: Target and Source objects (kept alive by the batch);
     cfgs: one SampleCfg per transfer.  run() returns, per transfer, the
-    solution x (device tensor) and the load vector b, the reports and the
-    per-transfer statuses.
+    solution x (device tensor, (n,) for one field, (F, n) for F > 1) and the
+    load vector b, the reports and statuses (one per field, transfer by
+    transfer).
     """
 
     def __init__(self, targets, sources, cfgs, graph=False):
@@ -568,14 +570,17 @@ class Batch:
     def run(self, rtol=1e-14, max_iter=60, xs=None, bs=None, want_b=True):
         torch = _torch()
         dev = self.targets[0].coords.device
+        def shape(t, c):
+            return (t.n_nodes,) if c.n_fields == 1 else (c.n_fields, t.n_nodes)
         if xs is None:
-            xs = [torch.empty(t.n_nodes, dtype=torch.float64, device=dev) for t in self.targets]
+            xs = [torch.empty(shape(t, c), dtype=torch.float64, device=dev) for t, c in zip(self.targets, self.cfgs)]
         if want_b and bs is None:
-            bs = [torch.empty(t.n_nodes, dtype=torch.float64, device=dev) for t in self.targets]
+            bs = [torch.empty(shape(t, c), dtype=torch.float64, device=dev) for t, c in zip(self.targets, self.cfgs)]
         f64 = (torch.float64,)
         xp = [_device_ptr(x, "x", f64) for x in xs]
         bp = [_device_ptr(b, "b", f64) for b in bs] if want_b else None
-        st, reps, sts = ft_batch_run(self.handle, SolveCfg(rtol, max_iter), xp, bp, current_stream())
+        st, reps, sts = ft_batch_run(self.handle, SolveCfg(rtol, max_iter), xp, bp, current_stream(),
+                                     n_systems=sum(c.n_fields for c in self.cfgs))
         return xs, bs, reps, sts, st
 
     def autotune(self, cache_path=None):

@@ -120,3 +120,43 @@ def test_batch_autotune_and_cache(tuned_case):
         assert torch.equal(bs2[k], bs[k])
     B2.close()
     os.remove(cache)
+
+
+def test_batch_many_fields_match_single_route_and_oracle():
+    """Transfers of several fields in one batch (each field a system of its
+    own on the transfer's target): per field the single-transfer fused route's
+    load vector and the oracle's; more than four fields, beyond the fused
+    route, against the oracle; reports per field, transfer by transfer."""
+    t2, s2 = meshes.delaunay_tri_mesh(10, 0.3, 181), meshes.delaunay_tri_mesh(15, 0.3, 182)
+    t3, s3 = meshes.kuhn_tet_mesh(4, 0.08, 183), meshes.kuhn_tet_mesh(6, 0.08, 184)
+    x2, x3 = s2[0], s3[0]
+    v2 = np.ascontiguousarray(np.stack([np.sin((f + 1) * x2[:, 0]) + np.cos((f + 2) * x2[:, 1]) for f in range(3)]))
+    v3 = np.ascontiguousarray(np.stack([np.cos(f * x3[:, 0] + 1.0) * x3[:, 2] + x3[:, 1] for f in range(7)]))
+    v1 = fields.evaluate("smooth_2d", np, s2[0])
+    t1 = meshes.delaunay_tri_mesh(8, 0.3, 185)
+    items = [(t2, s2, v2, 64), (t3, s3, v3, 32), (t1, s2, v1, 20)]
+    targets = [ft.Target(*tm) for tm, _, _, _ in items]
+    sources = [ft.Source(*sm, sv) for _, sm, sv, _ in items]
+    cfgs = [ft.SampleCfg(N, sv.shape[0], 1.0, SEED, 50 + k, ft.FT_F64) for k, (_, _, sv, N) in enumerate(items)]
+    log("batch of many-field transfers: F = 3, 7, 1")
+    B = ft.Batch(targets, sources, cfgs, graph=True)
+    for _ in range(2):
+        xs, bs, reps, sts, st = B.run(rtol=1e-14, max_iter=80)
+        assert st == ft.FT_OK and len(reps) == 3 + 7 + 1 and all(s_ == ft.FT_OK for s_ in sts)
+    r = 0
+    for k, ((tm, sm, sv, N), T, S, c) in enumerate(zip(items, targets, sources, cfgs)):
+        F = sv.shape[0]
+        bk = bs[k].cpu().numpy().reshape(F, -1)
+        xk = xs[k].cpu().numpy().reshape(F, -1)
+        ref = oracle_transfer(tm, sm, sv, N, 1.0, SEED, 50 + k)
+        assert rel_l2(bk, ref["b"]) < 1e-12 and rel_l2(xk, ref["x"]) < 1e-12
+        for f in range(F):
+            assert abs(reps[r + f]["sum_b"] - ref["report"][f]["sum_b"]) <= 1e-12 * abs(ref["report"][f]["sum_b"])
+        r += F
+        if F <= 4:
+            T.transfer_from(S, c)
+            single = T.project(F)
+            assert rel_l2(bk, single.b.cpu().numpy().reshape(F, -1)) < 1e-14
+    B.close()
+    for o in targets + sources:
+        o.close()
