@@ -484,6 +484,8 @@ enum { FT_BATCH_GRAPH = 1 };   /* capture a run as a HIP graph; later runs repla
  *   targets, sources   host arrays [count] of handles; not owned: they must
  *                      outlive the batch, and no other call may use them while
  *                      ft_batch_run runs.  Targets must be distinct (P1).
+ *                      sources may hold only null entries: a batch for
+ *                      caller values (ft_batch_consume_run)
  *   cfgs               host [count]: per-transfer sample configuration
  *                      (n_fields = the source's field count, FT_F64 or FT_F32)
  *   flags              0 or FT_BATCH_GRAPH
@@ -515,6 +517,27 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
  */
 ft_status ft_batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec,
                        ft_report* reports, int32_t* status, hipStream_t stream);
+
+/*
+ * ft_batch_consume_run - the black-box route for every transfer of a batch
+ * (sec. 4.1 steps 4-7 from the caller's values): each transfer's values are
+ * consumed as ft_consume_queries does, then all fields of all transfers are
+ * assembled and solved together by the batched Jacobi-PCG and reported as
+ * ft_batch_run does (n_out_of_domain -1, sum_b_stderr from the samples).
+ * Each target must hold the query list of its transfer (ft_sample_points
+ * with the transfer's cfg); the batch may have been created without sources
+ * (sources[k] all null), and then only this call runs it.
+ *   values   host array [count] of device pointers: the query values of
+ *            transfer k, [n_fields][Q_k] (or element tiles, per its cfg),
+ *            binary64 or binary32 as its cfg
+ *   x, b, reports, status   as ft_batch_run
+ * FT_F64 and FT_F32 transfers with one fixed alpha each.  Runs without a
+ * graph.  Errors: FT_E_ARG, FT_E_ORDER (a target not sampled with its
+ * transfer's configuration), FT_E_UNSUPPORTED; per-field FT_E_NOCONV /
+ * FT_E_NONFINITE as ft_batch_run.  Synchronizes `stream`.
+ */
+ft_status ft_batch_consume_run(ft_batch* b, const ft_solve_cfg* cfg, const void* const* values, double* const* x,
+                               double* const* bvec, ft_report* reports, int32_t* status, hipStream_t stream);
 
 /*
  * ft_batch_autotune - pick, for each kind of transfer in the batch, the

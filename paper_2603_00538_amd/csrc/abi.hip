@@ -35,6 +35,11 @@ void batch_mark_consumed(ft_batch* b);
 ft_status batch_autotune(ft_batch* b, const char* cache_path, int32_t* n_tuned, hipStream_t s);
 void batch_variant(const ft_batch* b, int k, int32_t* G, int32_t* P);
 int batch_count(const ft_batch* b);
+ft_target* batch_target(const ft_batch* b, int k);
+const ft_sample_cfg* batch_cfg(const ft_batch* b, int k);
+bool batch_has_sources(const ft_batch* b);
+ft_status batch_run_values(ft_batch* b, const ft_solve_cfg* cfg, const void* const* values, double* const* x,
+                           double* const* bvec, ft_report* rep, int32_t* status, hipStream_t s);
 ft_status plan_setup(ft_plan* pl, hipStream_t s);
 ft_status plan_transfer(ft_plan* pl, const double* vals, hipStream_t s);
 ft_plan* plan_new(ft_target* T, ft_source* S, const ft_sample_cfg* cfg);
@@ -407,6 +412,12 @@ ft_status ft_plan_destroy(ft_plan* p) {
     return FT_OK;
 }
 
+static bool sources_all_null(int count, ft_source* const* sources) {
+    for (int k = 0; k < count; ++k)
+        if (sources[k]) return false;
+    return true;
+}
+
 ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* const* sources,
                           const ft_sample_cfg* cfgs, int32_t flags, hipStream_t stream, ft_batch** out) {
     FT_GUARD_BEGIN
@@ -420,13 +431,16 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
     for (int k = 0; k < count; ++k) {
         const ft_target* t = targets[k];
         const ft_source* s = sources[k];
-        FT_ARG_CHECK(t && s, "transfer %d: null target or source", k);
+        FT_ARG_CHECK(t, "transfer %d: null target", k);
         FT_TRY(check_sample_cfg(t, &cfgs[k]));
-        FT_ARG_CHECK(s->dim == t->dim, "transfer %d: source dimension %d differs from target dimension %d", k,
-                     s->dim, t->dim);
+        FT_ARG_CHECK(!s || s->dim == t->dim, "transfer %d: source dimension %d differs from target dimension %d", k,
+                     s ? s->dim : 0, t->dim);
         FT_TRY(check_alpha_mode(t, &cfgs[k], false));
-        FT_ARG_CHECK(cfgs[k].n_fields == s->F, "transfer %d: n_fields (%d) must equal the source's field count (%d)",
-                     k, cfgs[k].n_fields, s->F);
+        FT_ARG_CHECK(!s || cfgs[k].n_fields == s->F,
+                     "transfer %d: n_fields (%d) must equal the source's field count (%d)", k, cfgs[k].n_fields,
+                     s ? s->F : 0);
+        FT_ARG_CHECK(s || sources_all_null(count, sources), "transfer %d: either every transfer has a source or none",
+                     k);
         if ((cfgs[k].precision != FT_F64 && cfgs[k].precision != FT_F32) || t->order != 1) {
             set_error("transfer %d: batches run FT_F64 or FT_F32 transfers to P1 targets", k);
             return FT_E_UNSUPPORTED;
@@ -457,7 +471,40 @@ ft_status ft_batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, d
     FT_ARG_CHECK(cfg->rtol >= 0.0 && std::isfinite(cfg->rtol), "rtol must be finite and >= 0");
     FT_ARG_CHECK(cfg->max_iter >= 0 && cfg->max_iter <= 100000, "max_iter must lie in [0, 100000]");
     FT_ARG_CHECK(cfg->refine_steps == 0, "batches solve in binary64 (refine_steps must be 0)");
+    if (!batch_has_sources(b)) {
+        set_error("this batch has no built-in sources: run it with ft_batch_consume_run");
+        return FT_E_ORDER;
+    }
     const ft_status st = batch_run(b, cfg, x, bvec, reports, status, stream);
+    if (st == FT_OK || st == FT_E_NOCONV || st == FT_E_NONFINITE) batch_mark_consumed(b);
+    return st;
+    FT_GUARD_END
+}
+
+ft_status ft_batch_consume_run(ft_batch* b, const ft_solve_cfg* cfg, const void* const* values, double* const* x,
+                               double* const* bvec, ft_report* reports, int32_t* status, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(b && cfg && values && x && reports, "null argument");
+    FT_ARG_CHECK(cfg->rtol >= 0.0 && std::isfinite(cfg->rtol), "rtol must be finite and >= 0");
+    FT_ARG_CHECK(cfg->max_iter >= 0 && cfg->max_iter <= 100000, "max_iter must lie in [0, 100000]");
+    FT_ARG_CHECK(cfg->refine_steps == 0, "batches solve in binary64 (refine_steps must be 0)");
+    for (int k = 0; k < batch_count(b); ++k) {
+        auto* T = static_cast<ft_target_ext*>(batch_target(b, k));
+        const ft_sample_cfg* c = batch_cfg(b, k);
+        FT_ARG_CHECK(values[k], "values[%d] is null", k);
+        if (!T->sampled || !same_samples(T->sampled_cfg, *c)) {
+            set_error("transfer %d: its target needs a prior ft_sample_points with the transfer's samples_per_elem, "
+                      "seed, stream_id and point precision", k);
+            return FT_E_ORDER;
+        }
+        if (c->alpha_mode != FT_ALPHA_FIXED) {
+            set_error("transfer %d: batches use one fixed alpha per transfer", k);
+            return FT_E_UNSUPPORTED;
+        }
+        FT_TRY(ensure_field_buffers(T, c->n_fields, stream));
+    }
+    const ft_status st = batch_run_values(b, cfg, values, x, bvec, reports, status, stream);
     if (st == FT_OK || st == FT_E_NOCONV || st == FT_E_NONFINITE) batch_mark_consumed(b);
     return st;
     FT_GUARD_END
@@ -467,6 +514,10 @@ ft_status ft_batch_autotune(ft_batch* b, const char* cache_path, int32_t* n_tune
     FT_GUARD_BEGIN
     clear_error();
     FT_ARG_CHECK(b, "batch is null");
+    if (!batch_has_sources(b)) {
+        set_error("the batch autotuner times the built-in route: this batch has no sources");
+        return FT_E_ORDER;
+    }
     return batch_autotune(b, cache_path, n_tuned, stream);
     FT_GUARD_END
 }

@@ -532,8 +532,12 @@ static void fill_live(ft_batch* b, int k, BatchXfer& x) {
     ft_target* T = b->T[k];
     ft_source* S = b->S[k];
     const int f = b->field[k];
-    x.src = source_view(S);
-    if (S->F > 1) {   // this system's field: the source seen as one field in its values array
+    if (!S) {   // caller-values batch: no built-in source
+        std::memset(&x.src, 0, sizeof(x.src));
+    } else {
+        x.src = source_view(S);
+    }
+    if (S && S->F > 1) {   // this system's field: the source seen as one field in its values array
         x.src.values += int64_t(f) * S->n;
         x.src.F = 1;
         x.src.rec_values = 0;
@@ -674,13 +678,15 @@ ft_status batch_setup(ft_batch* b, hipStream_t s) {
 }
 
 // Every launch of one run, in order; no host synchronization, no memset.
-static ft_status enqueue_run(ft_batch* b, const ft_solve_cfg* cfg, hipStream_t s) {
+// Without the element stage (the caller-values route) the runs starts from
+// g and the element loads the consumption left in the targets.
+static ft_status enqueue_run(ft_batch* b, const ft_solve_cfg* cfg, hipStream_t s, bool elements = true) {
     const int K = b->count;
     const unsigned nrt = unsigned(b->n_row_tiles);
     const int64_t rows = b->rows;
     k_fill_u64<<<grid_for(2 * K, 256), 256, 0, s>>>(b->nonfinite, 2 * K);
-    if (b->n_node_tiles) k_batch_nodes<<<b->grid_node, 256, 0, s>>>(b->d_x, b->d_node, b->n_node_tiles);
-    for (int i = 0; i < kCodes; ++i)
+    if (elements && b->n_node_tiles) k_batch_nodes<<<b->grid_node, 256, 0, s>>>(b->d_x, b->d_node, b->n_node_tiles);
+    for (int i = 0; elements && i < kCodes; ++i)
         if (b->code_first[i + 1] > b->code_first[i])
             launch_fused(b->code_order[i], b->code_grid[i], s, b->d_x, b->d_elem, b->code_first[i],
                          b->code_first[i + 1], b->nonfinite);
@@ -988,6 +994,64 @@ ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, doub
         if (R.status != FT_OK && (worst == FT_OK || R.status == FT_E_NONFINITE)) worst = ft_status(R.status);
     }
     if (worst == FT_E_NONFINITE) set_error("non-finite source values in at least one transfer of the batch");
+    else if (worst == FT_E_NOCONV) set_error("CG did not reach rtol=%g within %d iterations for at least one transfer",
+                                             cfg->rtol, cfg->max_iter);
+    return worst;
+}
+
+ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s);
+ft_status stderr_launch(ft_target* T, int F, hipStream_t s);
+
+ft_target* batch_target(const ft_batch* b, int k) { return b->T[b->first[k]]; }
+const ft_sample_cfg* batch_cfg(const ft_batch* b, int k) { return &b->xcfg[k]; }
+bool batch_has_sources(const ft_batch* b) {
+    for (const ft_source* S : b->S)
+        if (!S) return false;
+    return true;
+}
+
+// Steps 4-7 of every transfer from caller values (the black-box route of
+// each target, ft_consume_queries, then the batched solve): each transfer's
+// consumption writes its element loads, g and b_res for all its fields; the
+// batch then assembles, solves and reports every field, with no graph.
+ft_status batch_run_values(ft_batch* b, const ft_solve_cfg* cfg, const void* const* values, double* const* x,
+                           double* const* bvec, ft_report* rep, int32_t* status, hipStream_t s) {
+    const int K = b->count;
+    FT_TRY(refresh_descriptors(b, s));
+    std::vector<unsigned long long> nonfinite(b->n_xfer, 0ull);
+    for (int k = 0; k < b->n_xfer; ++k) {
+        ft_target* T = b->T[b->first[k]];
+        FT_TRY(consume_values(T, &b->xcfg[k], values[k], T->beta, s));
+        FT_TRY_HIP(hipMemcpyAsync(&nonfinite[k], T->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        FT_TRY(stderr_launch(T, b->xcfg[k].n_fields, s));
+    }
+    for (int k = 0; k < K; ++k) {
+        const int64_t off = int64_t(b->field[k]) * b->T[k]->n;
+        b->h_xs[k] = x[b->xfer[k]] + off;
+        b->h_xs[K + k] = bvec ? bvec[b->xfer[k]] + off : nullptr;
+    }
+    FT_TRY_HIP(hipMemcpyAsync(b->d_xs, b->h_xs, sizeof(double*) * 2 * K, hipMemcpyHostToDevice, s));
+    FT_TRY(enqueue_run(b, cfg, s, false));
+    FT_TRY_HIP(hipMemcpyAsync(b->h_sc, b->sc, sizeof(double) * BS_COUNT * K, hipMemcpyDeviceToHost, s));
+    FT_TRY_HIP(hipStreamSynchronize(s));
+    ft_status worst = FT_OK;
+    for (int k = 0; k < K; ++k) {
+        const double* h = b->h_sc + int64_t(k) * BS_COUNT;
+        ft_report& R = rep[k];
+        R.sum_b = h[BS_SUMB];
+        R.int_x = h[BS_INTX];
+        R.cons_defect = h[BS_SUMB] != 0.0 ? std::fabs(h[BS_INTX] - h[BS_SUMB]) / std::fabs(h[BS_SUMB])
+                                          : std::fabs(h[BS_INTX]);
+        R.rel_resid = h[BS_BB] > 0.0 ? std::sqrt(h[BS_TRR] / h[BS_BB]) : std::sqrt(h[BS_TRR]);
+        R.iters = int32_t(h[BS_ITERS]);
+        R.n_nonfinite = int64_t(nonfinite[b->xfer[k]]);
+        R.n_out_of_domain = -1;   // the caller's black box evaluated the points
+        R.sum_b_stderr = b->T[k]->var_mode == VAR_ESTIMATED ? std::sqrt(b->T[k]->h_var[b->field[k]]) : -1.0;
+        R.status = R.n_nonfinite ? FT_E_NONFINITE : (h[BS_DONE] != 0.0 ? FT_OK : FT_E_NOCONV);
+        if (status) status[k] = R.status;
+        if (R.status != FT_OK && (worst == FT_OK || R.status == FT_E_NONFINITE)) worst = ft_status(R.status);
+    }
+    if (worst == FT_E_NONFINITE) set_error("non-finite query values in at least one transfer of the batch");
     else if (worst == FT_E_NOCONV) set_error("CG did not reach rtol=%g within %d iterations for at least one transfer",
                                              cfg->rtol, cfg->max_iter);
     return worst;

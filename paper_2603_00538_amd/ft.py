@@ -32,7 +32,7 @@ EXPORTED = ["ft_target_create", "ft_target_create_p2", "ft_target_destroy", "ft_
             "ft_consume_queries", "ft_consume_queries_noalloc", "ft_transfer_p1",
             "ft_transfer_supermesh", "ft_project", "ft_source_create_p1", "ft_source_eval",
             "ft_source_eval_queries", "ft_source_eval_tiles", "ft_source_autotune", "ft_source_stats", "ft_batch_create", "ft_batch_run", "ft_batch_autotune", "ft_batch_variant",
-            "ft_batch_destroy",
+            "ft_batch_destroy", "ft_batch_consume_run",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_samples_for_tolerance",
             "ft_last_error"]
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
         "ft_batch_create": (I32, [I32, P, P, ctypes.POINTER(SampleCfg), I32, P, ctypes.POINTER(P)]),
         "ft_batch_run": (I32, [P, ctypes.POINTER(SolveCfg), P, P, ctypes.POINTER(Report), P, P]),
         "ft_batch_destroy": (I32, [P]),
+        "ft_batch_consume_run": (I32, [P, ctypes.POINTER(SolveCfg), P, P, P, ctypes.POINTER(Report), P, P]),
         "ft_batch_autotune": (I32, [P, ctypes.c_char_p, ctypes.POINTER(I32), P]),
         "ft_batch_variant": (I32, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "ft_plan_create": (I32, [P, P, ctypes.POINTER(SampleCfg), P, ctypes.POINTER(P)]),
@@ -207,6 +208,19 @@ def ft_batch_run(h, cfg: SolveCfg, x_ptrs, b_ptrs, stream, n_systems=None, allow
     reps = (Report * R)()
     sts = (ctypes.c_int32 * R)()
     st = _check(load().ft_batch_run(h, ctypes.byref(cfg), xs, bs, reps, sts, stream), "ft_batch_run", allow)
+    return st, [r.as_dict() for r in reps], list(sts)
+
+
+def ft_batch_consume_run(h, cfg: SolveCfg, value_ptrs, x_ptrs, b_ptrs, stream, n_systems,
+                         allow=(FT_E_NOCONV, FT_E_NONFINITE)):
+    K = len(x_ptrs)
+    vs = (ctypes.c_void_p * K)(*value_ptrs)
+    xs = (ctypes.c_void_p * K)(*x_ptrs)
+    bs = (ctypes.c_void_p * K)(*b_ptrs) if b_ptrs is not None else None
+    reps = (Report * n_systems)()
+    sts = (ctypes.c_int32 * n_systems)()
+    st = _check(load().ft_batch_consume_run(h, ctypes.byref(cfg), vs, xs, bs, reps, sts, stream),
+                "ft_batch_consume_run", allow)
     return st, [r.as_dict() for r in reps], list(sts)
 
 
@@ -562,14 +576,18 @@ class Batch:
     """
 
     def __init__(self, targets, sources, cfgs, graph=False):
-        self.targets, self.sources = list(targets), list(sources)
+        """sources=None: a batch for caller values (consume_run only)."""
+        self.targets = list(targets)
+        self.sources = list(sources) if sources is not None else [None] * len(self.targets)
         self.cfgs = list(cfgs)
-        self.handle = ft_batch_create([t.handle for t in self.targets], [s.handle for s in self.sources],
+        self.handle = ft_batch_create([t.handle for t in self.targets],
+                                      [s.handle if s is not None else None for s in self.sources],
                                       self.cfgs, FT_BATCH_GRAPH if graph else 0, current_stream())
 
-    def run(self, rtol=1e-14, max_iter=60, xs=None, bs=None, want_b=True):
+    def _outputs(self, xs, bs, want_b):
         torch = _torch()
         dev = self.targets[0].coords.device
+
         def shape(t, c):
             return (t.n_nodes,) if c.n_fields == 1 else (c.n_fields, t.n_nodes)
         if xs is None:
@@ -579,8 +597,22 @@ class Batch:
         f64 = (torch.float64,)
         xp = [_device_ptr(x, "x", f64) for x in xs]
         bp = [_device_ptr(b, "b", f64) for b in bs] if want_b else None
+        return xs, bs, xp, bp
+
+    def run(self, rtol=1e-14, max_iter=60, xs=None, bs=None, want_b=True):
+        xs, bs, xp, bp = self._outputs(xs, bs, want_b)
         st, reps, sts = ft_batch_run(self.handle, SolveCfg(rtol, max_iter), xp, bp, current_stream(),
                                      n_systems=sum(c.n_fields for c in self.cfgs))
+        return xs, bs, reps, sts, st
+
+    def consume_run(self, values, rtol=1e-14, max_iter=60, xs=None, bs=None, want_b=True):
+        """ft_batch_consume_run: values[k] holds transfer k's query values (its
+        target sampled with cfgs[k] beforehand)."""
+        torch = _torch()
+        vp = [_device_ptr(v, "values", (torch.float64, torch.float32)) for v in values]
+        xs, bs, xp, bp = self._outputs(xs, bs, want_b)
+        st, reps, sts = ft_batch_consume_run(self.handle, SolveCfg(rtol, max_iter), vp, xp, bp, current_stream(),
+                                             sum(c.n_fields for c in self.cfgs))
         return xs, bs, reps, sts, st
 
     def autotune(self, cache_path=None):

@@ -160,3 +160,50 @@ def test_batch_many_fields_match_single_route_and_oracle():
     B.close()
     for o in targets + sources:
         o.close()
+
+
+def test_batch_consume_run_matches_single_black_box():
+    """Caller values for every transfer (a batch created without sources): per
+    field the load vector and solution of each target's own black-box route
+    (ft_consume_queries + ft_project), binary64 and binary32, one and several
+    fields, with the standard error of sum b; the built-in run is refused for
+    such a batch, and so is a target sampled with another configuration."""
+    t2, s2 = meshes.delaunay_tri_mesh(11, 0.3, 191), meshes.delaunay_tri_mesh(16, 0.3, 192)
+    t3, s3 = meshes.kuhn_tet_mesh(5, 0.08, 193), meshes.kuhn_tet_mesh(6, 0.08, 194)
+    v2 = np.ascontiguousarray(np.stack([np.sin((f + 1) * s2[0][:, 0]) + s2[0][:, 1] for f in range(2)]))
+    v3 = fields.evaluate("gaussian_bumps_3d", np, s3[0])
+    items = [(t2, s2, v2, 48, ft.FT_F64), (t3, s3, v3, 64, ft.FT_F32), (t2, s2, v2[:1].copy(), 100, ft.FT_F64)]
+    targets = [ft.Target(*tm) for tm, _, _, _, _ in items]
+    sources = [ft.Source(*sm, sv) for _, sm, sv, _, _ in items]
+    cfgs = [ft.SampleCfg(N, sv.shape[0], 0.75, SEED, 60 + k, prec) for k, (_, _, sv, N, prec) in enumerate(items)]
+    log("batch of caller-value transfers")
+    B = ft.Batch(targets, None, cfgs)
+    values = []
+    for T, S, c in zip(targets, sources, cfgs):
+        pts = T.sample_points(c)
+        values.append(S.eval_query_list(pts, T.n_nodes))
+    xs, bs, reps, sts, st = B.consume_run(values, rtol=1e-14, max_iter=100)
+    assert st == ft.FT_OK and len(reps) == 2 + 1 + 1
+    r = 0
+    for k, (T, c) in enumerate(zip(targets, cfgs)):
+        F = c.n_fields
+        T.consume(c, values[k])
+        single = T.project(F)
+        assert rel_l2(bs[k].cpu().numpy().reshape(F, -1), single.b.cpu().numpy()) < 1e-14
+        assert rel_l2(xs[k].cpu().numpy().reshape(F, -1), single.x.cpu().numpy()) < 1e-12
+        for f in range(F):
+            assert reps[r + f]["n_out_of_domain"] == -1
+            assert abs(reps[r + f]["sum_b_stderr"] - single.reports[f]["sum_b_stderr"]) <= \
+                1e-12 * single.reports[f]["sum_b_stderr"]
+        r += F
+    with pytest.raises(ft.FtError) as e:
+        B.run()
+    assert e.value.status == ft.FT_E_ORDER
+    other = ft.SampleCfg(cfgs[0].samples_per_elem, cfgs[0].n_fields, 0.75, SEED, 99, ft.FT_F64)
+    targets[0].sample_points(other)
+    with pytest.raises(ft.FtError) as e:
+        B.consume_run(values)
+    assert e.value.status == ft.FT_E_ORDER
+    B.close()
+    for o in targets + sources:
+        o.close()
