@@ -100,6 +100,54 @@ __global__ __launch_bounds__(RB) void k_cg_spmv(Mat A, int k, const double* __re
     write_partial(part, P_PQ, pq);
 }
 
+// The same iteration for matrices with long rows (P2 tetrahedra: about 30
+// entries a row): L lanes per row walk its entries together (consecutive
+// entries, so each load of the matrix is a contiguous run) and add their
+// parts with a butterfly; a block takes RB / L rows per pass.
+template <int L>
+__global__ __launch_bounds__(RB) void k_cg_spmv_rows(Mat A, int k, const double* __restrict__ z,
+                                                     const double* __restrict__ p_old, double* __restrict__ p_new,
+                                                     double* __restrict__ q, double* __restrict__ part,
+                                                     double* __restrict__ scal) {
+    if (scal[S_DONE] != 0.0) return;
+    const double rz = partial_total(part, P_RZ, gridDim.x);
+    const double rr = partial_total(part, P_RR, gridDim.x);
+    if (rr <= scal[S_TOL2] || !isfinite(rr)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[S_DONE] = 1.0;
+            scal[S_ITERS] = double(k);
+        }
+        return;
+    }
+    const double bt = k == 0 ? 0.0 : rz / scal[S_RHO0 + ((k - 1) & 1)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_RHO0 + (k & 1)] = rz;
+    const int sub = int(threadIdx.x) & (L - 1);
+    double pq = 0.0;
+    for (int64_t i0 = int64_t(blockIdx.x) * (RB / L); i0 < A.n; i0 += int64_t(gridDim.x) * (RB / L)) {
+        const int64_t i = i0 + int(threadIdx.x) / L;
+        double qi = 0.0;
+        if (i < A.n) {
+            const int64_t k1 = A.rowptr[i + 1];
+            for (int64_t kk = A.rowptr[i] + sub; kk < k1; kk += L) {
+                const int32_t j = A.col[kk];
+                qi = fma(A.val[kk], fma(bt, p_old[j], z[j]), qi);
+            }
+        }
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) qi += __shfl_xor(qi, o, L);
+        if (i < A.n && sub == 0) {
+            const double pi = fma(bt, p_old[i], z[i]);
+            p_new[i] = pi;
+            q[i] = qi;
+            pq = fma(pi, qi, pq);
+        }
+    }
+    write_partial(part, P_PQ, pq);
+}
+
+// Rows this long or longer on average take the lanes-per-row product.
+constexpr int kLongRows = 24;
+
 // Iteration k, second half: alpha = rz_k / (p.q); y += alpha p; r -= alpha q;
 // z = D^-1 r; partials of r.z and r.r for iteration k+1.
 __global__ __launch_bounds__(RB) void k_cg_update(Mat A, int k, const double* __restrict__ p,
@@ -519,7 +567,10 @@ static ft_status project_one(ft_target* T, const ft_solve_cfg* cfg, double* x, d
             const int kk = launched + it;
             double* p_old = T->p + ((kk & 1) ? n : 0);
             double* p_new = T->p + ((kk & 1) ? 0 : n);
-            k_cg_spmv<<<nb, RB, 0, s>>>(A, kk, T->z, p_old, p_new, T->q, T->partials, T->scal);
+            if (T->nnz >= kLongRows * n)
+                k_cg_spmv_rows<8><<<nb, RB, 0, s>>>(A, kk, T->z, p_old, p_new, T->q, T->partials, T->scal);
+            else
+                k_cg_spmv<<<nb, RB, 0, s>>>(A, kk, T->z, p_old, p_new, T->q, T->partials, T->scal);
             k_cg_update<<<nb, RB, 0, s>>>(A, kk, p_new, T->q, T->y, T->r, T->z, T->partials, T->scal);
         }
         launched += k;

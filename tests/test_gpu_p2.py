@@ -154,3 +154,40 @@ def test_p2_noalloc_and_unsupported_routes():
     with pytest.raises(ft.FtError) as e:
         ft.Target(bad, t2, order=2)
     assert e.value.status == ft.FT_E_MESH
+
+
+@pytest.mark.parametrize("name,N", [("tri2d_1m_p2", 16), ("tet3d_2m_p2", 8)])
+def test_p2_fullsize_quadratic_and_conservation(name, N):
+    """At the full P2 workload sizes (2.0M and 2.9M nodes): a quadratic field
+    evaluated by the caller at the query points is reproduced at every node
+    (the P2 mass matrix, assembly and solve at scale), and for the workload's
+    own source sum b lies within six standard errors of the exact integral."""
+    from workloads import configs
+    w = configs.WORKLOADS[name]
+    c2, t2 = configs.target_mesh(w)
+    log(f"full-size P2: {name}, N={N}")
+    T = ft.Target(c2, t2, order=2)
+    cfg = _cfg(N)
+    pts = T.sample_points(cfg)
+    x = pts
+    if w.dim == 2:
+        vals = 1.0 + x[0] - 2.0 * x[1] + 3.0 * x[0] * x[1] - x[0] ** 2 + 0.5 * x[1] ** 2
+    else:
+        vals = 1.0 + x[0] - x[2] + 2.0 * x[1] * x[2] - x[0] ** 2 + x[0] * x[1]
+    T.consume(cfg, vals[None].contiguous())
+    del vals
+    r = T.project(1, rtol=1e-14, max_iter=1000)
+    assert r.status == ft.FT_OK
+    want = 1.0 + c2[:, 0] - 2.0 * c2[:, 1] + 3.0 * c2[:, 0] * c2[:, 1] - c2[:, 0] ** 2 + 0.5 * c2[:, 1] ** 2 \
+        if w.dim == 2 else 1.0 + c2[:, 0] - c2[:, 2] + 2.0 * c2[:, 1] * c2[:, 2] - c2[:, 0] ** 2 + c2[:, 0] * c2[:, 1]
+    assert np.abs(r.x[0].cpu().numpy() - want).max() < 1e-10
+    sm = configs.build_mesh(w.source)
+    S = ft.Source(*sm, configs.source_nodal_values(w, sm[0]), bins=w.bins[: w.dim] if any(w.bins) else None)
+    T.transfer_from(S, _cfg(N))
+    rep = T.project(1, rtol=1e-14, max_iter=1000).reports[0]
+    I = S.integral()[0]
+    log(f"  sum b {rep['sum_b']:.15e}, integral {I:.15e}, stderr {rep['sum_b_stderr']:.3e}, iters {rep['iters']}")
+    assert rep["cons_defect"] < 1e-10
+    assert abs(rep["sum_b"] - I) < 6.0 * rep["sum_b_stderr"]
+    T.close()
+    S.close()
