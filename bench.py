@@ -786,6 +786,44 @@ def main():
                 tms.append(e0.elapsed_time(e1))
             variants[name] = {"rel_l2_error": float(torch.linalg.norm(b - exact) / torch.linalg.norm(exact)),
                               "ms_per_step": float(np.median(tms))}
+        if prec in (ft.FT_F64, ft.FT_F32):
+            # variance-driven counts: a pilot of N/4 samples per element (fused
+            # route, its own stream) gives the element variances; the counts
+            # for N per element on average follow them (field 0)
+            n0 = max(2, N // 4)
+            pc = ft.SampleCfg(n0, F, w.alpha, w.philox_seed, 1 << 20, prec)
+            ac = ft.SampleCfg(0, F, w.alpha, w.philox_seed, 0, prec)
+            tp, tal, tms = [], [], []
+            for _ in range(3):
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record()
+                T.transfer_from(S, pc)
+                T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
+                e1.record()
+                offs, al = T.allocate_samples(N * E, n_min=2)
+                e2.record()
+                pa = torch.empty((dim, n + al.total), dtype=dt_, device=dev)
+                va = torch.empty((F, n + al.total), dtype=dt_, device=dev)
+                torch.cuda.synchronize()
+                e2b, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e2b.record()
+                T.sample_points_adaptive(ac, offs, al.total, out=pa)
+                S.eval_query_list(pa, n, out=va)
+                T.consume_adaptive(ac, offs, al.total, va)
+                ra = T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
+                e3.record()
+                torch.cuda.synchronize()
+                tp.append(e0.elapsed_time(e1))
+                tal.append(e1.elapsed_time(e2))
+                tms.append(e2b.elapsed_time(e3))
+                del pa, va
+            variants["neyman_counts"] = {
+                "rel_l2_error": float(torch.linalg.norm(b - exact) / torch.linalg.norm(exact)),
+                "ms_per_step": float(np.median(tms)), "pilot_ms": float(np.median(tp)),
+                "allocate_ms": float(np.median(tal)), "pilot_samples_per_elem": n0,
+                "total_samples": int(al.total), "sum_b_stderr": ra.reports[0]["sum_b_stderr"],
+                "predicted_stderr": al.predicted_stderr,
+                "uniform_sum_b_stderr": reports[0]["sum_b_stderr"]}
         supermesh_route["variance_variants"] = variants
         del b_mc, exact
 

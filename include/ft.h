@@ -272,6 +272,85 @@ ft_status ft_consume_queries(ft_target* t, const ft_sample_cfg* cfg, const void*
  */
 ft_status ft_consume_queries_noalloc(ft_target* t, const ft_sample_cfg* cfg, const void* values, hipStream_t stream);
 
+/* Result of ft_allocate_samples (host). */
+typedef struct {
+    int64_t total;              /* sum of the counts: samples of the new query list     */
+    double  weight_sum;         /* W = sum_t a_t, a_t = |Omega_t| sigma_t as the pilot  */
+                                /* estimated it                                          */
+    double  predicted_stderr;   /* sqrt(sum_t a_t^2 / N_t): the standard error of sum b  */
+                                /* the allocation should reach ((W^2 / total)^(1/2) when */
+                                /* no count is clamped or rounded)                       */
+} ft_allocation;
+
+/*
+ * ft_allocate_samples - samples per element from the element variances (sec. 7:
+ * better sampling; App. B, Eq. cv_global_integral_estimator: with N_t
+ * independent samples in element t, Var(sum b) = sum_t |Omega_t|^2 sigma_t^2 / N_t,
+ * smallest for a total B when N_t is proportional to a_t = |Omega_t| sigma_t,
+ * the Neyman allocation, where it equals W^2 / B).  The last transfer of the
+ * target is the pilot: a fixed N0 >= 2 samples per element on a route that
+ * estimates the element variances (ft_consume_queries in FT_F64 or FT_F32,
+ * ft_transfer_p1, plans, ft_batch_consume_run); its variance terms
+ * v_t = |Omega_t|^2 s_t^2 / N0 of field `field` give a_t = sqrt(N0 v_t)
+ * (non-finite terms count as 0), and
+ *   N_t = min(max(floor(budget a_t / W + 1/2), n_min), n_max)
+ * (n_min everywhere when W = 0), W = sum_t a_t summed in a fixed order, so
+ * the counts are the same on every run.
+ *   budget        total samples wanted, in [1, 2^40] (ft_budget_for_tolerance
+ *                 gives one for an error target); clamping makes the total differ
+ *   n_min, n_max  1 <= n_min <= n_max <= 2^20 (n_min >= 2 keeps the standard
+ *                 error of the next transfer estimable)
+ *   offsets       device, int64 [n_elems + 1], written: exclusive prefix sums of
+ *                 the counts, offsets[n_elems] = total (the input of
+ *                 ft_sample_points_adaptive and ft_consume_queries_adaptive)
+ *   out           host: total, W and the predicted standard error
+ * Errors: FT_E_ARG, FT_E_ORDER (no such pilot), FT_E_OOM (scratch of about
+ * n_elems / 64 doubles, kept by the target).  Synchronizes `stream`.
+ */
+ft_status ft_allocate_samples(ft_target* t, int32_t field, int64_t budget, int32_t n_min, int32_t n_max,
+                              int64_t* offsets, ft_allocation* out, hipStream_t stream);
+
+/* The total samples for which the Neyman prediction W / sqrt(B) reaches
+ * rel_tol |sum_b|: ceil((weight_sum / (rel_tol |sum_b|))^2), at least 1, at
+ * most 2^40 (1 when weight_sum or sum_b is 0; -1 on invalid arguments).
+ * Host-only, touches no device memory. */
+int64_t ft_budget_for_tolerance(double weight_sum, double sum_b, double rel_tol);
+
+/*
+ * ft_sample_points_adaptive - ft_sample_points with N_t = offsets[t+1] -
+ * offsets[t] samples in element t: entries [0, n_nodes) are the nodes, entry
+ * n_nodes + offsets[t] + j (j < N_t) is sample j of element t, the same
+ * Philox counter (j, t, stream_id, blk) and map as ft_sample_points (so
+ * N_t = N everywhere reproduces its samples).  cfg->samples_per_elem must be
+ * 0; plain sampling; FT_F64 or FT_F32 points.
+ *   offsets  device, int64 [n_elems + 1] (ft_allocate_samples, or the
+ *            caller's: non-decreasing, 1 <= N_t <= 2^20, offsets[0] = 0,
+ *            offsets[n_elems] = total); an element whose range is not valid
+ *            gets no samples written, and ft_consume_queries_adaptive counts it
+ *   total    host, the total number of samples, in [n_elems, 2^40]
+ *   points   device, [dim][n_nodes + total] in cfg->precision
+ * The caller keeps offsets unchanged until the matching consumption.
+ * Errors: FT_E_ARG, FT_E_UNSUPPORTED.  Asynchronous on `stream`.
+ */
+ft_status ft_sample_points_adaptive(ft_target* t, const ft_sample_cfg* cfg, const int64_t* offsets, int64_t total,
+                                    void* points, hipStream_t stream);
+
+/*
+ * ft_consume_queries_adaptive - ft_consume_queries for the list of
+ * ft_sample_points_adaptive (the same cfg, offsets pointer and total):
+ *   beta_tk = |Omega_t| / N_t * sum_{j < N_t} (y_tj - alpha g(X_tj)) psi_k(X_tj),
+ * unbiased for every N_t >= 1, with fixed alpha or each element's own
+ * (FT_ALPHA_ELEMENT, P1 targets), on P1 and P2 targets; values field-major
+ * [F][n_nodes + total].  The element variances are |Omega_t|^2 s_t^2 / N_t,
+ * so ft_project reports the standard error of sum b (-1 when an element has a
+ * single sample).  An element with an invalid range contributes 0 and counts
+ * as one non-finite value (ft_project then returns FT_E_NONFINITE).
+ * Errors: FT_E_ARG, FT_E_ORDER, FT_E_UNSUPPORTED, FT_E_OOM.  Asynchronous on
+ * `stream`.
+ */
+ft_status ft_consume_queries_adaptive(ft_target* t, const ft_sample_cfg* cfg, const int64_t* offsets, int64_t total,
+                                      const void* values, hipStream_t stream);
+
 /*
  * ft_project - step 2 and step 7 of sec. 4.1 and the conservation report.
  * Several fields (F > 1, at most 64) are solved together by a batched PCG that

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libft.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["runtime.hip", "setup.hip", "mc.hip", "mc_mfma.hip", "source.hip", "fused.hip", "solve.hip", "solve_multi.hip", "batch.hip", "plan.hip", "supermesh.hip", "noalloc.hip", "abi.hip"]
+SOURCES = ["runtime.hip", "setup.hip", "mc.hip", "mc_mfma.hip", "source.hip", "fused.hip", "solve.hip", "solve_multi.hip", "batch.hip", "plan.hip", "supermesh.hip", "adaptive.hip", "noalloc.hip", "abi.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

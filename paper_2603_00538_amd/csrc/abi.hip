@@ -3,6 +3,7 @@
 #include <cmath>
 #include <new>
 
+#include "adaptive.h"
 #include "common.h"
 
 namespace ft {
@@ -11,6 +12,14 @@ ft_status target_setup(ft_target* T, const double* coords, const int32_t* conn, 
 ft_status solver_alloc(ft_target* T, hipStream_t s);
 ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipStream_t s);
 ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s);
+ft_status emit_points_varn(ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total, void* points,
+                           hipStream_t s);
+ft_status consume_values_varn(ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total,
+                              const void* values, hipStream_t s);
+size_t alloc_scratch_bytes(int64_t E);
+ft_status allocate_samples(const double* var, int64_t E, int n0, int64_t budget, int n_min, int n_max,
+                           int64_t* offs, void* scratch, int64_t* total, double* W, double* pred_var,
+                           hipStream_t s);
 ft_status project(ft_target* T, const ft_solve_cfg* cfg, double* x, double* b_out, ft_report* rep, hipStream_t s);
 ft_status source_setup(ft_source* S, const double* coords, const int32_t* conn, const double* values,
                        const int32_t* bins, hipStream_t s);
@@ -158,6 +167,12 @@ using namespace ft;
 struct ft_target_ext : ft_target {
     bool sampled = false;
     ft_sample_cfg sampled_cfg{};
+    // the last sampling's per-element counts (null: samples_per_elem each)
+    const int64_t* sampled_offs = nullptr;
+    int64_t sampled_total = 0;
+    // device scratch of ft_allocate_samples
+    void* alloc_tmp = nullptr;
+    size_t alloc_tmp_bytes = 0;
 };
 
 extern "C" {
@@ -213,6 +228,7 @@ ft_status ft_target_create_p2(int32_t dim, int64_t n_nodes, const double* coords
 
 ft_status ft_target_destroy(ft_target* t) {
     if (!t) return FT_OK;
+    dev_free(static_cast<ft_target_ext*>(t)->alloc_tmp);
     target_release(t);
     delete static_cast<ft_target_ext*>(t);
     return FT_OK;
@@ -245,6 +261,108 @@ ft_status ft_sample_points(ft_target* t, const ft_sample_cfg* cfg, void* points,
     auto* T = static_cast<ft_target_ext*>(t);
     T->sampled = true;
     T->sampled_cfg = *cfg;
+    T->sampled_offs = nullptr;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+// Per-element counts: plain samples, field-major values, FT_F64 or FT_F32.
+static ft_status check_varn_cfg(const ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total) {
+    FT_ARG_CHECK(cfg, "cfg is null");
+    FT_ARG_CHECK(cfg->samples_per_elem == 0,
+                 "samples_per_elem must be 0 when the counts come from offsets (got %d)", cfg->samples_per_elem);
+    ft_sample_cfg c = *cfg;
+    c.samples_per_elem = 1;
+    FT_TRY(check_sample_cfg(T, &c));
+    FT_ARG_CHECK(offs, "offsets is null");
+    FT_ARG_CHECK(total >= T->E && total <= kMaxAllocTotal,
+                 "total (%lld) must lie in [n_elems, 2^40]: every element takes at least one sample",
+                 (long long)total);
+    if (cfg->sampling != FT_SAMPLING_PLAIN || cfg->values_layout != FT_VALUES_FIELD_MAJOR ||
+        (cfg->precision != FT_F64 && cfg->precision != FT_F32)) {
+        set_error("per-element sample counts take plain samples, field-major values and the FT_F64 or FT_F32 form");
+        return FT_E_UNSUPPORTED;
+    }
+    return FT_OK;
+}
+
+ft_status ft_allocate_samples(ft_target* t, int32_t field, int64_t budget, int32_t n_min, int32_t n_max,
+                              int64_t* offsets, ft_allocation* out, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t && offsets && out, "null argument");
+    auto* T = static_cast<ft_target_ext*>(t);
+    const int n0 = T->consumed_cfg.samples_per_elem;
+    if (!T->consumed || T->var_mode != VAR_ESTIMATED || n0 < 2) {
+        set_error("ft_allocate_samples needs a prior transfer with a fixed N >= 2 samples per element on a route "
+                  "that estimates the element variances");
+        return FT_E_ORDER;
+    }
+    FT_ARG_CHECK(field >= 0 && field < T->consumed_cfg.n_fields, "field %d out of range [0, %d)", field,
+                 T->consumed_cfg.n_fields);
+    FT_ARG_CHECK(n_min >= 1 && n_min <= n_max && n_max <= kMaxElemSamples,
+                 "need 1 <= n_min <= n_max <= 2^20 (got %d, %d)", n_min, n_max);
+    FT_ARG_CHECK(budget >= 1 && budget <= kMaxAllocTotal, "budget must lie in [1, 2^40] (got %lld)",
+                 (long long)budget);
+    // the counts add up to at most budget + n_elems / 2 before the clamps, which add at most n_elems * n_min
+    FT_ARG_CHECK(double(budget) + double(T->E) * (double(n_min) + 1.0) <= double(kMaxAllocTotal),
+                 "budget + n_elems * (n_min + 1) must stay within 2^40 samples");
+    const size_t need = alloc_scratch_bytes(T->E);
+    if (need > T->alloc_tmp_bytes) {
+        FT_TRY_HIP(hipStreamSynchronize(stream));
+        dev_free(T->alloc_tmp);
+        T->alloc_tmp = nullptr;
+        T->alloc_tmp_bytes = 0;
+        FT_TRY(dev_alloc_n(reinterpret_cast<double**>(&T->alloc_tmp), need / sizeof(double)));
+        T->alloc_tmp_bytes = need;
+    }
+    double W = 0.0, pv = 0.0;
+    int64_t total = 0;
+    FT_TRY(allocate_samples(T->var_el + int64_t(field) * T->E, T->E, n0, budget, n_min, n_max, offsets, T->alloc_tmp,
+                            &total, &W, &pv, stream));
+    out->total = total;
+    out->weight_sum = W;
+    out->predicted_stderr = std::sqrt(pv);
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_sample_points_adaptive(ft_target* t, const ft_sample_cfg* cfg, const int64_t* offsets, int64_t total,
+                                    void* points, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t, "target is null");
+    FT_TRY(check_varn_cfg(t, cfg, offsets, total));
+    FT_ARG_CHECK(points, "points is null");
+    FT_TRY(emit_points_varn(t, cfg, offsets, total, points, stream));
+    auto* T = static_cast<ft_target_ext*>(t);
+    T->sampled = true;
+    T->sampled_cfg = *cfg;
+    T->sampled_offs = offsets;
+    T->sampled_total = total;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_consume_queries_adaptive(ft_target* t, const ft_sample_cfg* cfg, const int64_t* offsets, int64_t total,
+                                      const void* values, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t, "target is null");
+    FT_TRY(check_varn_cfg(t, cfg, offsets, total));
+    FT_ARG_CHECK(values, "values is null");
+    auto* T = static_cast<ft_target_ext*>(t);
+    if (!T->sampled || T->sampled_offs != offsets || T->sampled_total != total || !same_samples(T->sampled_cfg, *cfg)) {
+        set_error("consume needs a prior ft_sample_points_adaptive with the same offsets, total, seed, stream_id "
+                  "and point precision");
+        return FT_E_ORDER;
+    }
+    FT_TRY(check_alpha_mode(T, cfg, true));
+    FT_TRY(ensure_field_buffers(T, cfg->n_fields, stream));
+    T->consumed = false;
+    FT_TRY(consume_values_varn(T, cfg, offsets, total, values, stream));
+    T->consumed = true;
+    T->consumed_cfg = consumed_view(*cfg);
     return FT_OK;
     FT_GUARD_END
 }
@@ -684,6 +802,16 @@ int32_t ft_samples_for_tolerance(const ft_report* rep, int32_t samples_per_elem,
     const double n = std::ceil(double(samples_per_elem) * r * r);
     if (!(n < double(1 << 20))) return 1 << 20;
     return n < 1.0 ? 1 : int32_t(n);
+}
+
+int64_t ft_budget_for_tolerance(double weight_sum, double sum_b, double rel_tol) {
+    if (!(rel_tol > 0.0) || !(weight_sum >= 0.0) || !std::isfinite(weight_sum) || !std::isfinite(sum_b)) return -1;
+    const double target = rel_tol * std::fabs(sum_b);
+    if (weight_sum == 0.0 || !(target > 0.0)) return 1;
+    const double r = weight_sum / target;
+    const double b = std::ceil(r * r);
+    if (!(b < double(kMaxAllocTotal))) return kMaxAllocTotal;
+    return b < 1.0 ? 1 : int64_t(b);
 }
 
 const char* ft_last_error(void) { return ft::last_error(); }

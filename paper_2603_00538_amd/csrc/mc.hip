@@ -17,6 +17,7 @@
 // (coalesced reads of y), keep per-lane partial sums, and the group reduces
 // them with a fixed butterfly.  No floating-point atomics anywhere, so results
 // are bitwise reproducible run to run.
+#include "adaptive.h"
 #include "sampling.h"
 
 namespace ft {
@@ -87,6 +88,43 @@ __global__ __launch_bounds__(256) void k_emit(const double* __restrict__ X, int6
 template <int D>
 constexpr int kEmitRuns = D == 2 ? 8 : 4;
 
+// Samples per element from allocation offsets: element t's samples go to
+// queries n + offs[t] + j, j < offs[t+1] - offs[t]; a wave takes kVarRuns
+// consecutive elements, its lanes striding over each one's samples.  An
+// element whose range is invalid (see element_range) writes nothing.
+constexpr int kVarRuns = 4;
+
+// Element t's samples from the allocation offsets: [o0, o1) of the sample block,
+// valid when 1 <= o1 - o0 <= kMaxElemSamples and both lie in [0, total].
+__device__ __forceinline__ bool element_range(const int64_t* __restrict__ offs, uint32_t t, int64_t total,
+                                              int64_t& o0, uint32_t& N) {
+    o0 = offs[t];
+    const int64_t o1 = offs[t + 1];
+    const bool ok = o0 >= 0 && o1 > o0 && o1 <= total && o1 - o0 <= kMaxElemSamples;
+    N = ok ? uint32_t(o1 - o0) : 0u;
+    return ok;
+}
+
+template <int D, bool F32>
+__global__ __launch_bounds__(256) void k_emit_varn(const double* __restrict__ X, int64_t n,
+                                                   const int32_t* __restrict__ conn, uint32_t E,
+                                                   const int64_t* __restrict__ offs, int64_t total, SampleKey key,
+                                                   void* __restrict__ out_, int64_t ld) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int r = 0; r < kVarRuns; ++r) {
+        const uint32_t t = wave * uint32_t(kVarRuns) + uint32_t(r);
+        if (t >= E) break;
+        int64_t o0;
+        uint32_t N;
+        if (!element_range(offs, t, total, o0, N)) continue;
+        int v[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) v[k] = conn[int64_t(t) * (D + 1) + k];
+        for (uint32_t j = lane; j < N; j += 64u) emit_sample<D, F32>(X, n, v, t, j, key, out_, ld, n + o0 + j);
+    }
+}
+
 template <bool F32>
 __global__ void k_emit_nodes(const double* __restrict__ X, int64_t n, int dim, void* __restrict__ out_, int64_t ld) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -121,23 +159,28 @@ constexpr double kOwnAlphaLo = 0.0, kOwnAlphaHi = 2.0;
 
 
 // P: degree of the target elements; dofs: the element's nodes, [E][nb].
-template <int D, int P, int G, int FC, bool F32, bool OWN>
+// N: the element's samples, at queries qbase .. qbase + N - 1 of field 0.
+// VN (samples per element from an allocation): the element variance of an
+// element with one sample is undefined (NaN) rather than 0, so that a sum
+// over elements says it cannot be estimated.
+template <int D, int P, int G, int FC, bool F32, bool OWN, bool VN>
 __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, const void* __restrict__ values_,
                                                         const ValueLayout& L, int F, const int32_t* __restrict__ dofs,
                                                         const double* __restrict__ vol, int64_t n, uint32_t E,
-                                                        uint32_t N, double alpha, const SampleKey& key,
-                                                        double* __restrict__ beta, double* __restrict__ var_el) {
+                                                        uint32_t N, int64_t qbase, double alpha,
+                                                        const SampleKey& key, double* __restrict__ beta,
+                                                        double* __restrict__ var_el) {
     static_assert(P == 1 || !OWN, "each element's own coefficient: P1 targets");
     constexpr int NB = Basis<D, P>::n;
     int v[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) v[k] = dofs[int64_t(t) * NB + k];
     const double scale = vol[t] / double(N);
-    const int64_t qbase = L.samp0 + int64_t(t) * L.samp_elem;
     unsigned int nf = 0;
     constexpr int FO = OWN ? FC : 1;
     const double Nd = double(N);
-    const double inv_n = 1.0 / Nd, inv_var = N > 1 ? inv_n / (Nd - 1.0) : 0.0;
+    const double inv_n = 1.0 / Nd;
+    const double inv_var = N > 1 ? inv_n / (Nd - 1.0) : (VN ? __builtin_nan("") : 0.0);
     for (int f0 = 0; f0 < F; f0 += FC) {
         double gk[FC][NB];
         double acc[FC][NB];       // sum r psi_k (fixed alpha) or sum y l_k (OWN)
@@ -309,14 +352,34 @@ __device__ __forceinline__ unsigned int consume_element(uint32_t t, int lane, co
     return nf;
 }
 
+// An element whose samples per element (VN) are out of range or whose queries
+// leave [0, total): no loads are taken, its element loads are 0, its variance
+// undefined, and it counts as one non-finite value.
+template <int NB>
+__device__ __forceinline__ unsigned int reject_element(uint32_t t, int lane, int F, uint32_t E,
+                                                       double* __restrict__ beta, double* __restrict__ var_el) {
+    if (lane != 0) return 0;
+    for (int f = 0; f < F; ++f) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) beta[(int64_t(f) * E + t) * NB + k] = 0.0;
+        if (var_el) var_el[int64_t(f) * E + t] = __builtin_nan("");
+    }
+    return 1;
+}
+
 // G lanes per element.  R > 1 (G == 64 only): each wave sums R consecutive
-// elements in turn, with their element data in scalar registers.
-template <int D, int P, int G, int FC, bool F32, int R, bool OWN>
+// elements in turn, with their element data in scalar registers.  VN (G == 64):
+// element t has the samples offs[t] .. offs[t+1] - 1 of the list's sample block
+// (total samples in all), N is not read.
+template <int D, int P, int G, int FC, bool F32, int R, bool OWN, bool VN>
 __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values_, ValueLayout L, int F,
                                                  const int32_t* __restrict__ dofs, const double* __restrict__ vol,
-                                                 int64_t n, uint32_t E, uint32_t N, double alpha, SampleKey key,
+                                                 int64_t n, uint32_t E, uint32_t N, const int64_t* __restrict__ offs,
+                                                 int64_t total, double alpha, SampleKey key,
                                                  double* __restrict__ beta, double* __restrict__ var_el,
                                                  unsigned long long* __restrict__ nonfinite) {
+    static_assert(!VN || G == 64, "samples per element from offsets: one element per wave");
+    constexpr int NB = Basis<D, P>::n;
     unsigned int nf = 0;
     if constexpr (R > 1) {
         static_assert(G == 64, "one element per wave");
@@ -325,8 +388,18 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         for (int e = 0; e < R; ++e) {
             const uint32_t t = wave * uint32_t(R) + uint32_t(e);
             if (t >= E) break;
-            nf += consume_element<D, P, G, FC, F32, OWN>(t, lane, values_, L, F, dofs, vol, n, E, N, alpha, key,
-                                                         beta, var_el);
+            uint32_t Nt = N;
+            int64_t qbase = L.samp0 + int64_t(t) * L.samp_elem;
+            if constexpr (VN) {
+                int64_t o0;
+                if (!element_range(offs, t, total, o0, Nt)) {
+                    nf += reject_element<NB>(t, lane, F, E, beta, var_el);
+                    continue;
+                }
+                qbase = L.samp0 + o0;
+            }
+            nf += consume_element<D, P, G, FC, F32, OWN, VN>(t, lane, values_, L, F, dofs, vol, n, E, Nt, qbase,
+                                                             alpha, key, beta, var_el);
         }
     } else {
         const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
@@ -334,8 +407,17 @@ __global__ __launch_bounds__(256) void k_consume(const void* __restrict__ values
         const int lane = int(gid & (G - 1));
         if (t >= E) return;   // the whole group leaves together
         if (G == 64) t = __builtin_amdgcn_readfirstlane(t);   // one element per wave: scalar element data
-        nf = consume_element<D, P, G, FC, F32, OWN>(t, lane, values_, L, F, dofs, vol, n, E, N, alpha, key, beta,
-                                                    var_el);
+        uint32_t Nt = N;
+        int64_t qbase = L.samp0 + int64_t(t) * L.samp_elem;
+        bool ok = true;
+        if constexpr (VN) {
+            int64_t o0;
+            ok = element_range(offs, t, total, o0, Nt);
+            qbase = L.samp0 + o0;
+        }
+        nf = ok ? consume_element<D, P, G, FC, F32, OWN, VN>(t, lane, values_, L, F, dofs, vol, n, E, Nt, qbase,
+                                                             alpha, key, beta, var_el)
+                : reject_element<NB>(t, lane, F, E, beta, var_el);
     }
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
@@ -434,28 +516,61 @@ ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipS
     return T->dim == 2 ? emit_impl<2>(T, cfg, points, s) : emit_impl<3>(T, cfg, points, s);
 }
 
+// The query list of per-element counts: the nodes, then element t's samples
+// at n + offs[t] + j (leading dimension n + total).
+template <int D>
+static ft_status emit_varn_impl(ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total,
+                                void* points, hipStream_t s) {
+    const int64_t ld = T->n + total;
+    const SampleKey key = make_key(T, cfg);   // plain samples
+    if (cfg->precision != FT_F64) {
+        k_emit_nodes<true><<<grid_for(T->n, 256), 256, 0, s>>>(T->coords, T->n, D, points, ld);
+        k_emit_varn<D, true><<<grid_for(T->E, 4 * kVarRuns), 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(T->E),
+                                                                          offs, total, key, points, ld);
+    } else {
+        k_emit_nodes<false><<<grid_for(T->n, 256), 256, 0, s>>>(T->coords, T->n, D, points, ld);
+        k_emit_varn<D, false><<<grid_for(T->E, 4 * kVarRuns), 256, 0, s>>>(T->coords, T->n, T->conn, uint32_t(T->E),
+                                                                           offs, total, key, points, ld);
+    }
+    FT_TRY_HIP(hipGetLastError());
+    return FT_OK;
+}
+
+ft_status emit_points_varn(ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total, void* points,
+                           hipStream_t s) {
+    return T->dim == 2 ? emit_varn_impl<2>(T, cfg, offs, total, points, s)
+                       : emit_varn_impl<3>(T, cfg, offs, total, points, s);
+}
+
 constexpr int kConsumeRuns = 4;   // elements per wave when G == 64
 
-template <int D, int P, int G, int FC, bool F32>
+// Per-element counts (offs non-null): ranges offs[t] .. offs[t+1] of total samples.
+struct VarCounts {
+    const int64_t* offs = nullptr;
+    int64_t total = 0;
+};
+
+template <int D, int P, int G, int FC, bool F32, bool VN = false>
 static void launch_consume(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
-                           double* beta, hipStream_t s) {
+                           double* beta, hipStream_t s, const VarCounts& vc = VarCounts{}) {
     const SampleKey key = make_key(T, cfg);
     constexpr int R = G == 64 ? kConsumeRuns : 1;
     const unsigned grid = grid_for(T->E * G, 256 * R);
-    auto kern = k_consume<D, P, G, FC, F32, R, false>;
+    auto kern = k_consume<D, P, G, FC, F32, R, false, VN>;
     if constexpr (P == 1)
-        if (cfg->alpha_mode == FT_ALPHA_ELEMENT) kern = k_consume<D, P, G, FC, F32, R, true>;
+        if (cfg->alpha_mode == FT_ALPHA_ELEMENT) kern = k_consume<D, P, G, FC, F32, R, true, VN>;
     kern<<<grid, 256, 0, s>>>(values, L, cfg->n_fields, T->dofs, T->vol, T->n, uint32_t(T->E),
-                              uint32_t(cfg->samples_per_elem), cfg->alpha, key, beta, T->var_el, T->counters);
+                              uint32_t(cfg->samples_per_elem), vc.offs, vc.total, cfg->alpha, key, beta, T->var_el,
+                              T->counters);
 }
 
-template <int D, int P, int G, bool F32>
+template <int D, int P, int G, bool F32, bool VN = false>
 static void consume_fc(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
-                       double* beta, hipStream_t s) {
+                       double* beta, hipStream_t s, const VarCounts& vc = VarCounts{}) {
     if (cfg->n_fields == 1)
-        launch_consume<D, P, G, 1, F32>(T, cfg, values, L, beta, s);
+        launch_consume<D, P, G, 1, F32, VN>(T, cfg, values, L, beta, s, vc);
     else
-        launch_consume<D, P, G, 4, F32>(T, cfg, values, L, beta, s);
+        launch_consume<D, P, G, 4, F32, VN>(T, cfg, values, L, beta, s, vc);
 }
 
 // Lanes per element G from N (P2 targets: one element per wave for N >= 64,
@@ -559,6 +674,37 @@ static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void
 // node assembly that follows it touch them.
 ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s) {
     return T->dim == 2 ? consume_impl<2>(T, cfg, values, beta, s) : consume_impl<3>(T, cfg, values, beta, s);
+}
+
+// Consumption of a list with per-element counts (field-major values, one
+// element per wave): the element variances are estimated (an element with a
+// single sample makes their sum undefined).
+template <int D>
+static ft_status consume_varn_impl(ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total,
+                                   const void* values, hipStream_t s) {
+    const int64_t Q = T->n + total;
+    const ValueLayout L{Q, T->n, Q, 0, make_fastdiv(1)};
+    const bool f32 = cfg->precision != FT_F64;
+    const VarCounts vc{offs, total};
+    zero_counter(T->counters, s);
+    T->ood_mode = 0;
+    T->var_mode = VAR_NONE;
+    if (T->order == 2) {
+        if (f32) consume_fc<D, 2, 64, true, true>(T, cfg, values, L, T->beta, s, vc);
+        else consume_fc<D, 2, 64, false, true>(T, cfg, values, L, T->beta, s, vc);
+    } else {
+        if (f32) consume_fc<D, 1, 64, true, true>(T, cfg, values, L, T->beta, s, vc);
+        else consume_fc<D, 1, 64, false, true>(T, cfg, values, L, T->beta, s, vc);
+    }
+    FT_TRY_HIP(hipGetLastError());
+    T->var_mode = VAR_ESTIMATED;
+    return assemble_from(T, T->beta, cfg->n_fields, values, L.node_ld, f32, s);
+}
+
+ft_status consume_values_varn(ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total,
+                              const void* values, hipStream_t s) {
+    return T->dim == 2 ? consume_varn_impl<2>(T, cfg, offs, total, values, s)
+                       : consume_varn_impl<3>(T, cfg, offs, total, values, s);
 }
 
 }  // namespace ft

@@ -258,7 +258,8 @@ ft_status stderr_launch(ft_target* T, int F, hipStream_t s) {
 // after the stream has been synchronized
 void stderr_fill(const ft_target* T, int F, ft_report* rep) {
     for (int f = 0; f < F; ++f)
-        rep[f].sum_b_stderr = T->var_mode == VAR_ESTIMATED ? std::sqrt(T->h_var[f])
+        // (a sum that is not finite: some element had a single sample, or a value was not finite)
+        rep[f].sum_b_stderr = T->var_mode == VAR_ESTIMATED ? (std::isfinite(T->h_var[f]) ? std::sqrt(T->h_var[f]) : -1.0)
                               : T->var_mode == VAR_EXACT   ? 0.0
                                                            : -1.0;
 }

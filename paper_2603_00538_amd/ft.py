@@ -35,7 +35,8 @@ EXPORTED = ["ft_target_create", "ft_target_create_p2", "ft_target_destroy", "ft_
             "ft_batch_destroy", "ft_batch_consume_run",
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_samples_for_tolerance",
-            "ft_last_error"]
+            "ft_allocate_samples", "ft_budget_for_tolerance", "ft_sample_points_adaptive",
+            "ft_consume_queries_adaptive", "ft_last_error"]
 
 
 class SampleCfg(ctypes.Structure):
@@ -62,6 +63,10 @@ class Report(ctypes.Structure):
 class TargetInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int64),
                 ("nnz", ctypes.c_int64), ("n_inverted", ctypes.c_int64), ("order", ctypes.c_int32)]
+
+
+class Allocation(ctypes.Structure):
+    _fields_ = [("total", ctypes.c_int64), ("weight_sum", ctypes.c_double), ("predicted_stderr", ctypes.c_double)]
 
 
 class SourceInfo(ctypes.Structure):
@@ -118,6 +123,10 @@ def load(path: str = LIB_PATH):
         "ft_plan_transfer": (I32, [P, P, P]),
         "ft_plan_destroy": (I32, [P]),
         "ft_samples_for_tolerance": (I32, [ctypes.POINTER(Report), I32, D]),
+        "ft_allocate_samples": (I32, [P, I32, I64, I32, I32, P, ctypes.POINTER(Allocation), P]),
+        "ft_budget_for_tolerance": (I64, [D, D, D]),
+        "ft_sample_points_adaptive": (I32, [P, ctypes.POINTER(SampleCfg), P, I64, P, P]),
+        "ft_consume_queries_adaptive": (I32, [P, ctypes.POINTER(SampleCfg), P, I64, P, P]),
         "ft_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -322,6 +331,28 @@ def ft_source_get_info(h) -> SourceInfo:
 
 
 # ------------------------------------------------------------------ torch conveniences
+def ft_allocate_samples(h, field, budget, n_min, n_max, offsets_ptr, stream) -> Allocation:
+    a = Allocation()
+    _check(load().ft_allocate_samples(h, field, budget, n_min, n_max, offsets_ptr, ctypes.byref(a), stream),
+           "ft_allocate_samples")
+    return a
+
+
+def ft_budget_for_tolerance(weight_sum, sum_b, rel_tol):
+    """Total samples for which the Neyman prediction reaches rel_tol |sum_b| (-1: invalid arguments)."""
+    return int(load().ft_budget_for_tolerance(weight_sum, sum_b, rel_tol))
+
+
+def ft_sample_points_adaptive(h, cfg: SampleCfg, offsets_ptr, total, points_ptr, stream):
+    return _check(load().ft_sample_points_adaptive(h, ctypes.byref(cfg), offsets_ptr, total, points_ptr, stream),
+                  "ft_sample_points_adaptive")
+
+
+def ft_consume_queries_adaptive(h, cfg: SampleCfg, offsets_ptr, total, values_ptr, stream):
+    return _check(load().ft_consume_queries_adaptive(h, ctypes.byref(cfg), offsets_ptr, total, values_ptr, stream),
+                  "ft_consume_queries_adaptive")
+
+
 def _torch():
     import torch
     return torch
@@ -416,6 +447,41 @@ class Target:
             raise ValueError(f"values hold {values.numel()} entries, need {cfg.n_fields * Q}")
         fn = ft_consume_queries_noalloc if noalloc else ft_consume_queries
         fn(self.handle, cfg, _device_ptr(values, "values", (dt,)), current_stream())
+
+    def allocate_samples(self, budget, field=0, n_min=2, n_max=1 << 20, offsets=None):
+        """ft_allocate_samples after a pilot transfer: (offsets int64 (E+1,) device
+        tensor, Allocation) for `budget` samples in all."""
+        torch = _torch()
+        if offsets is None:
+            offsets = torch.empty(self.n_elems + 1, dtype=torch.int64, device=self.coords.device)
+        if offsets.numel() < self.n_elems + 1:
+            raise ValueError(f"offsets hold {offsets.numel()} entries, need {self.n_elems + 1}")
+        a = ft_allocate_samples(self.handle, field, int(budget), n_min, n_max,
+                                _device_ptr(offsets, "offsets", (torch.int64,)), current_stream())
+        return offsets, a
+
+    def sample_points_adaptive(self, cfg: SampleCfg, offsets, total, out=None):
+        """ft_sample_points_adaptive: the list of per-element counts, (dim, n_nodes + total)."""
+        torch = _torch()
+        Q = self.n_nodes + int(total)
+        dt = torch.float64 if cfg.precision == FT_F64 else torch.float32
+        if out is None:
+            out = torch.empty((self.dim, Q), dtype=dt, device=self.coords.device)
+        if out.numel() < self.dim * Q:
+            raise ValueError(f"points buffer holds {out.numel()} values, needs {self.dim * Q}")
+        ft_sample_points_adaptive(self.handle, cfg, _device_ptr(offsets, "offsets", (torch.int64,)), int(total),
+                                  _device_ptr(out, "points", (dt,)), current_stream())
+        return out
+
+    def consume_adaptive(self, cfg: SampleCfg, offsets, total, values):
+        """ft_consume_queries_adaptive for values [F][n_nodes + total]."""
+        torch = _torch()
+        dt = torch.float64 if cfg.precision == FT_F64 else torch.float32
+        Q = self.n_nodes + int(total)
+        if values.numel() < cfg.n_fields * Q:
+            raise ValueError(f"values hold {values.numel()} entries, need {cfg.n_fields * Q}")
+        ft_consume_queries_adaptive(self.handle, cfg, _device_ptr(offsets, "offsets", (torch.int64,)), int(total),
+                                    _device_ptr(values, "values", (dt,)), current_stream())
 
     def transfer_from(self, source, cfg: SampleCfg):
         """Fused steps 1 and 3-6 from a built-in Source (no query list in memory)."""

@@ -55,6 +55,8 @@ def test_struct_layouts_match_header(tmp_path):
                    'printf("ft_solve_cfg %zu\\n", sizeof(ft_solve_cfg));\n'
                    'printf("ft_report %zu\\n", sizeof(ft_report));\n'
                    'printf("ft_target_info %zu\\n", sizeof(ft_target_info));\n'
+                   'printf("ft_allocation %zu\\n", sizeof(ft_allocation));\n'
+                   "P(ft_allocation, weight_sum); P(ft_allocation, predicted_stderr);\n"
                    "P(ft_sample_cfg, alpha); P(ft_sample_cfg, seed); P(ft_sample_cfg, stream_id); "
                    "P(ft_sample_cfg, precision);\n"
                    "P(ft_report, iters); P(ft_report, status); P(ft_report, n_nonfinite); "
@@ -70,7 +72,9 @@ def test_struct_layouts_match_header(tmp_path):
     assert int(got["ft_solve_cfg"]) == ctypes.sizeof(ft.SolveCfg)
     assert int(got["ft_report"]) == ctypes.sizeof(ft.Report)
     assert int(got["ft_target_info"]) == ctypes.sizeof(ft.TargetInfo)
-    for cls, cname in [(ft.SampleCfg, "ft_sample_cfg"), (ft.Report, "ft_report"), (ft.TargetInfo, "ft_target_info")]:
+    assert int(got["ft_allocation"]) == ctypes.sizeof(ft.Allocation)
+    for cls, cname in [(ft.SampleCfg, "ft_sample_cfg"), (ft.Report, "ft_report"), (ft.TargetInfo, "ft_target_info"),
+                       (ft.Allocation, "ft_allocation")]:
         for fname, _ in cls._fields_:
             key = f"{cname}.{fname}"
             if key in got:
@@ -107,6 +111,10 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.ft_source_get_info(None, None) == ft.FT_E_ARG
     assert lib.ft_target_destroy(None) == ft.FT_OK
     assert lib.ft_source_destroy(None) == ft.FT_OK
+    al = ft.Allocation()
+    assert lib.ft_allocate_samples(None, 0, 100, 2, 64, fake, ctypes.byref(al), None) == ft.FT_E_ARG
+    assert lib.ft_sample_points_adaptive(None, ctypes.byref(cfg), fake, 100, fake, None) == ft.FT_E_ARG
+    assert lib.ft_consume_queries_adaptive(None, ctypes.byref(cfg), fake, 100, fake, None) == ft.FT_E_ARG
 
 
 def test_samples_for_tolerance_matches_oracle(lib):
@@ -139,3 +147,25 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(ft, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         ft.load(str(tmp_path / "nope.so"))
+
+
+def test_budget_for_tolerance_matches_oracle(lib):
+    """Host-only: the total samples whose Neyman prediction W / sqrt(B) reaches
+    rel_tol |sum b|, as the oracle computes it, and the stated edge cases."""
+    from oracle import adaptive
+
+    rng = np.random.default_rng(12)
+    for _ in range(200):
+        sb = float(rng.choice([-1.0, 1.0]) * 10 ** rng.uniform(-3, 3))
+        W = abs(sb) * 10 ** rng.uniform(-5, 1)
+        tol = 10 ** rng.uniform(-6, -1)
+        B = ft.ft_budget_for_tolerance(W, sb, tol)
+        assert B == adaptive.budget_for_tolerance(W, sb, tol)
+        if 1 < B < 2 ** 40:
+            assert W / np.sqrt(B) <= tol * abs(sb) * (1 + 1e-12) and W / np.sqrt(B - 1) > tol * abs(sb) * (1 - 1e-12)
+    assert ft.ft_budget_for_tolerance(0.0, 1.0, 1e-3) == 1
+    assert ft.ft_budget_for_tolerance(1.0, 0.0, 1e-3) == 1
+    assert ft.ft_budget_for_tolerance(1.0, 1.0, 0.0) == -1
+    assert ft.ft_budget_for_tolerance(-1.0, 1.0, 1e-3) == -1
+    assert ft.ft_budget_for_tolerance(float("nan"), 1.0, 1e-3) == -1
+    assert ft.ft_budget_for_tolerance(1.0, 1.0, 1e-30) == 2 ** 40
