@@ -805,21 +805,28 @@ def main():
                 pa = torch.empty((dim, n + al.total), dtype=dt_, device=dev)
                 va = torch.empty((F, n + al.total), dtype=dt_, device=dev)
                 torch.cuda.synchronize()
-                e2b, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e2b.record()
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+                ev[0].record()
                 T.sample_points_adaptive(ac, offs, al.total, out=pa)
+                ev[1].record()
                 S.eval_query_list(pa, n, out=va)
+                ev[2].record()
                 T.consume_adaptive(ac, offs, al.total, va)
+                ev[3].record()
                 ra = T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
-                e3.record()
+                ev[4].record()
                 torch.cuda.synchronize()
                 tp.append(e0.elapsed_time(e1))
                 tal.append(e1.elapsed_time(e2))
-                tms.append(e2b.elapsed_time(e3))
+                tms.append([ev[k].elapsed_time(ev[k + 1]) for k in range(4)])
                 del pa, va
+            cnt = torch.diff(offs)
+            ph = np.median(np.array(tms), axis=0)
             variants["neyman_counts"] = {
                 "rel_l2_error": float(torch.linalg.norm(b - exact) / torch.linalg.norm(exact)),
-                "ms_per_step": float(np.median(tms)), "pilot_ms": float(np.median(tp)),
+                "ms_per_step": float(ph.sum()), "phases_ms": dict(zip(("emit", "eval", "consume", "project"),
+                                                                      map(float, ph))),
+                "counts_min_max": [int(cnt.min()), int(cnt.max())], "pilot_ms": float(np.median(tp)),
                 "allocate_ms": float(np.median(tal)), "pilot_samples_per_elem": n0,
                 "total_samples": int(al.total), "sum_b_stderr": ra.reports[0]["sum_b_stderr"],
                 "predicted_stderr": al.predicted_stderr,
