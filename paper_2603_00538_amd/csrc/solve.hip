@@ -72,13 +72,14 @@ __global__ __launch_bounds__(RB) void k_cg_init(Mat A, const double* __restrict_
 // p = z + beta p_old (own rows into p_new), q = M p (p formed on the fly at the
 // neighbours), partials of p.q.  A non-finite residual also stops (reported as
 // non-finite by the caller).
-__global__ __launch_bounds__(RB) void k_cg_spmv(Mat A, int k, const double* __restrict__ z,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_cg_spmv(Mat A, int k, const double* __restrict__ z,
                                                 const double* __restrict__ p_old, double* __restrict__ p_new,
                                                 double* __restrict__ q, double* __restrict__ part,
                                                 double* __restrict__ scal) {
     if (scal[S_DONE] != 0.0) return;
-    const double rz = partial_total(part, P_RZ, gridDim.x);
-    const double rr = partial_total(part, P_RR, gridDim.x);
+    const double rz = partial_total<NT>(part, P_RZ, gridDim.x);
+    const double rr = partial_total<NT>(part, P_RR, gridDim.x);
     if (rr <= scal[S_TOL2] || !isfinite(rr)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             scal[S_DONE] = 1.0;
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(RB) void k_cg_spmv(Mat A, int k, const double* __re
     const double bt = k == 0 ? 0.0 : rz / scal[S_RHO0 + ((k - 1) & 1)];
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_RHO0 + (k & 1)] = rz;
     double pq = 0.0;
-    FOR_ROW(i) {
+    FOR_ROW_NT(i, NT) {
         const double qi = row_dot4(A.col, A.val, A.rowptr[i], A.rowptr[i + 1],
                                    [&](int32_t j) { return fma(bt, p_old[j], z[j]); });
         const double pi = fma(bt, p_old[i], z[i]);
@@ -97,21 +98,21 @@ __global__ __launch_bounds__(RB) void k_cg_spmv(Mat A, int k, const double* __re
         q[i] = qi;
         pq = fma(pi, qi, pq);
     }
-    write_partial(part, P_PQ, pq);
+    write_partial<NT>(part, P_PQ, pq);
 }
 
 // The same iteration for matrices with long rows (P2 tetrahedra: about 30
 // entries a row): L lanes per row walk its entries together (consecutive
 // entries, so each load of the matrix is a contiguous run) and add their
 // parts with a butterfly; a block takes RB / L rows per pass.
-template <int L>
-__global__ __launch_bounds__(RB) void k_cg_spmv_rows(Mat A, int k, const double* __restrict__ z,
+template <int L, int NT>
+__global__ __launch_bounds__(NT) void k_cg_spmv_rows(Mat A, int k, const double* __restrict__ z,
                                                      const double* __restrict__ p_old, double* __restrict__ p_new,
                                                      double* __restrict__ q, double* __restrict__ part,
                                                      double* __restrict__ scal) {
     if (scal[S_DONE] != 0.0) return;
-    const double rz = partial_total(part, P_RZ, gridDim.x);
-    const double rr = partial_total(part, P_RR, gridDim.x);
+    const double rz = partial_total<NT>(part, P_RZ, gridDim.x);
+    const double rr = partial_total<NT>(part, P_RR, gridDim.x);
     if (rr <= scal[S_TOL2] || !isfinite(rr)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             scal[S_DONE] = 1.0;
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(RB) void k_cg_spmv_rows(Mat A, int k, const double*
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_RHO0 + (k & 1)] = rz;
     const int sub = int(threadIdx.x) & (L - 1);
     double pq = 0.0;
-    for (int64_t i0 = int64_t(blockIdx.x) * (RB / L); i0 < A.n; i0 += int64_t(gridDim.x) * (RB / L)) {
+    for (int64_t i0 = int64_t(blockIdx.x) * (NT / L); i0 < A.n; i0 += int64_t(gridDim.x) * (NT / L)) {
         const int64_t i = i0 + int(threadIdx.x) / L;
         double qi = 0.0;
         if (i < A.n) {
@@ -142,22 +143,31 @@ __global__ __launch_bounds__(RB) void k_cg_spmv_rows(Mat A, int k, const double*
             pq = fma(pi, qi, pq);
         }
     }
-    write_partial(part, P_PQ, pq);
+    write_partial<NT>(part, P_PQ, pq);
 }
 
 // Rows this long or longer on average take the lanes-per-row product.
 constexpr int kLongRows = 24;
 
+// Threads per block of the CG iteration kernels for long rows.  Their grid is
+// capped by the number of block partials (at most MAX_RBLOCKS, which every
+// block of the next kernel adds up), so wide blocks are what keeps enough
+// loads in flight: with 256 threads the P2 tetrahedral product ran two waves
+// per SIMD at 1.9 TB/s, with 1024 eight.  (The P1 matrices ran slower with
+// wide blocks and keep RB.)
+constexpr int kCgWide = 1024;
+
 // Iteration k, second half: alpha = rz_k / (p.q); y += alpha p; r -= alpha q;
 // z = D^-1 r; partials of r.z and r.r for iteration k+1.
-__global__ __launch_bounds__(RB) void k_cg_update(Mat A, int k, const double* __restrict__ p,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_cg_update(Mat A, int k, const double* __restrict__ p,
                                                   const double* __restrict__ q, double* __restrict__ y,
                                                   double* __restrict__ r, double* __restrict__ z,
                                                   double* __restrict__ part, double* __restrict__ scal) {
     if (scal[S_DONE] != 0.0) return;
-    const double a = scal[S_RHO0 + (k & 1)] / partial_total(part, P_PQ, gridDim.x);
+    const double a = scal[S_RHO0 + (k & 1)] / partial_total<NT>(part, P_PQ, gridDim.x);
     double rz = 0.0, rr = 0.0;
-    FOR_ROW(i) {
+    FOR_ROW_NT(i, NT) {
         y[i] = fma(a, p[i], y[i]);
         const double ri = fma(-a, q[i], r[i]);
         const double zi = ri / A.diag[i];
@@ -166,8 +176,8 @@ __global__ __launch_bounds__(RB) void k_cg_update(Mat A, int k, const double* __
         rz = fma(ri, zi, rz);
         rr = fma(ri, ri, rr);
     }
-    write_partial(part, P_RZ, rz);
-    write_partial(part, P_RR, rr);
+    write_partial<NT>(part, P_RZ, rz);
+    write_partial<NT>(part, P_RR, rr);
 }
 
 // After the last launched iteration: the stopping test for the final residual.
@@ -562,17 +572,22 @@ static ft_status project_one(ft_target* T, const ft_solve_cfg* cfg, double* x, d
     int launched = 0;
     int chunk = first_chunk(T->cg_hint[0]);
     bool done = false;
+    const bool long_rows = T->nnz >= kLongRows * n;
     while (true) {
         const int k = std::min(chunk, cfg->max_iter - launched);
         for (int it = 0; it < k; ++it) {
             const int kk = launched + it;
             double* p_old = T->p + ((kk & 1) ? n : 0);
             double* p_new = T->p + ((kk & 1) ? 0 : n);
-            if (T->nnz >= kLongRows * n)
-                k_cg_spmv_rows<8><<<nb, RB, 0, s>>>(A, kk, T->z, p_old, p_new, T->q, T->partials, T->scal);
-            else
-                k_cg_spmv<<<nb, RB, 0, s>>>(A, kk, T->z, p_old, p_new, T->q, T->partials, T->scal);
-            k_cg_update<<<nb, RB, 0, s>>>(A, kk, p_new, T->q, T->y, T->r, T->z, T->partials, T->scal);
+            if (long_rows) {
+                k_cg_spmv_rows<8, kCgWide><<<nb, kCgWide, 0, s>>>(A, kk, T->z, p_old, p_new, T->q, T->partials,
+                                                                 T->scal);
+                k_cg_update<kCgWide><<<nb, kCgWide, 0, s>>>(A, kk, p_new, T->q, T->y, T->r, T->z, T->partials,
+                                                           T->scal);
+            } else {
+                k_cg_spmv<RB><<<nb, RB, 0, s>>>(A, kk, T->z, p_old, p_new, T->q, T->partials, T->scal);
+                k_cg_update<RB><<<nb, RB, 0, s>>>(A, kk, p_new, T->q, T->y, T->r, T->z, T->partials, T->scal);
+            }
         }
         launched += k;
         k_cg_check<<<1, RB, 0, s>>>(launched, nb, T->partials, T->scal);

@@ -14,15 +14,17 @@ constexpr int MAX_RBLOCKS = 512;   // grid size cap (grid-stride loops beyond it
 enum { P_BB = 0, P_SB, P_SBC, P_RZ, P_RR, P_PQ, P_TRR, P_MX, P_MXC, P_COUNT };
 enum { S_RHO0 = 0, S_RHO1, S_TOL2, S_DONE, S_ITERS, S_BB, S_SUMB, S_TRR, S_INTX, S_COUNT };
 
+// NT: threads of the block (a multiple of 64)
+template <int NT = RB>
 __device__ __forceinline__ double block_total(double v) {
-    __shared__ double sm[RB / 64];
+    __shared__ double sm[NT / 64];
     __shared__ double tot;
     v = wave_sum_xor(v, 64);
     if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = sm[0];
-        for (int k = 1; k < RB / 64; ++k) s += sm[k];
+        for (int k = 1; k < NT / 64; ++k) s += sm[k];
         tot = s;
     }
     __syncthreads();
@@ -32,14 +34,16 @@ __device__ __forceinline__ double block_total(double v) {
 }
 
 // Sum of the nb partials of one slot, in block order (same value in every block).
+template <int NT = RB>
 __device__ __forceinline__ double partial_total(const double* __restrict__ part, int slot, int nb) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += RB) s += part[slot * nb + b];
-    return block_total(s);
+    for (int b = threadIdx.x; b < nb; b += NT) s += part[slot * nb + b];
+    return block_total<NT>(s);
 }
 
+template <int NT = RB>
 __device__ __forceinline__ void write_partial(double* __restrict__ part, int slot, double v) {
-    const double t = block_total(v);
+    const double t = block_total<NT>(v);
     if (threadIdx.x == 0) part[slot * gridDim.x + blockIdx.x] = t;
 }
 
@@ -118,5 +122,8 @@ struct Mat {
 };
 
 #define FOR_ROW(i) for (int64_t i = int64_t(blockIdx.x) * RB + threadIdx.x; i < A.n; i += int64_t(gridDim.x) * RB)
+// the same for blocks of NT threads
+#define FOR_ROW_NT(i, NT) \
+    for (int64_t i = int64_t(blockIdx.x) * (NT) + threadIdx.x; i < A.n; i += int64_t(gridDim.x) * (NT))
 
 }  // namespace ft
