@@ -37,11 +37,11 @@ DTYPES = {"f64": "f64", "f32": "f32", "split-f16": "f32+f16x2", "split-bf16": "f
 # device sources each timed kernel is compiled from: a counter record taken on
 # other sources no longer describes the kernel and is not reported
 KERNEL_SOURCES = {
-    "k_emit": ["mc.hip", "sampling.h", "common.h"],
+    "k_emit": ["mc.hip", "adaptive.h", "sampling.h", "common.h"],
     "k_src_eval": ["source.hip", "locate.h", "common.h"],
-    "k_consume": ["mc.hip", "sampling.h", "common.h"],
+    "k_consume": ["mc.hip", "adaptive.h", "sampling.h", "common.h"],
     "k_consume_mfma": ["mc_mfma.hip", "sampling.h", "common.h"],
-    "k_fused_p1": ["fused.hip", "fused.h", "locate.h", "sampling.h", "common.h"],
+    "k_fused_p1": ["fused.hip", "fused.h", "adaptive.h", "locate.h", "sampling.h", "common.h"],
 }
 TRAFFIC_RECORDS = os.path.join(ROOT, "profiles", "hbm_traffic.md")
 VALU_RECORDS = os.path.join(ROOT, "profiles", "valu_counts.md")
@@ -793,7 +793,7 @@ def main():
             n0 = max(2, N // 4)
             pc = ft.SampleCfg(n0, F, w.alpha, w.philox_seed, 1 << 20, prec)
             ac = ft.SampleCfg(0, F, w.alpha, w.philox_seed, 0, prec)
-            tp, tal, tms = [], [], []
+            tp, tal, tms, tfu = [], [], [], []
             for _ in range(3):
                 e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
                 e0.record()
@@ -816,10 +816,18 @@ def main():
                 ra = T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
                 ev[4].record()
                 torch.cuda.synchronize()
+                del pa, va
+                ef = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                ef[0].record()
+                T.transfer_from_adaptive(S, ac, offs, al.total)
+                ef[1].record()
+                rf = T.project(F, rtol=w.rtol, max_iter=1000, x=x, b=b)
+                ef[2].record()
+                torch.cuda.synchronize()
                 tp.append(e0.elapsed_time(e1))
                 tal.append(e1.elapsed_time(e2))
                 tms.append([ev[k].elapsed_time(ev[k + 1]) for k in range(4)])
-                del pa, va
+                tfu.append([ef[0].elapsed_time(ef[1]), ef[1].elapsed_time(ef[2])])
             cnt = torch.diff(offs)
             ph = np.median(np.array(tms), axis=0)
             variants["neyman_counts"] = {
@@ -830,7 +838,10 @@ def main():
                 "allocate_ms": float(np.median(tal)), "pilot_samples_per_elem": n0,
                 "total_samples": int(al.total), "sum_b_stderr": ra.reports[0]["sum_b_stderr"],
                 "predicted_stderr": al.predicted_stderr,
-                "uniform_sum_b_stderr": reports[0]["sum_b_stderr"]}
+                "uniform_sum_b_stderr": reports[0]["sum_b_stderr"],
+                "fused_route": {"ms_per_step": float(np.median(np.array(tfu).sum(axis=1))),
+                                "phases_ms": dict(zip(("fused", "project"), map(float, np.median(np.array(tfu), axis=0)))),
+                                "sum_b_stderr": rf.reports[0]["sum_b_stderr"]}}
         supermesh_route["variance_variants"] = variants
         del b_mc, exact
 

@@ -352,6 +352,21 @@ ft_status ft_consume_queries_adaptive(ft_target* t, const ft_sample_cfg* cfg, co
                                       const void* values, hipStream_t stream);
 
 /*
+ * ft_transfer_p1_adaptive - ft_transfer_p1 with N_t = offsets[t+1] - offsets[t]
+ * samples in element t (the counts of ft_allocate_samples): the same samples
+ * as ft_sample_points_adaptive draws (so the same element loads as consuming
+ * that list's values of the built-in source), with no query list in memory.
+ * cfg->samples_per_elem must be 0; plain samples, FT_F64 or FT_F32, at most 4
+ * fields, fixed alpha; P1 and P2 targets.  offsets and total as
+ * ft_sample_points_adaptive (an invalid range contributes 0 and counts as a
+ * non-finite value).  ft_project reports the standard error of sum b (-1 when
+ * an element has a single sample).
+ * Errors: FT_E_ARG, FT_E_UNSUPPORTED, FT_E_OOM.  Asynchronous on `stream`.
+ */
+ft_status ft_transfer_p1_adaptive(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, const int64_t* offsets,
+                                  int64_t total, hipStream_t stream);
+
+/*
  * ft_project - step 2 and step 7 of sec. 4.1 and the conservation report.
  * Several fields (F > 1, at most 64) are solved together by a batched PCG that
  * reads M once per iteration for all of them, each field with its own

@@ -32,6 +32,8 @@ ft_status source_eval_tiles(ft_source* S, int64_t n_nodes, int64_t n_elems, int 
 ft_status source_autotune(ft_source* S, int64_t head, int64_t npts, const void* pts, int64_t ld, int prec, int ncand,
                           const int32_t* cand, hipStream_t s);
 ft_status transfer_p1(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, hipStream_t s);
+ft_status transfer_p1_varn(ft_target* T, ft_source* S, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total,
+                           hipStream_t s);
 ft_status transfer_supermesh(ft_target* T, ft_source* S, double* area, hipStream_t s);
 ft_status batch_setup(ft_batch* b, hipStream_t s);
 ft_status batch_run(ft_batch* b, const ft_solve_cfg* cfg, double* const* x, double* const* bvec, ft_report* rep,
@@ -438,6 +440,29 @@ ft_status ft_transfer_p1(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, h
     FT_TRY(ensure_field_buffers(t, cfg->n_fields, stream));
     t->consumed = false;
     FT_TRY(transfer_p1(t, s, cfg, stream));
+    t->consumed = true;
+    t->consumed_cfg = *cfg;
+    return FT_OK;
+    FT_GUARD_END
+}
+
+ft_status ft_transfer_p1_adaptive(ft_target* t, ft_source* s, const ft_sample_cfg* cfg, const int64_t* offsets,
+                                  int64_t total, hipStream_t stream) {
+    FT_GUARD_BEGIN
+    clear_error();
+    FT_ARG_CHECK(t && s, "target and source must be non-null");
+    FT_TRY(check_varn_cfg(t, cfg, offsets, total));
+    FT_ARG_CHECK(s->dim == t->dim, "source dimension %d differs from target dimension %d", s->dim, t->dim);
+    FT_ARG_CHECK(cfg->n_fields == s->F, "n_fields (%d) must equal the source's field count (%d)", cfg->n_fields,
+                 s->F);
+    if (cfg->n_fields > 4) {
+        set_error("the fused built-in route supports at most 4 fields");
+        return FT_E_UNSUPPORTED;
+    }
+    FT_TRY(check_alpha_mode(t, cfg, false));
+    FT_TRY(ensure_field_buffers(t, cfg->n_fields, stream));
+    t->consumed = false;
+    FT_TRY(transfer_p1_varn(t, s, cfg, offsets, total, stream));
     t->consumed = true;
     t->consumed_cfg = *cfg;
     return FT_OK;

@@ -31,7 +31,9 @@ constexpr int kLamSlots = kStashLambda<D, P> ? 64 * P * (D + 1) : 0;
 // kernel writes it (sum and sum of squares of r - (1 - alpha) gbar).
 // ORD: degree of the target elements; for P2 dofs lists each element's
 // nodes ([E][nb]: vertices, then edge nodes), where g and the loads live.
-template <int D, int G, int P, int FC, bool F32 = false, int ORD = 1>
+// VN: N is this element's own count (per-element counts, G == 64); the
+// variance of a single-sample element is undefined (NaN) rather than 0.
+template <int D, int G, int P, int FC, bool F32 = false, int ORD = 1, bool VN = false>
 __device__ __forceinline__ void fused_elements(const SrcView& S, const double* __restrict__ X, int64_t n,
                                                const int32_t* __restrict__ conn, const double* __restrict__ vol,
                                                uint32_t E, uint32_t N, double alpha, SampleKey key,
@@ -186,7 +188,8 @@ __device__ __forceinline__ void fused_elements(const SrcView& S, const double* _
     if (valid && lane == 0) {
         const double scale = vol[t] / double(N);
         const double Nd = double(N);
-        const double inv_n = 1.0 / Nd, inv_var = N > 1 ? inv_n / (Nd - 1.0) : 0.0;
+        const double inv_n = 1.0 / Nd;
+        const double inv_var = N > 1 ? inv_n / (Nd - 1.0) : (VN ? __builtin_nan("") : 0.0);
 #pragma unroll
         for (int f = 0; f < FC; ++f) {
             if (f >= S.F) break;

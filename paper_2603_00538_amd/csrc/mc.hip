@@ -94,17 +94,6 @@ constexpr int kEmitRuns = D == 2 ? 8 : 4;
 // element whose range is invalid (see element_range) writes nothing.
 constexpr int kVarRuns = 4;
 
-// Element t's samples from the allocation offsets: [o0, o1) of the sample block,
-// valid when 1 <= o1 - o0 <= kMaxElemSamples and both lie in [0, total].
-__device__ __forceinline__ bool element_range(const int64_t* __restrict__ offs, uint32_t t, int64_t total,
-                                              int64_t& o0, uint32_t& N) {
-    o0 = offs[t];
-    const int64_t o1 = offs[t + 1];
-    const bool ok = o0 >= 0 && o1 > o0 && o1 <= total && o1 - o0 <= kMaxElemSamples;
-    N = ok ? uint32_t(o1 - o0) : 0u;
-    return ok;
-}
-
 template <int D, bool F32>
 __global__ __launch_bounds__(256) void k_emit_varn(const double* __restrict__ X, int64_t n,
                                                    const int32_t* __restrict__ conn, uint32_t E,

@@ -36,7 +36,7 @@ EXPORTED = ["ft_target_create", "ft_target_create_p2", "ft_target_destroy", "ft_
             "ft_plan_create", "ft_plan_transfer", "ft_plan_destroy",
             "ft_source_destroy", "ft_source_get_info", "ft_source_integral", "ft_samples_for_tolerance",
             "ft_allocate_samples", "ft_budget_for_tolerance", "ft_sample_points_adaptive",
-            "ft_consume_queries_adaptive", "ft_last_error"]
+            "ft_consume_queries_adaptive", "ft_transfer_p1_adaptive", "ft_last_error"]
 
 
 class SampleCfg(ctypes.Structure):
@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH):
         "ft_budget_for_tolerance": (I64, [D, D, D]),
         "ft_sample_points_adaptive": (I32, [P, ctypes.POINTER(SampleCfg), P, I64, P, P]),
         "ft_consume_queries_adaptive": (I32, [P, ctypes.POINTER(SampleCfg), P, I64, P, P]),
+        "ft_transfer_p1_adaptive": (I32, [P, P, ctypes.POINTER(SampleCfg), P, I64, P]),
         "ft_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -353,6 +354,11 @@ def ft_consume_queries_adaptive(h, cfg: SampleCfg, offsets_ptr, total, values_pt
                   "ft_consume_queries_adaptive")
 
 
+def ft_transfer_p1_adaptive(h, src, cfg: SampleCfg, offsets_ptr, total, stream):
+    return _check(load().ft_transfer_p1_adaptive(h, src, ctypes.byref(cfg), offsets_ptr, total, stream),
+                  "ft_transfer_p1_adaptive")
+
+
 def _torch():
     import torch
     return torch
@@ -482,6 +488,12 @@ class Target:
             raise ValueError(f"values hold {values.numel()} entries, need {cfg.n_fields * Q}")
         ft_consume_queries_adaptive(self.handle, cfg, _device_ptr(offsets, "offsets", (torch.int64,)), int(total),
                                     _device_ptr(values, "values", (dt,)), current_stream())
+
+    def transfer_from_adaptive(self, source, cfg: SampleCfg, offsets, total):
+        """ft_transfer_p1_adaptive: the fused route with per-element counts."""
+        torch = _torch()
+        ft_transfer_p1_adaptive(self.handle, source.handle, cfg, _device_ptr(offsets, "offsets", (torch.int64,)),
+                                int(total), current_stream())
 
     def transfer_from(self, source, cfg: SampleCfg):
         """Fused steps 1 and 3-6 from a built-in Source (no query list in memory)."""

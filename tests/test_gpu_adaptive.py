@@ -162,6 +162,72 @@ def test_uniform_counts_equal_fixed_n_bitwise(N):
     S.close()
 
 
+@pytest.mark.parametrize("dim,F,order", [(2, 1, 1), (3, 1, 1), (2, 3, 1), (2, 1, 2), (3, 1, 2)])
+def test_fused_adaptive_matches_black_box_and_oracle(dim, F, order):
+    """ft_transfer_p1_adaptive draws the same samples as the list of per-element
+    counts and sums them in the same lane order: the black-box route's loads
+    (both forms) and the oracle's (binary64)."""
+    if order == 1:
+        tm, sm = _pair(dim)
+    else:
+        c, t = meshes.delaunay_tri_mesh(7, 0.3, 199) if dim == 2 else meshes.kuhn_tet_mesh(3, 0.08, 200)
+        tm = meshes.p2_mesh(c, t)
+        sm = meshes.delaunay_tri_mesh(12, 0.3, 201) if dim == 2 else meshes.kuhn_tet_mesh(5, 0.08, 202)
+    sv = _values(dim, sm[0], F)
+    counts = _counts(tm[1].shape[0], 2, 300, 41 + dim + F + order)
+    ref = adaptive.transfer(*tm, P1Source(*sm, sv), counts, alpha=0.75, seed=SEED, stream=12)
+    log(f"fused adaptive dim={dim} F={F} order={order}")
+    T = ft.Target(*tm, order=order)
+    S = ft.Source(*sm, sv)
+    off = _offsets(counts)
+    total = int(counts.sum())
+    for prec in (ft.FT_F64, ft.FT_F32):
+        cfg = _cfg(0, F, 0.75, 12, prec)
+        T.transfer_from_adaptive(S, cfg, off, total)
+        rf = T.project(F)
+        pts = T.sample_points_adaptive(cfg, off, total)
+        T.consume_adaptive(cfg, off, total, S.eval_query_list(pts, T.n_nodes))
+        rb = T.project(F)
+        assert rf.status == ft.FT_OK and rb.status == ft.FT_OK
+        assert rel_l2(rf.b.cpu().numpy(), rb.b.cpu().numpy()) < 1e-13
+        tol = 1e-12 if prec == ft.FT_F64 else 1e-5
+        assert rel_l2(rf.b.cpu().numpy(), ref["b"]) < tol and rel_l2(rf.x.cpu().numpy(), ref["x"]) < 10 * tol
+        for f in range(F):
+            a_, b_ = rf.reports[f]["sum_b_stderr"], rb.reports[f]["sum_b_stderr"]
+            assert abs(a_ - b_) <= 1e-12 * b_
+            assert abs(a_ - ref["report"][f]["sum_b_stderr"]) <= (1e-9 if prec == ft.FT_F64 else 1e-2) * a_
+    T.close()
+    S.close()
+
+
+def test_fused_adaptive_errors_and_invalid_ranges():
+    tm, sm = _pair(2)
+    sv = _values(2, sm[0], 1)
+    E = tm[1].shape[0]
+    T = ft.Target(*tm)
+    S = ft.Source(*sm, sv)
+    counts = np.full(E, 12)
+    off = _offsets(counts)
+    total = int(counts.sum())
+    for kw, st in (({"alpha_mode": ft.FT_ALPHA_ELEMENT}, ft.FT_E_UNSUPPORTED),
+                   ({"sampling": ft.FT_SAMPLING_STRATIFIED}, ft.FT_E_UNSUPPORTED),
+                   ({"samples_per_elem": 12}, ft.FT_E_ARG), ({"n_fields": 2}, ft.FT_E_ARG)):
+        c = _cfg(0)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        with pytest.raises(ft.FtError) as e:
+            T.transfer_from_adaptive(S, c, off, total)
+        assert e.value.status == st, kw
+    bad = adaptive.offsets(counts)
+    bad[3] = bad[2]          # element 2 empty
+    bad[E] = total + 1       # the last element runs past total
+    T.transfer_from_adaptive(S, _cfg(0), torch.as_tensor(bad, device="cuda"), total)
+    r = T.project(1)
+    assert r.status == ft.FT_E_NONFINITE and r.reports[0]["n_nonfinite"] == 2
+    T.close()
+    S.close()
+
+
 def test_allocation_matches_oracle():
     """A pilot (N0 = 16) on both sides; the GPU counts equal the oracle's except
     where the proportional count lies within 1e-9 of a rounding tie (the two
@@ -295,7 +361,8 @@ def test_invalid_ranges_and_single_samples():
 def test_fullsize_pilot_allocation_transfer():
     """tri2d_1m (1M triangles): a pilot with N0 = 16 (fused route, its own
     stream), Neyman counts for 64 samples per element in all, then the
-    black-box transfer with those counts.  Its standard error is below that of
+    black-box transfer with those counts (and the fused route with them: the
+    same sum b).  Its standard error is below that of
     64 uniform samples and within 15% of the allocation's prediction, sum b lies
     within six standard errors of the exact source integral, and the
     conservation identity holds."""
@@ -317,6 +384,10 @@ def test_fullsize_pilot_allocation_transfer():
     T.consume_adaptive(cfg, off, al.total, S.eval_query_list(pts, T.n_nodes))
     del pts
     ra = T.project(1).reports[0]
+    T.transfer_from_adaptive(S, cfg, off, al.total)
+    rf = T.project(1).reports[0]
+    assert abs(rf["sum_b"] - ra["sum_b"]) <= 1e-13 * abs(ra["sum_b"])
+    assert abs(rf["sum_b_stderr"] - ra["sum_b_stderr"]) <= 1e-12 * ra["sum_b_stderr"]
     T.transfer_from(S, ft.SampleCfg(64, 1, w.alpha, w.philox_seed, 0, ft.FT_F64))
     ru = T.project(1).reports[0]
     I = S.integral()[0]
