@@ -8,10 +8,11 @@ The element measure of a simplex is |det J| / d!, J = [x_1-x_0, ..., x_d-x_0]
 
 Two independent routes to M are provided and must agree:
   * closed form of the P1 element matrix, |T| (1 + delta_kl) / ((d+1)(d+2));
-  * a degree-2 Gauss rule (exact for the quadratic products psi_k psi_l):
-    triangle: 3 points at barycentric (2/3, 1/6, 1/6) and permutations,
-    weights 1/3; tetrahedron: 4 points at (a, b, b, b) and permutations with
-    a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weights 1/4.
+  * a degree-2 rule (exact for the quadratic products psi_k psi_l): d+1
+    points at barycentric (a, b, ..., b) and permutations, weights 1/(d+1),
+    b = (d + 2 - sqrt(d + 2)) / ((d + 1)(d + 2)), a = 1 - d b (Stroud's
+    T_n:2-1); triangle (2/3, 1/6, 1/6), tetrahedron a = (5 + 3 sqrt 5)/20,
+    b = (5 - sqrt 5)/20.
 
 Parity: pinned by the Dirichlet monomial formula (quadrature exactness up to
 degree 2), sum(M) = |domain|, and closed form == quadrature.
@@ -28,15 +29,17 @@ def quadrature_rule(dim: int):
     """(barycentric points (q, d+1), weights (q,) summing to 1): degree-2 exact."""
     if dim == 2:
         a, b = 2.0 / 3.0, 1.0 / 6.0
-        pts = np.array([[a, b, b], [b, a, b], [b, b, a]])
-        w = np.full(3, 1.0 / 3.0)
     elif dim == 3:
         s5 = math.sqrt(5.0)
         a, b = (5.0 + 3.0 * s5) / 20.0, (5.0 - s5) / 20.0
-        pts = np.array([[a, b, b, b], [b, a, b, b], [b, b, a, b], [b, b, b, a]])
-        w = np.full(4, 0.25)
+    elif 4 <= dim <= 6:
+        b = (dim + 2 - math.sqrt(dim + 2)) / ((dim + 1) * (dim + 2))
+        a = 1.0 - dim * b
     else:
-        raise ValueError("dim must be 2 or 3")
+        raise ValueError("dim must lie in [2, 6]")
+    pts = np.full((dim + 1, dim + 1), b)
+    np.fill_diagonal(pts, a)
+    w = np.full(dim + 1, 1.0 / (dim + 1))
     return pts, w
 
 

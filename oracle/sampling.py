@@ -11,12 +11,18 @@ scalars are sorted, s1 <= s2 <= s3, and the spacings
 (s1, s2-s1, s3-s2, 1-s3) are the barycentric weights; uniform spacings are
 Dirichlet(1,1,1,1), i.e. uniform on the tetrahedron.
 
-Counter layout (one Philox4x32-10 block per 2D sample, two per 3D sample):
-counter = (j, t, stream, blk), key = (seed_lo, seed_hi), where t is the target
-element index, j the sample index within the element.
+Reading for d-simplices, d = 4..6 (sec. 2 states the formulation for any
+dimension and sec. 7 names 5D/6D transfers): the same sorted-spacings map
+with d uniforms, (s1, s2-s1, ..., sd-s(d-1), 1-sd) ~ Dirichlet(1, ..., 1).
+
+Counter layout (one Philox4x32-10 block per 2D sample, two per 3D sample,
+ceil(d/2) per d-simplex sample): counter = (j, t, stream, blk), key =
+(seed_lo, seed_hi), where t is the target element index, j the sample index
+within the element.
   2D: blk 0 words (0,1) -> xi, words (2,3) -> eta;
       lambda = (1 - sqrt(xi), sqrt(xi) (1 - eta), sqrt(xi) eta).
-  3D: blk 0 words (0,1) -> u1, words (2,3) -> u2; blk 1 words (0,1) -> u3.
+  d >= 3: uniform u_(i+1) from blk i/2, words (0,1) for even i and (2,3) for
+      odd i (3D: blk 0 words (0,1) -> u1, (2,3) -> u2; blk 1 words (0,1) -> u3).
 lambda_k multiplies vertex k of the element in connectivity order.
 
 Stratified (jittered) variant, a reading of the paper's suggestion of
@@ -50,17 +56,20 @@ def uniforms(dim: int, t: np.ndarray, j: np.ndarray, seed: int, stream: int):
     t = np.asarray(t, dtype=np.uint32)
     j = np.asarray(j, dtype=np.uint32)
     s = np.uint32(stream)
-    w = philox.philox4x32_10(j, t, s, np.uint32(0), k0, k1)
-    u = [philox.uniform53(w[0], w[1]), philox.uniform53(w[2], w[3])]
-    if dim == 3:
-        w1 = philox.philox4x32_10(j, t, s, np.uint32(1), k0, k1)
-        u.append(philox.uniform53(w1[0], w1[1]))
+    u = []
+    for blk in range((dim + 1) // 2):
+        w = philox.philox4x32_10(j, t, s, np.uint32(blk), k0, k1)
+        u.append(philox.uniform53(w[0], w[1]))
+        if len(u) < dim:
+            u.append(philox.uniform53(w[2], w[3]))
     return np.stack(u, axis=1)
 
 
 def strata_per_axis(dim: int, n_samples: int) -> int:
     """m = floor(N^(1/d')) with d' = dim uniforms per sample (2 or 3), exactly."""
-    dp = 2 if dim == 2 else 3
+    if dim not in (2, 3):
+        raise ValueError("stratified samples: triangles and tetrahedra")
+    dp = dim
     m = max(1, int(round(n_samples ** (1.0 / dp))))
     while m ** dp > n_samples:
         m -= 1
@@ -91,10 +100,11 @@ def barycentric_from_uniforms(dim: int, u: np.ndarray) -> np.ndarray:
         xi, eta = u[:, 0], u[:, 1]
         r = np.sqrt(xi)
         return np.stack([1.0 - r, r * (1.0 - eta), r * eta], axis=1)
-    if dim == 3:
+    if 3 <= dim <= 6:
         s = np.sort(u, axis=1)
-        return np.stack([s[:, 0], s[:, 1] - s[:, 0], s[:, 2] - s[:, 1], 1.0 - s[:, 2]], axis=1)
-    raise ValueError("dim must be 2 or 3")
+        cols = [s[:, 0]] + [s[:, k] - s[:, k - 1] for k in range(1, dim)] + [1.0 - s[:, dim - 1]]
+        return np.stack(cols, axis=1)
+    raise ValueError("dim must lie in [2, 6]")
 
 
 def element_samples(dim: int, n_elems: int, n_samples: int, seed: int, stream: int,

@@ -101,6 +101,21 @@ FIELDS = {
 }
 
 
+def phase_space(xp, *xs):
+    """A distribution-function-like field on [0,1]^d (d >= 2): spatial
+    modulation along x_1 times a drifting Gaussian in the other coordinates,
+    (1 + 0.3 cos(2 pi x_1)) exp(-sum_{i>1} (x_i - 0.5 - 0.05 sin(2 pi x_1))^2 / 0.08)."""
+    x1 = xs[0]
+    shift = 0.5 + 0.05 * xp.sin(2.0 * np.pi * x1)
+    r2 = 0.0 * x1
+    for xi in xs[1:]:
+        r2 = r2 + (xi - shift) ** 2
+    return (1.0 + 0.3 * xp.cos(2.0 * np.pi * x1)) * xp.exp(-r2 / 0.08)
+
+
+FIELDS["phase_space"] = phase_space
+
+
 def evaluate(name: str, xp, coords):
     """Evaluate a named field at points ``coords`` of shape (n, dim); returns (F, n)."""
     fn = FIELDS[name]

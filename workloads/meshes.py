@@ -47,7 +47,9 @@ def _orient(coords: np.ndarray, conn: np.ndarray) -> np.ndarray:
     """Swap the last two vertices of negatively oriented simplices."""
     x0 = coords[conn[:, 0]]
     e = [coords[conn[:, i]] - x0 for i in range(1, conn.shape[1])]
-    if conn.shape[1] == 3:
+    if conn.shape[1] > 4:
+        det = np.linalg.det(np.stack(e, axis=1))
+    elif conn.shape[1] == 3:
         det = e[0][:, 0] * e[1][:, 1] - e[0][:, 1] * e[1][:, 0]
     else:
         det = (e[0][:, 0] * (e[1][:, 1] * e[2][:, 2] - e[1][:, 2] * e[2][:, 1])
@@ -117,6 +119,30 @@ def kuhn_tet_mesh(k: int, jitter: float, seed: int):
     return coords, conn.astype(np.int32)
 
 
+def kuhn_mesh(dim: int, k: int, jitter: float, seed: int):
+    """Perturbed Kuhn (Freudenthal) split of a (k-1)^dim hypercube grid of
+    [0,1]^dim into dim! (k-1)^dim simplices: one per monotone lattice path
+    from a cell's lowest corner to its highest (the vertices after 0, 1, ...,
+    dim unit steps along the axes in the path's order).  dim = 3 gives the
+    same tetrahedra as kuhn_tet_mesh.  Jitter up to about 0.05h keeps every
+    volume positive in 6D (the default here is 0.03h)."""
+    coords = jittered_grid_points(k, dim, jitter, seed)
+    c = k - 1
+    idx = np.meshgrid(*([np.arange(c)] * dim), indexing="ij")
+    stride = np.array([k ** a for a in range(dim)], dtype=np.int64)
+    # cells with the x index fastest, as the node numbering
+    base = sum(idx[a].transpose(tuple(reversed(range(dim)))).ravel() * stride[a] for a in range(dim))
+    simp = []
+    for perm in itertools.permutations(range(dim)):
+        verts = [base]
+        for a in perm:
+            verts.append(verts[-1] + stride[a])
+        simp.append(np.stack(verts, 1))
+    conn = np.stack(simp, 1).reshape(-1, dim + 1)
+    conn = _orient(coords, conn)
+    return coords, conn.astype(np.int32)
+
+
 def make_mesh(kind: str, k: int, jitter: float, seed: int):
     if kind == "structured_tri":
         return structured_tri_mesh(k, jitter, seed)
@@ -124,6 +150,8 @@ def make_mesh(kind: str, k: int, jitter: float, seed: int):
         return delaunay_tri_mesh(k, jitter, seed)
     if kind == "kuhn_tet":
         return kuhn_tet_mesh(k, jitter, seed)
+    if kind.startswith("kuhn") and kind.endswith("d") and kind[4:-1].isdigit():
+        return kuhn_mesh(int(kind[4:-1]), k, jitter, seed)
     raise ValueError(f"unknown mesh kind {kind!r}")
 
 
