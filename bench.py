@@ -587,7 +587,7 @@ def main():
     import torch
 
     from paper_2603_00538_amd import ft
-    from workloads import configs
+    from workloads import configs, fields
 
     if args.workload == "batch256":
         bench_batch(args)
@@ -595,10 +595,15 @@ def main():
     w = configs.WORKLOADS[args.workload]
     log(f"workload {w.name}: building meshes")
     tmesh = configs.target_mesh(w)
-    smesh = configs.build_mesh(w.source)
-    svals = configs.source_nodal_values(w, smesh[0])
+    analytic = w.source is None   # the field itself is the black box (no source mesh)
+    if analytic and args.route != "blackbox":
+        print(f"{w.name} has no source mesh: only the black-box route applies", file=sys.stderr)
+        sys.exit(2)
+    if not analytic:
+        smesh = configs.build_mesh(w.source)
+        svals = configs.source_nodal_values(w, smesh[0])
+        sc, sconn = smesh
     tc, tconn = tmesh
-    sc, sconn = smesh
     dim, E, n = w.dim, tconn.shape[0], tc.shape[0]
     N, F = w.samples_per_elem, w.n_fields
     prec = getattr(ft, PRECISIONS[args.precision])
@@ -612,13 +617,13 @@ def main():
     t0 = time.perf_counter()
     T = ft.Target(tc, tconn, order=w.order)
     bins = (args.bins,) * 3 if args.bins else (w.bins if any(w.bins) else None)
-    S = ft.Source(sc, sconn, svals, bins=bins)
+    S = None if analytic else ft.Source(sc, sconn, svals, bins=bins)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"setup {setup_s * 1e3:.1f} ms; nnz {T.info.nnz}")
     Q = T.query_count(N)
     tuned = None
-    if args.autotune == "on" or (args.autotune == "auto" and bins is None):
+    if not analytic and (args.autotune == "on" or (args.autotune == "auto" and bins is None)):
         # sample: about 4M queries of this transfer's query list, the samples of
         # 16 runs of consecutive elements spread evenly over the target (runs,
         # so that neighbouring waves share cached candidates as in a full
@@ -668,7 +673,9 @@ def main():
             T.sample_points(cfg, out=pts)
             if record:
                 ev[1].record()
-            if tiles:
+            if analytic:
+                vals.copy_(fields.evaluate(w.field, torch, pts.t()))
+            elif tiles:
                 S.eval_tiles(pts, n, E, N, out=vals.view(-1))
             else:
                 S.eval_query_list(pts, n, out=vals)
@@ -707,13 +714,14 @@ def main():
     wall, phase_ms = timed(args.route, args.steps, args.warmup)
     ms_step = wall * 1e3 / args.steps
     extra_route = None
-    if args.route == "blackbox" and not args.no_fused and F <= 4 and prec == ft.FT_F64:
+    if args.route == "blackbox" and not args.no_fused and F <= 4 and prec == ft.FT_F64 and not analytic:
         fw, fph = timed("fused", args.steps, 1)
         extra_route = {"route": "fused (ft_transfer_p1, no query list)", "ms_per_step": fw * 1e3 / args.steps,
                        "value": E / (fw / args.steps), "phases_ms": fph}
 
     plan_route = None
-    if args.route == "blackbox" and not args.no_fused and F <= 4 and prec == ft.FT_F64 and w.order == 1:
+    if args.route == "blackbox" and not args.no_fused and F <= 4 and prec == ft.FT_F64 and w.order == 1 \
+            and not analytic:
         # setup/online split: localization cached once, then online transfers
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -741,7 +749,7 @@ def main():
         plan.close()
 
     supermesh_route = None
-    if args.route == "blackbox" and not args.no_fused and F <= 4 and w.order == 1:
+    if args.route == "blackbox" and not args.no_fused and F <= 4 and w.order == 1 and not analytic:
         # the exact load vector by mesh intersection (the paper's comparator):
         # its time, and the Monte Carlo load vector's distance from it
         b_mc = b.clone()
@@ -845,10 +853,14 @@ def main():
         supermesh_route["variance_variants"] = variants
         del b_mc, exact
 
-    si = S.info
-    src_info = {"E": sconn.shape[0], "n": sc.shape[0], "n_reg": int(si.n_registrations),
-                "nbins": int(np.prod([si.bins[c] for c in range(dim)]))}
-    cand = [k for k in ("emit", "eval", "consume", "fused") if k in phase_ms]
+    if analytic:
+        src_info = None
+    else:
+        si = S.info
+        src_info = {"E": sconn.shape[0], "n": sc.shape[0], "n_reg": int(si.n_registrations),
+                    "nbins": int(np.prod([si.bins[c] for c in range(dim)]))}
+    # (an analytic black box is the caller's work, not a kernel of the library)
+    cand = [k for k in ("emit", "eval", "consume", "fused") if k in phase_ms and not (analytic and k == "eval")]
     dom = max(cand, key=lambda k: phase_ms[k])
     split = prec in (ft.FT_SPLIT_F16, ft.FT_SPLIT_BF16) and N <= 256 and F <= 64
     kernel_names = {"emit": "k_emit", "eval": "k_src_eval_many" if F > 1 else "k_src_eval",
@@ -874,7 +886,7 @@ def main():
                   "ms": mt, "per_kernel": per}
     # conservation against the exact integral of the source field (sec. 2 Eq.
     # conservation; the relative conservation error of sec. 5.1)
-    ints = S.integral()
+    ints = S.integral() if not analytic else [configs.field_integral(w)] * F
     cons = []
     for f_, rep_ in enumerate(reports):
         I = ints[f_]
@@ -895,7 +907,9 @@ def main():
         "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "route": args.route, "dim": dim, "target_elements": E, "target_nodes": n,
-                   "source_elements": int(sconn.shape[0]), "samples_per_elem": N, "n_fields": F,
+                   "source_elements": None if analytic else int(sconn.shape[0]),
+                   "black_box": f"analytic {w.field}" if analytic else "P1 source mesh (ft_source_eval)",
+                   "samples_per_elem": N, "n_fields": F,
                    "queries": Q, "alpha": w.alpha, "rtol": w.rtol,
                    "bins": list(w.bins[:dim]) if any(w.bins) else "default", "precision": args.precision,
                    "values_layout": "element tiles" if tiles else "field-major",
@@ -923,16 +937,19 @@ def main():
         out["supermesh_route"] = supermesh_route
     if tuned is not None:
         out["bin_autotune"] = tuned
-    out["config"]["bins"] = [int(si.bins[c]) for c in range(dim)]
-    out["config"]["bin_registrations"] = int(si.n_registrations)
-    S.close()
+    if not analytic:
+        out["config"]["bins"] = [int(si.bins[c]) for c in range(dim)]
+        out["config"]["bin_registrations"] = int(si.n_registrations)
+        S.close()
+    else:
+        out["config"]["bins"] = None
     del pts, vals
     torch.cuda.empty_cache()
     if args.sequential and F > 1:
         out["sequential_f64"] = sequential_f64(T, w, tmesh, smesh, svals)
         out["sequential_f64"]["speedup_of_batched"] = out["sequential_f64"]["ms_total"] / ms_step
     T.close()
-    if not args.no_cpu_baseline and w.order == 1:
+    if not args.no_cpu_baseline and w.order == 1 and not analytic:
         log("cpu baseline (the oracle on the host cores, bounded samples, child process)")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -84,6 +84,11 @@ ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
                  "alpha_mode out of range (%d)", cfg->alpha_mode);
     FT_ARG_CHECK(cfg->values_layout == FT_VALUES_FIELD_MAJOR || cfg->values_layout == FT_VALUES_ELEMENT_TILES,
                  "values_layout out of range (%d)", cfg->values_layout);
+    if (T->dim > 3 && (cfg->sampling != FT_SAMPLING_PLAIN || cfg->precision == FT_SPLIT_F16 ||
+                       cfg->precision == FT_SPLIT_BF16)) {
+        set_error("targets of dimension 4 to 6 take plain samples in the FT_F64 and FT_F32 forms");
+        return FT_E_UNSUPPORTED;
+    }
     if (uint64_t(T->E) * uint64_t(cfg->samples_per_elem) >= (uint64_t(1) << 32) ||
         uint64_t(T->E) * 64u >= (uint64_t(1) << 32)) {
         set_error("n_elems * max(samples_per_elem, 64) must stay below 2^32 per transfer");
@@ -183,7 +188,8 @@ static ft_status target_create(int32_t dim, int order, int64_t n_nodes, const do
                                const int32_t* conn, hipStream_t stream, ft_target** out) {
     FT_ARG_CHECK(out, "out is null");
     *out = nullptr;
-    FT_ARG_CHECK(dim == 2 || dim == 3, "dim must be 2 or 3 (got %d)", dim);
+    FT_ARG_CHECK(dim >= 2 && dim <= (order == 1 ? 6 : 3), "dim must lie in [2, %d] (got %d)", order == 1 ? 6 : 3,
+                 dim);
     FT_ARG_CHECK(coords && conn, "coords and conn must be device pointers");
     const int nb = order == 1 ? dim + 1 : (dim + 1) * (dim + 2) / 2;
     FT_ARG_CHECK(n_nodes >= nb && n_nodes < INT32_MAX, "n_nodes out of range (%lld)", (long long)n_nodes);
@@ -575,6 +581,10 @@ ft_status ft_batch_create(int32_t count, ft_target* const* targets, ft_source* c
         const ft_target* t = targets[k];
         const ft_source* s = sources[k];
         FT_ARG_CHECK(t, "transfer %d: null target", k);
+        if (t->dim > 3) {
+            set_error("transfer %d: batches take triangle and tetrahedron targets", k);
+            return FT_E_UNSUPPORTED;
+        }
         FT_TRY(check_sample_cfg(t, &cfgs[k]));
         FT_ARG_CHECK(!s || s->dim == t->dim, "transfer %d: source dimension %d differs from target dimension %d", k,
                      s ? s->dim : 0, t->dim);

@@ -17,6 +17,8 @@
 // (coalesced reads of y), keep per-lane partial sums, and the group reduces
 // them with a fixed butterfly.  No floating-point atomics anywhere, so results
 // are bitwise reproducible run to run.
+#include <type_traits>
+
 #include "adaptive.h"
 #include "sampling.h"
 
@@ -439,6 +441,41 @@ __global__ void k_assemble(const double* __restrict__ beta, int64_t E, int nb, c
     if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
 }
 
+// The same with one wavefront per node, its lanes striding over the node's
+// incidence list (then a fixed butterfly): for meshes whose nodes touch
+// thousands of elements (d-simplices, d >= 4: 720 per vertex of a 5D Kuhn
+// mesh, 5040 in 6D), where one lane per node would leave the GPU nearly idle.
+template <bool F32>
+__global__ __launch_bounds__(256) void k_assemble_wide(const double* __restrict__ beta, int64_t E, int nb,
+                                                       const int64_t* __restrict__ inc_ptr,
+                                                       const int32_t* __restrict__ inc, int64_t n, int F,
+                                                       const void* __restrict__ values_, int64_t ld,
+                                                       double* __restrict__ bres, double* __restrict__ g,
+                                                       unsigned long long* __restrict__ nonfinite) {
+    const int64_t v = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (v >= n) return;   // the whole wave
+    const int lane = int(threadIdx.x & 63u);
+    const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
+    unsigned int nf = 0;
+    for (int f = 0; f < F; ++f) {
+        const double* bf = beta + int64_t(f) * E * nb;
+        double s = 0.0;
+        for (int64_t i = b + lane; i < e; i += 64) s += bf[inc[i]];
+        s = wave_sum_xor(s, 64);
+        if (lane == 0) {
+            bres[int64_t(f) * n + v] = s;
+            if (values_) {
+                const int64_t off = int64_t(f) * ld + v;
+                const double gv = F32 ? double(static_cast<const float*>(values_)[off])
+                                      : static_cast<const double*>(values_)[off];
+                nf += !isfinite(gv);
+                g[int64_t(f) * n + v] = gv;
+            }
+        }
+    }
+    if (nf) atomicAdd(nonfinite, (unsigned long long)nf);
+}
+
 // Fields-inner node assembly (many fields, F <= 64): one wavefront per node,
 // lane = field; each incidence entry adds one contiguous row beta[t][k][0..F)
 // in ascending (element, vertex) order; bres[v][f] and g[v][f] come out as
@@ -501,8 +538,21 @@ static ft_status emit_impl(ft_target* T, const ft_sample_cfg* cfg, void* points,
     return FT_OK;
 }
 
+// Calls f with the target's dimension as a compile-time constant (2..6).
+template <typename Fn>
+static ft_status by_dim(int dim, Fn&& f) {
+    switch (dim) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        default: set_error("dim must lie in [2, 6] (got %d)", dim); return FT_E_ARG;
+    }
+}
+
 ft_status emit_points(ft_target* T, const ft_sample_cfg* cfg, void* points, hipStream_t s) {
-    return T->dim == 2 ? emit_impl<2>(T, cfg, points, s) : emit_impl<3>(T, cfg, points, s);
+    return by_dim(T->dim, [&](auto d) { return emit_impl<decltype(d)::value>(T, cfg, points, s); });
 }
 
 // The query list of per-element counts: the nodes, then element t's samples
@@ -527,8 +577,7 @@ static ft_status emit_varn_impl(ft_target* T, const ft_sample_cfg* cfg, const in
 
 ft_status emit_points_varn(ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total, void* points,
                            hipStream_t s) {
-    return T->dim == 2 ? emit_varn_impl<2>(T, cfg, offs, total, points, s)
-                       : emit_varn_impl<3>(T, cfg, offs, total, points, s);
+    return by_dim(T->dim, [&](auto d) { return emit_varn_impl<decltype(d)::value>(T, cfg, offs, total, points, s); });
 }
 
 constexpr int kConsumeRuns = 4;   // elements per wave when G == 64
@@ -568,18 +617,22 @@ template <int D, bool F32>
 static void consume_g(ft_target* T, const ft_sample_cfg* cfg, const void* values, const ValueLayout& L,
                       double* beta, hipStream_t s) {
     const int N = cfg->samples_per_elem;
-    if (T->order == 2) {
-        if (N >= 64) consume_fc<D, 2, 64, F32>(T, cfg, values, L, beta, s);
-        else consume_fc<D, 2, 16, F32>(T, cfg, values, L, beta, s);
-        return;
+    if constexpr (D >= 4) {   // d-simplices (P1): one element per wave
+        consume_fc<D, 1, 64, F32>(T, cfg, values, L, beta, s);
+    } else {
+        if (T->order == 2) {
+            if (N >= 64) consume_fc<D, 2, 64, F32>(T, cfg, values, L, beta, s);
+            else consume_fc<D, 2, 16, F32>(T, cfg, values, L, beta, s);
+            return;
+        }
+        if (N >= 64) consume_fc<D, 1, 64, F32>(T, cfg, values, L, beta, s);
+        else if (N > 16) consume_fc<D, 1, 32, F32>(T, cfg, values, L, beta, s);
+        else if (N > 8) consume_fc<D, 1, 16, F32>(T, cfg, values, L, beta, s);
+        else if (N > 4) consume_fc<D, 1, 8, F32>(T, cfg, values, L, beta, s);
+        else if (N > 2) consume_fc<D, 1, 4, F32>(T, cfg, values, L, beta, s);
+        else if (N > 1) consume_fc<D, 1, 2, F32>(T, cfg, values, L, beta, s);
+        else consume_fc<D, 1, 1, F32>(T, cfg, values, L, beta, s);
     }
-    if (N >= 64) consume_fc<D, 1, 64, F32>(T, cfg, values, L, beta, s);
-    else if (N > 16) consume_fc<D, 1, 32, F32>(T, cfg, values, L, beta, s);
-    else if (N > 8) consume_fc<D, 1, 16, F32>(T, cfg, values, L, beta, s);
-    else if (N > 4) consume_fc<D, 1, 8, F32>(T, cfg, values, L, beta, s);
-    else if (N > 2) consume_fc<D, 1, 4, F32>(T, cfg, values, L, beta, s);
-    else if (N > 1) consume_fc<D, 1, 2, F32>(T, cfg, values, L, beta, s);
-    else consume_fc<D, 1, 1, F32>(T, cfg, values, L, beta, s);
 }
 
 // The layout of the caller's query values (ft_sample_cfg.values_layout).
@@ -598,6 +651,12 @@ void zero_counters(unsigned long long* p, int n, hipStream_t s) { k_zero_u64<<<1
 template <int D>
 static void launch_assemble(ft_target* T, const double* beta, int F, const void* values, int64_t ld, bool f32,
                             hipStream_t s) {
+    if constexpr (D >= 4) {
+        auto kern = f32 ? k_assemble_wide<true> : k_assemble_wide<false>;
+        kern<<<grid_for(T->n, 4), 256, 0, s>>>(beta, T->E, T->nb, T->inc_ptr, T->inc, T->n, F, values, ld, T->bres,
+                                              T->g, T->counters);
+        return;
+    }
     if (f32)
         k_assemble<D, true><<<grid_for(T->n, 256), 256, 0, s>>>(beta, T->E, T->nb, T->inc_ptr, T->inc, T->n, F, values,
                                                                ld, T->bres, T->g, T->counters);
@@ -608,8 +667,10 @@ static void launch_assemble(ft_target* T, const double* beta, int F, const void*
 
 static ft_status assemble_from(ft_target* T, const double* beta, int F, const void* values, int64_t ld, bool f32,
                                hipStream_t s) {
-    if (T->dim == 2) launch_assemble<2>(T, beta, F, values, ld, f32, s);
-    else launch_assemble<3>(T, beta, F, values, ld, f32, s);
+    FT_TRY(by_dim(T->dim, [&](auto d) {
+        launch_assemble<decltype(d)::value>(T, beta, F, values, ld, f32, s);
+        return FT_OK;
+    }));
     FT_TRY_HIP(hipGetLastError());
     return FT_OK;
 }
@@ -662,7 +723,7 @@ static ft_status consume_impl(ft_target* T, const ft_sample_cfg* cfg, const void
 // scratch of at least F E (d+1) doubles.  Only the element kernel and the
 // node assembly that follows it touch them.
 ft_status consume_values(ft_target* T, const ft_sample_cfg* cfg, const void* values, double* beta, hipStream_t s) {
-    return T->dim == 2 ? consume_impl<2>(T, cfg, values, beta, s) : consume_impl<3>(T, cfg, values, beta, s);
+    return by_dim(T->dim, [&](auto d) { return consume_impl<decltype(d)::value>(T, cfg, values, beta, s); });
 }
 
 // Consumption of a list with per-element counts (field-major values, one
@@ -678,10 +739,13 @@ static ft_status consume_varn_impl(ft_target* T, const ft_sample_cfg* cfg, const
     zero_counter(T->counters, s);
     T->ood_mode = 0;
     T->var_mode = VAR_NONE;
-    if (T->order == 2) {
-        if (f32) consume_fc<D, 2, 64, true, true>(T, cfg, values, L, T->beta, s, vc);
-        else consume_fc<D, 2, 64, false, true>(T, cfg, values, L, T->beta, s, vc);
-    } else {
+    if constexpr (D <= 3) {
+        if (T->order == 2) {
+            if (f32) consume_fc<D, 2, 64, true, true>(T, cfg, values, L, T->beta, s, vc);
+            else consume_fc<D, 2, 64, false, true>(T, cfg, values, L, T->beta, s, vc);
+        }
+    }
+    if (T->order != 2) {
         if (f32) consume_fc<D, 1, 64, true, true>(T, cfg, values, L, T->beta, s, vc);
         else consume_fc<D, 1, 64, false, true>(T, cfg, values, L, T->beta, s, vc);
     }
@@ -692,8 +756,7 @@ static ft_status consume_varn_impl(ft_target* T, const ft_sample_cfg* cfg, const
 
 ft_status consume_values_varn(ft_target* T, const ft_sample_cfg* cfg, const int64_t* offs, int64_t total,
                               const void* values, hipStream_t s) {
-    return T->dim == 2 ? consume_varn_impl<2>(T, cfg, offs, total, values, s)
-                       : consume_varn_impl<3>(T, cfg, offs, total, values, s);
+    return by_dim(T->dim, [&](auto d) { return consume_varn_impl<decltype(d)::value>(T, cfg, offs, total, values, s); });
 }
 
 }  // namespace ft

@@ -6,7 +6,10 @@
 //    area-uniform barycentric weights of Osada et al. (2002),
 //    lambda = (1 - sqrt(xi), sqrt(xi)(1 - eta), sqrt(xi) eta);
 //  * tetrahedra: u1, u2 from block 0, u3 from words (0,1) of block 1; sorted,
-//    the spacings (s1, s2 - s1, s3 - s2, 1 - s3) are uniform on the simplex.
+//    the spacings (s1, s2 - s1, s3 - s2, 1 - s3) are uniform on the simplex;
+//  * d-simplices, d = 4..6: the same with d uniforms, u_(i+1) from block i/2,
+//    words (0,1) for even i and (2,3) for odd i, sorted by a compare-exchange
+//    network (the sorted values, so the spacings are those of any sort).
 // lambda_k belongs to vertex k of the element in connectivity order; the
 // physical point is sum_k lambda_k x_{v_k}.
 // Stratified samples (FT_SAMPLING_STRATIFIED): with m = floor(N^(1/d')) cells
@@ -87,6 +90,22 @@ __device__ __forceinline__ double sqrt_unit(double a) {
     return fma(d, h, g);
 }
 
+// Ascending order of n values (uniforms in (0, 1), never NaN) by odd-even
+// transposition (n rounds of compare-exchanges): fixed, branch-free, exact
+// (min and max only).
+template <int NV, typename T>
+__device__ __forceinline__ void sort_network(T (&u)[NV]) {
+#pragma unroll
+    for (int r = 0; r < NV; ++r)
+#pragma unroll
+        for (int i = r & 1; i + 1 < NV; i += 2) {
+            const T lo = fmin(u[i], u[i + 1]);
+            const T hi = fmax(u[i], u[i + 1]);
+            u[i] = lo;
+            u[i + 1] = hi;
+        }
+}
+
 template <int D>
 __device__ __forceinline__ void sample_lambda(uint32_t t, uint32_t j, const SampleKey& key, double (&lam)[D + 1]) {
     const u32x4 w = philox4x32_10(u32x4{j, t, key.stream, 0u}, key.k0, key.k1);
@@ -103,6 +122,21 @@ __device__ __forceinline__ void sample_lambda(uint32_t t, uint32_t j, const Samp
         lam[0] = 1.0 - r;
         lam[1] = r * (1.0 - eta);
         lam[2] = r * eta;
+    } else if constexpr (D >= 4) {
+        double u[D];
+        u[0] = uniform53(w.x, w.y);
+        u[1] = uniform53(w.z, w.w);
+#pragma unroll
+        for (int b = 1; b < (D + 1) / 2; ++b) {
+            const u32x4 wb = philox4x32_10(u32x4{j, t, key.stream, uint32_t(b)}, key.k0, key.k1);
+            u[2 * b] = uniform53(wb.x, wb.y);
+            if (2 * b + 1 < D) u[2 * b + 1] = uniform53(wb.z, wb.w);
+        }
+        sort_network<D>(u);
+        lam[0] = u[0];
+#pragma unroll
+        for (int k = 1; k < D; ++k) lam[k] = u[k] - u[k - 1];
+        lam[D] = 1.0 - u[D - 1];
     } else {
         const u32x4 w1 = philox4x32_10(u32x4{j, t, key.stream, 1u}, key.k0, key.k1);
         double a = uniform53(w.x, w.y), b = uniform53(w.z, w.w), c = uniform53(w1.x, w1.y);
@@ -145,6 +179,21 @@ __device__ __forceinline__ void sample_lambda_f32(uint32_t t, uint32_t j, const 
         lam[0] = 1.0f - r;
         lam[1] = r * (1.0f - eta);
         lam[2] = r * eta;
+    } else if constexpr (D >= 4) {
+        float u[D];
+        u[0] = uniform24(w.x);
+        u[1] = uniform24(w.z);
+#pragma unroll
+        for (int b = 1; b < (D + 1) / 2; ++b) {
+            const u32x4 wb = philox4x32_10(u32x4{j, t, key.stream, uint32_t(b)}, key.k0, key.k1);
+            u[2 * b] = uniform24(wb.x);
+            if (2 * b + 1 < D) u[2 * b + 1] = uniform24(wb.z);
+        }
+        sort_network<D>(u);
+        lam[0] = u[0];
+#pragma unroll
+        for (int k = 1; k < D; ++k) lam[k] = u[k] - u[k - 1];
+        lam[D] = 1.0f - u[D - 1];
     } else {
         const u32x4 w1 = philox4x32_10(u32x4{j, t, key.stream, 1u}, key.k0, key.k1);
         float a = uniform24(w.x), b = uniform24(w.z), c = uniform24(w1.x);

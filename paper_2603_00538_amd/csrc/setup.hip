@@ -84,7 +84,7 @@ static RefMass reference_mass(int d, int order) {
 }
 
 template <int D>
-__global__ void k_elem_geom(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
+__global__ __launch_bounds__(256) void k_elem_geom(const double* __restrict__ X, int64_t n, const int32_t* __restrict__ conn, int64_t E,
                             double* __restrict__ vol, unsigned long long* __restrict__ flags) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= E) return;
@@ -109,10 +109,42 @@ __global__ void k_elem_geom(const double* __restrict__ X, int64_t n, const int32
     if constexpr (D == 2) {
         det = e[0][0] * e[1][1] - e[0][1] * e[1][0];
         fact = 2.0;
-    } else {
+    } else if constexpr (D == 3) {
         det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
         fact = 6.0;
+    } else {
+        // Gaussian elimination with partial pivoting, det = sign * product of
+        // pivots; the pivot row is brought up by conditional swaps with each
+        // lower row in turn (static indices: the matrix stays in registers)
+        det = 1.0;
+        fact = 1.0;
+#pragma unroll
+        for (int i = 2; i <= D; ++i) fact *= double(i);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+#pragma unroll
+            for (int r = c + 1; r < D; ++r) {
+                const bool sw = fabs(e[r][c]) > fabs(e[c][c]);
+                det = sw ? -det : det;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double a = e[c][k], b = e[r][k];
+                    e[c][k] = sw ? b : a;
+                    e[r][k] = sw ? a : b;
+                }
+            }
+            const double piv = e[c][c];
+            det *= piv;
+            if (piv != 0.0) {
+#pragma unroll
+                for (int r = c + 1; r < D; ++r) {
+                    const double m = e[r][c] / piv;
+#pragma unroll
+                    for (int k = c; k < D; ++k) e[r][k] = fma(-m, e[c][k], e[r][k]);
+                }
+            }
+        }
     }
     // longest edge
     double h2 = 0.0;
@@ -128,7 +160,7 @@ __global__ void k_elem_geom(const double* __restrict__ X, int64_t n, const int32
             }
             h2 = fmax(h2, s);
         }
-    const double hd = D == 2 ? h2 : h2 * sqrt(h2);
+    const double hd = D == 2 ? h2 : (D == 3 ? h2 * sqrt(h2) : pow(h2, 0.5 * D));
     if (!(fabs(det) > 1e-12 * hd)) atomicAdd(&flags[1], 1ull);
     if (det < 0.0) atomicAdd(&flags[2], 1ull);
     vol[t] = fabs(det) / fact;
@@ -206,14 +238,46 @@ __device__ void insertion_sort(int32_t* a, int64_t len) {
     }
 }
 
+// In-place heapsort: n log n for the long incidence lists of d-simplex meshes
+// (5040 entries per vertex in 6D), where insertion sort would take n^2 / 4 moves.
+__device__ void heap_sort(int32_t* a, int64_t len) {
+    auto sift = [a](int64_t root, int64_t end) {
+        while (true) {
+            int64_t c = 2 * root + 1;
+            if (c >= end) return;
+            if (c + 1 < end && a[c + 1] > a[c]) ++c;
+            if (a[root] >= a[c]) return;
+            const int32_t tmp = a[root];
+            a[root] = a[c];
+            a[c] = tmp;
+            root = c;
+        }
+    };
+    for (int64_t i = len / 2 - 1; i >= 0; --i) sift(i, len);
+    for (int64_t end = len - 1; end > 0; --end) {
+        const int32_t tmp = a[0];
+        a[0] = a[end];
+        a[end] = tmp;
+        sift(0, end);
+    }
+}
+
+// Each node's incidence entries ascending (they are distinct, so any sort gives
+// the same order).
 __global__ void k_sort_segments(const int64_t* __restrict__ ptr, int64_t nseg, int32_t* __restrict__ data) {
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= nseg) return;
-    insertion_sort(data + ptr[s], ptr[s + 1] - ptr[s]);
+    const int64_t len = ptr[s + 1] - ptr[s];
+    if (len <= 32) insertion_sort(data + ptr[s], len);
+    else heap_sort(data + ptr[s], len);
 }
 
-// Candidate columns of row v: every node of every element touching v.
-// Written to cand[nb*inc_ptr[v] ...], sorted, unique count -> rowlen[v].
+// Columns of row v: the nodes of the elements touching v, sorted and unique,
+// written to cand[nb*inc_ptr[v] ...] (room for every candidate), their count
+// to rowlen[v].  Each candidate is looked up by binary search in the columns
+// found so far and inserted if new: the work grows with the candidates times
+// log of the row length, not with the square of the candidates (a 6-simplex
+// vertex of a Kuhn mesh has 5040 elements, 35280 candidates, 127 columns).
 __global__ void k_row_candidates(const int32_t* __restrict__ dofs, int nb, const int64_t* __restrict__ inc_ptr,
                                  const int32_t* __restrict__ inc, int64_t n, int32_t* __restrict__ cand,
                                  int32_t* __restrict__ rowlen) {
@@ -221,15 +285,23 @@ __global__ void k_row_candidates(const int32_t* __restrict__ dofs, int nb, const
     if (v >= n) return;
     const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
     int32_t* seg = cand + nb * b;
+    int64_t u = 0;
     for (int64_t i = b; i < e; ++i) {
         const int t = inc[i] / nb;
-        for (int l = 0; l < nb; ++l) seg[nb * (i - b) + l] = dofs[int64_t(t) * nb + l];
+        for (int l = 0; l < nb; ++l) {
+            const int32_t c = dofs[int64_t(t) * nb + l];
+            int64_t lo = 0, hi = u;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (seg[mid] < c) lo = mid + 1; else hi = mid;
+            }
+            if (lo < u && seg[lo] == c) continue;
+            for (int64_t k = u; k > lo; --k) seg[k] = seg[k - 1];
+            seg[lo] = c;
+            ++u;
+        }
     }
-    const int64_t len = nb * (e - b);
-    insertion_sort(seg, len);
-    int32_t u = len > 0 ? 1 : 0;
-    for (int64_t i = 1; i < len; ++i) u += seg[i] != seg[i - 1];
-    rowlen[v] = u;
+    rowlen[v] = int32_t(u);
 }
 
 // Row v of M: for every (element t, local node k) at v, vol_t * R.m[k][l]
@@ -246,17 +318,12 @@ __global__ void k_fill_csr(const int32_t* __restrict__ dofs, int nb, int order, 
     const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
-    const int32_t* seg = cand + nb * b;
-    const int64_t len = nb * (e - b);
-    const int64_t r0 = rowptr[v];
-    int64_t w = r0;
-    for (int64_t i = 0; i < len; ++i)
-        if (i == 0 || seg[i] != seg[i - 1]) {
-            col[w] = seg[i];
-            val[w] = 0.0;
-            ++w;
-        }
-    const int64_t r1 = w;
+    const int32_t* seg = cand + nb * b;   // the row's sorted unique columns
+    const int64_t r0 = rowptr[v], r1 = rowptr[v + 1];
+    for (int64_t w = r0; w < r1; ++w) {
+        col[w] = seg[w - r0];
+        val[w] = 0.0;
+    }
     double m = 0.0;
     for (int64_t i = b; i < e; ++i) {
         const int64_t t = inc[i] / nb;
@@ -308,11 +375,14 @@ static ft_status build(ft_target* T, const double* coords_in, const int32_t* con
     if (T->order == 1) {
         FT_TRY_HIP(hipMemcpyAsync(T->conn, conn_in, sizeof(int32_t) * NI, hipMemcpyDeviceToDevice, s));
         T->dofs = T->conn;
-    } else {
+    } else if constexpr (D <= 3) {
         FT_TRY(dev_alloc_n(&T->dofs, size_t(NI)));
         FT_TRY_HIP(hipMemcpyAsync(T->dofs, conn_in, sizeof(int32_t) * NI, hipMemcpyDeviceToDevice, s));
         k_p2_vertices<D><<<grid_for(E, B), B, 0, s>>>(T->coords, n, T->dofs, E, T->conn, flags);
         FT_TRY_HIP(hipGetLastError());
+    } else {
+        set_error("P2 targets are triangles and tetrahedra");
+        return FT_E_UNSUPPORTED;
     }
     k_elem_geom<D><<<grid_for(E, B), B, 0, s>>>(T->coords, n, T->conn, E, T->vol, flags);
     FT_TRY_HIP(hipGetLastError());
@@ -371,7 +441,14 @@ static ft_status build(ft_target* T, const double* coords_in, const int32_t* con
 }
 
 ft_status target_setup(ft_target* T, const double* coords, const int32_t* conn, hipStream_t s) {
-    return T->dim == 2 ? build<2>(T, coords, conn, s) : build<3>(T, coords, conn, s);
+    switch (T->dim) {
+        case 2: return build<2>(T, coords, conn, s);
+        case 3: return build<3>(T, coords, conn, s);
+        case 4: return build<4>(T, coords, conn, s);
+        case 5: return build<5>(T, coords, conn, s);
+        case 6: return build<6>(T, coords, conn, s);
+        default: set_error("dim must lie in [2, 6] (got %d)", T->dim); return FT_E_ARG;
+    }
 }
 
 }  // namespace ft

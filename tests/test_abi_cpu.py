@@ -85,8 +85,9 @@ def test_host_validation_rejects_bad_arguments(lib):
     P = ctypes.c_void_p
     h = P()
     fake = P(0x1000)    # never dereferenced: validation fails first
-    assert lib.ft_target_create(5, 10, fake, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
+    assert lib.ft_target_create(7, 10, fake, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
     assert "dim" in lib.ft_last_error().decode()
+    assert lib.ft_target_create(1, 10, fake, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
     assert lib.ft_target_create(2, 10, None, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
     assert lib.ft_target_create(2, 2, fake, 4, fake, None, ctypes.byref(h)) == ft.FT_E_ARG
     assert lib.ft_target_create(2, 10, fake, 0, fake, None, ctypes.byref(h)) == ft.FT_E_ARG

@@ -153,3 +153,21 @@ def test_phase_space_field_and_kuhn_meshes():
         assert abs(geometry.element_measures(c, t).sum() - 1.0) < 1e-12
         v = fields.evaluate("phase_space", np, c)
         assert v.shape == (1, c.shape[0]) and v.min() > 0.0
+
+
+def test_phase_space_integral_against_direct_quadrature():
+    """The exact integral of the 5D/6D workload field (one-dimensional
+    quadrature after separating the other coordinates) against direct
+    two- and three-dimensional adaptive quadrature of the field itself."""
+    from scipy.integrate import dblquad, tplquad
+
+    def f2(y, x):
+        return float(fields.evaluate("phase_space", np, np.array([[x, y]]))[0, 0])
+
+    def f3(z, y, x):
+        return float(fields.evaluate("phase_space", np, np.array([[x, y, z]]))[0, 0])
+
+    v2, _ = dblquad(f2, 0, 1, 0, 1, epsabs=1e-13, epsrel=1e-12)
+    assert abs(v2 - fields.phase_space_integral(2)) < 1e-11
+    v3, _ = tplquad(f3, 0, 1, 0, 1, 0, 1, epsabs=1e-10, epsrel=1e-9)
+    assert abs(v3 - fields.phase_space_integral(3)) < 1e-8

@@ -14,7 +14,13 @@ tet3d_2m                3    Kuhn 71^3 nodes     2,058,000  Kuhn 111^3 nodes    
 tet3d_1m_64f            3    Kuhn 56^3 nodes     998,250    Kuhn 88^3 nodes      3,951,018   128   64
 tri2d_1m_p2             2    as tri2d_1m, P2     999,698    as tri2d_1m          3,998,792   256   1
 tet3d_2m_p2             3    as tet3d_2m, P2     2,058,000  as tet3d_2m          7,986,000   128   1
+kuhn5d_1m               5    Kuhn 7^5 nodes      933,120    analytic black box   -           64    1
+kuhn6d_500k             6    Kuhn 4^6 nodes      524,880    analytic black box   -           64    1
 ======================  ===  ==================  =========  ===================  ==========  ====  ==
+
+The 5D and 6D workloads (distribution-function-like transfers, sec. 7) have
+no source mesh: the field ``phase_space`` is the point-query black box
+itself, evaluated at the query points.
 
 Seeds: target jitter 11, source jitter 12, field parameters 13, Philox key
 ``0x0F7A5EED00000000 + index``.
@@ -42,7 +48,7 @@ PHILOX_SEED_BASE = 0x0F7A5EED00000000
 
 @dataclass(frozen=True)
 class MeshSpec:
-    kind: str          # structured_tri | delaunay_tri | kuhn_tet
+    kind: str          # structured_tri | delaunay_tri | kuhn_tet | kuhn<d>d
     k: int             # nodes per axis
     jitter: float      # fraction of the grid spacing
     seed: int
@@ -56,7 +62,7 @@ class Workload:
     name: str
     dim: int
     target: MeshSpec
-    source: MeshSpec
+    source: MeshSpec | None     # None: the field itself is the black box
     field: str
     samples_per_elem: int
     n_fields: int = 1
@@ -97,6 +103,11 @@ WORKLOADS = {
         "tet3d_2m_p2", 3,
         MeshSpec("kuhn_tet", 71, 0.08, 11), MeshSpec("kuhn_tet", 111, 0.08, 12),
         "gaussian_bumps_3d", 128, index=7, order=2),
+    # phase-space transfers: d-simplices of the unit hypercube, an analytic black box
+    "kuhn5d_1m": Workload(
+        "kuhn5d_1m", 5, MeshSpec("kuhn5d", 7, 0.03, 11), None, "phase_space", 64, index=8),
+    "kuhn6d_500k": Workload(
+        "kuhn6d_500k", 6, MeshSpec("kuhn6d", 4, 0.03, 11), None, "phase_space", 64, index=9),
 }
 
 
@@ -114,6 +125,14 @@ def build_mesh(spec: MeshSpec):
     coords.setflags(write=False)
     conn.setflags(write=False)
     return coords, conn
+
+
+def field_integral(w: Workload):
+    """The exact integral of an analytic black-box field over the unit hypercube
+    (None where no closed form is coded)."""
+    if w.field == "phase_space":
+        return _fields.phase_space_integral(w.dim)
+    return None
 
 
 def source_nodal_values(w: Workload, src_coords: np.ndarray) -> np.ndarray:

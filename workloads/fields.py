@@ -116,6 +116,25 @@ def phase_space(xp, *xs):
 FIELDS["phase_space"] = phase_space
 
 
+def phase_space_integral(dim: int) -> float:
+    """Integral of phase_space over [0,1]^dim: for fixed x_1 the other
+    coordinates separate, each giving G(s) = sqrt(0.08 pi)/2 (erf((1-s)/sqrt(0.08))
+    + erf(s/sqrt(0.08))) with s = 0.5 + 0.05 sin(2 pi x_1); the remaining
+    one-dimensional integral by adaptive quadrature."""
+    from scipy.integrate import quad
+    from scipy.special import erf
+
+    c = np.sqrt(0.08)
+
+    def g(x1):
+        sh = 0.5 + 0.05 * np.sin(2.0 * np.pi * x1)
+        G = 0.5 * np.sqrt(np.pi) * c * (erf((1.0 - sh) / c) + erf(sh / c))
+        return (1.0 + 0.3 * np.cos(2.0 * np.pi * x1)) * G ** (dim - 1)
+
+    val, _ = quad(g, 0.0, 1.0, epsabs=0.0, epsrel=1e-13, limit=200)
+    return float(val)
+
+
 def evaluate(name: str, xp, coords):
     """Evaluate a named field at points ``coords`` of shape (n, dim); returns (F, n)."""
     fn = FIELDS[name]
