@@ -165,7 +165,17 @@ typedef struct {
  * ft_target_create - setup of a P1 target mesh (sec. 2: M_ki = int psi_k psi_i,
  * computed exactly; the element measure |Omega_t| = |det J_t| / d! used by
  * sec. 4.1).
- *   dim      2 (triangles) or 3 (tetrahedra)
+ *   dim      2 (triangles), 3 (tetrahedra), or 4 to 6 (d-simplices: sec. 2
+ *            states the formulation for any dimension, sec. 7 names 5D/6D
+ *            distribution-function transfers).  A d-simplex sample takes
+ *            ceil(d/2) Philox blocks (u_(i+1) from block i/2, words (0,1)
+ *            for even i, (2,3) for odd i), sorted, whose spacings are its
+ *            barycentric weights.  Targets of dimension 4 to 6 take the
+ *            black-box route (ft_sample_points, ft_consume_queries, their
+ *            per-element-count forms, ft_project) with plain samples in the
+ *            FT_F64 and FT_F32 forms; there is no built-in source of those
+ *            dimensions, and stratified samples, the split forms and batches
+ *            return FT_E_UNSUPPORTED.
  *   coords   device, binary64, [dim][n_nodes] (SoA)
  *   conn     device, int32, [n_elems][dim+1] vertex ids in [0, n_nodes)
  *   out      host; receives a new handle (library-owned device memory:
