@@ -415,14 +415,60 @@ __global__ __launch_bounds__(RB) void k_m32_spmv(Mat32 A, int k, const float* __
     write_partial(part, P_PQ, pq);
 }
 
-__global__ __launch_bounds__(RB) void k_m32_update(Mat32 A, int k, const float* __restrict__ p,
+// The binary32 product for long rows: L lanes per row and NT-thread blocks,
+// as k_cg_spmv_rows.
+template <int L, int NT>
+__global__ __launch_bounds__(NT) void k_m32_spmv_rows(Mat32 A, int k, const float* __restrict__ z,
+                                                      const float* __restrict__ p_old, float* __restrict__ p_new,
+                                                      float* __restrict__ q, double* __restrict__ part,
+                                                      double* __restrict__ sc) {
+    if (sc[M_DONE] != 0.0) return;
+    const double rz = partial_total<NT>(part, P_RZ, gridDim.x);
+    const double rr = partial_total<NT>(part, P_RR, gridDim.x);
+    const double tol2 = k == 0 ? kInnerRtol * kInnerRtol * rr : sc[M_TOL2];
+    if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) sc[M_TOL2] = tol2;
+    if (rr <= tol2 || !isfinite(rr)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc[M_DONE] = 1.0;
+            sc[M_ITERS] = double(k);
+        }
+        return;
+    }
+    const float bt = k == 0 ? 0.0f : float(rz / sc[M_RHO0 + ((k - 1) & 1)]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[M_RHO0 + (k & 1)] = rz;
+    const int sub = int(threadIdx.x) & (L - 1);
+    double pq = 0.0;
+    for (int64_t i0 = int64_t(blockIdx.x) * (NT / L); i0 < A.n; i0 += int64_t(gridDim.x) * (NT / L)) {
+        const int64_t i = i0 + int(threadIdx.x) / L;
+        float qi = 0.0f;
+        if (i < A.n) {
+            const int64_t k1 = A.rowptr[i + 1];
+            for (int64_t kk = A.rowptr[i] + sub; kk < k1; kk += L) {
+                const int32_t j = A.col[kk];
+                qi = fmaf(A.val[kk], fmaf(bt, p_old[j], z[j]), qi);
+            }
+        }
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) qi += __shfl_xor(qi, o, L);
+        if (i < A.n && sub == 0) {
+            const float pi = fmaf(bt, p_old[i], z[i]);
+            p_new[i] = pi;
+            q[i] = qi;
+            pq = fma(double(pi), double(qi), pq);
+        }
+    }
+    write_partial<NT>(part, P_PQ, pq);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_m32_update(Mat32 A, int k, const float* __restrict__ p,
                                                    const float* __restrict__ q, float* __restrict__ d,
                                                    float* __restrict__ r, float* __restrict__ z,
                                                    double* __restrict__ part, const double* __restrict__ sc) {
     if (sc[M_DONE] != 0.0) return;
-    const float a = float(sc[M_RHO0 + (k & 1)] / partial_total(part, P_PQ, gridDim.x));
+    const float a = float(sc[M_RHO0 + (k & 1)] / partial_total<NT>(part, P_PQ, gridDim.x));
     double rz = 0.0, rr = 0.0;
-    FOR_ROW(i) {
+    FOR_ROW_NT(i, NT) {
         d[i] = fmaf(a, p[i], d[i]);
         const float ri = fmaf(-a, q[i], r[i]);
         const float zi = ri / A.diag[i];
@@ -431,8 +477,8 @@ __global__ __launch_bounds__(RB) void k_m32_update(Mat32 A, int k, const float* 
         rz = fma(double(ri), double(zi), rz);
         rr = fma(double(ri), double(ri), rr);
     }
-    write_partial(part, P_RZ, rz);
-    write_partial(part, P_RR, rr);
+    write_partial<NT>(part, P_RZ, rz);
+    write_partial<NT>(part, P_RR, rr);
 }
 
 __global__ __launch_bounds__(RB) void k_m32_check(int k, int nb, const double* __restrict__ part,
@@ -494,6 +540,7 @@ static ft_status project_mixed(ft_target* T, const ft_solve_cfg* cfg, double* x,
     double rr = T->h_scal[S_TRR];
     int iters = 0;
     bool done = rr <= tol2 || !std::isfinite(rr);
+    const bool long_rows = T->nnz >= kLongRows * n;
     for (int step = 0; step < cfg->refine_steps && !done; ++step) {
         k_m32_init<<<nb, RB, 0, s>>>(A32, T->r, r32, z32, d32, p32, T->partials, T->scal32);
         int launched = 0, chunk = first_chunk(T->cg_hint[1]);
@@ -503,8 +550,15 @@ static ft_status project_mixed(ft_target* T, const ft_solve_cfg* cfg, double* x,
                 const int kk = launched + it;
                 float* p_old = p32 + ((kk & 1) ? n : 0);
                 float* p_new = p32 + ((kk & 1) ? 0 : n);
-                k_m32_spmv<<<nb, RB, 0, s>>>(A32, kk, z32, p_old, p_new, q32, T->partials, T->scal32);
-                k_m32_update<<<nb, RB, 0, s>>>(A32, kk, p_new, q32, d32, r32, z32, T->partials, T->scal32);
+                if (long_rows) {
+                    k_m32_spmv_rows<8, kCgWide><<<nb, kCgWide, 0, s>>>(A32, kk, z32, p_old, p_new, q32,
+                                                                      T->partials, T->scal32);
+                    k_m32_update<kCgWide><<<nb, kCgWide, 0, s>>>(A32, kk, p_new, q32, d32, r32, z32, T->partials,
+                                                                T->scal32);
+                } else {
+                    k_m32_spmv<<<nb, RB, 0, s>>>(A32, kk, z32, p_old, p_new, q32, T->partials, T->scal32);
+                    k_m32_update<RB><<<nb, RB, 0, s>>>(A32, kk, p_new, q32, d32, r32, z32, T->partials, T->scal32);
+                }
             }
             launched += k;
             k_m32_check<<<1, RB, 0, s>>>(launched, nb, T->partials, T->scal32);
