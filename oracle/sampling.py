@@ -26,9 +26,8 @@ within the element.
 lambda_k multiplies vertex k of the element in connectivity order.
 
 Stratified (jittered) variant, a reading of the paper's suggestion of
-better sampling schemes (sec. 7): the d' uniforms of a sample (d' = 2 for
-triangles, 3 for tetrahedra) are stratified over the unit cube before the
-same maps.  With m = floor(N^(1/d')) cells per axis, sample j < m^d' of an
+better sampling schemes (sec. 7): the d' = d uniforms of a sample are
+stratified over the unit cube before the same maps.  With m = floor(N^(1/d')) cells per axis, sample j < m^d' of an
 element takes cell j (digits c_i = floor(j / m^i) mod m, lowest first) and
 u_i <- min((c_i + u_i) * (1/m), 1 - 2^-53), the same Philox uniform u_i
 placed in that cell; samples j >= m^d' stay plain.  Both maps are
@@ -66,9 +65,7 @@ def uniforms(dim: int, t: np.ndarray, j: np.ndarray, seed: int, stream: int):
 
 
 def strata_per_axis(dim: int, n_samples: int) -> int:
-    """m = floor(N^(1/d')) with d' = dim uniforms per sample (2 or 3), exactly."""
-    if dim not in (2, 3):
-        raise ValueError("stratified samples: triangles and tetrahedra")
+    """m = floor(N^(1/d')) with d' = dim uniforms per sample, exactly."""
     dp = dim
     m = max(1, int(round(n_samples ** (1.0 / dp))))
     while m ** dp > n_samples:

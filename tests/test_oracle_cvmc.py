@@ -214,14 +214,14 @@ def test_h_convergence_rates():
 
 
 # ---- stratified sampling ---------------------------------------------------------------
-@pytest.mark.parametrize("dim,N", [(2, 64), (2, 50), (3, 64), (3, 100)])
+@pytest.mark.parametrize("dim,N", [(2, 64), (2, 50), (3, 64), (3, 100), (4, 81), (5, 40), (6, 64)])
 def test_stratified_samples_fill_every_cell_once(dim, N):
     """Each element's first m^d' samples put their uniforms one in each cell of
     the m^d' grid (m = floor(N^(1/d'))), the rest stay plain; the placed value
     is (cell + u) / m to the last bit or two."""
     from oracle import sampling
 
-    dp = 2 if dim == 2 else 3
+    dp = dim
     m = sampling.strata_per_axis(dim, N)
     assert m ** dp <= N < (m + 1) ** dp
     E = 40

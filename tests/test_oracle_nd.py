@@ -122,8 +122,8 @@ def test_affine_reproduced_and_constant_conserved(dim):
         assert rc["report"][0]["cons_defect"] < 1e-12
 
 
-@pytest.mark.parametrize("dim", [4, 5])
-def test_unbiased_against_exact_quadratic_load(dim):
+@pytest.mark.parametrize("dim,strat", [(4, False), (5, False), (4, True)])
+def test_unbiased_against_exact_quadratic_load(dim, strat):
     """The exact load of a quadratic field (Dirichlet formula): the mean of b
     over 200 realizations (alpha = 1/2, N = 6) within a few standard errors at
     every node; the quadratic integrates exactly under the degree-2 rule, so
@@ -137,7 +137,9 @@ def test_unbiased_against_exact_quadratic_load(dim):
                             .reshape(len(t), -1)))
     assert abs(exact.sum() - integral) < 1e-13
     R = 200
-    bs = np.array([cvmc.transfer(c, t, f, 6, alpha=0.5, seed=300, stream=s)["b"][0] for s in range(R)])
+    N = 16 if strat else 6   # 16 = 2^4: every sample of a 4-simplex in its own cell
+    bs = np.array([cvmc.transfer(c, t, f, N, alpha=0.5, seed=300, stream=s, stratified=strat)["b"][0]
+                   for s in range(R)])
     z = (bs.mean(axis=0) - exact) / (bs.std(axis=0, ddof=1) / math.sqrt(R))
     assert np.abs(z).max() < 5.0
     assert 0.6 < np.mean(z ** 2) < 1.5
