@@ -172,10 +172,11 @@ typedef struct {
  *            for even i, (2,3) for odd i), sorted, whose spacings are its
  *            barycentric weights.  Targets of dimension 4 to 6 take the
  *            black-box route (ft_sample_points, ft_consume_queries, their
- *            per-element-count forms, ft_project) with plain samples in the
- *            FT_F64 and FT_F32 forms; there is no built-in source of those
- *            dimensions, and stratified samples, the split forms and batches
- *            return FT_E_UNSUPPORTED.
+ *            per-element-count forms, ft_project) in the FT_F64 and FT_F32
+ *            forms (plain or stratified samples, the strata given by the
+ *            base-m digits of the sample index over the d uniforms); there is
+ *            no built-in source of those dimensions, and the split forms and
+ *            batches return FT_E_UNSUPPORTED.
  *   coords   device, binary64, [dim][n_nodes] (SoA)
  *   conn     device, int32, [n_elems][dim+1] vertex ids in [0, n_nodes)
  *   out      host; receives a new handle (library-owned device memory:

@@ -84,9 +84,8 @@ ft_status check_sample_cfg(const ft_target* T, const ft_sample_cfg* cfg) {
                  "alpha_mode out of range (%d)", cfg->alpha_mode);
     FT_ARG_CHECK(cfg->values_layout == FT_VALUES_FIELD_MAJOR || cfg->values_layout == FT_VALUES_ELEMENT_TILES,
                  "values_layout out of range (%d)", cfg->values_layout);
-    if (T->dim > 3 && (cfg->sampling != FT_SAMPLING_PLAIN || cfg->precision == FT_SPLIT_F16 ||
-                       cfg->precision == FT_SPLIT_BF16)) {
-        set_error("targets of dimension 4 to 6 take plain samples in the FT_F64 and FT_F32 forms");
+    if (T->dim > 3 && (cfg->precision == FT_SPLIT_F16 || cfg->precision == FT_SPLIT_BF16)) {
+        set_error("targets of dimension 4 to 6 take the FT_F64 and FT_F32 forms");
         return FT_E_UNSUPPORTED;
     }
     if (uint64_t(T->E) * uint64_t(cfg->samples_per_elem) >= (uint64_t(1) << 32) ||

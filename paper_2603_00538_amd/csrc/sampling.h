@@ -13,8 +13,8 @@
 // lambda_k belongs to vertex k of the element in connectivity order; the
 // physical point is sum_k lambda_k x_{v_k}.
 // Stratified samples (FT_SAMPLING_STRATIFIED): with m = floor(N^(1/d')) cells
-// per axis of the d' uniforms (2 for triangles, 3 for tetrahedra), sample
-// j < m^d' takes cell (j mod m, (j / m) mod m, j / m^2) and its uniforms become
+// per axis of the d' = d uniforms, sample j < m^d' takes the cell given by the
+// base-m digits of j, lowest first (j mod m, (j / m) mod m, ...), and its uniforms become
 // min((cell_i + u_i) (1/m), 1 - 2^-53) (binary32: 1/m and 1 - 2^-24 in binary32)
 // before the same maps; the other samples stay plain.  Each cell maps onto an
 // equal-volume part of the simplex, so every sample stays uniform on its part
@@ -44,10 +44,14 @@ inline SampleKey make_sample_key(const ft_sample_cfg& c, int dim) {
     k.inv_m = 1.0;
     k.inv_m_f = 1.0f;
     if (c.sampling == FT_SAMPLING_STRATIFIED && c.samples_per_elem > 0) {
-        const int dp = dim == 2 ? 2 : 3;
+        const int dp = dim;   // uniforms per sample
         const uint64_t N = uint64_t(c.samples_per_elem);
         uint64_t m = 1;
-        auto pw = [dp](uint64_t x) { return dp == 2 ? x * x : x * x * x; };
+        auto pw = [dp](uint64_t x) {
+            uint64_t r = 1;
+            for (int i = 0; i < dp; ++i) r *= x;
+            return r;
+        };
         while (pw(m + 1) <= N) ++m;
         k.strat_n = uint32_t(pw(m));
         k.m_div = make_fastdiv(uint32_t(m));
@@ -60,18 +64,18 @@ inline SampleKey make_sample_key(const ft_sample_cfg& c, int dim) {
 constexpr double kBelowOne = 0x1.fffffffffffffp-1;   // 1 - 2^-53
 constexpr float kBelowOneF = 0x1.fffffep-1f;         // 1 - 2^-24
 
-// The stratum of sample j < strat_n: its cell per axis.
+// The stratum of sample j < strat_n: its cell per axis, the base-m digits
+// of j, lowest first.
 template <int DP>
 __device__ __forceinline__ void sample_cell(uint32_t j, const SampleKey& key, uint32_t (&cell)[DP]) {
-    const uint32_t q = fast_div(j, key.m_div);
-    cell[0] = j - q * key.m_div.d;
-    if (DP == 2) {
-        cell[1] = q;
-    } else {
-        const uint32_t q2 = fast_div(q, key.m_div);
-        cell[1] = q - q2 * key.m_div.d;
-        cell[DP - 1] = q2;
+    uint32_t q = j;
+#pragma unroll
+    for (int i = 0; i + 1 < DP; ++i) {
+        const uint32_t qn = fast_div(q, key.m_div);
+        cell[i] = q - qn * key.m_div.d;
+        q = qn;
     }
+    cell[DP - 1] = q;
 }
 
 // Square root of a in [2^-53, 1]: the hardware reciprocal-square-root estimate,
@@ -132,6 +136,12 @@ __device__ __forceinline__ void sample_lambda(uint32_t t, uint32_t j, const Samp
             u[2 * b] = uniform53(wb.x, wb.y);
             if (2 * b + 1 < D) u[2 * b + 1] = uniform53(wb.z, wb.w);
         }
+        if (j < key.strat_n) {
+            uint32_t cell[D];
+            sample_cell<D>(j, key, cell);
+#pragma unroll
+            for (int i = 0; i < D; ++i) u[i] = fmin((double(cell[i]) + u[i]) * key.inv_m, kBelowOne);
+        }
         sort_network<D>(u);
         lam[0] = u[0];
 #pragma unroll
@@ -188,6 +198,12 @@ __device__ __forceinline__ void sample_lambda_f32(uint32_t t, uint32_t j, const 
             const u32x4 wb = philox4x32_10(u32x4{j, t, key.stream, uint32_t(b)}, key.k0, key.k1);
             u[2 * b] = uniform24(wb.x);
             if (2 * b + 1 < D) u[2 * b + 1] = uniform24(wb.z);
+        }
+        if (j < key.strat_n) {
+            uint32_t cell[D];
+            sample_cell<D>(j, key, cell);
+#pragma unroll
+            for (int i = 0; i < D; ++i) u[i] = fminf((float(cell[i]) + u[i]) * key.inv_m_f, kBelowOneF);
         }
         sort_network<D>(u);
         lam[0] = u[0];

@@ -162,11 +162,37 @@ def test_nd_per_element_counts_match_oracle():
     T.close()
 
 
+@pytest.mark.parametrize("dim,N", [(4, 81), (5, 40), (6, 64)])
+def test_nd_stratified_matches_oracle(dim, N):
+    """Stratified samples on d-simplices: points (binary64 and binary32) and
+    the transfer against the oracle."""
+    c, t = _mesh(dim)
+    lam = sampling.element_samples(dim, t.shape[0], N, SEED, 6, stratified=True)
+    X = sampling.physical_points(c, np.asarray(t, dtype=np.int64), lam)
+    ref_pts = np.concatenate([c, X.reshape(-1, dim)]).T
+    ref = cvmc.transfer(c, t, _query_np(1), N, alpha=0.5, seed=SEED, stream=6, stratified=True)
+    log(f"stratified dim={dim} N={N}")
+    T = ft.Target(c, t)
+    for prec in (ft.FT_F64, ft.FT_F32):
+        cfg = _cfg(N, 1, 0.5, 6, prec)
+        cfg.sampling = ft.FT_SAMPLING_STRATIFIED
+        pts = T.sample_points(cfg)
+        err = np.abs(pts.double().cpu().numpy() - ref_pts)
+        T.consume(cfg, _query_torch(pts, 1))
+        r = T.project(1)
+        if prec == ft.FT_F64:
+            assert err.max() < 2e-15
+            assert rel_l2(r.b.cpu().numpy(), ref["b"]) < 1e-12 and rel_l2(r.x.cpu().numpy(), ref["x"]) < 1e-12
+        else:
+            assert np.median(err) < 1e-7 and err.max() < 1e-6
+            assert rel_l2(r.b.cpu().numpy(), ref["b"]) < 2e-5
+    T.close()
+
+
 def test_nd_unsupported_variants():
     c, t = _mesh(5)
     T = ft.Target(c, t)
-    for kw in ({"sampling": ft.FT_SAMPLING_STRATIFIED}, {"precision": ft.FT_SPLIT_F16},
-               {"precision": ft.FT_SPLIT_BF16}):
+    for kw in ({"precision": ft.FT_SPLIT_F16}, {"precision": ft.FT_SPLIT_BF16}):
         cfg = _cfg(16)
         for k, v in kw.items():
             setattr(cfg, k, v)
