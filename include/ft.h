@@ -230,7 +230,7 @@ int64_t ft_query_count(const ft_target* t, int32_t samples_per_elem);
  * f^s at the nodes); entry n_nodes + t*N + j is sample j of element t:
  * Philox4x32-10 at counter (j, t, stream_id, blk) with key seed gives
  * uniforms, mapped to area/volume-uniform barycentric weights (Osada map for
- * triangles, sorted spacings for tetrahedra) and then to the physical point
+ * triangles, sorted spacings for tetrahedra and d-simplices) and then to the physical point
  * sum_k lambda_k x_{v_k}.
  *   points   device, [dim][Q] in cfg->precision (Q = ft_query_count)
  * Errors: FT_E_ARG.  Asynchronous on `stream`.
