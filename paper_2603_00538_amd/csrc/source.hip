@@ -265,6 +265,7 @@ __global__ void k_node_major(const double* __restrict__ values, int64_t n, int F
 // values as one 128-byte row of the node-major copy; the values collect in an
 // LDS tile [16 fields][64 points] and leave as 16 coalesced row stores.
 constexpr int kManyFB = 16;   // fields per block
+constexpr int kManyU = 8;     // points per lane whose gathers are issued together
 
 template <int D, int P, bool OUT_F32>
 struct ManyLds {
@@ -351,17 +352,28 @@ __global__ __launch_bounds__(64) void k_src_eval_many(SrcView S, int64_t head, i
             a_fs = VL.samp_fld;
         }
         for (int f0 = 0; f0 < S.F; f0 += kManyFB) {
-            const int f = f0 + fl;
-            for (int it = 0; it < 16; ++it) {
-                const int j = it * 4 + pg;   // point of this slot
-                const int slot = q * 64 + j;
-                double y = 0.0;
-                if (f < S.F) {
+            // a field past F reads field 0 (a valid address); its values are never stored
+            const int f = f0 + fl < S.F ? f0 + fl : 0;
+            // eight points' vertex values in flight before the first is used: the
+            // gathers hit the caches, and their latency, not their bytes, sets the pace
+            for (int h = 0; h < 16; h += kManyU) {
+                double v[kManyU][D + 1];
+#pragma unroll
+                for (int u = 0; u < kManyU; ++u) {
+                    const int slot = q * 64 + (h + u) * 4 + pg;
 #pragma unroll
                     for (int k = 0; k <= D; ++k)
-                        y = fma(st_mu[slot * (D + 1) + k], S.values_nm[int64_t(st_v[slot * (D + 1) + k]) * S.F + f], y);
+                        v[u][k] = S.values_nm[int64_t(st_v[slot * (D + 1) + k]) * S.F + f];
                 }
-                tile[fl * 65 + j] = T(y);
+#pragma unroll
+                for (int u = 0; u < kManyU; ++u) {
+                    const int j = (h + u) * 4 + pg;   // point of this slot
+                    const int slot = q * 64 + j;
+                    double y = 0.0;
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) y = fma(st_mu[slot * (D + 1) + k], v[u][k], y);
+                    tile[fl * 65 + j] = T(y);
+                }
             }
             __builtin_amdgcn_wave_barrier();
             const int64_t i = i0 + lane;
