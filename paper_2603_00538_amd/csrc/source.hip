@@ -379,7 +379,9 @@ __global__ __launch_bounds__(64) void k_src_eval_many(SrcView S, int64_t head, i
             const int64_t i = i0 + lane;
             if (i < lim) {
                 for (int r = 0; r < kManyFB && f0 + r < S.F; ++r)
-                    static_cast<T*>(out_)[a_base + int64_t(f0 + r) * a_fs] = tile[r * 65 + lane];
+                    // streamed past the caches: the values are read by a later launch,
+                    // and the vertex rows of the gathers keep the level-2 cache
+                    __builtin_nontemporal_store(tile[r * 65 + lane], static_cast<T*>(out_) + a_base + int64_t(f0 + r) * a_fs);
             }
             __builtin_amdgcn_wave_barrier();
         }
